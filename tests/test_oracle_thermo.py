@@ -1,0 +1,153 @@
+"""Pins of the oracle's pointwise thermodynamics (Sec. 2.1-2.2).
+
+Each check compares the oracle against something other than itself:
+the inverse map, finite differences of an independently written function,
+the closed form of A0, or an identity the paper states.
+"""
+import numpy as np
+import pytest
+
+from oracle import ad
+from oracle import physics as ph
+
+GAMMA = 1.4
+
+
+def random_states(rng, n=200, Mmax=1.5):
+    rho = rng.uniform(0.3, 3.0, n)
+    P = rng.uniform(0.2, 3.0, n)
+    c = np.sqrt(GAMMA * P / rho)
+    V = rng.uniform(-1, 1, (3, n)) * c * Mmax / np.sqrt(3)
+    return rho, V, P
+
+
+def entropy_vars(rho, V, P):
+    """v of eq. (s222) written from primitive variables (independent form)."""
+    beta = rho / P
+    s = np.log(P / rho ** GAMMA)
+    V2 = (V ** 2).sum(0)
+    return [(GAMMA - s) / (GAMMA - 1) - beta * V2 / 2, beta * V[0], beta * V[1], beta * V[2], -beta]
+
+
+def test_u_of_v_inverts_v_of_u():
+    rng = np.random.default_rng(0)
+    rho, V, P = random_states(rng)
+    v = entropy_vars(rho, V, P)
+    u = ph.conservative_from_entropy(v, GAMMA)
+    assert np.allclose(u[0], rho, rtol=1e-14, atol=0)
+    for i in range(3):
+        assert np.allclose(u[1 + i], rho * V[i], rtol=1e-13, atol=1e-15)
+    E = P / ((GAMMA - 1) * rho) + (V ** 2).sum(0) / 2
+    assert np.allclose(u[4], rho * E, rtol=1e-14)
+    v2 = ph.entropy_from_conservative(u, GAMMA)
+    for k in range(5):
+        assert np.allclose(v2[k], v[k], rtol=1e-13, atol=1e-14)
+
+
+def test_entropy_variables_are_gradient_of_entropy():
+    """v = dH/du (Sec. 2.2): central FD of H(u) = -rho s/(gamma-1)."""
+    rng = np.random.default_rng(1)
+    rho, V, P = random_states(rng, 50)
+    v = entropy_vars(rho, V, P)
+    u = ph.conservative_from_entropy(v, GAMMA)
+    h = 1e-6
+    for l in range(5):
+        up = [x.copy() for x in u]
+        um = [x.copy() for x in u]
+        up[l] = up[l] + h
+        um[l] = um[l] - h
+        g = (ph.entropy_density(up, GAMMA) - ph.entropy_density(um, GAMMA)) / (2 * h)
+        assert np.allclose(g, v[l], rtol=1e-7, atol=1e-7)
+
+
+def test_A0_closed_form_dual_and_fd():
+    """A0 = du/dv: dual-number Jacobian == closed form == central FD; SPD."""
+    rng = np.random.default_rng(2)
+    rho, V, P = random_states(rng, 100)
+    v = entropy_vars(rho, V, P)
+    Ad = ad.jac(ph.conservative_from_entropy(ad.seed(v, 5, 0), GAMMA))
+    Ac = ph.entropy_jacobian(v, GAMMA)
+    assert np.max(np.abs(Ad - Ac) / (np.abs(Ac) + 1e-12)) < 1e-12
+    h = 1e-6
+    for l in range(5):
+        vp = [x.copy() for x in v]
+        vm = [x.copy() for x in v]
+        vp[l] += h
+        vm[l] -= h
+        col = (np.stack(ph.conservative_from_entropy(vp, GAMMA), -1)
+               - np.stack(ph.conservative_from_entropy(vm, GAMMA), -1)) / (2 * h)
+        assert np.allclose(col, Ac[..., :, l], rtol=1e-6, atol=1e-7)
+    assert np.allclose(Ac, np.swapaxes(Ac, -1, -2), rtol=1e-14)
+    assert np.all(np.linalg.eigvalsh(Ac) > 0)
+
+
+def test_entropy_potential_relation():
+    """Psi_j = F_j^T v - (entropy flux)_j = rho V_j, eq. (poen), with the
+    entropy flux read as H V; the printed -rho s V fails it."""
+    rng = np.random.default_rng(3)
+    rho, V, P = random_states(rng)
+    v = entropy_vars(rho, V, P)
+    F = ph.inviscid_flux(v, GAMMA)
+    Fe = ph.entropy_flux(v, GAMMA)
+    s = np.log(P / rho ** GAMMA)
+    for j in range(3):
+        Fv = sum(F[j][k] * v[k] for k in range(5))
+        assert np.allclose(Fv - Fe[j], rho * V[j], rtol=1e-12, atol=1e-13)
+        printed = -rho * s * V[j]
+        assert not np.allclose(Fv - printed, rho * V[j], rtol=1e-3)
+
+
+def test_flux_jacobian_in_entropy_variables_is_symmetric():
+    """dF_j/dv = A_j A0 is symmetric (Sec. 2.2), checked on the dual Jacobian,
+    and it matches central FD of F."""
+    rng = np.random.default_rng(4)
+    rho, V, P = random_states(rng, 60)
+    v = entropy_vars(rho, V, P)
+    F = ph.inviscid_flux(ad.seed(v, 5, 0), GAMMA)
+    for j in range(3):
+        Aj = ad.jac(F[j])
+        assert np.max(np.abs(Aj - np.swapaxes(Aj, -1, -2))) < 1e-11 * np.max(np.abs(Aj))
+        h = 1e-6
+        for l in range(5):
+            vp = [x.copy() for x in v]
+            vm = [x.copy() for x in v]
+            vp[l] += h
+            vm[l] -= h
+            col = (np.stack(ph.inviscid_flux(vp, GAMMA)[j], -1)
+                   - np.stack(ph.inviscid_flux(vm, GAMMA)[j], -1)) / (2 * h)
+            assert np.allclose(col, Aj[..., :, l], rtol=1e-6, atol=1e-7)
+
+
+def test_viscous_flux_matches_primitive_gradients():
+    """G(v, grad v) equals the stress/heat-flux definition of eq. (C5)-(C6)
+    evaluated from analytic gradients of V and T (linear fields)."""
+    rng = np.random.default_rng(5)
+    prm = dict(gamma=GAMMA, mu=0.013, kappa=0.07, lam=-2.0 / 3.0)
+    rho, V, P = random_states(rng, 20)
+    n = rho.size
+    gV = rng.standard_normal((3, 3, n)) * 0.3       # d_j V_i
+    grho = rng.standard_normal((3, n)) * 0.2
+    gP = rng.standard_normal((3, n)) * 0.2
+    # FD of v along each direction using the primitive gradients
+    v0 = entropy_vars(rho, V, P)
+    h = 1e-6
+    q = [[None] * 3 for _ in range(5)]
+    for j in range(3):
+        vp = entropy_vars(rho + h * grho[j], V + h * gV[:, j], P + h * gP[j])
+        vm = entropy_vars(rho - h * grho[j], V - h * gV[:, j], P - h * gP[j])
+        for l in range(5):
+            q[l][j] = (vp[l] - vm[l]) / (2 * h)
+    G = ph.viscous_flux(v0, q, prm)
+    T = GAMMA * P / rho
+    gT = GAMMA * (gP / rho - P * grho / rho ** 2)
+    div = gV[0, 0] + gV[1, 1] + gV[2, 2]
+    for j in range(3):
+        for i in range(3):
+            tau_ij = prm["mu"] * (gV[i, j] + gV[j, i] + (prm["lam"] * div if i == j else 0))
+            assert np.allclose(G[j][1 + i], -tau_ij, rtol=1e-6, atol=1e-9)
+        tauV = sum(prm["mu"] * (gV[j, i] + gV[i, j] + (prm["lam"] * div if i == j else 0)) * V[i]
+                   for i in range(3))
+        phi = -prm["kappa"] * gT[j]
+        assert np.allclose(G[j][4], -(tauV - phi), rtol=1e-6, atol=1e-9)
+        assert np.all(G[j][0] == 0)
+    assert np.all(np.isfinite(T))
