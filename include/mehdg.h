@@ -1,0 +1,141 @@
+/*
+ * mehdg.h -- C ABI of the MI355X library for the per-macro-element local
+ * work of one Newton step of the entropy-variable macro-element HDG method
+ * (arXiv 2507.22195).
+ *
+ * Discretisation.  Every macro-element is an axis-aligned box split into
+ * 2x2x2 hexahedral sub-elements carrying a C0-continuous tensor Q_p space on
+ * Gauss-Lobatto nodes (Sec. 3.1, local space W_p(K)); macro-elements are
+ * coupled only through the trace unknowns on their six faces.  Volume
+ * integrals use p+1 Gauss points per sub-element and axis, face integrals
+ * the matching 2-D rule (Sec. 3.1 eq. C31, C32).
+ *
+ * Unknowns and layouts (device memory, float64, row-major, per macro m):
+ *   n1d = 2p+1, n = n1d^3, nf = n1d^2
+ *   v      [m][5][n]        entropy variables (eq. s222), node a = i + n1d*(j + n1d*k)
+ *   q      [m][5][3][n]     gradient unknown q_{kj} ~ d v_k / d x_j
+ *   vhat   [m][6][5][nf]    trace, gathered per macro; faces (-x,+x,-y,+y,-z,+z);
+ *                           face node c = c1 + n1d*c2 over the two tangential axes
+ *                           in increasing axis order
+ *   N_V = 5n, N_Q = 15n, N_VH = 30 nf
+ *   V index  k*n + a,  Q index (k*3 + j)*n + a,  Vhat index (f*5 + k)*nf + c.
+ *
+ * Ownership.  The caller owns every array passed in or out.  The context
+ * owns its tables and workspaces: pointwise Jacobian coefficients, the
+ * bordered matrix [[S, -Y, r_V], [X, A', r_hat]] of every macro, and after
+ * mehdg_condense its factors (U of S, L^-1 P(-Y), L^-1 P r_V), which
+ * mehdg_recover reads.  mehdg_assemble(want_blocks = 1) overwrites the
+ * bordered matrices; mehdg_condense overwrites them with factors.
+ *
+ * Errors.  Argument errors are detected on the host before anything is
+ * enqueued and return MEHDG_EINVAL / MEHDG_ESTATE.  Device-side conditions
+ * (non-physical state, non-finite values, zero pivot) never abort a kernel:
+ * the kernel records a per-macro status code and writes NaN to that macro's
+ * outputs; mehdg_status returns the codes.
+ *
+ * Asynchrony.  Every compute call only enqueues work on the given stream
+ * (NULL = default stream) and returns.  mehdg_create and mehdg_status
+ * synchronise.  Calls on one context must not overlap on different streams.
+ */
+#ifndef MEHDG_H
+#define MEHDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mehdg_ctx mehdg_ctx;
+typedef struct ihipStream_t* mehdg_stream; /* a hipStream_t */
+
+typedef enum {
+    MEHDG_OK = 0,
+    MEHDG_EINVAL = 1,        /* bad argument */
+    MEHDG_ENOMEM = 2,        /* device allocation failed */
+    MEHDG_EHIP = 3,          /* HIP runtime error (launch, copy) */
+    MEHDG_ESTATE = 4,        /* call out of order (recover before condense) */
+    MEHDG_ENONPHYSICAL = 5,  /* per macro: beta = -v5 <= 0 or rho, P not positive */
+    MEHDG_ENONFINITE = 6,    /* per macro: NaN / Inf met in inputs or results */
+    MEHDG_ESINGULAR = 7      /* per macro: zero pivot in the LU of S */
+} mehdg_err;
+
+typedef enum {
+    MEHDG_FLUX_EC = 0,       /* entropy-conservative KEP flux, eq. (EC) */
+    MEHDG_FLUX_ES = 1,       /* entropy-stable flux, eq. (Flux_En_Inv) */
+    MEHDG_FLUX_KEPES = 2     /* KEP + entropy-stable flux, eq. (ES) */
+} mehdg_flux;
+
+/* Physical and numerical parameters (acoustic scaling: rho0 = c0 = 1). */
+typedef struct {
+    double gamma;          /* ratio of specific heats */
+    double mu;             /* mu / Re_c, viscous stress coefficient (eq. C6) */
+    double kappa;          /* heat flux phi = -kappa grad T, T = gamma P / rho */
+    double lam;            /* bulk viscosity ratio lambda (eq. C6), -2/3 Stokes */
+    double sigma_vis[5];   /* diagonal viscous trace penalty (eq. Flux_En_Vis) */
+    double alpha_t;        /* time term alpha_t (u(v) - u(v_old), w) (eq. C242) */
+    double alpha_ps;       /* pseudo-time term alpha_ps (A0 dv, w): Jacobian only */
+    double logmean_eps;    /* series branch of the log mean when ((a-b)/(a+b))^2 < eps */
+    int32_t flux;          /* mehdg_flux */
+    int32_t viscous;       /* 0: Euler (G = 0), 1: Navier-Stokes */
+} mehdg_params;
+
+/* Macro-element mesh.  All pointers are host memory, copied at create. */
+typedef struct {
+    int64_t n_macro;
+    int32_t p;             /* polynomial degree of the sub-elements, 1..4 */
+    int32_t pad_;
+    const double* h;       /* [n_macro][3] sub-element edge lengths (macro = 2h) */
+} mehdg_mesh;
+
+/* Sizes of one macro-element at degree p (n, nf, N_V, N_Q, N_VH). */
+mehdg_err mehdg_sizes(int32_t p, int64_t out[5]);
+
+/* Builds the reference tables, copies the mesh and allocates workspaces.
+ * Synchronises.  On error *out is NULL. */
+mehdg_err mehdg_create(const mehdg_mesh* mesh, const mehdg_params* prm, mehdg_ctx** out);
+
+mehdg_err mehdg_destroy(mehdg_ctx* ctx);
+
+/* Residual of eq. (s32a)-(s32c) with the stage time term of eq. (C242), per
+ * macro-element (the trace residual is this macro's local contribution; the
+ * caller sums the two sides of each face), plus the face entropy production
+ * sum_s w ([[v]]^T Fhat - [[Psi_n]]) of Thm. (EC_ES) with the inviscid trace
+ * flux.  q may be NULL: then q is the weak gradient of (v, vhat), i.e. the
+ * solution of R_Q = 0.  With want_blocks = 1 also assembles, per macro, the
+ * Jacobian blocks of Sec. 6.2 with Q eliminated (eq. R1-R3): the bordered
+ * matrix [[S, -Y, r_V], [X, A', r_hat]] in the context workspace.
+ *   v, v_old [n_macro][5][n]; vhat [n_macro][6][5][nf]; q NULL or [n_macro][5][3][n];
+ *   R_q [n_macro][5][3][n]; R_v [n_macro][5][n]; R_vhat [n_macro][6][5][nf];
+ *   entropy [n_macro].  All device pointers. */
+mehdg_err mehdg_assemble(mehdg_ctx* ctx, const double* v, const double* vhat, const double* q,
+                         const double* v_old, double* R_q, double* R_v, double* R_vhat,
+                         double* entropy, int32_t want_blocks, mehdg_stream stream);
+
+/* Static condensation (Sec. 6.2 eq. R4-R5): partial-pivoted LU of S and the
+ * trace Schur complement Ahat = A' + X S^-1 Y and right-hand side
+ * bhat = r_hat - X S^-1 r_V of every macro.  Requires a preceding assemble
+ * with want_blocks = 1.  Ahat [n_macro][N_VH][N_VH] may be NULL (only bhat is
+ * formed); bhat [n_macro][N_VH].  Device pointers. */
+mehdg_err mehdg_condense(mehdg_ctx* ctx, double* Ahat, double* bhat, mehdg_stream stream);
+
+/* Back-substitution once the trace update is known (eq. R2 then R6):
+ * dV = S^-1 (r_V + Y dVhat), dQ = A_qq^-1 (-R_Q - A_qv dV - A_qvhat dVhat).
+ * R_q is the residual returned by the assemble that preceded the condense.
+ *   dvhat [n_macro][6][5][nf]; dv [n_macro][5][n]; dq [n_macro][5][3][n]. */
+mehdg_err mehdg_recover(mehdg_ctx* ctx, const double* R_q, const double* dvhat, double* dv,
+                        double* dq, mehdg_stream stream);
+
+/* Copies the per-macro status codes (mehdg_err values, 0 = fine) of the last
+ * calls into host memory status[n_macro] and clears them.  Synchronises the
+ * stream.  Returns the first non-zero code met, or MEHDG_OK. */
+mehdg_err mehdg_status(mehdg_ctx* ctx, int32_t* status, mehdg_stream stream);
+
+/* Bytes of device workspace the context holds. */
+int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MEHDG_H */

@@ -1,0 +1,199 @@
+"""ctypes binding of ``libmehdg.so`` (argument marshalling only).
+
+Every step of the local work runs in the library's HIP kernels; this module
+checks tensor shapes, dtypes and devices, passes raw device pointers and the
+current HIP stream, and turns error codes into exceptions.  It never falls
+back to anything else: if the library is missing or a call fails, it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmehdg.so")
+
+ERRORS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESTATE", 5: "ENONPHYSICAL",
+          6: "ENONFINITE", 7: "ESINGULAR"}
+EXPORTS = ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
+           "mehdg_recover", "mehdg_status", "mehdg_workspace_bytes")
+
+
+class MehdgError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {ERRORS.get(code, code)}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("lam", ctypes.c_double), ("sigma_vis", ctypes.c_double * 5),
+                ("alpha_t", ctypes.c_double), ("alpha_ps", ctypes.c_double),
+                ("logmean_eps", ctypes.c_double), ("flux", ctypes.c_int32),
+                ("viscous", ctypes.c_int32)]
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("n_macro", ctypes.c_int64), ("p", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("h", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2507_22195_amd.build")
+    # torch ships its own HIP runtime; importing it first makes the library
+    # bind to that same runtime (same soname), so that torch's device
+    # pointers and streams are valid in the library's calls.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.mehdg_sizes.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.mehdg_create.argtypes = [ctypes.POINTER(Mesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
+    lib.mehdg_destroy.argtypes = [vp]
+    lib.mehdg_assemble.argtypes = [vp] + [vp] * 8 + [i32, vp]
+    lib.mehdg_condense.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_recover.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mehdg_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.mehdg_workspace_bytes.argtypes = [vp]
+    lib.mehdg_workspace_bytes.restype = i64
+    for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
+                 "mehdg_recover", "mehdg_status"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def sizes(p: int) -> dict:
+    out = (ctypes.c_int64 * 5)()
+    rc = load().mehdg_sizes(p, out)
+    if rc:
+        raise MehdgError(rc, "mehdg_sizes")
+    return dict(n=out[0], nf=out[1], N_V=out[2], N_Q=out[3], N_VH=out[4])
+
+
+def make_params(prm: dict) -> Params:
+    P = Params()
+    P.gamma = prm["gamma"]
+    P.mu = prm["mu"]
+    P.kappa = prm["kappa"]
+    P.lam = prm["lam"]
+    for k in range(5):
+        P.sigma_vis[k] = prm["sigma_vis"][k]
+    P.alpha_t = prm["alpha_t"]
+    P.alpha_ps = prm["alpha_ps"]
+    P.logmean_eps = prm["logmean_eps"]
+    P.flux = int(prm["flux"])
+    P.viscous = int(prm["viscous"])
+    return P
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ptr(t, shape, name, optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owner of one library context (tables, mesh sizes, workspaces)."""
+
+    def __init__(self, p: int, h, params: dict):
+        lib = load()
+        h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
+        if h.ndim != 2 or h.shape[1] != 3:
+            raise ValueError("h must be [n_macro][3]")
+        self.p = int(p)
+        self.n_macro = int(h.shape[0])
+        self._h = h
+        mesh = Mesh(self.n_macro, self.p, 0, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        self._prm = make_params(params)
+        handle = ctypes.c_void_p()
+        rc = lib.mehdg_create(ctypes.byref(mesh), ctypes.byref(self._prm), ctypes.byref(handle))
+        if rc:
+            raise MehdgError(rc, "mehdg_create")
+        self._handle = handle
+        self.sz = sizes(self.p)
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            load().mehdg_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # shapes -------------------------------------------------------------
+    def shapes(self):
+        M, s = self.n_macro, self.sz
+        n, nf = s["n"], s["nf"]
+        return dict(v=(M, 5, n), vhat=(M, 6, 5, nf), q=(M, 5, 3, n), R_q=(M, 5, 3, n),
+                    R_v=(M, 5, n), R_vhat=(M, 6, 5, nf), entropy=(M,),
+                    Ahat=(M, s["N_VH"], s["N_VH"]), bhat=(M, s["N_VH"]),
+                    dv=(M, 5, n), dq=(M, 5, 3, n))
+
+    def workspace_bytes(self) -> int:
+        return int(load().mehdg_workspace_bytes(self._handle))
+
+    # calls --------------------------------------------------------------
+    def assemble(self, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, want_blocks=False, stream=None):
+        S = self.shapes()
+        args = [_ptr(v, S["v"], "v"), _ptr(vhat, S["vhat"], "vhat"),
+                _ptr(q, S["q"], "q", optional=True), _ptr(v_old, S["v"], "v_old"),
+                _ptr(R_q, S["R_q"], "R_q"), _ptr(R_v, S["R_v"], "R_v"),
+                _ptr(R_vhat, S["R_vhat"], "R_vhat"), _ptr(entropy, S["entropy"], "entropy")]
+        rc = load().mehdg_assemble(self._handle, *args, int(bool(want_blocks)), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_assemble")
+
+    def condense(self, Ahat, bhat, stream=None):
+        S = self.shapes()
+        rc = load().mehdg_condense(self._handle, _ptr(Ahat, S["Ahat"], "Ahat", optional=True),
+                                   _ptr(bhat, S["bhat"], "bhat"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_condense")
+
+    def recover(self, R_q, dvhat, dv, dq, stream=None):
+        S = self.shapes()
+        rc = load().mehdg_recover(self._handle, _ptr(R_q, S["R_q"], "R_q"),
+                                  _ptr(dvhat, S["vhat"], "dvhat"), _ptr(dv, S["dv"], "dv"),
+                                  _ptr(dq, S["dq"], "dq"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_recover")
+
+    def status(self, stream=None):
+        out = np.zeros(self.n_macro, dtype=np.int32)
+        rc = load().mehdg_status(self._handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 _stream(stream))
+        return rc, out

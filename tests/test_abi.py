@@ -1,0 +1,56 @@
+"""Host-side checks of the C ABI (no GPU compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mehdg.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mehdg_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
+                     "mehdg_recover", "mehdg_status"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2507_22195_amd import mehdg
+    if not os.path.exists(mehdg.LIB_PATH):
+        pytest.skip("libmehdg.so not built")
+    lib = ctypes.CDLL(mehdg.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_argument_errors_are_synchronous():
+    """Calls with bad arguments return EINVAL without touching a device."""
+    from paper_2507_22195_amd import mehdg
+    if not os.path.exists(mehdg.LIB_PATH):
+        pytest.skip("libmehdg.so not built")
+    lib = mehdg.load()
+    out = (ctypes.c_int64 * 5)()
+    assert lib.mehdg_sizes(0, out) == 1
+    assert lib.mehdg_sizes(2, out) == 0 and list(out) == [125, 25, 625, 1875, 750]
+    assert lib.mehdg_create(None, None, None) == 1
+    h = (ctypes.c_double * 3)(0.1, 0.1, -0.1)     # negative size
+    mesh = mehdg.Mesh(1, 2, 0, ctypes.cast(h, ctypes.POINTER(ctypes.c_double)))
+    prm = mehdg.make_params(dict(gamma=1.4, mu=0, kappa=0, lam=0, sigma_vis=[0] * 5, alpha_t=0,
+                                 alpha_ps=0, logmean_eps=1e-4, flux=0, viscous=0))
+    handle = ctypes.c_void_p()
+    assert lib.mehdg_create(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(handle)) == 1
+    assert handle.value is None
+    mesh = mehdg.Mesh(1, 7, 0, ctypes.cast(h, ctypes.POINTER(ctypes.c_double)))   # bad degree
+    assert lib.mehdg_create(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(handle)) == 1
+    assert lib.mehdg_assemble(None, *([None] * 8), 0, None) == 1
+    assert lib.mehdg_condense(None, None, None, None) == 1
+    assert lib.mehdg_recover(None, None, None, None, None, None) == 1
+    assert lib.mehdg_status(None, None, None) == 1
