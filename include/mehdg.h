@@ -131,6 +131,13 @@ mehdg_err mehdg_recover(mehdg_ctx* ctx, const double* R_q, const double* dvhat, 
  * stream.  Returns the first non-zero code met, or MEHDG_OK. */
 mehdg_err mehdg_status(mehdg_ctx* ctx, int32_t* status, mehdg_stream stream);
 
+/* Diagnostics.  Copies the bordered matrix of macro m (after an assemble
+ * with want_blocks = 1; after mehdg_condense it holds the factors instead)
+ * into host memory out[rows][ld], row-major with columns
+ * [V (N_V) | Vhat (N_VH) | rhs | padding].  With out = NULL only *rows and
+ * *ld are set.  Synchronises the device. */
+mehdg_err mehdg_copy_bordered(mehdg_ctx* ctx, int64_t m, double* out, int64_t* rows, int64_t* ld);
+
 /* Bytes of device workspace the context holds. */
 int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
 

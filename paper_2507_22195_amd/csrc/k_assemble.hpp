@@ -1,0 +1,342 @@
+// Assembly of the bordered matrix of every macro-element (Sec. 6.2, eq. R1-R3):
+//
+//   B = [[ S,  -Y,  r_V  ],      S   = A_vv  - A_vq A_qq^-1 A_qv      (R3)
+//        [ X,   A', r_hat]]      -Y  = A_vvh - A_vq A_qq^-1 A_qvh
+//                                X   = A_hv  - A_hq A_qq^-1 A_qv
+//                                A'  = A_hh  - A_hq A_qq^-1 A_qvh
+//                                r_V = -R_V + A_vq A_qq^-1 R_Q,  r_hat = -R_Vhat + A_hq A_qq^-1 R_Q
+//
+// i.e. the Jacobian of (R_V, R_Vhat) in (V, Vhat) with Q eliminated, and the
+// matching right-hand side.  Row-major, leading dimension ldB, rows
+// [V rows | Vhat rows], columns [V cols | Vhat cols | rhs | padding].
+//
+// One workgroup owns the five rows of one test node and writes them whole
+// (no atomics).  The local blocks of a row are accumulated in LDS, one
+// sub-element (or sub-face) at a time, from the pointwise coefficients of
+// the residual kernel.  Q is then eliminated with the tensor structure of
+// A_qq = I (x) M: per axis j,
+//   (M^-1 C_j)[c, b]        = Lam[c_j][b_j] / h_j   (other indices equal),
+//   (M^-1 Chat_j)[c, (f,e)] = n_j Minv[c_j][i_f] / h_j  (faces normal to j),
+// with Lam = M1^-1 C1 and Minv = M1^-1 the 1-D reference operators, so the
+// elimination costs a 1-D contraction per entry.
+#pragma once
+#include "k_residual.hpp"
+
+namespace mehdg {
+
+__host__ __device__ constexpr int round_up8(int x) { return (x + 7) & ~7; }
+
+template <int P>
+struct Bdims {
+    using D = Dims<P>;
+    static constexpr int rows = D::NV + D::NH;
+    static constexpr int ld = round_up8(D::NV + D::NH + 1);
+    static constexpr int64_t per_macro = (int64_t)rows * ld;
+};
+
+// ---------------------------------------------------------------------------
+// M^-1 R_Q per macro (A_qq^-1 R_Q without the identity factor):
+// M^-1 = (Minv (x) Minv (x) Minv) / (hx hy hz).
+template <int P>
+__global__ void __launch_bounds__(256) k_minv_rq(const double* __restrict__ R_q, const double* __restrict__ hs,
+                                                 const Tab1D* __restrict__ tab, double* __restrict__ out) {
+    using D = Dims<P>;
+    constexpr int n1d = D::n1d, n = D::n;
+    __shared__ double a[15 * n], b[15 * n];
+    __shared__ double Mi[n1d][n1d];
+    const int64_t m = blockIdx.x;
+    for (int i = threadIdx.x; i < n1d * n1d; i += blockDim.x) Mi[i / n1d][i % n1d] = tab->Minv[i / n1d][i % n1d];
+    for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) a[i] = R_q[m * 15 * n + i];
+    __syncthreads();
+    const double s = 1.0 / (hs[3 * m] * hs[3 * m + 1] * hs[3 * m + 2]);
+    double* src = a;
+    double* dst = b;
+    for (int axis = 0; axis < 3; ++axis) {
+        const int stride = axis == 0 ? 1 : (axis == 1 ? n1d : n1d * n1d);
+        for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) {
+            const int node = i % n, field = i / n;
+            const int ci = (node / stride) % n1d;
+            const int base = node - ci * stride;
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < n1d; ++c) acc += Mi[ci][c] * src[field * n + base + c * stride];
+            dst[i] = acc;
+        }
+        __syncthreads();
+        double* t = src;
+        src = dst;
+        dst = t;
+    }
+    for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) out[m * 15 * n + i] = s * src[i];
+}
+
+// ---------------------------------------------------------------------------
+template <int P>
+struct RowLds {
+    using D = Dims<P>;
+    static constexpr int E3 = (P + 1) * (P + 1) * (P + 1);
+    static constexpr int E2 = (P + 1) * (P + 1);
+    double av[5][D::n];         // coefficient of trial v_{l,b}
+    double aq[15][D::n];        // coefficient of trial q_{l,j,c}  (index 3 l + j)
+    double ah[6][5][D::nf];     // coefficient of trial vhat_{f,l,e}
+    double wv[E3][20];          // per sub-element Gauss point: [0,5) value trial, [5,20) q trial
+    double wf[E2][25];          // per sub-face Gauss point: [0,5) v, [5,10) vhat, [10,25) q
+    double red[4];
+    Tab1D t;
+};
+
+template <int P>
+__device__ void row_zero(RowLds<P>& L) {
+    using D = Dims<P>;
+    double* p = &L.av[0][0];
+    for (int i = threadIdx.x; i < 20 * D::n; i += blockDim.x) p[i] = 0.0;   // av and aq are contiguous
+    double* h = &L.ah[0][0][0];
+    for (int i = threadIdx.x; i < 30 * D::nf; i += blockDim.x) h[i] = 0.0;
+}
+
+// Volume part of one row: test function phi_a (or d_i phi_a), node a, row k,
+// for the sub-element (e1,e2,e3).
+template <int P>
+__device__ void row_volume(RowLds<P>& L, const double* __restrict__ coefV, int64_t m, int a1, int a2, int a3,
+                           int e1, int e2, int e3, int k, bool viscous) {
+    using D = Dims<P>;
+    using R = RowLds<P>;
+    constexpr int n1d = D::n1d, nq1 = D::nq1, G = D::G;
+    constexpr int Q = P + 1;
+    for (int gl = threadIdx.x; gl < R::E3; gl += blockDim.x) {
+        const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
+        const int g = g1 + nq1 * (g2 + nq1 * g3);
+        const double B1 = L.t.B[g1][a1], B2 = L.t.B[g2][a2], B3 = L.t.B[g3][a3];
+        const double t0 = B1 * B2 * B3;
+        const double ti[3] = {L.t.D[g1][a1] * B2 * B3, B1 * L.t.D[g2][a2] * B3, B1 * B2 * L.t.D[g3][a3]};
+        const double* c = coefV + ((int64_t)m * G + g) * COEF_V;
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+            double w0 = t0 * c[5 * k + l];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) w0 += ti[i] * c[25 + 25 * i + 5 * k + l];
+            L.wv[gl][l] = w0;
+        }
+        if (viscous) {
+#pragma unroll
+            for (int l = 0; l < 5; ++l)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double wq = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) wq += ti[i] * c[100 + 25 * (3 * i + j) + 5 * k + l];
+                    L.wv[gl][5 + 3 * l + j] = wq;
+                }
+        }
+    }
+    __syncthreads();
+    const int nent = (viscous ? 20 : 5) * R::E3;
+    for (int idx = threadIdx.x; idx < nent; idx += blockDim.x) {
+        const int fld = idx / R::E3, bl = idx % R::E3;   // fld < 5: v trial l; else q trial (l,j)
+        const int b1 = e1 * P + bl % Q, b2 = e2 * P + (bl / Q) % Q, b3 = e3 * P + bl / (Q * Q);
+        double acc = 0.0;
+        for (int gl = 0; gl < R::E3; ++gl) {
+            const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
+            acc += L.wv[gl][fld] * (L.t.B[g1][b1] * L.t.B[g2][b2] * L.t.B[g3][b3]);
+        }
+        const int b = b1 + n1d * (b2 + n1d * b3);
+        if (fld < 5) L.av[fld][b] += acc;
+        else L.aq[fld - 5][b] += acc;
+    }
+    __syncthreads();
+}
+
+// Face part of one row on face f, sub-face (s1 block e1, s2 block e2); the test
+// function on the face has 2-D factors at the tangential indices (c1, c2).
+template <int P>
+__device__ void row_face(RowLds<P>& L, const double* __restrict__ coefF, int64_t m, int f, int c1, int c2,
+                         int e1, int e2, int k, bool viscous) {
+    using D = Dims<P>;
+    using R = RowLds<P>;
+    constexpr int n1d = D::n1d, nq1 = D::nq1, S = D::S;
+    constexpr int Q = P + 1;
+    for (int sl = threadIdx.x; sl < R::E2; sl += blockDim.x) {
+        const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
+        const int s = s1 + nq1 * s2;
+        const double t = L.t.B[s1][c1] * L.t.B[s2][c2];
+        const double* c = coefF + ((int64_t)m * 6 * S + f * S + s) * COEF_F;
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+            L.wf[sl][l] = t * c[5 * k + l];
+            L.wf[sl][5 + l] = t * c[25 + 5 * k + l];
+        }
+        if (viscous) {
+#pragma unroll
+            for (int l = 0; l < 5; ++l)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) L.wf[sl][10 + 3 * l + j] = t * c[50 + 25 * j + 5 * k + l];
+        }
+    }
+    __syncthreads();
+    const int d = face_axis(f), t1 = face_t1(f), t2 = face_t2(f);
+    const int ad = face_side(f) ? (n1d - 1) : 0;
+    const int nent = (viscous ? 25 : 10) * R::E2;
+    for (int idx = threadIdx.x; idx < nent; idx += blockDim.x) {
+        const int fld = idx / R::E2, bl = idx % R::E2;
+        const int b1 = e1 * P + bl % Q, b2 = e2 * P + bl / Q;
+        double acc = 0.0;
+        for (int sl = 0; sl < R::E2; ++sl) {
+            const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
+            acc += L.wf[sl][fld] * (L.t.B[s1][b1] * L.t.B[s2][b2]);
+        }
+        int bi[3];
+        bi[d] = ad;
+        bi[t1] = b1;
+        bi[t2] = b2;
+        const int b = bi[0] + n1d * (bi[1] + n1d * bi[2]);
+        if (fld < 5) L.av[fld][b] += acc;
+        else if (fld < 10) L.ah[f][fld - 5][b1 + n1d * b2] += acc;
+        else L.aq[fld - 10][b] += acc;
+    }
+    __syncthreads();
+}
+
+// Eliminate Q and write one row of B (plus its right-hand side entry).
+template <int P>
+__device__ void row_write(RowLds<P>& L, double* __restrict__ Brow, const double* __restrict__ minvrq,
+                          double Rval, const double hinv[3], bool viscous) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH;
+    for (int col = threadIdx.x; col < BD::ld; col += blockDim.x) {
+        double val = 0.0;
+        if (col < NV) {
+            const int l = col / n, b = col % n;
+            val = L.av[l][b];
+            if (viscous) {
+                const int bi[3] = {b % n1d, (b / n1d) % n1d, b / (n1d * n1d)};
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int stride = j == 0 ? 1 : (j == 1 ? n1d : n1d * n1d);
+                    const int base = b - bi[j] * stride;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < n1d; ++c) acc += L.aq[3 * l + j][base + c * stride] * L.t.Lam[c][bi[j]];
+                    val -= hinv[j] * acc;
+                }
+            }
+        } else if (col < NV + NH) {
+            const int r = col - NV;
+            const int f = r / (5 * nf), l = (r / nf) % 5, e = r % nf;
+            val = L.ah[f][l][e];
+            if (viscous) {
+                const int d = face_axis(f);
+                int ci[3];
+                ci[face_t1(f)] = e % n1d;
+                ci[face_t2(f)] = e / n1d;
+                const int iF = face_side(f) ? (n1d - 1) : 0;
+                double acc = 0.0;
+#pragma unroll
+                for (int cd = 0; cd < n1d; ++cd) {
+                    ci[d] = cd;
+                    acc += L.aq[3 * l + d][ci[0] + n1d * (ci[1] + n1d * ci[2])] * L.t.Minv[cd][iF];
+                }
+                val += face_sign(f) * hinv[d] * acc;
+            }
+        }
+        if (col != NV + NH) Brow[col] = val;
+    }
+    // right-hand side: -R + A_.q A_qq^-1 R_Q
+    double part = 0.0;
+    if (viscous)
+        for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) part += (&L.aq[0][0])[i] * minvrq[i];
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+    if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += L.red[i];
+        Brow[NV + NH] = -Rval + s;
+    }
+    __syncthreads();
+}
+
+template <int P>
+__device__ void stage_tables(RowLds<P>& L, const Tab1D* __restrict__ tab) {
+    const double* src = reinterpret_cast<const double*>(tab);
+    double* dst = reinterpret_cast<double*>(&L.t);
+    for (int i = threadIdx.x; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
+}
+
+// Rows of the interior equations: one workgroup per (macro, node a), 5 rows.
+template <int P>
+__global__ void __launch_bounds__(256) k_rows_v(const double* __restrict__ coefV, const double* __restrict__ coefF,
+                                                const double* __restrict__ R_v, const double* __restrict__ minvrq,
+                                                const double* __restrict__ hs, const Tab1D* __restrict__ tab,
+                                                int viscous_i, double* __restrict__ B) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int n1d = D::n1d, n = D::n;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    RowLds<P>& L = *reinterpret_cast<RowLds<P>*>(smem_raw);
+    const int64_t m = blockIdx.y;
+    const int a = blockIdx.x;
+    const bool viscous = viscous_i != 0;
+    const int a1 = a % n1d, a2 = (a / n1d) % n1d, a3 = a / (n1d * n1d);
+    const double hinv[3] = {1.0 / hs[3 * m], 1.0 / hs[3 * m + 1], 1.0 / hs[3 * m + 2]};
+    stage_tables<P>(L, tab);
+    int lo[3], hi[3];
+    support_1d<P>(a1, lo[0], hi[0]);
+    support_1d<P>(a2, lo[1], hi[1]);
+    support_1d<P>(a3, lo[2], hi[2]);
+    const int ai[3] = {a1, a2, a3};
+    for (int k = 0; k < 5; ++k) {
+        row_zero<P>(L);
+        __syncthreads();
+        for (int e3 = lo[2]; e3 <= hi[2]; ++e3)
+            for (int e2 = lo[1]; e2 <= hi[1]; ++e2)
+                for (int e1 = lo[0]; e1 <= hi[0]; ++e1)
+                    row_volume<P>(L, coefV, m, a1, a2, a3, e1, e2, e3, k, viscous);
+        for (int f = 0; f < 6; ++f) {
+            const int d = face_axis(f);
+            if (ai[d] != (face_side(f) ? n1d - 1 : 0)) continue;
+            const int c1 = ai[face_t1(f)], c2 = ai[face_t2(f)];
+            int l1, u1, l2, u2;
+            support_1d<P>(c1, l1, u1);
+            support_1d<P>(c2, l2, u2);
+            for (int e2 = l2; e2 <= u2; ++e2)
+                for (int e1 = l1; e1 <= u1; ++e1) row_face<P>(L, coefF, m, f, c1, c2, e1, e2, k, viscous);
+        }
+        const int row = k * n + a;
+        row_write<P>(L, B + m * BD::per_macro + (int64_t)row * BD::ld, minvrq + m * 15 * n,
+                     R_v[(m * 5 + k) * n + a], hinv, viscous);
+    }
+}
+
+// Rows of the trace equations: one workgroup per (macro, face f, trace node c), 5 rows.
+template <int P>
+__global__ void __launch_bounds__(256) k_rows_h(const double* __restrict__ coefF, const double* __restrict__ R_vh,
+                                                const double* __restrict__ minvrq, const double* __restrict__ hs,
+                                                const Tab1D* __restrict__ tab, int viscous_i,
+                                                double* __restrict__ B) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    RowLds<P>& L = *reinterpret_cast<RowLds<P>*>(smem_raw);
+    const int64_t m = blockIdx.y;
+    const int f = blockIdx.x / nf, c = blockIdx.x % nf;
+    const bool viscous = viscous_i != 0;
+    const int c1 = c % n1d, c2 = c / n1d;
+    const double hinv[3] = {1.0 / hs[3 * m], 1.0 / hs[3 * m + 1], 1.0 / hs[3 * m + 2]};
+    stage_tables<P>(L, tab);
+    int l1, u1, l2, u2;
+    support_1d<P>(c1, l1, u1);
+    support_1d<P>(c2, l2, u2);
+    for (int k = 0; k < 5; ++k) {
+        row_zero<P>(L);
+        __syncthreads();
+        for (int e2 = l2; e2 <= u2; ++e2)
+            for (int e1 = l1; e1 <= u1; ++e1) row_face<P>(L, coefF, m, f, c1, c2, e1, e2, k, viscous);
+        const int row = NV + (f * 5 + k) * nf + c;
+        row_write<P>(L, B + m * BD::per_macro + (int64_t)row * BD::ld, minvrq + m * 15 * n,
+                     R_vh[((m * 6 + f) * 5 + k) * nf + c], hinv, viscous);
+    }
+}
+
+}  // namespace mehdg

@@ -1,0 +1,121 @@
+// Back-substitution once the trace update is known (Sec. 6.2, eq. R2 then R6).
+//
+// After condensation the top rows of the bordered matrix hold U (upper
+// factor of P S), U12 = L^-1 P (-Y) and y = L^-1 P r_V, so
+//   dV = S^-1 (r_V + Y dVhat) = U^-1 (y - U12 dVhat),
+// and then, with A_qq = I (x) M and the 1-D tensor structure of the lifts,
+//   dQ_{lj} = -M^-1 R_Q,lj - (Lam/h_j)_axis-j dV_l + (lift of dVhat_l on the faces normal to j).
+// One workgroup per macro; U is read once, row-wise and coalesced.
+#pragma once
+#include "k_condense.hpp"
+
+namespace mehdg {
+
+template <int P>
+struct RecLds {
+    using D = Dims<P>;
+    double z[D::NV];
+    double dvh[D::NH];
+    double U[64][65];
+    double a[15 * D::n], b[15 * D::n];
+    Tab1D t;
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) k_recover(const double* __restrict__ B, const double* __restrict__ R_q,
+                                                 const double* __restrict__ dvhat, const double* __restrict__ hs,
+                                                 const Tab1D* __restrict__ tab, double* __restrict__ dv,
+                                                 double* __restrict__ dq) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH, ld = BD::ld;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    RecLds<P>& L = *reinterpret_cast<RecLds<P>*>(smem_raw);
+    const int64_t m = blockIdx.x;
+    const double* Bm = B + m * BD::per_macro;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    {
+        const double* src = reinterpret_cast<const double*>(tab);
+        double* dst = reinterpret_cast<double*>(&L.t);
+        for (int i = tid; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
+    }
+    for (int i = tid; i < NH; i += blockDim.x) L.dvh[i] = dvhat[m * NH + i];
+    __syncthreads();
+    // z = y - U12 dVhat   (one wave per row, lanes along the row)
+    for (int r = wave; r < NV; r += nw) {
+        const double* row = Bm + (int64_t)r * ld + NV;
+        double s = 0.0;
+        for (int c = lane; c < NH; c += 64) s += row[c] * L.dvh[c];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) L.z[r] = row[NH] - s;
+    }
+    __syncthreads();
+    // U dV = z, blocks of 64 rows from the bottom
+    for (int i1 = NV; i1 > 0; i1 -= 64) {
+        const int i0 = i1 - 64 > 0 ? i1 - 64 : 0;
+        const int nb = i1 - i0;
+        for (int e = tid; e < 64 * 64; e += blockDim.x) {
+            const int r = e >> 6, c = e & 63;
+            L.U[r][c] = (r < nb && c < nb) ? Bm[(int64_t)(i0 + r) * ld + i0 + c] : 0.0;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double zi = (lane < nb) ? L.z[i0 + lane] : 0.0;
+            for (int j = nb - 1; j >= 0; --j) {
+                double xj = (lane == j) ? zi / L.U[j][j] : 0.0;
+                xj = __shfl(xj, j, 64);
+                if (lane == j) zi = xj;
+                else if (lane < j) zi -= L.U[lane][j] * xj;
+            }
+            if (lane < nb) L.z[i0 + lane] = zi;   // now holds dV for this block
+        }
+        __syncthreads();
+        for (int r = wave; r < i0; r += nw) {
+            const double* row = Bm + (int64_t)r * ld + i0;
+            double s = (lane < nb) ? row[lane] * L.z[i0 + lane] : 0.0;
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+            if (lane == 0) L.z[r] -= s;
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < NV; i += blockDim.x) dv[m * NV + i] = L.z[i];
+    // M^-1 R_Q by three 1-D passes
+    for (int i = tid; i < 15 * n; i += blockDim.x) L.a[i] = R_q[m * 15 * n + i];
+    __syncthreads();
+    double* src = L.a;
+    double* dst = L.b;
+    for (int axis = 0; axis < 3; ++axis) {
+        const int stride = axis == 0 ? 1 : (axis == 1 ? n1d : n1d * n1d);
+        for (int i = tid; i < 15 * n; i += blockDim.x) {
+            const int node = i % n, fld = i / n;
+            const int ci = (node / stride) % n1d;
+            const int base = node - ci * stride;
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < n1d; ++c) acc += L.t.Minv[ci][c] * src[fld * n + base + c * stride];
+            dst[i] = acc;
+        }
+        __syncthreads();
+        double* t = src;
+        src = dst;
+        dst = t;
+    }
+    const double h[3] = {hs[3 * m], hs[3 * m + 1], hs[3 * m + 2]};
+    const double vinv = 1.0 / (h[0] * h[1] * h[2]);
+    for (int i = tid; i < 15 * n; i += blockDim.x) {
+        const int c = i % n, lj = i / n, l = lj / 3, j = lj % 3;
+        const int ci[3] = {c % n1d, (c / n1d) % n1d, c / (n1d * n1d)};
+        const int stride = j == 0 ? 1 : (j == 1 ? n1d : n1d * n1d);
+        const int base = c - ci[j] * stride;
+        double acc = 0.0;
+#pragma unroll
+        for (int b = 0; b < n1d; ++b) acc -= L.t.Lam[ci[j]][b] * L.z[l * n + base + b * stride];
+        const int t1 = (j == 0) ? 1 : 0, t2 = (j == 2) ? 1 : 2;
+        const int fc = ci[t1] + n1d * ci[t2];
+        acc -= L.t.Minv[ci[j]][0] * L.dvh[(2 * j * 5 + l) * nf + fc];
+        acc += L.t.Minv[ci[j]][n1d - 1] * L.dvh[((2 * j + 1) * 5 + l) * nf + fc];
+        dq[m * 15 * n + i] = acc / h[j] - vinv * src[i];
+    }
+}
+
+}  // namespace mehdg

@@ -38,6 +38,120 @@ struct ResLds {
     Tab1D t;
 };
 
+// Pointwise Jacobian coefficients (weights and 1/h of the test derivative
+// folded in).  Per volume Gauss point, COEF_V doubles, each a 5x5 [k][l]:
+//   [0,25)    (alpha_t + alpha_ps) w A0,          A0 = du/dv
+//   [25,100)  -(w/h_i) d(F_i + G_i)/dv,          block i
+//   [100,325) -(w/h_i) dG_i/dq_{.j},             block 3 i + j
+// Per face Gauss point, COEF_F doubles:
+//   [0,25) w dFtot/dv, [25,50) w dFtot/dvhat, [50,125) w dGhat/dq_{.j} (block j),
+// with Ftot = Fhat + Ghat the total trace flux.
+constexpr int COEF_V = 325;
+constexpr int COEF_F = 125;
+
+__device__ __forceinline__ void volume_coefficients(const double vv[5], const double qq[5][3], double w,
+                                                    const double hinv[3], const DevParams& pr,
+                                                    double* __restrict__ out) {
+    dual<5> vd[5];
+#pragma unroll
+    for (int l = 0; l < 5; ++l) vd[l] = seed_dual<5>(vv[l], l);
+    Prim<dual<5>> s;
+    primitive(vd, pr.gamma, s);
+    {
+        dual<5> u[5];
+        conservative(s, pr.gamma, u);
+        const double c = (pr.alpha_t + pr.alpha_ps) * w;
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+#pragma unroll
+            for (int l = 0; l < 5; ++l) out[5 * k + l] = c * u[k].d[l];
+    }
+    dual<5> qd[5][3];
+    if (pr.viscous) {
+#pragma unroll
+        for (int l = 0; l < 5; ++l)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) qd[l][j] = make_dual<5>(qq[l][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        dual<5> F[5];
+        euler_flux(s, pr.gamma, i, F);
+        if (pr.viscous) {
+            dual<5> Gv[5];
+            viscous_flux(vd, qd, pr, i, Gv);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) F[k] = F[k] + Gv[k];
+        }
+        const double c = -w * hinv[i];
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+#pragma unroll
+            for (int l = 0; l < 5; ++l) out[25 + 25 * i + 5 * k + l] = c * F[k].d[l];
+    }
+    // G is linear in q: its q-derivative columns are G evaluated at unit q.
+    for (int i = 0; i < 3; ++i) {
+        const double c = -w * hinv[i];
+        for (int l = 0; l < 5; ++l)
+            for (int j = 0; j < 3; ++j) {
+                double Gv[5] = {0, 0, 0, 0, 0};
+                if (pr.viscous) {
+                    double qu[5][3];
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) qu[a][0] = qu[a][1] = qu[a][2] = 0.0;
+                    qu[l][j] = 1.0;
+                    viscous_flux(vv, qu, pr, i, Gv);
+                }
+#pragma unroll
+                for (int k = 0; k < 5; ++k) out[100 + 25 * (3 * i + j) + 5 * k + l] = c * Gv[k];
+            }
+    }
+}
+
+__device__ __forceinline__ void face_coefficients(const double vh[5], const double vv[5], const double qq[5][3],
+                                                  double ws, const DevParams& pr, int d, double sg,
+                                                  double* __restrict__ out) {
+    // derivatives of the inviscid trace flux in v (pass 0) and vhat (pass 1)
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+        dual<5> a[5], b[5], F[5];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+            a[l] = (pass == 1) ? seed_dual<5>(vh[l], l) : make_dual<5>(vh[l]);
+            b[l] = (pass == 0) ? seed_dual<5>(vv[l], l) : make_dual<5>(vv[l]);
+        }
+        trace_flux(a, b, pr, d, sg, F);
+        if (pr.viscous) {
+            dual<5> qd[5][3], Gh[5];
+#pragma unroll
+            for (int l = 0; l < 5; ++l)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) qd[l][j] = make_dual<5>(qq[l][j]);
+            viscous_trace_flux(a, b, qd, pr, d, sg, Gh);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) F[k] = F[k] + Gh[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+#pragma unroll
+            for (int l = 0; l < 5; ++l) out[25 * pass + 5 * k + l] = ws * F[k].d[l];
+    }
+    // Ghat = sg G_d(vhat, q) - ...: linear in q
+    for (int l = 0; l < 5; ++l)
+        for (int j = 0; j < 3; ++j) {
+            double Gv[5] = {0, 0, 0, 0, 0};
+            if (pr.viscous) {
+                double qu[5][3];
+#pragma unroll
+                for (int a = 0; a < 5; ++a) qu[a][0] = qu[a][1] = qu[a][2] = 0.0;
+                qu[l][j] = 1.0;
+                viscous_flux(vh, qu, pr, d, Gv);
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) out[50 + 25 * j + 5 * k + l] = ws * sg * Gv[k];
+        }
+}
+
 // Weak gradient at every node (R_Q = 0): q_kj = (1/h_j)[ -sum_c Lam[b_j,c] v_k(b_j -> c)
 //   - Minv[b_j,0] vhat_k(face -j) + Minv[b_j,n1d-1] vhat_k(face +j) ].
 template <int P>
@@ -64,13 +178,14 @@ __device__ void lift_gradient(ResLds<P>& L, const double hinv[3]) {
     }
 }
 
-template <int P>
+template <int P, bool JAC>
 __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, const double* __restrict__ vhat,
                                                   const double* __restrict__ q, const double* __restrict__ v_old,
                                                   const double* __restrict__ hs, DevParams pr,
                                                   const Tab1D* __restrict__ tab, double* __restrict__ R_q,
                                                   double* __restrict__ R_v, double* __restrict__ R_vh,
                                                   double* __restrict__ entropy, double* __restrict__ scratch,
+                                                  double* __restrict__ coefV, double* __restrict__ coefF,
                                                   int32_t* __restrict__ status) {
     using D = Dims<P>;
     constexpr int n1d = D::n1d, nq1 = D::nq1, n = D::n, nf = D::nf, G = D::G, S = D::S;
@@ -165,6 +280,7 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
                 scr[(20 + 3 * k + j) * G + g] = w * qq[k][j];
                 scr[(35 + 5 * j + k) * G + g] = w * hinv[j] * vv[k];
             }
+        if constexpr (JAC) volume_coefficients(vv, qq, w, hinv, pr, coefV + ((int64_t)m * G + g) * COEF_V);
     }
 
     // ---- phase 3: face Gauss points
@@ -221,6 +337,7 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
 #pragma unroll
             for (int k = 0; k < 5; ++k) Fh[k] += Gh[k];
         }
+        if constexpr (JAC) face_coefficients(vh, vv, qq, ws, pr, d, sg, coefF + ((int64_t)m * 6 * S + idx) * COEF_F);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             L.fh[f][k][s] = ws * Fh[k];

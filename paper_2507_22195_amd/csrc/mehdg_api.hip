@@ -12,7 +12,7 @@
 
 #include "../../include/mehdg.h"
 #include "common.hpp"
-#include "k_residual.hpp"
+#include "k_recover.hpp"
 #include "tables.hpp"
 
 using namespace mehdg;
@@ -27,6 +27,11 @@ struct mehdg_ctx {
     Tab1D* d_tab = nullptr;
     int32_t* d_status = nullptr;    // [n_macro]
     double* d_scratch = nullptr;    // residual scratch
+    double* d_coefV = nullptr;      // pointwise Jacobian coefficients (volume)
+    double* d_coefF = nullptr;      // pointwise Jacobian coefficients (faces)
+    double* d_minvrq = nullptr;     // M^-1 R_Q per macro
+    double* d_B = nullptr;          // bordered matrices
+    int32_t* d_ipiv = nullptr;      // pivot rows of the LU of S
     int64_t bytes = 0;
     int stage = 0;                  // 0 nothing, 1 blocks assembled, 2 condensed
 };
@@ -57,21 +62,164 @@ mehdg_err dev_alloc(mehdg_ctx* c, T** ptr, int64_t count) {
     return MEHDG_OK;
 }
 
+template <typename K>
+bool allow_lds(K* kern, size_t bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes) == hipSuccess;
+}
+
 template <int P>
-mehdg_err launch_residual(mehdg_ctx* c, const double* v, const double* vhat, const double* q,
+mehdg_err ensure_block_workspace(mehdg_ctx* c) {
+    if (c->d_B) return MEHDG_OK;
+    using D = Dims<P>;
+    mehdg_err e;
+    if ((e = dev_alloc(c, &c->d_coefV, c->n_macro * (int64_t)D::G * COEF_V)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_coefF, c->n_macro * (int64_t)6 * D::S * COEF_F)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_minvrq, c->n_macro * (int64_t)15 * D::n)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_ipiv, c->n_macro * (int64_t)D::NV)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_B, c->n_macro * Bdims<P>::per_macro)) != MEHDG_OK) return e;
+    return MEHDG_OK;
+}
+
+template <int P>
+mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, const double* q,
                           const double* v_old, double* R_q, double* R_v, double* R_vhat, double* ent,
-                          hipStream_t st) {
+                          bool blocks, hipStream_t st) {
+    using D = Dims<P>;
     const size_t lds = res_lds<P>();
-    static bool attr = false;
-    if (!attr) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_residual<P>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            return MEHDG_EHIP;
-        attr = true;
+    const unsigned M = (unsigned)c->n_macro;
+    if (!blocks) {
+        if (!allow_lds(&k_residual<P, false>, lds)) return MEHDG_EHIP;
+        hipLaunchKernelGGL((k_residual<P, false>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
+                           c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, (double*)nullptr, (double*)nullptr,
+                           c->d_status);
+        return hip_ok(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_residual<P>, dim3((unsigned)c->n_macro), dim3(256), lds, st, v, vhat, q, v_old,
-                       c->d_h, c->dp, c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, c->d_status);
+    mehdg_err e = ensure_block_workspace<P>(c);
+    if (e != MEHDG_OK) return e;
+    if (!allow_lds(&k_residual<P, true>, lds)) return MEHDG_EHIP;
+    hipLaunchKernelGGL((k_residual<P, true>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
+                       c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, c->d_coefV, c->d_coefF, c->d_status);
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    hipLaunchKernelGGL(k_minv_rq<P>, dim3(M), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    const size_t rl = sizeof(RowLds<P>);
+    if (!allow_lds(&k_rows_v<P>, rl) || !allow_lds(&k_rows_h<P>, rl)) return MEHDG_EHIP;
+    hipLaunchKernelGGL(k_rows_v<P>, dim3(D::n, M), dim3(256), rl, st, c->d_coefV, c->d_coefF, R_v, c->d_minvrq,
+                       c->d_h, c->d_tab, c->dp.viscous, c->d_B);
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    hipLaunchKernelGGL(k_rows_h<P>, dim3(6 * D::nf, M), dim3(256), rl, st, c->d_coefF, R_vhat, c->d_minvrq, c->d_h,
+                       c->d_tab, c->dp.viscous, c->d_B);
     return hip_ok(hipGetLastError());
+}
+
+mehdg_err launch_gemm(GemmArgs g, unsigned M, hipStream_t st) {
+    const int tr = (g.rows + GT - 1) / GT;
+    g.tiles_c = (g.cols + GT - 1) / GT;
+    if (tr <= 0 || g.tiles_c <= 0 || g.K <= 0) return MEHDG_OK;
+    hipLaunchKernelGGL(k_gemm, dim3((unsigned)(tr * g.tiles_c), M), dim3(256), 0, st, g);
+    return hip_ok(hipGetLastError());
+}
+
+template <int P>
+mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t st) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    using PN = Panel<P>;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld, ROWS = BD::rows;
+    const unsigned M = (unsigned)c->n_macro;
+    double* B = c->d_B;
+    for (int kb = 0; kb < NV; kb += PN::NB) {
+        const int nb = (NV - kb) < PN::NB ? (NV - kb) : PN::NB;
+        hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, c->d_ipiv, c->d_status);
+        if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+        const int ncols = ld - (kb + nb);
+        if (ncols > 0) {
+            hipLaunchKernelGGL(k_rowblock<P>, dim3((unsigned)((ncols + 255) / 256), M), dim3(256), 0, st, B, kb,
+                               c->d_ipiv);
+            if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+        }
+        // trailing update of the L-shaped region (A' is formed at the end)
+        const int o = kb + nb;
+        GemmArgs g{};
+        g.A = B + (int64_t)o * ld + kb;
+        g.Bt = B + (int64_t)kb * ld + o;
+        g.C = B + (int64_t)o * ld + o;
+        g.D = B + (int64_t)o * ld + o;
+        g.D2 = nullptr;
+        g.sA = g.sB = g.sC = g.sD = BD::per_macro;
+        g.sD2 = 0;
+        g.lda = g.ldb = g.ldc = g.ldd = ld;
+        g.ldd2 = 0;
+        g.rows = ROWS - o;
+        g.cols = NV + NH + 1 - o;
+        g.K = nb;
+        g.dsplit = g.cols;
+        g.skip_r = NV - o;
+        g.skip_c = NV - o;
+        mehdg_err e = launch_gemm(g, M, st);
+        if (e != MEHDG_OK) return e;
+    }
+    // Ahat = A' - L21 U12, bhat = r_hat - L21 y
+    GemmArgs g{};
+    g.A = B + (int64_t)NV * ld;
+    g.sA = g.sB = g.sC = BD::per_macro;
+    g.lda = g.ldb = g.ldc = ld;
+    g.rows = NH;
+    g.K = NV;
+    g.skip_r = NH;
+    g.skip_c = NH + 1;
+    if (Ahat) {
+        g.Bt = B + NV;
+        g.C = B + (int64_t)NV * ld + NV;
+        g.D = Ahat;
+        g.sD = (int64_t)NH * NH;
+        g.ldd = NH;
+        g.D2 = bhat;
+        g.sD2 = NH;
+        g.ldd2 = 1;
+        g.cols = NH + 1;
+        g.dsplit = NH;
+    } else {
+        g.Bt = B + NV + NH;
+        g.C = B + (int64_t)NV * ld + NV + NH;
+        g.D = bhat;
+        g.sD = NH;
+        g.ldd = 1;
+        g.D2 = bhat;
+        g.sD2 = NH;
+        g.ldd2 = 1;
+        g.cols = 1;
+        g.dsplit = 0;
+    }
+    return launch_gemm(g, M, st);
+}
+
+template <int P>
+mehdg_err launch_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, double* dv, double* dq,
+                         hipStream_t st) {
+    const size_t lds = sizeof(RecLds<P>);
+    if (!allow_lds(&k_recover<P>, lds)) return MEHDG_EHIP;
+    hipLaunchKernelGGL(k_recover<P>, dim3((unsigned)c->n_macro), dim3(256), lds, st, c->d_B, R_q, dvhat, c->d_h,
+                       c->d_tab, dv, dq);
+    return hip_ok(hipGetLastError());
+}
+
+int64_t bordered_rows(int p) {
+    switch (p) {
+        case 1: return Bdims<1>::rows;
+        case 2: return Bdims<2>::rows;
+        case 3: return Bdims<3>::rows;
+        default: return 0;
+    }
+}
+int64_t bordered_ld(int p) {
+    switch (p) {
+        case 1: return Bdims<1>::ld;
+        case 2: return Bdims<2>::ld;
+        case 3: return Bdims<3>::ld;
+        default: return 0;
+    }
 }
 
 }  // namespace
@@ -95,6 +243,11 @@ mehdg_err mehdg_destroy(mehdg_ctx* c) {
     (void)hipFree(c->d_tab);
     (void)hipFree(c->d_status);
     (void)hipFree(c->d_scratch);
+    (void)hipFree(c->d_coefV);
+    (void)hipFree(c->d_coefF);
+    (void)hipFree(c->d_minvrq);
+    (void)hipFree(c->d_ipiv);
+    (void)hipFree(c->d_B);
     delete c;
     return MEHDG_OK;
 }
@@ -152,32 +305,58 @@ mehdg_err mehdg_assemble(mehdg_ctx* c, const double* v, const double* vhat, cons
                          const double* v_old, double* R_q, double* R_v, double* R_vhat, double* entropy,
                          int32_t want_blocks, mehdg_stream stream) {
     if (!c || !v || !vhat || !v_old || !R_q || !R_v || !R_vhat || !entropy) return MEHDG_EINVAL;
-    if (want_blocks) return MEHDG_EINVAL;   // block assembly not yet available
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool blocks = want_blocks != 0;
     mehdg_err e = MEHDG_EINVAL;
     switch (c->p) {
-        case 1: e = launch_residual<1>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, st); break;
-        case 2: e = launch_residual<2>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, st); break;
-        case 3: e = launch_residual<3>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, st); break;
+        case 1: e = launch_assemble<1>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, blocks, st); break;
+        case 2: e = launch_assemble<2>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, blocks, st); break;
+        case 3: e = launch_assemble<3>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, blocks, st); break;
         default: break;
     }
+    if (e == MEHDG_OK && blocks) c->stage = 1;
     return e;
 }
 
 mehdg_err mehdg_condense(mehdg_ctx* c, double* Ahat, double* bhat, mehdg_stream stream) {
-    (void)Ahat;
-    (void)stream;
     if (!c || !bhat) return MEHDG_EINVAL;
-    if (c->stage < 1) return MEHDG_ESTATE;
-    return MEHDG_EINVAL;
+    if (c->stage != 1) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mehdg_err e = MEHDG_EINVAL;
+    switch (c->p) {
+        case 1: e = launch_condense<1>(c, Ahat, bhat, st); break;
+        case 2: e = launch_condense<2>(c, Ahat, bhat, st); break;
+        case 3: e = launch_condense<3>(c, Ahat, bhat, st); break;
+        default: break;
+    }
+    if (e == MEHDG_OK) c->stage = 2;
+    return e;
 }
 
 mehdg_err mehdg_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, double* dv, double* dq,
                         mehdg_stream stream) {
-    (void)stream;
     if (!c || !R_q || !dvhat || !dv || !dq) return MEHDG_EINVAL;
-    if (c->stage < 2) return MEHDG_ESTATE;
-    return MEHDG_EINVAL;
+    if (c->stage != 2) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    switch (c->p) {
+        case 1: return launch_recover<1>(c, R_q, dvhat, dv, dq, st);
+        case 2: return launch_recover<2>(c, R_q, dvhat, dv, dq, st);
+        case 3: return launch_recover<3>(c, R_q, dvhat, dv, dq, st);
+        default: return MEHDG_EINVAL;
+    }
+}
+
+mehdg_err mehdg_copy_bordered(mehdg_ctx* c, int64_t m, double* out, int64_t* rows, int64_t* ld) {
+    if (!c || m < 0 || m >= c->n_macro || !rows || !ld) return MEHDG_EINVAL;
+    *rows = bordered_rows(c->p);
+    *ld = bordered_ld(c->p);
+    if (!out) return MEHDG_OK;
+    if (!c->d_B || c->stage < 1) return MEHDG_ESTATE;
+    const int64_t count = (*rows) * (*ld);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(out, c->d_B + m * count, count * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return MEHDG_EHIP;
+    return MEHDG_OK;
 }
 
 mehdg_err mehdg_status(mehdg_ctx* c, int32_t* status, mehdg_stream stream) {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmehdg.so")
 ERRORS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESTATE", 5: "ENONPHYSICAL",
           6: "ENONFINITE", 7: "ESINGULAR"}
 EXPORTS = ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
-           "mehdg_recover", "mehdg_status", "mehdg_workspace_bytes")
+           "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_workspace_bytes")
 
 
 class MehdgError(RuntimeError):
@@ -64,10 +64,12 @@ def load(path: str = LIB_PATH):
     lib.mehdg_condense.argtypes = [vp, vp, vp, vp]
     lib.mehdg_recover.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mehdg_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.mehdg_copy_bordered.argtypes = [vp, i64, vp, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]
     lib.mehdg_workspace_bytes.argtypes = [vp]
     lib.mehdg_workspace_bytes.restype = i64
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
-                 "mehdg_recover", "mehdg_status"):
+                 "mehdg_recover", "mehdg_status", "mehdg_copy_bordered"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -191,6 +193,20 @@ class Context:
                                   _ptr(dq, S["dq"], "dq"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_recover")
+
+    def bordered(self, m: int):
+        """Host copy [rows][ld] of macro m's bordered matrix (diagnostics)."""
+        rows, ld = ctypes.c_int64(), ctypes.c_int64()
+        lib = load()
+        rc = lib.mehdg_copy_bordered(self._handle, int(m), None, ctypes.byref(rows), ctypes.byref(ld))
+        if rc:
+            raise MehdgError(rc, "mehdg_copy_bordered")
+        out = np.empty((rows.value, ld.value), dtype=np.float64)
+        rc = lib.mehdg_copy_bordered(self._handle, int(m), ctypes.c_void_p(out.ctypes.data),
+                                     ctypes.byref(rows), ctypes.byref(ld))
+        if rc:
+            raise MehdgError(rc, "mehdg_copy_bordered")
+        return out
 
     def status(self, stream=None):
         out = np.zeros(self.n_macro, dtype=np.int32)

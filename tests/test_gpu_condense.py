@@ -1,0 +1,99 @@
+"""GPU parity of the Jacobian blocks, the condensed trace system and the
+recovery against the FP64 oracle.
+
+Bar: per macro normwise relative error <= 1e-12 for S, Y, X, A' (compared
+block by block from the bordered matrix), Ahat, bhat, dV, dQ.  The
+right-hand-side columns r_V, r_hat carry -R_V and are compared with the
+residual's rounding floor (see test_gpu_residual); bhat and dV, which
+inherit it through r_V, get the same floor propagated through the exact
+solve.  LU factors are not compared (pivot orders may differ).
+"""
+import numpy as np
+import pytest
+
+from oracle import local
+from paper_2507_22195_amd import workloads as W
+from tests.gpu_util import banner, dev, empty, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def gpu_pipeline(w, dvhat, blocks_of=()):
+    from paper_2507_22195_amd import mehdg
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+    ctx.assemble(dev(w.v), dev(w.vhat), None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=True)
+    bord = {m: ctx.bordered(m) for m in blocks_of}
+    Ahat, bhat = empty(S["Ahat"]), empty(S["bhat"])
+    ctx.condense(Ahat, bhat)
+    dv, dq = empty(S["dv"]), empty(S["dq"])
+    ctx.recover(R_q, dev(dvhat), dv, dq)
+    rc, st = ctx.status()
+    out = dict(Ahat=host(Ahat), bhat=host(bhat), dv=host(dv), dq=host(dq), R_v=host(R_v), bord=bord)
+    ctx.close()
+    return out, rc, st
+
+
+def rhs_floor(w, key_scale=10.0, trials=2):
+    """Per-macro change of the oracle's r_V = -R_V under one-ulp input noise."""
+    rng = np.random.default_rng(7)
+    base = local.residual(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params)["R_v"]
+    worst = np.zeros(w.n_macro)
+    for _ in range(trials):
+        pert = lambda x: x * (1 + 2.2e-16 * rng.uniform(-1, 1, x.shape))
+        r = local.residual(w.p, w.mesh.h, pert(w.v), pert(w.vhat), w.v_old, w.params)["R_v"]
+        worst = np.maximum(worst, np.linalg.norm((r - base).reshape(w.n_macro, -1), axis=1))
+    return key_scale * worst
+
+
+def check(w, sample_blocks=(0,)):
+    banner(f"condense {w.name} p={w.p} M={w.n_macro} flux={w.params['flux']} visc={w.params['viscous']}")
+    rng = np.random.default_rng(5)
+    dvhat = 1e-2 * rng.standard_normal(w.vhat.shape)
+    got, rc, st = gpu_pipeline(w, dvhat, blocks_of=sample_blocks)
+    assert rc == 0 and not st.any(), (rc, st)
+    ref = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params)
+    ref_dv, ref_dq = local.recover(ref, dvhat)
+    NV, NH = ref["S"].shape[1], ref["Ap"].shape[1]
+    fl = rhs_floor(w)
+    for m in sample_blocks:
+        Bm = got["bord"][m]
+        e = dict(S=rel_err(Bm[None, :NV, :NV], ref["S"][m:m + 1]),
+                 Y=rel_err(-Bm[None, :NV, NV:NV + NH], ref["Y"][m:m + 1]),
+                 X=rel_err(Bm[None, NV:, :NV], ref["X"][m:m + 1]),
+                 Ap=rel_err(Bm[None, NV:, NV:NV + NH], ref["Ap"][m:m + 1]),
+                 r_v=rel_err(Bm[None, :NV, NV + NH], ref["r_v"][m:m + 1], floor=fl[m:m + 1] / TOL),
+                 r_hat=rel_err(Bm[None, NV:, NV + NH], ref["r_hat"][m:m + 1]))
+        banner(f"  blocks macro {m}: " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+        assert all(v < TOL for v in e.values()), e
+    # floors of the solved quantities: the r_V floor through S^-1
+    Sinv_norm = np.array([np.linalg.norm(np.linalg.inv(ref["S"][m]), 2) for m in range(w.n_macro)])
+    Xn = np.array([np.linalg.norm(ref["X"][m], 2) for m in range(w.n_macro)])
+    e_A = rel_err(got["Ahat"], ref["Ahat"])
+    e_b = rel_err(got["bhat"], ref["bhat"], floor=10 * Xn * Sinv_norm * fl / TOL)
+    e_dv = rel_err(got["dv"], ref_dv, floor=10 * Sinv_norm * fl / TOL)
+    e_dq = rel_err(got["dq"], ref_dq, floor=10 * Sinv_norm * fl / TOL)
+    banner(f"  Ahat {e_A:.2e} bhat {e_b:.2e} dV {e_dv:.2e} dQ {e_dq:.2e}")
+    assert e_A < TOL and e_b < TOL and e_dv < TOL and e_dq < TOL
+
+
+def test_condense_vortex_ec_euler():
+    check(W.workload(1), sample_blocks=(0, 7))
+
+
+def test_condense_tgv_viscous_es():
+    check(W.workload(2, shape=(3, 2, 1)), sample_blocks=(0, 5))
+
+
+def test_condense_tgv_inviscid_kepes():
+    w = W.workload(3, shape=(2, 1, 1))
+    w.params = dict(w.params, flux=2)
+    check(w, sample_blocks=(1,))
+
+
+def test_condense_p1_viscous_kepes():
+    w = W.tgv_workload(shape=(3, 3, 2), p=1, M0=0.3, Re=500.0, flux="KEPES", seed_v=2, seed_vh=3)
+    check(w, sample_blocks=(0, 17))
