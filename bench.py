@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the per-macro-element local work of one Newton step.
+
+One step = mehdg_assemble (residual + bordered Jacobian with Q eliminated)
++ mehdg_condense (LU of S, Ahat, bhat) + mehdg_recover (dV, dQ) over every
+macro-element of the workload, inputs resident in HBM.  Default workload:
+viscous Taylor-Green vortex, 16^3 macro-elements of 2x2x2 p=2 hexahedra
+(4096 dense 625x625 interior blocks, 750 trace dofs each), ES flux,
+Re 1600, Mach 0.1, FP64.
+
+Prints one JSON line.  The roofline object is for the kernel with the
+largest share of the timed region, from HIP events recorded by the library
+around every launch on the launch's own stream.  The CPU baseline runs the
+FP64 oracle on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
+FP64_VALU_PEAK_TFS = 78.6
+
+
+def kernel_models(p, n_macro, NV, NH, viscous):
+    """Algorithmic work per step of each kernel slot: (flops, bytes)."""
+    from paper_2507_22195_amd.workloads import sizes
+    s = sizes(p)
+    n, nf = s["n"], s["nf"]
+    ld = (NV + NH + 1 + 7) // 8 * 8
+    NB = 64
+    upd = 0.0
+    for kb in range(0, NV, NB):
+        nb = min(NB, NV - kb)
+        o = kb + nb
+        region = (NV - o) * (NV + NH + 1 - o) + NH * (NV - o)
+        upd += 2.0 * nb * region
+    schur = 2.0 * NH * (NH + 1) * NV
+    panel = sum(2.0 * (NV - kb - j) * (min(NB, NV - kb) - j) for kb in range(0, NV, NB)
+                for j in range(min(NB, NV - kb))) + sum(
+        NH * min(NB, NV - kb) ** 2 for kb in range(0, NV, NB))
+    rowblock = sum((ld - kb - min(NB, NV - kb)) * min(NB, NV - kb) ** 2 for kb in range(0, NV, NB))
+    M = n_macro
+    return {
+        # flops for MFMA/ALU work, bytes for streaming kernels
+        "update": ("mfma", upd * M),
+        "schur": ("mfma", schur * M),
+        "panel": ("alu", panel * M),
+        "rowblock": ("alu", rowblock * M),
+        # bordered rows: every entry written once
+        "rows_v": ("hbm", 8.0 * NV * ld * M),
+        "rows_h": ("hbm", 8.0 * NH * ld * M),
+        # recovery reads U (upper half) and U12, y
+        "recover": ("hbm", 8.0 * (NV * (NV + 1) / 2 + NV * (NH + 1)) * M),
+        "residual": ("hbm", 8.0 * (5 * n * 2 + 30 * nf + 15 * n + 5 * n + 30 * nf) * M),
+        "minv_rq": ("hbm", 8.0 * 30 * n * M),
+    }
+
+
+def cpu_baseline(w, target_s=15.0):
+    """Oracle (FP64, numpy) assemble + condense + recover on a sample of macros."""
+    from oracle import local
+    from paper_2507_22195_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    rng = np.random.default_rng(99)
+
+    def run(idx):
+        ws = W.subset(w, idx)
+        dvh = 1e-2 * rng.standard_normal(ws.vhat.shape)
+        t0 = time.perf_counter()
+        c = local.condense(ws.p, ws.mesh.h, ws.v, ws.vhat, ws.v_old, ws.params)
+        local.recover(c, dvh)
+        return time.perf_counter() - t0
+
+    run(np.arange(1))                                  # warm caches / BLAS threads
+    per = run(np.arange(2)) / 2.0
+    count = int(max(2, min(64, target_s / max(per, 1e-3))))
+    idx = rng.choice(w.n_macro, size=count, replace=False)
+    t = run(np.sort(idx))
+    return dict(value=count / t, unit="macro-elements/s", cores=int(threads), kind="oracle",
+                sample=f"{count} of {w.n_macro} macro-elements (seeded random), assemble+condense+recover, "
+                       f"{t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shape", type=int, nargs=3, default=None, help="macro grid (default 16 16 16)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the per-macro local work shards "
+                                   "by macro-element (see DESIGN.md), --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2507_22195_amd import mehdg
+    from paper_2507_22195_amd import workloads as W
+
+    w = W.workload(2, shape=tuple(args.shape) if args.shape else None)
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    v, vh, vo = dev(w.v), dev(w.vhat), dev(w.v_old)
+    rng = np.random.default_rng(1)
+    dvh = dev(1e-2 * rng.standard_normal(w.vhat.shape))
+    e = lambda k: torch.empty(S[k], dtype=torch.float64, device="cuda")
+    R_q, R_v, R_vh, ent = e("R_q"), e("R_v"), e("R_vhat"), e("entropy")
+    Ahat, bhat, dv, dq = e("Ahat"), e("bhat"), e("dv"), e("dq")
+
+    def step():
+        ctx.assemble(v, vh, None, vo, R_q, R_v, R_vh, ent, want_blocks=True)
+        ctx.condense(Ahat, bhat)
+        ctx.recover(R_q, dvh, dv, dq)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rc, st = ctx.status()
+    if rc != 0:
+        print(json.dumps({"error": f"device status {rc} on {int((st != 0).sum())} macro-elements"}))
+        sys.exit(1)
+    ctx.profile(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    rc, st = ctx.status()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    M = w.n_macro
+    value = M / (ms_per_step / 1e3)
+    sz = ctx.sz
+    NV, NH = sz["N_V"], sz["N_VH"]
+
+    models = kernel_models(w.p, M, NV, NH, w.params["viscous"])
+    kernels = {}
+    for name, (ms, calls) in prof.items():
+        if calls == 0:
+            continue
+        kind, work = models[name]
+        per_step_ms = ms / args.steps
+        entry = {"ms_per_step": round(per_step_ms, 4), "launches_per_step": calls // args.steps,
+                 "avg_launch_ms": round(ms / calls, 5)}
+        if kind == "hbm":
+            entry["GB/s"] = round(work / (per_step_ms / 1e3) / 1e9, 1)
+        else:
+            entry["TFLOP/s"] = round(work / (per_step_ms / 1e3) / 1e12, 2)
+        kernels[name] = entry
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kind, work = models[dom]
+    dom_ms = kernels[dom]["ms_per_step"]
+    calls = max(1, kernels[dom]["launches_per_step"])
+    if kind == "hbm":
+        achieved = work / (dom_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        achieved = work / (dom_ms / 1e3) / 1e12
+        peak = FP64_MFMA_PEAK_TFS if kind == "mfma" else FP64_VALU_PEAK_TFS
+        roof = {"bound": "mfma" if kind == "mfma" else "alu", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None}
+    roof["kernel"] = dom
+    roof["work_per_launch"] = work / calls
+    # whole condensation against the dense algorithmic count (2/3 N^3 + 2 N^2 M + 2 M^2 N per macro)
+    cond_ms = sum(kernels[k]["ms_per_step"] for k in ("panel", "rowblock", "update", "schur") if k in kernels)
+    cond_flops = M * (2.0 / 3.0 * NV ** 3 + 2.0 * NV ** 2 * NH + 2.0 * NH ** 2 * NV)
+    out = {
+        "metric": "macro-elements/s for assemble+condense; mixed vs FP64 at 1e-10 rel err",
+        "value": round(value, 1),
+        "unit": "macro-elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"viscous TGV, {w.mesh.shape[0]}x{w.mesh.shape[1]}x{w.mesh.shape[2]} macro-elements "
+                               f"of 2x2x2 p=2 hexahedra, ES flux, Re 1600, Mach 0.1, one Newton step "
+                               f"(assemble + condense + recover)",
+                   "n_macro": M, "p": w.p, "N_V": NV, "N_VH": NH, "flux": "ES", "viscous": True},
+        "dof_per_s": round(value * (NV + sz["N_Q"]), 1),
+        "status_ok": bool(rc == 0),
+        "roofline": roof,
+        "condense": {"ms_per_step": round(cond_ms, 3),
+                     "TFLOP/s": round(cond_flops / (cond_ms / 1e3) / 1e12, 2),
+                     "frac_fp64_peak": round(cond_flops / (cond_ms / 1e3) / 1e12 / FP64_MFMA_PEAK_TFS, 4)},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

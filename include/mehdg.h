@@ -138,6 +138,26 @@ mehdg_err mehdg_status(mehdg_ctx* ctx, int32_t* status, mehdg_stream stream);
  * *ld are set.  Synchronises the device. */
 mehdg_err mehdg_copy_bordered(mehdg_ctx* ctx, int64_t m, double* out, int64_t* rows, int64_t* ld);
 
+/* Kernel timing.  While enabled, every kernel launch of the context is
+ * bracketed by HIP events recorded on the launch's own stream.
+ * mehdg_profile_read synchronises the device, then returns and clears, per
+ * kernel slot i < n (at most MEHDG_NPROF), the summed milliseconds ms[i] and
+ * the number of launches calls[i] since the last read.  Host arrays. */
+enum {
+    MEHDG_PROF_RESIDUAL = 0,   /* residual (+ pointwise Jacobian coefficients) */
+    MEHDG_PROF_MINV_RQ = 1,    /* M^-1 R_Q */
+    MEHDG_PROF_ROWS_V = 2,     /* bordered rows of the interior equations */
+    MEHDG_PROF_ROWS_H = 3,     /* bordered rows of the trace equations */
+    MEHDG_PROF_PANEL = 4,      /* panel factorisation */
+    MEHDG_PROF_ROWBLOCK = 5,   /* row interchanges + L_kk solve */
+    MEHDG_PROF_UPDATE = 6,     /* trailing MFMA update */
+    MEHDG_PROF_SCHUR = 7,      /* Ahat = A' - L21 U12 on MFMA */
+    MEHDG_PROF_RECOVER = 8,    /* back-substitution */
+    MEHDG_NPROF = 9
+};
+mehdg_err mehdg_profile_enable(mehdg_ctx* ctx, int32_t enable);
+mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t n);
+
 /* Bytes of device workspace the context holds. */
 int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
 

@@ -33,12 +33,38 @@ struct mehdg_ctx {
     double* d_B = nullptr;          // bordered matrices
     int32_t* d_ipiv = nullptr;      // pivot rows of the LU of S
     int64_t bytes = 0;
+    // kernel timing with HIP events (mehdg_profile_*)
+    bool prof = false;
+    struct Mark { int slot; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    double prof_ms[MEHDG_NPROF] = {};
+    int64_t prof_calls[MEHDG_NPROF] = {};
     int stage = 0;                  // 0 nothing, 1 blocks assembled, 2 condensed
 };
 
 namespace {
 
 constexpr int kMaxP = 3;
+
+// Brackets one launch with events when profiling is on.
+struct Timed {
+    mehdg_ctx* c;
+    int slot;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(mehdg_ctx* c_, int slot_, hipStream_t st_) : c(c_), slot(slot_), st(st_) {
+        if (c->prof && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, st);
+        else
+            a = b = nullptr;
+    }
+    ~Timed() {
+        if (a && b) {
+            (void)hipEventRecord(b, st);
+            c->marks.push_back({slot, a, b});
+        }
+    }
+};
 
 int64_t res_scratch_doubles(int p) {
     const int nq1 = 2 * (p + 1);
@@ -90,6 +116,7 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     const unsigned M = (unsigned)c->n_macro;
     if (!blocks) {
         if (!allow_lds(&k_residual<P, false>, lds)) return MEHDG_EHIP;
+        Timed t(c, MEHDG_PROF_RESIDUAL, st);
         hipLaunchKernelGGL((k_residual<P, false>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
                            c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, (double*)nullptr, (double*)nullptr,
                            c->d_status);
@@ -98,26 +125,40 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     mehdg_err e = ensure_block_workspace<P>(c);
     if (e != MEHDG_OK) return e;
     if (!allow_lds(&k_residual<P, true>, lds)) return MEHDG_EHIP;
-    hipLaunchKernelGGL((k_residual<P, true>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
-                       c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, c->d_coefV, c->d_coefF, c->d_status);
+    {
+        Timed t(c, MEHDG_PROF_RESIDUAL, st);
+        hipLaunchKernelGGL((k_residual<P, true>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
+                           c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, c->d_coefV, c->d_coefF, c->d_status);
+    }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
-    hipLaunchKernelGGL(k_minv_rq<P>, dim3(M), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
+    {
+        Timed t(c, MEHDG_PROF_MINV_RQ, st);
+        hipLaunchKernelGGL(k_minv_rq<P>, dim3(M), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
+    }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     const size_t rl = sizeof(RowLds<P>);
     if (!allow_lds(&k_rows_v<P>, rl) || !allow_lds(&k_rows_h<P>, rl)) return MEHDG_EHIP;
-    hipLaunchKernelGGL(k_rows_v<P>, dim3(D::n, M), dim3(256), rl, st, c->d_coefV, c->d_coefF, R_v, c->d_minvrq,
-                       c->d_h, c->d_tab, c->dp.viscous, c->d_B);
+    {
+        Timed t(c, MEHDG_PROF_ROWS_V, st);
+        hipLaunchKernelGGL(k_rows_v<P>, dim3(D::n, M), dim3(256), rl, st, c->d_coefV, c->d_coefF, R_v,
+                           c->d_minvrq, c->d_h, c->d_tab, c->dp.viscous, c->d_B);
+    }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
-    hipLaunchKernelGGL(k_rows_h<P>, dim3(6 * D::nf, M), dim3(256), rl, st, c->d_coefF, R_vhat, c->d_minvrq, c->d_h,
-                       c->d_tab, c->dp.viscous, c->d_B);
+    {
+        Timed t(c, MEHDG_PROF_ROWS_H, st);
+        hipLaunchKernelGGL(k_rows_h<P>, dim3(6 * D::nf, M), dim3(256), rl, st, c->d_coefF, R_vhat, c->d_minvrq,
+                           c->d_h, c->d_tab, c->dp.viscous, c->d_B);
+    }
     return hip_ok(hipGetLastError());
 }
 
-mehdg_err launch_gemm(GemmArgs g, unsigned M, hipStream_t st) {
+template <int TAG>
+mehdg_err launch_gemm(mehdg_ctx* c, GemmArgs g, unsigned M, hipStream_t st) {
     const int tr = (g.rows + GT - 1) / GT;
     g.tiles_c = (g.cols + GT - 1) / GT;
     if (tr <= 0 || g.tiles_c <= 0 || g.K <= 0) return MEHDG_OK;
-    hipLaunchKernelGGL(k_gemm, dim3((unsigned)(tr * g.tiles_c), M), dim3(256), 0, st, g);
+    Timed t(c, TAG == 0 ? MEHDG_PROF_UPDATE : MEHDG_PROF_SCHUR, st);
+    hipLaunchKernelGGL(k_gemm<TAG>, dim3((unsigned)(tr * g.tiles_c), M), dim3(256), 0, st, g);
     return hip_ok(hipGetLastError());
 }
 
@@ -131,10 +172,14 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
     double* B = c->d_B;
     for (int kb = 0; kb < NV; kb += PN::NB) {
         const int nb = (NV - kb) < PN::NB ? (NV - kb) : PN::NB;
-        hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, c->d_ipiv, c->d_status);
+        {
+            Timed t(c, MEHDG_PROF_PANEL, st);
+            hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, c->d_ipiv, c->d_status);
+        }
         if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
         const int ncols = ld - (kb + nb);
         if (ncols > 0) {
+            Timed t(c, MEHDG_PROF_ROWBLOCK, st);
             hipLaunchKernelGGL(k_rowblock<P>, dim3((unsigned)((ncols + 255) / 256), M), dim3(256), 0, st, B, kb,
                                c->d_ipiv);
             if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
@@ -157,7 +202,7 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         g.dsplit = g.cols;
         g.skip_r = NV - o;
         g.skip_c = NV - o;
-        mehdg_err e = launch_gemm(g, M, st);
+        mehdg_err e = launch_gemm<0>(c, g, M, st);
         if (e != MEHDG_OK) return e;
     }
     // Ahat = A' - L21 U12, bhat = r_hat - L21 y
@@ -192,7 +237,7 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         g.cols = 1;
         g.dsplit = 0;
     }
-    return launch_gemm(g, M, st);
+    return launch_gemm<1>(c, g, M, st);
 }
 
 template <int P>
@@ -200,6 +245,7 @@ mehdg_err launch_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, d
                          hipStream_t st) {
     const size_t lds = sizeof(RecLds<P>);
     if (!allow_lds(&k_recover<P>, lds)) return MEHDG_EHIP;
+    Timed t(c, MEHDG_PROF_RECOVER, st);
     hipLaunchKernelGGL(k_recover<P>, dim3((unsigned)c->n_macro), dim3(256), lds, st, c->d_B, R_q, dvhat, c->d_h,
                        c->d_tab, dv, dq);
     return hip_ok(hipGetLastError());
@@ -237,8 +283,17 @@ mehdg_err mehdg_sizes(int32_t p, int64_t out[5]) {
     return MEHDG_OK;
 }
 
+static void drop_marks(mehdg_ctx* c) {
+    for (auto& mk : c->marks) {
+        (void)hipEventDestroy(mk.a);
+        (void)hipEventDestroy(mk.b);
+    }
+    c->marks.clear();
+}
+
 mehdg_err mehdg_destroy(mehdg_ctx* c) {
     if (!c) return MEHDG_EINVAL;
+    drop_marks(c);
     (void)hipFree(c->d_h);
     (void)hipFree(c->d_tab);
     (void)hipFree(c->d_status);
@@ -375,5 +430,31 @@ mehdg_err mehdg_status(mehdg_ctx* c, int32_t* status, mehdg_stream stream) {
 }
 
 int64_t mehdg_workspace_bytes(const mehdg_ctx* c) { return c ? c->bytes : 0; }
+
+mehdg_err mehdg_profile_enable(mehdg_ctx* c, int32_t enable) {
+    if (!c) return MEHDG_EINVAL;
+    c->prof = enable != 0;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_profile_read(mehdg_ctx* c, double* ms, int64_t* calls, int32_t n) {
+    if (!c || !ms || !calls || n < 0) return MEHDG_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return MEHDG_EHIP;
+    for (auto& mk : c->marks) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, mk.a, mk.b) == hipSuccess) {
+            c->prof_ms[mk.slot] += t;
+            c->prof_calls[mk.slot] += 1;
+        }
+    }
+    drop_marks(c);
+    for (int i = 0; i < n && i < MEHDG_NPROF; ++i) {
+        ms[i] = c->prof_ms[i];
+        calls[i] = c->prof_calls[i];
+        c->prof_ms[i] = 0.0;
+        c->prof_calls[i] = 0;
+    }
+    return MEHDG_OK;
+}
 
 }  // extern "C"

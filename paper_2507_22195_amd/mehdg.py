@@ -19,7 +19,10 @@ LIB_PATH = os.path.join(HERE, "libmehdg.so")
 ERRORS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESTATE", 5: "ENONPHYSICAL",
           6: "ENONFINITE", 7: "ESINGULAR"}
 EXPORTS = ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
-           "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_workspace_bytes")
+           "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_workspace_bytes",
+           "mehdg_profile_enable", "mehdg_profile_read")
+PROF_SLOTS = ("residual", "minv_rq", "rows_v", "rows_h", "panel", "rowblock", "update", "schur",
+              "recover")
 
 
 class MehdgError(RuntimeError):
@@ -66,10 +69,13 @@ def load(path: str = LIB_PATH):
     lib.mehdg_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.mehdg_copy_bordered.argtypes = [vp, i64, vp, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64)]
+    lib.mehdg_profile_enable.argtypes = [vp, i32]
+    lib.mehdg_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.mehdg_workspace_bytes.argtypes = [vp]
     lib.mehdg_workspace_bytes.restype = i64
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
-                 "mehdg_recover", "mehdg_status", "mehdg_copy_bordered"):
+                 "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_profile_enable",
+                 "mehdg_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -207,6 +213,20 @@ class Context:
         if rc:
             raise MehdgError(rc, "mehdg_copy_bordered")
         return out
+
+    def profile(self, enable: bool):
+        rc = load().mehdg_profile_enable(self._handle, int(bool(enable)))
+        if rc:
+            raise MehdgError(rc, "mehdg_profile_enable")
+
+    def profile_read(self) -> dict:
+        n = len(PROF_SLOTS)
+        ms = (ctypes.c_double * n)()
+        calls = (ctypes.c_int64 * n)()
+        rc = load().mehdg_profile_read(self._handle, ms, calls, n)
+        if rc:
+            raise MehdgError(rc, "mehdg_profile_read")
+        return {name: (ms[i], calls[i]) for i, name in enumerate(PROF_SLOTS)}
 
     def status(self, stream=None):
         out = np.zeros(self.n_macro, dtype=np.int32)
