@@ -149,7 +149,7 @@ enum {
     MEHDG_PROF_ROWS_V = 2,     /* bordered rows of the interior equations */
     MEHDG_PROF_ROWS_H = 3,     /* bordered rows of the trace equations */
     MEHDG_PROF_PANEL = 4,      /* panel factorisation */
-    MEHDG_PROF_ROWBLOCK = 5,   /* row interchanges + L_kk solve */
+    MEHDG_PROF_ROWBLOCK = 5,   /* L_kk^-1 and U_kk^-1 applied to the panel's row / column block */
     MEHDG_PROF_UPDATE = 6,     /* trailing MFMA update */
     MEHDG_PROF_SCHUR = 7,      /* Ahat = A' - L21 U12 on MFMA */
     MEHDG_PROF_RECOVER = 8,    /* back-substitution */

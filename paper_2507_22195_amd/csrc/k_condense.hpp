@@ -11,10 +11,11 @@
 //
 // Schedule per 64-column panel [kb, kb+nb):
 //   k_panel     one workgroup per macro: factor the S rows of the panel
-//               (one row per thread, the panel segment in registers), then
-//               the X rows of the panel by a triangular solve with U_kk;
-//   k_rowblock  apply the panel's row interchanges to columns >= kb+nb and
-//               solve L_kk U = P B for the top rows (one column per thread);
+//               (one row per thread, the panel segment in registers) and
+//               invert the diagonal blocks L_kk, U_kk;
+//   k_tri       per 64-column tile right of the panel: apply the panel's row
+//               interchanges to the tile and form U_top = L_kk^-1 (P B)_top on
+//               MFMA; per 64-row tile of X: L21 = X_panel U_kk^-1 (in place);
 //   k_gemm      rank-nb trailing update on FP64 MFMA of the L-shaped region
 //               (all rows x S columns, and S rows x border columns); the A'
 //               block is left alone.
@@ -34,245 +35,424 @@ struct Panel {
     static constexpr int NV = Dims<P>::NV;
     static constexpr int THREADS = ((NV + 63) / 64) * 64 > 1024 ? 1024 : ((NV + 63) / 64) * 64;
     static constexpr int RPT = (NV + THREADS - 1) / THREADS;   // S rows per thread
+    static constexpr int64_t TRI = 2 * NB * NB;                 // per macro: L_kk^-1, U_kk^-1
+    static constexpr int64_t PERM = 3 * NB + 1;                 // per macro: composed interchange
 };
 
 // ---------------------------------------------------------------------------
 // Panel factorisation.  Rows of S in [kb, NV) are spread one (or RPT) per
-// thread; column j of the panel: arg-max over those rows, interchange of the
-// two rows' panel segments, scaling and rank-1 update in registers.
+// thread with their panel segment in registers; the column loop is fully
+// unrolled so every register index is a constant.  Column j: arg-max over the
+// rows (wave shuffles, then every thread reduces the per-wave results), the
+// pivot row and the row it displaces are exchanged through LDS, then scaling
+// and rank-1 update in registers (two barriers per column).
+// The panel is read and written row-coalesced: each wave moves 64 rows x CH
+// columns at a time through its own LDS tile and transposes it there.
+// Afterwards: the composed row interchange (for k_tri) and the inverses of
+// the diagonal blocks L_kk (unit lower) and U_kk go to per-macro workspaces.
+template <int P>
+struct PanelLds {
+    static constexpr int NB = Panel<P>::NB, NW = Panel<P>::THREADS / 64, NV = Dims<P>::NV;
+    static constexpr int CH = NW <= 10 ? 16 : 8;           // staging chunk width
+    static constexpr int STAGE = NW * 64 * (CH + 1);       // doubles
+    static constexpr int TRIS = NB * (NB + 1) * 3;         // T and two inverse buffers
+    static constexpr int RAW = STAGE > TRIS ? STAGE : TRIS;
+};
+
+template <int P>
+__device__ __forceinline__ void panel_move(double* Bm, double* stage, double (&seg)[Panel<P>::RPT][Panel<P>::NB],
+                                           int kb, int nb, bool store) {
+    using PN = Panel<P>;
+    using PL = PanelLds<P>;
+    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT, CH = PL::CH, ld = Bdims<P>::ld;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* tile = stage + wave * 64 * (CH + 1);
+    constexpr int PER = 64 * CH / 64;      // elements per lane per chunk
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int rbase = kb + r * PN::THREADS + wave * 64;    // rows of this wave
+#pragma unroll
+        for (int c0 = 0; c0 < NB; c0 += CH) {
+            if (store) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) tile[lane * (CH + 1) + c] = seg[r][c0 + c];
+            }
+            // wave-local: the tile is private to this wave
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int e = lane + 64 * i;
+                const int rr = e / CH, cc = e % CH;
+                const int row = rbase + rr, col = c0 + cc;
+                if (store) {
+                    if (row < NV && col < nb) Bm[(int64_t)row * ld + kb + col] = tile[rr * (CH + 1) + cc];
+                } else {
+                    tile[rr * (CH + 1) + cc] = (row < NV && col < nb) ? Bm[(int64_t)row * ld + kb + col] : 0.0;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (!store) {
+#pragma unroll
+                for (int c = 0; c < CH; ++c) seg[r][c0 + c] = tile[lane * (CH + 1) + c];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    }
+}
+
 template <int P>
 __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb,
                                                              int32_t* __restrict__ ipiv,
+                                                             int32_t* __restrict__ perm,
+                                                             double* __restrict__ tri,
                                                              int32_t* __restrict__ status) {
     using BD = Bdims<P>;
     using PN = Panel<P>;
-    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld, ROWS = BD::rows;
+    using PL = PanelLds<P>;
+    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT;
     constexpr int NW = PN::THREADS / 64;
+    __shared__ double raw[PL::RAW];        // staging tiles, later T and the inverses
     __shared__ double prow[NB];            // current pivot row segment
     __shared__ double xch[2][NB];          // row interchange buffer
-    __shared__ double U[NB][NB + 1];       // U_kk for the X-row solve
     __shared__ double redv[NW];
     __shared__ int redi[NW];
     __shared__ int piv_sh;
-    __shared__ int bad_sh;
+    __shared__ int pivs[NB];
+    __shared__ int mp[NV];
+    __shared__ int mark[NV];
     const int64_t m = blockIdx.x;
     double* Bm = B + m * BD::per_macro;
     const int nb = (NV - kb) < NB ? (NV - kb) : NB;
-    const int tid = threadIdx.x;
-    if (tid == 0) bad_sh = 0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    bool bad = false;
 
     double seg[RPT][NB];
     int rows[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        rows[r] = kb + tid + r * PN::THREADS;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-            seg[r][c] = (rows[r] < NV && c < nb) ? Bm[(int64_t)rows[r] * ld + kb + c] : 0.0;
+    for (int r = 0; r < RPT; ++r) rows[r] = kb + tid + r * PN::THREADS;
+    panel_move<P>(Bm, raw, seg, kb, nb, false);
+    for (int r = tid; r < NV; r += PN::THREADS) {
+        mp[r] = r;
+        mark[r] = 0;
     }
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
+#pragma clang loop unroll(full)
+    for (int j = 0; j < NB; ++j) {
+      if (j < nb) {                                // uniform: only the last panel is narrower
         const int col = kb + j;
-        // pivot search over rows [col, NV)
         double best = -1.0;
-        int bi = col;
+        int bi = NV;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            double x = 0.0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c == j) x = seg[r][c];
-            const double ax = fabs(x);
+            const double ax = fabs(seg[r][j]);
             if (rows[r] >= col && rows[r] < NV && (ax > best || (ax == best && rows[r] < bi))) {
                 best = ax;
                 bi = rows[r];
             }
         }
+#pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_down(best, off, 64);
-            const int oi = __shfl_down(bi, off, 64);
+            const double ob = __shfl_xor(best, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
             if (ob > best || (ob == best && oi < bi)) {
                 best = ob;
                 bi = oi;
             }
         }
-        if ((tid & 63) == 0) {
-            redv[tid >> 6] = best;
-            redi[tid >> 6] = bi;
+        if (lane == 0) {
+            redv[wave] = best;
+            redi[wave] = bi;
         }
         __syncthreads();
-        if (tid == 0) {
-            double b = redv[0];
-            int i = redi[0];
-            for (int w = 1; w < NW; ++w)
-                if (redv[w] > b || (redv[w] == b && redi[w] < i)) {
-                    b = redv[w];
-                    i = redi[w];
-                }
-            piv_sh = i;
-            ipiv[m * NV + col] = i;
-            if (!(b > 0.0) || !isfinite(b)) bad_sh = 1;
-        }
-        __syncthreads();
-        const int p = piv_sh;
-        // interchange rows col and p (panel segment only)
-        if (p != col) {
+        double b = redv[0];
+        int p = redi[0];
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                if (rows[r] == col) {
-#pragma unroll
-                    for (int c = 0; c < NB; ++c) xch[0][c] = seg[r][c];
-                }
-                if (rows[r] == p) {
-#pragma unroll
-                    for (int c = 0; c < NB; ++c) xch[1][c] = seg[r][c];
-                }
+        for (int w = 1; w < NW; ++w)
+            if (redv[w] > b || (redv[w] == b && redi[w] < p)) {
+                b = redv[w];
+                p = redi[w];
             }
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                if (rows[r] == col) {
-#pragma unroll
-                    for (int c = 0; c < NB; ++c) seg[r][c] = xch[1][c];
-                }
-                if (rows[r] == p) {
-#pragma unroll
-                    for (int c = 0; c < NB; ++c) seg[r][c] = xch[0][c];
-                }
-            }
+        if (!(b > 0.0) || !isfinite(b) || p >= NV) {
+            bad = true;
+            p = col;
         }
 #pragma unroll
-        for (int r = 0; r < RPT; ++r)
-            if (rows[r] == col) {
+        for (int r = 0; r < RPT; ++r) {
+            if (rows[r] == p) {
 #pragma unroll
                 for (int c = 0; c < NB; ++c) prow[c] = seg[r][c];
             }
+            if (rows[r] == col && p != col) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) xch[0][c] = seg[r][c];
+            }
+        }
+        if (tid == 0) pivs[j] = p;
         __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if (p != col && rows[r] == p) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) seg[r][c] = xch[0][c];
+            }
+            if (rows[r] == col) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) seg[r][c] = prow[c];
+            }
+        }
         const double pv = prow[j];
         const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (rows[r] > col && rows[r] < NV) {
-                double l = 0.0;
+                const double l = seg[r][j] * inv;
+                seg[r][j] = l;
 #pragma unroll
-                for (int c = 0; c < NB; ++c)
-                    if (c == j) l = seg[r][c] * inv;
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    if (c == j) seg[r][c] = l;
-                    else if (c > j) seg[r][c] -= l * prow[c];
-                }
+                for (int c = j + 1; c < NB; ++c) seg[r][c] -= l * prow[c];
             }
         }
         __syncthreads();
+      }
     }
-    // write back the S rows of the panel, keep U_kk for the X rows
+    panel_move<P>(Bm, raw, seg, kb, nb, true);
+    __syncthreads();
+    // diagonal block T (aliases the staging tiles)
+    double (*T)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        if (rows[r] < NV) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < nb) Bm[(int64_t)rows[r] * ld + kb + c] = seg[r][c];
-        }
         const int i = rows[r] - kb;
-        if (i >= 0 && i < nb) {
+        if (i >= 0 && i < NB) {
 #pragma unroll
-            for (int c = 0; c < NB; ++c) U[i][c] = seg[r][c];
+            for (int c = 0; c < NB; ++c) T[i][c] = (i < nb && c < nb) ? seg[r][c] : (i == c ? 1.0 : 0.0);
         }
     }
+    if (tid < nb) ipiv[m * NV + kb + tid] = pivs[tid];
     __syncthreads();
-    // X rows: L21 = X_panel U_kk^-1 (forward substitution along the row)
-    for (int r = NV + tid; r < ROWS; r += PN::THREADS) {
-        double x[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) x[c] = (c < nb) ? Bm[(int64_t)r * ld + kb + c] : 0.0;
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            if (c < nb) {
-                double s = x[c];
-#pragma unroll
-                for (int i = 0; i < NB; ++i)
-                    if (i < c) s -= x[i] * U[i][c];
-                x[c] = (U[c][c] != 0.0) ? s / U[c][c] : 0.0;
+    // composed interchange: after it row r holds the old row mp[r].  perm[m]:
+    // [0, NB) source rows of the top block, [NB, 2NB) displaced rows below the
+    // block, [2NB, 3NB) their source rows, [3NB] their number.
+    if (tid == 0) {
+        for (int i = 0; i < nb; ++i) {
+            const int p = pivs[i];
+            const int t = mp[kb + i];
+            mp[kb + i] = mp[p];
+            mp[p] = t;
+        }
+        int32_t* pm = perm + m * (3 * NB + 1);
+        int nd = 0;
+        for (int i = 0; i < nb; ++i) {
+            pm[i] = mp[kb + i];
+            const int p = pivs[i];
+            if (p >= kb + nb && !mark[p]) {
+                mark[p] = 1;
+                pm[NB + nd] = p;
+                pm[2 * NB + nd] = mp[p];
+                ++nd;
             }
         }
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-            if (c < nb) Bm[(int64_t)r * ld + kb + c] = x[c];
+        pm[3 * NB] = nd;
     }
-    if (tid == 0 && bad_sh) record_status(status, m, ST_SINGULAR);
+    // inverses of the diagonal block.  Wave 0: L_kk^-1 (unit lower).  Wave 1:
+    // U_kk^-1 as the inverse of the lower triangular J U_kk J (J reverses the
+    // index order), so both waves run the same forward substitution; the
+    // solution columns live in LDS (one column per lane).
+    double* Ti = tri + m * PN::TRI;
+    const int wU = NW > 1 ? 1 : 0;
+    for (int pass = 0; pass < (NW > 1 ? 1 : 2); ++pass) {
+        const bool isU = (NW > 1) ? (wave == wU) : (pass == 1);
+        if (wave == 0 || (NW > 1 && wave == wU)) {
+            const int c = lane;   // solve T~ x = e_c, x_i = 0 for i < c
+            double (*X)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + NB * (NB + 1) * (isU ? 2 : 1));
+            for (int i = 0; i < NB; ++i) {
+                double s = (i == c) ? 1.0 : 0.0;
+                for (int k = c; k < i; ++k) s -= (isU ? T[NB - 1 - i][NB - 1 - k] : T[i][k]) * X[k][c];
+                const double d = isU ? T[NB - 1 - i][NB - 1 - i] : 1.0;
+                X[i][c] = (i < c) ? 0.0 : ((d != 0.0) ? s / d : 0.0);
+            }
+            for (int i = 0; i < NB; ++i) {
+                if (isU) Ti[NB * NB + (NB - 1 - i) * NB + (NB - 1 - c)] = X[i][c];
+                else Ti[i * NB + c] = X[i][c];
+            }
+        }
+    }
+    if (bad && tid == 0) record_status(status, m, ST_SINGULAR);
 }
 
 // ---------------------------------------------------------------------------
-// Row interchanges and L_kk solve for the top rows [kb, kb+nb) of every
-// column c >= kb+nb (one column per thread).
+// 64 x 64 FP64 MFMA tile: acc (+)= sgn * A[r0.., 0..K) * Bt[0..K, c0..)
+// with four waves in 2 x 2, each owning 2 x 2 blocks of 16 x 16 (register r of
+// lane l holds row (l >> 4) + 4 r, column l & 15 of its block).  K is staged
+// through LDS in chunks of GK with the next chunk's global loads issued
+// before the current chunk is multiplied.
+constexpr int GT = 64;
+constexpr int GK = 32;
+
+struct TileSmem {
+    double As[2][GT][GK + 1];
+    double Bs[2][GK][GT + 1];
+};
+
+template <bool NEG>
+__device__ __forceinline__ void tile_mma(const double* A, int lda, const double* Bt, int ldb, int K, int r0,
+                                         int c0, int rows, int cols, v4d acc[2][2], TileSmem& sm) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const double sgn = NEG ? -1.0 : 1.0;
+    double ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = tid + 256 * i;
+            const int ar = e >> 5, ak = e & 31;        // A chunk 64 x 32
+            const int r = r0 + ar, k = k0 + ak;
+            ra[i] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
+            const int bk = e >> 6, bc = e & 63;        // B chunk 32 x 64
+            const int kk = k0 + bk, c = c0 + bc;
+            rb[i] = (kk < K && c < cols) ? Bt[(int64_t)kk * ldb + c] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = tid + 256 * i;
+            sm.As[buf][e >> 5][e & 31] = sgn * ra[i];
+            sm.Bs[buf][e >> 6][e & 63] = rb[i];
+        }
+    };
+    const int nchunk = (K + GK - 1) / GK;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) load((ch + 1) * GK);
+#pragma unroll
+        for (int ks = 0; ks < GK; ks += 4) {
+            const int kq = ks + (lane >> 4);
+            const double a0 = sm.As[buf][wr * 32 + (lane & 15)][kq];
+            const double a1 = sm.As[buf][wr * 32 + 16 + (lane & 15)][kq];
+            const double b0 = sm.Bs[buf][kq][wc * 32 + (lane & 15)];
+            const double b1 = sm.Bs[buf][kq][wc * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        if (ch + 1 < nchunk) stash(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// tile_mma with the K rows of Bt taken from rows srcrow[k] of Bfull.
+__device__ __forceinline__ void tile_mma_gather(const double* A, int lda, const double* Bfull, int ldb,
+                                                const int* srcrow, int K, int r0, int c0, int rows, int cols,
+                                                v4d acc[2][2], TileSmem& sm) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int nchunk = (K + GK - 1) / GK;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int k0 = ch * GK;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = tid + 256 * i;
+            const int ar = e >> 5, ak = e & 31;
+            const int r = r0 + ar, k = k0 + ak;
+            sm.As[0][ar][ak] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
+            const int bk = e >> 6, bc = e & 63;
+            const int kk = k0 + bk, c = c0 + bc;
+            sm.Bs[0][bk][bc] = (kk < K && c < cols) ? Bfull[(int64_t)srcrow[kk] * ldb + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < GK; ks += 4) {
+            const int kq = ks + (lane >> 4);
+            const double a0 = sm.As[0][wr * 32 + (lane & 15)][kq];
+            const double a1 = sm.As[0][wr * 32 + 16 + (lane & 15)][kq];
+            const double b0 = sm.Bs[0][kq][wc * 32 + (lane & 15)];
+            const double b1 = sm.Bs[0][kq][wc * 32 + 16 + (lane & 15)];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ int tile_row(int r0, int bi, int q) {
+    const int lane = threadIdx.x & 63, wr = (threadIdx.x >> 6) >> 1;
+    return r0 + wr * 32 + bi * 16 + (lane >> 4) + 4 * q;
+}
+__device__ __forceinline__ int tile_col(int c0, int bj) {
+    const int lane = threadIdx.x & 63, wc = (threadIdx.x >> 6) & 1;
+    return c0 + wc * 32 + bj * 16 + (lane & 15);
+}
+
+// ---------------------------------------------------------------------------
+// In-place triangular applications of one panel, on MFMA:
+//   blocks [0, ct):      U_top[:, c-tile] <- L_kk^-1 U_top[:, c-tile]   (columns >= kb+nb)
+//   blocks [ct, ct+rt):  L21[r-tile, :]   <- X_panel[r-tile, :] U_kk^-1 (rows NV..)
+// Each workgroup reads the whole 64 x 64 (or 64 x nb) block it overwrites
+// before writing it.
 template <int P>
-__global__ void __launch_bounds__(256) k_rowblock(double* __restrict__ B, int kb,
-                                                  const int32_t* __restrict__ ipiv) {
+__global__ void __launch_bounds__(256) k_tri(double* B, int kb, const double* __restrict__ tri,
+                                             const int32_t* __restrict__ perm) {
     using BD = Bdims<P>;
-    constexpr int NB = Panel<P>::NB, NV = Dims<P>::NV, ld = BD::ld;
-    __shared__ double Lk[NB][NB + 1];
-    __shared__ int src_top[NB];          // original row whose value lands in row kb+i
-    __shared__ int out_dst[NB], out_src[NB];
-    __shared__ int n_out;
-    __shared__ int map[NV];
+    using PN = Panel<P>;
+    constexpr int NB = PN::NB, NV = PN::NV, ld = BD::ld, ROWS = BD::rows;
+    __shared__ TileSmem sm;
+    __shared__ int pm[3 * NB + 1];
     const int64_t m = blockIdx.y;
     double* Bm = B + m * BD::per_macro;
+    const double* Ti = tri + m * PN::TRI;
     const int nb = (NV - kb) < NB ? (NV - kb) : NB;
-    const int tid = threadIdx.x;
-    // the interchanges, composed into a gather
-    for (int r = tid; r < NV; r += blockDim.x) map[r] = r;
-    for (int i = tid; i < NB * NB; i += blockDim.x) {
-        const int r = i / NB, c = i % NB;
-        Lk[r][c] = (r < nb && c < nb) ? Bm[(int64_t)(kb + r) * ld + kb + c] : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        for (int i = 0; i < nb; ++i) {
-            const int p = ipiv[m * NV + kb + i];
-            const int t = map[kb + i];
-            map[kb + i] = map[p];
-            map[p] = t;
+    const int c0 = kb + nb;
+    const int ct = (ld - c0 + GT - 1) / GT;
+    v4d acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+    if ((int)blockIdx.x < ct) {
+        const int cc = c0 + blockIdx.x * GT;     // columns [cc, cc+64) of the S rows
+        for (int i = threadIdx.x; i < 3 * NB + 1; i += blockDim.x) pm[i] = perm[m * (3 * NB + 1) + i];
+        __syncthreads();
+        const int nd = pm[3 * NB];
+        // displaced rows below the block read their new values before anything is written
+        double mvr[NB * GT / 256];
+#pragma unroll
+        for (int i = 0; i < NB * GT / 256; ++i) {
+            const int e = threadIdx.x + 256 * i, q = e / GT, c = cc + e % GT;
+            mvr[i] = (q < nd && c < ld) ? Bm[(int64_t)pm[2 * NB + q] * ld + c] : 0.0;
         }
-        int no = 0;
-        for (int i = 0; i < nb; ++i) {
-            src_top[i] = map[kb + i];
-            const int p = ipiv[m * NV + kb + i];
-            if (p >= kb + nb && map[p] != p) {
-                bool seen = false;
-                for (int q = 0; q < no; ++q)
-                    if (out_dst[q] == p) seen = true;
-                if (!seen) {
-                    out_dst[no] = p;
-                    out_src[no] = map[p];
-                    ++no;
+        tile_mma_gather(Ti, NB, Bm, ld, pm, nb, 0, cc, nb, ld, acc, sm);
+#pragma unroll
+        for (int i = 0; i < NB * GT / 256; ++i) {
+            const int e = threadIdx.x + 256 * i, q = e / GT, c = cc + e % GT;
+            if (q < nd && c < ld) Bm[(int64_t)pm[NB + q] * ld + c] = mvr[i];
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
+                    if (r < nb && c < ld) Bm[(int64_t)(kb + r) * ld + c] = acc[bi][bj][q];
                 }
-            }
-        }
-        n_out = no;
+    } else {
+        const int rr = NV + (blockIdx.x - ct) * GT;   // rows [rr, rr+64) of the X block
+        tile_mma<false>(Bm + kb, ld, Ti + NB * NB, NB, nb, rr, 0, ROWS, nb, acc, sm);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = tile_row(rr, bi, q), c = tile_col(0, bj);
+                    if (r < ROWS && c < nb) Bm[(int64_t)r * ld + kb + c] = acc[bi][bj][q];
+                }
     }
-    __syncthreads();
-    const int c = kb + nb + blockIdx.x * blockDim.x + tid;
-    if (c >= ld) return;
-    double x[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) x[i] = (i < nb) ? Bm[(int64_t)src_top[i] * ld + c] : 0.0;
-    const int no = n_out;
-    double moved[NB];
-    for (int q = 0; q < no; ++q) moved[q < NB ? q : 0] = Bm[(int64_t)out_src[q] * ld + c];
-    for (int q = 0; q < no; ++q) Bm[(int64_t)out_dst[q] * ld + c] = moved[q < NB ? q : 0];
-    // unit lower solve with L_kk
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        double s = x[i];
-#pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (k < i) s -= Lk[i][k] * x[k];
-        x[i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-        if (i < nb) Bm[(int64_t)(kb + i) * ld + c] = x[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -296,65 +476,29 @@ struct GemmArgs {
     int tiles_c;             // column tiles
 };
 
-constexpr int GT = 64;       // tile edge
-constexpr int GK = 16;       // K chunk staged in LDS
-
 // TAG only separates the trailing-update launches (0) from the final Schur
 // product (1) in profiles; the code is the same.
 template <int TAG>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-    __shared__ double As[GT][GK + 1];
-    __shared__ double Bs[GK][GT + 1];
+    __shared__ TileSmem sm;
     const int64_t m = blockIdx.y;
     const int tr = blockIdx.x / g.tiles_c, tc = blockIdx.x % g.tiles_c;
     const int r0 = tr * GT, c0 = tc * GT;
     if (r0 >= g.skip_r && c0 >= g.skip_c) return;   // tile entirely in the masked corner
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const double* A = g.A + m * g.sA;
-    const double* Bt = g.Bt + m * g.sB;
     const double* C = g.C + m * g.sC;
     v4d acc[2][2];
-    // initial accumulators: C
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + wr * 32 + bi * 16 + (lane >> 4) + 4 * q;
-                const int c = c0 + wc * 32 + bj * 16 + (lane & 15);
+                const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
                 const bool in = r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c);
                 acc[bi][bj][q] = in ? C[(int64_t)r * g.ldc + c] : 0.0;
             }
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
-        // stage -A (64 x 16) and Bt (16 x 64)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i;
-            const int ar = e >> 4, ak = e & 15;
-            const int r = r0 + ar, k = k0 + ak;
-            As[ar][ak] = (r < g.rows && k < g.K) ? -A[(int64_t)r * g.lda + k] : 0.0;
-            const int bk = e >> 6, bc = e & 63;
-            const int kk = k0 + bk, c = c0 + bc;
-            Bs[bk][bc] = (kk < g.K && c < g.cols) ? Bt[(int64_t)kk * g.ldb + c] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < GK; ks += 4) {
-            const int kq = ks + (lane >> 4);
-            const double a0 = As[wr * 32 + (lane & 15)][kq];
-            const double a1 = As[wr * 32 + 16 + (lane & 15)][kq];
-            const double b0 = Bs[kq][wc * 32 + (lane & 15)];
-            const double b1 = Bs[kq][wc * 32 + 16 + (lane & 15)];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-    double* D = g.D + m * g.sD;
+    tile_mma<true>(g.A + m * g.sA, g.lda, g.Bt + m * g.sB, g.ldb, g.K, r0, c0, g.rows, g.cols, acc, sm);
+    double* D = g.D ? g.D + m * g.sD : nullptr;
     double* D2 = g.D2 ? g.D2 + m * g.sD2 : nullptr;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -362,11 +506,10 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = r0 + wr * 32 + bi * 16 + (lane >> 4) + 4 * q;
-                const int c = c0 + wc * 32 + bj * 16 + (lane & 15);
+                const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
                 if (r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c)) {
                     if (D2 && c >= g.dsplit) D2[(int64_t)r * g.ldd2 + (c - g.dsplit)] = acc[bi][bj][q];
-                    else D[(int64_t)r * g.ldd + c] = acc[bi][bj][q];
+                    else if (D) D[(int64_t)r * g.ldd + c] = acc[bi][bj][q];
                 }
             }
 }

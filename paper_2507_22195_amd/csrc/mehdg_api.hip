@@ -32,6 +32,8 @@ struct mehdg_ctx {
     double* d_minvrq = nullptr;     // M^-1 R_Q per macro
     double* d_B = nullptr;          // bordered matrices
     int32_t* d_ipiv = nullptr;      // pivot rows of the LU of S
+    double* d_tri = nullptr;        // inverses of the diagonal blocks of the current panel
+    int32_t* d_perm = nullptr;      // composed row interchange of the current panel
     int64_t bytes = 0;
     // kernel timing with HIP events (mehdg_profile_*)
     bool prof = false;
@@ -103,6 +105,8 @@ mehdg_err ensure_block_workspace(mehdg_ctx* c) {
     if ((e = dev_alloc(c, &c->d_coefF, c->n_macro * (int64_t)6 * D::S * COEF_F)) != MEHDG_OK) return e;
     if ((e = dev_alloc(c, &c->d_minvrq, c->n_macro * (int64_t)15 * D::n)) != MEHDG_OK) return e;
     if ((e = dev_alloc(c, &c->d_ipiv, c->n_macro * (int64_t)D::NV)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_tri, c->n_macro * Panel<P>::TRI)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_perm, c->n_macro * Panel<P>::PERM)) != MEHDG_OK) return e;
     if ((e = dev_alloc(c, &c->d_B, c->n_macro * Bdims<P>::per_macro)) != MEHDG_OK) return e;
     return MEHDG_OK;
 }
@@ -174,14 +178,16 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         const int nb = (NV - kb) < PN::NB ? (NV - kb) : PN::NB;
         {
             Timed t(c, MEHDG_PROF_PANEL, st);
-            hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, c->d_ipiv, c->d_status);
+            hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, c->d_ipiv, c->d_perm,
+                               c->d_tri, c->d_status);
         }
         if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
-        const int ncols = ld - (kb + nb);
-        if (ncols > 0) {
+        {
+            const int ct = (ld - (kb + nb) + GT - 1) / GT;
+            const int rt = (NH + GT - 1) / GT;
             Timed t(c, MEHDG_PROF_ROWBLOCK, st);
-            hipLaunchKernelGGL(k_rowblock<P>, dim3((unsigned)((ncols + 255) / 256), M), dim3(256), 0, st, B, kb,
-                               c->d_ipiv);
+            hipLaunchKernelGGL(k_tri<P>, dim3((unsigned)(ct + rt), M), dim3(256), 0, st, B, kb, c->d_tri,
+                               c->d_perm);
             if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
         }
         // trailing update of the L-shaped region (A' is formed at the end)
@@ -302,6 +308,8 @@ mehdg_err mehdg_destroy(mehdg_ctx* c) {
     (void)hipFree(c->d_coefF);
     (void)hipFree(c->d_minvrq);
     (void)hipFree(c->d_ipiv);
+    (void)hipFree(c->d_tri);
+    (void)hipFree(c->d_perm);
     (void)hipFree(c->d_B);
     delete c;
     return MEHDG_OK;
