@@ -28,6 +28,45 @@ namespace mehdg {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Wave-wide maximum of a double with DPP row permutations (quad swaps, half
+// and full row mirrors) and a read of the four row results; every lane gets
+// the maximum.  NaN inputs are ignored by fmax.
+__device__ __forceinline__ double dpp_perm_f64(double v, int ctrl) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    switch (ctrl) {
+        case 0:
+            lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+            break;
+        case 1:
+            lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+            break;
+        case 2:
+            lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+            break;
+        default:
+            lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+            hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
+            break;
+    }
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane_f64(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+    v = fmax(v, dpp_perm_f64(v, 0));
+    v = fmax(v, dpp_perm_f64(v, 1));
+    v = fmax(v, dpp_perm_f64(v, 2));
+    v = fmax(v, dpp_perm_f64(v, 3));
+    return fmax(fmax(read_lane_f64(v, 0), read_lane_f64(v, 16)), fmax(read_lane_f64(v, 32), read_lane_f64(v, 48)));
+}
+
 // panel width of the blocked factorisation
 template <int P>
 struct Panel {
@@ -43,63 +82,13 @@ struct Panel {
 // Panel factorisation.  Rows of S in [kb, NV) are spread one (or RPT) per
 // thread with their panel segment in registers; the column loop is fully
 // unrolled so every register index is a constant.  Column j: arg-max over the
-// rows (wave shuffles, then every thread reduces the per-wave results), the
-// pivot row and the row it displaces are exchanged through LDS, then scaling
-// and rank-1 update in registers (two barriers per column).
-// The panel is read and written row-coalesced: each wave moves 64 rows x CH
-// columns at a time through its own LDS tile and transposes it there.
+// rows (DPP wave maximum, then every thread reduces the per-wave results),
+// the pivot row and the row it displaces are exchanged through LDS, then
+// scaling and rank-1 update in registers.  Look-ahead: column j+1 is updated
+// first and its pivot search is issued before the rest of the update, and
+// the LDS buffers alternate by column parity, so two barriers per column.
 // Afterwards: the composed row interchange (for k_tri) and the inverses of
 // the diagonal blocks L_kk (unit lower) and U_kk go to per-macro workspaces.
-template <int P>
-struct PanelLds {
-    static constexpr int NB = Panel<P>::NB, NW = Panel<P>::THREADS / 64, NV = Dims<P>::NV;
-    static constexpr int CH = NW <= 10 ? 16 : 8;           // staging chunk width
-    static constexpr int STAGE = NW * 64 * (CH + 1);       // doubles
-    static constexpr int TRIS = NB * (NB + 1) * 3;         // T and two inverse buffers
-    static constexpr int RAW = STAGE > TRIS ? STAGE : TRIS;
-};
-
-template <int P>
-__device__ __forceinline__ void panel_move(double* Bm, double* stage, double (&seg)[Panel<P>::RPT][Panel<P>::NB],
-                                           int kb, int nb, bool store) {
-    using PN = Panel<P>;
-    using PL = PanelLds<P>;
-    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT, CH = PL::CH, ld = Bdims<P>::ld;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double* tile = stage + wave * 64 * (CH + 1);
-    constexpr int PER = 64 * CH / 64;      // elements per lane per chunk
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int rbase = kb + r * PN::THREADS + wave * 64;    // rows of this wave
-#pragma unroll
-        for (int c0 = 0; c0 < NB; c0 += CH) {
-            if (store) {
-#pragma unroll
-                for (int c = 0; c < CH; ++c) tile[lane * (CH + 1) + c] = seg[r][c0 + c];
-            }
-            // wave-local: the tile is private to this wave
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const int e = lane + 64 * i;
-                const int rr = e / CH, cc = e % CH;
-                const int row = rbase + rr, col = c0 + cc;
-                if (store) {
-                    if (row < NV && col < nb) Bm[(int64_t)row * ld + kb + col] = tile[rr * (CH + 1) + cc];
-                } else {
-                    tile[rr * (CH + 1) + cc] = (row < NV && col < nb) ? Bm[(int64_t)row * ld + kb + col] : 0.0;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            if (!store) {
-#pragma unroll
-                for (int c = 0; c < CH; ++c) seg[r][c0 + c] = tile[lane * (CH + 1) + c];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        }
-    }
-}
-
 template <int P>
 __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb,
                                                              int32_t* __restrict__ ipiv,
@@ -108,15 +97,13 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
                                                              int32_t* __restrict__ status) {
     using BD = Bdims<P>;
     using PN = Panel<P>;
-    using PL = PanelLds<P>;
-    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT;
+    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
     constexpr int NW = PN::THREADS / 64;
-    __shared__ double raw[PL::RAW];        // staging tiles, later T and the inverses
-    __shared__ double prow[NB];            // current pivot row segment
-    __shared__ double xch[2][NB];          // row interchange buffer
-    __shared__ double redv[NW];
-    __shared__ int redi[NW];
-    __shared__ int piv_sh;
+    __shared__ double raw[3 * NB * (NB + 1)];   // T and the two inverses
+    __shared__ double prow[2][NB];         // pivot row segment (by column parity)
+    __shared__ double xch[2][NB];          // segment of the row the pivot displaces
+    __shared__ double redv[2][NW];
+    __shared__ int redi[2][NW];
     __shared__ int pivs[NB];
     __shared__ int mp[NV];
     __shared__ int mark[NV];
@@ -130,47 +117,54 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     int rows[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) rows[r] = kb + tid + r * PN::THREADS;
-    panel_move<P>(Bm, raw, seg, kb, nb, false);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            seg[r][c] = (rows[r] < NV && c < nb) ? Bm[(int64_t)rows[r] * ld + kb + c] : 0.0;
     for (int r = tid; r < NV; r += PN::THREADS) {
         mp[r] = r;
         mark[r] = 0;
     }
-    __syncthreads();
-#pragma clang loop unroll(full)
-    for (int j = 0; j < NB; ++j) {
-      if (j < nb) {                                // uniform: only the last panel is narrower
-        const int col = kb + j;
+    // candidate pivot of column j among rows >= kb+j: wave arg-max to LDS
+    auto candidate = [&](int j, int bf, const double (&cv)[RPT]) {
         double best = -1.0;
         int bi = NV;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const double ax = fabs(seg[r][j]);
-            if (rows[r] >= col && rows[r] < NV && (ax > best || (ax == best && rows[r] < bi))) {
+            const double ax = fabs(cv[r]);
+            if (rows[r] >= kb + j && rows[r] < NV && (ax > best || (ax == best && rows[r] < bi))) {
                 best = ax;
                 bi = rows[r];
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
+        const double wm = wave_max_f64(best);
+        const unsigned long long bal = __ballot(best == wm);
+        const int ol = bal ? (__ffsll((long long)bal) - 1) : 0;
+        const int wrow = __builtin_amdgcn_readlane(bi, ol);
         if (lane == 0) {
-            redv[wave] = best;
-            redi[wave] = bi;
+            redv[bf][wave] = wm;
+            redi[bf][wave] = wrow;
         }
+    };
+    {
+        double cv[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) cv[r] = seg[r][0];
+        candidate(0, 0, cv);
+    }
+#pragma clang loop unroll(full)
+    for (int j = 0; j < NB; ++j) {
+      if (j < nb) {                                // uniform: only the last panel is narrower
+        const int col = kb + j, bf = j & 1;
         __syncthreads();
-        double b = redv[0];
-        int p = redi[0];
+        double b = redv[bf][0];
+        int p = redi[bf][0];
 #pragma unroll
         for (int w = 1; w < NW; ++w)
-            if (redv[w] > b || (redv[w] == b && redi[w] < p)) {
-                b = redv[w];
-                p = redi[w];
+            if (redv[bf][w] > b || (redv[bf][w] == b && redi[bf][w] < p)) {
+                b = redv[bf][w];
+                p = redi[bf][w];
             }
         if (!(b > 0.0) || !isfinite(b) || p >= NV) {
             bad = true;
@@ -180,44 +174,62 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         for (int r = 0; r < RPT; ++r) {
             if (rows[r] == p) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) prow[c] = seg[r][c];
+                for (int c = 0; c < NB; ++c) prow[bf][c] = seg[r][c];
             }
             if (rows[r] == col && p != col) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) xch[0][c] = seg[r][c];
+                for (int c = 0; c < NB; ++c) xch[bf][c] = seg[r][c];
             }
         }
         if (tid == 0) pivs[j] = p;
         __syncthreads();
+        const double pv = prow[bf][j];
+        const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+        double l[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (p != col && rows[r] == p) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) seg[r][c] = xch[0][c];
-            }
             if (rows[r] == col) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) seg[r][c] = prow[c];
+                for (int c = 0; c < NB; ++c) seg[r][c] = prow[bf][c];
+            } else if (p != col && rows[r] == p) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) seg[r][c] = xch[bf][c];
+            }
+            const bool below = rows[r] > col && rows[r] < NV;
+            l[r] = below ? seg[r][j] * inv : 0.0;
+            if (below) {
+                seg[r][j] = l[r];
+                if (j + 1 < NB) seg[r][(j + 1) % NB] -= l[r] * prow[bf][(j + 1) % NB];   // look-ahead column
             }
         }
-        const double pv = prow[j];
-        const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+        if (j + 1 < nb) {
+            double cv[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) cv[r] = (j + 1 < NB) ? seg[r][(j + 1) % NB] : 0.0;
+            candidate(j + 1, bf ^ 1, cv);
+        }
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             if (rows[r] > col && rows[r] < NV) {
-                const double l = seg[r][j] * inv;
-                seg[r][j] = l;
 #pragma unroll
-                for (int c = j + 1; c < NB; ++c) seg[r][c] -= l * prow[c];
+                for (int c = j + 2; c < NB; ++c) seg[r][c] -= l[r] * prow[bf][c];
             }
         }
-        __syncthreads();
       }
     }
-    panel_move<P>(Bm, raw, seg, kb, nb, true);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        if (rows[r] < NV) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < nb) Bm[(int64_t)rows[r] * ld + kb + c] = seg[r][c];
+        }
+    }
     __syncthreads();
-    // diagonal block T (aliases the staging tiles)
+    // diagonal block T and the two inverses X_L, X_U
     double (*T)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
+    double (*XL)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + NB * (NB + 1));
+    double (*XU)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + 2 * NB * (NB + 1));
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int i = rows[r] - kb;
@@ -225,6 +237,11 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
 #pragma unroll
             for (int c = 0; c < NB; ++c) T[i][c] = (i < nb && c < nb) ? seg[r][c] : (i == c ? 1.0 : 0.0);
         }
+    }
+    for (int e = tid; e < NB * NB; e += PN::THREADS) {
+        const int i = e / NB, c = e % NB;
+        XL[i][c] = (i == c) ? 1.0 : 0.0;
+        XU[i][c] = (i == c) ? 1.0 : 0.0;
     }
     if (tid < nb) ipiv[m * NV + kb + tid] = pivs[tid];
     __syncthreads();
@@ -252,28 +269,34 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         }
         pm[3 * NB] = nd;
     }
-    // inverses of the diagonal block.  Wave 0: L_kk^-1 (unit lower).  Wave 1:
-    // U_kk^-1 as the inverse of the lower triangular J U_kk J (J reverses the
-    // index order), so both waves run the same forward substitution; the
-    // solution columns live in LDS (one column per lane).
-    double* Ti = tri + m * PN::TRI;
-    const int wU = NW > 1 ? 1 : 0;
-    for (int pass = 0; pass < (NW > 1 ? 1 : 2); ++pass) {
-        const bool isU = (NW > 1) ? (wave == wU) : (pass == 1);
-        if (wave == 0 || (NW > 1 && wave == wU)) {
-            const int c = lane;   // solve T~ x = e_c, x_i = 0 for i < c
-            double (*X)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + NB * (NB + 1) * (isU ? 2 : 1));
-            for (int i = 0; i < NB; ++i) {
-                double s = (i == c) ? 1.0 : 0.0;
-                for (int k = c; k < i; ++k) s -= (isU ? T[NB - 1 - i][NB - 1 - k] : T[i][k]) * X[k][c];
-                const double d = isU ? T[NB - 1 - i][NB - 1 - i] : 1.0;
-                X[i][c] = (i < c) ? 0.0 : ((d != 0.0) ? s / d : 0.0);
+    // L_kk^-1 (forward, unit diagonal) by one half of the workgroup and
+    // U_kk^-1 (backward; rows scaled by 1/U_kk at the end) by the other, one
+    // elimination step per barrier.
+    constexpr int GN = PN::THREADS / 2;
+    const bool gU = tid >= GN;
+    const int gt = gU ? tid - GN : tid;
+    for (int s = 0; s < NB; ++s) {
+        if (!gU) {
+            const int k = s;
+            for (int e = gt; e < (NB - 1 - k) * NB; e += GN) {
+                const int i = k + 1 + e / NB, c = e % NB;
+                XL[i][c] -= T[i][k] * XL[k][c];
             }
-            for (int i = 0; i < NB; ++i) {
-                if (isU) Ti[NB * NB + (NB - 1 - i) * NB + (NB - 1 - c)] = X[i][c];
-                else Ti[i * NB + c] = X[i][c];
+        } else {
+            const int k = NB - 1 - s;
+            const double invd = 1.0 / T[k][k];
+            for (int e = gt; e < k * NB; e += GN) {
+                const int i = e / NB, c = e % NB;
+                XU[i][c] -= T[i][k] * (XU[k][c] * invd);
             }
         }
+        __syncthreads();
+    }
+    double* Ti = tri + m * PN::TRI;
+    for (int e = tid; e < NB * NB; e += PN::THREADS) {
+        const int i = e / NB, c = e % NB;
+        Ti[e] = XL[i][c];
+        Ti[NB * NB + e] = XU[i][c] / T[i][i];
     }
     if (bad && tid == 0) record_status(status, m, ST_SINGULAR);
 }
