@@ -71,51 +71,64 @@ __global__ void __launch_bounds__(256) k_minv_rq(const double* __restrict__ R_q,
 }
 
 // ---------------------------------------------------------------------------
+// Row workgroups build the KG rows (k = 0..KG-1 of one test node) together:
+// KG = 1: smaller LDS footprint, several workgroups per CU (measured faster
+// than building all five rows per pass, whose accumulators fill the LDS).
+template <int P>
+struct RowCfg {
+    static constexpr int KG = 1;
+    static constexpr int THREADS = 256;
+};
+
 template <int P>
 struct RowLds {
     using D = Dims<P>;
+    static constexpr int KG = RowCfg<P>::KG;
     static constexpr int E3 = (P + 1) * (P + 1) * (P + 1);
     static constexpr int E2 = (P + 1) * (P + 1);
-    double av[5][D::n];         // coefficient of trial v_{l,b}
-    double aq[15][D::n];        // coefficient of trial q_{l,j,c}  (index 3 l + j)
-    double ah[6][5][D::nf];     // coefficient of trial vhat_{f,l,e}
-    double wv[E3][20];          // per sub-element Gauss point: [0,5) value trial, [5,20) q trial
-    double wf[E2][25];          // per sub-face Gauss point: [0,5) v, [5,10) vhat, [10,25) q
-    double red[4];
+    static constexpr int WV = E3 * 20 * KG;     // per sub-element Gauss point: [0,5) value trial, [5,20) q trial
+    static constexpr int WF = E2 * 25 * KG;     // per sub-face Gauss point: [0,5) v, [5,10) vhat, [10,25) q
+    double av[KG][5][D::n];         // coefficient of trial v_{l,b}
+    double aq[KG][15][D::n];        // coefficient of trial q_{l,j,c}  (index 3 l + j)
+    double ah[KG][6][5][D::nf];     // coefficient of trial vhat_{f,l,e}
+    double w[WV > WF ? WV : WF];    // work buffer of the current sub-element or sub-face
+    double red[KG][RowCfg<P>::THREADS / 64];
     Tab1D t;
 };
 
 template <int P>
 __device__ void row_zero(RowLds<P>& L) {
     using D = Dims<P>;
-    double* p = &L.av[0][0];
-    for (int i = threadIdx.x; i < 20 * D::n; i += blockDim.x) p[i] = 0.0;   // av and aq are contiguous
-    double* h = &L.ah[0][0][0];
-    for (int i = threadIdx.x; i < 30 * D::nf; i += blockDim.x) h[i] = 0.0;
+    constexpr int KG = RowLds<P>::KG;
+    double* p = &L.av[0][0][0];
+    for (int i = threadIdx.x; i < KG * 20 * D::n; i += blockDim.x) p[i] = 0.0;   // av and aq are contiguous
+    double* h = &L.ah[0][0][0][0];
+    for (int i = threadIdx.x; i < KG * 30 * D::nf; i += blockDim.x) h[i] = 0.0;
 }
 
-// Volume part of one row: test function phi_a (or d_i phi_a), node a, row k,
-// for the sub-element (e1,e2,e3).
+// Volume part of the rows (k0 .. k0+KG-1) of node a for the sub-element (e1,e2,e3).
 template <int P>
 __device__ void row_volume(RowLds<P>& L, const double* __restrict__ coefV, int64_t m, int a1, int a2, int a3,
-                           int e1, int e2, int e3, int k, bool viscous) {
+                           int e1, int e2, int e3, int k0, bool viscous) {
     using D = Dims<P>;
     using R = RowLds<P>;
-    constexpr int n1d = D::n1d, nq1 = D::nq1, G = D::G;
+    constexpr int n1d = D::n1d, nq1 = D::nq1, G = D::G, KG = R::KG;
     constexpr int Q = P + 1;
-    for (int gl = threadIdx.x; gl < R::E3; gl += blockDim.x) {
+    for (int idx = threadIdx.x; idx < R::E3 * KG; idx += blockDim.x) {
+        const int gl = idx % R::E3, kk = idx / R::E3, k = k0 + kk;
         const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
         const int g = g1 + nq1 * (g2 + nq1 * g3);
         const double B1 = L.t.B[g1][a1], B2 = L.t.B[g2][a2], B3 = L.t.B[g3][a3];
         const double t0 = B1 * B2 * B3;
         const double ti[3] = {L.t.D[g1][a1] * B2 * B3, B1 * L.t.D[g2][a2] * B3, B1 * B2 * L.t.D[g3][a3]};
         const double* c = coefV + ((int64_t)m * G + g) * COEF_V;
+        double* w = L.w + (kk * R::E3 + gl) * 20;
 #pragma unroll
         for (int l = 0; l < 5; ++l) {
             double w0 = t0 * c[5 * k + l];
 #pragma unroll
             for (int i = 0; i < 3; ++i) w0 += ti[i] * c[25 + 25 * i + 5 * k + l];
-            L.wv[gl][l] = w0;
+            w[l] = w0;
         }
         if (viscous) {
 #pragma unroll
@@ -125,89 +138,100 @@ __device__ void row_volume(RowLds<P>& L, const double* __restrict__ coefV, int64
                     double wq = 0.0;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) wq += ti[i] * c[100 + 25 * (3 * i + j) + 5 * k + l];
-                    L.wv[gl][5 + 3 * l + j] = wq;
+                    w[5 + 3 * l + j] = wq;
                 }
         }
     }
     __syncthreads();
-    const int nent = (viscous ? 20 : 5) * R::E3;
+    const int nf_ = viscous ? 20 : 5;
+    const int nent = KG * nf_ * R::E3;
     for (int idx = threadIdx.x; idx < nent; idx += blockDim.x) {
-        const int fld = idx / R::E3, bl = idx % R::E3;   // fld < 5: v trial l; else q trial (l,j)
+        const int bl = idx % R::E3, rest = idx / R::E3;
+        const int fld = rest % nf_, kk = rest / nf_;     // fld < 5: v trial l; else q trial (l,j)
         const int b1 = e1 * P + bl % Q, b2 = e2 * P + (bl / Q) % Q, b3 = e3 * P + bl / (Q * Q);
+        const double* w = L.w + kk * R::E3 * 20 + fld;
         double acc = 0.0;
         for (int gl = 0; gl < R::E3; ++gl) {
             const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
-            acc += L.wv[gl][fld] * (L.t.B[g1][b1] * L.t.B[g2][b2] * L.t.B[g3][b3]);
+            acc += w[gl * 20] * (L.t.B[g1][b1] * L.t.B[g2][b2] * L.t.B[g3][b3]);
         }
         const int b = b1 + n1d * (b2 + n1d * b3);
-        if (fld < 5) L.av[fld][b] += acc;
-        else L.aq[fld - 5][b] += acc;
+        if (fld < 5) L.av[kk][fld][b] += acc;
+        else L.aq[kk][fld - 5][b] += acc;
     }
     __syncthreads();
 }
 
-// Face part of one row on face f, sub-face (s1 block e1, s2 block e2); the test
-// function on the face has 2-D factors at the tangential indices (c1, c2).
+// Face part of the rows on face f, sub-face (e1, e2); the test function on the
+// face has 2-D factors at the tangential indices (c1, c2).
 template <int P>
 __device__ void row_face(RowLds<P>& L, const double* __restrict__ coefF, int64_t m, int f, int c1, int c2,
-                         int e1, int e2, int k, bool viscous) {
+                         int e1, int e2, int k0, bool viscous) {
     using D = Dims<P>;
     using R = RowLds<P>;
-    constexpr int n1d = D::n1d, nq1 = D::nq1, S = D::S;
+    constexpr int n1d = D::n1d, nq1 = D::nq1, S = D::S, KG = R::KG;
     constexpr int Q = P + 1;
-    for (int sl = threadIdx.x; sl < R::E2; sl += blockDim.x) {
+    for (int idx = threadIdx.x; idx < R::E2 * KG; idx += blockDim.x) {
+        const int sl = idx % R::E2, kk = idx / R::E2, k = k0 + kk;
         const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
         const int s = s1 + nq1 * s2;
         const double t = L.t.B[s1][c1] * L.t.B[s2][c2];
         const double* c = coefF + ((int64_t)m * 6 * S + f * S + s) * COEF_F;
+        double* w = L.w + (kk * R::E2 + sl) * 25;
 #pragma unroll
         for (int l = 0; l < 5; ++l) {
-            L.wf[sl][l] = t * c[5 * k + l];
-            L.wf[sl][5 + l] = t * c[25 + 5 * k + l];
+            w[l] = t * c[5 * k + l];
+            w[5 + l] = t * c[25 + 5 * k + l];
         }
         if (viscous) {
 #pragma unroll
             for (int l = 0; l < 5; ++l)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) L.wf[sl][10 + 3 * l + j] = t * c[50 + 25 * j + 5 * k + l];
+                for (int j = 0; j < 3; ++j) w[10 + 3 * l + j] = t * c[50 + 25 * j + 5 * k + l];
         }
     }
     __syncthreads();
     const int d = face_axis(f), t1 = face_t1(f), t2 = face_t2(f);
     const int ad = face_side(f) ? (n1d - 1) : 0;
-    const int nent = (viscous ? 25 : 10) * R::E2;
+    const int nf_ = viscous ? 25 : 10;
+    const int nent = KG * nf_ * R::E2;
     for (int idx = threadIdx.x; idx < nent; idx += blockDim.x) {
-        const int fld = idx / R::E2, bl = idx % R::E2;
+        const int bl = idx % R::E2, rest = idx / R::E2;
+        const int fld = rest % nf_, kk = rest / nf_;
         const int b1 = e1 * P + bl % Q, b2 = e2 * P + bl / Q;
+        const double* w = L.w + kk * R::E2 * 25 + fld;
         double acc = 0.0;
         for (int sl = 0; sl < R::E2; ++sl) {
             const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
-            acc += L.wf[sl][fld] * (L.t.B[s1][b1] * L.t.B[s2][b2]);
+            acc += w[sl * 25] * (L.t.B[s1][b1] * L.t.B[s2][b2]);
         }
         int bi[3];
         bi[d] = ad;
         bi[t1] = b1;
         bi[t2] = b2;
         const int b = bi[0] + n1d * (bi[1] + n1d * bi[2]);
-        if (fld < 5) L.av[fld][b] += acc;
-        else if (fld < 10) L.ah[f][fld - 5][b1 + n1d * b2] += acc;
-        else L.aq[fld - 10][b] += acc;
+        if (fld < 5) L.av[kk][fld][b] += acc;
+        else if (fld < 10) L.ah[kk][f][fld - 5][b1 + n1d * b2] += acc;
+        else L.aq[kk][fld - 10][b] += acc;
     }
     __syncthreads();
 }
 
-// Eliminate Q and write one row of B (plus its right-hand side entry).
+// Eliminate Q and write the KG rows row0 + kk*rstride of B (plus their
+// right-hand side entries -R + A_.q A_qq^-1 R_Q).
 template <int P>
-__device__ void row_write(RowLds<P>& L, double* __restrict__ Brow, const double* __restrict__ minvrq,
-                          double Rval, const double hinv[3], bool viscous) {
+__device__ void row_write(RowLds<P>& L, double* __restrict__ Bm, int row0, int rstride,
+                          const double* __restrict__ minvrq, const double* Rvals, const double hinv[3],
+                          bool viscous) {
     using D = Dims<P>;
     using BD = Bdims<P>;
-    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH;
-    for (int col = threadIdx.x; col < BD::ld; col += blockDim.x) {
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH, KG = RowLds<P>::KG;
+    for (int idx = threadIdx.x; idx < KG * BD::ld; idx += blockDim.x) {
+        const int kk = idx / BD::ld, col = idx % BD::ld;
         double val = 0.0;
         if (col < NV) {
             const int l = col / n, b = col % n;
-            val = L.av[l][b];
+            val = L.av[kk][l][b];
             if (viscous) {
                 const int bi[3] = {b % n1d, (b / n1d) % n1d, b / (n1d * n1d)};
 #pragma unroll
@@ -216,14 +240,14 @@ __device__ void row_write(RowLds<P>& L, double* __restrict__ Brow, const double*
                     const int base = b - bi[j] * stride;
                     double acc = 0.0;
 #pragma unroll
-                    for (int c = 0; c < n1d; ++c) acc += L.aq[3 * l + j][base + c * stride] * L.t.Lam[c][bi[j]];
+                    for (int c = 0; c < n1d; ++c) acc += L.aq[kk][3 * l + j][base + c * stride] * L.t.Lam[c][bi[j]];
                     val -= hinv[j] * acc;
                 }
             }
         } else if (col < NV + NH) {
             const int r = col - NV;
             const int f = r / (5 * nf), l = (r / nf) % 5, e = r % nf;
-            val = L.ah[f][l][e];
+            val = L.ah[kk][f][l][e];
             if (viscous) {
                 const int d = face_axis(f);
                 int ci[3];
@@ -234,24 +258,35 @@ __device__ void row_write(RowLds<P>& L, double* __restrict__ Brow, const double*
 #pragma unroll
                 for (int cd = 0; cd < n1d; ++cd) {
                     ci[d] = cd;
-                    acc += L.aq[3 * l + d][ci[0] + n1d * (ci[1] + n1d * ci[2])] * L.t.Minv[cd][iF];
+                    acc += L.aq[kk][3 * l + d][ci[0] + n1d * (ci[1] + n1d * ci[2])] * L.t.Minv[cd][iF];
                 }
                 val += face_sign(f) * hinv[d] * acc;
             }
         }
-        if (col != NV + NH) Brow[col] = val;
+        if (col != NV + NH) Bm[(int64_t)(row0 + kk * rstride) * BD::ld + col] = val;
     }
-    // right-hand side: -R + A_.q A_qq^-1 R_Q
-    double part = 0.0;
+    // right-hand sides
+    double part[KG];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) part[kk] = 0.0;
     if (viscous)
-        for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) part += (&L.aq[0][0])[i] * minvrq[i];
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-    if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = part;
+        for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) {
+            const double mr = minvrq[i];
+#pragma unroll
+            for (int kk = 0; kk < KG; ++kk) part[kk] += (&L.aq[kk][0][0])[i] * mr;
+        }
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) {
+        double v = part[kk];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if ((threadIdx.x & 63) == 0) L.red[kk][threadIdx.x >> 6] = v;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < KG) {
+        const int kk = threadIdx.x;
         double s = 0.0;
-        for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += L.red[i];
-        Brow[NV + NH] = -Rval + s;
+        for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += L.red[kk][i];
+        Bm[(int64_t)(row0 + kk * rstride) * BD::ld + NV + NH] = -Rvals[kk] + s;
     }
     __syncthreads();
 }
@@ -265,13 +300,16 @@ __device__ void stage_tables(RowLds<P>& L, const Tab1D* __restrict__ tab) {
 
 // Rows of the interior equations: one workgroup per (macro, node a), 5 rows.
 template <int P>
-__global__ void __launch_bounds__(256) k_rows_v(const double* __restrict__ coefV, const double* __restrict__ coefF,
-                                                const double* __restrict__ R_v, const double* __restrict__ minvrq,
-                                                const double* __restrict__ hs, const Tab1D* __restrict__ tab,
-                                                int viscous_i, double* __restrict__ B) {
+__global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_v(const double* __restrict__ coefV,
+                                                               const double* __restrict__ coefF,
+                                                               const double* __restrict__ R_v,
+                                                               const double* __restrict__ minvrq,
+                                                               const double* __restrict__ hs,
+                                                               const Tab1D* __restrict__ tab, int viscous_i,
+                                                               double* __restrict__ B) {
     using D = Dims<P>;
     using BD = Bdims<P>;
-    constexpr int n1d = D::n1d, n = D::n;
+    constexpr int n1d = D::n1d, n = D::n, KG = RowLds<P>::KG;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     RowLds<P>& L = *reinterpret_cast<RowLds<P>*>(smem_raw);
     const int64_t m = blockIdx.y;
@@ -285,13 +323,13 @@ __global__ void __launch_bounds__(256) k_rows_v(const double* __restrict__ coefV
     support_1d<P>(a2, lo[1], hi[1]);
     support_1d<P>(a3, lo[2], hi[2]);
     const int ai[3] = {a1, a2, a3};
-    for (int k = 0; k < 5; ++k) {
+    for (int k0 = 0; k0 < 5; k0 += KG) {
         row_zero<P>(L);
         __syncthreads();
         for (int e3 = lo[2]; e3 <= hi[2]; ++e3)
             for (int e2 = lo[1]; e2 <= hi[1]; ++e2)
                 for (int e1 = lo[0]; e1 <= hi[0]; ++e1)
-                    row_volume<P>(L, coefV, m, a1, a2, a3, e1, e2, e3, k, viscous);
+                    row_volume<P>(L, coefV, m, a1, a2, a3, e1, e2, e3, k0, viscous);
         for (int f = 0; f < 6; ++f) {
             const int d = face_axis(f);
             if (ai[d] != (face_side(f) ? n1d - 1 : 0)) continue;
@@ -300,23 +338,26 @@ __global__ void __launch_bounds__(256) k_rows_v(const double* __restrict__ coefV
             support_1d<P>(c1, l1, u1);
             support_1d<P>(c2, l2, u2);
             for (int e2 = l2; e2 <= u2; ++e2)
-                for (int e1 = l1; e1 <= u1; ++e1) row_face<P>(L, coefF, m, f, c1, c2, e1, e2, k, viscous);
+                for (int e1 = l1; e1 <= u1; ++e1) row_face<P>(L, coefF, m, f, c1, c2, e1, e2, k0, viscous);
         }
-        const int row = k * n + a;
-        row_write<P>(L, B + m * BD::per_macro + (int64_t)row * BD::ld, minvrq + m * 15 * n,
-                     R_v[(m * 5 + k) * n + a], hinv, viscous);
+        double Rv[KG];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) Rv[kk] = R_v[(m * 5 + k0 + kk) * n + a];
+        row_write<P>(L, B + m * BD::per_macro, k0 * n + a, n, minvrq + m * 15 * n, Rv, hinv, viscous);
     }
 }
 
 // Rows of the trace equations: one workgroup per (macro, face f, trace node c), 5 rows.
 template <int P>
-__global__ void __launch_bounds__(256) k_rows_h(const double* __restrict__ coefF, const double* __restrict__ R_vh,
-                                                const double* __restrict__ minvrq, const double* __restrict__ hs,
-                                                const Tab1D* __restrict__ tab, int viscous_i,
-                                                double* __restrict__ B) {
+__global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_h(const double* __restrict__ coefF,
+                                                               const double* __restrict__ R_vh,
+                                                               const double* __restrict__ minvrq,
+                                                               const double* __restrict__ hs,
+                                                               const Tab1D* __restrict__ tab, int viscous_i,
+                                                               double* __restrict__ B) {
     using D = Dims<P>;
     using BD = Bdims<P>;
-    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, KG = RowLds<P>::KG;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     RowLds<P>& L = *reinterpret_cast<RowLds<P>*>(smem_raw);
     const int64_t m = blockIdx.y;
@@ -328,14 +369,16 @@ __global__ void __launch_bounds__(256) k_rows_h(const double* __restrict__ coefF
     int l1, u1, l2, u2;
     support_1d<P>(c1, l1, u1);
     support_1d<P>(c2, l2, u2);
-    for (int k = 0; k < 5; ++k) {
+    for (int k0 = 0; k0 < 5; k0 += KG) {
         row_zero<P>(L);
         __syncthreads();
         for (int e2 = l2; e2 <= u2; ++e2)
-            for (int e1 = l1; e1 <= u1; ++e1) row_face<P>(L, coefF, m, f, c1, c2, e1, e2, k, viscous);
-        const int row = NV + (f * 5 + k) * nf + c;
-        row_write<P>(L, B + m * BD::per_macro + (int64_t)row * BD::ld, minvrq + m * 15 * n,
-                     R_vh[((m * 6 + f) * 5 + k) * nf + c], hinv, viscous);
+            for (int e1 = l1; e1 <= u1; ++e1) row_face<P>(L, coefF, m, f, c1, c2, e1, e2, k0, viscous);
+        double Rv[KG];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) Rv[kk] = R_vh[((m * 6 + f) * 5 + k0 + kk) * nf + c];
+        row_write<P>(L, B + m * BD::per_macro, NV + (f * 5 + k0) * nf + c, nf, minvrq + m * 15 * n, Rv, hinv,
+                     viscous);
     }
 }
 

@@ -308,7 +308,8 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
 // through LDS in chunks of GK with the next chunk's global loads issued
 // before the current chunk is multiplied.
 constexpr int GT = 64;
-constexpr int GK = 32;
+constexpr int GK = 16;
+constexpr int GL = GT * GK / 256;              // elements of each operand chunk per thread
 
 struct TileSmem {
     double As[2][GT][GK + 1];
@@ -321,25 +322,25 @@ __device__ __forceinline__ void tile_mma(const double* A, int lda, const double*
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const double sgn = NEG ? -1.0 : 1.0;
-    double ra[8], rb[8];
+    double ra[GL], rb[GL];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < GL; ++i) {
             const int e = tid + 256 * i;
-            const int ar = e >> 5, ak = e & 31;        // A chunk 64 x 32
+            const int ar = e / GK, ak = e % GK;        // A chunk GT x GK
             const int r = r0 + ar, k = k0 + ak;
             ra[i] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
-            const int bk = e >> 6, bc = e & 63;        // B chunk 32 x 64
+            const int bk = e / GT, bc = e % GT;        // B chunk GK x GT
             const int kk = k0 + bk, c = c0 + bc;
             rb[i] = (kk < K && c < cols) ? Bt[(int64_t)kk * ldb + c] : 0.0;
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < GL; ++i) {
             const int e = tid + 256 * i;
-            sm.As[buf][e >> 5][e & 31] = sgn * ra[i];
-            sm.Bs[buf][e >> 6][e & 63] = rb[i];
+            sm.As[buf][e / GK][e % GK] = sgn * ra[i];
+            sm.Bs[buf][e / GT][e % GT] = rb[i];
         }
     };
     const int nchunk = (K + GK - 1) / GK;
@@ -376,12 +377,12 @@ __device__ __forceinline__ void tile_mma_gather(const double* A, int lda, const 
     for (int ch = 0; ch < nchunk; ++ch) {
         const int k0 = ch * GK;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < GL; ++i) {
             const int e = tid + 256 * i;
-            const int ar = e >> 5, ak = e & 31;
+            const int ar = e / GK, ak = e % GK;
             const int r = r0 + ar, k = k0 + ak;
             sm.As[0][ar][ak] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
-            const int bk = e >> 6, bc = e & 63;
+            const int bk = e / GT, bc = e % GT;
             const int kk = k0 + bk, c = c0 + bc;
             sm.Bs[0][bk][bc] = (kk < K && c < cols) ? Bfull[(int64_t)srcrow[kk] * ldb + c] : 0.0;
         }
@@ -509,7 +510,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     const int r0 = tr * GT, c0 = tc * GT;
     if (r0 >= g.skip_r && c0 >= g.skip_c) return;   // tile entirely in the masked corner
     const double* C = g.C + m * g.sC;
-    v4d acc[2][2];
+    // C is fetched first and only added after the K loop, so its latency
+    // overlaps the staging and the MFMA work.
+    double cr[2][2][4];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -518,8 +521,13 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
             for (int q = 0; q < 4; ++q) {
                 const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
                 const bool in = r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c);
-                acc[bi][bj][q] = in ? C[(int64_t)r * g.ldc + c] : 0.0;
+                cr[bi][bj][q] = in ? C[(int64_t)r * g.ldc + c] : 0.0;
             }
+    v4d acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
     tile_mma<true>(g.A + m * g.sA, g.lda, g.Bt + m * g.sB, g.ldb, g.K, r0, c0, g.rows, g.cols, acc, sm);
     double* D = g.D ? g.D + m * g.sD : nullptr;
     double* D2 = g.D2 ? g.D2 + m * g.sD2 : nullptr;
@@ -531,8 +539,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
             for (int q = 0; q < 4; ++q) {
                 const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
                 if (r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c)) {
-                    if (D2 && c >= g.dsplit) D2[(int64_t)r * g.ldd2 + (c - g.dsplit)] = acc[bi][bj][q];
-                    else if (D) D[(int64_t)r * g.ldd + c] = acc[bi][bj][q];
+                    const double v = cr[bi][bj][q] + acc[bi][bj][q];
+                    if (D2 && c >= g.dsplit) D2[(int64_t)r * g.ldd2 + (c - g.dsplit)] = v;
+                    else if (D) D[(int64_t)r * g.ldd + c] = v;
                 }
             }
 }
