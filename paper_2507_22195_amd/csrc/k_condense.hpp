@@ -9,16 +9,21 @@
 // and the top rows hold U (of S), U12 = L^-1 P (-Y) and y = L^-1 P r_V, which
 // is all that back-substitution needs (the factor L of S is not kept).
 //
-// Schedule per 64-column panel [kb, kb+nb):
-//   k_panel     one workgroup per macro: factor the S rows of the panel
-//               (one row per thread, the panel segment in registers) and
-//               invert the diagonal blocks L_kk, U_kk;
-//   k_tri       per 64-column tile right of the panel: apply the panel's row
-//               interchanges to the tile and form U_top = L_kk^-1 (P B)_top on
-//               MFMA; per 64-row tile of X: L21 = X_panel U_kk^-1 (in place);
-//   k_gemm      rank-nb trailing update on FP64 MFMA of the L-shaped region
-//               (all rows x S columns, and S rows x border columns); the A'
-//               block is left alone.
+// Two-level blocking.  The columns of S go in outer blocks of OB = 128, each
+// made of (up to) two register panels of NB = 64:
+//   k_panel     one workgroup per macro: factor the S rows of one panel (one
+//               row per thread, the panel segment in registers) and invert
+//               its diagonal blocks L_kk, U_kk.  The second panel of a block
+//               also re-orders the first panel's L columns by its own
+//               interchanges, composes the interchanges of both panels and
+//               forms the inverse of the block's unit-lower diagonal block;
+//   k_tri       per 64-column tile right of the (panel or outer) block: apply
+//               the composed row interchange and form U_top = L^-1 (P B)_top
+//               on MFMA; per 128-row tile of X: L21 = X_panel U_kk^-1;
+//   k_gemm      rank-nb update on FP64 MFMA: inside the outer block, the
+//               second panel's columns after the first panel; after the
+//               block, the L-shaped trailing region (all rows x S columns and
+//               S rows x border columns) with K = 128; A' is left alone.
 // Then one k_gemm with K = N_V forms Ahat = A' - L21 U12 and bhat = r_hat - L21 y
 // directly in the caller's arrays.
 #pragma once
@@ -67,16 +72,74 @@ __device__ __forceinline__ double wave_max_f64(double v) {
     return fmax(fmax(read_lane_f64(v, 0), read_lane_f64(v, 16)), fmax(read_lane_f64(v, 32), read_lane_f64(v, 48)));
 }
 
-// panel width of the blocked factorisation
+// panel and outer block widths of the blocked factorisation
 template <int P>
 struct Panel {
     static constexpr int NB = 64;
+    static constexpr int OB = 2 * NB;
     static constexpr int NV = Dims<P>::NV;
     static constexpr int THREADS = ((NV + 63) / 64) * 64 > 1024 ? 1024 : ((NV + 63) / 64) * 64;
     static constexpr int RPT = (NV + THREADS - 1) / THREADS;   // S rows per thread
-    static constexpr int64_t TRI = 2 * NB * NB;                 // per macro: L_kk^-1, U_kk^-1
-    static constexpr int64_t PERM = 3 * NB + 1;                 // per macro: composed interchange
+    // per macro: L^-1, U^-1 of the first and of the second panel (NB x NB
+    // each), then L^-1 of the outer block's unit-lower diagonal block (OB x OB)
+    static constexpr int64_t TRI = 4 * NB * NB + OB * OB;
+    static constexpr int LINV1 = 0, UINV1 = NB * NB, LINV2 = 2 * NB * NB, UINV2 = 3 * NB * NB, LINVW = 4 * NB * NB;
+    // per macro: composed interchange of the current block: [0, OB) source
+    // rows of the top rows, [OB, 2 OB) rows below the block that change,
+    // [2 OB, 3 OB) their source rows, [3 OB] their number
+    static constexpr int64_t PERM = 3 * OB + 1;
 };
+
+// 64 x 64 x 64 products of LDS matrices (leading dimension N + 1) on FP64
+// MFMA: the sixteen 16 x 16 output tiles are dealt to the NW waves, TPW per
+// wave; register r of lane l holds row (l >> 4) + 4 r, column l & 15 of a tile.
+template <int N, int NW, int TPW>
+__device__ __forceinline__ void lds_mm64(const double (*A)[N + 1], const double (*Bm)[N + 1], v4d (&acc)[TPW]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+        const int t = wave + NW * i;
+        if (t < 16) {
+            const int ti = t >> 2, tj = t & 3;
+#pragma unroll
+            for (int k0 = 0; k0 < N; k0 += 4) {
+                const double a = A[ti * 16 + (lane & 15)][k0 + (lane >> 4)];
+                const double b = Bm[k0 + (lane >> 4)][tj * 16 + (lane & 15)];
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int N, int NW, int TPW>
+__device__ __forceinline__ void lds_mm64_store(const v4d (&acc)[TPW], double (*D)[N + 1], double scale) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int t = wave + NW * i;
+        if (t < 16) {
+            const int ti = t >> 2, tj = t & 3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) D[ti * 16 + (lane >> 4) + 4 * r][tj * 16 + (lane & 15)] = scale * acc[i][r];
+        }
+    }
+}
+
+template <int N, int NW, int TPW>
+__device__ __forceinline__ void lds_mm64_store_global(const v4d (&acc)[TPW], double* D, int ldd, double scale) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        const int t = wave + NW * i;
+        if (t < 16) {
+            const int ti = t >> 2, tj = t & 3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                D[(int64_t)(ti * 16 + (lane >> 4) + 4 * r) * ldd + tj * 16 + (lane & 15)] = scale * acc[i][r];
+        }
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Panel factorisation.  Rows of S in [kb, NV) are spread one (or RPT) per
@@ -87,19 +150,24 @@ struct Panel {
 // scaling and rank-1 update in registers.  Look-ahead: column j+1 is updated
 // first and its pivot search is issued before the rest of the update, and
 // the LDS buffers alternate by column parity, so two barriers per column.
-// Afterwards: the composed row interchange (for k_tri) and the inverses of
-// the diagonal blocks L_kk (unit lower) and U_kk go to per-macro workspaces.
+// Afterwards: the inverses of the diagonal blocks L_kk (unit lower) and U_kk
+// go to per-macro workspaces, and the composed row interchange of the block
+// to perm.  A panel with kb > kb0 is the second panel of the outer block that
+// starts at kb0 (see the file comment).
 template <int P>
-__global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb,
+__global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb, int kb0,
                                                              int32_t* __restrict__ ipiv,
                                                              int32_t* __restrict__ perm,
                                                              double* __restrict__ tri,
                                                              int32_t* __restrict__ status) {
     using BD = Bdims<P>;
     using PN = Panel<P>;
-    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
+    constexpr int NB = PN::NB, OB = PN::OB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
     constexpr int NW = PN::THREADS / 64;
     __shared__ double raw[3 * NB * (NB + 1)];   // T and the two inverses
+    __shared__ int mvd[2 * NB], mvs[2 * NB];    // rows whose first-panel segment moves, and their sources
+    __shared__ int nmv;
+    __shared__ int pv1[NB];                      // the first panel's pivots (second panel only)
     __shared__ double prow[2][NB];         // pivot row segment (by column parity)
     __shared__ double xch[2][NB];          // segment of the row the pivot displaces
     __shared__ double redv[2][NW];
@@ -225,8 +293,7 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
                 if (c < nb) Bm[(int64_t)rows[r] * ld + kb + c] = seg[r][c];
         }
     }
-    __syncthreads();
-    // diagonal block T and the two inverses X_L, X_U
+    // diagonal block T (the register segment is dead after this)
     double (*T)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
     double (*XL)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + NB * (NB + 1));
     double (*XU)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + 2 * NB * (NB + 1));
@@ -244,10 +311,10 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         XU[i][c] = (i == c) ? 1.0 : 0.0;
     }
     if (tid < nb) ipiv[m * NV + kb + tid] = pivs[tid];
+    const bool second = kb > kb0;
+    if (second && tid < NB) pv1[tid] = ipiv[m * NV + kb0 + tid];
     __syncthreads();
-    // composed interchange: after it row r holds the old row mp[r].  perm[m]:
-    // [0, NB) source rows of the top block, [NB, 2NB) displaced rows below the
-    // block, [2NB, 3NB) their source rows, [3NB] their number.
+    // this panel's interchange: afterwards row r holds the old row mp[r]
     if (tid == 0) {
         for (int i = 0; i < nb; ++i) {
             const int p = pivs[i];
@@ -255,19 +322,86 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
             mp[kb + i] = mp[p];
             mp[p] = t;
         }
-        int32_t* pm = perm + m * (3 * NB + 1);
+        int n = 0;
+        int32_t* pm = perm + m * PN::PERM;
+        for (int i = 0; i < nb; ++i) {
+            const int r = kb + i;
+            if (second && mp[r] != r) {
+                mvd[n] = r;
+                mvs[n] = mp[r];
+                ++n;
+            }
+            if (!second) pm[i] = mp[r];
+        }
         int nd = 0;
         for (int i = 0; i < nb; ++i) {
-            pm[i] = mp[kb + i];
             const int p = pivs[i];
             if (p >= kb + nb && !mark[p]) {
                 mark[p] = 1;
-                pm[NB + nd] = p;
-                pm[2 * NB + nd] = mp[p];
-                ++nd;
+                if (second) {
+                    mvd[n] = p;
+                    mvs[n] = mp[p];
+                    ++n;
+                } else {
+                    pm[OB + nd] = p;
+                    pm[2 * OB + nd] = mp[p];
+                    ++nd;
+                }
             }
         }
-        pm[3 * NB] = nd;
+        nmv = n;
+        if (!second) pm[3 * OB] = nd;
+    }
+    __syncthreads();
+    if (second) {
+        // the first panel's L columns follow this panel's interchange (read all, then write)
+        constexpr int MVE = (2 * NB * NB + PN::THREADS - 1) / PN::THREADS;
+        const int cnt = nmv * NB;
+        double mv[MVE];
+#pragma unroll
+        for (int q = 0; q < MVE; ++q) {
+            const int e = tid + q * PN::THREADS;
+            mv[q] = e < cnt ? Bm[(int64_t)mvs[e / NB] * ld + kb0 + e % NB] : 0.0;
+        }
+        // interchange of the whole outer block: the first panel's pivots, then this panel's
+        for (int r = kb0 + tid; r < NV; r += PN::THREADS) {
+            mp[r] = r;
+            mark[r] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < MVE; ++q) {
+            const int e = tid + q * PN::THREADS;
+            if (e < cnt) Bm[(int64_t)mvd[e / NB] * ld + kb0 + e % NB] = mv[q];
+        }
+        if (tid == 0) {
+            for (int i = 0; i < NB; ++i) {
+                const int p = pv1[i];
+                const int t = mp[kb0 + i];
+                mp[kb0 + i] = mp[p];
+                mp[p] = t;
+            }
+            for (int i = 0; i < nb; ++i) {
+                const int p = pivs[i];
+                const int t = mp[kb + i];
+                mp[kb + i] = mp[p];
+                mp[p] = t;
+            }
+            const int w = kb + nb - kb0;
+            int32_t* pm = perm + m * PN::PERM;
+            for (int i = 0; i < w; ++i) pm[i] = mp[kb0 + i];
+            int nd = 0;
+            for (int i = 0; i < NB + nb; ++i) {
+                const int p = i < NB ? pv1[i] : pivs[i - NB];
+                if (p >= kb0 + w && !mark[p]) {
+                    mark[p] = 1;
+                    pm[OB + nd] = p;
+                    pm[2 * OB + nd] = mp[p];
+                    ++nd;
+                }
+            }
+            pm[3 * OB] = nd;
+        }
     }
     // L_kk^-1 (forward, unit diagonal) by one half of the workgroup and
     // U_kk^-1 (backward; rows scaled by 1/U_kk at the end) by the other, one
@@ -293,28 +427,70 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         __syncthreads();
     }
     double* Ti = tri + m * PN::TRI;
+    double* Tl = Ti + (second ? PN::LINV2 : PN::LINV1);
+    double* Tu = Ti + (second ? PN::UINV2 : PN::UINV1);
     for (int e = tid; e < NB * NB; e += PN::THREADS) {
         const int i = e / NB, c = e % NB;
-        Ti[e] = XL[i][c];
-        Ti[NB * NB + e] = XU[i][c] / T[i][i];
+        Tl[e] = XL[i][c];
+        Tu[e] = XU[i][c] / T[i][i];
+    }
+    if (second) {
+        // inverse of the block's unit-lower diagonal block [[L11, 0], [L21, L22]]:
+        // [[L11^-1, 0], [-L22^-1 L21 L11^-1, L22^-1]]   (L22^-1 = XL), both products on MFMA
+        __syncthreads();
+        for (int e = tid; e < NB * NB; e += PN::THREADS) {
+            const int i = e / NB, c = e % NB;
+            T[i][c] = (i < nb) ? Bm[(int64_t)(kb + i) * ld + kb0 + c] : 0.0;
+            XU[i][c] = Ti[PN::LINV1 + e];
+        }
+        __syncthreads();
+        constexpr int TPW = (16 + NW - 1) / NW;
+        v4d acc[TPW];
+        lds_mm64<NB, NW, TPW>(T, XU, acc);
+        __syncthreads();
+        lds_mm64_store<NB, NW, TPW>(acc, T, 1.0);
+        __syncthreads();
+        lds_mm64<NB, NW, TPW>(XL, T, acc);
+        double* LW = Ti + PN::LINVW;
+        lds_mm64_store_global<NB, NW, TPW>(acc, LW + NB * OB, OB, -1.0);
+        for (int e = tid; e < OB * OB; e += PN::THREADS) {
+            const int i = e / OB, c = e % OB;
+            if (i < NB) LW[e] = c < NB ? XU[i][c] : 0.0;
+            else if (c >= NB) LW[e] = XL[i - NB][c - NB];
+        }
     }
     if (bad && tid == 0) record_status(status, m, ST_SINGULAR);
 }
 
 // ---------------------------------------------------------------------------
-// 64 x 64 FP64 MFMA tile: acc (+)= sgn * A[r0.., 0..K) * Bt[0..K, c0..)
-// with four waves in 2 x 2, each owning 2 x 2 blocks of 16 x 16 (register r of
-// lane l holds row (l >> 4) + 4 r, column l & 15 of its block).  K is staged
-// through LDS in chunks of GK with the next chunk's global loads issued
-// before the current chunk is multiplied.
+// GM x GT = 128 x 64 FP64 MFMA tile: acc (+)= sgn * A[r0.., 0..K) * Bt[0..K, c0..)
+// with eight waves in 4 x 2, each owning 2 x 2 blocks of 16 x 16 (register r
+// of lane l holds row (l >> 4) + 4 r, column l & 15 of its block).  K is
+// staged through LDS in chunks of GK with the next chunk's global loads
+// issued before the current chunk is multiplied.
 constexpr int GT = 64;
+constexpr int GM = 128;
 constexpr int GK = 16;
-constexpr int GL = GT * GK / 256;              // elements of each operand chunk per thread
+constexpr int GTHREADS = 512;
+constexpr int GLA = GM * GK / GTHREADS;        // A elements of a chunk per thread
+constexpr int GLB = GK * GT / GTHREADS;        // B elements of a chunk per thread
 
 struct TileSmem {
-    double As[2][GT][GK + 1];
+    double As[2][GM][GK + 1];
     double Bs[2][GK][GT + 1];
 };
+
+// Tiles of one macro-element run on one XCD: workgroups are dealt to the
+// eight XCDs in turn, so workgroup b is tile (b / 8) % tiles of macro
+// ((b / 8) / tiles) * 8 + b % 8.  The grid has ceil(n / 8) * 8 * tiles
+// workgroups; m >= n marks an idle one.
+__device__ __forceinline__ void xcd_tile(int tiles, int64_t& m, int& tile) {
+    const unsigned b = blockIdx.x, x = b & 7u, loc = b >> 3;
+    m = (int64_t)(loc / (unsigned)tiles) * 8 + x;
+    tile = (int)(loc % (unsigned)tiles);
+}
+
+inline unsigned xcd_grid(int tiles, int64_t n) { return (unsigned)(((n + 7) / 8) * 8 * tiles); }
 
 template <bool NEG>
 __device__ __forceinline__ void tile_mma(const double* A, int lda, const double* Bt, int ldb, int K, int r0,
@@ -322,24 +498,32 @@ __device__ __forceinline__ void tile_mma(const double* A, int lda, const double*
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const double sgn = NEG ? -1.0 : 1.0;
-    double ra[GL], rb[GL];
+    double ra[GLA], rb[GLB];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < GL; ++i) {
-            const int e = tid + 256 * i;
-            const int ar = e / GK, ak = e % GK;        // A chunk GT x GK
+        for (int i = 0; i < GLA; ++i) {
+            const int e = tid + GTHREADS * i;
+            const int ar = e / GK, ak = e % GK;
             const int r = r0 + ar, k = k0 + ak;
             ra[i] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
-            const int bk = e / GT, bc = e % GT;        // B chunk GK x GT
+        }
+#pragma unroll
+        for (int i = 0; i < GLB; ++i) {
+            const int e = tid + GTHREADS * i;
+            const int bk = e / GT, bc = e % GT;
             const int kk = k0 + bk, c = c0 + bc;
             rb[i] = (kk < K && c < cols) ? Bt[(int64_t)kk * ldb + c] : 0.0;
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < GL; ++i) {
-            const int e = tid + 256 * i;
+        for (int i = 0; i < GLA; ++i) {
+            const int e = tid + GTHREADS * i;
             sm.As[buf][e / GK][e % GK] = sgn * ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < GLB; ++i) {
+            const int e = tid + GTHREADS * i;
             sm.Bs[buf][e / GT][e % GT] = rb[i];
         }
     };
@@ -377,11 +561,15 @@ __device__ __forceinline__ void tile_mma_gather(const double* A, int lda, const 
     for (int ch = 0; ch < nchunk; ++ch) {
         const int k0 = ch * GK;
 #pragma unroll
-        for (int i = 0; i < GL; ++i) {
-            const int e = tid + 256 * i;
+        for (int i = 0; i < GLA; ++i) {
+            const int e = tid + GTHREADS * i;
             const int ar = e / GK, ak = e % GK;
             const int r = r0 + ar, k = k0 + ak;
             sm.As[0][ar][ak] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < GLB; ++i) {
+            const int e = tid + GTHREADS * i;
             const int bk = e / GT, bc = e % GT;
             const int kk = k0 + bk, c = c0 + bc;
             sm.Bs[0][bk][bc] = (kk < K && c < cols) ? Bfull[(int64_t)srcrow[kk] * ldb + c] : 0.0;
@@ -412,48 +600,64 @@ __device__ __forceinline__ int tile_col(int c0, int bj) {
     return c0 + wc * 32 + bj * 16 + (lane & 15);
 }
 
-// ---------------------------------------------------------------------------
-// In-place triangular applications of one panel, on MFMA:
-//   blocks [0, ct):      U_top[:, c-tile] <- L_kk^-1 U_top[:, c-tile]   (columns >= kb+nb)
-//   blocks [ct, ct+rt):  L21[r-tile, :]   <- X_panel[r-tile, :] U_kk^-1 (rows NV..)
-// Each workgroup reads the whole 64 x 64 (or 64 x nb) block it overwrites
-// before writing it.
-template <int P>
-__global__ void __launch_bounds__(256) k_tri(double* B, int kb, const double* __restrict__ tri,
-                                             const int32_t* __restrict__ perm) {
-    using BD = Bdims<P>;
-    using PN = Panel<P>;
-    constexpr int NB = PN::NB, NV = PN::NV, ld = BD::ld, ROWS = BD::rows;
-    __shared__ TileSmem sm;
-    __shared__ int pm[3 * NB + 1];
-    const int64_t m = blockIdx.y;
-    double* Bm = B + m * BD::per_macro;
-    const double* Ti = tri + m * PN::TRI;
-    const int nb = (NV - kb) < NB ? (NV - kb) : NB;
-    const int c0 = kb + nb;
-    const int ct = (ld - c0 + GT - 1) / GT;
-    v4d acc[2][2];
+__device__ __forceinline__ void zero_acc(v4d acc[2][2]) {
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-    if ((int)blockIdx.x < ct) {
-        const int cc = c0 + blockIdx.x * GT;     // columns [cc, cc+64) of the S rows
-        for (int i = threadIdx.x; i < 3 * NB + 1; i += blockDim.x) pm[i] = perm[m * (3 * NB + 1) + i];
+}
+
+// ---------------------------------------------------------------------------
+// In-place triangular applications on MFMA after a panel or an outer block:
+//   tiles [0, ct):       U_top[:, c-tile] <- L^-1 (P B)_top[:, c-tile] for the
+//                        columns [c_lo, c_hi); L^-1 is w x w, the top rows are
+//                        [kb0, kb0+w) and P the composed interchange in perm
+//   tiles [ct, ct+rt):   L21[r-tile, :] <- X_panel[r-tile, :] U_kk^-1 for the
+//                        X rows and the panel columns [kp, kp+np)
+// Each workgroup reads everything it overwrites before writing it.
+struct TriArgs {
+    int kb0, w;          // top rows [kb0, kb0+w), also the K of the column tiles
+    int loff, ldl;       // L^-1 of the top rows: offset in the per-macro workspace, leading dimension
+    int c_lo, c_hi;      // columns that get U_top
+    int kp, np;          // panel whose X columns become L21
+    int uoff;            // that panel's U_kk^-1 (leading dimension NB) in the workspace
+    int ct, rt;          // column tiles, X row tiles
+};
+
+template <int P>
+__global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __restrict__ tri,
+                                                  const int32_t* __restrict__ perm, TriArgs a, int64_t n_macro) {
+    using BD = Bdims<P>;
+    using PN = Panel<P>;
+    constexpr int NB = PN::NB, OB = PN::OB, NV = PN::NV, ld = BD::ld, ROWS = BD::rows;
+    constexpr int MV = OB * GT / GTHREADS;       // displaced-row elements per thread
+    __shared__ TileSmem sm;
+    __shared__ int pm[3 * OB + 1];
+    int64_t m;
+    int tile;
+    xcd_tile(a.ct + a.rt, m, tile);
+    if (m >= n_macro) return;
+    double* Bm = B + m * BD::per_macro;
+    const double* Ti = tri + m * PN::TRI;
+    v4d acc[2][2];
+    zero_acc(acc);
+    if (tile < a.ct) {
+        const int cc = a.c_lo + tile * GT;     // columns [cc, cc+64)
+        for (int i = threadIdx.x; i < 3 * OB + 1; i += GTHREADS) pm[i] = perm[m * PN::PERM + i];
         __syncthreads();
-        const int nd = pm[3 * NB];
-        // displaced rows below the block read their new values before anything is written
-        double mvr[NB * GT / 256];
+        const int nd = pm[3 * OB];
+        // rows below the block that change read their new values before anything is written
+        double mvr[MV];
 #pragma unroll
-        for (int i = 0; i < NB * GT / 256; ++i) {
-            const int e = threadIdx.x + 256 * i, q = e / GT, c = cc + e % GT;
-            mvr[i] = (q < nd && c < ld) ? Bm[(int64_t)pm[2 * NB + q] * ld + c] : 0.0;
+        for (int i = 0; i < MV; ++i) {
+            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+            mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
         }
-        tile_mma_gather(Ti, NB, Bm, ld, pm, nb, 0, cc, nb, ld, acc, sm);
+        tile_mma_gather(Ti + a.loff, a.ldl, Bm, ld, pm, a.w, 0, cc, a.w, a.c_hi, acc, sm);
 #pragma unroll
-        for (int i = 0; i < NB * GT / 256; ++i) {
-            const int e = threadIdx.x + 256 * i, q = e / GT, c = cc + e % GT;
-            if (q < nd && c < ld) Bm[(int64_t)pm[NB + q] * ld + c] = mvr[i];
+        for (int i = 0; i < MV; ++i) {
+            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+            if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
@@ -462,11 +666,11 @@ __global__ void __launch_bounds__(256) k_tri(double* B, int kb, const double* __
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
-                    if (r < nb && c < ld) Bm[(int64_t)(kb + r) * ld + c] = acc[bi][bj][q];
+                    if (r < a.w && c < a.c_hi) Bm[(int64_t)(a.kb0 + r) * ld + c] = acc[bi][bj][q];
                 }
     } else {
-        const int rr = NV + (blockIdx.x - ct) * GT;   // rows [rr, rr+64) of the X block
-        tile_mma<false>(Bm + kb, ld, Ti + NB * NB, NB, nb, rr, 0, ROWS, nb, acc, sm);
+        const int rr = NV + (tile - a.ct) * GM;   // rows [rr, rr+128) of the X block
+        tile_mma<false>(Bm + a.kp, ld, Ti + a.uoff, NB, a.np, rr, 0, ROWS, a.np, acc, sm);
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -474,13 +678,13 @@ __global__ void __launch_bounds__(256) k_tri(double* B, int kb, const double* __
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int r = tile_row(rr, bi, q), c = tile_col(0, bj);
-                    if (r < ROWS && c < nb) Bm[(int64_t)r * ld + kb + c] = acc[bi][bj][q];
+                    if (r < ROWS && c < a.np) Bm[(int64_t)r * ld + a.kp + c] = acc[bi][bj][q];
                 }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP64 MFMA product  D = C - A * Bt  on a 64 x 64 tile per workgroup.
+// Batched FP64 MFMA product  D = C - A * Bt  on a 128 x 64 tile per workgroup.
 //   A  (rows r, K): A[m*sA + r*lda + k]
 //   Bt (K, cols c): Bt[m*sB + k*ldb + c]
 //   C  (rows, cols): C[m*sC + r*ldc + c];  D: same as C, except that columns
@@ -497,17 +701,21 @@ struct GemmArgs {
     int rows, cols, K;       // extent of the region (relative to its origin)
     int dsplit;              // first column that goes to D2 (cols if none)
     int skip_r, skip_c;      // masked corner (relative), rows/cols if none
-    int tiles_c;             // column tiles
+    int tiles_c, tiles;      // column tiles, tiles per macro
+    int64_t n_macro;
 };
 
 // TAG only separates the trailing-update launches (0) from the final Schur
 // product (1) in profiles; the code is the same.
 template <int TAG>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+__global__ void __launch_bounds__(GTHREADS, 4) k_gemm(GemmArgs g) {
     __shared__ TileSmem sm;
-    const int64_t m = blockIdx.y;
-    const int tr = blockIdx.x / g.tiles_c, tc = blockIdx.x % g.tiles_c;
-    const int r0 = tr * GT, c0 = tc * GT;
+    int64_t m;
+    int tile;
+    xcd_tile(g.tiles, m, tile);
+    if (m >= g.n_macro) return;
+    const int tr = tile / g.tiles_c, tc = tile % g.tiles_c;
+    const int r0 = tr * GM, c0 = tc * GT;
     if (r0 >= g.skip_r && c0 >= g.skip_c) return;   // tile entirely in the masked corner
     const double* C = g.C + m * g.sC;
     // C is fetched first and only added after the K loop, so its latency
@@ -524,10 +732,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
                 cr[bi][bj][q] = in ? C[(int64_t)r * g.ldc + c] : 0.0;
             }
     v4d acc[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+    zero_acc(acc);
     tile_mma<true>(g.A + m * g.sA, g.lda, g.Bt + m * g.sB, g.ldb, g.K, r0, c0, g.rows, g.cols, acc, sm);
     double* D = g.D ? g.D + m * g.sD : nullptr;
     double* D2 = g.D2 ? g.D2 + m * g.sD2 : nullptr;

@@ -32,8 +32,8 @@ struct mehdg_ctx {
     double* d_minvrq = nullptr;     // M^-1 R_Q per macro
     double* d_B = nullptr;          // bordered matrices
     int32_t* d_ipiv = nullptr;      // pivot rows of the LU of S
-    double* d_tri = nullptr;        // inverses of the diagonal blocks of the current panel
-    int32_t* d_perm = nullptr;      // composed row interchange of the current panel
+    double* d_tri = nullptr;        // inverses of the diagonal blocks of the current outer block
+    int32_t* d_perm = nullptr;      // composed row interchange of the current panel or outer block
     int64_t bytes = 0;
     // kernel timing with HIP events (mehdg_profile_*)
     bool prof = false;
@@ -157,12 +157,54 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
 }
 
 template <int TAG>
-mehdg_err launch_gemm(mehdg_ctx* c, GemmArgs g, unsigned M, hipStream_t st) {
-    const int tr = (g.rows + GT - 1) / GT;
+mehdg_err launch_gemm(mehdg_ctx* c, GemmArgs g, int slot, hipStream_t st) {
+    const int tr = (g.rows + GM - 1) / GM;
     g.tiles_c = (g.cols + GT - 1) / GT;
     if (tr <= 0 || g.tiles_c <= 0 || g.K <= 0) return MEHDG_OK;
-    Timed t(c, TAG == 0 ? MEHDG_PROF_UPDATE : MEHDG_PROF_SCHUR, st);
-    hipLaunchKernelGGL(k_gemm<TAG>, dim3((unsigned)(tr * g.tiles_c), M), dim3(256), 0, st, g);
+    g.tiles = tr * g.tiles_c;
+    g.n_macro = c->n_macro;
+    Timed t(c, slot, st);
+    hipLaunchKernelGGL(k_gemm<TAG>, dim3(xcd_grid(g.tiles, c->n_macro)), dim3(GTHREADS), 0, st, g);
+    return hip_ok(hipGetLastError());
+}
+
+// D(rows, cols) -= B[rows, kb0 : kb0+K] * B[kb0 : kb0+K, cols] inside one bordered matrix,
+// origin (o_r, o_c), with the corner from (skip_r, skip_c) left alone
+template <int P>
+mehdg_err launch_update(mehdg_ctx* c, int kb0, int K, int o_r, int o_c, int rows, int cols, int skip_r,
+                        int skip_c, hipStream_t st) {
+    using BD = Bdims<P>;
+    constexpr int ld = BD::ld;
+    if (skip_r <= 0 && skip_c <= 0) return MEHDG_OK;   // all of it is the corner
+    double* B = c->d_B;
+    GemmArgs g{};
+    g.A = B + (int64_t)o_r * ld + kb0;
+    g.Bt = B + (int64_t)kb0 * ld + o_c;
+    g.C = B + (int64_t)o_r * ld + o_c;
+    g.D = B + (int64_t)o_r * ld + o_c;
+    g.D2 = nullptr;
+    g.sA = g.sB = g.sC = g.sD = BD::per_macro;
+    g.sD2 = 0;
+    g.lda = g.ldb = g.ldc = g.ldd = ld;
+    g.ldd2 = 0;
+    g.rows = rows;
+    g.cols = cols;
+    g.K = K;
+    g.dsplit = cols;
+    g.skip_r = skip_r;
+    g.skip_c = skip_c;
+    return launch_gemm<0>(c, g, MEHDG_PROF_UPDATE, st);
+}
+
+template <int P>
+mehdg_err launch_tri(mehdg_ctx* c, TriArgs a, hipStream_t st) {
+    using D = Dims<P>;
+    a.ct = a.c_hi > a.c_lo ? (a.c_hi - a.c_lo + GT - 1) / GT : 0;
+    a.rt = a.np > 0 ? (D::NH + GM - 1) / GM : 0;
+    if (a.ct + a.rt == 0) return MEHDG_OK;
+    Timed t(c, MEHDG_PROF_ROWBLOCK, st);
+    hipLaunchKernelGGL(k_tri<P>, dim3(xcd_grid(a.ct + a.rt, c->n_macro)), dim3(GTHREADS), 0, st, c->d_B, c->d_tri,
+                       c->d_perm, a, (int64_t)c->n_macro);
     return hip_ok(hipGetLastError());
 }
 
@@ -171,45 +213,62 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
     using D = Dims<P>;
     using BD = Bdims<P>;
     using PN = Panel<P>;
-    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld, ROWS = BD::rows;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld, ROWS = BD::rows, NB = PN::NB;
     const unsigned M = (unsigned)c->n_macro;
     double* B = c->d_B;
-    for (int kb = 0; kb < NV; kb += PN::NB) {
-        const int nb = (NV - kb) < PN::NB ? (NV - kb) : PN::NB;
-        {
-            Timed t(c, MEHDG_PROF_PANEL, st);
-            hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, c->d_ipiv, c->d_perm,
-                               c->d_tri, c->d_status);
-        }
-        if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
-        {
-            const int ct = (ld - (kb + nb) + GT - 1) / GT;
-            const int rt = (NH + GT - 1) / GT;
-            Timed t(c, MEHDG_PROF_ROWBLOCK, st);
-            hipLaunchKernelGGL(k_tri<P>, dim3((unsigned)(ct + rt), M), dim3(256), 0, st, B, kb, c->d_tri,
-                               c->d_perm);
-            if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    mehdg_err e;
+    auto panel = [&](int kb, int kb0) {
+        Timed t(c, MEHDG_PROF_PANEL, st);
+        hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, kb0, c->d_ipiv, c->d_perm,
+                           c->d_tri, c->d_status);
+        return hip_ok(hipGetLastError());
+    };
+    for (int kb0 = 0; kb0 < NV; kb0 += PN::OB) {
+        const int w = (NV - kb0) < PN::OB ? (NV - kb0) : PN::OB;
+        if ((e = panel(kb0, kb0)) != MEHDG_OK) return e;
+        TriArgs a{};
+        a.kb0 = kb0;
+        if (w > NB) {
+            // first panel: its U rows over the second panel's columns, L21 of X
+            a.w = NB;
+            a.loff = PN::LINV1;
+            a.ldl = NB;
+            a.c_lo = kb0 + NB;
+            a.c_hi = kb0 + w;
+            a.kp = kb0;
+            a.np = NB;
+            a.uoff = PN::UINV1;
+            if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
+            // the second panel's columns, all rows below the first panel
+            const int o = kb0 + NB;
+            if ((e = launch_update<P>(c, kb0, NB, o, o, ROWS - o, w - NB, ROWS - o, w - NB, st)) != MEHDG_OK)
+                return e;
+            if ((e = panel(kb0 + NB, kb0)) != MEHDG_OK) return e;
+            // the whole block: U rows right of it, L21 of X for the second panel
+            a.w = w;
+            a.loff = PN::LINVW;
+            a.ldl = PN::OB;
+            a.c_lo = kb0 + w;
+            a.c_hi = ld;
+            a.kp = kb0 + NB;
+            a.np = w - NB;
+            a.uoff = PN::UINV2;
+            if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
+        } else {
+            a.w = w;
+            a.loff = PN::LINV1;
+            a.ldl = NB;
+            a.c_lo = kb0 + w;
+            a.c_hi = ld;
+            a.kp = kb0;
+            a.np = w;
+            a.uoff = PN::UINV1;
+            if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
         }
         // trailing update of the L-shaped region (A' is formed at the end)
-        const int o = kb + nb;
-        GemmArgs g{};
-        g.A = B + (int64_t)o * ld + kb;
-        g.Bt = B + (int64_t)kb * ld + o;
-        g.C = B + (int64_t)o * ld + o;
-        g.D = B + (int64_t)o * ld + o;
-        g.D2 = nullptr;
-        g.sA = g.sB = g.sC = g.sD = BD::per_macro;
-        g.sD2 = 0;
-        g.lda = g.ldb = g.ldc = g.ldd = ld;
-        g.ldd2 = 0;
-        g.rows = ROWS - o;
-        g.cols = NV + NH + 1 - o;
-        g.K = nb;
-        g.dsplit = g.cols;
-        g.skip_r = NV - o;
-        g.skip_c = NV - o;
-        mehdg_err e = launch_gemm<0>(c, g, M, st);
-        if (e != MEHDG_OK) return e;
+        const int o = kb0 + w;
+        if ((e = launch_update<P>(c, kb0, w, o, o, ROWS - o, NV + NH + 1 - o, NV - o, NV - o, st)) != MEHDG_OK)
+            return e;
     }
     // Ahat = A' - L21 U12, bhat = r_hat - L21 y
     GemmArgs g{};
@@ -243,7 +302,7 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         g.cols = 1;
         g.dsplit = 0;
     }
-    return launch_gemm<1>(c, g, M, st);
+    return launch_gemm<1>(c, g, MEHDG_PROF_SCHUR, st);
 }
 
 template <int P>
