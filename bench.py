@@ -29,30 +29,44 @@ FP64_VALU_PEAK_TFS = 78.6
 
 
 def kernel_models(p, n_macro, NV, NH, viscous):
-    """Algorithmic work per step of each kernel slot: (flops, bytes)."""
+    """Algorithmic work per step of each kernel slot: (kind, flops or bytes).
+
+    Follows the blocking of the condensation: outer blocks of OB = 128
+    columns made of two 64-column panels; inside a block the second panel's
+    columns are updated after the first panel (K = 64), after the block the
+    L-shaped trailing region without the A' corner (K = block width), and at
+    the end Ahat = A' - L21 U12 with K = N_V.  Flops count useful products
+    only (no padding of tiles or of the triangular inverses).
+    """
     from paper_2507_22195_amd.workloads import sizes
     s = sizes(p)
     n, nf = s["n"], s["nf"]
-    ld = (NV + NH + 1 + 7) // 8 * 8
-    NB = 64
-    upd = 0.0
-    for kb in range(0, NV, NB):
-        nb = min(NB, NV - kb)
-        o = kb + nb
-        region = (NV - o) * (NV + NH + 1 - o) + NH * (NV - o)
-        upd += 2.0 * nb * region
+    ROWS, COLS = NV + NH, NV + NH + 1
+    ld = (COLS + 7) // 8 * 8
+    NB, OB = 64, 128
+    upd = tri = panel = 0.0
+    for kb0 in range(0, NV, OB):
+        w = min(OB, NV - kb0)
+        panels = [(kb0, min(NB, w))] + ([(kb0 + NB, w - NB)] if w > NB else [])
+        for kb, nb in panels:
+            # panel: rank-1 updates inside the panel columns, then the two inverses
+            panel += sum(2.0 * (NV - kb - j) * (nb - j) for j in range(nb)) + 2.0 * nb ** 3 / 3.0
+            # L21 of X for the panel columns: X_panel (NH x nb) times U_kk^-1 (upper)
+            tri += NH * nb * nb
+        if w > NB:
+            o = kb0 + NB
+            upd += 2.0 * NB * (ROWS - o) * (w - NB)          # second panel's columns
+            tri += NB * NB * (w - NB)                        # its U rows (unit-lower solve)
+        o = kb0 + w
+        tri += w * w * (COLS - o)                            # U rows right of the block
+        upd += 2.0 * w * ((ROWS - o) * (COLS - o) - NH * (NH + 1) if o < NV else 0.0)
     schur = 2.0 * NH * (NH + 1) * NV
-    panel = sum(2.0 * (NV - kb - j) * (min(NB, NV - kb) - j) for kb in range(0, NV, NB)
-                for j in range(min(NB, NV - kb))) + sum(
-        NH * min(NB, NV - kb) ** 2 for kb in range(0, NV, NB))
-    rowblock = sum((ld - kb - min(NB, NV - kb)) * min(NB, NV - kb) ** 2 for kb in range(0, NV, NB))
     M = n_macro
     return {
-        # flops for MFMA/ALU work, bytes for streaming kernels
         "update": ("mfma", upd * M),
         "schur": ("mfma", schur * M),
         "panel": ("alu", panel * M),
-        "rowblock": ("alu", rowblock * M),
+        "rowblock": ("mfma", tri * M),
         # bordered rows: every entry written once
         "rows_v": ("hbm", 8.0 * NV * ld * M),
         "rows_h": ("hbm", 8.0 * NH * ld * M),
@@ -61,6 +75,43 @@ def kernel_models(p, n_macro, NV, NH, viscous):
         "residual": ("hbm", 8.0 * (5 * n * 2 + 30 * nf + 15 * n + 5 * n + 30 * nf) * M),
         "minv_rq": ("hbm", 8.0 * 30 * n * M),
     }
+
+
+# Library slot -> kernel symbol prefix in rocprofv3 output
+SLOT_KERNELS = {
+    "residual": "k_residual", "minv_rq": "k_minv_rq", "rows_v": "k_rows_v", "rows_h": "k_rows_h",
+    "panel": "k_panel", "rowblock": "k_tri", "update": "k_gemm<0>", "schur": "k_gemm<1>", "recover": "k_recover",
+}
+# source file of each slot's kernel (the HBM traffic on record is void once it changes)
+SLOT_SOURCES = {
+    "residual": "k_residual.hpp", "minv_rq": "k_assemble.hpp", "rows_v": "k_assemble.hpp", "rows_h": "k_assemble.hpp",
+    "panel": "k_condense.hpp", "rowblock": "k_condense.hpp", "update": "k_condense.hpp", "schur": "k_condense.hpp",
+    "recover": "k_recover.hpp",
+}
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "tgv16_p2_hbm_traffic.txt")
+
+
+def source_digest(slot):
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2507_22195_amd", "csrc", SLOT_SOURCES[slot])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic(slot, workload):
+    """HBM bytes per launch of a slot's kernel from the rocprofv3 counter summary,
+    or None when there is none for this workload or the kernel source changed since."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if not ln.startswith("traffic "):
+            continue
+        kv = dict(tok.split("=", 1) for tok in ln.split()[1:])
+        if kv.get("slot") == slot and kv.get("workload") == workload and kv.get("source") == source_digest(slot):
+            return float(kv["bytes_per_launch"])
+    return None
 
 
 def cpu_baseline(w, target_s=15.0):
@@ -99,6 +150,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shape", type=int, nargs=3, default=None, help="macro grid (default 16 16 16)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="before warm-up, copy a MIB-sized buffer three times (untimed) so that a counter "
+                         "run sees a plain copy kernel of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the per-macro local work shards "
@@ -119,6 +173,14 @@ def main():
     e = lambda k: torch.empty(S[k], dtype=torch.float64, device="cuda")
     R_q, R_v, R_vh, ent = e("R_q"), e("R_v"), e("R_vhat"), e("entropy")
     Ahat, bhat, dv, dq = e("Ahat"), e("bhat"), e("dv"), e("dq")
+
+    if args.copy_calib > 0:
+        src = torch.ones(args.copy_calib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         ctx.assemble(v, vh, None, vo, R_q, R_v, R_vh, ent, want_blocks=True)
@@ -176,7 +238,13 @@ def main():
         peak = FP64_MFMA_PEAK_TFS if kind == "mfma" else FP64_VALU_PEAK_TFS
         roof = {"bound": "mfma" if kind == "mfma" else "alu", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None}
-    roof["kernel"] = dom
+    wl = f"tgv{w.mesh.shape[0]}x{w.mesh.shape[1]}x{w.mesh.shape[2]}_p{w.p}"
+    tb = recorded_traffic(dom, wl)
+    # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), and the rate it implies
+    roof["traffic"] = None if tb is None else round(tb)
+    if tb is not None:
+        roof["traffic_GBps"] = round(tb / (dom_ms / calls / 1e3) / 1e9, 1)
+    roof["kernel"] = SLOT_KERNELS[dom]
     roof["work_per_launch"] = work / calls
     # whole condensation against the dense algorithmic count (2/3 N^3 + 2 N^2 M + 2 M^2 N per macro)
     cond_ms = sum(kernels[k]["ms_per_step"] for k in ("panel", "rowblock", "update", "schur") if k in kernels)
