@@ -62,3 +62,15 @@ __device__ __forceinline__ void record_status(int32_t* status, int64_t m, int co
 }
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }
+
+// Workgroups of one macro-element run on one XCD (and share its L2): the
+// hardware deals workgroups to the eight XCDs in turn, so workgroup b is tile
+// (b / 8) % tiles of macro ((b / 8) / tiles) * 8 + b % 8.  The grid has
+// ceil(n / 8) * 8 * tiles workgroups; m >= n marks an idle one.
+__device__ __forceinline__ void xcd_tile(int tiles, int64_t& m, int& tile) {
+    const unsigned b = blockIdx.x, x = b & 7u, loc = b >> 3;
+    m = (int64_t)(loc / (unsigned)tiles) * 8 + x;
+    tile = (int)(loc % (unsigned)tiles);
+}
+
+inline unsigned xcd_grid(int tiles, int64_t n) { return (unsigned)(((n + 7) / 8) * 8 * tiles); }

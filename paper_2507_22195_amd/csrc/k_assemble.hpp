@@ -298,7 +298,9 @@ __device__ void stage_tables(RowLds<P>& L, const Tab1D* __restrict__ tab) {
     for (int i = threadIdx.x; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
 }
 
-// Rows of the interior equations: one workgroup per (macro, node a), 5 rows.
+// Rows of the interior equations: one workgroup per (macro, node a), 5 rows;
+// the workgroups of a macro share one XCD, whose L2 then serves the
+// coefficient slabs they all read.
 template <int P>
 __global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_v(const double* __restrict__ coefV,
                                                                const double* __restrict__ coefF,
@@ -306,14 +308,16 @@ __global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_v(const double* __r
                                                                const double* __restrict__ minvrq,
                                                                const double* __restrict__ hs,
                                                                const Tab1D* __restrict__ tab, int viscous_i,
-                                                               double* __restrict__ B) {
+                                                               double* __restrict__ B, int64_t n_macro) {
     using D = Dims<P>;
     using BD = Bdims<P>;
     constexpr int n1d = D::n1d, n = D::n, KG = RowLds<P>::KG;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     RowLds<P>& L = *reinterpret_cast<RowLds<P>*>(smem_raw);
-    const int64_t m = blockIdx.y;
-    const int a = blockIdx.x;
+    int64_t m;
+    int a;
+    xcd_tile(n, m, a);
+    if (m >= n_macro) return;
     const bool viscous = viscous_i != 0;
     const int a1 = a % n1d, a2 = (a / n1d) % n1d, a3 = a / (n1d * n1d);
     const double hinv[3] = {1.0 / hs[3 * m], 1.0 / hs[3 * m + 1], 1.0 / hs[3 * m + 2]};
@@ -354,14 +358,17 @@ __global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_h(const double* __r
                                                                const double* __restrict__ minvrq,
                                                                const double* __restrict__ hs,
                                                                const Tab1D* __restrict__ tab, int viscous_i,
-                                                               double* __restrict__ B) {
+                                                               double* __restrict__ B, int64_t n_macro) {
     using D = Dims<P>;
     using BD = Bdims<P>;
     constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, KG = RowLds<P>::KG;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     RowLds<P>& L = *reinterpret_cast<RowLds<P>*>(smem_raw);
-    const int64_t m = blockIdx.y;
-    const int f = blockIdx.x / nf, c = blockIdx.x % nf;
+    int64_t m;
+    int fc;
+    xcd_tile(6 * nf, m, fc);
+    if (m >= n_macro) return;
+    const int f = fc / nf, c = fc % nf;
     const bool viscous = viscous_i != 0;
     const int c1 = c % n1d, c2 = c / n1d;
     const double hinv[3] = {1.0 / hs[3 * m], 1.0 / hs[3 * m + 1], 1.0 / hs[3 * m + 2]};

@@ -142,18 +142,25 @@ __device__ __forceinline__ void lds_mm64_store_global(const v4d (&acc)[TPW], dou
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorisation.  Rows of S in [kb, NV) are spread one (or RPT) per
-// thread with their panel segment in registers; the column loop is fully
-// unrolled so every register index is a constant.  Column j: arg-max over the
-// rows (DPP wave maximum, then every thread reduces the per-wave results),
-// the pivot row and the row it displaces are exchanged through LDS, then
-// scaling and rank-1 update in registers.  Look-ahead: column j+1 is updated
-// first and its pivot search is issued before the rest of the update, and
-// the LDS buffers alternate by column parity, so two barriers per column.
-// Afterwards: the inverses of the diagonal blocks L_kk (unit lower) and U_kk
-// go to per-macro workspaces, and the composed row interchange of the block
-// to perm.  A panel with kb > kb0 is the second panel of the outer block that
-// starts at kb0 (see the file comment).
+// Panel factorisation.  Each thread owns one (or RPT) rows of S in [kb, NV)
+// by identity: rows are never exchanged between threads, the pivot rows are
+// only broadcast.  A row's 64 values live in registers as z[0..64): after j
+// columns z[0 .. 64-j) hold its current entries of columns j..63 and
+// z[64-j .. 64) the multipliers of columns 0..j-1, so every column is the
+// same code with constant register indices:
+//   z[c] <- z[c+1] - l * prow[c+1]   (c < 63),   z[63] <- l,
+// where the broadcast pivot row has zeros over its multiplier part.  Column
+// j: wave arg-max (DPP) and a reduction over the waves choose the pivot row,
+// which is broadcast through LDS; the next column is updated first and its
+// pivot search issued before the rest of the row (look-ahead), with the LDS
+// buffers alternating by column parity: two barriers per column and no
+// global memory traffic inside the column loop.  A row that becomes pivot at
+// column j keeps z as it is then.  Afterwards the row interchanges are
+// replayed (LAPACK order: position kb+j with the pivot's current position),
+// every row is written to its final position, the inverses of the diagonal
+// blocks L_kk (unit lower) and U_kk go to per-macro workspaces, and the
+// composed row interchange of the block to perm.  A panel with kb > kb0 is the
+// second panel of the outer block that starts at kb0 (see the file comment).
 template <int P>
 __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb, int kb0,
                                                              int32_t* __restrict__ ipiv,
@@ -164,46 +171,53 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     using PN = Panel<P>;
     constexpr int NB = PN::NB, OB = PN::OB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
     constexpr int NW = PN::THREADS / 64;
-    __shared__ double raw[3 * NB * (NB + 1)];   // T and the two inverses
-    __shared__ int mvd[2 * NB], mvs[2 * NB];    // rows whose first-panel segment moves, and their sources
-    __shared__ int nmv;
-    __shared__ int pv1[NB];                      // the first panel's pivots (second panel only)
-    __shared__ double prow[2][NB];         // pivot row segment (by column parity)
-    __shared__ double xch[2][NB];          // segment of the row the pivot displaces
+    __shared__ double raw[3 * NB * (NB + 1)];   // T and the two inverses (staging before that)
+    __shared__ double prow[2][NB];              // pivot row (by column parity)
     __shared__ double redv[2][NW];
     __shared__ int redi[2][NW];
-    __shared__ int pivs[NB];
-    __shared__ int mp[NV];
+    __shared__ int pidj[NB];                    // pivot row (identity) of each column
+    __shared__ int pivs[NB];                    // pivot position of each column (LAPACK order)
+    __shared__ int mvd[2 * NB], mvs[2 * NB];    // rows whose first-panel segment moves, and their sources
+    __shared__ int nmv;
+    __shared__ int pv1[NB];                     // the first panel's pivots (second panel only)
+    __shared__ int mp[NV];                      // position -> row identity
+    __shared__ int ps[NV];                      // row identity -> position
     __shared__ int mark[NV];
     const int64_t m = blockIdx.x;
     double* Bm = B + m * BD::per_macro;
     const int nb = (NV - kb) < NB ? (NV - kb) : NB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    bool bad = false;
+    const bool second = kb > kb0;
 
-    double seg[RPT][NB];
-    int rows[RPT];
+    double z[RPT][NB];
+    int id[RPT], jp[RPT];
+    bool done[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) rows[r] = kb + tid + r * PN::THREADS;
+    for (int r = 0; r < RPT; ++r) {
+        id[r] = kb + tid + r * PN::THREADS;
+        done[r] = id[r] >= NV;
+        jp[r] = nb;
+    }
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
-        for (int c = 0; c < NB; ++c)
-            seg[r][c] = (rows[r] < NV && c < nb) ? Bm[(int64_t)rows[r] * ld + kb + c] : 0.0;
-    for (int r = tid; r < NV; r += PN::THREADS) {
+        for (int c = 0; c < NB; ++c) z[r][c] = (!done[r] && c < nb) ? Bm[(int64_t)id[r] * ld + kb + c] : 0.0;
+    for (int r = kb + tid; r < NV; r += PN::THREADS) {
         mp[r] = r;
+        ps[r] = r;
         mark[r] = 0;
     }
-    // candidate pivot of column j among rows >= kb+j: wave arg-max to LDS
-    auto candidate = [&](int j, int bf, const double (&cv)[RPT]) {
+    // candidate pivot among the rows that are not pivots yet: wave arg-max to LDS
+    auto candidate = [&](int bf, const double (&cv)[RPT]) {
         double best = -1.0;
         int bi = NV;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            const double ax = fabs(cv[r]);
-            if (rows[r] >= kb + j && rows[r] < NV && (ax > best || (ax == best && rows[r] < bi))) {
+            double ax = fabs(cv[r]);
+            if (!(ax >= 0.0)) ax = 0.0;          // NaN
+            if (!done[r] && (ax > best || (ax == best && id[r] < bi))) {
                 best = ax;
-                bi = rows[r];
+                bi = id[r];
             }
         }
         const double wm = wave_max_f64(best);
@@ -218,13 +232,13 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     {
         double cv[RPT];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) cv[r] = seg[r][0];
-        candidate(0, 0, cv);
+        for (int r = 0; r < RPT; ++r) cv[r] = z[r][0];
+        candidate(0, cv);
     }
-#pragma clang loop unroll(full)
-    for (int j = 0; j < NB; ++j) {
-      if (j < nb) {                                // uniform: only the last panel is narrower
-        const int col = kb + j, bf = j & 1;
+    bool bad = false;
+#pragma clang loop unroll(disable)
+    for (int j = 0; j < nb; ++j) {
+        const int bf = j & 1;
         __syncthreads();
         double b = redv[bf][0];
         int p = redi[bf][0];
@@ -234,94 +248,72 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
                 b = redv[bf][w];
                 p = redi[bf][w];
             }
-        if (!(b > 0.0) || !isfinite(b) || p >= NV) {
-            bad = true;
-            p = col;
-        }
+        if (!(b > 0.0) || !isfinite(b)) bad = true;
+        // the pivot row publishes its current entries; wave 0 zeroes the multiplier part
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (rows[r] == p) {
+            if (id[r] == p) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) prow[bf][c] = seg[r][c];
-            }
-            if (rows[r] == col && p != col) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) xch[bf][c] = seg[r][c];
+                for (int c = 0; c < NB; ++c)
+                    if (c < NB - j) prow[bf][c] = z[r][c];
+                done[r] = true;
+                jp[r] = j;
             }
         }
-        if (tid == 0) pivs[j] = p;
+        if (wave == 0 && lane >= NB - j) prow[bf][lane] = 0.0;
+        if (tid == 0) pidj[j] = p;
         __syncthreads();
-        const double pv = prow[bf][j];
+        const double pv = prow[bf][0];
         const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
-        double l[RPT];
+        double l[RPT], nz0[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (rows[r] == col) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) seg[r][c] = prow[bf][c];
-            } else if (p != col && rows[r] == p) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) seg[r][c] = xch[bf][c];
-            }
-            const bool below = rows[r] > col && rows[r] < NV;
-            l[r] = below ? seg[r][j] * inv : 0.0;
-            if (below) {
-                seg[r][j] = l[r];
-                if (j + 1 < NB) seg[r][(j + 1) % NB] -= l[r] * prow[bf][(j + 1) % NB];   // look-ahead column
-            }
+            l[r] = done[r] ? 0.0 : z[r][0] * inv;
+            nz0[r] = z[r][1] - l[r] * prow[bf][1];       // look-ahead column
         }
-        if (j + 1 < nb) {
-            double cv[RPT];
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) cv[r] = (j + 1 < NB) ? seg[r][(j + 1) % NB] : 0.0;
-            candidate(j + 1, bf ^ 1, cv);
-        }
+        if (j + 1 < nb) candidate(bf ^ 1, nz0);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (rows[r] > col && rows[r] < NV) {
+            if (!done[r]) {
+                z[r][0] = nz0[r];
 #pragma unroll
-                for (int c = j + 2; c < NB; ++c) seg[r][c] -= l[r] * prow[bf][c];
+                for (int c = 1; c < NB - 1; ++c) z[r][c] = z[r][c + 1] - l[r] * prow[bf][c + 1];
+                z[r][NB - 1] = l[r];
             }
         }
-      }
     }
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        if (rows[r] < NV) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < nb) Bm[(int64_t)rows[r] * ld + kb + c] = seg[r][c];
-        }
-    }
-    // diagonal block T (the register segment is dead after this)
-    double (*T)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
-    double (*XL)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + NB * (NB + 1));
-    double (*XU)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + 2 * NB * (NB + 1));
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int i = rows[r] - kb;
-        if (i >= 0 && i < NB) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c) T[i][c] = (i < nb && c < nb) ? seg[r][c] : (i == c ? 1.0 : 0.0);
-        }
-    }
-    for (int e = tid; e < NB * NB; e += PN::THREADS) {
-        const int i = e / NB, c = e % NB;
-        XL[i][c] = (i == c) ? 1.0 : 0.0;
-        XU[i][c] = (i == c) ? 1.0 : 0.0;
-    }
-    if (tid < nb) ipiv[m * NV + kb + tid] = pivs[tid];
-    const bool second = kb > kb0;
+    // replay of the interchanges: position kb+j with the pivot's current position
     if (second && tid < NB) pv1[tid] = ipiv[m * NV + kb0 + tid];
     __syncthreads();
-    // this panel's interchange: afterwards row r holds the old row mp[r]
     if (tid == 0) {
-        for (int i = 0; i < nb; ++i) {
-            const int p = pivs[i];
-            const int t = mp[kb + i];
-            mp[kb + i] = mp[p];
-            mp[p] = t;
+        for (int j = 0; j < nb; ++j) {
+            const int pid = pidj[j], pp = ps[pid], other = mp[kb + j];
+            mp[kb + j] = pid;
+            ps[pid] = kb + j;
+            mp[pp] = other;
+            ps[other] = pp;
+            pivs[j] = pp;
         }
+    }
+    __syncthreads();
+    // every row to its final position, in column order: a row that became
+    // pivot at column jp holds [multipliers of columns < jp | U entries]
+    // rotated by jp; the others hold their nb multipliers rotated by nb
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        if (id[r] < NV) {
+            const int64_t row = (int64_t)ps[id[r]] * ld + kb;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const int col = (c + jp[r]) & (NB - 1);
+                if (col < nb) Bm[row + col] = z[r][c];
+            }
+        }
+    }
+    if (tid < nb) ipiv[m * NV + kb + tid] = pivs[tid];
+    // this panel's interchange as lists: perm (first panel) or the rows whose
+    // first-panel multipliers move (second panel)
+    if (tid == 0) {
         int n = 0;
         int32_t* pm = perm + m * PN::PERM;
         for (int i = 0; i < nb; ++i) {
@@ -335,16 +327,16 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         }
         int nd = 0;
         for (int i = 0; i < nb; ++i) {
-            const int p = pivs[i];
-            if (p >= kb + nb && !mark[p]) {
-                mark[p] = 1;
+            const int q = pivs[i];
+            if (q >= kb + nb && !mark[q]) {
+                mark[q] = 1;
                 if (second) {
-                    mvd[n] = p;
-                    mvs[n] = mp[p];
+                    mvd[n] = q;
+                    mvs[n] = mp[q];
                     ++n;
                 } else {
-                    pm[OB + nd] = p;
-                    pm[2 * OB + nd] = mp[p];
+                    pm[OB + nd] = q;
+                    pm[2 * OB + nd] = mp[q];
                     ++nd;
                 }
             }
@@ -354,55 +346,69 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     }
     __syncthreads();
     if (second) {
-        // the first panel's L columns follow this panel's interchange (read all, then write)
-        constexpr int MVE = (2 * NB * NB + PN::THREADS - 1) / PN::THREADS;
+        // the first panel's multipliers follow this panel's interchange (read all, then write)
         const int cnt = nmv * NB;
-        double mv[MVE];
-#pragma unroll
-        for (int q = 0; q < MVE; ++q) {
-            const int e = tid + q * PN::THREADS;
-            mv[q] = e < cnt ? Bm[(int64_t)mvs[e / NB] * ld + kb0 + e % NB] : 0.0;
-        }
+        for (int e = tid; e < cnt; e += PN::THREADS) raw[e] = Bm[(int64_t)mvs[e / NB] * ld + kb0 + e % NB];
+        __syncthreads();
+        for (int e = tid; e < cnt; e += PN::THREADS) Bm[(int64_t)mvd[e / NB] * ld + kb0 + e % NB] = raw[e];
         // interchange of the whole outer block: the first panel's pivots, then this panel's
         for (int r = kb0 + tid; r < NV; r += PN::THREADS) {
             mp[r] = r;
             mark[r] = 0;
         }
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < MVE; ++q) {
-            const int e = tid + q * PN::THREADS;
-            if (e < cnt) Bm[(int64_t)mvd[e / NB] * ld + kb0 + e % NB] = mv[q];
-        }
         if (tid == 0) {
             for (int i = 0; i < NB; ++i) {
-                const int p = pv1[i];
+                const int q = pv1[i];
                 const int t = mp[kb0 + i];
-                mp[kb0 + i] = mp[p];
-                mp[p] = t;
+                mp[kb0 + i] = mp[q];
+                mp[q] = t;
             }
             for (int i = 0; i < nb; ++i) {
-                const int p = pivs[i];
+                const int q = pivs[i];
                 const int t = mp[kb + i];
-                mp[kb + i] = mp[p];
-                mp[p] = t;
+                mp[kb + i] = mp[q];
+                mp[q] = t;
             }
             const int w = kb + nb - kb0;
             int32_t* pm = perm + m * PN::PERM;
             for (int i = 0; i < w; ++i) pm[i] = mp[kb0 + i];
             int nd = 0;
             for (int i = 0; i < NB + nb; ++i) {
-                const int p = i < NB ? pv1[i] : pivs[i - NB];
-                if (p >= kb0 + w && !mark[p]) {
-                    mark[p] = 1;
-                    pm[OB + nd] = p;
-                    pm[2 * OB + nd] = mp[p];
+                const int q = i < NB ? pv1[i] : pivs[i - NB];
+                if (q >= kb0 + w && !mark[q]) {
+                    mark[q] = 1;
+                    pm[OB + nd] = q;
+                    pm[2 * OB + nd] = mp[q];
                     ++nd;
                 }
             }
             pm[3 * OB] = nd;
         }
+        __syncthreads();
     }
+    // diagonal block T (rows of the pivots, in column order) and the two inverses X_L, X_U
+    double (*T)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
+    double (*XL)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + NB * (NB + 1));
+    double (*XU)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + 2 * NB * (NB + 1));
+    for (int e = tid; e < NB * NB; e += PN::THREADS) {
+        const int i = e / NB, c = e % NB;
+        if (i >= nb) T[i][c] = (i == c) ? 1.0 : 0.0;
+        else if (c >= nb) T[i][c] = 0.0;
+        XL[i][c] = (i == c) ? 1.0 : 0.0;
+        XU[i][c] = (i == c) ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        if (id[r] < NV && jp[r] < nb) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const int col = (c + jp[r]) & (NB - 1);
+                if (col < nb) T[jp[r]][col] = z[r][c];
+            }
+        }
+    }
+    __syncthreads();
     // L_kk^-1 (forward, unit diagonal) by one half of the workgroup and
     // U_kk^-1 (backward; rows scaled by 1/U_kk at the end) by the other, one
     // elimination step per barrier.
@@ -479,18 +485,6 @@ struct TileSmem {
     double As[2][GM][GK + 1];
     double Bs[2][GK][GT + 1];
 };
-
-// Tiles of one macro-element run on one XCD: workgroups are dealt to the
-// eight XCDs in turn, so workgroup b is tile (b / 8) % tiles of macro
-// ((b / 8) / tiles) * 8 + b % 8.  The grid has ceil(n / 8) * 8 * tiles
-// workgroups; m >= n marks an idle one.
-__device__ __forceinline__ void xcd_tile(int tiles, int64_t& m, int& tile) {
-    const unsigned b = blockIdx.x, x = b & 7u, loc = b >> 3;
-    m = (int64_t)(loc / (unsigned)tiles) * 8 + x;
-    tile = (int)(loc % (unsigned)tiles);
-}
-
-inline unsigned xcd_grid(int tiles, int64_t n) { return (unsigned)(((n + 7) / 8) * 8 * tiles); }
 
 template <bool NEG>
 __device__ __forceinline__ void tile_mma(const double* A, int lda, const double* Bt, int ldb, int K, int r0,

@@ -144,14 +144,15 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     if (!allow_lds(&k_rows_v<P>, rl) || !allow_lds(&k_rows_h<P>, rl)) return MEHDG_EHIP;
     {
         Timed t(c, MEHDG_PROF_ROWS_V, st);
-        hipLaunchKernelGGL(k_rows_v<P>, dim3(D::n, M), dim3(RowCfg<P>::THREADS), rl, st, c->d_coefV, c->d_coefF, R_v,
-                           c->d_minvrq, c->d_h, c->d_tab, c->dp.viscous, c->d_B);
+        hipLaunchKernelGGL(k_rows_v<P>, dim3(xcd_grid(D::n, c->n_macro)), dim3(RowCfg<P>::THREADS), rl, st, c->d_coefV,
+                           c->d_coefF, R_v, c->d_minvrq, c->d_h, c->d_tab, c->dp.viscous, c->d_B, (int64_t)c->n_macro);
     }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     {
         Timed t(c, MEHDG_PROF_ROWS_H, st);
-        hipLaunchKernelGGL(k_rows_h<P>, dim3(6 * D::nf, M), dim3(RowCfg<P>::THREADS), rl, st, c->d_coefF, R_vhat, c->d_minvrq,
-                           c->d_h, c->d_tab, c->dp.viscous, c->d_B);
+        hipLaunchKernelGGL(k_rows_h<P>, dim3(xcd_grid(6 * D::nf, c->n_macro)), dim3(RowCfg<P>::THREADS), rl, st,
+                           c->d_coefF, R_vhat, c->d_minvrq, c->d_h, c->d_tab, c->dp.viscous, c->d_B,
+                           (int64_t)c->n_macro);
     }
     return hip_ok(hipGetLastError());
 }
