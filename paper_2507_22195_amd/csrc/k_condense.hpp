@@ -144,23 +144,26 @@ __device__ __forceinline__ void lds_mm64_store_global(const v4d (&acc)[TPW], dou
 // ---------------------------------------------------------------------------
 // Panel factorisation.  Each thread owns one (or RPT) rows of S in [kb, NV)
 // by identity: rows are never exchanged between threads, the pivot rows are
-// only broadcast.  A row's 64 values live in registers as z[0..64): after j
+// only broadcast.  A row's 64 values live in registers as z[0..64) and move
+// down by one register per column, so every column is the same code with
+// constant register indices.  For a row that is not a pivot yet, after j
 // columns z[0 .. 64-j) hold its current entries of columns j..63 and
-// z[64-j .. 64) the multipliers of columns 0..j-1, so every column is the
-// same code with constant register indices:
+// z[64-j .. 64) the multipliers of columns 0..j-1:
 //   z[c] <- z[c+1] - l * prow[c+1]   (c < 63),   z[63] <- l,
-// where the broadcast pivot row has zeros over its multiplier part.  Column
-// j: wave arg-max (DPP) and a reduction over the waves choose the pivot row,
-// which is broadcast through LDS; the next column is updated first and its
-// pivot search issued before the rest of the row (look-ahead), with the LDS
-// buffers alternating by column parity: two barriers per column and no
-// global memory traffic inside the column loop.  A row that becomes pivot at
-// column j keeps z as it is then.  Afterwards the row interchanges are
-// replayed (LAPACK order: position kb+j with the pivot's current position),
-// every row is written to its final position, the inverses of the diagonal
-// blocks L_kk (unit lower) and U_kk go to per-macro workspaces, and the
-// composed row interchange of the block to perm.  A panel with kb > kb0 is the
-// second panel of the outer block that starts at kb0 (see the file comment).
+// where the broadcast pivot row reads as zero over its multiplier part.  A
+// pivot row takes l = 0 and z[63] <- z[0] instead, i.e. it just rotates, so
+// after the last column every row's z[c] belongs to column (c + nb) mod 64.
+// Column j: wave arg-max (DPP) and a reduction over the waves choose the
+// pivot row, which is broadcast through LDS; the next column is updated
+// first and its pivot search issued before the rest of the row (look-ahead),
+// with the LDS buffers alternating by column parity: two barriers per column
+// and no global memory traffic inside the column loop.  Afterwards the row
+// interchanges are replayed (LAPACK order: position kb+j with the pivot's
+// current position), rows go to their final positions through LDS
+// (coalesced), the inverses of the diagonal blocks L_kk (unit lower) and
+// U_kk are formed one column per lane, and the composed row interchange of
+// the block goes to perm.  A panel with kb > kb0 is the second panel of the
+// outer block that starts at kb0 (see the file comment).
 template <int P>
 __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb, int kb0,
                                                              int32_t* __restrict__ ipiv,
@@ -170,8 +173,9 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     using BD = Bdims<P>;
     using PN = Panel<P>;
     constexpr int NB = PN::NB, OB = PN::OB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
-    constexpr int NW = PN::THREADS / 64;
-    __shared__ double raw[3 * NB * (NB + 1)];   // T and the two inverses (staging before that)
+    constexpr int NT = PN::THREADS, NW = NT / 64;
+    constexpr int CH = 3 * NB;                  // rows per staging chunk of raw
+    __shared__ double raw[3 * NB * (NB + 1)];   // staging, then T and the two inverses
     __shared__ double prow[2][NB];              // pivot row (by column parity)
     __shared__ double redv[2][NW];
     __shared__ int redi[2][NW];
@@ -188,26 +192,28 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     const int nb = (NV - kb) < NB ? (NV - kb) : NB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool second = kb > kb0;
+    const int nrows = NV - kb;
+    double (*stage)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
 
     double z[RPT][NB];
-    int id[RPT], jp[RPT];
+    int id[RPT];
     bool done[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        id[r] = kb + tid + r * PN::THREADS;
+        id[r] = kb + tid + r * NT;
         done[r] = id[r] >= NV;
-        jp[r] = nb;
     }
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
         for (int c = 0; c < NB; ++c) z[r][c] = (!done[r] && c < nb) ? Bm[(int64_t)id[r] * ld + kb + c] : 0.0;
-    for (int r = kb + tid; r < NV; r += PN::THREADS) {
+    for (int r = kb + tid; r < NV; r += NT) {
         mp[r] = r;
         ps[r] = r;
         mark[r] = 0;
     }
-    // candidate pivot among the rows that are not pivots yet: wave arg-max to LDS
+    // wave candidate over the rows that are not pivots yet, from their current
+    // column values cv: arg-max to LDS (ties to the lower row)
     auto candidate = [&](int bf, const double (&cv)[RPT]) {
         double best = -1.0;
         int bi = NV;
@@ -249,43 +255,44 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
                 p = redi[bf][w];
             }
         if (!(b > 0.0) || !isfinite(b)) bad = true;
-        // the pivot row publishes its current entries; wave 0 zeroes the multiplier part
+        if (tid == 0) pidj[j] = p;
+        // the pivot row publishes its values; its wave then zeroes the multiplier part
+        bool own_wave = false;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (id[r] == p) {
+            const bool own = id[r] == p;
+            if (own) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c)
-                    if (c < NB - j) prow[bf][c] = z[r][c];
+                for (int c = 0; c < NB; ++c) prow[bf][c] = z[r][c];
                 done[r] = true;
-                jp[r] = j;
             }
+            own_wave |= __ballot(own) != 0ull;
         }
-        if (wave == 0 && lane >= NB - j) prow[bf][lane] = 0.0;
-        if (tid == 0) pidj[j] = p;
+        if (own_wave && lane >= NB - j) prow[bf][lane] = 0.0;   // same wave, after the row
         __syncthreads();
         const double pv = prow[bf][0];
         const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
-        double l[RPT], nz0[RPT];
+        double l[RPT], nz0[RPT], z0[RPT];
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            l[r] = done[r] ? 0.0 : z[r][0] * inv;
+            z0[r] = z[r][0];
+            l[r] = done[r] ? 0.0 : z0[r] * inv;
             nz0[r] = z[r][1] - l[r] * prow[bf][1];       // look-ahead column
         }
         if (j + 1 < nb) candidate(bf ^ 1, nz0);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            if (!done[r]) {
-                z[r][0] = nz0[r];
 #pragma unroll
-                for (int c = 1; c < NB - 1; ++c) z[r][c] = z[r][c + 1] - l[r] * prow[bf][c + 1];
-                z[r][NB - 1] = l[r];
-            }
+            for (int c = 1; c < NB - 1; ++c) z[r][c] = z[r][c + 1] - l[r] * prow[bf][c + 1];
+            z[r][0] = nz0[r];
+            z[r][NB - 1] = done[r] ? z0[r] : l[r];
         }
     }
     // replay of the interchanges: position kb+j with the pivot's current position
     if (second && tid < NB) pv1[tid] = ipiv[m * NV + kb0 + tid];
     __syncthreads();
     if (tid == 0) {
+#pragma clang loop unroll(disable)
         for (int j = 0; j < nb; ++j) {
             const int pid = pidj[j], pp = ps[pid], other = mp[kb + j];
             mp[kb + j] = pid;
@@ -296,19 +303,24 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         }
     }
     __syncthreads();
-    // every row to its final position, in column order: a row that became
-    // pivot at column jp holds [multipliers of columns < jp | U entries]
-    // rotated by jp; the others hold their nb multipliers rotated by nb
+    // every row to its final position, through LDS in chunks (coalesced); its
+    // z[c] belongs to column (c + nb) mod 64
+    for (int base = 0; base < RPT * NT; base += CH) {
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        if (id[r] < NV) {
-            const int64_t row = (int64_t)ps[id[r]] * ld + kb;
+        for (int r = 0; r < RPT; ++r) {
+            const int sl = tid + r * NT - base;
+            if (sl >= 0 && sl < CH) {
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const int col = (c + jp[r]) & (NB - 1);
-                if (col < nb) Bm[row + col] = z[r][c];
+                for (int c = 0; c < NB; ++c) stage[sl][c] = z[r][c];
             }
         }
+        __syncthreads();
+        for (int e = tid; e < CH * NB; e += NT) {
+            const int rr = base + e / NB, c = e % NB;
+            if (rr < nrows && c < nb)
+                Bm[(int64_t)ps[kb + rr] * ld + kb + c] = stage[e / NB][(c - nb) & (NB - 1)];
+        }
+        __syncthreads();
     }
     if (tid < nb) ipiv[m * NV + kb + tid] = pivs[tid];
     // this panel's interchange as lists: perm (first panel) or the rows whose
@@ -316,6 +328,7 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     if (tid == 0) {
         int n = 0;
         int32_t* pm = perm + m * PN::PERM;
+#pragma clang loop unroll(disable)
         for (int i = 0; i < nb; ++i) {
             const int r = kb + i;
             if (second && mp[r] != r) {
@@ -326,6 +339,7 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
             if (!second) pm[i] = mp[r];
         }
         int nd = 0;
+#pragma clang loop unroll(disable)
         for (int i = 0; i < nb; ++i) {
             const int q = pivs[i];
             if (q >= kb + nb && !mark[q]) {
@@ -348,11 +362,11 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     if (second) {
         // the first panel's multipliers follow this panel's interchange (read all, then write)
         const int cnt = nmv * NB;
-        for (int e = tid; e < cnt; e += PN::THREADS) raw[e] = Bm[(int64_t)mvs[e / NB] * ld + kb0 + e % NB];
+        for (int e = tid; e < cnt; e += NT) raw[e] = Bm[(int64_t)mvs[e / NB] * ld + kb0 + e % NB];
         __syncthreads();
-        for (int e = tid; e < cnt; e += PN::THREADS) Bm[(int64_t)mvd[e / NB] * ld + kb0 + e % NB] = raw[e];
+        for (int e = tid; e < cnt; e += NT) Bm[(int64_t)mvd[e / NB] * ld + kb0 + e % NB] = raw[e];
         // interchange of the whole outer block: the first panel's pivots, then this panel's
-        for (int r = kb0 + tid; r < NV; r += PN::THREADS) {
+        for (int r = kb0 + tid; r < NV; r += NT) {
             mp[r] = r;
             mark[r] = 0;
         }
@@ -387,64 +401,61 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         }
         __syncthreads();
     }
-    // diagonal block T (rows of the pivots, in column order) and the two inverses X_L, X_U
+    // diagonal block T (the pivot rows, now at kb..kb+nb) and the two inverses
     double (*T)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
     double (*XL)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + NB * (NB + 1));
     double (*XU)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw + 2 * NB * (NB + 1));
-    for (int e = tid; e < NB * NB; e += PN::THREADS) {
+    for (int e = tid; e < NB * NB; e += NT) {
         const int i = e / NB, c = e % NB;
-        if (i >= nb) T[i][c] = (i == c) ? 1.0 : 0.0;
-        else if (c >= nb) T[i][c] = 0.0;
-        XL[i][c] = (i == c) ? 1.0 : 0.0;
-        XU[i][c] = (i == c) ? 1.0 : 0.0;
+        T[i][c] = (i < nb && c < nb) ? Bm[(int64_t)(kb + i) * ld + kb + c] : (i == c ? 1.0 : 0.0);
     }
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        if (id[r] < NV && jp[r] < nb) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const int col = (c + jp[r]) & (NB - 1);
-                if (col < nb) T[jp[r]][col] = z[r][c];
+    __syncthreads();
+    // L_kk^-1 by wave 0 and U_kk^-1 by wave 1, one column per lane:
+    //   L x = e_c forward (unit diagonal),  U x = e_c backward
+    // (four partial sums keep the LDS reads of a row in flight together)
+    if (wave == 0) {
+        const int c = lane;
+        for (int i = 0; i < NB; ++i) {
+            double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int k = 0;
+            for (; k + 4 <= i; k += 4) {
+                s0 -= T[i][k] * XL[k][c];
+                s1 -= T[i][k + 1] * XL[k + 1][c];
+                s2 -= T[i][k + 2] * XL[k + 2][c];
+                s3 -= T[i][k + 3] * XL[k + 3][c];
             }
+            for (; k < i; ++k) s0 -= T[i][k] * XL[k][c];
+            XL[i][c] = (s0 + s1) + (s2 + s3);
+        }
+    } else if (wave == 1) {
+        const int c = lane;
+        for (int i = NB - 1; i >= 0; --i) {
+            double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int k = i + 1;
+            for (; k + 4 <= NB; k += 4) {
+                s0 -= T[i][k] * XU[k][c];
+                s1 -= T[i][k + 1] * XU[k + 1][c];
+                s2 -= T[i][k + 2] * XU[k + 2][c];
+                s3 -= T[i][k + 3] * XU[k + 3][c];
+            }
+            for (; k < NB; ++k) s0 -= T[i][k] * XU[k][c];
+            XU[i][c] = ((s0 + s1) + (s2 + s3)) / T[i][i];
         }
     }
     __syncthreads();
-    // L_kk^-1 (forward, unit diagonal) by one half of the workgroup and
-    // U_kk^-1 (backward; rows scaled by 1/U_kk at the end) by the other, one
-    // elimination step per barrier.
-    constexpr int GN = PN::THREADS / 2;
-    const bool gU = tid >= GN;
-    const int gt = gU ? tid - GN : tid;
-    for (int s = 0; s < NB; ++s) {
-        if (!gU) {
-            const int k = s;
-            for (int e = gt; e < (NB - 1 - k) * NB; e += GN) {
-                const int i = k + 1 + e / NB, c = e % NB;
-                XL[i][c] -= T[i][k] * XL[k][c];
-            }
-        } else {
-            const int k = NB - 1 - s;
-            const double invd = 1.0 / T[k][k];
-            for (int e = gt; e < k * NB; e += GN) {
-                const int i = e / NB, c = e % NB;
-                XU[i][c] -= T[i][k] * (XU[k][c] * invd);
-            }
-        }
-        __syncthreads();
-    }
     double* Ti = tri + m * PN::TRI;
     double* Tl = Ti + (second ? PN::LINV2 : PN::LINV1);
     double* Tu = Ti + (second ? PN::UINV2 : PN::UINV1);
-    for (int e = tid; e < NB * NB; e += PN::THREADS) {
+    for (int e = tid; e < NB * NB; e += NT) {
         const int i = e / NB, c = e % NB;
         Tl[e] = XL[i][c];
-        Tu[e] = XU[i][c] / T[i][i];
+        Tu[e] = XU[i][c];
     }
     if (second) {
         // inverse of the block's unit-lower diagonal block [[L11, 0], [L21, L22]]:
         // [[L11^-1, 0], [-L22^-1 L21 L11^-1, L22^-1]]   (L22^-1 = XL), both products on MFMA
         __syncthreads();
-        for (int e = tid; e < NB * NB; e += PN::THREADS) {
+        for (int e = tid; e < NB * NB; e += NT) {
             const int i = e / NB, c = e % NB;
             T[i][c] = (i < nb) ? Bm[(int64_t)(kb + i) * ld + kb0 + c] : 0.0;
             XU[i][c] = Ti[PN::LINV1 + e];
@@ -459,7 +470,7 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         lds_mm64<NB, NW, TPW>(XL, T, acc);
         double* LW = Ti + PN::LINVW;
         lds_mm64_store_global<NB, NW, TPW>(acc, LW + NB * OB, OB, -1.0);
-        for (int e = tid; e < OB * OB; e += PN::THREADS) {
+        for (int e = tid; e < OB * OB; e += NT) {
             const int i = e / OB, c = e % OB;
             if (i < NB) LW[e] = c < NB ? XU[i][c] : 0.0;
             else if (c >= NB) LW[e] = XL[i - NB][c - NB];
