@@ -30,8 +30,11 @@
  * Errors.  Argument errors are detected on the host before anything is
  * enqueued and return MEHDG_EINVAL / MEHDG_ESTATE.  Device-side conditions
  * (non-physical state, non-finite values, zero pivot) never abort a kernel:
- * the kernel records a per-macro status code and writes NaN to that macro's
- * outputs; mehdg_status returns the codes.
+ * the kernel records a per-macro status code, and at the end of every
+ * compute call the outputs of each macro whose code is set (codes persist
+ * until mehdg_status clears them) are overwritten with NaN: R_q, R_v,
+ * R_vhat, entropy after mehdg_assemble; Ahat, bhat after mehdg_condense;
+ * dv, dq after mehdg_recover.  mehdg_status returns the codes.
  *
  * Asynchrony.  Every compute call only enqueues work on the given stream
  * (NULL = default stream) and returns.  mehdg_create and mehdg_status
@@ -126,9 +129,12 @@ mehdg_err mehdg_condense(mehdg_ctx* ctx, double* Ahat, double* bhat, mehdg_strea
 mehdg_err mehdg_recover(mehdg_ctx* ctx, const double* R_q, const double* dvhat, double* dv,
                         double* dq, mehdg_stream stream);
 
-/* Copies the per-macro status codes (mehdg_err values, 0 = fine) of the last
- * calls into host memory status[n_macro] and clears them.  Synchronises the
- * stream.  Returns the first non-zero code met, or MEHDG_OK. */
+/* Copies the per-macro status codes (mehdg_err values, 0 = fine) of the
+ * calls since the last mehdg_status into host memory status[n_macro] and
+ * clears them.  Per macro the most basic condition met is kept (the smallest
+ * code: MEHDG_ENONPHYSICAL before MEHDG_ENONFINITE before MEHDG_ESINGULAR).
+ * Synchronises the stream.  Returns the first non-zero code in macro order,
+ * or MEHDG_OK. */
 mehdg_err mehdg_status(mehdg_ctx* ctx, int32_t* status, mehdg_stream stream);
 
 /* Diagnostics.  Copies the bordered matrix of macro m (after an assemble

@@ -57,8 +57,18 @@ __device__ __forceinline__ void support_1d(int i, int& lo, int& hi) {
     hi = (i >= P) ? 1 : 0;
 }
 
+// Per-macro status: the most basic condition is kept, i.e. the smallest
+// non-zero code (non-physical before non-finite before singular), so a
+// zero pivot caused by a non-physical state still reports the state.
 __device__ __forceinline__ void record_status(int32_t* status, int64_t m, int code) {
-    if (status) atomicMax(reinterpret_cast<int*>(status + m), code);
+    if (!status) return;
+    int* p = reinterpret_cast<int*>(status + m);
+    int old = atomicAdd(p, 0);
+    while (old == 0 || code < old) {
+        const int prev = atomicCAS(p, old, code);
+        if (prev == old) break;
+        old = prev;
+    }
 }
 
 __device__ __forceinline__ bool finite(double x) { return isfinite(x); }

@@ -157,6 +157,28 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     return hip_ok(hipGetLastError());
 }
 
+// Outputs of the macro-elements whose status is not OK are set to NaN.
+struct PoisonArgs {
+    double* ptr[4];
+    int64_t per[4];       // doubles per macro of each array
+};
+
+__global__ void __launch_bounds__(256) k_poison(const int32_t* __restrict__ status, PoisonArgs a) {
+    const int64_t m = blockIdx.x;
+    if (status[m] == 0) return;
+    const double nan = __builtin_nan("");
+    for (int k = 0; k < 4; ++k) {
+        double* q = a.ptr[k];
+        if (!q) continue;
+        for (int64_t i = threadIdx.x; i < a.per[k]; i += blockDim.x) q[m * a.per[k] + i] = nan;
+    }
+}
+
+mehdg_err launch_poison(mehdg_ctx* c, PoisonArgs a, hipStream_t st) {
+    hipLaunchKernelGGL(k_poison, dim3((unsigned)c->n_macro), dim3(256), 0, st, c->d_status, a);
+    return hip_ok(hipGetLastError());
+}
+
 template <int TAG>
 mehdg_err launch_gemm(mehdg_ctx* c, GemmArgs g, int slot, hipStream_t st) {
     const int tr = (g.rows + GM - 1) / GM;
@@ -437,6 +459,11 @@ mehdg_err mehdg_assemble(mehdg_ctx* c, const double* v, const double* vhat, cons
         case 3: e = launch_assemble<3>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, blocks, st); break;
         default: break;
     }
+    if (e == MEHDG_OK) {
+        int64_t sz[5];
+        (void)mehdg_sizes(c->p, sz);
+        e = launch_poison(c, PoisonArgs{{R_q, R_v, R_vhat, entropy}, {sz[3], sz[2], sz[4], 1}}, st);
+    }
     if (e == MEHDG_OK && blocks) c->stage = 1;
     return e;
 }
@@ -452,6 +479,11 @@ mehdg_err mehdg_condense(mehdg_ctx* c, double* Ahat, double* bhat, mehdg_stream 
         case 3: e = launch_condense<3>(c, Ahat, bhat, st); break;
         default: break;
     }
+    if (e == MEHDG_OK) {
+        int64_t sz[5];
+        (void)mehdg_sizes(c->p, sz);
+        e = launch_poison(c, PoisonArgs{{Ahat, bhat, nullptr, nullptr}, {sz[4] * sz[4], sz[4], 0, 0}}, st);
+    }
     if (e == MEHDG_OK) c->stage = 2;
     return e;
 }
@@ -461,12 +493,19 @@ mehdg_err mehdg_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, do
     if (!c || !R_q || !dvhat || !dv || !dq) return MEHDG_EINVAL;
     if (c->stage != 2) return MEHDG_ESTATE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mehdg_err e = MEHDG_EINVAL;
     switch (c->p) {
-        case 1: return launch_recover<1>(c, R_q, dvhat, dv, dq, st);
-        case 2: return launch_recover<2>(c, R_q, dvhat, dv, dq, st);
-        case 3: return launch_recover<3>(c, R_q, dvhat, dv, dq, st);
-        default: return MEHDG_EINVAL;
+        case 1: e = launch_recover<1>(c, R_q, dvhat, dv, dq, st); break;
+        case 2: e = launch_recover<2>(c, R_q, dvhat, dv, dq, st); break;
+        case 3: e = launch_recover<3>(c, R_q, dvhat, dv, dq, st); break;
+        default: break;
     }
+    if (e == MEHDG_OK) {
+        int64_t sz[5];
+        (void)mehdg_sizes(c->p, sz);
+        e = launch_poison(c, PoisonArgs{{dv, dq, nullptr, nullptr}, {sz[2], sz[3], 0, 0}}, st);
+    }
+    return e;
 }
 
 mehdg_err mehdg_copy_bordered(mehdg_ctx* c, int64_t m, double* out, int64_t* rows, int64_t* ld) {
