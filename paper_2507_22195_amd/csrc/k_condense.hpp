@@ -27,6 +27,8 @@
 // Then one k_gemm with K = N_V forms Ahat = A' - L21 U12 and bhat = r_hat - L21 y
 // directly in the caller's arrays.
 #pragma once
+#include <type_traits>
+
 #include "k_assemble.hpp"
 
 namespace mehdg {
@@ -242,8 +244,11 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         candidate(0, cv);
     }
     bool bad = false;
-#pragma clang loop unroll(disable)
-    for (int j = 0; j < nb; ++j) {
+    // one column; from column j0 on only z[0 .. 64-j0) can hold live entries
+    // (the pivot row reads as zero beyond), so the segment starting at j0 is
+    // compiled with AW = 64 - j0 live registers and moves the rest unchanged
+    auto column = [&](int j, auto aw) {
+        constexpr int AW = decltype(aw)::value;
         const int bf = j & 1;
         __syncthreads();
         double b = redv[bf][0];
@@ -263,12 +268,12 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
             const bool own = id[r] == p;
             if (own) {
 #pragma unroll
-                for (int c = 0; c < NB; ++c) prow[bf][c] = z[r][c];
+                for (int c = 0; c < AW; ++c) prow[bf][c] = z[r][c];
                 done[r] = true;
             }
             own_wave |= __ballot(own) != 0ull;
         }
-        if (own_wave && lane >= NB - j) prow[bf][lane] = 0.0;   // same wave, after the row
+        if (own_wave && lane >= NB - j && lane < AW) prow[bf][lane] = 0.0;   // same wave, after the row
         __syncthreads();
         const double pv = prow[bf][0];
         const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
@@ -283,11 +288,22 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
 #pragma unroll
-            for (int c = 1; c < NB - 1; ++c) z[r][c] = z[r][c + 1] - l[r] * prow[bf][c + 1];
+            for (int c = 1; c < AW - 1; ++c) z[r][c] = z[r][c + 1] - l[r] * prow[bf][c + 1];
+#pragma unroll
+            for (int c = (AW - 1 > 1 ? AW - 1 : 1); c < NB - 1; ++c) z[r][c] = z[r][c + 1];
             z[r][0] = nz0[r];
             z[r][NB - 1] = done[r] ? z0[r] : l[r];
         }
-    }
+    };
+    const int j1 = nb < 16 ? nb : 16, j2 = nb < 32 ? nb : 32, j3 = nb < 48 ? nb : 48;
+#pragma clang loop unroll(disable)
+    for (int j = 0; j < j1; ++j) column(j, std::integral_constant<int, 64>{});
+#pragma clang loop unroll(disable)
+    for (int j = j1; j < j2; ++j) column(j, std::integral_constant<int, 48>{});
+#pragma clang loop unroll(disable)
+    for (int j = j2; j < j3; ++j) column(j, std::integral_constant<int, 32>{});
+#pragma clang loop unroll(disable)
+    for (int j = j3; j < nb; ++j) column(j, std::integral_constant<int, 16>{});
     // replay of the interchanges: position kb+j with the pivot's current position
     if (second && tid < NB) pv1[tid] = ipiv[m * NV + kb0 + tid];
     __syncthreads();
