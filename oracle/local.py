@@ -127,8 +127,12 @@ def _face_flux(vhs, vs, qs, n, prm):
     return list(Fh), Fh
 
 
-def residual(p, h, v, vhat, v_old, prm, q=None, face_bc=None):
+def residual(p, h, v, vhat, v_old, prm, q=None, face_bc=None, old=None):
     """Residual blocks and face entropy production of a batch of macros.
+
+    With ``old`` [M][5][n] given, the time term is alpha_t ((u(v), phi_a) - old)
+    instead of alpha_t (u(v) - u(v_old), phi_a): the stage form of a DIRK
+    step, whose old term is a combination of earlier stages (Sec. 5.3).
 
     Returns dict R_q [M][5][3][n], R_v [M][5][n], R_vhat [M][6][5][nf],
     entropy [M], q [M][5][3][n] (the q used).
@@ -168,7 +172,10 @@ def residual(p, h, v, vhat, v_old, prm, q=None, face_bc=None):
         Fv = F
     R_v = np.zeros((M_, 5, geo.n))
     for k in range(5):
-        R_v[:, k] += prm["alpha_t"] * ((wv * (u[k] - u_old[k])) @ t["vol_phi"])
+        if old is None:
+            R_v[:, k] += prm["alpha_t"] * ((wv * (u[k] - u_old[k])) @ t["vol_phi"])
+        else:
+            R_v[:, k] += prm["alpha_t"] * ((wv * u[k]) @ t["vol_phi"] - old[:, k])
         for j in range(3):
             R_v[:, k] -= ((wv * geo.invh[:, j, None]) * Fv[j][k]) @ t["vol_dphi"][j]
 
@@ -186,6 +193,15 @@ def residual(p, h, v, vhat, v_old, prm, q=None, face_bc=None):
         integrand = ph.entropy_production_integrand(_comp(vhs, 1), _comp(vs, 1), Finv, n, gamma)
         ent += np.sum(ws * integrand, axis=1)
     return dict(R_q=R_q, R_v=R_v, R_vhat=R_vh, entropy=ent, q=q)
+
+
+def time_functional(p, h, v, prm):
+    """(u(v), phi_a) per macro -> [M][5][n] (the mass term of the time derivative)."""
+    geo = Geometry(p, h)
+    vg = np.einsum("ga,mka->mkg", geo.t["vol_phi"], v)
+    u = ph.conservative_from_entropy(_comp(vg, 1), prm["gamma"])
+    wv = geo.w_vol()
+    return np.stack([(wv * u[k]) @ geo.t["vol_phi"] for k in range(5)], axis=1)
 
 
 # --------------------------------------------------------------------------
@@ -314,13 +330,13 @@ def _apply_Aqq_inv(Mm, X):
     return out.reshape(X.shape) if not vec else out.reshape(-1)
 
 
-def condense(p, h, v, vhat, v_old, prm, q=None, want_cond=False):
+def condense(p, h, v, vhat, v_old, prm, q=None, want_cond=False, old=None):
     """Residual, blocks and condensed system of each macro.
 
     Returns dict with R_q, R_v, R_vhat, entropy, Ahat [M][NH][NH],
-    bhat [M][NH], and the pieces needed for recovery.
+    bhat [M][NH], and the pieces needed for recovery.  ``old``: see residual.
     """
-    res = residual(p, h, v, vhat, v_old, prm, q=q)
+    res = residual(p, h, v, vhat, v_old, prm, q=q, old=old)
     J = jacobian(p, h, v, vhat, v_old, prm, q=res["q"])
     M_ = v.shape[0]
     out = dict(res)
