@@ -352,8 +352,70 @@ __global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_v(const double* __r
 }
 
 // Rows of the trace equations: one workgroup per (macro, face f, trace node c), 5 rows.
+// The test function of such a row lives on face f, so the row couples to v and
+// q only through the nf nodes of that face and to vhat only on that face: the
+// accumulators are stored face-compact (index e = b_t1 + n1d b_t2 over the
+// face's tangential axes), a quarter of the LDS of a volume row, so more
+// workgroups share a CU.  The elimination of Q is the same as in row_write,
+// with the off-face entries read as zero.
 template <int P>
-__global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_h(const double* __restrict__ coefF,
+struct RowLdsH {
+    using D = Dims<P>;
+    static constexpr int E2 = (P + 1) * (P + 1);
+    double av[5][D::nf];
+    double aq[15][D::nf];
+    double ah[5][D::nf];
+    double w[E2 * 25];
+    double red[RowCfg<P>::THREADS / 64];
+    Tab1D t;
+};
+
+template <int P>
+__device__ void row_face_h(RowLdsH<P>& L, const double* __restrict__ coefF, int64_t m, int f, int c1, int c2,
+                           int e1, int e2, int k, bool viscous) {
+    using D = Dims<P>;
+    using R = RowLdsH<P>;
+    constexpr int n1d = D::n1d, nq1 = D::nq1, S = D::S;
+    constexpr int Q = P + 1;
+    for (int sl = threadIdx.x; sl < R::E2; sl += blockDim.x) {
+        const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
+        const int s = s1 + nq1 * s2;
+        const double t = L.t.B[s1][c1] * L.t.B[s2][c2];
+        const double* c = coefF + ((int64_t)m * 6 * S + f * S + s) * COEF_F;
+        double* w = L.w + sl * 25;
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+            w[l] = t * c[5 * k + l];
+            w[5 + l] = t * c[25 + 5 * k + l];
+        }
+        if (viscous) {
+#pragma unroll
+            for (int l = 0; l < 5; ++l)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) w[10 + 3 * l + j] = t * c[50 + 25 * j + 5 * k + l];
+        }
+    }
+    __syncthreads();
+    const int nf_ = viscous ? 25 : 10;
+    for (int idx = threadIdx.x; idx < nf_ * R::E2; idx += blockDim.x) {
+        const int bl = idx % R::E2, fld = idx / R::E2;
+        const int b1 = e1 * P + bl % Q, b2 = e2 * P + bl / Q;
+        const double* w = L.w + fld;
+        double acc = 0.0;
+        for (int sl = 0; sl < R::E2; ++sl) {
+            const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
+            acc += w[sl * 25] * (L.t.B[s1][b1] * L.t.B[s2][b2]);
+        }
+        const int e = b1 + n1d * b2;
+        if (fld < 5) L.av[fld][e] += acc;
+        else if (fld < 10) L.ah[fld - 5][e] += acc;
+        else L.aq[fld - 10][e] += acc;
+    }
+    __syncthreads();
+}
+
+template <int P>
+__global__ void __launch_bounds__(RowCfg<P>::THREADS, 6) k_rows_h(const double* __restrict__ coefF,
                                                                const double* __restrict__ R_vh,
                                                                const double* __restrict__ minvrq,
                                                                const double* __restrict__ hs,
@@ -361,9 +423,9 @@ __global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_h(const double* __r
                                                                double* __restrict__ B, int64_t n_macro) {
     using D = Dims<P>;
     using BD = Bdims<P>;
-    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, KG = RowLds<P>::KG;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    RowLds<P>& L = *reinterpret_cast<RowLds<P>*>(smem_raw);
+    RowLdsH<P>& L = *reinterpret_cast<RowLdsH<P>*>(smem_raw);
     int64_t m;
     int fc;
     xcd_tile(6 * nf, m, fc);
@@ -371,21 +433,94 @@ __global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_h(const double* __r
     const int f = fc / nf, c = fc % nf;
     const bool viscous = viscous_i != 0;
     const int c1 = c % n1d, c2 = c / n1d;
+    const int d = face_axis(f), ft1 = face_t1(f), ft2 = face_t2(f);
+    const int iF = face_side(f) ? (n1d - 1) : 0;
     const double hinv[3] = {1.0 / hs[3 * m], 1.0 / hs[3 * m + 1], 1.0 / hs[3 * m + 2]};
-    stage_tables<P>(L, tab);
+    {
+        const double* src = reinterpret_cast<const double*>(tab);
+        double* dst = reinterpret_cast<double*>(&L.t);
+        for (int i = threadIdx.x; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
+    }
     int l1, u1, l2, u2;
     support_1d<P>(c1, l1, u1);
     support_1d<P>(c2, l2, u2);
-    for (int k0 = 0; k0 < 5; k0 += KG) {
-        row_zero<P>(L);
+    double* Bm = B + m * BD::per_macro;
+    const double* mrq = minvrq + m * 15 * n;
+    for (int k = 0; k < 5; ++k) {
+        for (int i = threadIdx.x; i < 25 * nf; i += blockDim.x) (&L.av[0][0])[i] = 0.0;   // av, aq, ah
         __syncthreads();
         for (int e2 = l2; e2 <= u2; ++e2)
-            for (int e1 = l1; e1 <= u1; ++e1) row_face<P>(L, coefF, m, f, c1, c2, e1, e2, k0, viscous);
-        double Rv[KG];
-#pragma unroll
-        for (int kk = 0; kk < KG; ++kk) Rv[kk] = R_vh[((m * 6 + f) * 5 + k0 + kk) * nf + c];
-        row_write<P>(L, B + m * BD::per_macro, NV + (f * 5 + k0) * nf + c, nf, minvrq + m * 15 * n, Rv, hinv,
-                     viscous);
+            for (int e1 = l1; e1 <= u1; ++e1) row_face_h<P>(L, coefF, m, f, c1, c2, e1, e2, k, viscous);
+        const int64_t row = NV + (f * 5 + k) * nf + c;
+        for (int col = threadIdx.x; col < BD::ld; col += blockDim.x) {
+            double val = 0.0;
+            if (col < NV) {
+                const int l = col / n, b = col % n;
+                const int bi[3] = {b % n1d, (b / n1d) % n1d, b / (n1d * n1d)};
+                const int t1 = bi[ft1], t2 = bi[ft2];
+                const bool on = bi[d] == iF;
+                if (on) val = L.av[l][t1 + n1d * t2];
+                if (viscous) {
+                    // lift along the normal axis: the line meets the face in one node
+                    val -= hinv[d] * (L.aq[3 * l + d][t1 + n1d * t2] * L.t.Lam[iF][bi[d]]);
+                    // lifts along the face: only for nodes of the face
+                    if (on) {
+                        double a1 = 0.0, a2 = 0.0;
+                        for (int cc = 0; cc < n1d; ++cc) {
+                            a1 += L.aq[3 * l + ft1][cc + n1d * t2] * L.t.Lam[cc][t1];
+                            a2 += L.aq[3 * l + ft2][t1 + n1d * cc] * L.t.Lam[cc][t2];
+                        }
+                        val -= hinv[ft1] * a1;
+                        val -= hinv[ft2] * a2;
+                    }
+                }
+            } else if (col < NV + NH) {
+                const int r = col - NV;
+                const int fp = r / (5 * nf), l = (r / nf) % 5, e = r % nf;
+                if (fp == f) val = L.ah[l][e];
+                if (viscous) {
+                    const int dp = face_axis(fp);
+                    const int iFp = face_side(fp) ? (n1d - 1) : 0;
+                    double acc = 0.0;
+                    if (dp == d) {
+                        // faces of the same axis: the line along d meets face f at node e
+                        acc = L.aq[3 * l + d][e] * L.t.Minv[iF][iFp];
+                    } else {
+                        int ci[3];
+                        ci[face_t1(fp)] = e % n1d;
+                        ci[face_t2(fp)] = e / n1d;
+                        if (ci[d] == iF) {
+                            for (int cd = 0; cd < n1d; ++cd) {
+                                ci[dp] = cd;
+                                acc += L.aq[3 * l + dp][ci[ft1] + n1d * ci[ft2]] * L.t.Minv[cd][iFp];
+                            }
+                        }
+                    }
+                    val += face_sign(fp) * hinv[dp] * acc;
+                }
+            }
+            if (col != NV + NH) Bm[row * BD::ld + col] = val;
+        }
+        // right-hand side -R_Vhat + A_hq A_qq^-1 R_Q (only face nodes of q contribute)
+        double part = 0.0;
+        if (viscous)
+            for (int i = threadIdx.x; i < 15 * nf; i += blockDim.x) {
+                const int fld = i / nf, e = i % nf;
+                int bi[3];
+                bi[d] = iF;
+                bi[ft1] = e % n1d;
+                bi[ft2] = e / n1d;
+                part += L.aq[fld][e] * mrq[fld * n + bi[0] + n1d * (bi[1] + n1d * bi[2])];
+            }
+        for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+        if ((threadIdx.x & 63) == 0) L.red[threadIdx.x >> 6] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int i = 0; i < (int)(blockDim.x / 64); ++i) s += L.red[i];
+            Bm[row * BD::ld + NV + NH] = -R_vh[((m * 6 + f) * 5 + k) * nf + c] + s;
+        }
+        __syncthreads();
     }
 }
 

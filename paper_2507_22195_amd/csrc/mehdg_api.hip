@@ -140,8 +140,8 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
         hipLaunchKernelGGL(k_minv_rq<P>, dim3(M), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
     }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
-    const size_t rl = sizeof(RowLds<P>);
-    if (!allow_lds(&k_rows_v<P>, rl) || !allow_lds(&k_rows_h<P>, rl)) return MEHDG_EHIP;
+    const size_t rl = sizeof(RowLds<P>), rlh = sizeof(RowLdsH<P>);
+    if (!allow_lds(&k_rows_v<P>, rl) || !allow_lds(&k_rows_h<P>, rlh)) return MEHDG_EHIP;
     {
         Timed t(c, MEHDG_PROF_ROWS_V, st);
         hipLaunchKernelGGL(k_rows_v<P>, dim3(xcd_grid(D::n, c->n_macro)), dim3(RowCfg<P>::THREADS), rl, st, c->d_coefV,
@@ -150,7 +150,7 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     {
         Timed t(c, MEHDG_PROF_ROWS_H, st);
-        hipLaunchKernelGGL(k_rows_h<P>, dim3(xcd_grid(6 * D::nf, c->n_macro)), dim3(RowCfg<P>::THREADS), rl, st,
+        hipLaunchKernelGGL(k_rows_h<P>, dim3(xcd_grid(6 * D::nf, c->n_macro)), dim3(RowCfg<P>::THREADS), rlh, st,
                            c->d_coefF, R_vhat, c->d_minvrq, c->d_h, c->d_tab, c->dp.viscous, c->d_B,
                            (int64_t)c->n_macro);
     }
