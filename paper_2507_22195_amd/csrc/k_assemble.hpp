@@ -171,24 +171,19 @@ __device__ void row_face(RowLds<P>& L, const double* __restrict__ coefF, int64_t
     using R = RowLds<P>;
     constexpr int n1d = D::n1d, nq1 = D::nq1, S = D::S, KG = R::KG;
     constexpr int Q = P + 1;
-    for (int idx = threadIdx.x; idx < R::E2 * KG; idx += blockDim.x) {
-        const int sl = idx % R::E2, kk = idx / R::E2, k = k0 + kk;
+    // one (point, trial field) pair per thread (one coefficient load each)
+    const int nff = viscous ? 25 : 10;
+    for (int idx = threadIdx.x; idx < R::E2 * nff * KG; idx += blockDim.x) {
+        const int sl = idx % R::E2, rest = idx / R::E2;
+        const int fld = rest % nff, kk = rest / nff, k = k0 + kk;
         const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
         const int s = s1 + nq1 * s2;
-        const double t = L.t.B[s1][c1] * L.t.B[s2][c2];
         const double* c = coefF + ((int64_t)m * 6 * S + f * S + s) * COEF_F;
-        double* w = L.w + (kk * R::E2 + sl) * 25;
-#pragma unroll
-        for (int l = 0; l < 5; ++l) {
-            w[l] = t * c[5 * k + l];
-            w[5 + l] = t * c[25 + 5 * k + l];
-        }
-        if (viscous) {
-#pragma unroll
-            for (int l = 0; l < 5; ++l)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) w[10 + 3 * l + j] = t * c[50 + 25 * j + 5 * k + l];
-        }
+        int off;
+        if (fld < 5) off = 5 * k + fld;
+        else if (fld < 10) off = 25 + 5 * k + (fld - 5);
+        else off = 50 + 25 * ((fld - 10) % 3) + 5 * k + (fld - 10) / 3;
+        L.w[(kk * R::E2 + sl) * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off];
     }
     __syncthreads();
     const int d = face_axis(f), t1 = face_t1(f), t2 = face_t2(f);
@@ -302,7 +297,7 @@ __device__ void stage_tables(RowLds<P>& L, const Tab1D* __restrict__ tab) {
 // the workgroups of a macro share one XCD, whose L2 then serves the
 // coefficient slabs they all read.
 template <int P>
-__global__ void __launch_bounds__(RowCfg<P>::THREADS) k_rows_v(const double* __restrict__ coefV,
+__global__ void __launch_bounds__(RowCfg<P>::THREADS, 4) k_rows_v(const double* __restrict__ coefV,
                                                                const double* __restrict__ coefF,
                                                                const double* __restrict__ R_v,
                                                                const double* __restrict__ minvrq,
@@ -377,26 +372,20 @@ __device__ void row_face_h(RowLdsH<P>& L, const double* __restrict__ coefF, int6
     using R = RowLdsH<P>;
     constexpr int n1d = D::n1d, nq1 = D::nq1, S = D::S;
     constexpr int Q = P + 1;
-    for (int sl = threadIdx.x; sl < R::E2; sl += blockDim.x) {
+    // one (point, trial field) pair per thread (one coefficient load each)
+    const int nf_ = viscous ? 25 : 10;
+    for (int idx = threadIdx.x; idx < R::E2 * nf_; idx += blockDim.x) {
+        const int sl = idx % R::E2, fld = idx / R::E2;
         const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
         const int s = s1 + nq1 * s2;
-        const double t = L.t.B[s1][c1] * L.t.B[s2][c2];
         const double* c = coefF + ((int64_t)m * 6 * S + f * S + s) * COEF_F;
-        double* w = L.w + sl * 25;
-#pragma unroll
-        for (int l = 0; l < 5; ++l) {
-            w[l] = t * c[5 * k + l];
-            w[5 + l] = t * c[25 + 5 * k + l];
-        }
-        if (viscous) {
-#pragma unroll
-            for (int l = 0; l < 5; ++l)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) w[10 + 3 * l + j] = t * c[50 + 25 * j + 5 * k + l];
-        }
+        int off;
+        if (fld < 5) off = 5 * k + fld;
+        else if (fld < 10) off = 25 + 5 * k + (fld - 5);
+        else off = 50 + 25 * ((fld - 10) % 3) + 5 * k + (fld - 10) / 3;
+        L.w[sl * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off];
     }
     __syncthreads();
-    const int nf_ = viscous ? 25 : 10;
     for (int idx = threadIdx.x; idx < nf_ * R::E2; idx += blockDim.x) {
         const int bl = idx % R::E2, fld = idx / R::E2;
         const int b1 = e1 * P + bl % Q, b2 = e2 * P + bl / Q;
