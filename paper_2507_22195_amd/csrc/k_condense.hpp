@@ -66,6 +66,15 @@ __device__ __forceinline__ double read_lane_f64(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
+// Wave-wide sum with the same permutations; every lane gets the sum.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_perm_f64(v, 0);
+    v += dpp_perm_f64(v, 1);
+    v += dpp_perm_f64(v, 2);
+    v += dpp_perm_f64(v, 3);
+    return (read_lane_f64(v, 0) + read_lane_f64(v, 16)) + (read_lane_f64(v, 32) + read_lane_f64(v, 48));
+}
+
 __device__ __forceinline__ double wave_max_f64(double v) {
     v = fmax(v, dpp_perm_f64(v, 0));
     v = fmax(v, dpp_perm_f64(v, 1));

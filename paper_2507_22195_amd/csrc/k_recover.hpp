@@ -5,7 +5,8 @@
 //   dV = S^-1 (r_V + Y dVhat) = U^-1 (y - U12 dVhat),
 // and then, with A_qq = I (x) M and the 1-D tensor structure of the lifts,
 //   dQ_{lj} = -M^-1 R_Q,lj - (Lam/h_j)_axis-j dV_l + (lift of dVhat_l on the faces normal to j).
-// One workgroup per macro; U is read once, row-wise and coalesced.
+// One workgroup per macro; U and U12 are read once, row-wise and coalesced;
+// dot products are reduced within a wave with DPP row permutations.
 #pragma once
 #include "k_condense.hpp"
 
@@ -22,7 +23,7 @@ struct RecLds {
 };
 
 template <int P>
-__global__ void __launch_bounds__(256) k_recover(const double* __restrict__ B, const double* __restrict__ R_q,
+__global__ void __launch_bounds__(1024) k_recover(const double* __restrict__ B, const double* __restrict__ R_q,
                                                  const double* __restrict__ dvhat, const double* __restrict__ hs,
                                                  const Tab1D* __restrict__ tab, double* __restrict__ dv,
                                                  double* __restrict__ dq) {
@@ -41,16 +42,34 @@ __global__ void __launch_bounds__(256) k_recover(const double* __restrict__ B, c
     }
     for (int i = tid; i < NH; i += blockDim.x) L.dvh[i] = dvhat[m * NH + i];
     __syncthreads();
-    // z = y - U12 dVhat   (one wave per row, lanes along the row)
-    for (int r = wave; r < NV; r += nw) {
-        const double* row = Bm + (int64_t)r * ld + NV;
-        double s = 0.0;
-        for (int c = lane; c < NH; c += 64) s += row[c] * L.dvh[c];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) L.z[r] = row[NH] - s;
+    // z = y - U12 dVhat: each wave takes RB rows at a time, lanes along the
+    // rows (coalesced), and reduces the RB dot products together
+    constexpr int RB = 8;
+    for (int r0 = wave * RB; r0 < NV; r0 += nw * RB) {
+        double s[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = 0.0;
+        for (int c = lane; c < NH; c += 64) {
+            const double x = L.dvh[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < NV) s[i] += Bm[(int64_t)(r0 + i) * ld + NV + c] * x;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+        if (lane < RB && r0 + lane < NV) {
+            double si = s[0];
+#pragma unroll
+            for (int i = 1; i < RB; ++i)
+                if (lane == i) si = s[i];
+            L.z[r0 + lane] = Bm[(int64_t)(r0 + lane) * ld + NV + NH] - si;
+        }
     }
     __syncthreads();
-    // U dV = z, blocks of 64 rows from the bottom
+    // U dV = z, left-looking over blocks of 64 rows from the bottom: the rows
+    // of a block first take their dot products with the solved part, then
+    // wave 0 solves the 64 x 64 triangle (lane j holds row j; the solved value
+    // is broadcast with a lane read)
     for (int i1 = NV; i1 > 0; i1 -= 64) {
         const int i0 = i1 - 64 > 0 ? i1 - 64 : 0;
         const int nb = i1 - i0;
@@ -58,23 +77,35 @@ __global__ void __launch_bounds__(256) k_recover(const double* __restrict__ B, c
             const int r = e >> 6, c = e & 63;
             L.U[r][c] = (r < nb && c < nb) ? Bm[(int64_t)(i0 + r) * ld + i0 + c] : 0.0;
         }
+        for (int r0 = i0 + wave * RB; r0 < i1; r0 += nw * RB) {
+            double s[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) s[i] = 0.0;
+            for (int c = i1 + lane; c < NV; c += 64) {
+                const double x = L.z[c];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    if (r0 + i < i1) s[i] += Bm[(int64_t)(r0 + i) * ld + c] * x;
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+            if (lane < RB && r0 + lane < i1) {
+                double si = s[0];
+#pragma unroll
+                for (int i = 1; i < RB; ++i)
+                    if (lane == i) si = s[i];
+                L.z[r0 + lane] -= si;
+            }
+        }
         __syncthreads();
         if (wave == 0) {
             double zi = (lane < nb) ? L.z[i0 + lane] : 0.0;
             for (int j = nb - 1; j >= 0; --j) {
-                double xj = (lane == j) ? zi / L.U[j][j] : 0.0;
-                xj = __shfl(xj, j, 64);
+                const double xj = read_lane_f64(zi, j) / L.U[j][j];
                 if (lane == j) zi = xj;
                 else if (lane < j) zi -= L.U[lane][j] * xj;
             }
             if (lane < nb) L.z[i0 + lane] = zi;   // now holds dV for this block
-        }
-        __syncthreads();
-        for (int r = wave; r < i0; r += nw) {
-            const double* row = Bm + (int64_t)r * ld + i0;
-            double s = (lane < nb) ? row[lane] * L.z[i0 + lane] : 0.0;
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-            if (lane == 0) L.z[r] -= s;
         }
         __syncthreads();
     }
