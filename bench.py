@@ -135,7 +135,7 @@ def cpu_baseline(w, target_s=15.0):
 
     run(np.arange(1))                                  # warm caches / BLAS threads
     per = run(np.arange(2)) / 2.0
-    count = int(max(2, min(64, target_s / max(per, 1e-3))))
+    count = int(max(2, min(256, target_s / max(per, 1e-3))))
     idx = rng.choice(w.n_macro, size=count, replace=False)
     t = run(np.sort(idx))
     return dict(value=count / t, unit="macro-elements/s", cores=int(threads), kind="oracle",
