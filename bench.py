@@ -34,32 +34,34 @@ def kernel_models(p, n_macro, NV, NH, viscous):
     Follows the blocking of the condensation: outer blocks of OB = 128
     columns made of two 64-column panels; inside a block the second panel's
     columns are updated after the first panel (K = 64), after the block the
-    L-shaped trailing region without the A' corner (K = block width), and at
-    the end Ahat = A' - L21 U12 with K = N_V.  Flops count useful products
-    only (no padding of tiles or of the triangular inverses).
+    S rows right of it (K = block width); the X rows are solved afterwards,
+    panel by panel (L21[:, q] = (X[:, q] - L21[:, <q] U[<q, q]) U_qq^-1), and
+    at the end Ahat = A' - L21 U12 with K = N_V.  Flops count useful
+    products only (no padding of tiles or of the triangular inverses).
     """
     from paper_2507_22195_amd.workloads import sizes
     s = sizes(p)
     n, nf = s["n"], s["nf"]
-    ROWS, COLS = NV + NH, NV + NH + 1
+    COLS = NV + NH + 1
     ld = (COLS + 7) // 8 * 8
     NB, OB = 64, 128
-    upd = tri = panel = 0.0
+    upd = tri = panel = trsm = 0.0
     for kb0 in range(0, NV, OB):
         w = min(OB, NV - kb0)
         panels = [(kb0, min(NB, w))] + ([(kb0 + NB, w - NB)] if w > NB else [])
         for kb, nb in panels:
             # panel: rank-1 updates inside the panel columns, then the two inverses
             panel += sum(2.0 * (NV - kb - j) * (nb - j) for j in range(nb)) + 2.0 * nb ** 3 / 3.0
-            # L21 of X for the panel columns: X_panel (NH x nb) times U_kk^-1 (upper)
-            tri += NH * nb * nb
         if w > NB:
             o = kb0 + NB
-            upd += 2.0 * NB * (ROWS - o) * (w - NB)          # second panel's columns
+            upd += 2.0 * NB * (NV - o) * (w - NB)            # second panel's columns, S rows
             tri += NB * NB * (w - NB)                        # its U rows (unit-lower solve)
         o = kb0 + w
         tri += w * w * (COLS - o)                            # U rows right of the block
-        upd += 2.0 * w * ((ROWS - o) * (COLS - o) - NH * (NH + 1) if o < NV else 0.0)
+        upd += 2.0 * w * (NV - o) * (COLS - o)               # S rows right of the block
+    for kq in range(0, NV, NB):
+        nbq = min(NB, NV - kq)
+        trsm += 2.0 * NH * nbq * kq + NH * nbq * nbq          # X rows: long-K product + U_qq^-1
     schur = 2.0 * NH * (NH + 1) * NV
     M = n_macro
     return {
@@ -67,6 +69,7 @@ def kernel_models(p, n_macro, NV, NH, viscous):
         "schur": ("mfma", schur * M),
         "panel": ("alu", panel * M),
         "rowblock": ("mfma", tri * M),
+        "trsm": ("mfma", trsm * M),
         # bordered rows: every entry written once
         "rows_v": ("hbm", 8.0 * NV * ld * M),
         "rows_h": ("hbm", 8.0 * NH * ld * M),
@@ -81,12 +84,13 @@ def kernel_models(p, n_macro, NV, NH, viscous):
 SLOT_KERNELS = {
     "residual": "k_residual", "minv_rq": "k_minv_rq", "rows_v": "k_rows_v", "rows_h": "k_rows_h",
     "panel": "k_panel", "rowblock": "k_tri", "update": "k_gemm<0>", "schur": "k_gemm<1>", "recover": "k_recover",
+    "trsm": "k_trsm_x",
 }
 # source file of each slot's kernel (the HBM traffic on record is void once it changes)
 SLOT_SOURCES = {
     "residual": "k_residual.hpp", "minv_rq": "k_assemble.hpp", "rows_v": "k_assemble.hpp", "rows_h": "k_assemble.hpp",
     "panel": "k_condense.hpp", "rowblock": "k_condense.hpp", "update": "k_condense.hpp", "schur": "k_condense.hpp",
-    "recover": "k_recover.hpp",
+    "recover": "k_recover.hpp", "trsm": "k_condense.hpp",
 }
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "tgv16_p2_hbm_traffic.txt")
 
@@ -247,7 +251,8 @@ def main():
     roof["kernel"] = SLOT_KERNELS[dom]
     roof["work_per_launch"] = work / calls
     # whole condensation against the dense algorithmic count (2/3 N^3 + 2 N^2 M + 2 M^2 N per macro)
-    cond_ms = sum(kernels[k]["ms_per_step"] for k in ("panel", "rowblock", "update", "schur") if k in kernels)
+    cond_ms = sum(kernels[k]["ms_per_step"] for k in ("panel", "rowblock", "update", "schur", "trsm")
+                  if k in kernels)
     cond_flops = M * (2.0 / 3.0 * NV ** 3 + 2.0 * NV ** 2 * NH + 2.0 * NH ** 2 * NV)
     out = {
         "metric": "macro-elements/s for assemble+condense; mixed vs FP64 at 1e-10 rel err",

@@ -155,11 +155,12 @@ enum {
     MEHDG_PROF_ROWS_V = 2,     /* bordered rows of the interior equations */
     MEHDG_PROF_ROWS_H = 3,     /* bordered rows of the trace equations */
     MEHDG_PROF_PANEL = 4,      /* panel factorisation */
-    MEHDG_PROF_ROWBLOCK = 5,   /* L_kk^-1 and U_kk^-1 applied to the panel's row / column block */
+    MEHDG_PROF_ROWBLOCK = 5,   /* L^-1 applied to the columns right of a panel / block */
     MEHDG_PROF_UPDATE = 6,     /* trailing MFMA update */
     MEHDG_PROF_SCHUR = 7,      /* Ahat = A' - L21 U12 on MFMA */
     MEHDG_PROF_RECOVER = 8,    /* back-substitution */
-    MEHDG_NPROF = 9
+    MEHDG_PROF_TRSM = 9,       /* L21 = X U^-1 of the trace rows */
+    MEHDG_NPROF = 10
 };
 mehdg_err mehdg_profile_enable(mehdg_ctx* ctx, int32_t enable);
 mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t n);

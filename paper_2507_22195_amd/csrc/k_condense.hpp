@@ -19,13 +19,17 @@
 //               forms the inverse of the block's unit-lower diagonal block;
 //   k_tri       per 64-column tile right of the (panel or outer) block: apply
 //               the composed row interchange and form U_top = L^-1 (P B)_top
-//               on MFMA; per 128-row tile of X: L21 = X_panel U_kk^-1;
-//   k_gemm      rank-nb update on FP64 MFMA: inside the outer block, the
-//               second panel's columns after the first panel; after the
-//               block, the L-shaped trailing region (all rows x S columns and
-//               S rows x border columns) with K = 128; A' is left alone.
-// Then one k_gemm with K = N_V forms Ahat = A' - L21 U12 and bhat = r_hat - L21 y
-// directly in the caller's arrays.
+//               on MFMA;
+//   k_gemm      rank-nb update of the S rows on FP64 MFMA: inside the outer
+//               block, the second panel's columns after the first panel;
+//               after the block, the S rows right of it (S and border
+//               columns) with K = 128.
+// The X rows take no part in the factorisation of S.  Afterwards, panel by
+// panel, k_trsm_x forms L21 = X U^-1 left-looking,
+//   L21[:, q] = (X[:, q] - L21[:, <q] U[<q, q]) U_qq^-1,
+// long-K MFMA products written once, in place of X.  Then one k_gemm with
+// K = N_V forms Ahat = A' - L21 U12 and bhat = r_hat - L21 y directly in the
+// caller's arrays.
 #pragma once
 #include <type_traits>
 
@@ -91,10 +95,13 @@ struct Panel {
     static constexpr int NV = Dims<P>::NV;
     static constexpr int THREADS = ((NV + 63) / 64) * 64 > 1024 ? 1024 : ((NV + 63) / 64) * 64;
     static constexpr int RPT = (NV + THREADS - 1) / THREADS;   // S rows per thread
-    // per macro: L^-1, U^-1 of the first and of the second panel (NB x NB
-    // each), then L^-1 of the outer block's unit-lower diagonal block (OB x OB)
-    static constexpr int64_t TRI = 4 * NB * NB + OB * OB;
-    static constexpr int LINV1 = 0, UINV1 = NB * NB, LINV2 = 2 * NB * NB, UINV2 = 3 * NB * NB, LINVW = 4 * NB * NB;
+    static constexpr int NPAN = (NV + NB - 1) / NB;             // panels of S
+    // per macro: L^-1 of the first and of the second panel of the current
+    // outer block (NB x NB each), L^-1 of the block's unit-lower diagonal block
+    // (OB x OB), then U_kk^-1 of every panel (NPAN x NB x NB, kept for the
+    // triangular solve of the X rows)
+    static constexpr int LINV1 = 0, LINV2 = NB * NB, LINVW = 2 * NB * NB, UINV = 2 * NB * NB + OB * OB;
+    static constexpr int64_t TRI = (int64_t)UINV + (int64_t)NPAN * NB * NB;
     // per macro: composed interchange of the current block: [0, OB) source
     // rows of the top rows, [OB, 2 OB) rows below the block that change,
     // [2 OB, 3 OB) their source rows, [3 OB] their number
@@ -470,7 +477,7 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
     __syncthreads();
     double* Ti = tri + m * PN::TRI;
     double* Tl = Ti + (second ? PN::LINV2 : PN::LINV1);
-    double* Tu = Ti + (second ? PN::UINV2 : PN::UINV1);
+    double* Tu = Ti + PN::UINV + (int64_t)(kb / NB) * NB * NB;
     for (int e = tid; e < NB * NB; e += NT) {
         const int i = e / NB, c = e % NB;
         Tl[e] = XL[i][c];
@@ -711,6 +718,63 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
                     if (r < ROWS && c < a.np) Bm[(int64_t)r * ld + a.kp + c] = acc[bi][bj][q];
                 }
     }
+}
+
+// ---------------------------------------------------------------------------
+// L21 of the X rows for panel q (columns [kq, kq+nbq)), left-looking: per
+// 128-row tile of X, acc = X[:, q] - L21[:, <q] U[<q, q] (K = kq, the earlier
+// panels' L21 already in place of X), written in place, then
+// L21[:, q] = acc U_qq^-1 (K = nbq) in place.  Each workgroup reads its own
+// tile back only after writing it.
+template <int P>
+__global__ void __launch_bounds__(GTHREADS, 4) k_trsm_x(double* B, const double* __restrict__ tri, int q,
+                                                     int64_t n_macro) {
+    using BD = Bdims<P>;
+    using PN = Panel<P>;
+    constexpr int NB = PN::NB, NV = PN::NV, ld = BD::ld, ROWS = BD::rows;
+    __shared__ TileSmem sm;
+    int64_t m;
+    int tile;
+    xcd_tile((ROWS - NV + GM - 1) / GM, m, tile);
+    if (m >= n_macro) return;
+    double* Bm = B + m * BD::per_macro;
+    const int kq = q * NB, nbq = (NV - kq) < NB ? (NV - kq) : NB;
+    const int rr = NV + tile * GM;                 // rows [rr, rr+128) of X
+    double cr[2][2][4];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int r = tile_row(rr, bi, qq), c = tile_col(0, bj);
+                cr[bi][bj][qq] = (r < ROWS && c < nbq) ? Bm[(int64_t)r * ld + kq + c] : 0.0;
+            }
+    v4d acc[2][2];
+    zero_acc(acc);
+    if (kq > 0) tile_mma<true>(Bm, ld, Bm + kq, ld, kq, rr, 0, ROWS, nbq, acc, sm);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int r = tile_row(rr, bi, qq), c = tile_col(0, bj);
+                if (r < ROWS && c < nbq) Bm[(int64_t)r * ld + kq + c] = cr[bi][bj][qq] + acc[bi][bj][qq];
+            }
+    __syncthreads();
+    zero_acc(acc);
+    const double* Ui = tri + m * PN::TRI + PN::UINV + (int64_t)q * NB * NB;
+    tile_mma<false>(Bm + kq, ld, Ui, NB, nbq, rr, 0, ROWS, nbq, acc, sm);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int r = tile_row(rr, bi, qq), c = tile_col(0, bj);
+                if (r < ROWS && c < nbq) Bm[(int64_t)r * ld + kq + c] = acc[bi][bj][qq];
+            }
 }
 
 // ---------------------------------------------------------------------------

@@ -252,30 +252,24 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         TriArgs a{};
         a.kb0 = kb0;
         if (w > NB) {
-            // first panel: its U rows over the second panel's columns, L21 of X
+            // first panel: its U rows over the second panel's columns
             a.w = NB;
             a.loff = PN::LINV1;
             a.ldl = NB;
             a.c_lo = kb0 + NB;
             a.c_hi = kb0 + w;
-            a.kp = kb0;
-            a.np = NB;
-            a.uoff = PN::UINV1;
             if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
-            // the second panel's columns, all rows below the first panel
+            // the second panel's columns, S rows below the first panel
             const int o = kb0 + NB;
-            if ((e = launch_update<P>(c, kb0, NB, o, o, ROWS - o, w - NB, ROWS - o, w - NB, st)) != MEHDG_OK)
+            if ((e = launch_update<P>(c, kb0, NB, o, o, NV - o, w - NB, NV - o, w - NB, st)) != MEHDG_OK)
                 return e;
             if ((e = panel(kb0 + NB, kb0)) != MEHDG_OK) return e;
-            // the whole block: U rows right of it, L21 of X for the second panel
+            // the whole block: U rows right of it
             a.w = w;
             a.loff = PN::LINVW;
             a.ldl = PN::OB;
             a.c_lo = kb0 + w;
             a.c_hi = ld;
-            a.kp = kb0 + NB;
-            a.np = w - NB;
-            a.uoff = PN::UINV2;
             if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
         } else {
             a.w = w;
@@ -283,15 +277,23 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
             a.ldl = NB;
             a.c_lo = kb0 + w;
             a.c_hi = ld;
-            a.kp = kb0;
-            a.np = w;
-            a.uoff = PN::UINV1;
             if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
         }
-        // trailing update of the L-shaped region (A' is formed at the end)
+        // trailing update of the S rows (S and border columns)
         const int o = kb0 + w;
-        if ((e = launch_update<P>(c, kb0, w, o, o, ROWS - o, NV + NH + 1 - o, NV - o, NV - o, st)) != MEHDG_OK)
+        if ((e = launch_update<P>(c, kb0, w, o, o, NV - o, NV + NH + 1 - o, NV - o, NV + NH + 1 - o, st)) !=
+            MEHDG_OK)
             return e;
+    }
+    // L21 of the X rows, panel by panel
+    {
+        const int tiles = (NH + GM - 1) / GM;
+        for (int q = 0; q < PN::NPAN; ++q) {
+            Timed t(c, MEHDG_PROF_TRSM, st);
+            hipLaunchKernelGGL(k_trsm_x<P>, dim3(xcd_grid(tiles, c->n_macro)), dim3(GTHREADS), 0, st, c->d_B,
+                               c->d_tri, q, (int64_t)c->n_macro);
+            if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+        }
     }
     // Ahat = A' - L21 U12, bhat = r_hat - L21 y
     GemmArgs g{};

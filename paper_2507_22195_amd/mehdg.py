@@ -22,7 +22,7 @@ EXPORTS = ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "me
            "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_workspace_bytes",
            "mehdg_profile_enable", "mehdg_profile_read")
 PROF_SLOTS = ("residual", "minv_rq", "rows_v", "rows_h", "panel", "rowblock", "update", "schur",
-              "recover")
+              "recover", "trsm")
 
 
 class MehdgError(RuntimeError):
