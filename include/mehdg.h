@@ -168,6 +168,53 @@ mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t
 /* Bytes of device workspace the context holds. */
 int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
 
+/* ---------------------------------------------------------------------------
+ * Global trace system of one Newton step (Sec. 6.2, Algorithm 1): with the
+ * trace single-valued per global face,
+ *   K dVhat = F,  K = sum_m P_m^T Ahat_m P_m,  F = sum_m P_m^T bhat_m,
+ * the linearisation of sum_m R_Vhat,m = 0 (conservation on every face); P_m
+ * gathers the six faces of macro m.  Global traces are [n_faces][5][nf]
+ * (float64, device), a face's nodes ordered as on either of its two sides
+ * (axis-aligned boxes of one orientation).  Ahat, bhat as returned by
+ * mehdg_condense.
+ *
+ * Builds the face map: face_ids [n_macro][6] (host) gives the global face of
+ * every local face; every face in [0, n_faces) must occur exactly twice
+ * (periodic or interior faces; wall faces are not part of this path), else
+ * MEHDG_EINVAL.  Synchronises. */
+mehdg_err mehdg_trace_setup(mehdg_ctx* ctx, const int64_t* face_ids, int64_t n_faces);
+
+/* F = sum_m P_m^T bhat_m. */
+mehdg_err mehdg_trace_rhs(mehdg_ctx* ctx, const double* bhat, double* F, mehdg_stream stream);
+
+/* y = K x, matrix-free from the per-macro Ahat (x, y global traces). */
+mehdg_err mehdg_trace_apply(mehdg_ctx* ctx, const double* Ahat, const double* x, double* y,
+                            mehdg_stream stream);
+
+/* Per-macro trace xl [n_macro][6][5][nf] (the layout of vhat / dvhat) of a
+ * global one xg. */
+mehdg_err mehdg_trace_gather(mehdg_ctx* ctx, const double* xg, double* xl, mehdg_stream stream);
+
+/* Block-Jacobi preconditioner of K (Sec. 6.4): inverts every diagonal face
+ * block of K (5nf x 5nf: Ahat_m1[f1,f1] + Ahat_m2[f2,f2], plus the cross blocks
+ * when both sides are faces of one macro) by Gauss-Jordan elimination with
+ * partial pivoting; kept in the context.  p <= 2 (the block lives in LDS). */
+mehdg_err mehdg_trace_precond_setup(mehdg_ctx* ctx, const double* Ahat, mehdg_stream stream);
+
+/* z = D^-1 r per face with the blocks of the last mehdg_trace_precond_setup. */
+mehdg_err mehdg_trace_precond_apply(mehdg_ctx* ctx, const double* r, double* z, mehdg_stream stream);
+
+/* Solves K x = F by restarted GMRES(restart) with the block-Jacobi
+ * preconditioner on the right (set up here), classical Gram-Schmidt applied
+ * twice; x holds the initial guess and returns the solution.  Stops when the
+ * residual estimate reaches rtol ||F|| or after maxit iterations; *iters and
+ * *relres (final true residual / ||F||) on return.  The tiny Hessenberg
+ * least-squares problem is solved on the host: synchronises the stream in
+ * every iteration.  restart in [1, 60], p <= 2. */
+mehdg_err mehdg_trace_solve(mehdg_ctx* ctx, const double* Ahat, const double* F, double* x, double rtol,
+                            int32_t maxit, int32_t restart, int32_t* iters, double* relres,
+                            mehdg_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,19 @@ def _dof_map(face_ids, nf):
     return (face_ids[:, :, None] * (5 * nf) + loc[None, None, :]).reshape(M, 6 * 5 * nf)
 
 
+def trace_system(cond, face_ids, nfaces, nf):
+    """Global K (sparse, CSC) and F of the condensed local systems in ``cond``
+    (local.condense output): K = sum_m P_m^T Ahat_m P_m, F = sum_m P_m^T bhat_m."""
+    dmap = _dof_map(face_ids, nf)
+    ndof = nfaces * 5 * nf
+    rows = np.repeat(dmap[:, :, None], dmap.shape[1], axis=2).reshape(-1)
+    cols = np.repeat(dmap[:, None, :], dmap.shape[1], axis=1).reshape(-1)
+    K = sp.csc_matrix((cond["Ahat"].reshape(-1), (rows, cols)), shape=(ndof, ndof))
+    F = np.zeros(ndof)
+    np.add.at(F, dmap.reshape(-1), cond["bhat"].reshape(-1))
+    return K, F
+
+
 def gather(vh_g, face_ids):
     """Per-macro trace [M][6][5][nf] from the global one [faces][5][nf]."""
     return vh_g[face_ids]
@@ -92,11 +105,7 @@ def newton_stage(p, h, face_ids, nfaces, v, vh_g, old, prm, tol=1e-11, maxit=15)
         if res < tol or it == maxit:
             return v, vh_g, it, res
         M = v.shape[0]
-        rows = np.repeat(dmap[:, :, None], dmap.shape[1], axis=2).reshape(-1)
-        cols = np.repeat(dmap[:, None, :], dmap.shape[1], axis=1).reshape(-1)
-        K = sp.csc_matrix((c["Ahat"].reshape(-1), (rows, cols)), shape=(ndof, ndof))
-        F = np.zeros(ndof)
-        np.add.at(F, dmap.reshape(-1), c["bhat"].reshape(-1))
+        K, F = trace_system(c, face_ids, nfaces, nf)
         dV = spla.spsolve(K, F)
         dv, _ = local.recover(c, dV[dmap].reshape(M, 6, 5, nf))
         v += dv

@@ -1,0 +1,267 @@
+// Global trace system of one Newton step (Sec. 6.2, Algorithm 1):
+//   K dVhat = F,  K = sum_m P_m^T Ahat_m P_m,  F = sum_m P_m^T bhat_m,
+// the linearisation of sum_m R_Vhat,m = 0 (conservation on every face) with
+// the trace single-valued per global face.  P_m gathers the six faces of
+// macro m; a global face has exactly two sides (m1, f1), (m2, f2), whose
+// nodes are ordered alike (axis-aligned boxes of one orientation), so every
+// face-local block of 5 nf unknowns maps one to one.
+//
+// Kernels: the face sums (F, and K x from per-macro products), the gather
+// of a local trace, the matrix-free product Ahat_m x_m of every macro, the
+// inverse of the diagonal face blocks of K (block Jacobi, Sec. 6.4) by
+// in-place Gauss-Jordan with partial pivoting in LDS, its application, and
+// the vector kernels of GMRES.
+#pragma once
+#include "k_condense.hpp"
+
+namespace mehdg {
+
+// dst[g][e] = src[m1][f1][e] + src[m2][f2][e]  (face blocks of BS = 5 nf values)
+// side[g] = {m1, f1, m2, f2}
+template <int P>
+__global__ void __launch_bounds__(128) k_face_sum(const double* __restrict__ src, const int64_t* __restrict__ side,
+                                                  double* __restrict__ dst, int64_t n_faces) {
+    using D = Dims<P>;
+    constexpr int BS = 5 * D::nf, NH = D::NH;
+    const int64_t g = blockIdx.x;
+    if (g >= n_faces) return;
+    const int64_t m1 = side[4 * g], f1 = side[4 * g + 1], m2 = side[4 * g + 2], f2 = side[4 * g + 3];
+    for (int e = threadIdx.x; e < BS; e += blockDim.x)
+        dst[g * BS + e] = src[m1 * NH + f1 * BS + e] + src[m2 * NH + f2 * BS + e];
+}
+
+// xl[m][f][e] = xg[fid[m][f]][e]
+template <int P>
+__global__ void __launch_bounds__(256) k_face_gather(const double* __restrict__ xg, const int64_t* __restrict__ fid,
+                                                     double* __restrict__ xl, int64_t n_macro) {
+    using D = Dims<P>;
+    constexpr int BS = 5 * D::nf, NH = D::NH;
+    const int64_t m = blockIdx.x;
+    if (m >= n_macro) return;
+    for (int i = threadIdx.x; i < NH; i += blockDim.x) xl[m * NH + i] = xg[fid[6 * m + i / BS] * BS + i % BS];
+}
+
+// yl[m] = Ahat_m (P_m x): 64 rows of one macro per workgroup, each wave
+// RB = 8 rows at a time with lanes along the row and DPP wave sums.
+template <int P>
+__global__ void __launch_bounds__(256) k_local_apply(const double* __restrict__ Ahat, const double* __restrict__ xg,
+                                                     const int64_t* __restrict__ fid, double* __restrict__ yl,
+                                                     int64_t n_macro) {
+    using D = Dims<P>;
+    constexpr int BS = 5 * D::nf, NH = D::NH, RT = (NH + 63) / 64, RB = 8;
+    __shared__ double x[NH];
+    int64_t m;
+    int tile;
+    xcd_tile(RT, m, tile);
+    if (m >= n_macro) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < NH; i += blockDim.x) x[i] = xg[fid[6 * m + i / BS] * BS + i % BS];
+    __syncthreads();
+    const double* A = Ahat + m * (int64_t)NH * NH;
+    const int rlo = tile * 64, rhi = (rlo + 64) < NH ? (rlo + 64) : NH;
+    for (int r0 = rlo + wave * RB; r0 < rhi; r0 += nw * RB) {
+        double s[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = 0.0;
+        for (int c = lane; c < NH; c += 64) {
+            const double xc = x[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < rhi) s[i] += A[(int64_t)(r0 + i) * NH + c] * xc;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+        if (lane < RB && r0 + lane < rhi) {
+            double si = s[0];
+#pragma unroll
+            for (int i = 1; i < RB; ++i)
+                if (lane == i) si = s[i];
+            yl[m * NH + r0 + lane] = si;
+        }
+    }
+}
+
+// Inverse of every diagonal face block of K:
+//   D_g = Ahat_m1[f1, f1] + Ahat_m2[f2, f2]   (BS x BS),
+// plus Ahat_m[f1, f2] + Ahat_m[f2, f1] when both sides belong to one macro m,
+// in place in LDS by Gauss-Jordan elimination with row pivoting; the row
+// interchanges become column interchanges of the inverse, undone at the end.
+template <int P>
+struct BlockInvLds {
+    static constexpr int BS = 5 * Dims<P>::nf;
+    double a[BS][BS + 1];
+    double colk[BS];
+    int piv[BS];
+    double redv[4];
+    int redi[4];
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict__ Ahat,
+                                                        const int64_t* __restrict__ side, double* __restrict__ Dinv,
+                                                        int64_t n_faces) {
+    using D = Dims<P>;
+    constexpr int BS = 5 * D::nf, NH = D::NH;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    BlockInvLds<P>& L = *reinterpret_cast<BlockInvLds<P>*>(smem_raw);
+    const int64_t g = blockIdx.x;
+    if (g >= n_faces) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m1 = side[4 * g], f1 = side[4 * g + 1], m2 = side[4 * g + 2], f2 = side[4 * g + 3];
+    const double* A1 = Ahat + m1 * (int64_t)NH * NH + (f1 * BS) * (int64_t)NH + f1 * BS;
+    const double* A2 = Ahat + m2 * (int64_t)NH * NH + (f2 * BS) * (int64_t)NH + f2 * BS;
+    // both sides on one macro (a periodic box one macro wide): K's block also
+    // holds that macro's couplings between the two faces
+    const bool same = m1 == m2;
+    const double* A12 = Ahat + m1 * (int64_t)NH * NH + (f1 * BS) * (int64_t)NH + f2 * BS;
+    const double* A21 = Ahat + m1 * (int64_t)NH * NH + (f2 * BS) * (int64_t)NH + f1 * BS;
+    for (int e = tid; e < BS * BS; e += blockDim.x) {
+        const int i = e / BS, j = e % BS;
+        double d = A1[(int64_t)i * NH + j] + A2[(int64_t)i * NH + j];
+        if (same) d += A12[(int64_t)i * NH + j] + A21[(int64_t)i * NH + j];
+        L.a[i][j] = d;
+    }
+    __syncthreads();
+    for (int k = 0; k < BS; ++k) {
+        // pivot: largest |a[i][k]|, i >= k (ties to the lower row)
+        double best = -1.0;
+        int bi = BS;
+        for (int i = k + tid; i < BS; i += blockDim.x) {
+            const double v = fabs(L.a[i][k]);
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        const double wm = wave_max_f64(best);
+        const unsigned long long bal = __ballot(best == wm && bi < BS);
+        const int ol = bal ? (__ffsll((long long)bal) - 1) : 0;
+        const int wrow = __builtin_amdgcn_readlane(bi, ol);
+        if (lane == 0) {
+            L.redv[wave] = wm;
+            L.redi[wave] = bal ? wrow : BS;
+        }
+        __syncthreads();
+        int p = L.redi[0];
+        double b = L.redv[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            if (L.redv[w] > b || (L.redv[w] == b && L.redi[w] < p)) {
+                b = L.redv[w];
+                p = L.redi[w];
+            }
+        if (p >= BS) p = k;
+        if (tid == 0) L.piv[k] = p;
+        if (p != k)
+            for (int j = tid; j < BS; j += blockDim.x) {
+                const double t = L.a[k][j];
+                L.a[k][j] = L.a[p][j];
+                L.a[p][j] = t;
+            }
+        __syncthreads();
+        const double inv = 1.0 / L.a[k][k];
+        for (int i = tid; i < BS; i += blockDim.x) L.colk[i] = L.a[i][k];
+        __syncthreads();
+        // row k scaled, a[k][k] <- 1 / pivot
+        for (int j = tid; j < BS; j += blockDim.x) L.a[k][j] = (j == k) ? inv : L.a[k][j] * inv;
+        __syncthreads();
+        // every other row: a[i][j] -= a[i][k] a[k][j], with a[i][k] <- -a[i][k] / pivot
+        for (int e = tid; e < BS * BS; e += blockDim.x) {
+            const int i = e / BS, j = e % BS;
+            if (i == k) continue;
+            const double f = L.colk[i];
+            if (j == k) L.a[i][j] = -f * inv;
+            else L.a[i][j] -= f * L.a[k][j];
+        }
+        __syncthreads();
+    }
+    // row interchanges of the elimination = column interchanges of the inverse, in reverse
+    for (int k = BS - 1; k >= 0; --k) {
+        const int p = L.piv[k];
+        if (p != k)
+            for (int i = tid; i < BS; i += blockDim.x) {
+                const double t = L.a[i][k];
+                L.a[i][k] = L.a[i][p];
+                L.a[i][p] = t;
+            }
+        __syncthreads();
+    }
+    double* out = Dinv + g * (int64_t)BS * BS;
+    for (int e = tid; e < BS * BS; e += blockDim.x) out[e] = L.a[e / BS][e % BS];
+}
+
+// z[g] = Dinv_g r[g]
+template <int P>
+__global__ void __launch_bounds__(256) k_face_block_apply(const double* __restrict__ Dinv, const double* __restrict__ r,
+                                                          double* __restrict__ z, int64_t n_faces) {
+    using D = Dims<P>;
+    constexpr int BS = 5 * D::nf, RB = 8;
+    __shared__ double x[BS];
+    const int64_t g = blockIdx.x;
+    if (g >= n_faces) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < BS; i += blockDim.x) x[i] = r[g * BS + i];
+    __syncthreads();
+    const double* A = Dinv + g * (int64_t)BS * BS;
+    for (int r0 = wave * RB; r0 < BS; r0 += nw * RB) {
+        double s[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = 0.0;
+        for (int c = lane; c < BS; c += 64) {
+            const double xc = x[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < BS) s[i] += A[(int64_t)(r0 + i) * BS + c] * xc;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+        if (lane < RB && r0 + lane < BS) {
+            double si = s[0];
+#pragma unroll
+            for (int i = 1; i < RB; ++i)
+                if (lane == i) si = s[i];
+            z[g * BS + r0 + lane] = si;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels of GMRES (n doubles per vector, nv <= 64 basis vectors).
+
+// partial[i][b] = sum over block b's elements of V[i] * w
+__global__ void __launch_bounds__(256) k_dots(const double* __restrict__ V, int64_t n, int nv,
+                                              const double* __restrict__ w, double* __restrict__ partial) {
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int i = 0; i < nv; ++i) {
+        const double* v = V + (int64_t)i * n;
+        double s = 0.0;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) s += v[e] * w[e];
+        s = wave_sum_f64(s);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[(int64_t)i * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        __syncthreads();
+    }
+}
+
+// w += sum_i c[i] V[i]
+__global__ void __launch_bounds__(256) k_combine(const double* __restrict__ V, int64_t n, int nv,
+                                                 const double* __restrict__ c, double* __restrict__ w) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        double s = w[e];
+        for (int i = 0; i < nv; ++i) s += c[i] * V[(int64_t)i * n + e];
+        w[e] = s;
+    }
+}
+
+// y = a x + b y
+__global__ void __launch_bounds__(256) k_axpby(int64_t n, double a, const double* __restrict__ x, double b,
+                                               double* __restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
+        y[e] = a * x[e] + (b == 0.0 ? 0.0 : b * y[e]);
+}
+
+}  // namespace mehdg

@@ -4,6 +4,8 @@
 // every kernel template is instantiated here for p = 1..3.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -13,6 +15,7 @@
 #include "../../include/mehdg.h"
 #include "common.hpp"
 #include "k_recover.hpp"
+#include "k_trace.hpp"
 #include "tables.hpp"
 
 using namespace mehdg;
@@ -42,6 +45,19 @@ struct mehdg_ctx {
     double prof_ms[MEHDG_NPROF] = {};
     int64_t prof_calls[MEHDG_NPROF] = {};
     int stage = 0;                  // 0 nothing, 1 blocks assembled, 2 condensed
+    // global trace system (mehdg_trace_*)
+    int64_t n_faces = 0;
+    int64_t* d_fid = nullptr;       // [n_macro][6] global face of each local face
+    int64_t* d_side = nullptr;      // [n_faces][4] m1, f1, m2, f2
+    double* d_yl = nullptr;         // [n_macro][N_VH] per-macro products
+    double* d_Dinv = nullptr;       // [n_faces][5nf][5nf] inverses of the diagonal face blocks
+    double* d_V = nullptr;          // GMRES basis [restart + 1][N]
+    double* d_w = nullptr;          // [N]
+    double* d_z = nullptr;          // [N]
+    double* d_part = nullptr;       // partial dot products [restart + 1][kDotBlocks]
+    double* d_coef = nullptr;       // [restart + 1]
+    int gm_restart = 0;
+    std::vector<double> h_part, h_coef;
 };
 
 namespace {
@@ -360,6 +376,201 @@ int64_t bordered_ld(int p) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Global trace system
+namespace {
+
+constexpr int kDotBlocks = 256;
+constexpr int kMaxRestart = 60;
+
+int64_t face_block(int p) { return 5 * (int64_t)(2 * p + 1) * (2 * p + 1); }
+
+unsigned vec_grid(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 2048 ? (b > 0 ? b : 1) : 2048);
+}
+
+template <int P>
+mehdg_err trace_launch_apply(mehdg_ctx* c, const double* Ahat, const double* x, double* y, hipStream_t st) {
+    using D = Dims<P>;
+    constexpr int RT = (D::NH + 63) / 64;
+    hipLaunchKernelGGL(k_local_apply<P>, dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st, Ahat, x, c->d_fid, c->d_yl,
+                       (int64_t)c->n_macro);
+    hipLaunchKernelGGL(k_face_sum<P>, dim3((unsigned)c->n_faces), dim3(128), 0, st, c->d_yl, c->d_side, y,
+                       c->n_faces);
+    return hip_ok(hipGetLastError());
+}
+
+template <int P>
+mehdg_err trace_launch_precond_setup(mehdg_ctx* c, const double* Ahat, hipStream_t st) {
+    const size_t lds = sizeof(BlockInvLds<P>);
+    if (lds > 160 * 1024) return MEHDG_EINVAL;
+    if (!allow_lds(&k_face_block_inv<P>, lds)) return MEHDG_EHIP;
+    hipLaunchKernelGGL(k_face_block_inv<P>, dim3((unsigned)c->n_faces), dim3(256), lds, st, Ahat, c->d_side,
+                       c->d_Dinv, c->n_faces);
+    return hip_ok(hipGetLastError());
+}
+
+template <int P>
+mehdg_err trace_launch_precond_apply(mehdg_ctx* c, const double* r, double* z, hipStream_t st) {
+    hipLaunchKernelGGL(k_face_block_apply<P>, dim3((unsigned)c->n_faces), dim3(256), 0, st, c->d_Dinv, r, z,
+                       c->n_faces);
+    return hip_ok(hipGetLastError());
+}
+
+mehdg_err trace_ready(mehdg_ctx* c) {
+    if (!c) return MEHDG_EINVAL;
+    if (!c->d_side) return MEHDG_ESTATE;
+    return MEHDG_OK;
+}
+
+mehdg_err ensure_trace_work(mehdg_ctx* c, bool precond) {
+    mehdg_err e;
+    const int64_t BS = face_block(c->p), NH = 6 * BS;
+    if (!c->d_yl && (e = dev_alloc(c, &c->d_yl, c->n_macro * NH)) != MEHDG_OK) return e;
+    if (precond && !c->d_Dinv && (e = dev_alloc(c, &c->d_Dinv, c->n_faces * BS * BS)) != MEHDG_OK) return e;
+    return MEHDG_OK;
+}
+
+// sums of the partial dot products of nv vectors, in block order
+mehdg_err host_dots(mehdg_ctx* c, const double* V, int64_t n, int nv, const double* w, double* out,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, st, V, n, nv, w, c->d_part);
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    if (hipMemcpyAsync(c->h_part.data(), c->d_part, sizeof(double) * nv * kDotBlocks, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MEHDG_EHIP;
+    for (int i = 0; i < nv; ++i) {
+        double s = 0.0;
+        for (int b = 0; b < kDotBlocks; ++b) s += c->h_part[(size_t)i * kDotBlocks + b];
+        out[i] = s;
+    }
+    return MEHDG_OK;
+}
+
+// w += sum_i coef[i] V[i]
+mehdg_err host_combine(mehdg_ctx* c, const double* V, int64_t n, int nv, const double* coef, double* w,
+                       hipStream_t st) {
+    for (int i = 0; i < nv; ++i) c->h_coef[i] = coef[i];
+    if (hipMemcpyAsync(c->d_coef, c->h_coef.data(), sizeof(double) * nv, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MEHDG_EHIP;
+    hipLaunchKernelGGL(k_combine, dim3(vec_grid(n)), dim3(256), 0, st, V, n, nv, c->d_coef, w);
+    return hip_ok(hipGetLastError());
+}
+
+mehdg_err host_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3(vec_grid(n)), dim3(256), 0, st, n, a, x, b, y);
+    return hip_ok(hipGetLastError());
+}
+
+// Right-preconditioned restarted GMRES with classical Gram-Schmidt applied
+// twice; the (restart+1) x restart Hessenberg matrix and its Givens
+// rotations live on the host.
+template <int P>
+mehdg_err trace_gmres(mehdg_ctx* c, const double* Ahat, const double* F, double* x, double rtol, int maxit,
+                      int restart, int32_t* iters, double* relres, hipStream_t st) {
+    const int64_t N = c->n_faces * face_block(P);
+    mehdg_err e;
+    if (restart > c->gm_restart) {
+        (void)hipFree(c->d_V);
+        (void)hipFree(c->d_part);
+        (void)hipFree(c->d_coef);
+        c->d_V = c->d_part = c->d_coef = nullptr;
+        if ((e = dev_alloc(c, &c->d_V, (restart + 1) * N)) != MEHDG_OK ||
+            (e = dev_alloc(c, &c->d_part, (int64_t)(restart + 1) * kDotBlocks)) != MEHDG_OK ||
+            (e = dev_alloc(c, &c->d_coef, (int64_t)restart + 1)) != MEHDG_OK)
+            return e;
+        c->gm_restart = restart;
+    }
+    if (!c->d_w && (e = dev_alloc(c, &c->d_w, N)) != MEHDG_OK) return e;
+    if (!c->d_z && (e = dev_alloc(c, &c->d_z, N)) != MEHDG_OK) return e;
+    c->h_part.assign((size_t)(restart + 1) * kDotBlocks, 0.0);
+    c->h_coef.assign((size_t)restart + 1, 0.0);
+    if ((e = trace_launch_precond_setup<P>(c, Ahat, st)) != MEHDG_OK) return e;
+    double* V = c->d_V;
+    double* w = c->d_w;
+    double* z = c->d_z;
+    double bn2;
+    if ((e = host_dots(c, F, N, 1, F, &bn2, st)) != MEHDG_OK) return e;
+    const double bnorm = std::sqrt(bn2);
+    int it = 0;
+    double res = 0.0;
+    if (!(bnorm > 0.0)) {
+        if ((e = host_axpby(N, 0.0, F, 0.0, x, st)) != MEHDG_OK) return e;
+        *iters = 0;
+        *relres = 0.0;
+        return MEHDG_OK;
+    }
+    std::vector<double> H((size_t)(restart + 1) * restart, 0.0), cs(restart), sn(restart), g(restart + 1),
+        y(restart), h(restart + 1), h2(restart + 1);
+    auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * restart + j]; };
+    while (true) {
+        // r = F - K x
+        if ((e = trace_launch_apply<P>(c, Ahat, x, w, st)) != MEHDG_OK) return e;
+        if ((e = host_axpby(N, 1.0, F, -1.0, w, st)) != MEHDG_OK) return e;
+        double b2;
+        if ((e = host_dots(c, w, N, 1, w, &b2, st)) != MEHDG_OK) return e;
+        const double beta = std::sqrt(b2);
+        res = beta;
+        if (beta <= rtol * bnorm || it >= maxit || !std::isfinite(beta)) break;
+        if ((e = host_axpby(N, 1.0 / beta, w, 0.0, V, st)) != MEHDG_OK) return e;
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        while (j < restart && it < maxit) {
+            double* vj = V + (int64_t)j * N;
+            if ((e = trace_launch_precond_apply<P>(c, vj, z, st)) != MEHDG_OK) return e;
+            if ((e = trace_launch_apply<P>(c, Ahat, z, w, st)) != MEHDG_OK) return e;
+            for (int pass = 0; pass < 2; ++pass) {
+                double* hh = pass ? h2.data() : h.data();
+                if ((e = host_dots(c, V, N, j + 1, w, hh, st)) != MEHDG_OK) return e;
+                for (int i = 0; i <= j; ++i) hh[i] = -hh[i];
+                if ((e = host_combine(c, V, N, j + 1, hh, w, st)) != MEHDG_OK) return e;
+            }
+            for (int i = 0; i <= j; ++i) Hij(i, j) = -(h[i] + h2[i]);
+            double hn2;
+            if ((e = host_dots(c, w, N, 1, w, &hn2, st)) != MEHDG_OK) return e;
+            const double hn = std::sqrt(hn2);
+            Hij(j + 1, j) = hn;
+            if (hn > 0.0 && (e = host_axpby(N, 1.0 / hn, w, 0.0, V + (int64_t)(j + 1) * N, st)) != MEHDG_OK)
+                return e;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+                Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+                Hij(i, j) = t;
+            }
+            const double rr = std::hypot(Hij(j, j), Hij(j + 1, j));
+            cs[j] = rr > 0.0 ? Hij(j, j) / rr : 1.0;
+            sn[j] = rr > 0.0 ? Hij(j + 1, j) / rr : 0.0;
+            Hij(j, j) = rr;
+            Hij(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            res = std::fabs(g[j + 1]);
+            ++it;
+            ++j;
+            if (res <= rtol * bnorm || hn == 0.0) break;
+        }
+        // x += M^-1 (V y),  H y = g
+        for (int i = j - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < j; ++k) s -= Hij(i, k) * y[k];
+            y[i] = s / Hij(i, i);
+        }
+        if ((e = host_axpby(N, 0.0, F, 0.0, w, st)) != MEHDG_OK) return e;
+        if ((e = host_combine(c, V, N, j, y.data(), w, st)) != MEHDG_OK) return e;
+        if ((e = trace_launch_precond_apply<P>(c, w, z, st)) != MEHDG_OK) return e;
+        if ((e = host_axpby(N, 1.0, z, 1.0, x, st)) != MEHDG_OK) return e;
+    }
+    *iters = it;
+    *relres = res / bnorm;
+    return MEHDG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]) {
@@ -395,6 +606,15 @@ mehdg_err mehdg_destroy(mehdg_ctx* c) {
     (void)hipFree(c->d_tri);
     (void)hipFree(c->d_perm);
     (void)hipFree(c->d_B);
+    (void)hipFree(c->d_fid);
+    (void)hipFree(c->d_side);
+    (void)hipFree(c->d_yl);
+    (void)hipFree(c->d_Dinv);
+    (void)hipFree(c->d_V);
+    (void)hipFree(c->d_w);
+    (void)hipFree(c->d_z);
+    (void)hipFree(c->d_part);
+    (void)hipFree(c->d_coef);
     delete c;
     return MEHDG_OK;
 }
@@ -539,6 +759,115 @@ mehdg_err mehdg_status(mehdg_ctx* c, int32_t* status, mehdg_stream stream) {
 }
 
 int64_t mehdg_workspace_bytes(const mehdg_ctx* c) { return c ? c->bytes : 0; }
+
+
+mehdg_err mehdg_trace_setup(mehdg_ctx* c, const int64_t* face_ids, int64_t n_faces) {
+    if (!c || !face_ids || n_faces <= 0) return MEHDG_EINVAL;
+    const int64_t M = c->n_macro;
+    std::vector<int64_t> side((size_t)n_faces * 4, -1);
+    std::vector<int> cnt((size_t)n_faces, 0);
+    for (int64_t m = 0; m < M; ++m)
+        for (int f = 0; f < 6; ++f) {
+            const int64_t g = face_ids[m * 6 + f];
+            if (g < 0 || g >= n_faces || cnt[g] >= 2) return MEHDG_EINVAL;
+            side[g * 4 + 2 * cnt[g]] = m;
+            side[g * 4 + 2 * cnt[g] + 1] = f;
+            ++cnt[g];
+        }
+    for (int64_t g = 0; g < n_faces; ++g)
+        if (cnt[g] != 2) return MEHDG_EINVAL;
+    (void)hipFree(c->d_fid);
+    (void)hipFree(c->d_side);
+    (void)hipFree(c->d_Dinv);
+    (void)hipFree(c->d_w);
+    (void)hipFree(c->d_z);
+    (void)hipFree(c->d_V);
+    c->d_fid = c->d_side = nullptr;
+    c->d_Dinv = c->d_w = c->d_z = c->d_V = nullptr;
+    c->gm_restart = 0;
+    c->n_faces = n_faces;
+    mehdg_err e;
+    if ((e = dev_alloc(c, &c->d_fid, M * 6)) != MEHDG_OK || (e = dev_alloc(c, &c->d_side, n_faces * 4)) != MEHDG_OK)
+        return e;
+    if (hipMemcpy(c->d_fid, face_ids, sizeof(int64_t) * M * 6, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->d_side, side.data(), sizeof(int64_t) * n_faces * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return MEHDG_EHIP;
+    return ensure_trace_work(c, false);
+}
+
+mehdg_err mehdg_trace_rhs(mehdg_ctx* c, const double* bhat, double* F, mehdg_stream stream) {
+    mehdg_err e = trace_ready(c);
+    if (e != MEHDG_OK) return e;
+    if (!bhat || !F) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    switch (c->p) {
+        case 1: hipLaunchKernelGGL(k_face_sum<1>, dim3((unsigned)c->n_faces), dim3(128), 0, st, bhat, c->d_side, F, c->n_faces); break;
+        case 2: hipLaunchKernelGGL(k_face_sum<2>, dim3((unsigned)c->n_faces), dim3(128), 0, st, bhat, c->d_side, F, c->n_faces); break;
+        case 3: hipLaunchKernelGGL(k_face_sum<3>, dim3((unsigned)c->n_faces), dim3(128), 0, st, bhat, c->d_side, F, c->n_faces); break;
+        default: return MEHDG_EINVAL;
+    }
+    return hip_ok(hipGetLastError());
+}
+
+mehdg_err mehdg_trace_gather(mehdg_ctx* c, const double* xg, double* xl, mehdg_stream stream) {
+    mehdg_err e = trace_ready(c);
+    if (e != MEHDG_OK) return e;
+    if (!xg || !xl) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)c->n_macro);
+    switch (c->p) {
+        case 1: hipLaunchKernelGGL(k_face_gather<1>, grid, dim3(256), 0, st, xg, c->d_fid, xl, (int64_t)c->n_macro); break;
+        case 2: hipLaunchKernelGGL(k_face_gather<2>, grid, dim3(256), 0, st, xg, c->d_fid, xl, (int64_t)c->n_macro); break;
+        case 3: hipLaunchKernelGGL(k_face_gather<3>, grid, dim3(256), 0, st, xg, c->d_fid, xl, (int64_t)c->n_macro); break;
+        default: return MEHDG_EINVAL;
+    }
+    return hip_ok(hipGetLastError());
+}
+
+mehdg_err mehdg_trace_apply(mehdg_ctx* c, const double* Ahat, const double* x, double* y, mehdg_stream stream) {
+    mehdg_err e = trace_ready(c);
+    if (e != MEHDG_OK) return e;
+    if (!Ahat || !x || !y) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    switch (c->p) {
+        case 1: return trace_launch_apply<1>(c, Ahat, x, y, st);
+        case 2: return trace_launch_apply<2>(c, Ahat, x, y, st);
+        case 3: return trace_launch_apply<3>(c, Ahat, x, y, st);
+        default: return MEHDG_EINVAL;
+    }
+}
+
+mehdg_err mehdg_trace_precond_setup(mehdg_ctx* c, const double* Ahat, mehdg_stream stream) {
+    mehdg_err e = trace_ready(c);
+    if (e != MEHDG_OK) return e;
+    if (!Ahat || c->p > 2) return MEHDG_EINVAL;
+    if ((e = ensure_trace_work(c, true)) != MEHDG_OK) return e;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return c->p == 1 ? trace_launch_precond_setup<1>(c, Ahat, st) : trace_launch_precond_setup<2>(c, Ahat, st);
+}
+
+mehdg_err mehdg_trace_precond_apply(mehdg_ctx* c, const double* r, double* z, mehdg_stream stream) {
+    mehdg_err e = trace_ready(c);
+    if (e != MEHDG_OK) return e;
+    if (!r || !z || c->p > 2) return MEHDG_EINVAL;
+    if (!c->d_Dinv) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return c->p == 1 ? trace_launch_precond_apply<1>(c, r, z, st) : trace_launch_precond_apply<2>(c, r, z, st);
+}
+
+mehdg_err mehdg_trace_solve(mehdg_ctx* c, const double* Ahat, const double* F, double* x, double rtol,
+                            int32_t maxit, int32_t restart, int32_t* iters, double* relres, mehdg_stream stream) {
+    mehdg_err e = trace_ready(c);
+    if (e != MEHDG_OK) return e;
+    if (!Ahat || !F || !x || !iters || !relres || !(rtol > 0.0) || maxit < 0 || restart < 1 ||
+        restart > kMaxRestart || c->p > 2)
+        return MEHDG_EINVAL;
+    if ((e = ensure_trace_work(c, true)) != MEHDG_OK) return e;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return c->p == 1 ? trace_gmres<1>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st)
+                     : trace_gmres<2>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
+}
+
 
 mehdg_err mehdg_profile_enable(mehdg_ctx* c, int32_t enable) {
     if (!c) return MEHDG_EINVAL;

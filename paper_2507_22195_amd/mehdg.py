@@ -73,9 +73,19 @@ def load(path: str = LIB_PATH):
     lib.mehdg_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.mehdg_workspace_bytes.argtypes = [vp]
     lib.mehdg_workspace_bytes.restype = i64
+    lib.mehdg_trace_setup.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i64]
+    lib.mehdg_trace_rhs.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_trace_apply.argtypes = [vp, vp, vp, vp, vp]
+    lib.mehdg_trace_gather.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_trace_precond_setup.argtypes = [vp, vp, vp]
+    lib.mehdg_trace_precond_apply.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_trace_solve.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_double), vp]
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
                  "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_profile_enable",
-                 "mehdg_profile_read"):
+                 "mehdg_profile_read", "mehdg_trace_setup", "mehdg_trace_rhs", "mehdg_trace_apply",
+                 "mehdg_trace_gather", "mehdg_trace_precond_setup", "mehdg_trace_precond_apply",
+                 "mehdg_trace_solve"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -173,6 +183,65 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return int(load().mehdg_workspace_bytes(self._handle))
+
+    # global trace system ------------------------------------------------
+    def trace_setup(self, face_ids, n_faces: int):
+        """face_ids [n_macro][6] (int64, host): global face of every local face."""
+        ids = np.ascontiguousarray(np.asarray(face_ids, dtype=np.int64))
+        if ids.shape != (self.n_macro, 6):
+            raise ValueError(f"face_ids has shape {ids.shape}, expected {(self.n_macro, 6)}")
+        rc = load().mehdg_trace_setup(self._handle, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      int(n_faces))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_setup")
+        self.n_faces = int(n_faces)
+
+    def trace_shape(self):
+        return (self.n_faces, 5, self.sz["nf"])
+
+    def trace_rhs(self, bhat, F, stream=None):
+        S = self.shapes()
+        rc = load().mehdg_trace_rhs(self._handle, _ptr(bhat, S["bhat"], "bhat"),
+                                    _ptr(F, self.trace_shape(), "F"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_rhs")
+
+    def trace_apply(self, Ahat, x, y, stream=None):
+        S, T = self.shapes(), self.trace_shape()
+        rc = load().mehdg_trace_apply(self._handle, _ptr(Ahat, S["Ahat"], "Ahat"), _ptr(x, T, "x"),
+                                      _ptr(y, T, "y"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_apply")
+
+    def trace_gather(self, xg, xl, stream=None):
+        rc = load().mehdg_trace_gather(self._handle, _ptr(xg, self.trace_shape(), "xg"),
+                                       _ptr(xl, self.shapes()["vhat"], "xl"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_gather")
+
+    def trace_precond_setup(self, Ahat, stream=None):
+        rc = load().mehdg_trace_precond_setup(self._handle, _ptr(Ahat, self.shapes()["Ahat"], "Ahat"),
+                                              _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_precond_setup")
+
+    def trace_precond_apply(self, r, z, stream=None):
+        T = self.trace_shape()
+        rc = load().mehdg_trace_precond_apply(self._handle, _ptr(r, T, "r"), _ptr(z, T, "z"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_precond_apply")
+
+    def trace_solve(self, Ahat, F, x, rtol=1e-10, maxit=500, restart=30, stream=None):
+        """GMRES on K x = F (x: initial guess in, solution out); returns (iterations, relative residual)."""
+        S, T = self.shapes(), self.trace_shape()
+        it = ctypes.c_int32()
+        rr = ctypes.c_double()
+        rc = load().mehdg_trace_solve(self._handle, _ptr(Ahat, S["Ahat"], "Ahat"), _ptr(F, T, "F"),
+                                      _ptr(x, T, "x"), float(rtol), int(maxit), int(restart),
+                                      ctypes.byref(it), ctypes.byref(rr), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_solve")
+        return int(it.value), float(rr.value)
 
     # calls --------------------------------------------------------------
     def assemble(self, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, want_blocks=False, stream=None):

@@ -1,0 +1,90 @@
+"""GPU global trace system (Sec. 6.2, Algorithm 1) against the oracle.
+
+On small periodic meshes: F = sum_m P_m^T bhat_m and K x (matrix-free from
+the per-macro Ahat) against the oracle's assembled sparse K and F; the
+block-Jacobi inverse against the oracle's diagonal face blocks; the GMRES
+solution against a sparse direct solve of the oracle's system; and the
+Newton update (dV, dQ) recovered from it.  Tolerances: K x, F at 1e-11
+(products and sums of quantities at 1e-12); the solve and what follows at
+1e-7: the 1e-12 parity of Ahat and bhat and the 1e-12 Krylov tolerance are
+amplified by cond(K), about 5e2 (p=1 case) and 9e3 (p=2 case) here.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import global_solve, local
+from paper_2507_22195_amd import workloads as W
+from tests.gpu_util import banner, dev, empty, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    return [("tgv viscous ES p1", W.tgv_workload(shape=(2, 2, 2), p=1)),
+            ("vortex ES p2", W.vortex_workload(shape=(2, 2, 1), p=2, flux="ES", hi=(10.0, 10.0, 5.0)))]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_trace_system_and_newton_update(case):
+    from paper_2507_22195_amd import mehdg
+    name, w = _cases()[case]
+    banner(f"trace: {name} M={w.n_macro}")
+    ids, nfaces = global_solve.periodic_face_ids(w.mesh.shape, w.mesh.ijk)
+    nf = (2 * w.p + 1) ** 2
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+    ctx.assemble(dev(w.v), dev(w.vhat), None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=True)
+    Ahat, bhat = empty(S["Ahat"]), empty(S["bhat"])
+    ctx.condense(Ahat, bhat)
+    ctx.trace_setup(ids, nfaces)
+    T = ctx.trace_shape()
+
+    ref = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params)
+    K, F = global_solve.trace_system(ref, ids, nfaces, nf)
+
+    Fg = empty(T)
+    ctx.trace_rhs(bhat, Fg)
+    assert rel_err(host(Fg).reshape(1, -1), F.reshape(1, -1)) < 1e-11
+
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(T)
+    y = empty(T)
+    ctx.trace_apply(Ahat, dev(x), y)
+    assert rel_err(host(y).reshape(1, -1), (K @ x.reshape(-1)).reshape(1, -1)) < 1e-11
+
+    # block Jacobi: D_g z_g = r_g with the oracle's diagonal face blocks
+    ctx.trace_precond_setup(Ahat)
+    r = rng.standard_normal(T)
+    z = empty(T)
+    ctx.trace_precond_apply(dev(r), z)
+    zh = host(z).reshape(nfaces, -1)
+    BS = 5 * nf
+    Kd = K.toarray() if K.shape[0] <= 6000 else None
+    worst = 0.0
+    for g in range(nfaces):
+        Dg = Kd[g * BS:(g + 1) * BS, g * BS:(g + 1) * BS]
+        rg = r.reshape(nfaces, -1)[g]
+        worst = max(worst, np.linalg.norm(Dg @ zh[g] - rg) / np.linalg.norm(rg))
+    assert worst < 1e-9, worst
+
+    # GMRES against a sparse direct solve; then the Newton update
+    xs = empty(T)
+    xs.zero_()
+    its, rr = ctx.trace_solve(Ahat, Fg, xs, rtol=1e-12, maxit=400, restart=40)
+    banner(f"trace: GMRES {its} iterations, relative residual {rr:.2e}")
+    assert rr < 1e-11
+    xd = spla.spsolve(K, F)
+    assert rel_err(host(xs).reshape(1, -1), xd.reshape(1, -1)) < 1e-7
+    xl = empty(S["vhat"])
+    ctx.trace_gather(xs, xl)
+    assert np.array_equal(host(xl), host(xs)[ids])
+    dv, dq = empty(S["dv"]), empty(S["dq"])
+    ctx.recover(R_q, xl, dv, dq)
+    rdv, rdq = local.recover(ref, xd[global_solve._dof_map(ids, nf)].reshape(w.n_macro, 6, 5, nf))
+    assert rel_err(host(dv), rdv) < 1e-7
+    assert rel_err(host(dq), rdq) < 1e-7
+    rc, st = ctx.status()
+    assert rc == 0
+    ctx.close()
