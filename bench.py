@@ -147,6 +147,39 @@ def cpu_baseline(w, target_s=15.0):
                        f"{t:.1f} s")
 
 
+def trace_solve(ctx, w, Ahat, bhat, rtol=1e-8, restart=30, maxit=300):
+    """Global trace system of the step's last condensation (not part of the
+    metric): F = sum P^T bhat, then GMRES(restart) with block Jacobi to rtol;
+    also the bandwidth of the matrix-free K x (reads every Ahat once)."""
+    import torch
+    from paper_2507_22195_amd import workloads as W
+    gid = W.global_face_ids(w.mesh)
+    nfaces = int(gid.max()) + 1
+    ctx.trace_setup(gid, nfaces)
+    T = ctx.trace_shape()
+    F = torch.empty(T, dtype=torch.float64, device="cuda")
+    x = torch.zeros(T, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    ctx.trace_rhs(bhat, F)
+    ctx.trace_apply(Ahat, F, y)                       # warm
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.trace_apply(Ahat, F, y)
+    torch.cuda.synchronize()
+    apply_s = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    its, rr = ctx.trace_solve(Ahat, F, x, rtol=rtol, maxit=maxit, restart=restart)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    NH = ctx.sz["N_VH"]
+    return {"unknowns": int(np.prod(T)), "rtol": rtol, "restart": restart, "iterations": its,
+            "relres": rr, "solve_ms": round(solve_s * 1e3, 2),
+            "apply_ms": round(apply_s * 1e3, 3),
+            "apply_GBps": round(8.0 * NH * NH * w.n_macro / apply_s / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +187,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shape", type=int, nargs=3, default=None, help="macro grid (default 16 16 16)")
+    ap.add_argument("--no-trace", action="store_true", help="skip the global trace solve measurement")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="before warm-up, copy a MIB-sized buffer three times (untimed) so that a counter "
                          "run sees a plain copy kernel of known size")
@@ -279,6 +313,8 @@ def main():
                      "frac_fp64_peak": round(cond_flops / (cond_ms / 1e3) / 1e12 / FP64_MFMA_PEAK_TFS, 4)},
         "kernels": kernels,
     }
+    if not args.no_trace:
+        out["trace_solve"] = trace_solve(ctx, w, Ahat, bhat)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
