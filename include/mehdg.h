@@ -215,6 +215,23 @@ mehdg_err mehdg_trace_solve(mehdg_ctx* ctx, const double* Ahat, const double* F,
                             int32_t maxit, int32_t restart, int32_t* iters, double* relres,
                             mehdg_stream stream);
 
+/* Constant source of a DIRK stage (Sec. 5.3): adds s [n_macro][5][n] to the
+ * interior residual R_v and subtracts it from the right-hand side r_V of the
+ * bordered matrix.  With v_old = v^n, stage i of a DIRK method with a_ii = a
+ * for all i (alpha_t = 1/(a dt)) has the residual of mehdg_assemble plus
+ * s_i = alpha_t dt sum_{j<i} a_ij R_sp(V_j), R_sp the residual without time
+ * term.  Call between mehdg_assemble(want_blocks = 1) and mehdg_condense;
+ * else MEHDG_ESTATE. */
+mehdg_err mehdg_add_source(mehdg_ctx* ctx, const double* s, double* R_v, mehdg_stream stream);
+
+/* y = a x + b y for device vectors of n doubles (b = 0: y is not read). */
+mehdg_err mehdg_axpby(int64_t n, double a, const double* x, double b, double* y, mehdg_stream stream);
+
+/* *out = x . y for device vectors of n doubles (partial sums on the device,
+ * summed on the host in a fixed order).  Synchronises the stream. */
+mehdg_err mehdg_dot(mehdg_ctx* ctx, int64_t n, const double* x, const double* y, double* out,
+                    mehdg_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -264,4 +264,21 @@ __global__ void __launch_bounds__(256) k_axpby(int64_t n, double a, const double
         y[e] = a * x[e] + (b == 0.0 ? 0.0 : b * y[e]);
 }
 
+// Constant source of a DIRK stage: R_v += s and r_V -= s in the bordered
+// matrix (the rows of the interior equations), per macro.
+template <int P>
+__global__ void __launch_bounds__(256) k_add_source(const double* __restrict__ s, double* __restrict__ R_v,
+                                                    double* __restrict__ B, int64_t n_macro) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld;
+    const int64_t m = blockIdx.x;
+    if (m >= n_macro) return;
+    for (int a = threadIdx.x; a < NV; a += blockDim.x) {
+        const double v = s[m * NV + a];
+        R_v[m * NV + a] += v;
+        B[m * BD::per_macro + (int64_t)a * ld + NV + NH] -= v;
+    }
+}
+
 }  // namespace mehdg

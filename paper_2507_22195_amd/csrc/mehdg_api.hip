@@ -895,4 +895,37 @@ mehdg_err mehdg_profile_read(mehdg_ctx* c, double* ms, int64_t* calls, int32_t n
     return MEHDG_OK;
 }
 
+
+mehdg_err mehdg_add_source(mehdg_ctx* c, const double* s, double* R_v, mehdg_stream stream) {
+    if (!c || !s || !R_v) return MEHDG_EINVAL;
+    if (c->stage != 1) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)c->n_macro);
+    switch (c->p) {
+        case 1: hipLaunchKernelGGL(k_add_source<1>, grid, dim3(256), 0, st, s, R_v, c->d_B, (int64_t)c->n_macro); break;
+        case 2: hipLaunchKernelGGL(k_add_source<2>, grid, dim3(256), 0, st, s, R_v, c->d_B, (int64_t)c->n_macro); break;
+        case 3: hipLaunchKernelGGL(k_add_source<3>, grid, dim3(256), 0, st, s, R_v, c->d_B, (int64_t)c->n_macro); break;
+        default: return MEHDG_EINVAL;
+    }
+    return hip_ok(hipGetLastError());
+}
+
+mehdg_err mehdg_axpby(int64_t n, double a, const double* x, double b, double* y, mehdg_stream stream) {
+    if (n < 0 || (n > 0 && (!x || !y))) return MEHDG_EINVAL;
+    if (n == 0) return MEHDG_OK;
+    return host_axpby(n, a, x, b, y, reinterpret_cast<hipStream_t>(stream));
+}
+
+mehdg_err mehdg_dot(mehdg_ctx* c, int64_t n, const double* x, const double* y, double* out, mehdg_stream stream) {
+    if (!c || n < 0 || !out || (n > 0 && (!x || !y))) return MEHDG_EINVAL;
+    if (n == 0) {
+        *out = 0.0;
+        return MEHDG_OK;
+    }
+    mehdg_err e;
+    if (!c->d_part && (e = dev_alloc(c, &c->d_part, (int64_t)kDotBlocks)) != MEHDG_OK) return e;
+    if (c->h_part.size() < (size_t)kDotBlocks) c->h_part.assign(kDotBlocks, 0.0);
+    return host_dots(c, x, n, 1, y, out, reinterpret_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

@@ -81,6 +81,11 @@ def load(path: str = LIB_PATH):
     lib.mehdg_trace_precond_apply.argtypes = [vp, vp, vp, vp]
     lib.mehdg_trace_solve.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_double), vp]
+    lib.mehdg_add_source.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
+    lib.mehdg_dot.argtypes = [vp, i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
                  "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_profile_enable",
                  "mehdg_profile_read", "mehdg_trace_setup", "mehdg_trace_rhs", "mehdg_trace_apply",
@@ -89,6 +94,16 @@ def load(path: str = LIB_PATH):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def axpby(a, x, b, y, stream=None):
+    """y = a x + b y (device float64 tensors of one shape)."""
+    if x.shape != y.shape:
+        raise ValueError("x and y differ in shape")
+    rc = load().mehdg_axpby(int(x.numel()), float(a), _ptr(x, tuple(x.shape), "x"), float(b),
+                            _ptr(y, tuple(y.shape), "y"), _stream(stream))
+    if rc:
+        raise MehdgError(rc, "mehdg_axpby")
 
 
 def sizes(p: int) -> dict:
@@ -230,6 +245,23 @@ class Context:
         rc = load().mehdg_trace_precond_apply(self._handle, _ptr(r, T, "r"), _ptr(z, T, "z"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_trace_precond_apply")
+
+    def add_source(self, s, R_v, stream=None):
+        S = self.shapes()
+        rc = load().mehdg_add_source(self._handle, _ptr(s, S["R_v"], "s"), _ptr(R_v, S["R_v"], "R_v"),
+                                     _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_add_source")
+
+    def dot(self, x, y, stream=None):
+        if x.shape != y.shape:
+            raise ValueError("x and y differ in shape")
+        out = ctypes.c_double()
+        rc = load().mehdg_dot(self._handle, int(x.numel()), _ptr(x, tuple(x.shape), "x"),
+                              _ptr(y, tuple(y.shape), "y"), ctypes.byref(out), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_dot")
+        return float(out.value)
 
     def trace_solve(self, Ahat, F, x, rtol=1e-10, maxit=500, restart=30, stream=None):
         """GMRES on K x = F (x: initial guess in, solution out); returns (iterations, relative residual)."""

@@ -49,8 +49,8 @@ CASES = {
 }
 
 
-def run(kind, p, N):
-    """Returns (h, L2 error of rho at the final time, Newton iterations)."""
+def setup(kind, p, N):
+    """Mesh, parameters, initial state (nodal interpolant) and time steps of one case."""
     prim, L, T, dt1 = CASES[kind]
     mesh = W.box_mesh((N, N, 1), (0.0, 0.0, 0.0), (L, L, L / N))
     prm = W.make_params(gamma=GAMMA, flux="ES", dt=1.0, alpha_ps=0.0)
@@ -62,27 +62,35 @@ def run(kind, p, N):
     vh_g = np.zeros((nfaces, 5, vh_loc.shape[-1]))
     vh_g[ids.reshape(-1)] = vh_loc.reshape(-1, 5, vh_loc.shape[-1])
     steps = int(round(T / (dt1 / N)))
-    dt = T / steps
-    its = []
-    for _ in range(steps):
-        v, vh_g, it = global_solve.dirk33_step(p, mesh.h, ids, nfaces, v, vh_g, prm, dt)
-        its += it
-    # L2 error of the density at the volume quadrature points
+    return dict(mesh=mesh, prm=prm, v=v, vh_g=vh_g, ids=ids, nfaces=nfaces, steps=steps, dt=T / steps,
+                prim=prim, T=T)
+
+
+def l2_error(kind, p, mesh, v):
+    """L2 error of the density at the volume Gauss points at the final time."""
+    prim, T = CASES[kind][0], CASES[kind][2]
     geo = local.Geometry(p, mesh.h)
     vg = np.einsum("ga,mka->mkg", geo.t["vol_phi"], v)
     rho_h = physics.conservative_from_entropy([vg[:, k] for k in range(5)], GAMMA)[0]
     # physical volume points: g = g1 + nq (g2 + nq g3), 1-D points on [0, 2] times h
     xq = basis.tables_1d(p)["xq"]
     nq = xq.size
-    G = nq ** 3
-    gidx = np.arange(G)
-    px = xq[gidx % nq]
-    py = xq[(gidx // nq) % nq]
-    pz = xq[gidx // (nq * nq)]
-    xg = mesh.origin[:, :, None] + mesh.h[:, :, None] * np.stack([px, py, pz])[None]   # [M][3][G]
+    gidx = np.arange(nq ** 3)
+    ref = np.stack([xq[gidx % nq], xq[(gidx // nq) % nq], xq[gidx // (nq * nq)]])
+    xg = mesh.origin[:, :, None] + mesh.h[:, :, None] * ref[None]          # [M][3][G]
     rho_ex = prim(xg, T)[0]
-    err = np.sqrt(np.sum(geo.w_vol() * (rho_h - rho_ex) ** 2))
-    return float(mesh.h[0, 0]), float(err), its
+    return float(np.sqrt(np.sum(geo.w_vol() * (rho_h - rho_ex) ** 2)))
+
+
+def run(kind, p, N):
+    """Returns (h, L2 error of rho at the final time, Newton iterations)."""
+    c = setup(kind, p, N)
+    v, vh_g = c["v"], c["vh_g"]
+    its = []
+    for _ in range(c["steps"]):
+        v, vh_g, it = global_solve.dirk33_step(p, c["mesh"].h, c["ids"], c["nfaces"], v, vh_g, c["prm"], c["dt"])
+        its += it
+    return float(c["mesh"].h[0, 0]), l2_error(kind, p, c["mesh"], v), its
 
 
 def study(kind, p, Ns):
