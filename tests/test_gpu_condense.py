@@ -7,6 +7,14 @@ right-hand-side columns r_V, r_hat carry -R_V and are compared with the
 residual's rounding floor (see test_gpu_residual); bhat and dV, which
 inherit it through r_V, get the same floor propagated through the exact
 solve.  LU factors are not compared (pivot orders may differ).
+
+The KEPES switch theta = sqrt|(P - Phat)/(P + Phat)| (eq. KEPES5) has a
+derivative ~ 1/sqrt|P - Phat|: at a face node where P is close to Phat the
+Jacobian entries are ill-conditioned functions of the state, and the
+oracle's own blocks move by ~1e-11 relative under one-ulp input noise at
+p = 3 (ES on the same state: ~1e-15).  Such cases take a block floor measured
+the same way as the r_V floor; the same workload with the ES flux keeps the
+plain 1e-12 bar and pins the degree-3 kernel paths.
 """
 import numpy as np
 import pytest
@@ -49,7 +57,25 @@ def rhs_floor(w, key_scale=10.0, trials=2):
     return key_scale * worst
 
 
-def check(w, sample_blocks=(0,)):
+def block_floor(w, dvhat, trials=2, key_scale=10.0):
+    """Per-macro change (Frobenius norm) of the oracle's S, Y, X, A', Ahat,
+    bhat and of the recovered dV, dQ under one-ulp input noise, times key_scale."""
+    rng = np.random.default_rng(11)
+    base = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params)
+    base["dv"], base["dq"] = local.recover(base, dvhat)
+    keys = ("S", "Y", "X", "Ap", "Ahat", "bhat", "dv", "dq")
+    worst = {k: np.zeros(w.n_macro) for k in keys}
+    for _ in range(trials):
+        pert = lambda x: x * (1 + 2.2e-16 * rng.uniform(-1, 1, x.shape))
+        c = local.condense(w.p, w.mesh.h, pert(w.v), pert(w.vhat), w.v_old, w.params)
+        c["dv"], c["dq"] = local.recover(c, dvhat)
+        for k in keys:
+            d = np.linalg.norm((c[k] - base[k]).reshape(w.n_macro, -1), axis=1)
+            worst[k] = np.maximum(worst[k], d)
+    return {k: key_scale * v for k, v in worst.items()}
+
+
+def check(w, sample_blocks=(0,), with_block_floor=False):
     banner(f"condense {w.name} p={w.p} M={w.n_macro} flux={w.params['flux']} visc={w.params['viscous']}")
     rng = np.random.default_rng(5)
     dvhat = 1e-2 * rng.standard_normal(w.vhat.shape)
@@ -59,12 +85,20 @@ def check(w, sample_blocks=(0,)):
     ref_dv, ref_dq = local.recover(ref, dvhat)
     NV, NH = ref["S"].shape[1], ref["Ap"].shape[1]
     fl = rhs_floor(w)
+    zero = np.zeros(w.n_macro)
+    bf = block_floor(w, dvhat) if with_block_floor else {
+        k: zero for k in ("S", "Y", "X", "Ap", "Ahat", "bhat", "dv", "dq")}
+    if with_block_floor:
+        banner("  block floors (relative): " + " ".join(
+            f"{k} {np.max(bf[k] / np.linalg.norm(r.reshape(w.n_macro, -1), axis=1)):.1e}"
+            for k, r in dict(ref, dv=ref_dv, dq=ref_dq).items() if k in bf))
     for m in sample_blocks:
         Bm = got["bord"][m]
-        e = dict(S=rel_err(Bm[None, :NV, :NV], ref["S"][m:m + 1]),
-                 Y=rel_err(-Bm[None, :NV, NV:NV + NH], ref["Y"][m:m + 1]),
-                 X=rel_err(Bm[None, NV:, :NV], ref["X"][m:m + 1]),
-                 Ap=rel_err(Bm[None, NV:, NV:NV + NH], ref["Ap"][m:m + 1]),
+        bfm = {k: bf[k][m:m + 1] / TOL for k in bf}
+        e = dict(S=rel_err(Bm[None, :NV, :NV], ref["S"][m:m + 1], floor=bfm["S"]),
+                 Y=rel_err(-Bm[None, :NV, NV:NV + NH], ref["Y"][m:m + 1], floor=bfm["Y"]),
+                 X=rel_err(Bm[None, NV:, :NV], ref["X"][m:m + 1], floor=bfm["X"]),
+                 Ap=rel_err(Bm[None, NV:, NV:NV + NH], ref["Ap"][m:m + 1], floor=bfm["Ap"]),
                  r_v=rel_err(Bm[None, :NV, NV + NH], ref["r_v"][m:m + 1], floor=fl[m:m + 1] / TOL),
                  r_hat=rel_err(Bm[None, NV:, NV + NH], ref["r_hat"][m:m + 1]))
         banner(f"  blocks macro {m}: " + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
@@ -72,10 +106,10 @@ def check(w, sample_blocks=(0,)):
     # floors of the solved quantities: the r_V floor through S^-1
     Sinv_norm = np.array([np.linalg.norm(np.linalg.inv(ref["S"][m]), 2) for m in range(w.n_macro)])
     Xn = np.array([np.linalg.norm(ref["X"][m], 2) for m in range(w.n_macro)])
-    e_A = rel_err(got["Ahat"], ref["Ahat"])
-    e_b = rel_err(got["bhat"], ref["bhat"], floor=10 * Xn * Sinv_norm * fl / TOL)
-    e_dv = rel_err(got["dv"], ref_dv, floor=10 * Sinv_norm * fl / TOL)
-    e_dq = rel_err(got["dq"], ref_dq, floor=10 * Sinv_norm * fl / TOL)
+    e_A = rel_err(got["Ahat"], ref["Ahat"], floor=bf["Ahat"] / TOL)
+    e_b = rel_err(got["bhat"], ref["bhat"], floor=np.maximum(10 * Xn * Sinv_norm * fl, bf["bhat"]) / TOL)
+    e_dv = rel_err(got["dv"], ref_dv, floor=np.maximum(10 * Sinv_norm * fl, bf["dv"]) / TOL)
+    e_dq = rel_err(got["dq"], ref_dq, floor=np.maximum(10 * Sinv_norm * fl, bf["dq"]) / TOL)
     banner(f"  Ahat {e_A:.2e} bhat {e_b:.2e} dV {e_dv:.2e} dQ {e_dq:.2e}")
     assert e_A < TOL and e_b < TOL and e_dv < TOL and e_dq < TOL
 
@@ -96,4 +130,15 @@ def test_condense_tgv_inviscid_kepes():
 
 def test_condense_p1_viscous_kepes():
     w = W.tgv_workload(shape=(3, 3, 2), p=1, M0=0.3, Re=500.0, flux="KEPES", seed_v=2, seed_vh=3)
-    check(w, sample_blocks=(0, 17))
+    check(w, sample_blocks=(0, 17), with_block_floor=True)
+
+
+def test_condense_p3_viscous_es():
+    # degree 3: 1715 interior unknowns (27 panels of 64), 1470 trace unknowns
+    w = W.workload(5, shape=(2, 1, 1))
+    w.params = dict(w.params, flux=1)
+    check(w, sample_blocks=(1,))
+
+
+def test_condense_p3_viscous_kepes():
+    check(W.workload(5, shape=(2, 1, 1)), sample_blocks=(1,), with_block_floor=True)
