@@ -107,7 +107,10 @@ mehdg_err mehdg_destroy(mehdg_ctx* ctx);
  * flux.  q may be NULL: then q is the weak gradient of (v, vhat), i.e. the
  * solution of R_Q = 0.  With want_blocks = 1 also assembles, per macro, the
  * Jacobian blocks of Sec. 6.2 with Q eliminated (eq. R1-R3): the bordered
- * matrix [[S, -Y, r_V], [X, A', r_hat]] in the context workspace.
+ * matrix [[S, -Y, r_V], [X, A', r_hat]] in the context workspace.  With
+ * want_blocks = 2 only the pointwise Jacobian coefficients that mehdg_jvp and
+ * mehdg_vjp read are stored (no bordered matrix; a preceding condensation's
+ * factors stay valid).  Both 1 and 2 set the state those products linearise at.
  *   v, v_old [n_macro][5][n]; vhat [n_macro][6][5][nf]; q NULL or [n_macro][5][3][n];
  *   R_q [n_macro][5][3][n]; R_v [n_macro][5][n]; R_vhat [n_macro][6][5][nf];
  *   entropy [n_macro].  All device pointers. */
@@ -128,6 +131,30 @@ mehdg_err mehdg_condense(mehdg_ctx* ctx, double* Ahat, double* bhat, mehdg_strea
  *   dvhat [n_macro][6][5][nf]; dv [n_macro][5][n]; dq [n_macro][5][3][n]. */
 mehdg_err mehdg_recover(mehdg_ctx* ctx, const double* R_q, const double* dvhat, double* dv,
                         double* dq, mehdg_stream stream);
+
+/* Jacobian-vector product of the residual of mehdg_assemble (Sec. 4.1
+ * eq. s32a-c with the time term of eq. C242; the Jacobian of Sec. 6.2 eq. R1,
+ * with the pseudo-time term alpha_ps (A0 dv, w) included as in the assembled
+ * blocks), at the state of the last mehdg_assemble with want_blocks 1 or 2
+ * (else MEHDG_ESTATE):
+ *   [JR_q; JR_v; JR_vhat] = J [dq; dv; dvhat].
+ * dq may be NULL: then dq is the weak gradient of (dv, dvhat), which is the
+ * derivative of the residual computed with q = NULL (JR_q is then zero up to
+ * rounding).  Layouts as in mehdg_assemble: dv, JR_v [n_macro][5][n];
+ * dvhat, JR_vhat [n_macro][6][5][nf]; dq, JR_q [n_macro][5][3][n].  Device
+ * pointers; outputs of macros with a status code set are NaN. */
+mehdg_err mehdg_jvp(mehdg_ctx* ctx, const double* dv, const double* dvhat, const double* dq, double* JR_q,
+                    double* JR_v, double* JR_vhat, mehdg_stream stream);
+
+/* Vector-Jacobian product, the transpose of mehdg_jvp at the same state.
+ * With w_q and g_q given: [g_q; g_v; g_vhat] = J^T [w_q; w_v; w_vhat], the
+ * gradient of w_q.R_Q + w_v.R_V + w_vhat.R_Vhat in (q, v, vhat).  With
+ * w_q = g_q = NULL: the gradient of w_v.R_V + w_vhat.R_Vhat in (v, vhat) with
+ * q the weak gradient of (v, vhat) (the transpose of mehdg_jvp with
+ * dq = NULL).  Exactly one of w_q, g_q NULL is MEHDG_EINVAL.  Layouts as in
+ * mehdg_jvp; device pointers; outputs of flagged macros are NaN. */
+mehdg_err mehdg_vjp(mehdg_ctx* ctx, const double* w_q, const double* w_v, const double* w_vhat, double* g_q,
+                    double* g_v, double* g_vhat, mehdg_stream stream);
 
 /* Copies the per-macro status codes (mehdg_err values, 0 = fine) of the
  * calls since the last mehdg_status into host memory status[n_macro] and
@@ -160,7 +187,9 @@ enum {
     MEHDG_PROF_SCHUR = 7,      /* Ahat = A' - L21 U12 on MFMA */
     MEHDG_PROF_RECOVER = 8,    /* back-substitution */
     MEHDG_PROF_TRSM = 9,       /* L21 = X U^-1 of the trace rows */
-    MEHDG_NPROF = 10
+    MEHDG_PROF_JVP = 10,       /* Jacobian-vector product */
+    MEHDG_PROF_VJP = 11,       /* vector-Jacobian product */
+    MEHDG_NPROF = 12
 };
 mehdg_err mehdg_profile_enable(mehdg_ctx* ctx, int32_t enable);
 mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t n);

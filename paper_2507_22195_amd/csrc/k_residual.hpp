@@ -178,6 +178,96 @@ __device__ void lift_gradient(ResLds<P>& L, const double hinv[3]) {
     }
 }
 
+// Testing of the integrands against the basis functions (phase 4): volume
+// fields of scr (layout above) and face fields fh, qh of the workgroup's LDS
+// -> R_q, R_v, R_vh of macro m.  One thread per node, then per trace node.
+// The same step closes the linearised products (k_linear.hpp).
+template <int P>
+__device__ __forceinline__ void test_integrands(const ResLds<P>& L, const double* __restrict__ scr, int64_t m,
+                                                double* __restrict__ R_q, double* __restrict__ R_v,
+                                                double* __restrict__ R_vh) {
+    using D = Dims<P>;
+    constexpr int n1d = D::n1d, nq1 = D::nq1, n = D::n, nf = D::nf, G = D::G;
+    const int tid = threadIdx.x;
+    for (int a = tid; a < n; a += blockDim.x) {
+        const int a1 = a % n1d, a2 = (a / n1d) % n1d, a3 = a / (n1d * n1d);
+        int lo1, hi1, lo2, hi2, lo3, hi3;
+        support_1d<P>(a1, lo1, hi1);
+        support_1d<P>(a2, lo2, hi2);
+        support_1d<P>(a3, lo3, hi3);
+        double rv[5] = {0, 0, 0, 0, 0}, rq[5][3];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) rq[k][0] = rq[k][1] = rq[k][2] = 0.0;
+        for (int g3 = lo3 * (P + 1); g3 < (hi3 + 1) * (P + 1); ++g3) {
+            const double B3 = L.t.B[g3][a3], D3 = L.t.D[g3][a3];
+            for (int g2 = lo2 * (P + 1); g2 < (hi2 + 1) * (P + 1); ++g2) {
+                const double B2 = L.t.B[g2][a2], D2 = L.t.D[g2][a2];
+                for (int g1 = lo1 * (P + 1); g1 < (hi1 + 1) * (P + 1); ++g1) {
+                    const double B1 = L.t.B[g1][a1], D1 = L.t.D[g1][a1];
+                    const int g = g1 + nq1 * (g2 + nq1 * g3);
+                    const double phi = B1 * B2 * B3;
+                    const double dphi[3] = {D1 * B2 * B3, B1 * D2 * B3, B1 * B2 * D3};
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        double acc = phi * scr[k * G + g];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) acc += dphi[j] * scr[(5 + 5 * j + k) * G + g];
+                        rv[k] += acc;
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+                            rq[k][j] += phi * scr[(20 + 3 * k + j) * G + g] + dphi[j] * scr[(35 + 5 * j + k) * G + g];
+                    }
+                }
+            }
+        }
+        // trace terms on the faces containing node a
+        const int ai[3] = {a1, a2, a3};
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int d = face_axis(f);
+            if (ai[d] != (face_side(f) ? n1d - 1 : 0)) continue;
+            const int c1 = ai[face_t1(f)], c2 = ai[face_t2(f)];
+            int l1, u1, l2, u2;
+            support_1d<P>(c1, l1, u1);
+            support_1d<P>(c2, l2, u2);
+            for (int s2 = l2 * (P + 1); s2 < (u2 + 1) * (P + 1); ++s2)
+                for (int s1 = l1 * (P + 1); s1 < (u1 + 1) * (P + 1); ++s1) {
+                    const int s = s1 + nq1 * s2;
+                    const double psi = L.t.B[s1][c1] * L.t.B[s2][c2];
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) {
+                        rv[k] += psi * L.fh[f][k][s];
+                        rq[k][d] -= psi * L.qh[f][k][s];
+                    }
+                }
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            R_v[(m * 5 + k) * n + a] = rv[k];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) R_q[((m * 5 + k) * 3 + j) * n + a] = rq[k][j];
+        }
+    }
+    // ---- phase 4b: test against trace basis functions
+    for (int idx = tid; idx < 6 * nf; idx += blockDim.x) {
+        const int f = idx / nf, c = idx % nf;
+        const int c1 = c % n1d, c2 = c / n1d;
+        int l1, u1, l2, u2;
+        support_1d<P>(c1, l1, u1);
+        support_1d<P>(c2, l2, u2);
+        double acc[5] = {0, 0, 0, 0, 0};
+        for (int s2 = l2 * (P + 1); s2 < (u2 + 1) * (P + 1); ++s2)
+            for (int s1 = l1 * (P + 1); s1 < (u1 + 1) * (P + 1); ++s1) {
+                const int s = s1 + nq1 * s2;
+                const double psi = L.t.B[s1][c1] * L.t.B[s2][c2];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) acc[k] += psi * L.fh[f][k][s];
+            }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) R_vh[((m * 6 + f) * 5 + k) * nf + c] = acc[k];
+    }
+}
+
 template <int P, bool JAC>
 __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, const double* __restrict__ vhat,
                                                   const double* __restrict__ q, const double* __restrict__ v_old,
@@ -355,84 +445,8 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
         entropy[m] = e;
     }
 
-    // ---- phase 4a: test against volume basis functions
-    for (int a = tid; a < n; a += blockDim.x) {
-        const int a1 = a % n1d, a2 = (a / n1d) % n1d, a3 = a / (n1d * n1d);
-        int lo1, hi1, lo2, hi2, lo3, hi3;
-        support_1d<P>(a1, lo1, hi1);
-        support_1d<P>(a2, lo2, hi2);
-        support_1d<P>(a3, lo3, hi3);
-        double rv[5] = {0, 0, 0, 0, 0}, rq[5][3];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) rq[k][0] = rq[k][1] = rq[k][2] = 0.0;
-        for (int g3 = lo3 * (P + 1); g3 < (hi3 + 1) * (P + 1); ++g3) {
-            const double B3 = L.t.B[g3][a3], D3 = L.t.D[g3][a3];
-            for (int g2 = lo2 * (P + 1); g2 < (hi2 + 1) * (P + 1); ++g2) {
-                const double B2 = L.t.B[g2][a2], D2 = L.t.D[g2][a2];
-                for (int g1 = lo1 * (P + 1); g1 < (hi1 + 1) * (P + 1); ++g1) {
-                    const double B1 = L.t.B[g1][a1], D1 = L.t.D[g1][a1];
-                    const int g = g1 + nq1 * (g2 + nq1 * g3);
-                    const double phi = B1 * B2 * B3;
-                    const double dphi[3] = {D1 * B2 * B3, B1 * D2 * B3, B1 * B2 * D3};
-#pragma unroll
-                    for (int k = 0; k < 5; ++k) {
-                        double acc = phi * scr[k * G + g];
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) acc += dphi[j] * scr[(5 + 5 * j + k) * G + g];
-                        rv[k] += acc;
-#pragma unroll
-                        for (int j = 0; j < 3; ++j)
-                            rq[k][j] += phi * scr[(20 + 3 * k + j) * G + g] + dphi[j] * scr[(35 + 5 * j + k) * G + g];
-                    }
-                }
-            }
-        }
-        // trace terms on the faces containing node a
-        const int ai[3] = {a1, a2, a3};
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            const int d = face_axis(f);
-            if (ai[d] != (face_side(f) ? n1d - 1 : 0)) continue;
-            const int c1 = ai[face_t1(f)], c2 = ai[face_t2(f)];
-            int l1, u1, l2, u2;
-            support_1d<P>(c1, l1, u1);
-            support_1d<P>(c2, l2, u2);
-            for (int s2 = l2 * (P + 1); s2 < (u2 + 1) * (P + 1); ++s2)
-                for (int s1 = l1 * (P + 1); s1 < (u1 + 1) * (P + 1); ++s1) {
-                    const int s = s1 + nq1 * s2;
-                    const double psi = L.t.B[s1][c1] * L.t.B[s2][c2];
-#pragma unroll
-                    for (int k = 0; k < 5; ++k) {
-                        rv[k] += psi * L.fh[f][k][s];
-                        rq[k][d] -= psi * L.qh[f][k][s];
-                    }
-                }
-        }
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            R_v[(m * 5 + k) * n + a] = rv[k];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) R_q[((m * 5 + k) * 3 + j) * n + a] = rq[k][j];
-        }
-    }
-    // ---- phase 4b: test against trace basis functions
-    for (int idx = tid; idx < 6 * nf; idx += blockDim.x) {
-        const int f = idx / nf, c = idx % nf;
-        const int c1 = c % n1d, c2 = c / n1d;
-        int l1, u1, l2, u2;
-        support_1d<P>(c1, l1, u1);
-        support_1d<P>(c2, l2, u2);
-        double acc[5] = {0, 0, 0, 0, 0};
-        for (int s2 = l2 * (P + 1); s2 < (u2 + 1) * (P + 1); ++s2)
-            for (int s1 = l1 * (P + 1); s1 < (u1 + 1) * (P + 1); ++s1) {
-                const int s = s1 + nq1 * s2;
-                const double psi = L.t.B[s1][c1] * L.t.B[s2][c2];
-#pragma unroll
-                for (int k = 0; k < 5; ++k) acc[k] += psi * L.fh[f][k][s];
-            }
-#pragma unroll
-        for (int k = 0; k < 5; ++k) R_vh[((m * 6 + f) * 5 + k) * nf + c] = acc[k];
-    }
+    // ---- phase 4: test against the volume and trace basis functions
+    test_integrands<P>(L, scr, m, R_q, R_v, R_vh);
     if (bad_phys) record_status(status, m, ST_NONPHYSICAL);
     else if (bad_fin) record_status(status, m, ST_NONFINITE);
 }

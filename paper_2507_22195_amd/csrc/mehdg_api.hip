@@ -14,6 +14,7 @@
 
 #include "../../include/mehdg.h"
 #include "common.hpp"
+#include "k_linear.hpp"
 #include "k_recover.hpp"
 #include "k_trace.hpp"
 #include "tables.hpp"
@@ -45,6 +46,7 @@ struct mehdg_ctx {
     double prof_ms[MEHDG_NPROF] = {};
     int64_t prof_calls[MEHDG_NPROF] = {};
     int stage = 0;                  // 0 nothing, 1 blocks assembled, 2 condensed
+    bool have_coef = false;         // pointwise coefficients of some state stored (mehdg_jvp / mehdg_vjp)
     // global trace system (mehdg_trace_*)
     int64_t n_faces = 0;
     int64_t* d_fid = nullptr;       // [n_macro][6] global face of each local face
@@ -113,12 +115,20 @@ bool allow_lds(K* kern, size_t bytes) {
 }
 
 template <int P>
-mehdg_err ensure_block_workspace(mehdg_ctx* c) {
-    if (c->d_B) return MEHDG_OK;
+mehdg_err ensure_coef_workspace(mehdg_ctx* c) {
+    if (c->d_coefF) return MEHDG_OK;
     using D = Dims<P>;
     mehdg_err e;
-    if ((e = dev_alloc(c, &c->d_coefV, c->n_macro * (int64_t)D::G * COEF_V)) != MEHDG_OK) return e;
-    if ((e = dev_alloc(c, &c->d_coefF, c->n_macro * (int64_t)6 * D::S * COEF_F)) != MEHDG_OK) return e;
+    if (!c->d_coefV && (e = dev_alloc(c, &c->d_coefV, c->n_macro * (int64_t)D::G * COEF_V)) != MEHDG_OK) return e;
+    return dev_alloc(c, &c->d_coefF, c->n_macro * (int64_t)6 * D::S * COEF_F);
+}
+
+template <int P>
+mehdg_err ensure_block_workspace(mehdg_ctx* c) {
+    mehdg_err e = ensure_coef_workspace<P>(c);
+    if (e != MEHDG_OK) return e;
+    if (c->d_B) return MEHDG_OK;
+    using D = Dims<P>;
     if ((e = dev_alloc(c, &c->d_minvrq, c->n_macro * (int64_t)15 * D::n)) != MEHDG_OK) return e;
     if ((e = dev_alloc(c, &c->d_ipiv, c->n_macro * (int64_t)D::NV)) != MEHDG_OK) return e;
     if ((e = dev_alloc(c, &c->d_tri, c->n_macro * Panel<P>::TRI)) != MEHDG_OK) return e;
@@ -130,11 +140,11 @@ mehdg_err ensure_block_workspace(mehdg_ctx* c) {
 template <int P>
 mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, const double* q,
                           const double* v_old, double* R_q, double* R_v, double* R_vhat, double* ent,
-                          bool blocks, hipStream_t st) {
+                          int mode, hipStream_t st) {
     using D = Dims<P>;
     const size_t lds = res_lds<P>();
     const unsigned M = (unsigned)c->n_macro;
-    if (!blocks) {
+    if (mode == 0) {
         if (!allow_lds(&k_residual<P, false>, lds)) return MEHDG_EHIP;
         Timed t(c, MEHDG_PROF_RESIDUAL, st);
         hipLaunchKernelGGL((k_residual<P, false>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
@@ -142,7 +152,7 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
                            c->d_status);
         return hip_ok(hipGetLastError());
     }
-    mehdg_err e = ensure_block_workspace<P>(c);
+    mehdg_err e = (mode == 1) ? ensure_block_workspace<P>(c) : ensure_coef_workspace<P>(c);
     if (e != MEHDG_OK) return e;
     if (!allow_lds(&k_residual<P, true>, lds)) return MEHDG_EHIP;
     {
@@ -151,6 +161,7 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
                            c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, c->d_coefV, c->d_coefF, c->d_status);
     }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    if (mode == 2) return MEHDG_OK;
     {
         Timed t(c, MEHDG_PROF_MINV_RQ, st);
         hipLaunchKernelGGL(k_minv_rq<P>, dim3(M), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
@@ -354,6 +365,28 @@ mehdg_err launch_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, d
     Timed t(c, MEHDG_PROF_RECOVER, st);
     hipLaunchKernelGGL(k_recover<P>, dim3((unsigned)c->n_macro), dim3(1024), lds, st, c->d_B, R_q, dvhat, c->d_h,
                        c->d_tab, dv, dq);
+    return hip_ok(hipGetLastError());
+}
+
+template <int P>
+mehdg_err launch_jvp(mehdg_ctx* c, const double* dv, const double* dvh, const double* dq, double* J_q, double* J_v,
+                     double* J_vh, hipStream_t st) {
+    const size_t lds = res_lds<P>();
+    if (!allow_lds(&k_jvp<P>, lds)) return MEHDG_EHIP;
+    Timed t(c, MEHDG_PROF_JVP, st);
+    hipLaunchKernelGGL(k_jvp<P>, dim3((unsigned)c->n_macro), dim3(256), lds, st, dv, dvh, dq, c->d_h, c->d_tab,
+                       c->d_coefV, c->d_coefF, c->dp.viscous, J_q, J_v, J_vh, c->d_scratch);
+    return hip_ok(hipGetLastError());
+}
+
+template <int P>
+mehdg_err launch_vjp(mehdg_ctx* c, const double* wq, const double* wv, const double* wvh, double* g_q, double* g_v,
+                     double* g_vh, hipStream_t st) {
+    const size_t lds = res_lds<P>();
+    if (!allow_lds(&k_vjp<P>, lds)) return MEHDG_EHIP;
+    Timed t(c, MEHDG_PROF_VJP, st);
+    hipLaunchKernelGGL(k_vjp<P>, dim3((unsigned)c->n_macro), dim3(256), lds, st, wq, wv, wvh, c->d_h, c->d_tab,
+                       c->d_coefV, c->d_coefF, c->dp.viscous, g_q, g_v, g_vh, c->d_scratch);
     return hip_ok(hipGetLastError());
 }
 
@@ -672,13 +705,14 @@ mehdg_err mehdg_assemble(mehdg_ctx* c, const double* v, const double* vhat, cons
                          const double* v_old, double* R_q, double* R_v, double* R_vhat, double* entropy,
                          int32_t want_blocks, mehdg_stream stream) {
     if (!c || !v || !vhat || !v_old || !R_q || !R_v || !R_vhat || !entropy) return MEHDG_EINVAL;
+    if (want_blocks < 0 || want_blocks > 2) return MEHDG_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const bool blocks = want_blocks != 0;
+    const int mode = want_blocks;
     mehdg_err e = MEHDG_EINVAL;
     switch (c->p) {
-        case 1: e = launch_assemble<1>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, blocks, st); break;
-        case 2: e = launch_assemble<2>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, blocks, st); break;
-        case 3: e = launch_assemble<3>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, blocks, st); break;
+        case 1: e = launch_assemble<1>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, mode, st); break;
+        case 2: e = launch_assemble<2>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, mode, st); break;
+        case 3: e = launch_assemble<3>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, mode, st); break;
         default: break;
     }
     if (e == MEHDG_OK) {
@@ -686,7 +720,48 @@ mehdg_err mehdg_assemble(mehdg_ctx* c, const double* v, const double* vhat, cons
         (void)mehdg_sizes(c->p, sz);
         e = launch_poison(c, PoisonArgs{{R_q, R_v, R_vhat, entropy}, {sz[3], sz[2], sz[4], 1}}, st);
     }
-    if (e == MEHDG_OK && blocks) c->stage = 1;
+    if (e == MEHDG_OK && mode == 1) c->stage = 1;
+    if (e == MEHDG_OK && mode != 0) c->have_coef = true;
+    return e;
+}
+
+mehdg_err mehdg_jvp(mehdg_ctx* c, const double* dv, const double* dvhat, const double* dq, double* JR_q,
+                    double* JR_v, double* JR_vhat, mehdg_stream stream) {
+    if (!c || !dv || !dvhat || !JR_q || !JR_v || !JR_vhat) return MEHDG_EINVAL;
+    if (!c->have_coef) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mehdg_err e = MEHDG_EINVAL;
+    switch (c->p) {
+        case 1: e = launch_jvp<1>(c, dv, dvhat, dq, JR_q, JR_v, JR_vhat, st); break;
+        case 2: e = launch_jvp<2>(c, dv, dvhat, dq, JR_q, JR_v, JR_vhat, st); break;
+        case 3: e = launch_jvp<3>(c, dv, dvhat, dq, JR_q, JR_v, JR_vhat, st); break;
+        default: break;
+    }
+    if (e == MEHDG_OK) {
+        int64_t sz[5];
+        (void)mehdg_sizes(c->p, sz);
+        e = launch_poison(c, PoisonArgs{{JR_q, JR_v, JR_vhat, nullptr}, {sz[3], sz[2], sz[4], 0}}, st);
+    }
+    return e;
+}
+
+mehdg_err mehdg_vjp(mehdg_ctx* c, const double* w_q, const double* w_v, const double* w_vhat, double* g_q,
+                    double* g_v, double* g_vhat, mehdg_stream stream) {
+    if (!c || !w_v || !w_vhat || !g_v || !g_vhat || (w_q == nullptr) != (g_q == nullptr)) return MEHDG_EINVAL;
+    if (!c->have_coef) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mehdg_err e = MEHDG_EINVAL;
+    switch (c->p) {
+        case 1: e = launch_vjp<1>(c, w_q, w_v, w_vhat, g_q, g_v, g_vhat, st); break;
+        case 2: e = launch_vjp<2>(c, w_q, w_v, w_vhat, g_q, g_v, g_vhat, st); break;
+        case 3: e = launch_vjp<3>(c, w_q, w_v, w_vhat, g_q, g_v, g_vhat, st); break;
+        default: break;
+    }
+    if (e == MEHDG_OK) {
+        int64_t sz[5];
+        (void)mehdg_sizes(c->p, sz);
+        e = launch_poison(c, PoisonArgs{{g_q, g_v, g_vhat, nullptr}, {sz[3], sz[2], sz[4], 0}}, st);
+    }
     return e;
 }
 

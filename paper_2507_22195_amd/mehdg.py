@@ -22,7 +22,7 @@ EXPORTS = ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "me
            "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_workspace_bytes",
            "mehdg_profile_enable", "mehdg_profile_read")
 PROF_SLOTS = ("residual", "minv_rq", "rows_v", "rows_h", "panel", "rowblock", "update", "schur",
-              "recover", "trsm")
+              "recover", "trsm", "jvp", "vjp")
 
 
 class MehdgError(RuntimeError):
@@ -82,9 +82,11 @@ def load(path: str = LIB_PATH):
     lib.mehdg_trace_solve.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_double), vp]
     lib.mehdg_add_source.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_jvp.argtypes = [vp] + [vp] * 6 + [vp]
+    lib.mehdg_vjp.argtypes = [vp] + [vp] * 6 + [vp]
     lib.mehdg_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
     lib.mehdg_dot.argtypes = [vp, i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
-    for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot"):
+    for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
                  "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_profile_enable",
@@ -169,6 +171,7 @@ class Context:
         self._h = h
         mesh = Mesh(self.n_macro, self.p, 0, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
         self._prm = make_params(params)
+        self.params = dict(params)
         handle = ctypes.c_void_p()
         rc = lib.mehdg_create(ctypes.byref(mesh), ctypes.byref(self._prm), ctypes.byref(handle))
         if rc:
@@ -282,9 +285,32 @@ class Context:
                 _ptr(q, S["q"], "q", optional=True), _ptr(v_old, S["v"], "v_old"),
                 _ptr(R_q, S["R_q"], "R_q"), _ptr(R_v, S["R_v"], "R_v"),
                 _ptr(R_vhat, S["R_vhat"], "R_vhat"), _ptr(entropy, S["entropy"], "entropy")]
-        rc = load().mehdg_assemble(self._handle, *args, int(bool(want_blocks)), _stream(stream))
+        mode = want_blocks if isinstance(want_blocks, int) and not isinstance(want_blocks, bool) \
+            else int(bool(want_blocks))
+        rc = load().mehdg_assemble(self._handle, *args, mode, _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_assemble")
+
+    def jvp(self, dv, dvhat, dq, JR_q, JR_v, JR_vhat, stream=None):
+        """J [dq; dv; dvhat] at the state of the last assemble with want_blocks 1 or 2;
+        dq None: the weak gradient of (dv, dvhat)."""
+        S = self.shapes()
+        rc = load().mehdg_jvp(self._handle, _ptr(dv, S["v"], "dv"), _ptr(dvhat, S["vhat"], "dvhat"),
+                              _ptr(dq, S["q"], "dq", optional=True), _ptr(JR_q, S["R_q"], "JR_q"),
+                              _ptr(JR_v, S["R_v"], "JR_v"), _ptr(JR_vhat, S["R_vhat"], "JR_vhat"),
+                              _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_jvp")
+
+    def vjp(self, w_v, w_vhat, g_v, g_vhat, w_q=None, g_q=None, stream=None):
+        """J^T w at the same state; w_q, g_q None: through the weak gradient."""
+        S = self.shapes()
+        rc = load().mehdg_vjp(self._handle, _ptr(w_q, S["R_q"], "w_q", optional=True),
+                              _ptr(w_v, S["R_v"], "w_v"), _ptr(w_vhat, S["R_vhat"], "w_vhat"),
+                              _ptr(g_q, S["q"], "g_q", optional=True), _ptr(g_v, S["v"], "g_v"),
+                              _ptr(g_vhat, S["vhat"], "g_vhat"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_vjp")
 
     def condense(self, Ahat, bhat, stream=None):
         S = self.shapes()

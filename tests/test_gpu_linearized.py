@@ -1,0 +1,234 @@
+"""GPU residual JVP / VJP (mehdg_jvp, mehdg_vjp) and the autograd wrapper.
+
+* parity with the oracle's products (oracle.linearized: the dense Jacobian
+  of eq. R1 times a vector), full (dq / w_q given) and reduced (q the weak
+  gradient of (v, vhat)), per macro normwise relative <= 1e-12; with the
+  KEPES flux, max(1e-12 |ref|, 10 s), s the oracle's own change under one-ulp
+  noise on the state (the switch of eq. KEPES5);
+* on the whole 8^3 inviscid p = 2 mesh of the differentiation workload
+  (Mach 0.4, seeded 1e-3 perturbation of v): the adjoint identity
+  <w, J x> = <J^T w, x> per macro to 1e-12 (a property that holds at any
+  size) and two sampled macros against the oracle; on the same mesh with
+  the trace perturbed as well (away from the kink of |Vhat.n|), the JVP
+  against a central difference of the GPU residual (step 1e-7, relative
+  1e-6);
+* the torch.autograd.Function: gradcheck (reverse and forward mode) on one
+  p = 1 macro, and forward-mode dual tensors against mehdg_jvp.
+"""
+import numpy as np
+import pytest
+
+from oracle import linearized as lin
+from oracle import local
+from paper_2507_22195_amd import workloads as W
+from tests.gpu_util import banner, dev, empty, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _cases():
+    return {
+        "vortex EC p2": W.subset(W.workload(1), [0, 5]),
+        "tgv viscous ES p2": W.subset(W.workload(2, shape=(4, 4, 4)), [0, 21, 40]),
+        "tgv viscous KEPES p1": W.tgv_workload(shape=(2, 2, 1), p=1, M0=0.3, Re=500.0, flux="KEPES",
+                                               seed_v=5, seed_vh=6),
+        "tgv viscous ES p3": W.subset(W.tgv_workload(shape=(2, 1, 1), p=3, M0=0.3, Re=5000.0, flux="ES",
+                                                     seed_v=51, seed_vh=52), [1]),
+    }
+
+
+def _oracle_products(w, qq, vecs):
+    dv, dh, dq, wv, wh, wq = vecs
+    out = {}
+    out["jvp_r v"], out["jvp_r vhat"] = lin.jvp(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, dv, dh, q=qq)[1:]
+    out["vjp_r v"], out["vjp_r vhat"] = lin.vjp(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, wv, wh, q=qq)
+    out["jvp q"], out["jvp v"], out["jvp vhat"] = lin.jvp(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, dv, dh,
+                                                          dq=dq, q=qq)
+    out["vjp q"], out["vjp v"], out["vjp vhat"] = lin.vjp(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, wv, wh,
+                                                          w_q=wq, q=qq, full=True)
+    return out
+
+
+def _product_floor(w, qq, vecs, ref, trials=2):
+    """10x the per-macro change (norm) of every oracle product under one-ulp
+    noise on the state: the KEPES switch sqrt|(P - Phat)/(P + Phat)|
+    (eq. KEPES5) makes the Jacobian ill-conditioned where P is close to Phat."""
+    import copy
+    rng = np.random.default_rng(12)
+    worst = {k: np.zeros(w.n_macro) for k in ref}
+    for _ in range(trials):
+        pert = lambda x: x * (1 + 2.2e-16 * rng.uniform(-1, 1, x.shape))
+        wp = copy.copy(w)
+        wp.v, wp.vhat = pert(w.v), pert(w.vhat)
+        o = _oracle_products(wp, None if qq is None else pert(qq), vecs)
+        for k in ref:
+            worst[k] = np.maximum(worst[k], np.linalg.norm((o[k] - ref[k]).reshape(w.n_macro, -1), axis=1))
+    return {k: 10 * v for k, v in worst.items()}
+
+
+def _linearised_ctx(w, q=None, mode=2):
+    from paper_2507_22195_amd import mehdg
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+    ctx.assemble(dev(w.v), dev(w.vhat), None if q is None else dev(q), dev(w.v_old), R_q, R_v, R_vh, ent,
+                 want_blocks=mode)
+    return ctx, dict(R_q=R_q, R_v=R_v, R_vhat=R_vh)
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_jvp_vjp_match_oracle(name):
+    w = _cases()[name]
+    banner(f"linearized: {name} M={w.n_macro}")
+    rng = np.random.default_rng(8)
+    geo = local.Geometry(w.p, w.mesh.h)
+    q = local.lift_q(geo, w.v, w.vhat) + 1e-3 * rng.standard_normal((w.n_macro, 5, 3, geo.n))
+    vecs = (rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape), rng.standard_normal(q.shape),
+            rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape), rng.standard_normal(q.shape))
+    dv, dh, dq, wv, wh, wq = vecs
+    kepes = w.params["flux"] == 2
+    errs = {}
+    for qmode in ("lifted", "given"):
+        qq = None if qmode == "lifted" else q
+        ctx, _ = _linearised_ctx(w, q=qq)
+        S = ctx.shapes()
+        got = {}
+        Jq, Jv, Jh = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"])
+        gq, gv, gh = empty(S["q"]), empty(S["v"]), empty(S["vhat"])
+        # reduced products (weak-gradient direction / adjoint through the lift)
+        ctx.jvp(dev(dv), dev(dh), None, Jq, Jv, Jh)
+        got["jvp_r v"], got["jvp_r vhat"] = host(Jv), host(Jh)
+        ctx.vjp(dev(wv), dev(wh), gv, gh)
+        got["vjp_r v"], got["vjp_r vhat"] = host(gv), host(gh)
+        # full products
+        ctx.jvp(dev(dv), dev(dh), dev(dq), Jq, Jv, Jh)
+        got["jvp q"], got["jvp v"], got["jvp vhat"] = host(Jq), host(Jv), host(Jh)
+        ctx.vjp(dev(wv), dev(wh), gv, gh, w_q=dev(wq), g_q=gq)
+        got["vjp q"], got["vjp v"], got["vjp vhat"] = host(gq), host(gv), host(gh)
+        rc, st = ctx.status()
+        assert rc == 0
+        ctx.close()
+        ref = _oracle_products(w, qq, vecs)
+        fl = _product_floor(w, qq, vecs, ref) if kepes else {k: 0.0 for k in ref}
+        for k in ref:
+            errs[f"{qmode} {k}"] = rel_err(got[k], ref[k], floor=fl[k] / TOL)
+    banner("  " + " ".join(f"[{k}] {v:.1e}" for k, v in errs.items()))
+    assert all(v < TOL for v in errs.values()), errs
+
+
+def test_products_on_the_differentiation_mesh():
+    """8^3 macros, p = 2, inviscid ES, Mach 0.4: adjoint identity everywhere,
+    sampled macros against the oracle, JVP against central differences."""
+    import torch
+    w = W.workload(3)
+    w.params = dict(w.params, alpha_ps=0.0)
+    banner(f"linearized: differentiation mesh M={w.n_macro}")
+    ctx, base = _linearised_ctx(w)
+    S = ctx.shapes()
+    g = torch.Generator(device="cuda").manual_seed(4)
+    rnd = lambda k: torch.randn(S[k], dtype=torch.float64, device="cuda", generator=g)
+    dv, dh, wv, wh = rnd("v"), rnd("vhat"), rnd("R_v"), rnd("R_vhat")
+    Jq, Jv, Jh = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"])
+    gv, gh = empty(S["v"]), empty(S["vhat"])
+    ctx.jvp(dv, dh, None, Jq, Jv, Jh)
+    ctx.vjp(wv, wh, gv, gh)
+    M = w.n_macro
+    flat = lambda *t: torch.cat([x.reshape(M, -1) for x in t], dim=1)
+    lhs = (flat(wv, wh) * flat(Jv, Jh)).sum(1)
+    rhs = (flat(gv, gh) * flat(dv, dh)).sum(1)
+    scale = flat(wv, wh).norm(dim=1) * flat(Jv, Jh).norm(dim=1)
+    adj = float(((lhs - rhs).abs() / scale).max())
+    banner(f"  adjoint identity max {adj:.1e}")
+    assert adj < TOL
+
+    # sampled macros against the oracle (the products are per macro)
+    for m in (0, 300):
+        ws = W.subset(w, [m])
+        rv, rh = lin.jvp(ws.p, ws.mesh.h, ws.v, ws.vhat, ws.v_old, ws.params, host(dv)[m:m + 1],
+                         host(dh)[m:m + 1])[1:]
+        sv, sh = lin.vjp(ws.p, ws.mesh.h, ws.v, ws.vhat, ws.v_old, ws.params, host(wv)[m:m + 1],
+                         host(wh)[m:m + 1])
+        e = [rel_err(host(Jv)[m:m + 1], rv), rel_err(host(Jh)[m:m + 1], rh),
+             rel_err(host(gv)[m:m + 1], sv), rel_err(host(gh)[m:m + 1], sh)]
+        banner(f"  macro {m}: " + " ".join(f"{x:.1e}" for x in e))
+        assert max(e) < TOL
+
+    rc, st = ctx.status()
+    assert rc == 0
+    ctx.close()
+
+    # central differences of the GPU residual, step 1e-7.  The trace is
+    # perturbed too here: with the exact trace, V.n vanishes on some face
+    # planes (sin x = 0), where sigma = |Vhat.n| + c of the ES flux has a kink
+    # that a finite step straddles.
+    w = W.tgv_workload(shape=(8, 8, 8), p=2, M0=0.4, viscous=False, flux="ES", seed_v=31, seed_vh=32)
+    w.params = dict(w.params, alpha_ps=0.0)
+    ctx, base = _linearised_ctx(w)
+    ctx.jvp(dv, dh, None, Jq, Jv, Jh)
+    hstep = 1e-7
+    R = {}
+    for sgn in (1, -1):
+        R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+        ctx.assemble((dev(w.v) + sgn * hstep * dv).contiguous(), (dev(w.vhat) + sgn * hstep * dh).contiguous(),
+                     None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=0)
+        R[sgn] = (R_v, R_vh)
+    fdv = (R[1][0] - R[-1][0]) / (2 * hstep)
+    fdh = (R[1][1] - R[-1][1]) / (2 * hstep)
+    # macros where the step moves some face point's normal velocity across 0
+    # (the kink of |Vhat.n|) are left out; they are counted
+    geo = local.Geometry(w.p, w.mesh.h)
+    dhh = host(dh)
+    cross = np.zeros(w.n_macro, dtype=bool)
+    for f in range(6):
+        psi = geo.t["face_psi"][f]
+        d = f // 2
+        a = np.einsum("sc,mc->ms", psi, w.vhat[:, f, d + 1])
+        b = np.einsum("sc,mc->ms", psi, dhh[:, f, d + 1])
+        cross |= np.any(np.abs(a) <= 2 * hstep * np.abs(b), axis=1)
+    keep = ~cross
+    e_fd = max(rel_err(host(Jv)[keep], host(fdv)[keep]), rel_err(host(Jh)[keep], host(fdh)[keep]))
+    banner(f"  JVP vs central difference {e_fd:.1e} over {keep.sum()} macros "
+           f"({cross.sum()} with a face point within the step of the kink left out)")
+    assert keep.sum() >= 0.85 * w.n_macro
+    assert e_fd < 1e-6
+    rc, st = ctx.status()
+    assert rc == 0
+    ctx.close()
+
+
+def test_autograd_function():
+    import torch
+    from paper_2507_22195_amd import mehdg
+    from paper_2507_22195_amd.autograd import Residual
+    w = W.subset(W.tgv_workload(shape=(2, 2, 1), p=1, M0=0.3, Re=500.0, flux="ES", seed_v=5, seed_vh=6), [2])
+    prm = dict(w.params, alpha_ps=0.0)
+    banner("linearized: autograd gradcheck p=1, one macro")
+    ctx = mehdg.Context(w.p, w.mesh.h, prm)
+    f = Residual(ctx, dev(w.v_old))
+    v = dev(w.v).requires_grad_(True)
+    vh = dev(w.vhat).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, b: f(a, b), (v, vh), eps=1e-6, atol=1e-6, rtol=1e-4,
+                                    check_forward_ad=True, check_backward_ad=True, check_undefined_grad=False)
+    # forward-mode dual tensors equal a direct mehdg_jvp
+    import torch.autograd.forward_ad as fwAD
+    rng = np.random.default_rng(9)
+    dv = dev(rng.standard_normal(w.v.shape))
+    dh = dev(rng.standard_normal(w.vhat.shape))
+    with fwAD.dual_level():
+        Rv, Rh = f(fwAD.make_dual(v.detach(), dv), fwAD.make_dual(vh.detach(), dh))
+        tv, th = fwAD.unpack_dual(Rv).tangent, fwAD.unpack_dual(Rh).tangent
+    S = ctx.shapes()
+    Jq, Jv, Jh = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"])
+    f.linearise(v, vh)
+    ctx.jvp(dv, dh, None, Jq, Jv, Jh)
+    assert torch.equal(tv, Jv) and torch.equal(th, Jh)
+    # reverse mode through a scalar loss
+    loss = (f(v, vh)[0] ** 2).sum()
+    loss.backward()
+    R_v = f.linearise(v, vh)[0]
+    g_v, g_h = torch.empty_like(v), torch.empty_like(vh)
+    ctx.vjp((2 * R_v).contiguous(), torch.zeros_like(vh), g_v, g_h)
+    assert torch.equal(v.grad, g_v) and torch.equal(vh.grad, g_h)
+    ctx.close()
