@@ -125,6 +125,18 @@ mehdg_err mehdg_assemble(mehdg_ctx* ctx, const double* v, const double* vhat, co
  * formed); bhat [n_macro][N_VH].  Device pointers. */
 mehdg_err mehdg_condense(mehdg_ctx* ctx, double* Ahat, double* bhat, mehdg_stream stream);
 
+/* The stored condensation applied to a new right-hand side (Sec. 6.2 eq. R4,
+ * R5b): with r_V [n_macro][N_V] (V ordering) and r_hat [n_macro][N_VH]
+ * (NULL: zero) in place of the assembled -R_V + A_vq A_qq^-1 R_Q and
+ * -R_Vhat + A_vhatq A_qq^-1 R_Q, writes bhat = r_hat - X S^-1 r_V and makes
+ * the next mehdg_recover return dV = S^-1 (r_V + Y dVhat) (dQ from its R_q
+ * argument as before).  Requires a preceding mehdg_condense (else
+ * MEHDG_ESTATE); the factors are kept.  This solves the assembled Newton
+ * system for any right-hand side, e.g. as the preconditioner of a
+ * Jacobian-free Newton-Krylov iteration.  Device pointers. */
+mehdg_err mehdg_condense_rhs(mehdg_ctx* ctx, const double* r_v, const double* r_hat, double* bhat,
+                             mehdg_stream stream);
+
 /* Back-substitution once the trace update is known (eq. R2 then R6):
  * dV = S^-1 (r_V + Y dVhat), dQ = A_qq^-1 (-R_Q - A_qv dV - A_qvhat dVhat).
  * R_q is the residual returned by the assemble that preceded the condense.
@@ -189,7 +201,8 @@ enum {
     MEHDG_PROF_TRSM = 9,       /* L21 = X U^-1 of the trace rows */
     MEHDG_PROF_JVP = 10,       /* Jacobian-vector product */
     MEHDG_PROF_VJP = 11,       /* vector-Jacobian product */
-    MEHDG_NPROF = 12
+    MEHDG_PROF_FSOLVE = 12,    /* stored factors applied to a new right-hand side */
+    MEHDG_NPROF = 13
 };
 mehdg_err mehdg_profile_enable(mehdg_ctx* ctx, int32_t enable);
 mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t n);

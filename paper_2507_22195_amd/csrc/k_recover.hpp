@@ -149,4 +149,108 @@ __global__ void __launch_bounds__(1024) k_recover(const double* __restrict__ B, 
     }
 }
 
+// New right-hand side (r_V, r_hat) for the stored factors: y = L^-1 P r_V and
+// bhat = r_hat - L21 y = r_hat - X S^-1 r_V (eq. R5b); y replaces the
+// right-hand-side column, so that the next k_recover gives
+// dV = S^-1 (r_V + Y dVhat).  The multipliers of an outer block are stored in
+// the row order of that block's elimination (later blocks never move the
+// columns left of them), so the forward substitution replays the block's
+// interchanges (LAPACK order) right before the block, exactly as the
+// condensation transformed its own right-hand-side column.  Per 64-column
+// chunk: wave 0 solves the unit-lower triangle (lane j holds row j), then all
+// waves update the rows below with coalesced row reads.
+template <int P>
+struct FsLds {
+    double z[Dims<P>::NV];
+    double T[64][65];
+};
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_fsolve(double* __restrict__ B, const int32_t* __restrict__ ipiv,
+                                                const double* __restrict__ r_v, const double* __restrict__ r_h,
+                                                double* __restrict__ bhat) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    using PN = Panel<P>;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld, OB = PN::OB;
+    constexpr int RB = 8;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    FsLds<P>& L = *reinterpret_cast<FsLds<P>*>(smem_raw);
+    const int64_t m = blockIdx.x;
+    double* Bm = B + m * BD::per_macro;
+    const int32_t* pv = ipiv + m * NV;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    for (int i = tid; i < NV; i += blockDim.x) L.z[i] = r_v[m * NV + i];
+    __syncthreads();
+    for (int kb0 = 0; kb0 < NV; kb0 += OB) {
+        const int w = (NV - kb0) < OB ? (NV - kb0) : OB;
+        if (tid == 0) {
+            for (int j = kb0; j < kb0 + w; ++j) {
+                const int p = pv[j];
+                if (p != j && p > j && p < NV) {
+                    const double t = L.z[j];
+                    L.z[j] = L.z[p];
+                    L.z[p] = t;
+                }
+            }
+        }
+        __syncthreads();
+        for (int c0 = kb0; c0 < kb0 + w; c0 += 64) {
+            const int nb = (kb0 + w - c0) < 64 ? (kb0 + w - c0) : 64;
+            for (int e = tid; e < 64 * 64; e += blockDim.x) {
+                const int r = e >> 6, c = e & 63;
+                L.T[r][c] = (r < nb && c < nb) ? Bm[(int64_t)(c0 + r) * ld + c0 + c] : 0.0;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                double zi = (lane < nb) ? L.z[c0 + lane] : 0.0;
+                for (int j = 0; j < nb; ++j) {
+                    const double xj = read_lane_f64(zi, j);
+                    if (lane > j) zi -= L.T[lane][j] * xj;
+                }
+                if (lane < nb) L.z[c0 + lane] = zi;
+            }
+            __syncthreads();
+            const double x = (lane < nb) ? L.z[c0 + lane] : 0.0;
+            for (int r0 = c0 + nb + wave * RB; r0 < NV; r0 += nw * RB) {
+                double s[RB];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    s[i] = (lane < nb && r0 + i < NV) ? Bm[(int64_t)(r0 + i) * ld + c0 + lane] * x : 0.0;
+#pragma unroll
+                for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+                if (lane < RB && r0 + lane < NV) {
+                    double si = s[0];
+#pragma unroll
+                    for (int i = 1; i < RB; ++i)
+                        if (lane == i) si = s[i];
+                    L.z[r0 + lane] -= si;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < NV; i += blockDim.x) Bm[(int64_t)i * ld + NV + NH] = L.z[i];
+    for (int r0 = wave * RB; r0 < NH; r0 += nw * RB) {
+        double s[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = 0.0;
+        for (int c = lane; c < NV; c += 64) {
+            const double x = L.z[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < NH) s[i] += Bm[(int64_t)(NV + r0 + i) * ld + c] * x;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+        if (lane < RB && r0 + lane < NH) {
+            double si = s[0];
+#pragma unroll
+            for (int i = 1; i < RB; ++i)
+                if (lane == i) si = s[i];
+            bhat[m * NH + r0 + lane] = (r_h ? r_h[m * NH + r0 + lane] : 0.0) - si;
+        }
+    }
+}
+
 }  // namespace mehdg

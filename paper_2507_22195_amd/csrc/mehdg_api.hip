@@ -390,6 +390,16 @@ mehdg_err launch_vjp(mehdg_ctx* c, const double* wq, const double* wv, const dou
     return hip_ok(hipGetLastError());
 }
 
+template <int P>
+mehdg_err launch_fsolve(mehdg_ctx* c, const double* r_v, const double* r_h, double* bhat, hipStream_t st) {
+    const size_t lds = sizeof(FsLds<P>);
+    if (!allow_lds(&k_fsolve<P>, lds)) return MEHDG_EHIP;
+    Timed t(c, MEHDG_PROF_FSOLVE, st);
+    hipLaunchKernelGGL(k_fsolve<P>, dim3((unsigned)c->n_macro), dim3(1024), lds, st, c->d_B, c->d_ipiv, r_v, r_h,
+                       bhat);
+    return hip_ok(hipGetLastError());
+}
+
 int64_t bordered_rows(int p) {
     switch (p) {
         case 1: return Bdims<1>::rows;
@@ -782,6 +792,26 @@ mehdg_err mehdg_condense(mehdg_ctx* c, double* Ahat, double* bhat, mehdg_stream 
         e = launch_poison(c, PoisonArgs{{Ahat, bhat, nullptr, nullptr}, {sz[4] * sz[4], sz[4], 0, 0}}, st);
     }
     if (e == MEHDG_OK) c->stage = 2;
+    return e;
+}
+
+mehdg_err mehdg_condense_rhs(mehdg_ctx* c, const double* r_v, const double* r_hat, double* bhat,
+                             mehdg_stream stream) {
+    if (!c || !r_v || !bhat) return MEHDG_EINVAL;
+    if (c->stage != 2) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mehdg_err e = MEHDG_EINVAL;
+    switch (c->p) {
+        case 1: e = launch_fsolve<1>(c, r_v, r_hat, bhat, st); break;
+        case 2: e = launch_fsolve<2>(c, r_v, r_hat, bhat, st); break;
+        case 3: e = launch_fsolve<3>(c, r_v, r_hat, bhat, st); break;
+        default: break;
+    }
+    if (e == MEHDG_OK) {
+        int64_t sz[5];
+        (void)mehdg_sizes(c->p, sz);
+        e = launch_poison(c, PoisonArgs{{bhat, nullptr, nullptr, nullptr}, {sz[4], 0, 0, 0}}, st);
+    }
     return e;
 }
 

@@ -22,7 +22,7 @@ EXPORTS = ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "me
            "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_workspace_bytes",
            "mehdg_profile_enable", "mehdg_profile_read")
 PROF_SLOTS = ("residual", "minv_rq", "rows_v", "rows_h", "panel", "rowblock", "update", "schur",
-              "recover", "trsm", "jvp", "vjp")
+              "recover", "trsm", "jvp", "vjp", "fsolve")
 
 
 class MehdgError(RuntimeError):
@@ -83,10 +83,11 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_double), vp]
     lib.mehdg_add_source.argtypes = [vp, vp, vp, vp]
     lib.mehdg_jvp.argtypes = [vp] + [vp] * 6 + [vp]
+    lib.mehdg_condense_rhs.argtypes = [vp, vp, vp, vp, vp]
     lib.mehdg_vjp.argtypes = [vp] + [vp] * 6 + [vp]
     lib.mehdg_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
     lib.mehdg_dot.argtypes = [vp, i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
-    for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp"):
+    for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
                  "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_profile_enable",
@@ -318,6 +319,18 @@ class Context:
                                    _ptr(bhat, S["bhat"], "bhat"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_condense")
+
+    def condense_rhs(self, r_v, r_hat, bhat, stream=None):
+        """bhat = r_hat - X S^-1 r_v with the stored factors; r_hat None means zero.
+        The next recover uses r_v.  r_v shaped like v, r_hat like R_vhat or bhat."""
+        S = self.shapes()
+        rh = None
+        if r_hat is not None:
+            rh = _ptr(r_hat, S["bhat"] if r_hat.dim() == 2 else S["R_vhat"], "r_hat")
+        rc = load().mehdg_condense_rhs(self._handle, _ptr(r_v, S["v"], "r_v"), rh, _ptr(bhat, S["bhat"], "bhat"),
+                                       _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_condense_rhs")
 
     def recover(self, R_q, dvhat, dv, dq, stream=None):
         S = self.shapes()
