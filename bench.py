@@ -180,6 +180,63 @@ def trace_solve(ctx, w, Ahat, bhat, rtol=1e-8, restart=30, maxit=300):
             "apply_GBps": round(8.0 * NH * NH * w.n_macro / apply_s / 1e9, 1)}
 
 
+def differentiation(reps=5):
+    """Residual JVP / VJP on the differentiation workload (8^3 macros, p = 2,
+    inviscid ES, Mach 0.4; not part of the metric).  Both kernels are bound by
+    reading the pointwise coefficients: algorithmic bytes per macro = the
+    coefficient blocks a product reads (inviscid: the v-blocks only) + its
+    inputs + its outputs, each once."""
+    import torch
+    from paper_2507_22195_amd import mehdg
+    from paper_2507_22195_amd import workloads as W
+    w = W.workload(3)
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    e = lambda k: torch.empty(S[k], dtype=torch.float64, device="cuda")
+    v, vh, vo = dev(w.v), dev(w.vhat), dev(w.v_old)
+    R_q, R_v, R_vh, ent = e("R_q"), e("R_v"), e("R_vhat"), e("entropy")
+    g = torch.Generator(device="cuda").manual_seed(2)
+    rnd = lambda k: torch.randn(S[k], dtype=torch.float64, device="cuda", generator=g)
+    dv, dh, wv, wh = rnd("v"), rnd("vhat"), rnd("R_v"), rnd("R_vhat")
+    Jq, Jv, Jh, gv, gh = e("R_q"), e("R_v"), e("R_vhat"), e("v"), e("vhat")
+
+    def run():
+        ctx.assemble(v, vh, None, vo, R_q, R_v, R_vh, ent, want_blocks=2)
+        ctx.jvp(dv, dh, None, Jq, Jv, Jh)
+        ctx.vjp(wv, wh, gv, gh)
+
+    run()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read()
+    for _ in range(reps):
+        run()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    rc, _ = ctx.status()
+    sz = ctx.sz
+    n, nf, M = sz["n"], sz["nf"], w.n_macro
+    G = (2 * (w.p + 1)) ** 3
+    Sf = 6 * (2 * (w.p + 1)) ** 2
+    visc = bool(w.params["viscous"])
+    coef = 8 * (G * (325 if visc else 100) + Sf * (125 if visc else 50))
+    io_jvp = 8 * (5 * n + 30 * nf + 15 * n + 5 * n + 30 * nf)
+    io_vjp = 8 * (5 * n + 30 * nf + 5 * n + 30 * nf)
+    out = {"workload": f"inviscid TGV 8x8x8 macro-elements of 2x2x2 p=2 hexahedra, ES flux, Mach 0.4",
+           "n_macro": M, "status_ok": bool(rc == 0),
+           "bytes_per_macro": {"jvp": coef + io_jvp, "vjp": coef + io_vjp}}
+    for name, kb in (("residual", None), ("jvp", coef + io_jvp), ("vjp", coef + io_vjp)):
+        ms, calls = prof[name]
+        avg = ms / max(calls, 1)
+        out[f"{name}_ms"] = round(avg, 4)
+        if kb is not None:
+            out[f"{name}_GBps"] = round(kb * M / (avg / 1e3) / 1e9, 1)
+            out[f"{name}_frac_hbm"] = round(kb * M / (avg / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +245,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shape", type=int, nargs=3, default=None, help="macro grid (default 16 16 16)")
     ap.add_argument("--no-trace", action="store_true", help="skip the global trace solve measurement")
+    ap.add_argument("--no-diff", action="store_true", help="skip the JVP / VJP measurement")
+    ap.add_argument("--diff-only", action="store_true", help="only the JVP / VJP measurement (profiling)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="before warm-up, copy a MIB-sized buffer three times (untimed) so that a counter "
                          "run sees a plain copy kernel of known size")
@@ -201,6 +260,9 @@ def main():
     from paper_2507_22195_amd import mehdg
     from paper_2507_22195_amd import workloads as W
 
+    if args.diff_only:
+        print(json.dumps({"differentiation": differentiation(reps=args.steps)}), flush=True)
+        return
     w = W.workload(2, shape=tuple(args.shape) if args.shape else None)
     ctx = mehdg.Context(w.p, w.mesh.h, w.params)
     S = ctx.shapes()
@@ -315,6 +377,9 @@ def main():
     }
     if not args.no_trace:
         out["trace_solve"] = trace_solve(ctx, w, Ahat, bhat)
+    if not args.no_diff:
+        ctx.close()
+        out["differentiation"] = differentiation()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
