@@ -306,6 +306,24 @@ def main():
     ctx.profile(False)
     rc, st = ctx.status()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # the same step captured once in a HIP graph and replayed
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        step()
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    del graph
     M = w.n_macro
     value = M / (ms_per_step / 1e3)
     sz = ctx.sz
@@ -368,6 +386,7 @@ def main():
                                f"(assemble + condense + recover)",
                    "n_macro": M, "p": w.p, "N_V": NV, "N_VH": NH, "flux": "ES", "viscous": True},
         "dof_per_s": round(value * (NV + sz["N_Q"]), 1),
+        "graph_ms_per_step": round(graph_ms, 3),
         "status_ok": bool(rc == 0),
         "roofline": roof,
         "condense": {"ms_per_step": round(cond_ms, 3),
