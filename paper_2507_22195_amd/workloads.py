@@ -318,6 +318,22 @@ def tgv_workload(shape=(16, 16, 16), p=2, M0=0.1, Re=1600.0, Pr=0.71, viscous=Tr
                   seed_v, seed_vh, amp, noise_vhat)
 
 
+def mixed_degree_tgv(shape=(16, 16, 16), degrees=(1, 2, 3), seed_p=41, M0=0.1, Re=1600.0, flux="ES",
+                     seed_v=43, seed_vh=44):
+    """Viscous Taylor-Green box whose macro-elements take degrees drawn
+    uniformly (seeded) from ``degrees``.  Returns (p [n_macro], parts) with
+    parts[d] the workload of the macros of degree d (in macro order), each
+    sampled from the box at its own degree."""
+    mesh = box_mesh(shape, (0.0, 0.0, 0.0), (2 * math.pi,) * 3)
+    deg = np.asarray(degrees, dtype=np.int64)
+    p = deg[np.random.default_rng(seed_p).integers(0, deg.size, mesh.n_macro)]
+    parts = {}
+    for d in sorted(set(p.tolist())):
+        w = tgv_workload(shape=shape, p=d, M0=M0, Re=Re, flux=flux, seed_v=seed_v, seed_vh=seed_vh)
+        parts[d] = subset(w, np.nonzero(p == d)[0])
+    return p, parts
+
+
 def workload(config: int, shape=None):
     """The five workloads of the hot-path study, optionally on a smaller box."""
     if config == 1:
