@@ -24,6 +24,8 @@ Two forms of each product:
              [A_hv + A_hq L_v, A_hh + A_hq L_h]],
   the operator a Jacobian-free Newton-Krylov method on the (v, vhat)
   unknowns of Algorithm 1 multiplies by.
+
+``face_bc`` (wall faces) is passed to local.jacobian.
 """
 from __future__ import annotations
 
@@ -32,8 +34,8 @@ import numpy as np
 from . import local
 
 
-def _blocks(p, h, v, vhat, v_old, prm, q=None):
-    return local.jacobian(p, h, v, vhat, v_old, prm, q=q)
+def _blocks(p, h, v, vhat, v_old, prm, q=None, face_bc=None):
+    return local.jacobian(p, h, v, vhat, v_old, prm, q=q, face_bc=face_bc)
 
 
 def reduced_jacobian(J):
@@ -49,13 +51,13 @@ def reduced_jacobian(J):
     return np.stack(out)
 
 
-def jvp(p, h, v, vhat, v_old, prm, dv, dvhat, dq=None, q=None):
+def jvp(p, h, v, vhat, v_old, prm, dv, dvhat, dq=None, q=None, face_bc=None):
     """J x at the state (q, v, vhat); q None means the weak gradient.
 
     With dq given: the full product, returns (JR_q, JR_v, JR_vhat) shaped like
     (q, v, vhat).  With dq None: dq is the weak gradient of (dv, dvhat), so
     JR_q vanishes; returns (zeros, JR_v, JR_vhat) from J_r."""
-    J = _blocks(p, h, v, vhat, v_old, prm, q=q)
+    J = _blocks(p, h, v, vhat, v_old, prm, q=q, face_bc=face_bc)
     M_ = v.shape[0]
     NV, NH = J["A_vv"].shape[1], J["A_hh"].shape[1]
     if dq is None:
@@ -75,14 +77,14 @@ def jvp(p, h, v, vhat, v_old, prm, dv, dvhat, dq=None, q=None):
     return (y[:, :NQ].reshape(dq.shape), y[:, NQ:NQ + NV].reshape(dv.shape), y[:, NQ + NV:].reshape(dvhat.shape))
 
 
-def vjp(p, h, v, vhat, v_old, prm, w_v, w_vhat, w_q=None, q=None, full=False):
+def vjp(p, h, v, vhat, v_old, prm, w_v, w_vhat, w_q=None, q=None, full=False, face_bc=None):
     """J^T w at the state (q, v, vhat); q None means the weak gradient.
 
     full: gradient of w_q.R_Q + w_v.R_V + w_vhat.R_Vhat in (q, v, vhat),
     returns (g_q, g_v, g_vhat).  Reduced (full False, w_q None): gradient of
     w_v.R_V + w_vhat.R_Vhat in (v, vhat) through the weak gradient, returns
     (g_v, g_vhat) from J_r^T."""
-    J = _blocks(p, h, v, vhat, v_old, prm, q=q)
+    J = _blocks(p, h, v, vhat, v_old, prm, q=q, face_bc=face_bc)
     M_ = v.shape[0]
     NV, NH = J["A_vv"].shape[1], J["A_hh"].shape[1]
     if not full:

@@ -82,6 +82,13 @@ class Geometry:
         return out
 
 
+def _walls(face_bc, M_):
+    """[M][6] bool: the faces with the isothermal wall operator."""
+    if face_bc is None:
+        return np.zeros((M_, 6), dtype=bool)
+    return np.asarray(face_bc).reshape(M_, 6) != 0
+
+
 def _comp(x, axis):
     """Split an array into a list of components along ``axis``."""
     return [np.take(x, i, axis=axis) for i in range(x.shape[axis])]
@@ -134,11 +141,16 @@ def residual(p, h, v, vhat, v_old, prm, q=None, face_bc=None, old=None):
     instead of alpha_t (u(v) - u(v_old), phi_a): the stage form of a DIRK
     step, whose old term is a combination of earlier stages (Sec. 5.3).
 
+    ``face_bc`` [M][6] (nonzero: isothermal no-slip wall): on a wall face the
+    trace equations use the boundary operator
+        B = [(Fhat + Ghat)_1, vhat_2, vhat_3, vhat_4, vhat_5 + gamma / T_wall]
+    (no mass flux, zero velocity since vhat_2..4 = beta V, and T = T_wall since
+    vhat_5 = -gamma / T), tested against the trace basis like the flux; the
+    element equations keep Fhat + Ghat.
+
     Returns dict R_q [M][5][3][n], R_v [M][5][n], R_vhat [M][6][5][nf],
     entropy [M], q [M][5][3][n] (the q used).
     """
-    if face_bc is not None and np.any(np.asarray(face_bc) != 0):
-        raise NotImplementedError("wall boundary operator is not part of this oracle path")
     geo = Geometry(p, h)
     t = geo.t
     gamma = prm["gamma"]
@@ -190,6 +202,11 @@ def residual(p, h, v, vhat, v_old, prm, q=None, face_bc=None, old=None):
         for k in range(5):
             R_v[:, k] += (ws * tot[k]) @ t["face_phi"][f]
             R_vh[:, f, k] = (ws * tot[k]) @ t["face_psi"][f]
+        wall = _walls(face_bc, M_)[:, f]
+        if wall.any():
+            for k in range(1, 5):
+                Bk = vhs[:, k] + (gamma / prm["T_wall"] if k == 4 else 0.0)
+                R_vh[wall, f, k] = ((ws * Bk) @ t["face_psi"][f])[wall]
         integrand = ph.entropy_production_integrand(_comp(vhs, 1), _comp(vs, 1), Finv, n, gamma)
         ent += np.sum(ws * integrand, axis=1)
     return dict(R_q=R_q, R_v=R_v, R_vhat=R_vh, entropy=ent, q=q)
@@ -217,9 +234,8 @@ def _assemble(test, coef, trial):
 
 
 def jacobian(p, h, v, vhat, v_old, prm, q=None, face_bc=None):
-    """All Jacobian blocks of the residual at (q, v, vhat), dense per macro."""
-    if face_bc is not None and np.any(np.asarray(face_bc) != 0):
-        raise NotImplementedError("wall boundary operator is not part of this oracle path")
+    """All Jacobian blocks of the residual at (q, v, vhat), dense per macro
+    (``face_bc``: see residual)."""
     geo = Geometry(p, h)
     t = geo.t
     gamma = prm["gamma"]
@@ -295,6 +311,15 @@ def jacobian(p, h, v, vhat, v_old, prm, q=None, face_bc=None):
             dq = ws * ad.jac(Gh)                              # m,s,k,15
             A_vq += _assemble(phi, dq, phi)
             A_hq[:, f] += _assemble(psi, dq, phi)
+        # wall faces: rows 2..5 of the trace equations are vhat_k (+ const)
+        wall = _walls(face_bc, M_)[:, f]
+        if wall.any():
+            A_hv[wall, f, 1:] = 0.0
+            A_hq[wall, f, 1:] = 0.0
+            A_hh[wall, f, 1:] = 0.0
+            Mf = np.einsum("ms,sc,sd->mcd", geo.w_face(f), psi, psi)
+            for k in range(1, 5):
+                A_hh[wall, f, k, :, f, k, :] = Mf[wall]
 
     # constant blocks of R_Q (eq. s32a) ...................................
     Mm = geo.mass()
@@ -330,14 +355,15 @@ def _apply_Aqq_inv(Mm, X):
     return out.reshape(X.shape) if not vec else out.reshape(-1)
 
 
-def condense(p, h, v, vhat, v_old, prm, q=None, want_cond=False, old=None):
+def condense(p, h, v, vhat, v_old, prm, q=None, want_cond=False, old=None, face_bc=None):
     """Residual, blocks and condensed system of each macro.
 
     Returns dict with R_q, R_v, R_vhat, entropy, Ahat [M][NH][NH],
-    bhat [M][NH], and the pieces needed for recovery.  ``old``: see residual.
+    bhat [M][NH], and the pieces needed for recovery.  ``old``, ``face_bc``:
+    see residual.
     """
-    res = residual(p, h, v, vhat, v_old, prm, q=q, old=old)
-    J = jacobian(p, h, v, vhat, v_old, prm, q=res["q"])
+    res = residual(p, h, v, vhat, v_old, prm, q=q, old=old, face_bc=face_bc)
+    J = jacobian(p, h, v, vhat, v_old, prm, q=res["q"], face_bc=face_bc)
     M_ = v.shape[0]
     out = dict(res)
     keys = ["S", "X", "Y", "Ap", "r_v", "r_hat", "Ahat", "bhat"]

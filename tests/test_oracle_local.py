@@ -85,16 +85,16 @@ def test_weak_gradient_reproduces_linear_fields(p):
     assert np.allclose(q, np.broadcast_to(G[None, :, :, None], q.shape), atol=1e-12)
 
 
-def _jac_vs_fd(w, q_noise=1e-3, seed=0):
+def _jac_vs_fd(w, q_noise=1e-3, seed=0, face_bc=None):
     rng = np.random.default_rng(seed)
     geo = local.Geometry(w.p, w.mesh.h)
     q = local.lift_q(geo, w.v, w.vhat) + q_noise * rng.standard_normal((w.n_macro, 5, 3, geo.n))
     prm = dict(w.params)
     prm["alpha_ps"] = 0.0      # the pseudo-time term is Jacobian-only
-    J = local.jacobian(w.p, w.mesh.h, w.v, w.vhat, w.v_old, prm, q=q)
+    J = local.jacobian(w.p, w.mesh.h, w.v, w.vhat, w.v_old, prm, q=q, face_bc=face_bc)
 
     def R(q_, v_, vh_):
-        r = local.residual(w.p, w.mesh.h, v_, vh_, w.v_old, prm, q=q_)
+        r = local.residual(w.p, w.mesh.h, v_, vh_, w.v_old, prm, q=q_, face_bc=face_bc)
         return np.concatenate([r["R_q"].reshape(w.n_macro, -1), r["R_v"].reshape(w.n_macro, -1),
                                r["R_vhat"].reshape(w.n_macro, -1)], axis=1)
 
@@ -128,6 +128,47 @@ def test_jacobian_matches_fd_viscous_kepes_p1():
     _jac_vs_fd(W.subset(w, [0, 13]))
 
 
+def _wall_case():
+    w = W.subset(W.tgv_workload(shape=(3, 3, 3), p=1, M0=0.3, Re=500.0, flux="ES", seed_v=5, seed_vh=6,
+                                amp=3e-2), [0, 13])
+    bc = np.zeros((2, 6), dtype=np.uint8)
+    bc[0, 4] = 1
+    bc[1, [1, 4, 5]] = 1
+    return w, bc
+
+
+def test_jacobian_matches_fd_with_walls():
+    w, bc = _wall_case()
+    _jac_vs_fd(w, face_bc=bc)
+
+
+def test_wall_operator_at_the_wall_state():
+    """Isothermal no-slip wall (boundary operator reading): with the trace of
+    a wall face at rest and at T = T_wall (entropy variables of that state
+    from the input module), trace rows 2..5 vanish there; trace row 1 and the
+    element equations are those of the same face without the wall."""
+    w, bc = _wall_case()
+    prm = dict(w.params, T_wall=1.3)
+    vh = w.vhat.copy()
+    gamma = prm["gamma"]
+    rng = np.random.default_rng(2)
+    for m, f in zip(*np.nonzero(bc)):
+        nf = vh.shape[-1]
+        rho = 1.0 + 0.1 * rng.uniform(size=nf)
+        P = rho * prm["T_wall"] / gamma                    # T = gamma P / rho
+        vh[m, f] = W.entropy_variables(rho, np.zeros((3, nf)), P, gamma)
+    r0 = local.residual(w.p, w.mesh.h, w.v, vh, w.v_old, prm)
+    r1 = local.residual(w.p, w.mesh.h, w.v, vh, w.v_old, prm, face_bc=bc)
+    scale = np.abs(r0["R_vhat"]).max()
+    for m, f in zip(*np.nonzero(bc)):
+        assert np.abs(r1["R_vhat"][m, f, 1:]).max() <= 1e-14 * scale
+        assert np.array_equal(r1["R_vhat"][m, f, 0], r0["R_vhat"][m, f, 0])
+    for key in ("R_v", "R_q", "entropy"):
+        assert np.array_equal(r1[key], r0[key])
+    free = bc == 0
+    assert np.array_equal(r1["R_vhat"][free], r0["R_vhat"][free])
+
+
 def test_pseudo_time_term_is_A0_mass():
     """alpha_ps enters A_vv only, as alpha_ps (A0(v) dv, w)."""
     w = W.subset(W.workload(1), [3])
@@ -148,16 +189,19 @@ def test_pseudo_time_term_is_A0_mass():
 
 
 @pytest.mark.parametrize("cfg,shape,idx", [(1, None, [2]), (2, (4, 4, 4), [7]),
-                                           ("p1", None, [0, 4])])
+                                           ("p1", None, [0, 4]), ("walls", None, None)])
 def test_condensation_equals_unreduced_solve(cfg, shape, idx):
     """Static condensation (R2-R6) vs solving rows 1-2 of eq. (R1) for
     (dQ, dV) directly; row 3 must then equal Ahat dVhat - bhat."""
+    bc = None
     if cfg == "p1":
-        w = W.tgv_workload(shape=(2, 2, 2), p=1, M0=0.3, Re=800.0, flux="KEPES", seed_v=7, seed_vh=8)
+        w = W.subset(W.tgv_workload(shape=(2, 2, 2), p=1, M0=0.3, Re=800.0, flux="KEPES", seed_v=7, seed_vh=8),
+                     idx)
+    elif cfg == "walls":
+        w, bc = _wall_case()
     else:
-        w = W.workload(cfg, shape=shape)
-    w = W.subset(w, idx)
-    c = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params)
+        w = W.subset(W.workload(cfg, shape=shape), idx)
+    c = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, face_bc=bc)
     rng = np.random.default_rng(3)
     dh = rng.standard_normal(w.vhat.shape)
     dv, dq = local.recover(c, dh)
