@@ -239,16 +239,18 @@ def differentiation(reps=5):
 
 def mixed_degree(steps=2):
     """One Newton step's local work on 16^3 viscous Taylor-Green macro-elements
-    whose degrees are drawn uniformly (seeded) from {1, 2, 3}, grouped by degree
-    on three streams (not part of the metric); eager and graph-replayed."""
+    whose degrees are drawn uniformly (seeded) from {1, 2, 3}, 20% of them with
+    an isothermal wall on the -z face, grouped by degree on three streams (not
+    part of the metric); eager and graph-replayed."""
     import torch
     from paper_2507_22195_amd import workloads as W
     from paper_2507_22195_amd.batch import MixedBatch
-    p, parts = W.mixed_degree_tgv(shape=(16, 16, 16), degrees=(1, 2, 3), seed_p=41)
+    p, bc, parts = W.mixed_degree_tgv(shape=(16, 16, 16), degrees=(1, 2, 3), seed_p=41, wall_frac=0.2,
+                                      seed_wall=42)
     h = np.empty((p.size, 3))
     for d, w in parts.items():
         h[np.nonzero(p == d)[0]] = w.mesh.h
-    b = MixedBatch(p, h, parts[1].params)
+    b = MixedBatch(p, h, parts[1].params, face_bc=bc)
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
     rng = np.random.default_rng(1)
     v = dev(b.pack("v", {d: w.v for d, w in parts.items()}))
@@ -282,9 +284,10 @@ def mixed_degree(steps=2):
         NV, NH = ctx.sz["N_V"], ctx.sz["N_VH"]
         flops += c * (2.0 / 3.0 * NV ** 3 + 2.0 * NV ** 2 * NH + 2.0 * NH ** 2 * NV)
     res = {"workload": "viscous TGV 16x16x16 macro-elements of 2x2x2 hexahedra, degree drawn uniformly from "
-                       "{1, 2, 3} (seed 41), ES flux, Re 1600, Mach 0.1, one Newton step (assemble + condense + "
-                       "recover), one stream per degree",
+                       "{1, 2, 3} (seed 41), isothermal wall on the -z face of 20% of them (seed 42), ES flux, "
+                       "Re 1600, Mach 0.1, one Newton step (assemble + condense + recover), one stream per degree",
            "n_macro": b.n_macro, "macros_per_degree": {str(d): c for (d, _, c, _) in b.groups},
+           "wall_faces": int(bc.sum()),
            "status_ok": bool(rc == 0), "ms_per_step": round(eager * 1e3, 2),
            "graph_ms_per_step": round(replay * 1e3, 2),
            "macro_per_s": round(b.n_macro / min(eager, replay), 1),
@@ -305,6 +308,9 @@ def main():
     ap.add_argument("--no-diff", action="store_true", help="skip the JVP / VJP measurement")
     ap.add_argument("--diff-only", action="store_true", help="only the JVP / VJP measurement (profiling)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree measurement")
+    ap.add_argument("--config", type=int, default=2, choices=(2, 5),
+                    help="2: viscous TGV 16^3, p=2, ES (default); 5: viscous TGV 16x16x8, p=3, KEPES, Re 5000, "
+                         "Mach 0.3 (the FP64 path of the precision workload)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="before warm-up, copy a MIB-sized buffer three times (untimed) so that a counter "
                          "run sees a plain copy kernel of known size")
@@ -321,7 +327,7 @@ def main():
     if args.diff_only:
         print(json.dumps({"differentiation": differentiation(reps=args.steps)}), flush=True)
         return
-    w = W.workload(2, shape=tuple(args.shape) if args.shape else None)
+    w = W.workload(args.config, shape=tuple(args.shape) if args.shape else None)
     ctx = mehdg.Context(w.p, w.mesh.h, w.params)
     S = ctx.shapes()
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
@@ -415,6 +421,8 @@ def main():
         roof = {"bound": "mfma" if kind == "mfma" else "alu", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None}
     wl = f"tgv{w.mesh.shape[0]}x{w.mesh.shape[1]}x{w.mesh.shape[2]}_p{w.p}"
+    flux_name = ("EC", "ES", "KEPES")[int(w.params["flux"])]
+    re_, m0 = (1600.0, 0.1) if args.config == 2 else (5000.0, 0.3)
     tb = recorded_traffic(dom, wl)
     # HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated), and the rate it implies
     roof["traffic"] = None if tb is None else round(tb)
@@ -440,9 +448,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"viscous TGV, {w.mesh.shape[0]}x{w.mesh.shape[1]}x{w.mesh.shape[2]} macro-elements "
-                               f"of 2x2x2 p=2 hexahedra, ES flux, Re 1600, Mach 0.1, one Newton step "
-                               f"(assemble + condense + recover)",
-                   "n_macro": M, "p": w.p, "N_V": NV, "N_VH": NH, "flux": "ES", "viscous": True},
+                               f"of 2x2x2 p={w.p} hexahedra, {flux_name} flux, Re {re_:g}, Mach {m0:g}, one Newton "
+                               f"step (assemble + condense + recover)",
+                   "n_macro": M, "p": w.p, "N_V": NV, "N_VH": NH, "flux": flux_name, "viscous": True},
         "dof_per_s": round(value * (NV + sz["N_Q"]), 1),
         "graph_ms_per_step": round(graph_ms, 3),
         "status_ok": bool(rc == 0),

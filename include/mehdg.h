@@ -79,6 +79,7 @@ typedef struct {
     double alpha_t;        /* time term alpha_t (u(v) - u(v_old), w) (eq. C242) */
     double alpha_ps;       /* pseudo-time term alpha_ps (A0 dv, w): Jacobian only */
     double logmean_eps;    /* series branch of the log mean when ((a-b)/(a+b))^2 < eps */
+    double T_wall;         /* wall temperature T = gamma P / rho of isothermal wall faces (> 0 if any) */
     int32_t flux;          /* mehdg_flux */
     int32_t viscous;       /* 0: Euler (G = 0), 1: Navier-Stokes */
 } mehdg_params;
@@ -86,16 +87,18 @@ typedef struct {
 /* Macro-element mesh.  All pointers are host memory, copied at create. */
 typedef struct {
     int64_t n_macro;
-    int32_t p;             /* polynomial degree of the sub-elements, 1..4 */
+    int32_t p;             /* polynomial degree of the sub-elements, 1..3 */
     int32_t pad_;
     const double* h;       /* [n_macro][3] sub-element edge lengths (macro = 2h) */
+    const uint8_t* face_bc;/* [n_macro][6] or NULL: 1 = isothermal no-slip wall, 0 = interior/periodic */
 } mehdg_mesh;
 
 /* Sizes of one macro-element at degree p (n, nf, N_V, N_Q, N_VH). */
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]);
 
 /* Builds the reference tables, copies the mesh and allocates workspaces.
- * Synchronises.  On error *out is NULL. */
+ * Synchronises.  On error *out is NULL.  face_bc entries other than 0 and 1,
+ * or wall faces with T_wall <= 0, are MEHDG_EINVAL. */
 mehdg_err mehdg_create(const mehdg_mesh* mesh, const mehdg_params* prm, mehdg_ctx** out);
 
 mehdg_err mehdg_destroy(mehdg_ctx* ctx);
@@ -104,7 +107,11 @@ mehdg_err mehdg_destroy(mehdg_ctx* ctx);
  * macro-element (the trace residual is this macro's local contribution; the
  * caller sums the two sides of each face), plus the face entropy production
  * sum_s w ([[v]]^T Fhat - [[Psi_n]]) of Thm. (EC_ES) with the inviscid trace
- * flux.  q may be NULL: then q is the weak gradient of (v, vhat), i.e. the
+ * flux.  On a wall face (mesh face_bc = 1) the trace equations take the
+ * boundary operator [(Fhat + Ghat)_1, vhat_2, vhat_3, vhat_4, vhat_5 + gamma/T_wall]
+ * (no mass flux, zero velocity, T = T_wall; a reading: the paper gives no
+ * wall operator) tested against the trace basis; the element equations keep
+ * Fhat + Ghat.  q may be NULL: then q is the weak gradient of (v, vhat), i.e. the
  * solution of R_Q = 0.  With want_blocks = 1 also assembles, per macro, the
  * Jacobian blocks of Sec. 6.2 with Q eliminated (eq. R1-R3): the bordered
  * matrix [[S, -Y, r_V], [X, A', r_hat]] in the context workspace.  With
@@ -222,8 +229,8 @@ int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
  *
  * Builds the face map: face_ids [n_macro][6] (host) gives the global face of
  * every local face; every face in [0, n_faces) must occur exactly twice
- * (periodic or interior faces; wall faces are not part of this path), else
- * MEHDG_EINVAL.  Synchronises. */
+ * (periodic or interior faces), else MEHDG_EINVAL; a context with wall faces
+ * is MEHDG_EINVAL too (not part of this path).  Synchronises. */
 mehdg_err mehdg_trace_setup(mehdg_ctx* ctx, const int64_t* face_ids, int64_t n_faces);
 
 /* F = sum_m P_m^T bhat_m. */

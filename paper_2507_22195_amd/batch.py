@@ -27,9 +27,10 @@ _PER = {
 
 
 class MixedBatch:
-    """p [n_macro] degrees, h [n_macro][3], one parameter set."""
+    """p [n_macro] degrees, h [n_macro][3], one parameter set, face_bc
+    [n_macro][6] wall flags or None."""
 
-    def __init__(self, p, h, params):
+    def __init__(self, p, h, params, face_bc=None):
         p = np.asarray(p, dtype=np.int64)
         h = np.asarray(h, dtype=np.float64)
         if p.ndim != 1 or h.shape != (p.size, 3):
@@ -42,7 +43,8 @@ class MixedBatch:
         for d in sorted(set(p.tolist())):
             cnt = int((p == d).sum())
             idx = self.order[first:first + cnt]
-            self.groups.append((int(d), first, cnt, mehdg.Context(int(d), h[idx], params)))
+            bc = None if face_bc is None else np.asarray(face_bc, dtype=np.uint8)[idx]
+            self.groups.append((int(d), first, cnt, mehdg.Context(int(d), h[idx], params, face_bc=bc)))
             first += cnt
         self._streams = None
 

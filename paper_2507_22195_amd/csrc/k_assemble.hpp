@@ -513,4 +513,39 @@ __global__ void __launch_bounds__(RowCfg<P>::THREADS, 6) k_rows_h(const double* 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Trace rows 2..5 of the wall faces (isothermal no-slip wall: the trace
+// equations there are vhat_k, plus gamma/T_wall for the energy row, tested
+// against the trace basis).  Those rows depend on nothing but vhat of their
+// own face and component, with the face mass matrix
+//   M_f[c][c'] = h_t1 h_t2 M1[c1][c1'] M1[c2][c2']
+// as coefficients; no q dependence, so no lift terms; right-hand side
+// -R_vhat.  One workgroup per (macro, face); written after k_rows_h.
+template <int P>
+__global__ void __launch_bounds__(256) k_wall_rows(const uint8_t* __restrict__ face_bc,
+                                                   const double* __restrict__ R_vh, const double* __restrict__ hs,
+                                                   const Tab1D* __restrict__ tab, double* __restrict__ B) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int n1d = D::n1d, nf = D::nf, NV = D::NV, NH = D::NH, ld = BD::ld;
+    const int64_t m = blockIdx.x / 6;
+    const int f = blockIdx.x % 6;
+    if (!face_bc[m * 6 + f]) return;
+    const double hh = hs[3 * m + face_t1(f)] * hs[3 * m + face_t2(f)];
+    double* Bm = B + m * BD::per_macro;
+    for (int64_t e = threadIdx.x; e < (int64_t)4 * nf * ld; e += blockDim.x) {
+        const int rloc = (int)(e / ld), col = (int)(e % ld);
+        const int k = 1 + rloc / nf, c = rloc % nf;
+        const int blk = NV + (f * 5 + k) * nf;          // this row's own (face, component) columns
+        double val = 0.0;
+        if (col == NV + NH) {
+            val = -R_vh[((m * 6 + f) * 5 + k) * nf + c];
+        } else if (col >= blk && col < blk + nf) {
+            const int cp = col - blk;
+            val = hh * tab->M1[c % n1d][cp % n1d] * tab->M1[c / n1d][cp / n1d];
+        }
+        Bm[(int64_t)(blk + c) * ld + col] = val;
+    }
+}
+
 }  // namespace mehdg

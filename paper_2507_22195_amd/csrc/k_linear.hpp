@@ -46,8 +46,9 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
                                              const double* __restrict__ dq, const double* __restrict__ hs,
                                              const Tab1D* __restrict__ tab, const double* __restrict__ coefV,
                                              const double* __restrict__ coefF, int viscous,
-                                             double* __restrict__ J_q, double* __restrict__ J_v,
-                                             double* __restrict__ J_vh, double* __restrict__ scratch) {
+                                             const uint8_t* __restrict__ face_bc, double* __restrict__ J_q,
+                                             double* __restrict__ J_v, double* __restrict__ J_vh,
+                                             double* __restrict__ scratch) {
     using D = Dims<P>;
     constexpr int n1d = D::n1d, nq1 = D::nq1, n = D::n, nf = D::nf, G = D::G, S = D::S;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -179,7 +180,8 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
         }
     }
     __syncthreads();
-    test_integrands<P>(L, scr, m, J_q, J_v, J_vh);
+    // the wall rows are linear in vhat: no constant term in the derivative
+    test_integrands<P>(L, scr, m, face_bc ? face_bc + m * 6 : nullptr, h, 0.0, J_q, J_v, J_vh);
 }
 
 // VJP.  With g_q given (then w_q too): the gradient of
@@ -191,8 +193,9 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
                                              const double* __restrict__ wvh, const double* __restrict__ hs,
                                              const Tab1D* __restrict__ tab, const double* __restrict__ coefV,
                                              const double* __restrict__ coefF, int viscous,
-                                             double* __restrict__ g_q, double* __restrict__ g_v,
-                                             double* __restrict__ g_vh, double* __restrict__ scratch) {
+                                             const uint8_t* __restrict__ face_bc, double* __restrict__ g_q,
+                                             double* __restrict__ g_v, double* __restrict__ g_vh,
+                                             double* __restrict__ scratch) {
     using D = Dims<P>;
     using VS = VjpScratch<P>;
     constexpr int n1d = D::n1d, nq1 = D::nq1, n = D::n, nf = D::nf, G = D::G, S = D::S;
@@ -287,16 +290,20 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
             }
     }
 
-    // face Gauss points: rho = trace of w_v + w_vhat, tau = trace of the
-    // normal component of w_q; sources for v (fh), vhat (qh) and q (scratch)
+    // face Gauss points: rho = trace of w_v + w_vhat (on a wall face only the
+    // mass row of w_vhat: rows 2..5 there are vhat_k, whose adjoint rw goes
+    // straight to vhat), tau = trace of the normal component of w_q; sources
+    // for v (fh), vhat (qh) and q (scratch)
+    const uint8_t* bcm = face_bc ? face_bc + m * 6 : nullptr;
     for (int idx = tid; idx < 6 * S; idx += blockDim.x) {
         const int f = idx / S, s = idx % S;
         const int d = face_axis(f), t1 = face_t1(f), t2 = face_t2(f);
         const double sg = face_sign(f);
+        const bool wall = bcm && bcm[f];
         const int s1 = s % nq1, s2 = s / nq1;
         const int e1 = s1 / (P + 1), e2 = s2 / (P + 1);
         const int ad = face_side(f) ? (n1d - 1) : 0;
-        double rho[5] = {0, 0, 0, 0, 0}, tau[5] = {0, 0, 0, 0, 0};
+        double rho[5] = {0, 0, 0, 0, 0}, tau[5] = {0, 0, 0, 0, 0}, rw[5] = {0, 0, 0, 0, 0};
         for (int cc = 0; cc <= P; ++cc) {
             const int c2 = e2 * P + cc;
             const double bq2 = L.t.B[s2][c2];
@@ -311,7 +318,10 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
                 const int fc = c1 + n1d * c2;
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    rho[k] += psi * (L.v[k][a] + L.vh[f][k][fc]);
+                    const double wh = psi * L.vh[f][k][fc];
+                    rho[k] += psi * L.v[k][a];
+                    if (wall && k > 0) rw[k] += wh;
+                    else rho[k] += wh;
                     if (full) tau[k] += psi * L.q[3 * k + d][a];
                 }
             }
@@ -327,7 +337,7 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
                 ah += cf[25 + 5 * k + l] * rho[k];
             }
             L.fh[f][l][s] = av;
-            L.qh[f][l][s] = ah - ws * sg * tau[l];
+            L.qh[f][l][s] = ah - ws * sg * tau[l] + ws * rw[l];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 double aq = 0.0;

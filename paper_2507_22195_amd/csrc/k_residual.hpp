@@ -181,9 +181,13 @@ __device__ void lift_gradient(ResLds<P>& L, const double hinv[3]) {
 // Testing of the integrands against the basis functions (phase 4): volume
 // fields of scr (layout above) and face fields fh, qh of the workgroup's LDS
 // -> R_q, R_v, R_vh of macro m.  One thread per node, then per trace node.
-// The same step closes the linearised products (k_linear.hpp).
+// The same step closes the linearised products (k_linear.hpp).  On a wall
+// face (bc[f] != 0) the trace equations 2..5 test the boundary operator
+// vhat_k (+ gT for the energy row) instead of the flux: qh holds
+// ws sg vhat_k, so ws vhat_k = sg qh.
 template <int P>
 __device__ __forceinline__ void test_integrands(const ResLds<P>& L, const double* __restrict__ scr, int64_t m,
+                                                const uint8_t* __restrict__ bc, const double h[3], double gT,
                                                 double* __restrict__ R_q, double* __restrict__ R_v,
                                                 double* __restrict__ R_vh) {
     using D = Dims<P>;
@@ -256,13 +260,26 @@ __device__ __forceinline__ void test_integrands(const ResLds<P>& L, const double
         support_1d<P>(c1, l1, u1);
         support_1d<P>(c2, l2, u2);
         double acc[5] = {0, 0, 0, 0, 0};
-        for (int s2 = l2 * (P + 1); s2 < (u2 + 1) * (P + 1); ++s2)
-            for (int s1 = l1 * (P + 1); s1 < (u1 + 1) * (P + 1); ++s1) {
-                const int s = s1 + nq1 * s2;
-                const double psi = L.t.B[s1][c1] * L.t.B[s2][c2];
+        if (bc && bc[f]) {
+            const double sg = face_sign(f), hh = h[face_t1(f)] * h[face_t2(f)];
+            for (int s2 = l2 * (P + 1); s2 < (u2 + 1) * (P + 1); ++s2)
+                for (int s1 = l1 * (P + 1); s1 < (u1 + 1) * (P + 1); ++s1) {
+                    const int s = s1 + nq1 * s2;
+                    const double psi = L.t.B[s1][c1] * L.t.B[s2][c2];
+                    acc[0] += psi * L.fh[f][0][s];
 #pragma unroll
-                for (int k = 0; k < 5; ++k) acc[k] += psi * L.fh[f][k][s];
-            }
+                    for (int k = 1; k < 5; ++k) acc[k] += psi * sg * L.qh[f][k][s];
+                    acc[4] += psi * hh * L.t.w[s1] * L.t.w[s2] * gT;
+                }
+        } else {
+            for (int s2 = l2 * (P + 1); s2 < (u2 + 1) * (P + 1); ++s2)
+                for (int s1 = l1 * (P + 1); s1 < (u1 + 1) * (P + 1); ++s1) {
+                    const int s = s1 + nq1 * s2;
+                    const double psi = L.t.B[s1][c1] * L.t.B[s2][c2];
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) acc[k] += psi * L.fh[f][k][s];
+                }
+        }
 #pragma unroll
         for (int k = 0; k < 5; ++k) R_vh[((m * 6 + f) * 5 + k) * nf + c] = acc[k];
     }
@@ -276,7 +293,7 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
                                                   double* __restrict__ R_v, double* __restrict__ R_vh,
                                                   double* __restrict__ entropy, double* __restrict__ scratch,
                                                   double* __restrict__ coefV, double* __restrict__ coefF,
-                                                  int32_t* __restrict__ status) {
+                                                  const uint8_t* __restrict__ face_bc, int32_t* __restrict__ status) {
     using D = Dims<P>;
     constexpr int n1d = D::n1d, nq1 = D::nq1, n = D::n, nf = D::nf, G = D::G, S = D::S;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -446,7 +463,7 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
     }
 
     // ---- phase 4: test against the volume and trace basis functions
-    test_integrands<P>(L, scr, m, R_q, R_v, R_vh);
+    test_integrands<P>(L, scr, m, face_bc ? face_bc + m * 6 : nullptr, h, pr.gT, R_q, R_v, R_vh);
     if (bad_phys) record_status(status, m, ST_NONPHYSICAL);
     else if (bad_fin) record_status(status, m, ST_NONFINITE);
 }

@@ -47,6 +47,7 @@ struct mehdg_ctx {
     int64_t prof_calls[MEHDG_NPROF] = {};
     int stage = 0;                  // 0 nothing, 1 blocks assembled, 2 condensed
     bool have_coef = false;         // pointwise coefficients of some state stored (mehdg_jvp / mehdg_vjp)
+    uint8_t* d_bc = nullptr;        // [n_macro][6] wall flags, or nullptr (no wall faces)
     // global trace system (mehdg_trace_*)
     int64_t n_faces = 0;
     int64_t* d_fid = nullptr;       // [n_macro][6] global face of each local face
@@ -149,7 +150,7 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
         Timed t(c, MEHDG_PROF_RESIDUAL, st);
         hipLaunchKernelGGL((k_residual<P, false>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
                            c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, (double*)nullptr, (double*)nullptr,
-                           c->d_status);
+                           (const uint8_t*)c->d_bc, c->d_status);
         return hip_ok(hipGetLastError());
     }
     mehdg_err e = (mode == 1) ? ensure_block_workspace<P>(c) : ensure_coef_workspace<P>(c);
@@ -158,7 +159,8 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     {
         Timed t(c, MEHDG_PROF_RESIDUAL, st);
         hipLaunchKernelGGL((k_residual<P, true>), dim3(M), dim3(256), lds, st, v, vhat, q, v_old, c->d_h, c->dp,
-                           c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, c->d_coefV, c->d_coefF, c->d_status);
+                           c->d_tab, R_q, R_v, R_vhat, ent, c->d_scratch, c->d_coefV, c->d_coefF,
+                           (const uint8_t*)c->d_bc, c->d_status);
     }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     if (mode == 2) return MEHDG_OK;
@@ -180,6 +182,9 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
         hipLaunchKernelGGL(k_rows_h<P>, dim3(xcd_grid(6 * D::nf, c->n_macro)), dim3(RowCfg<P>::THREADS), rlh, st,
                            c->d_coefF, R_vhat, c->d_minvrq, c->d_h, c->d_tab, c->dp.viscous, c->d_B,
                            (int64_t)c->n_macro);
+        if (c->d_bc)
+            hipLaunchKernelGGL(k_wall_rows<P>, dim3((unsigned)(6 * c->n_macro)), dim3(256), 0, st,
+                               (const uint8_t*)c->d_bc, R_vhat, c->d_h, c->d_tab, c->d_B);
     }
     return hip_ok(hipGetLastError());
 }
@@ -375,7 +380,8 @@ mehdg_err launch_jvp(mehdg_ctx* c, const double* dv, const double* dvh, const do
     if (!allow_lds(&k_jvp<P>, lds)) return MEHDG_EHIP;
     Timed t(c, MEHDG_PROF_JVP, st);
     hipLaunchKernelGGL(k_jvp<P>, dim3((unsigned)c->n_macro), dim3(256), lds, st, dv, dvh, dq, c->d_h, c->d_tab,
-                       c->d_coefV, c->d_coefF, c->dp.viscous, J_q, J_v, J_vh, c->d_scratch);
+                       c->d_coefV, c->d_coefF, c->dp.viscous, (const uint8_t*)c->d_bc, J_q, J_v, J_vh,
+                       c->d_scratch);
     return hip_ok(hipGetLastError());
 }
 
@@ -386,7 +392,8 @@ mehdg_err launch_vjp(mehdg_ctx* c, const double* wq, const double* wv, const dou
     if (!allow_lds(&k_vjp<P>, lds)) return MEHDG_EHIP;
     Timed t(c, MEHDG_PROF_VJP, st);
     hipLaunchKernelGGL(k_vjp<P>, dim3((unsigned)c->n_macro), dim3(256), lds, st, wq, wv, wvh, c->d_h, c->d_tab,
-                       c->d_coefV, c->d_coefF, c->dp.viscous, g_q, g_v, g_vh, c->d_scratch);
+                       c->d_coefV, c->d_coefF, c->dp.viscous, (const uint8_t*)c->d_bc, g_q, g_v, g_vh,
+                       c->d_scratch);
     return hip_ok(hipGetLastError());
 }
 
@@ -641,6 +648,7 @@ mehdg_err mehdg_destroy(mehdg_ctx* c) {
     (void)hipFree(c->d_h);
     (void)hipFree(c->d_tab);
     (void)hipFree(c->d_status);
+    (void)hipFree(c->d_bc);
     (void)hipFree(c->d_scratch);
     (void)hipFree(c->d_coefV);
     (void)hipFree(c->d_coefF);
@@ -672,6 +680,14 @@ mehdg_err mehdg_create(const mehdg_mesh* mesh, const mehdg_params* prm, mehdg_ct
     if (mesh->n_macro > (int64_t)0x7fffffff) return MEHDG_EINVAL;
     for (int64_t i = 0; i < 3 * mesh->n_macro; ++i)
         if (!(mesh->h[i] > 0.0)) return MEHDG_EINVAL;
+    bool walls = false;
+    if (mesh->face_bc) {
+        for (int64_t i = 0; i < 6 * mesh->n_macro; ++i) {
+            if (mesh->face_bc[i] > 1) return MEHDG_EINVAL;
+            walls = walls || mesh->face_bc[i] == 1;
+        }
+        if (walls && !(prm->T_wall > 0.0)) return MEHDG_EINVAL;
+    }
     mehdg_ctx* c = new (std::nothrow) mehdg_ctx();
     if (!c) return MEHDG_ENOMEM;
     c->p = mesh->p;
@@ -686,6 +702,7 @@ mehdg_err mehdg_create(const mehdg_mesh* mesh, const mehdg_params* prm, mehdg_ct
     d.alpha_t = prm->alpha_t;
     d.alpha_ps = prm->alpha_ps;
     d.eps = prm->logmean_eps;
+    d.gT = walls ? prm->gamma / prm->T_wall : 0.0;
     d.flux = prm->flux;
     d.viscous = prm->viscous ? 1 : 0;
     if (!build_tables(c->p, c->tab)) {
@@ -699,6 +716,11 @@ mehdg_err mehdg_create(const mehdg_mesh* mesh, const mehdg_params* prm, mehdg_ct
         (e = dev_alloc(c, &c->d_scratch, c->n_macro * res_scratch_doubles(c->p))) != MEHDG_OK) {
         mehdg_destroy(c);
         return e;
+    }
+    if (walls && ((e = dev_alloc(c, &c->d_bc, 6 * c->n_macro)) != MEHDG_OK ||
+                  hipMemcpy(c->d_bc, mesh->face_bc, 6 * c->n_macro, hipMemcpyHostToDevice) != hipSuccess)) {
+        mehdg_destroy(c);
+        return e != MEHDG_OK ? e : MEHDG_EHIP;
     }
     if (hipMemcpy(c->d_h, mesh->h, 3 * c->n_macro * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_tab, &c->tab, sizeof(Tab1D), hipMemcpyHostToDevice) != hipSuccess ||
@@ -867,7 +889,7 @@ int64_t mehdg_workspace_bytes(const mehdg_ctx* c) { return c ? c->bytes : 0; }
 
 
 mehdg_err mehdg_trace_setup(mehdg_ctx* c, const int64_t* face_ids, int64_t n_faces) {
-    if (!c || !face_ids || n_faces <= 0) return MEHDG_EINVAL;
+    if (!c || !face_ids || n_faces <= 0 || c->d_bc) return MEHDG_EINVAL;
     const int64_t M = c->n_macro;
     std::vector<int64_t> side((size_t)n_faces * 4, -1);
     std::vector<int> cnt((size_t)n_faces, 0);

@@ -12,6 +12,7 @@ struct DevParams {
     double gamma, mu, kappa, lam;
     double sv[5];
     double alpha_t, alpha_ps, eps;
+    double gT;             // gamma / T_wall (wall faces)
     int flux, viscous;
 };
 

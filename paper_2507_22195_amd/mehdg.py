@@ -35,13 +35,13 @@ class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("lam", ctypes.c_double), ("sigma_vis", ctypes.c_double * 5),
                 ("alpha_t", ctypes.c_double), ("alpha_ps", ctypes.c_double),
-                ("logmean_eps", ctypes.c_double), ("flux", ctypes.c_int32),
+                ("logmean_eps", ctypes.c_double), ("T_wall", ctypes.c_double), ("flux", ctypes.c_int32),
                 ("viscous", ctypes.c_int32)]
 
 
 class Mesh(ctypes.Structure):
     _fields_ = [("n_macro", ctypes.c_int64), ("p", ctypes.c_int32), ("pad_", ctypes.c_int32),
-                ("h", ctypes.POINTER(ctypes.c_double))]
+                ("h", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8))]
 
 
 _lib = None
@@ -128,6 +128,7 @@ def make_params(prm: dict) -> Params:
     P.alpha_t = prm["alpha_t"]
     P.alpha_ps = prm["alpha_ps"]
     P.logmean_eps = prm["logmean_eps"]
+    P.T_wall = float(prm.get("T_wall", 1.0))
     P.flux = int(prm["flux"])
     P.viscous = int(prm["viscous"])
     return P
@@ -162,7 +163,7 @@ def _ptr(t, shape, name, optional=False):
 class Context:
     """Owner of one library context (tables, mesh sizes, workspaces)."""
 
-    def __init__(self, p: int, h, params: dict):
+    def __init__(self, p: int, h, params: dict, face_bc=None):
         lib = load()
         h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
         if h.ndim != 2 or h.shape[1] != 3:
@@ -170,7 +171,13 @@ class Context:
         self.p = int(p)
         self.n_macro = int(h.shape[0])
         self._h = h
-        mesh = Mesh(self.n_macro, self.p, 0, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        bc_ptr = None
+        if face_bc is not None:
+            self._bc = np.ascontiguousarray(np.asarray(face_bc, dtype=np.uint8))
+            if self._bc.shape != (self.n_macro, 6):
+                raise ValueError("face_bc must be [n_macro][6]")
+            bc_ptr = self._bc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        mesh = Mesh(self.n_macro, self.p, 0, h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bc_ptr)
         self._prm = make_params(params)
         self.params = dict(params)
         handle = ctypes.c_void_p()

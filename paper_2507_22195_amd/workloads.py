@@ -319,19 +319,24 @@ def tgv_workload(shape=(16, 16, 16), p=2, M0=0.1, Re=1600.0, Pr=0.71, viscous=Tr
 
 
 def mixed_degree_tgv(shape=(16, 16, 16), degrees=(1, 2, 3), seed_p=41, M0=0.1, Re=1600.0, flux="ES",
-                     seed_v=43, seed_vh=44):
+                     seed_v=43, seed_vh=44, wall_frac=0.2, seed_wall=42):
     """Viscous Taylor-Green box whose macro-elements take degrees drawn
-    uniformly (seeded) from ``degrees``.  Returns (p [n_macro], parts) with
-    parts[d] the workload of the macros of degree d (in macro order), each
-    sampled from the box at its own degree."""
+    uniformly (seeded) from ``degrees``, with the -z face of a seeded
+    fraction ``wall_frac`` of the macros flagged as an isothermal wall.
+    Returns (p [n_macro], face_bc [n_macro][6], parts) with parts[d] the
+    workload of the macros of degree d (in macro order, face_bc included),
+    each sampled from the box at its own degree."""
     mesh = box_mesh(shape, (0.0, 0.0, 0.0), (2 * math.pi,) * 3)
     deg = np.asarray(degrees, dtype=np.int64)
     p = deg[np.random.default_rng(seed_p).integers(0, deg.size, mesh.n_macro)]
+    face_bc = np.zeros((mesh.n_macro, 6), dtype=np.uint8)
+    face_bc[np.random.default_rng(seed_wall).permutation(mesh.n_macro)[:int(round(wall_frac * mesh.n_macro))], 4] = 1
     parts = {}
     for d in sorted(set(p.tolist())):
         w = tgv_workload(shape=shape, p=d, M0=M0, Re=Re, flux=flux, seed_v=seed_v, seed_vh=seed_vh)
+        w.face_bc = face_bc
         parts[d] = subset(w, np.nonzero(p == d)[0])
-    return p, parts
+    return p, face_bc, parts
 
 
 def workload(config: int, shape=None):

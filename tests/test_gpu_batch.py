@@ -1,6 +1,7 @@
 """Macro-elements of mixed degree in one step (paper_2507_22195_amd.batch).
 
-On a 3x2x2 viscous Taylor-Green box with degrees drawn from {1, 2, 3}: every
+On a 3x2x2 viscous Taylor-Green box with degrees drawn from {1, 2, 3} and
+isothermal walls on the -z face of a third of the macros: every
 output of the batched step (residual, entropy production, Ahat, bhat, dV,
 dQ) equals, bit for bit, what a single-degree context computes for the same
 macros (the same kernels on the same data); one macro of each degree has its
@@ -22,13 +23,13 @@ def test_mixed_degree_batch():
     import torch
     from paper_2507_22195_amd import mehdg
     from paper_2507_22195_amd.batch import MixedBatch
-    p, parts = W.mixed_degree_tgv(shape=(3, 2, 2), degrees=(1, 2, 3), seed_p=41)
-    banner(f"batch: degrees {dict(zip(*np.unique(p, return_counts=True)))}")
+    p, bc, parts = W.mixed_degree_tgv(shape=(3, 2, 2), degrees=(1, 2, 3), seed_p=41, wall_frac=0.34)
+    banner(f"batch: degrees {dict(zip(*np.unique(p, return_counts=True)))}, {int(bc.sum())} wall faces")
     h = np.empty((p.size, 3))
     for d, w in parts.items():
         h[np.nonzero(p == d)[0]] = w.mesh.h
     prm = parts[1].params
-    b = MixedBatch(p, h, prm)
+    b = MixedBatch(p, h, prm, face_bc=bc)
     rng = np.random.default_rng(7)
     dvh_parts = {d: 1e-2 * rng.standard_normal(w.vhat.shape) for d, w in parts.items()}
     v = dev(b.pack("v", {d: w.v for d, w in parts.items()}))
@@ -46,7 +47,7 @@ def test_mixed_degree_batch():
 
     for gi, (d, first, cnt, _) in enumerate(b.groups):
         w = parts[d]
-        ctx = mehdg.Context(d, w.mesh.h, prm)
+        ctx = mehdg.Context(d, w.mesh.h, prm, face_bc=w.face_bc)
         S = ctx.shapes()
         o = {k: empty(S[k]) for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
         ctx.assemble(dev(w.v), dev(w.vhat), None, dev(w.v_old), o["R_q"], o["R_v"], o["R_vhat"], o["entropy"],
@@ -59,7 +60,8 @@ def test_mixed_degree_batch():
         ctx.close()
         ws = W.subset(w, [0])
         e = rel_err(host(b.view(ref["Ahat"], "Ahat", gi))[:1],
-                    local.condense(ws.p, ws.mesh.h, ws.v, ws.vhat, ws.v_old, ws.params)["Ahat"])
+                    local.condense(ws.p, ws.mesh.h, ws.v, ws.vhat, ws.v_old, ws.params,
+                                   face_bc=ws.face_bc)["Ahat"])
         banner(f"  degree {d}: {cnt} macros equal the single-degree context; Ahat vs oracle {e:.1e}")
         assert e < 1e-12
 

@@ -14,7 +14,9 @@ Jacobian entries are ill-conditioned functions of the state, and the
 oracle's own blocks move by ~1e-11 relative under one-ulp input noise at
 p = 3 (ES on the same state: ~1e-15).  Such cases take a block floor measured
 the same way as the r_V floor; the same workload with the ES flux keeps the
-plain 1e-12 bar and pins the degree-3 kernel paths.
+plain 1e-12 bar and pins the degree-3 kernel paths.  Isothermal wall faces
+(the boundary operator of the trace equations) are checked on p = 1 and
+p = 2 meshes with walls on the -z face of a seeded half of the macros.
 """
 import numpy as np
 import pytest
@@ -28,9 +30,9 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def gpu_pipeline(w, dvhat, blocks_of=()):
+def gpu_pipeline(w, dvhat, blocks_of=(), face_bc=None):
     from paper_2507_22195_amd import mehdg
-    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params, face_bc=face_bc)
     S = ctx.shapes()
     R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
     ctx.assemble(dev(w.v), dev(w.vhat), None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=True)
@@ -45,14 +47,14 @@ def gpu_pipeline(w, dvhat, blocks_of=()):
     return out, rc, st
 
 
-def rhs_floor(w, key_scale=10.0, trials=2):
+def rhs_floor(w, key_scale=10.0, trials=2, face_bc=None):
     """Per-macro change of the oracle's r_V = -R_V under one-ulp input noise."""
     rng = np.random.default_rng(7)
-    base = local.residual(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params)["R_v"]
+    base = local.residual(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, face_bc=face_bc)["R_v"]
     worst = np.zeros(w.n_macro)
     for _ in range(trials):
         pert = lambda x: x * (1 + 2.2e-16 * rng.uniform(-1, 1, x.shape))
-        r = local.residual(w.p, w.mesh.h, pert(w.v), pert(w.vhat), w.v_old, w.params)["R_v"]
+        r = local.residual(w.p, w.mesh.h, pert(w.v), pert(w.vhat), w.v_old, w.params, face_bc=face_bc)["R_v"]
         worst = np.maximum(worst, np.linalg.norm((r - base).reshape(w.n_macro, -1), axis=1))
     return key_scale * worst
 
@@ -75,16 +77,17 @@ def block_floor(w, dvhat, trials=2, key_scale=10.0):
     return {k: key_scale * v for k, v in worst.items()}
 
 
-def check(w, sample_blocks=(0,), with_block_floor=False):
-    banner(f"condense {w.name} p={w.p} M={w.n_macro} flux={w.params['flux']} visc={w.params['viscous']}")
+def check(w, sample_blocks=(0,), with_block_floor=False, face_bc=None):
+    banner(f"condense {w.name} p={w.p} M={w.n_macro} flux={w.params['flux']} visc={w.params['viscous']}"
+           f" walls={0 if face_bc is None else int(np.sum(face_bc))}")
     rng = np.random.default_rng(5)
     dvhat = 1e-2 * rng.standard_normal(w.vhat.shape)
-    got, rc, st = gpu_pipeline(w, dvhat, blocks_of=sample_blocks)
+    got, rc, st = gpu_pipeline(w, dvhat, blocks_of=sample_blocks, face_bc=face_bc)
     assert rc == 0 and not st.any(), (rc, st)
-    ref = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params)
+    ref = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, face_bc=face_bc)
     ref_dv, ref_dq = local.recover(ref, dvhat)
     NV, NH = ref["S"].shape[1], ref["Ap"].shape[1]
-    fl = rhs_floor(w)
+    fl = rhs_floor(w, face_bc=face_bc)
     zero = np.zeros(w.n_macro)
     bf = block_floor(w, dvhat) if with_block_floor else {
         k: zero for k in ("S", "Y", "X", "Ap", "Ahat", "bhat", "dv", "dq")}
@@ -142,3 +145,22 @@ def test_condense_p3_viscous_es():
 
 def test_condense_p3_viscous_kepes():
     check(W.workload(5, shape=(2, 1, 1)), sample_blocks=(1,), with_block_floor=True)
+
+
+def _walls(n_macro, seed, frac=0.5):
+    """Wall flags: the -z face of a seeded subset of macros, plus +x on the first."""
+    rng = np.random.default_rng(seed)
+    bc = np.zeros((n_macro, 6), dtype=np.uint8)
+    bc[rng.permutation(n_macro)[:max(1, int(frac * n_macro))], 4] = 1
+    bc[0, 1] = 1
+    return bc
+
+
+def test_condense_walls_p1_viscous_es():
+    w = W.tgv_workload(shape=(3, 2, 1), p=1, M0=0.1, Re=1600.0, flux="ES", seed_v=43, seed_vh=44)
+    check(w, sample_blocks=(0, 3), face_bc=_walls(w.n_macro, 42))
+
+
+def test_condense_walls_p2_viscous_es():
+    w = W.workload(2, shape=(2, 2, 1))
+    check(w, sample_blocks=(0, 2), face_bc=_walls(w.n_macro, 42))

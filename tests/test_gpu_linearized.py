@@ -232,3 +232,34 @@ def test_autograd_function():
     ctx.vjp((2 * R_v).contiguous(), torch.zeros_like(vh), g_v, g_h)
     assert torch.equal(v.grad, g_v) and torch.equal(vh.grad, g_h)
     ctx.close()
+
+
+def test_jvp_vjp_with_walls():
+    """Wall faces (trace rows 2..5 are vhat_k): reduced and full products
+    against the oracle's with the same wall flags."""
+    w = W.tgv_workload(shape=(3, 2, 1), p=2, M0=0.1, Re=1600.0, flux="ES", seed_v=43, seed_vh=44)
+    bc = np.zeros((w.n_macro, 6), dtype=np.uint8)
+    bc[[0, 2, 5], 4] = 1
+    bc[0, 1] = 1
+    banner(f"linearized: walls on {int(bc.sum())} faces, M={w.n_macro}")
+    from paper_2507_22195_amd import mehdg
+    rng = np.random.default_rng(10)
+    dv, dh = rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape)
+    wv, wh = rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape)
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params, face_bc=bc)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+    ctx.assemble(dev(w.v), dev(w.vhat), None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=2)
+    Jq, Jv, Jh = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"])
+    gv, gh = empty(S["v"]), empty(S["vhat"])
+    ctx.jvp(dev(dv), dev(dh), None, Jq, Jv, Jh)
+    ctx.vjp(dev(wv), dev(wh), gv, gh)
+    rv, rh = lin.jvp(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, dv, dh, face_bc=bc)[1:]
+    sv, sh = lin.vjp(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, wv, wh, face_bc=bc)
+    e = dict(jvp_v=rel_err(host(Jv), rv), jvp_vhat=rel_err(host(Jh), rh), vjp_v=rel_err(host(gv), sv),
+             vjp_vhat=rel_err(host(gh), sh))
+    banner("  " + " ".join(f"{k} {v:.1e}" for k, v in e.items()))
+    assert max(e.values()) < TOL, e
+    rc, st = ctx.status()
+    assert rc == 0
+    ctx.close()
