@@ -17,8 +17,8 @@
 // of (v, vhat) (R_Q = 0), a linear map: the JVP lifts the direction, the
 // VJP applies the transposed lift at the end.
 //
-// One workgroup of 256 threads per macro, LDS ResLds<P>, the per-macro
-// residual scratch reused.
+// One workgroup of 256 threads per macro, LDS ResLds<P>, the residual's
+// per-point fields reused (in LDS for p <= 2, see ResScratch).
 #pragma once
 #include "k_residual.hpp"
 
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
         lift_gradient<P>(L, hinv);
     }
     __syncthreads();
-    double* scr = scratch + m * (int64_t)RES_FIELDS * G;
+    double* scr = ResScratch<P>::get(smem_raw, scratch, m);
 
     // volume Gauss points: linearised integrands
     for (int g = tid; g < G; g += blockDim.x) {
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
     const double hinv[3] = {1.0 / h[0], 1.0 / h[1], 1.0 / h[2]};
     const double vol = h[0] * h[1] * h[2];
     __syncthreads();
-    double* scr = scratch + m * (int64_t)RES_FIELDS * G;
+    double* scr = ResScratch<P>::get(smem_raw, scratch, m);
 
     // volume Gauss points: adjoint sources for v (5) and q (15)
     for (int g = tid; g < G; g += blockDim.x) {

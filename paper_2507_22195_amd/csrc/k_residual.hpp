@@ -38,6 +38,21 @@ struct ResLds {
     Tab1D t;
 };
 
+// Where the per-point fields live: in the workgroup's LDS behind ResLds when
+// they fit (p <= 2: RES_FIELDS x G doubles, 86 KB at p = 2), so that the test
+// step reads them at LDS latency; else in the per-macro global scratch.
+template <int P>
+struct ResScratch {
+    static constexpr size_t offset = (sizeof(ResLds<P>) + 15) / 16 * 16;
+    static constexpr size_t bytes = (size_t)RES_FIELDS * Dims<P>::G * sizeof(double);
+    static constexpr bool in_lds = offset + bytes <= 150 * 1024;
+    static constexpr size_t lds_bytes = in_lds ? offset + bytes : sizeof(ResLds<P>);
+    __device__ static double* get(unsigned char* smem, double* scratch, int64_t m) {
+        if constexpr (in_lds) return reinterpret_cast<double*>(smem + offset);
+        else return scratch + m * (int64_t)RES_FIELDS * Dims<P>::G;
+    }
+};
+
 // Pointwise Jacobian coefficients (weights and 1/h of the test derivative
 // folded in).  Per volume Gauss point, COEF_V doubles, each a 5x5 [k][l]:
 //   [0,25)    (alpha_t + alpha_ps) w A0,          A0 = du/dv
@@ -324,7 +339,7 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
     __syncthreads();
 
     bool bad_phys = false, bad_fin = false;
-    double* scr = scratch + m * (int64_t)RES_FIELDS * G;
+    double* scr = ResScratch<P>::get(smem_raw, scratch, m);
 
     // ---- phase 2: volume Gauss points
     for (int g = tid; g < G; g += blockDim.x) {

@@ -93,7 +93,7 @@ int64_t res_scratch_doubles(int p) {
 }
 
 template <int P>
-size_t res_lds() { return sizeof(ResLds<P>); }
+size_t res_lds() { return ResScratch<P>::lds_bytes; }
 
 mehdg_err hip_ok(hipError_t e) { return e == hipSuccess ? MEHDG_OK : MEHDG_EHIP; }
 
