@@ -62,6 +62,7 @@ class JfnkStepper(DirkStepper):
         self.zero_q = torch.zeros(S["R_q"], dtype=torch.float64, device="cuda")
         self.dq_tmp = e("dq")
         self.krylov = []
+        self._basis = None            # Krylov vectors, allocated on the first solve
 
     # vector algebra through the library ------------------------------------
     def _dot(self, a, b):
@@ -98,8 +99,12 @@ class JfnkStepper(DirkStepper):
         if bnorm == 0.0:
             return 0
         its = 0
-        r = _Pair.like(b)
-        w = _Pair.like(b)
+        if self._basis is None:
+            m = self.k_restart
+            self._basis = dict(r=_Pair.like(b), w=_Pair.like(b), V=[_Pair.like(b) for _ in range(m + 1)],
+                               Z=[_Pair.like(b) for _ in range(m)])
+        r, w = self._basis["r"], self._basis["w"]
+        Vb, Zb = self._basis["V"], self._basis["Z"]
         while its < self.k_maxit:
             # r = b - J x
             self._apply_J(x, r)
@@ -108,17 +113,15 @@ class JfnkStepper(DirkStepper):
             if beta <= self.k_rtol * bnorm:
                 break
             m = self.k_restart
-            V = [_Pair.like(b)]
-            Z = []
+            V, Z = Vb, Zb
             self._axpby(1.0 / beta, r, 0.0, V[0])
             H = np.zeros((m + 1, m))
             g = np.zeros(m + 1)
             g[0] = beta
             k = 0
             for k in range(m):
-                z = _Pair.like(b)
+                z = Z[k]
                 self._apply_M(V[k], z)
-                Z.append(z)
                 self._apply_J(z, w)
                 for _ in range(2):                       # classical Gram-Schmidt, twice
                     hs = [self._dot(w, V[i]) for i in range(k + 1)]
@@ -131,7 +134,6 @@ class JfnkStepper(DirkStepper):
                 res = np.linalg.norm(g[:k + 2] - H[:k + 2, :k + 1] @ y)
                 if res <= self.k_rtol * bnorm or H[k + 1, k] == 0.0 or its >= self.k_maxit:
                     break
-                V.append(_Pair.like(b))
                 self._axpby(1.0 / H[k + 1, k], w, 0.0, V[k + 1])
             for i in range(len(y)):
                 self._axpby(float(y[i]), Z[i], 1.0, x)
