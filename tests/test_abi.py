@@ -54,3 +54,26 @@ def test_argument_errors_are_synchronous():
     assert lib.mehdg_condense(None, None, None, None) == 1
     assert lib.mehdg_recover(None, None, None, None, None, None) == 1
     assert lib.mehdg_status(None, None, None) == 1
+    assert lib.mehdg_jvp(None, *([None] * 6), None) == 1
+    assert lib.mehdg_vjp(None, *([None] * 6), None) == 1
+    assert lib.mehdg_condense_rhs(None, None, None, None, None) == 1
+
+
+def test_wall_flags_are_checked_before_any_device_work():
+    """face_bc entries other than 0 / 1, or walls with T_wall <= 0, are EINVAL."""
+    from paper_2507_22195_amd import mehdg
+    if not os.path.exists(mehdg.LIB_PATH):
+        pytest.skip("libmehdg.so not built")
+    lib = mehdg.load()
+    h = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    base = dict(gamma=1.4, mu=0, kappa=0, lam=0, sigma_vis=[0] * 5, alpha_t=0, alpha_ps=0, logmean_eps=1e-4,
+                flux=0, viscous=0)
+    for flags, T_wall in (((0, 0, 0, 0, 2, 0), 1.0), ((0, 0, 0, 0, 1, 0), 0.0), ((0, 0, 0, 0, 1, 0), -1.0)):
+        bc = (ctypes.c_uint8 * 6)(*flags)
+        mesh = mehdg.Mesh(1, 2, 0, ctypes.cast(h, ctypes.POINTER(ctypes.c_double)),
+                          ctypes.cast(bc, ctypes.POINTER(ctypes.c_uint8)))
+        prm = mehdg.make_params(dict(base, T_wall=T_wall))
+        handle = ctypes.c_void_p()
+        assert lib.mehdg_create(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(handle)) == 1, (flags, T_wall)
+        assert handle.value is None
+

@@ -47,3 +47,51 @@ def test_nonphysical_macro_is_flagged_and_poisoned():
     rc2, st2 = ctx.status()
     assert rc2 == 0 and not st2.any()
     ctx.close()
+
+
+def test_call_order_and_argument_errors_of_the_newer_entry_points():
+    """mehdg_jvp / mehdg_vjp before an assemble that stored the coefficients,
+    mehdg_condense_rhs before a condensation: MEHDG_ESTATE; w_q without g_q,
+    an unknown want_blocks, or the trace setup of a context with wall faces:
+    MEHDG_EINVAL.  A flagged macro's JVP outputs are NaN."""
+    from paper_2507_22195_amd import mehdg
+    w = W.subset(W.workload(1), [0, 1, 2])
+    banner("status: call order of jvp / vjp / condense_rhs")
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    e = lambda k: empty(S[k])
+    R_q, R_v, R_vh, ent = e("R_q"), e("R_v"), e("R_vhat"), e("entropy")
+    Jq, Jv, Jh, gv, gh = e("R_q"), e("R_v"), e("R_vhat"), e("v"), e("vhat")
+    x, xh = dev(w.v), dev(w.vhat)
+    with pytest.raises(mehdg.MehdgError) as ei:
+        ctx.jvp(x, xh, None, Jq, Jv, Jh)
+    assert ei.value.code == 4
+    with pytest.raises(mehdg.MehdgError) as ei:
+        ctx.vjp(R_v, R_vh, gv, gh)
+    assert ei.value.code == 4
+    with pytest.raises(mehdg.MehdgError) as ei:
+        ctx.condense_rhs(R_v, None, e("bhat"))
+    assert ei.value.code == 4
+    with pytest.raises(mehdg.MehdgError) as ei:
+        ctx.assemble(x, xh, None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=3)
+    assert ei.value.code == 1
+    # a non-physical macro: its JVP outputs are NaN, the others finite
+    v = w.v.copy()
+    v[1, 4, :] = 0.5
+    ctx.assemble(dev(v), xh, None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=2)
+    ctx.jvp(x, xh, None, Jq, Jv, Jh)
+    with pytest.raises(mehdg.MehdgError) as ei:
+        ctx.vjp(R_v, R_vh, gv, gh, w_q=R_q)              # w_q without g_q
+    assert ei.value.code == 1
+    a = host(Jv)
+    assert np.isnan(a[1]).all() and np.isfinite(a[[0, 2]]).all()
+    rc, st = ctx.status()
+    assert rc == ENONPHYSICAL and st[1] == ENONPHYSICAL
+    ctx.close()
+    bc = np.zeros((w.n_macro, 6), dtype=np.uint8)
+    bc[0, 4] = 1
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params, face_bc=bc)
+    with pytest.raises(mehdg.MehdgError) as ei:
+        ctx.trace_setup(np.zeros((w.n_macro, 6), dtype=np.int64), 1)
+    assert ei.value.code == 1
+    ctx.close()
