@@ -247,7 +247,9 @@ mehdg_err mehdg_trace_gather(mehdg_ctx* ctx, const double* xg, double* xl, mehdg
 /* Block-Jacobi preconditioner of K (Sec. 6.4): inverts every diagonal face
  * block of K (5nf x 5nf: Ahat_m1[f1,f1] + Ahat_m2[f2,f2], plus the cross blocks
  * when both sides are faces of one macro) by Gauss-Jordan elimination with
- * partial pivoting; kept in the context.  p <= 2 (the block lives in LDS). */
+ * partial pivoting; kept in the context.  For p <= 2 the block is eliminated
+ * in LDS; the p = 3 block (245 x 245) in place in the context's workspace
+ * (correct, bandwidth-bound). */
 mehdg_err mehdg_trace_precond_setup(mehdg_ctx* ctx, const double* Ahat, mehdg_stream stream);
 
 /* z = D^-1 r per face with the blocks of the last mehdg_trace_precond_setup. */
@@ -259,7 +261,7 @@ mehdg_err mehdg_trace_precond_apply(mehdg_ctx* ctx, const double* r, double* z, 
  * residual estimate reaches rtol ||F|| or after maxit iterations; *iters and
  * *relres (final true residual / ||F||) on return.  The tiny Hessenberg
  * least-squares problem is solved on the host: synchronises the stream in
- * every iteration.  restart in [1, 60], p <= 2. */
+ * every iteration.  restart in [1, 60]. */
 mehdg_err mehdg_trace_solve(mehdg_ctx* ctx, const double* Ahat, const double* F, double* x, double rtol,
                             int32_t maxit, int32_t restart, int32_t* iters, double* relres,
                             mehdg_stream stream);

@@ -96,16 +96,44 @@ struct BlockInvLds {
     int redi[4];
 };
 
+// Pivot column, pivots and reductions only: the block itself is eliminated in
+// place in the global inverse workspace (blocks too large for LDS, p = 3:
+// 245 x 245).  Every step then sweeps the block through L2; correct, not fast.
+template <int P>
+struct BlockInvSmall {
+    static constexpr int BS = 5 * Dims<P>::nf;
+    double colk[BS];
+    int piv[BS];
+    double redv[4];
+    int redi[4];
+};
+
+template <int P>
+struct BlockInvCfg {
+    static constexpr bool in_lds = sizeof(BlockInvLds<P>) <= 150 * 1024;
+    static constexpr size_t lds_bytes = in_lds ? sizeof(BlockInvLds<P>) : sizeof(BlockInvSmall<P>);
+};
+
+// Inverse of the diagonal face block of K by Gauss-Jordan with row pivoting.
 template <int P>
 __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict__ Ahat,
                                                         const int64_t* __restrict__ side, double* __restrict__ Dinv,
                                                         int64_t n_faces) {
     using D = Dims<P>;
+    using CFG = BlockInvCfg<P>;
     constexpr int BS = 5 * D::nf, NH = D::NH;
+    constexpr int lda = CFG::in_lds ? BS + 1 : BS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    BlockInvLds<P>& L = *reinterpret_cast<BlockInvLds<P>*>(smem_raw);
+    BlockInvLds<P>& LL = *reinterpret_cast<BlockInvLds<P>*>(smem_raw);
+    BlockInvSmall<P>& LS = *reinterpret_cast<BlockInvSmall<P>*>(smem_raw);
+    double* colk = CFG::in_lds ? LL.colk : LS.colk;
+    int* piv = CFG::in_lds ? LL.piv : LS.piv;
+    double* redv = CFG::in_lds ? LL.redv : LS.redv;
+    int* redi = CFG::in_lds ? LL.redi : LS.redi;
     const int64_t g = blockIdx.x;
     if (g >= n_faces) return;
+    double* out = Dinv + g * (int64_t)BS * BS;
+    double* a = CFG::in_lds ? &LL.a[0][0] : out;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t m1 = side[4 * g], f1 = side[4 * g + 1], m2 = side[4 * g + 2], f2 = side[4 * g + 3];
     const double* A1 = Ahat + m1 * (int64_t)NH * NH + (f1 * BS) * (int64_t)NH + f1 * BS;
@@ -119,7 +147,7 @@ __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict
         const int i = e / BS, j = e % BS;
         double d = A1[(int64_t)i * NH + j] + A2[(int64_t)i * NH + j];
         if (same) d += A12[(int64_t)i * NH + j] + A21[(int64_t)i * NH + j];
-        L.a[i][j] = d;
+        a[i * lda + j] = d;
     }
     __syncthreads();
     for (int k = 0; k < BS; ++k) {
@@ -127,7 +155,7 @@ __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict
         double best = -1.0;
         int bi = BS;
         for (int i = k + tid; i < BS; i += blockDim.x) {
-            const double v = fabs(L.a[i][k]);
+            const double v = fabs(a[i * lda + k]);
             if (v > best) {
                 best = v;
                 bi = i;
@@ -138,55 +166,55 @@ __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict
         const int ol = bal ? (__ffsll((long long)bal) - 1) : 0;
         const int wrow = __builtin_amdgcn_readlane(bi, ol);
         if (lane == 0) {
-            L.redv[wave] = wm;
-            L.redi[wave] = bal ? wrow : BS;
+            redv[wave] = wm;
+            redi[wave] = bal ? wrow : BS;
         }
         __syncthreads();
-        int p = L.redi[0];
-        double b = L.redv[0];
+        int p = redi[0];
+        double b = redv[0];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-            if (L.redv[w] > b || (L.redv[w] == b && L.redi[w] < p)) {
-                b = L.redv[w];
-                p = L.redi[w];
+            if (redv[w] > b || (redv[w] == b && redi[w] < p)) {
+                b = redv[w];
+                p = redi[w];
             }
         if (p >= BS) p = k;
-        if (tid == 0) L.piv[k] = p;
+        if (tid == 0) piv[k] = p;
         if (p != k)
             for (int j = tid; j < BS; j += blockDim.x) {
-                const double t = L.a[k][j];
-                L.a[k][j] = L.a[p][j];
-                L.a[p][j] = t;
+                const double t = a[k * lda + j];
+                a[k * lda + j] = a[p * lda + j];
+                a[p * lda + j] = t;
             }
         __syncthreads();
-        const double inv = 1.0 / L.a[k][k];
-        for (int i = tid; i < BS; i += blockDim.x) L.colk[i] = L.a[i][k];
+        const double inv = 1.0 / a[k * lda + k];
+        for (int i = tid; i < BS; i += blockDim.x) colk[i] = a[i * lda + k];
         __syncthreads();
         // row k scaled, a[k][k] <- 1 / pivot
-        for (int j = tid; j < BS; j += blockDim.x) L.a[k][j] = (j == k) ? inv : L.a[k][j] * inv;
+        for (int j = tid; j < BS; j += blockDim.x) a[k * lda + j] = (j == k) ? inv : a[k * lda + j] * inv;
         __syncthreads();
         // every other row: a[i][j] -= a[i][k] a[k][j], with a[i][k] <- -a[i][k] / pivot
         for (int e = tid; e < BS * BS; e += blockDim.x) {
             const int i = e / BS, j = e % BS;
             if (i == k) continue;
-            const double f = L.colk[i];
-            if (j == k) L.a[i][j] = -f * inv;
-            else L.a[i][j] -= f * L.a[k][j];
+            const double f = colk[i];
+            if (j == k) a[i * lda + j] = -f * inv;
+            else a[i * lda + j] -= f * a[k * lda + j];
         }
         __syncthreads();
     }
     // row interchanges of the elimination = column interchanges of the inverse, in reverse
     for (int k = BS - 1; k >= 0; --k) {
-        const int p = L.piv[k];
+        const int p = piv[k];
         if (p != k)
             for (int i = tid; i < BS; i += blockDim.x) {
-                const double t = L.a[i][k];
-                L.a[i][k] = L.a[i][p];
-                L.a[i][p] = t;
+                const double t = a[i * lda + k];
+                a[i * lda + k] = a[i * lda + p];
+                a[i * lda + p] = t;
             }
         __syncthreads();
     }
-    double* out = Dinv + g * (int64_t)BS * BS;
-    for (int e = tid; e < BS * BS; e += blockDim.x) out[e] = L.a[e / BS][e % BS];
+    if constexpr (CFG::in_lds)
+        for (int e = tid; e < BS * BS; e += blockDim.x) out[e] = a[(e / BS) * lda + e % BS];
 }
 
 // z[g] = Dinv_g r[g]

@@ -453,8 +453,7 @@ mehdg_err trace_launch_apply(mehdg_ctx* c, const double* Ahat, const double* x, 
 
 template <int P>
 mehdg_err trace_launch_precond_setup(mehdg_ctx* c, const double* Ahat, hipStream_t st) {
-    const size_t lds = sizeof(BlockInvLds<P>);
-    if (lds > 160 * 1024) return MEHDG_EINVAL;
+    const size_t lds = BlockInvCfg<P>::lds_bytes;
     if (!allow_lds(&k_face_block_inv<P>, lds)) return MEHDG_EHIP;
     hipLaunchKernelGGL(k_face_block_inv<P>, dim3((unsigned)c->n_faces), dim3(256), lds, st, Ahat, c->d_side,
                        c->d_Dinv, c->n_faces);
@@ -967,19 +966,29 @@ mehdg_err mehdg_trace_apply(mehdg_ctx* c, const double* Ahat, const double* x, d
 mehdg_err mehdg_trace_precond_setup(mehdg_ctx* c, const double* Ahat, mehdg_stream stream) {
     mehdg_err e = trace_ready(c);
     if (e != MEHDG_OK) return e;
-    if (!Ahat || c->p > 2) return MEHDG_EINVAL;
+    if (!Ahat) return MEHDG_EINVAL;
     if ((e = ensure_trace_work(c, true)) != MEHDG_OK) return e;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return c->p == 1 ? trace_launch_precond_setup<1>(c, Ahat, st) : trace_launch_precond_setup<2>(c, Ahat, st);
+    switch (c->p) {
+        case 1: return trace_launch_precond_setup<1>(c, Ahat, st);
+        case 2: return trace_launch_precond_setup<2>(c, Ahat, st);
+        case 3: return trace_launch_precond_setup<3>(c, Ahat, st);
+        default: return MEHDG_EINVAL;
+    }
 }
 
 mehdg_err mehdg_trace_precond_apply(mehdg_ctx* c, const double* r, double* z, mehdg_stream stream) {
     mehdg_err e = trace_ready(c);
     if (e != MEHDG_OK) return e;
-    if (!r || !z || c->p > 2) return MEHDG_EINVAL;
+    if (!r || !z) return MEHDG_EINVAL;
     if (!c->d_Dinv) return MEHDG_ESTATE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return c->p == 1 ? trace_launch_precond_apply<1>(c, r, z, st) : trace_launch_precond_apply<2>(c, r, z, st);
+    switch (c->p) {
+        case 1: return trace_launch_precond_apply<1>(c, r, z, st);
+        case 2: return trace_launch_precond_apply<2>(c, r, z, st);
+        case 3: return trace_launch_precond_apply<3>(c, r, z, st);
+        default: return MEHDG_EINVAL;
+    }
 }
 
 mehdg_err mehdg_trace_solve(mehdg_ctx* c, const double* Ahat, const double* F, double* x, double rtol,
@@ -987,12 +996,16 @@ mehdg_err mehdg_trace_solve(mehdg_ctx* c, const double* Ahat, const double* F, d
     mehdg_err e = trace_ready(c);
     if (e != MEHDG_OK) return e;
     if (!Ahat || !F || !x || !iters || !relres || !(rtol > 0.0) || maxit < 0 || restart < 1 ||
-        restart > kMaxRestart || c->p > 2)
+        restart > kMaxRestart)
         return MEHDG_EINVAL;
     if ((e = ensure_trace_work(c, true)) != MEHDG_OK) return e;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    return c->p == 1 ? trace_gmres<1>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st)
-                     : trace_gmres<2>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
+    switch (c->p) {
+        case 1: return trace_gmres<1>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
+        case 2: return trace_gmres<2>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
+        case 3: return trace_gmres<3>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
+        default: return MEHDG_EINVAL;
+    }
 }
 
 

@@ -22,10 +22,12 @@ pytestmark = pytest.mark.gpu
 
 def _cases():
     return [("tgv viscous ES p1", W.tgv_workload(shape=(2, 2, 2), p=1)),
-            ("vortex ES p2", W.vortex_workload(shape=(2, 2, 1), p=2, flux="ES", hi=(10.0, 10.0, 5.0)))]
+            ("vortex ES p2", W.vortex_workload(shape=(2, 2, 1), p=2, flux="ES", hi=(10.0, 10.0, 5.0))),
+            ("tgv viscous ES p3", W.tgv_workload(shape=(2, 1, 1), p=3, M0=0.3, Re=5000.0, flux="ES",
+                                                 seed_v=51, seed_vh=52))]
 
 
-@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("case", [0, 1, 2])
 def test_trace_system_and_newton_update(case):
     from paper_2507_22195_amd import mehdg
     name, w = _cases()[case]
