@@ -16,6 +16,12 @@ Modules
   basis     2x2x2 Q_p macro space, Gauss quadrature, trace space
   physics   u(v), fluxes F, G, the EC / ES / KEPES trace fluxes, entropy
   local     residual, Jacobian blocks, condensation (R1-R6), recovery
+  linearized  Jacobian-vector and vector-Jacobian products of the residual
+  global_solve  the global trace system
+  tet       tetrahedral macro-elements: 8 P_p sub-tetrahedra, simplex
+            quadrature, affine geometry
+  forms     residual, Jacobian and condensation on any macro shape given as
+            quadrature tables (tetrahedral and hexahedral)
 
 Every function is pinned by a CPU test (``tests/test_oracle_*.py``)
 against identities the paper proves, closed forms, finite differences or

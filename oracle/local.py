@@ -364,7 +364,14 @@ def condense(p, h, v, vhat, v_old, prm, q=None, want_cond=False, old=None, face_
     """
     res = residual(p, h, v, vhat, v_old, prm, q=q, old=old, face_bc=face_bc)
     J = jacobian(p, h, v, vhat, v_old, prm, q=res["q"], face_bc=face_bc)
-    M_ = v.shape[0]
+    return condense_blocks(res, J, want_cond=want_cond)
+
+
+def condense_blocks(res, J, want_cond=False):
+    """The condensed system of each macro from its residual ``res`` and its
+    Jacobian blocks ``J`` (any macro shape: the algebra of eq. R3, R5a-b
+    only needs A_qq = I_15 (x) mass)."""
+    M_ = res["R_v"].shape[0]
     out = dict(res)
     keys = ["S", "X", "Y", "Ap", "r_v", "r_hat", "Ahat", "bhat"]
     for kname in keys:

@@ -364,3 +364,161 @@ def subset(w: Workload, idx) -> Workload:
                     np.ascontiguousarray(w.vhat[idx]), np.ascontiguousarray(w.v_old[idx]),
                     np.ascontiguousarray(w.face_bc[idx]),
                     None if w.q is None else np.ascontiguousarray(w.q[idx]))
+
+
+# --------------------------------------------------------------------------
+# tetrahedral macro-elements
+# --------------------------------------------------------------------------
+# Layout of a tetrahedral macro-element of degree p (the degree-2p lattice of
+# its eight P_p sub-tetrahedra, Sec. 3.1):
+#   * vertices X [4][3]; a point with reference coordinates xi (in the unit
+#     tetrahedron (0,0,0), e_x, e_y, e_z) sits at X0 + sum_i xi_i (X_i - X0);
+#   * node a at xi = (i, j, k)/(2p), i + j + k <= 2p, i fastest, then j, k:
+#     n = (2p+1)(2p+2)(2p+3)/6 nodes;
+#   * face f is opposite vertex f, with vertices (P0, P1, P2) the other three
+#     in increasing order; face node c at P0 + (i (P1-P0) + j (P2-P0))/(2p),
+#     i + j <= 2p, i fastest: nf = (2p+1)(2p+2)/2 nodes;
+#   * ``vhat`` [n_macro][4][5][nf].
+
+@dataclasses.dataclass
+class TetMesh:
+    shape: tuple            # cubes per axis
+    lo: np.ndarray
+    hi: np.ndarray
+    X: np.ndarray           # [n_macro][4][3] vertex coordinates
+    vid: np.ndarray         # [n_macro][4] periodic vertex ids
+
+    @property
+    def n_macro(self) -> int:
+        return int(self.X.shape[0])
+
+
+def tet_sizes(p: int) -> dict:
+    m = 2 * p
+    n = (m + 1) * (m + 2) * (m + 3) // 6
+    nf = (m + 1) * (m + 2) // 2
+    return dict(n=n, nf=nf, N_V=5 * n, N_Q=15 * n, N_VH=20 * nf)
+
+
+def _lattice3(m):
+    return np.array([(i, j, k) for k in range(m + 1) for j in range(m + 1 - k)
+                     for i in range(m + 1 - j - k)], dtype=np.int64)
+
+
+def _lattice2(m):
+    return np.array([(i, j) for j in range(m + 1) for i in range(m + 1 - j)], dtype=np.int64)
+
+
+def tet_box_mesh(shape, lo, hi) -> TetMesh:
+    """Periodic box of cubes, each split into the six tetrahedra around its
+    main diagonal (vertices c, c + e_a, c + e_a + e_b, c + (1,1,1) for the
+    six orders (a, b) of the axes); conforming across cubes."""
+    shape = tuple(int(s) for s in shape)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    size = (hi - lo) / np.asarray(shape, dtype=np.float64)
+    nx, ny, nz = shape
+    Xs, ids = [], []
+    E = np.eye(3, dtype=np.int64)
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                c = np.array([i, j, k], dtype=np.int64)
+                for (a, b, _) in perms:
+                    corners = [c, c + E[a], c + E[a] + E[b], c + 1]
+                    Xs.append([lo + size * cc for cc in corners])
+                    ids.append([int(cc[0] % nx + nx * (cc[1] % ny + ny * (cc[2] % nz))) for cc in corners])
+    return TetMesh(shape, lo, hi, np.array(Xs, dtype=np.float64), np.array(ids, dtype=np.int64))
+
+
+def tet_face_vertices(f: int):
+    return tuple(v for v in range(4) if v != f)
+
+
+def tet_node_coords(mesh: TetMesh, p: int) -> np.ndarray:
+    """Physical coordinates [n_macro][3][n] of the macro nodes."""
+    xi = _lattice3(2 * p) / (2.0 * p)                   # [n][3]
+    X = mesh.X
+    E = X[:, 1:] - X[:, :1]                             # [M][3 edges][3]
+    return (X[:, 0, :, None] + np.einsum("ne,mec->mcn", xi, E))
+
+
+def tet_face_node_coords(mesh: TetMesh, p: int) -> np.ndarray:
+    """Physical coordinates [n_macro][4][3][nf] of the trace nodes."""
+    ij = _lattice2(2 * p) / (2.0 * p)
+    out = np.empty((mesh.n_macro, 4, 3, ij.shape[0]))
+    for f in range(4):
+        P0, P1, P2 = tet_face_vertices(f)
+        X = mesh.X
+        out[:, f] = (X[:, P0, :, None] + ij[None, None, :, 0] * (X[:, P1] - X[:, P0])[:, :, None]
+                     + ij[None, None, :, 1] * (X[:, P2] - X[:, P0])[:, :, None])
+    return out
+
+
+def tet_global_faces(mesh: TetMesh, p: int):
+    """(face id [n_macro][4], node id [n_macro][4][nf]): the global macro-face
+    each local face is, and the global index of each of its trace nodes in a
+    numbering shared by both sides of the face.  A trace node is named by its
+    lattice weights on the face's three (periodic) vertex ids, sorted; this
+    naming is one-to-one only with at least three cubes per axis."""
+    if min(mesh.shape) < 3:
+        raise ValueError("periodic face numbering needs at least 3 cubes per axis")
+    m = 2 * p
+    ij = _lattice2(m)
+    keys, fid = {}, np.empty((mesh.n_macro, 4), dtype=np.int64)
+    nodes = np.empty((mesh.n_macro, 4, ij.shape[0]), dtype=np.int64)
+    for t in range(mesh.n_macro):
+        for f in range(4):
+            vs = [int(mesh.vid[t, v]) for v in tet_face_vertices(f)]
+            key = tuple(sorted(vs))
+            fid[t, f] = keys.setdefault(key, len(keys))
+            for c, (i, j) in enumerate(ij):
+                wts = {vs[0]: m - i - j, vs[1]: i, vs[2]: j}
+                w_sorted = [wts[g] for g in key]        # weights on sorted vertices
+                # index of (w1, w2) in the same lattice order
+                a, b = w_sorted[1], w_sorted[2]
+                nodes[t, f, c] = fid[t, f] * ij.shape[0] + int(b * (m + 1) - b * (b - 1) // 2 + a)
+    return fid, nodes
+
+
+@dataclasses.dataclass
+class TetWorkload:
+    name: str
+    p: int
+    mesh: TetMesh
+    params: dict
+    v: np.ndarray            # [n_macro][5][n]
+    vhat: np.ndarray         # [n_macro][4][5][nf]
+    v_old: np.ndarray
+    face_bc: np.ndarray      # [n_macro][4]
+
+    @property
+    def n_macro(self):
+        return self.mesh.n_macro
+
+
+def tet_tgv_workload(shape=(2, 2, 2), p=2, M0=0.1, Re=1600.0, Pr=0.71, viscous=True, flux="ES",
+                     seed_v=61, seed_vh=62, amp=1e-3):
+    """Taylor-Green vortex on the periodic box [0, 2pi]^3 of tetrahedral
+    macro-elements (six per cube, as in the paper's tetrahedral meshes of
+    Sec. 7.2), dt = 0.057 t_c."""
+    gamma = 1.4
+    mesh = tet_box_mesh(shape, (0.0, 0.0, 0.0), (2 * math.pi,) * 3)
+    prm = make_params(gamma=gamma, viscous=viscous, Re=Re, M0=M0, Pr=Pr, dt=0.057 / M0, flux=flux)
+    prim = lambda x: tgv_primitive(x, M0, gamma)
+    v_clean = entropy_variables(*prim(tet_node_coords(mesh, p)), gamma)
+    vhat = entropy_variables(*prim(tet_face_node_coords(mesh, p)), gamma)   # [M][4][5][nf]
+    v = v_clean.copy()
+    if seed_v is not None:
+        v += _noise(np.random.default_rng(seed_v), v.shape, amp)
+    if seed_vh is not None and min(mesh.shape) >= 3:
+        # one noise sample per global trace node, shared by both sides
+        _, nodes = tet_global_faces(mesh, p)
+        table = _noise(np.random.default_rng(seed_vh), (int(nodes.max()) + 1, 5), amp)
+        vhat += table[nodes].transpose(0, 1, 3, 2)
+    elif seed_vh is not None:
+        # boxes too small for the periodic naming: independent noise per side
+        vhat += _noise(np.random.default_rng(seed_vh), vhat.shape, amp)
+    return TetWorkload("tet_tgv", p, mesh, prm, np.ascontiguousarray(v), np.ascontiguousarray(vhat),
+                       np.ascontiguousarray(v_clean), np.zeros((mesh.n_macro, 4), dtype=np.uint8))
