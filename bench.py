@@ -297,6 +297,44 @@ def mixed_degree(steps=2):
     return res
 
 
+def tet_residual(reps=5):
+    """Residual of tetrahedral macro-elements (mehdg_tet_residual) on the
+    paper's viscous Taylor-Green mesh at p = 3: 12^3 cubes of six macro-
+    tetrahedra, eight P_3 sub-tetrahedra each (84 nodes, 28 per face), KEPES
+    flux, Re 1600, Mach 0.1 (not part of the metric).  Timed with HIP events
+    on the launch stream; bytes per macro = inputs (v, v_old, vhat) + outputs
+    (R_Q, R_V, R_Vhat, entropy), each once."""
+    import torch
+    from paper_2507_22195_amd import mehdg
+    from paper_2507_22195_amd import workloads as W
+    w = W.tet_tgv_workload(shape=(12, 12, 12), p=3, M0=0.1, Re=1600.0, flux="KEPES", seed_v=61, seed_vh=62)
+    ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
+    S = ctx.shapes()
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    e = lambda k: torch.empty(S[k], dtype=torch.float64, device="cuda")
+    v, vh, vo = dev(w.v), dev(w.vhat), dev(w.v_old)
+    R_q, R_v, R_vh, ent = e("R_q"), e("R_v"), e("R_vhat"), e("entropy")
+    run = lambda: ctx.residual(v, vh, None, vo, R_q, R_v, R_vh, ent)
+    run()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        run()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    rc, _ = ctx.status()
+    n, nf, M = ctx.sz["n"], ctx.sz["nf"], w.n_macro
+    bytes_per = 8 * (2 * 5 * n + 20 * nf + 15 * n + 5 * n + 20 * nf + 1)
+    ctx.close()
+    return {"workload": "viscous TGV, 12x12x12 cubes of 6 tetrahedral macro-elements of 8 P_3 sub-tetrahedra, "
+                        "KEPES flux, Re 1600, Mach 0.1, residual with the weak gradient",
+            "n_macro": M, "status_ok": bool(rc == 0), "ms": round(ms, 4),
+            "macro_per_s": round(M / (ms / 1e3), 1), "bytes_per_macro": bytes_per,
+            "GBps": round(bytes_per * M / (ms / 1e3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +346,8 @@ def main():
     ap.add_argument("--no-diff", action="store_true", help="skip the JVP / VJP measurement")
     ap.add_argument("--diff-only", action="store_true", help="only the JVP / VJP measurement (profiling)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree measurement")
+    ap.add_argument("--no-tet", action="store_true", help="skip the tetrahedral residual measurement")
+    ap.add_argument("--tet-only", action="store_true", help="only the tetrahedral residual measurement")
     ap.add_argument("--config", type=int, default=2, choices=(2, 5),
                     help="2: viscous TGV 16^3, p=2, ES (default); 5: viscous TGV 16x16x8, p=3, KEPES, Re 5000, "
                          "Mach 0.3 (the FP64 path of the precision workload)")
@@ -316,8 +356,8 @@ def main():
                          "run sees a plain copy kernel of known size")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the per-macro local work shards "
-                                   "by macro-element (see DESIGN.md), --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the per-macro local work would shard by macro-element, "
+                                   "one contiguous range of macros per GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -326,6 +366,9 @@ def main():
 
     if args.diff_only:
         print(json.dumps({"differentiation": differentiation(reps=args.steps)}), flush=True)
+        return
+    if args.tet_only:
+        print(json.dumps({"tet_residual": tet_residual(reps=args.steps)}), flush=True)
         return
     w = W.workload(args.config, shape=tuple(args.shape) if args.shape else None)
     ctx = mehdg.Context(w.p, w.mesh.h, w.params)
@@ -467,6 +510,8 @@ def main():
         out["differentiation"] = differentiation()
     if not args.no_mixed:
         out["mixed_degree"] = mixed_degree()
+    if not args.no_tet:
+        out["tet_residual"] = tet_residual()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -283,6 +283,68 @@ mehdg_err mehdg_axpby(int64_t n, double a, const double* x, double b, double* y,
 mehdg_err mehdg_dot(mehdg_ctx* ctx, int64_t n, const double* x, const double* y, double* out,
                     mehdg_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Tetrahedral macro-elements (Sec. 3.1: K a tetrahedron resolved by eight
+ * P_p sub-tetrahedra, continuous inside K; the paper's own discretisation).
+ *
+ * The submesh is the red refinement of K: four corner tetrahedra at the edge
+ * midpoints and the inner octahedron split along the diagonal joining the
+ * midpoints of reference edges 0-2 and 1-3.  Equispaced Lagrange nodes of
+ * degree p on every sub-tetrahedron make the macro nodes the degree-2p
+ * lattice of K.  Reference tetrahedron (0,0,0), e_x, e_y, e_z; a macro is its
+ * affine image x = X0 + sum_i xi_i (X_i - X0).
+ *   n  = (2p+1)(2p+2)(2p+3)/6, node a at xi = (i,j,k)/(2p), i+j+k <= 2p,
+ *        i fastest, then j, then k;
+ *   nf = (2p+1)(2p+2)/2 per face; face f is opposite vertex f, with vertices
+ *        (P0,P1,P2) the other three in increasing order, node c at
+ *        P0 + (i (P1-P0) + j (P2-P0))/(2p), i+j <= 2p, i fastest;
+ *   v [m][5][n], q [m][5][3][n], vhat [m][4][5][nf];
+ *   N_V = 5n, N_Q = 15n, N_VH = 20 nf.
+ * Quadrature: the collapsed Gauss-Jacobi rule with p+1 points per direction
+ * on every sub-tetrahedron, the matching rule on every face sub-triangle.
+ * ------------------------------------------------------------------------ */
+typedef struct mehdg_tet_ctx mehdg_tet_ctx;
+
+/* Tetrahedral mesh.  Host memory, copied at create. */
+typedef struct {
+    int64_t n_macro;
+    int32_t p;               /* 1..3 */
+    int32_t pad_;
+    const double* X;         /* [n_macro][4][3] vertex coordinates (non-degenerate) */
+    const uint8_t* face_bc;  /* [n_macro][4] or NULL: 1 = isothermal no-slip wall (T_wall > 0 required) */
+} mehdg_tet_mesh;
+
+/* Sizes at degree p (n, nf, N_V, N_Q, N_VH); EINVAL for p outside 1..3. */
+mehdg_err mehdg_tet_sizes(int32_t p, int64_t out[5]);
+
+/* Builds the reference tables (host) and the per-macro geometry (J^-1,
+ * |det J|, outward face normals, face areas).  EINVAL for a bad degree,
+ * parameter set, wall flag or a degenerate macro; ENOMEM if device memory
+ * runs out.  The parameters mean what they mean for mehdg_create. */
+mehdg_err mehdg_tet_create(const mehdg_tet_mesh* mesh, const mehdg_params* params, mehdg_tet_ctx** ctx);
+mehdg_err mehdg_tet_destroy(mehdg_tet_ctx* ctx);
+
+/* Residual of every macro (Sec. 4.1 eq. s32a-c, time term of eq. C242):
+ *   R_Q[k,j,a] = (q_kj, phi_a) + (v_k, d_j phi_a) - <vhat_k, phi_a n_j>,
+ *   R_V[k,a]   = alpha_t (u_k(v) - u_k(v_old), phi_a) - (F_kj + G_kj, d_j phi_a)
+ *                + <Fhat_k + Ghat_k, phi_a>,
+ *   R_Vhat[f,k,c] = <Fhat_k + Ghat_k, psi_c>_f  (wall faces: rows 2..5 are
+ *                <vhat_k (+ gamma/T_wall for k = 5), psi_c>_f, as for mehdg_assemble),
+ * and entropy[m], the face entropy production sum over face points of
+ * w ([[v]]^T Fhat - [[rho V.n]]).  q NULL: q is the weak gradient, the q that
+ * makes R_Q vanish.  Device pointers, layouts above; asynchronous on
+ * ``stream``.  A macro with a non-physical state (beta <= 0, rho or P not
+ * positive) or a non-finite result gets NaN outputs and a status code
+ * (mehdg_tet_status); EINVAL for a NULL argument, EHIP for a launch error. */
+mehdg_err mehdg_tet_residual(mehdg_tet_ctx* ctx, const double* v, const double* vhat, const double* q,
+                             const double* v_old, double* R_q, double* R_v, double* R_vhat,
+                             double* entropy, mehdg_stream stream);
+
+/* Per-macro status of the last mehdg_tet_residual (0, ENONPHYSICAL or
+ * ENONFINITE) into host memory; returns the first non-zero code or OK.
+ * Synchronises the stream. */
+mehdg_err mehdg_tet_status(mehdg_tet_ctx* ctx, int32_t* status, mehdg_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

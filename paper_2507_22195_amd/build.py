@@ -2,8 +2,9 @@
 
     python -m paper_2507_22195_amd.build
 
-The library is one translation unit (``csrc/mehdg_api.hip``) that includes
-every kernel family.  Packed FP32 instructions are disabled for all device
+The library is two translation units: ``csrc/mehdg_api.hip`` (hexahedral
+macro-elements, every kernel family of the step) and ``csrc/mehdg_tet.hip``
+(the tetrahedral residual).  Packed FP32 instructions are disabled for all device
 code.
 """
 from __future__ import annotations
@@ -27,11 +28,11 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(CSRC, "mehdg_api.hip")
+    srcs = [os.path.join(CSRC, "mehdg_api.hip"), os.path.join(CSRC, "mehdg_tet.hip")]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-function", "-o", tmp, src]
+           "-Wall", "-Wno-unused-function", "-o", tmp] + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, cwd=CSRC, capture_output=True, text=True)

@@ -1,0 +1,245 @@
+// Host runtime and C ABI of the tetrahedral macro-element residual
+// (mehdg_tet_*).  A separate translation unit of the same library.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mehdg.h"
+#include "k_tet.hpp"
+#include "tet_tables.hpp"
+
+using namespace mehdg;
+
+struct mehdg_tet_ctx {
+    int p = 0;
+    int64_t n_macro = 0;
+    DevParams dp{};
+    TetTab tab;
+    TetDevTab dt{};
+    double* d_tab = nullptr;       // all double tables
+    int* d_itab = nullptr;         // all int tables
+    double* d_geo = nullptr;       // [n_macro][TET_GEO]
+    uint8_t* d_bc = nullptr;       // [n_macro][4] or nullptr
+    int32_t* d_status = nullptr;   // [n_macro]
+};
+
+namespace {
+
+template <int P>
+size_t tet_lds() { return sizeof(TetLds<P>); }
+
+size_t tet_lds_bytes(int p) { return p == 1 ? tet_lds<1>() : p == 2 ? tet_lds<2>() : tet_lds<3>(); }
+
+template <int P>
+bool tet_allow_lds() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tet_residual<P>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tet_lds<P>()) == hipSuccess;
+}
+
+// J^-1, |det J|, outward normals and twice the areas of one macro; false if degenerate.
+bool tet_geometry(const double* X, double* out) {
+    double J[3][3];
+    for (int d = 0; d < 3; ++d)
+        for (int e = 0; e < 3; ++e) J[d][e] = X[(e + 1) * 3 + d] - X[d];
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (!std::isfinite(det) || std::fabs(det) < 1e-300) return false;
+    double inv[3][3];
+    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) out[i * 3 + j] = inv[i][j];
+    out[9] = std::fabs(det);
+    const int FV[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    for (int f = 0; f < 4; ++f) {
+        const double* P0 = X + 3 * FV[f][0];
+        const double* P1 = X + 3 * FV[f][1];
+        const double* P2 = X + 3 * FV[f][2];
+        const double* Pf = X + 3 * f;
+        double e1[3], e2[3], c[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = P1[d] - P0[d];
+            e2[d] = P2[d] - P0[d];
+        }
+        c[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        c[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        c[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double a = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (!(a > 0.0)) return false;
+        const double out_dir = c[0] * (P0[0] - Pf[0]) + c[1] * (P0[1] - Pf[1]) + c[2] * (P0[2] - Pf[2]);
+        const double sgn = out_dir > 0.0 ? 1.0 : -1.0;
+        for (int d = 0; d < 3; ++d) out[10 + 3 * f + d] = sgn * c[d] / a;
+        out[22 + f] = a;
+    }
+    for (int i = 26; i < TET_GEO; ++i) out[i] = 0.0;
+    return true;
+}
+
+template <typename T>
+bool upload(const std::vector<std::vector<T>*>& parts, T** dev, std::vector<const T*>& ptrs) {
+    size_t total = 0;
+    for (auto* v : parts) total += v->size();
+    std::vector<T> host;
+    host.reserve(total);
+    for (auto* v : parts) host.insert(host.end(), v->begin(), v->end());
+    void* d = nullptr;
+    if (hipMalloc(&d, total * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (hipMemcpy(d, host.data(), total * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return false;
+    }
+    *dev = static_cast<T*>(d);
+    size_t off = 0;
+    for (auto* v : parts) {
+        ptrs.push_back(*dev + off);
+        off += v->size();
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+mehdg_err mehdg_tet_sizes(int32_t p, int64_t out[5]) {
+    if (!out || p < 1 || p > 3) return MEHDG_EINVAL;
+    const int64_t m = 2 * p;
+    out[0] = (m + 1) * (m + 2) * (m + 3) / 6;
+    out[1] = (m + 1) * (m + 2) / 2;
+    out[2] = 5 * out[0];
+    out[3] = 15 * out[0];
+    out[4] = 20 * out[1];
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_tet_destroy(mehdg_tet_ctx* c) {
+    if (!c) return MEHDG_EINVAL;
+    (void)hipFree(c->d_tab);
+    (void)hipFree(c->d_itab);
+    (void)hipFree(c->d_geo);
+    (void)hipFree(c->d_bc);
+    (void)hipFree(c->d_status);
+    delete c;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_tet_create(const mehdg_tet_mesh* mesh, const mehdg_params* prm, mehdg_tet_ctx** out) {
+    if (!out) return MEHDG_EINVAL;
+    *out = nullptr;
+    if (!mesh || !prm || !mesh->X || mesh->n_macro <= 0 || mesh->n_macro > (int64_t)0x7fffffff ||
+        mesh->p < 1 || mesh->p > 3)
+        return MEHDG_EINVAL;
+    if (!(prm->gamma > 1.0) || prm->flux < 0 || prm->flux > 2 || !(prm->logmean_eps >= 0.0)) return MEHDG_EINVAL;
+    bool walls = false;
+    if (mesh->face_bc) {
+        for (int64_t i = 0; i < 4 * mesh->n_macro; ++i) {
+            if (mesh->face_bc[i] > 1) return MEHDG_EINVAL;
+            walls = walls || mesh->face_bc[i] == 1;
+        }
+        if (walls && !(prm->T_wall > 0.0)) return MEHDG_EINVAL;
+    }
+    std::vector<double> geo((size_t)mesh->n_macro * TET_GEO);
+    for (int64_t m = 0; m < mesh->n_macro; ++m)
+        if (!tet_geometry(mesh->X + 12 * m, geo.data() + m * TET_GEO)) return MEHDG_EINVAL;
+    mehdg_tet_ctx* c = new (std::nothrow) mehdg_tet_ctx();
+    if (!c) return MEHDG_ENOMEM;
+    c->p = mesh->p;
+    c->n_macro = mesh->n_macro;
+    DevParams& d = c->dp;
+    d.gamma = prm->gamma;
+    d.mu = prm->viscous ? prm->mu : 0.0;
+    d.kappa = prm->viscous ? prm->kappa : 0.0;
+    d.lam = prm->lam;
+    for (int k = 0; k < 5; ++k) d.sv[k] = prm->viscous ? prm->sigma_vis[k] : 0.0;
+    d.alpha_t = prm->alpha_t;
+    d.alpha_ps = prm->alpha_ps;
+    d.eps = prm->logmean_eps;
+    d.gT = walls ? prm->gamma / prm->T_wall : 0.0;
+    d.flux = prm->flux;
+    d.viscous = prm->viscous ? 1 : 0;
+    if (!build_tet_tables(c->p, c->tab)) {
+        delete c;
+        return MEHDG_EINVAL;
+    }
+    TetTab& t = c->tab;
+    std::vector<const double*> dp;
+    std::vector<const int*> ip;
+    if (!upload<double>({&t.phi, &t.dphi, &t.wv, &t.BiT, &t.psi, &t.wf, &t.Mt, &t.CT, &t.ChT, &t.DT, &t.DhT},
+                        &c->d_tab, dp) ||
+        !upload<int>({&t.vnode, &t.fnode, &t.tnode, &t.vptr, &t.vinc, &t.fptr, &t.finc}, &c->d_itab, ip)) {
+        mehdg_tet_destroy(c);
+        return MEHDG_ENOMEM;
+    }
+    c->dt = TetDevTab{dp[0], dp[1], dp[2], dp[3], dp[4], dp[5], dp[6], dp[7], dp[8], dp[9], dp[10],
+                      ip[0], ip[1], ip[2], ip[3], ip[4], ip[5], ip[6]};
+    const size_t gbytes = geo.size() * sizeof(double);
+    if (hipMalloc(&c->d_geo, gbytes) != hipSuccess ||
+        hipMemcpy(c->d_geo, geo.data(), gbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc(&c->d_status, c->n_macro * sizeof(int32_t)) != hipSuccess ||
+        hipMemset(c->d_status, 0, c->n_macro * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        mehdg_tet_destroy(c);
+        return MEHDG_ENOMEM;
+    }
+    if (walls && (hipMalloc(&c->d_bc, 4 * c->n_macro) != hipSuccess ||
+                  hipMemcpy(c->d_bc, mesh->face_bc, 4 * c->n_macro, hipMemcpyHostToDevice) != hipSuccess)) {
+        (void)hipGetLastError();
+        mehdg_tet_destroy(c);
+        return MEHDG_ENOMEM;
+    }
+    const bool lds_ok = c->p == 1 ? tet_allow_lds<1>() : c->p == 2 ? tet_allow_lds<2>() : tet_allow_lds<3>();
+    if (!lds_ok) {
+        mehdg_tet_destroy(c);
+        return MEHDG_EHIP;
+    }
+    *out = c;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_tet_residual(mehdg_tet_ctx* c, const double* v, const double* vhat, const double* q,
+                             const double* v_old, double* R_q, double* R_v, double* R_vhat, double* entropy,
+                             mehdg_stream stream) {
+    if (!c || !v || !vhat || !v_old || !R_q || !R_v || !R_vhat || !entropy) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)c->n_macro), block(TET_THREADS);
+    const size_t lds = tet_lds_bytes(c->p);
+#define MEHDG_TET_LAUNCH(PP)                                                                                   \
+    hipLaunchKernelGGL(k_tet_residual<PP>, grid, block, lds, st, v, vhat, q, v_old, c->d_geo, c->dt, c->dp,    \
+                       c->d_bc, R_q, R_v, R_vhat, entropy, c->d_status)
+    if (c->p == 1)
+        MEHDG_TET_LAUNCH(1);
+    else if (c->p == 2)
+        MEHDG_TET_LAUNCH(2);
+    else
+        MEHDG_TET_LAUNCH(3);
+#undef MEHDG_TET_LAUNCH
+    return hipGetLastError() == hipSuccess ? MEHDG_OK : MEHDG_EHIP;
+}
+
+mehdg_err mehdg_tet_status(mehdg_tet_ctx* c, int32_t* status, mehdg_stream stream) {
+    if (!c || !status) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(status, c->d_status, c->n_macro * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MEHDG_EHIP;
+    for (int64_t i = 0; i < c->n_macro; ++i)
+        if (status[i] != 0) return static_cast<mehdg_err>(status[i]);
+    return MEHDG_OK;
+}
+
+}  // extern "C"

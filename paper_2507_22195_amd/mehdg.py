@@ -44,6 +44,11 @@ class Mesh(ctypes.Structure):
                 ("h", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8))]
 
 
+class TetMesh(ctypes.Structure):
+    _fields_ = [("n_macro", ctypes.c_int64), ("p", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("X", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8))]
+
+
 _lib = None
 
 
@@ -87,6 +92,14 @@ def load(path: str = LIB_PATH):
     lib.mehdg_vjp.argtypes = [vp] + [vp] * 6 + [vp]
     lib.mehdg_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
     lib.mehdg_dot.argtypes = [vp, i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.mehdg_tet_sizes.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
+    lib.mehdg_tet_create.argtypes = [ctypes.POINTER(TetMesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
+    lib.mehdg_tet_destroy.argtypes = [vp]
+    lib.mehdg_tet_residual.argtypes = [vp] + [vp] * 8 + [vp]
+    lib.mehdg_tet_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    for name in ("mehdg_tet_sizes", "mehdg_tet_create", "mehdg_tet_destroy", "mehdg_tet_residual",
+                 "mehdg_tet_status"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
@@ -379,4 +392,74 @@ class Context:
         out = np.zeros(self.n_macro, dtype=np.int32)
         rc = load().mehdg_status(self._handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                  _stream(stream))
+        return rc, out
+
+
+def tet_sizes(p: int) -> dict:
+    out = (ctypes.c_int64 * 5)()
+    rc = load().mehdg_tet_sizes(p, out)
+    if rc:
+        raise MehdgError(rc, "mehdg_tet_sizes")
+    return dict(n=out[0], nf=out[1], N_V=out[2], N_Q=out[3], N_VH=out[4])
+
+
+class TetContext:
+    """Owner of one context of tetrahedral macro-elements X [n_macro][4][3]
+    (vertex coordinates, host); face_bc [n_macro][4] wall flags or None."""
+
+    def __init__(self, p: int, X, params: dict, face_bc=None):
+        lib = load()
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+        if X.ndim != 3 or X.shape[1:] != (4, 3):
+            raise ValueError("X must be [n_macro][4][3]")
+        self.p = int(p)
+        self.n_macro = int(X.shape[0])
+        self._X = X
+        bc_ptr = None
+        if face_bc is not None:
+            self._bc = np.ascontiguousarray(np.asarray(face_bc, dtype=np.uint8))
+            if self._bc.shape != (self.n_macro, 4):
+                raise ValueError("face_bc must be [n_macro][4]")
+            bc_ptr = self._bc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        mesh = TetMesh(self.n_macro, self.p, 0, X.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bc_ptr)
+        self._prm = make_params(params)
+        self.params = dict(params)
+        handle = ctypes.c_void_p()
+        rc = lib.mehdg_tet_create(ctypes.byref(mesh), ctypes.byref(self._prm), ctypes.byref(handle))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_create")
+        self._handle = handle
+        self.sz = tet_sizes(self.p)
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            load().mehdg_tet_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shapes(self):
+        M, n, nf = self.n_macro, self.sz["n"], self.sz["nf"]
+        return dict(v=(M, 5, n), vhat=(M, 4, 5, nf), q=(M, 5, 3, n), R_q=(M, 5, 3, n), R_v=(M, 5, n),
+                    R_vhat=(M, 4, 5, nf), entropy=(M,))
+
+    def residual(self, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, stream=None):
+        """q None: the weak gradient of (v, vhat)."""
+        S = self.shapes()
+        rc = load().mehdg_tet_residual(
+            self._handle, _ptr(v, S["v"], "v"), _ptr(vhat, S["vhat"], "vhat"),
+            _ptr(q, S["q"], "q", optional=True), _ptr(v_old, S["v"], "v_old"), _ptr(R_q, S["R_q"], "R_q"),
+            _ptr(R_v, S["R_v"], "R_v"), _ptr(R_vhat, S["R_vhat"], "R_vhat"),
+            _ptr(entropy, S["entropy"], "entropy"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_residual")
+
+    def status(self, stream=None):
+        out = np.zeros(self.n_macro, dtype=np.int32)
+        rc = load().mehdg_tet_status(self._handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     _stream(stream))
         return rc, out

@@ -77,3 +77,34 @@ def test_wall_flags_are_checked_before_any_device_work():
         assert lib.mehdg_create(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(handle)) == 1, (flags, T_wall)
         assert handle.value is None
 
+
+
+def test_tet_entry_points_check_arguments_on_the_host():
+    """mehdg_tet_*: sizes of the degree-2p lattice; bad degrees, wall flags and
+    degenerate macros are EINVAL before any device work."""
+    from paper_2507_22195_amd import mehdg
+    if not os.path.exists(mehdg.LIB_PATH):
+        pytest.skip("libmehdg.so not built")
+    lib = mehdg.load()
+    out = (ctypes.c_int64 * 5)()
+    assert lib.mehdg_tet_sizes(0, out) == 1 and lib.mehdg_tet_sizes(4, out) == 1
+    assert lib.mehdg_tet_sizes(3, out) == 0 and list(out) == [84, 28, 420, 1260, 560]
+    assert lib.mehdg_tet_sizes(1, out) == 0 and list(out) == [10, 6, 50, 150, 120]
+    base = dict(gamma=1.4, mu=0, kappa=0, lam=0, sigma_vis=[0] * 5, alpha_t=0, alpha_ps=0, logmean_eps=1e-4,
+                flux=0, viscous=0)
+    good = [0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1]
+    flat = [0, 0, 0, 1, 0, 0, 0, 1, 0, 1, 1, 0]            # fourth vertex in the plane of the others
+    cases = [(good, 0, None, 1.0), (good, 4, None, 1.0), (flat, 2, None, 1.0),
+             (good, 2, (0, 2, 0, 0), 1.0), (good, 2, (0, 1, 0, 0), 0.0)]
+    for X, p, flags, T_wall in cases:
+        xs = (ctypes.c_double * 12)(*X)
+        bc = None if flags is None else ctypes.cast((ctypes.c_uint8 * 4)(*flags), ctypes.POINTER(ctypes.c_uint8))
+        mesh = mehdg.TetMesh(1, p, 0, ctypes.cast(xs, ctypes.POINTER(ctypes.c_double)), bc)
+        prm = mehdg.make_params(dict(base, T_wall=T_wall))
+        handle = ctypes.c_void_p()
+        assert lib.mehdg_tet_create(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(handle)) == 1, (p, flags)
+        assert handle.value is None
+    assert lib.mehdg_tet_create(None, None, None) == 1
+    assert lib.mehdg_tet_residual(None, *([None] * 8), None) == 1
+    assert lib.mehdg_tet_status(None, None, None) == 1
+    assert lib.mehdg_tet_destroy(None) == 1

@@ -1,0 +1,103 @@
+"""GPU residual of tetrahedral macro-elements (mehdg_tet_residual) against
+the oracle (oracle.forms on oracle.tet geometry).
+
+* p = 1, 2, 3 on the Taylor-Green box of Kuhn tetrahedra (12 macros, every
+  flux, viscous and inviscid), per macro normwise relative <= 1e-12 for R_V
+  and R_Vhat; R_Q with q lifted vanishes to round-off, checked against the
+  size of its terms; with q given (seeded), R_Q itself to 1e-12;
+* distorted macros (random affine vertices): general face normals;
+* wall faces (isothermal no-slip) on a seeded set of faces;
+* the entropy production to 1e-12 of the size of the face terms;
+* a macro with a non-physical state gets NaN outputs and ENONPHYSICAL while
+  the others are unaffected.
+"""
+import numpy as np
+import pytest
+
+from oracle import forms, tet
+from paper_2507_22195_amd import workloads as W
+from tests.gpu_util import banner, dev, empty, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _run(w, X, q=None, face_bc=None, prm=None):
+    from paper_2507_22195_amd import mehdg
+    prm = prm or w.params
+    ctx = mehdg.TetContext(w.p, X, prm, face_bc=face_bc)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+    ctx.residual(dev(w.v), dev(w.vhat), None if q is None else dev(q), dev(w.v_old), R_q, R_v, R_vh, ent)
+    rc, st = ctx.status()
+    ctx.close()
+    return rc, st, dict(R_q=host(R_q), R_v=host(R_v), R_vhat=host(R_vh), entropy=host(ent))
+
+
+def _check(w, X, q=None, face_bc=None, prm=None, label=""):
+    prm = prm or w.params
+    banner(f"tet residual {label}: p={w.p} macros={w.n_macro} flux={prm['flux']} viscous={prm['viscous']}")
+    rc, st, got = _run(w, X, q=q, face_bc=face_bc, prm=prm)
+    assert rc == 0, st
+    ref = forms.residual(tet.TetGeometry(w.p, X), w.v, w.vhat, w.v_old, prm, q=q, face_bc=face_bc)
+    errs = dict(R_v=rel_err(got["R_v"], ref["R_v"]), R_vhat=rel_err(got["R_vhat"], ref["R_vhat"]))
+    if q is None:
+        # R_Q vanishes: compare with the size of its terms, |M q|
+        geo = tet.TetGeometry(w.p, X)
+        Mq = np.einsum("mab,mkjb->mkja", forms.mass(geo), ref["q"])
+        errs["R_q"] = float(np.max(np.abs(got["R_q"]) / np.abs(Mq).max()))
+    else:
+        errs["R_q"] = rel_err(got["R_q"], ref["R_q"])
+    escale = np.abs(ref["R_vhat"]).max() * np.abs(w.vhat).max()
+    errs["entropy"] = float(np.max(np.abs(got["entropy"] - ref["entropy"])) / escale)
+    banner(f"  errors {errs}")
+    for k, e in errs.items():
+        assert e <= TOL, (k, e)
+
+
+def _tgv(p, flux="ES", viscous=True, shape=(2, 1, 1), seed=61):
+    return W.tet_tgv_workload(shape=shape, p=p, M0=0.3, Re=500.0, flux=flux, viscous=viscous,
+                              seed_v=seed, seed_vh=seed + 1, amp=1e-2)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_tet_residual_matches_oracle(p):
+    w = _tgv(p)
+    _check(w, w.mesh.X, label="tgv ES viscous")
+
+
+@pytest.mark.parametrize("flux,viscous", [("EC", False), ("ES", False), ("KEPES", True)])
+def test_tet_residual_fluxes(flux, viscous):
+    w = _tgv(2, flux, viscous, seed=71)
+    _check(w, w.mesh.X, label=f"tgv {flux}")
+
+
+def test_tet_residual_given_q_and_distorted_macros():
+    w = _tgv(2, "KEPES", True, seed=81)
+    rng = np.random.default_rng(5)
+    X = w.mesh.X + 0.15 * rng.standard_normal(w.mesh.X.shape)
+    q = 0.1 * rng.standard_normal((w.n_macro, 5, 3, w.v.shape[2]))
+    _check(w, X, q=q, label="distorted, q given")
+    _check(w, X, label="distorted, q lifted")
+
+
+def test_tet_residual_walls():
+    w = _tgv(3, "ES", True, seed=91)
+    rng = np.random.default_rng(7)
+    bc = (rng.random((w.n_macro, 4)) < 0.3).astype(np.uint8)
+    prm = dict(w.params, T_wall=1.05)
+    _check(w, w.mesh.X, face_bc=bc, prm=prm, label="walls")
+
+
+def test_tet_nonphysical_macro_is_flagged():
+    w = _tgv(1)
+    bad = 3
+    w.v[bad, 4, :] = 0.5                     # beta = -v5 < 0 at every point of the macro
+    banner("tet residual: non-physical state in macro 3")
+    rc, st, got = _run(w, w.mesh.X)
+    assert rc == 5 and st[bad] == 5 and np.count_nonzero(st) == 1, st
+    assert np.all(np.isnan(got["R_v"][bad])) and np.all(np.isnan(got["R_vhat"][bad]))
+    ok = [m for m in range(w.n_macro) if m != bad]
+    ref = forms.residual(tet.TetGeometry(1, w.mesh.X[ok]), w.v[ok], w.vhat[ok], w.v_old[ok], w.params)
+    assert rel_err(got["R_v"][ok], ref["R_v"]) <= TOL
