@@ -303,7 +303,8 @@ def tet_residual(reps=5):
     tetrahedra, eight P_3 sub-tetrahedra each (84 nodes, 28 per face), KEPES
     flux, Re 1600, Mach 0.1 (not part of the metric).  Timed with HIP events
     on the launch stream; bytes per macro = inputs (v, v_old, vhat) + outputs
-    (R_Q, R_V, R_Vhat, entropy), each once."""
+    (R_Q, R_V, R_Vhat, entropy), each once.  Then the reduced JVP
+    (mehdg_tet_jvp, dq the weak gradient) in a seeded random direction."""
     import torch
     from paper_2507_22195_amd import mehdg
     from paper_2507_22195_amd import workloads as W
@@ -314,16 +315,24 @@ def tet_residual(reps=5):
     e = lambda k: torch.empty(S[k], dtype=torch.float64, device="cuda")
     v, vh, vo = dev(w.v), dev(w.vhat), dev(w.v_old)
     R_q, R_v, R_vh, ent = e("R_q"), e("R_v"), e("R_vhat"), e("entropy")
-    run = lambda: ctx.residual(v, vh, None, vo, R_q, R_v, R_vh, ent)
-    run()
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        run()
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
+    g = torch.Generator(device="cuda").manual_seed(3)
+    dv = torch.randn(S["v"], dtype=torch.float64, device="cuda", generator=g)
+    dvh = torch.randn(S["vhat"], dtype=torch.float64, device="cuda", generator=g)
+    Jq, Jv, Jh = e("R_q"), e("R_v"), e("R_vhat")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ms = timed(lambda: ctx.residual(v, vh, None, vo, R_q, R_v, R_vh, ent))
+    ms_jvp = timed(lambda: ctx.jvp(v, vh, None, dv, dvh, None, Jq, Jv, Jh))
     rc, _ = ctx.status()
     n, nf, M = ctx.sz["n"], ctx.sz["nf"], w.n_macro
     bytes_per = 8 * (2 * 5 * n + 20 * nf + 15 * n + 5 * n + 20 * nf + 1)
@@ -332,7 +341,8 @@ def tet_residual(reps=5):
                         "KEPES flux, Re 1600, Mach 0.1, residual with the weak gradient",
             "n_macro": M, "status_ok": bool(rc == 0), "ms": round(ms, 4),
             "macro_per_s": round(M / (ms / 1e3), 1), "bytes_per_macro": bytes_per,
-            "GBps": round(bytes_per * M / (ms / 1e3) / 1e9, 1)}
+            "GBps": round(bytes_per * M / (ms / 1e3) / 1e9, 1),
+            "jvp_ms": round(ms_jvp, 4), "jvp_macro_per_s": round(M / (ms_jvp / 1e3), 1)}
 
 
 def main():

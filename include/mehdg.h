@@ -340,7 +340,21 @@ mehdg_err mehdg_tet_residual(mehdg_tet_ctx* ctx, const double* v, const double* 
                              const double* v_old, double* R_q, double* R_v, double* R_vhat,
                              double* entropy, mehdg_stream stream);
 
-/* Per-macro status of the last mehdg_tet_residual (0, ENONPHYSICAL or
+/* Jacobian-vector product of mehdg_tet_residual at the state (q, v, vhat),
+ * with the pseudo-time term alpha_ps (A0 dv, w) added as in the assembled
+ * Jacobian of the hexahedral path (Sec. 6.2 eq. R1):
+ *   [JR_q; JR_v; JR_vhat] = J [dq; dv; dvhat].
+ * q NULL: q is the weak gradient of (v, vhat).  dq NULL: dq is the weak
+ * gradient of (dv, dvhat), the derivative of the residual computed with
+ * q = NULL (JR_q then vanishes up to rounding).  The pointwise physics is
+ * differentiated exactly (dual numbers).  Layouts as for mehdg_tet_residual;
+ * device pointers; asynchronous on ``stream``; flagged macros get NaN
+ * outputs and a status code; EINVAL for a NULL required argument. */
+mehdg_err mehdg_tet_jvp(mehdg_tet_ctx* ctx, const double* v, const double* vhat, const double* q,
+                        const double* dv, const double* dvhat, const double* dq, double* JR_q, double* JR_v,
+                        double* JR_vhat, mehdg_stream stream);
+
+/* Per-macro status of the last mehdg_tet_residual or mehdg_tet_jvp (0, ENONPHYSICAL or
  * ENONFINITE) into host memory; returns the first non-zero code or OK.
  * Synchronises the stream. */
 mehdg_err mehdg_tet_status(mehdg_tet_ctx* ctx, int32_t* status, mehdg_stream stream);

@@ -22,7 +22,16 @@
 // Every integral is a plain weighted sum over the sub-element rules; the
 // tables are constant across macros (L2-resident), the per-macro geometry is
 // J^-1, |det J|, and per face the outward normal and twice the area.
+//
+// The same kernel with LIN = true is the Jacobian-vector product of that
+// residual (with the pseudo-time term alpha_ps (A0 dv, w), as in the
+// assembled Jacobian): phases 1, 3 and 5 are linear and run unchanged on the
+// tangents (dq, dv, dvhat); phases 2 and 4 evaluate the pointwise physics in
+// dual numbers seeded with the interpolated tangents and keep only the
+// tangent parts.
 #pragma once
+#include <type_traits>
+
 #include "physics_n.hpp"
 
 namespace mehdg {
@@ -48,12 +57,14 @@ struct TetDevTab {
     const int *vnode, *fnode, *tnode, *vptr, *vinc, *fptr, *finc;
 };
 
-template <int P>
+template <int P, bool LIN>
 struct TetLds {
     using D = TetDims<P>;
     static constexpr int PT = (20 * D::G > 10 * D::FP) ? 20 * D::G : 10 * D::FP;
     static constexpr int SC = (8 * 5 * D::ns > 2 * 80 * D::nfs) ? 8 * 5 * D::ns : 2 * 80 * D::nfs;
+    static constexpr int NL = LIN ? D::n : 1, NFL = LIN ? D::nf : 1;
     double v[5][D::n], vo[5][D::n], vh[4][5][D::nf], q[15][D::n], rv[5][D::n];
+    double dv[5][NL], dvh[4][5][NFL], dq[15][NL];   // tangents (LIN)
     double pt[PT];
     double sc[SC];
     double red[4];
@@ -61,68 +72,71 @@ struct TetLds {
 
 constexpr int TET_THREADS = 256;
 
-template <int P>
-__global__ void __launch_bounds__(TET_THREADS)
-k_tet_residual(const double* __restrict__ v, const double* __restrict__ vhat, const double* __restrict__ qin,
-               const double* __restrict__ v_old, const double* __restrict__ geo, TetDevTab T, DevParams pr,
-               const uint8_t* __restrict__ face_bc, double* __restrict__ R_q, double* __restrict__ R_v,
-               double* __restrict__ R_vh, double* __restrict__ entropy, int32_t* __restrict__ status) {
-    using D = TetDims<P>;
-    constexpr int n = D::n, nf = D::nf, ns = D::ns, nfs = D::nfs, Gs = D::Gs, Ss = D::Ss;
-    extern __shared__ __align__(16) unsigned char smem[];
-    TetLds<P>& L = *reinterpret_cast<TetLds<P>*>(smem);
-    const int tid = threadIdx.x;
-    const int64_t m = blockIdx.x;
-    const double* gm = geo + m * TET_GEO;
-    double invJ[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) invJ[i] = gm[i];
-    const double adet = gm[9];
-    bool bad_phys = false, bad_fin = false;
+// value / tangent access for the two scalar types of the point phases
+template <typename S>
+struct TetScalar;
+template <>
+struct TetScalar<double> {
+    static MEHDG_HD double mk(double v, double) { return v; }
+    static MEHDG_HD double val(double x) { return x; }
+    static MEHDG_HD double out(double x) { return x; }
+};
+template <>
+struct TetScalar<dual<1>> {
+    static MEHDG_HD dual<1> mk(double v, double d) {
+        dual<1> r;
+        r.v = v;
+        r.d[0] = d;
+        return r;
+    }
+    static MEHDG_HD double val(const dual<1>& x) { return x.v; }
+    static MEHDG_HD double out(const dual<1>& x) { return x.d[0]; }
+};
 
-    // ---- 1. state, weak gradient, R_Q
-    for (int i = tid; i < 5 * n; i += TET_THREADS) {
-        (&L.v[0][0])[i] = v[m * 5 * n + i];
-        (&L.vo[0][0])[i] = v_old[m * 5 * n + i];
-    }
-    for (int i = tid; i < 20 * nf; i += TET_THREADS) (&L.vh[0][0][0])[i] = vhat[m * 20 * nf + i];
-    if (qin)
-        for (int i = tid; i < 15 * n; i += TET_THREADS) (&L.q[0][0])[i] = qin[m * 15 * n + i];
-    __syncthreads();
-    if (!qin) {
-        for (int i = tid; i < 5 * n; i += TET_THREADS) {
-            const int k = i / n, a = i - k * n;
-            double dv[3] = {0.0, 0.0, 0.0};
-            for (int b = 0; b < n; ++b) {
-                const double x = L.v[k][b];
+// q = M^-1 (Chat_j vh - C_j v) from the tables D_i, Dh_f (eq. s32a with R_Q = 0).
+template <int P>
+__device__ void tet_lift(const TetDevTab& T, const double* gm, const double* invJ, double adet,
+                         const double (*V)[TetDims<P>::n], const double (*VH)[5][TetDims<P>::nf],
+                         double (*Q)[TetDims<P>::n]) {
+    constexpr int n = TetDims<P>::n, nf = TetDims<P>::nf;
+    for (int i = threadIdx.x; i < 5 * n; i += TET_THREADS) {
+        const int k = i / n, a = i - k * n;
+        double dv[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < n; ++b) {
+            const double x = V[k][b];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) dv[d] += T.DT[(d * n + b) * n + a] * x;
-            }
-            double qj[3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                qj[j] = -(invJ[0 * 3 + j] * dv[0] + invJ[1 * 3 + j] * dv[1] + invJ[2 * 3 + j] * dv[2]);
-            for (int f = 0; f < 4; ++f) {
-                double dh = 0.0;
-                for (int c = 0; c < nf; ++c) dh += T.DhT[(f * nf + c) * n + a] * L.vh[f][k][c];
-                const double s = gm[22 + f] / adet * dh;
-#pragma unroll
-                for (int j = 0; j < 3; ++j) qj[j] += s * gm[10 + 3 * f + j];
-            }
-#pragma unroll
-            for (int j = 0; j < 3; ++j) L.q[3 * k + j][a] = qj[j];
+            for (int d = 0; d < 3; ++d) dv[d] += T.DT[(d * n + b) * n + a] * x;
         }
-        __syncthreads();
+        double qj[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) qj[j] = -(invJ[0 * 3 + j] * dv[0] + invJ[1 * 3 + j] * dv[1] + invJ[2 * 3 + j] * dv[2]);
+        for (int f = 0; f < 4; ++f) {
+            double dh = 0.0;
+            for (int c = 0; c < nf; ++c) dh += T.DhT[(f * nf + c) * n + a] * VH[f][k][c];
+            const double s = gm[22 + f] / adet * dh;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) qj[j] += s * gm[10 + 3 * f + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Q[3 * k + j][a] = qj[j];
     }
-    for (int i = tid; i < 5 * n; i += TET_THREADS) {
+}
+
+// R_Q = M q + C_j v - Chat_j vh of one macro, to global memory.
+template <int P>
+__device__ void tet_rq(const TetDevTab& T, const double* gm, const double* invJ, double adet,
+                       const double (*V)[TetDims<P>::n], const double (*VH)[5][TetDims<P>::nf],
+                       const double (*Q)[TetDims<P>::n], double* __restrict__ out) {
+    constexpr int n = TetDims<P>::n, nf = TetDims<P>::nf;
+    for (int i = threadIdx.x; i < 5 * n; i += TET_THREADS) {
         const int k = i / n, a = i - k * n;
         double mq[3] = {0.0, 0.0, 0.0}, cv[3] = {0.0, 0.0, 0.0};
         for (int b = 0; b < n; ++b) {
             const double mt = T.Mt[b * n + a];
-            const double x = L.v[k][b];
+            const double x = V[k][b];
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                mq[j] += mt * L.q[3 * k + j][b];
+                mq[j] += mt * Q[3 * k + j][b];
                 cv[j] += T.CT[(j * n + b) * n + a] * x;
             }
         }
@@ -132,54 +146,132 @@ k_tet_residual(const double* __restrict__ v, const double* __restrict__ vhat, co
             r[j] = adet * (mq[j] + invJ[0 * 3 + j] * cv[0] + invJ[1 * 3 + j] * cv[1] + invJ[2 * 3 + j] * cv[2]);
         for (int f = 0; f < 4; ++f) {
             double ch = 0.0;
-            for (int c = 0; c < nf; ++c) ch += T.ChT[(f * nf + c) * n + a] * L.vh[f][k][c];
+            for (int c = 0; c < nf; ++c) ch += T.ChT[(f * nf + c) * n + a] * VH[f][k][c];
 #pragma unroll
             for (int j = 0; j < 3; ++j) r[j] -= gm[22 + f] * gm[10 + 3 * f + j] * ch;
         }
 #pragma unroll
-        for (int j = 0; j < 3; ++j) R_q[((m * 5 + k) * 3 + j) * n + a] = r[j];
+        for (int j = 0; j < 3; ++j) out[(k * 3 + j) * n + a] = r[j];
     }
+}
+
+// LIN false: residual (R_q, R_v, R_vh, entropy) at (q, v, vhat) with q = qin or
+// the weak gradient.  LIN true: the tangents (JR_q, JR_v, JR_vh) in the
+// direction (dq, dv, dvhat), dq = dqin or the weak gradient of (dv, dvhat);
+// entropy is not written and may be null.
+template <int P, bool LIN>
+__global__ void __launch_bounds__(TET_THREADS)
+k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const double* __restrict__ qin,
+      const double* __restrict__ v_old, const double* __restrict__ dvin, const double* __restrict__ dvhin,
+      const double* __restrict__ dqin, const double* __restrict__ geo, TetDevTab T, DevParams pr,
+      const uint8_t* __restrict__ face_bc, double* __restrict__ R_q, double* __restrict__ R_v,
+      double* __restrict__ R_vh, double* __restrict__ entropy, int32_t* __restrict__ status) {
+    using D = TetDims<P>;
+    using S = typename std::conditional<LIN, dual<1>, double>::type;
+    using SC = TetScalar<S>;
+    constexpr int n = D::n, nf = D::nf, ns = D::ns, nfs = D::nfs, Gs = D::Gs, Ss = D::Ss;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TetLds<P, LIN>& L = *reinterpret_cast<TetLds<P, LIN>*>(smem);
+    const int tid = threadIdx.x;
+    const int64_t m = blockIdx.x;
+    const double* gm = geo + m * TET_GEO;
+    double invJ[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) invJ[i] = gm[i];
+    const double adet = gm[9];
+    bool bad_phys = false, bad_fin = false;
+
+    // ---- 1. state, weak gradient, R_Q (tangents: the same linear maps)
+    for (int i = tid; i < 5 * n; i += TET_THREADS) {
+        (&L.v[0][0])[i] = v[m * 5 * n + i];
+        if constexpr (LIN) (&L.dv[0][0])[i] = dvin[m * 5 * n + i];
+        else (&L.vo[0][0])[i] = v_old[m * 5 * n + i];
+    }
+    for (int i = tid; i < 20 * nf; i += TET_THREADS) {
+        (&L.vh[0][0][0])[i] = vhat[m * 20 * nf + i];
+        if constexpr (LIN) (&L.dvh[0][0][0])[i] = dvhin[m * 20 * nf + i];
+    }
+    if (qin)
+        for (int i = tid; i < 15 * n; i += TET_THREADS) (&L.q[0][0])[i] = qin[m * 15 * n + i];
+    if constexpr (LIN) {
+        if (dqin)
+            for (int i = tid; i < 15 * n; i += TET_THREADS) (&L.dq[0][0])[i] = dqin[m * 15 * n + i];
+    }
+    __syncthreads();
+    if (!qin) tet_lift<P>(T, gm, invJ, adet, L.v, L.vh, L.q);
+    if constexpr (LIN) {
+        if (!dqin) tet_lift<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq);
+    }
+    __syncthreads();
+    if constexpr (LIN) tet_rq<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq, R_q + m * 15 * n);
+    else tet_rq<P>(T, gm, invJ, adet, L.v, L.vh, L.q, R_q + m * 15 * n);
 
     // ---- 2. volume points
     const double g = pr.gamma;
     for (int gp = tid; gp < D::G; gp += TET_THREADS) {
         const int s = gp / Gs, gl = gp - s * Gs;
-        double vv[5] = {0, 0, 0, 0, 0}, vvo[5] = {0, 0, 0, 0, 0}, qq[5][3] = {};
+        double vv0[5] = {0, 0, 0, 0, 0}, vvd[5] = {0, 0, 0, 0, 0}, vvo[5] = {0, 0, 0, 0, 0};
+        double qq0[5][3] = {}, qqd[5][3] = {};
         for (int b = 0; b < ns; ++b) {
             const double ph = T.phi[gl * ns + b];
             const int a = T.vnode[s * ns + b];
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                vv[k] += ph * L.v[k][a];
-                vvo[k] += ph * L.vo[k][a];
+                vv0[k] += ph * L.v[k][a];
+                if constexpr (LIN) vvd[k] += ph * L.dv[k][a];
+                else vvo[k] += ph * L.vo[k][a];
 #pragma unroll
-                for (int j = 0; j < 3; ++j) qq[k][j] += ph * L.q[3 * k + j][a];
+                for (int j = 0; j < 3; ++j) {
+                    qq0[k][j] += ph * L.q[3 * k + j][a];
+                    if constexpr (LIN) qqd[k][j] += ph * L.dq[3 * k + j][a];
+                }
             }
         }
-        Prim<double> st, so;
+        S vv[5], qq[5][3];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            vv[k] = SC::mk(vv0[k], vvd[k]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) qq[k][j] = SC::mk(qq0[k][j], qqd[k][j]);
+        }
+        Prim<S> st;
         primitive(vv, g, st);
-        primitive(vvo, g, so);
-        if (!(vv[4] < 0.0) || !(st.rho > 0.0) || !(vvo[4] < 0.0) || !(so.rho > 0.0)) bad_phys = true;
-        double u[5], uo[5];
+        if (!(vv0[4] < 0.0) || !(SC::val(st.rho) > 0.0)) bad_phys = true;
+        S u[5];
         conservative(st, g, u);
-        conservative(so, g, uo);
+        double tt[5];
+        if constexpr (LIN) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) tt[k] = (pr.alpha_t + pr.alpha_ps) * SC::out(u[k]);
+        } else {
+            Prim<double> so;
+            primitive(vvo, g, so);
+            if (!(vvo[4] < 0.0) || !(so.rho > 0.0)) bad_phys = true;
+            double uo[5];
+            conservative(so, g, uo);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) tt[k] = pr.alpha_t * (u[k] - uo[k]);
+        }
         double F[3][5];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            euler_flux(st, g, d, F[d]);
+            S Fs[5];
+            euler_flux(st, g, d, Fs);
             if (pr.viscous) {
-                double Gv[5];
+                S Gv[5];
                 viscous_flux(vv, qq, pr, d, Gv);
 #pragma unroll
-                for (int k = 0; k < 5; ++k) F[d][k] += Gv[k];
+                for (int k = 0; k < 5; ++k) Fs[k] = Fs[k] + Gv[k];
             }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) F[d][k] = SC::out(Fs[k]);
         }
         const double w = T.wv[gl] * adet;
         const double* Bi = T.BiT + s * 9;
         double* o = L.pt + gp * 20;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            o[k] = w * pr.alpha_t * (u[k] - uo[k]);
+            o[k] = w * tt[k];
             double Fx[3];   // sum_j invJ[i][j] F_kj
 #pragma unroll
             for (int i = 0; i < 3; ++i) Fx[i] = invJ[i * 3 + 0] * F[0][k] + invJ[i * 3 + 1] * F[1][k] + invJ[i * 3 + 2] * F[2][k];
@@ -217,54 +309,76 @@ k_tet_residual(const double* __restrict__ v, const double* __restrict__ vhat, co
     double ent = 0.0;
     for (int fp = tid; fp < D::FP; fp += TET_THREADS) {
         const int f = fp / (4 * Ss), r = fp - f * 4 * Ss, tr = r / Ss, sl = r - tr * Ss;
-        double vh[5] = {0, 0, 0, 0, 0}, vs[5] = {0, 0, 0, 0, 0}, qq[5][3] = {};
+        double vh0[5] = {0, 0, 0, 0, 0}, vs0[5] = {0, 0, 0, 0, 0}, qq0[5][3] = {};
+        double vhd[5] = {0, 0, 0, 0, 0}, vsd[5] = {0, 0, 0, 0, 0}, qqd[5][3] = {};
         for (int b = 0; b < nfs; ++b) {
             const double ps = T.psi[sl * nfs + b];
             const int c = T.tnode[tr * nfs + b];
             const int a = T.fnode[f * nf + c];
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                vh[k] += ps * L.vh[f][k][c];
-                vs[k] += ps * L.v[k][a];
+                vh0[k] += ps * L.vh[f][k][c];
+                vs0[k] += ps * L.v[k][a];
+                if constexpr (LIN) {
+                    vhd[k] += ps * L.dvh[f][k][c];
+                    vsd[k] += ps * L.dv[k][a];
+                }
 #pragma unroll
-                for (int j = 0; j < 3; ++j) qq[k][j] += ps * L.q[3 * k + j][a];
+                for (int j = 0; j < 3; ++j) {
+                    qq0[k][j] += ps * L.q[3 * k + j][a];
+                    if constexpr (LIN) qqd[k][j] += ps * L.dq[3 * k + j][a];
+                }
             }
+        }
+        S vh[5], vs[5], qq[5][3];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            vh[k] = SC::mk(vh0[k], vhd[k]);
+            vs[k] = SC::mk(vs0[k], vsd[k]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) qq[k][j] = SC::mk(qq0[k][j], qqd[k][j]);
         }
         const double nrm[3] = {gm[10 + 3 * f], gm[11 + 3 * f], gm[12 + 3 * f]};
         double t1[3], t2[3];
         face_frame(nrm, t1, t2);
         const double ws = T.wf[sl] * gm[22 + f];
-        double Fh[5];
+        S Fh[5];
         trace_flux_n(vh, vs, pr, nrm, t1, t2, Fh);
         {
             Prim<double> a, b;
-            primitive(vh, g, a);
-            primitive(vs, g, b);
-            if (!(vh[4] < 0.0) || !(a.rho > 0.0)) bad_phys = true;
-            double e = 0.0;
+            primitive(vh0, g, a);
+            primitive(vs0, g, b);
+            if (!(vh0[4] < 0.0) || !(a.rho > 0.0)) bad_phys = true;
+            if constexpr (!LIN) {
+                double e = 0.0;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) e += (vh[k] - vs[k]) * Fh[k];
-            e -= a.rho * dot3(a.V, nrm) - b.rho * dot3(b.V, nrm);
-            ent += ws * e;
+                for (int k = 0; k < 5; ++k) e += (vh0[k] - vs0[k]) * Fh[k];
+                e -= a.rho * dot3(a.V, nrm) - b.rho * dot3(b.V, nrm);
+                ent += ws * e;
+            }
         }
         if (pr.viscous) {
-            double Gh[5];
+            S Gh[5];
             viscous_trace_flux_n(vh, vs, qq, pr, nrm, Gh);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) Fh[k] += Gh[k];
+            for (int k = 0; k < 5; ++k) Fh[k] = Fh[k] + Gh[k];
         }
         double* o = L.pt + fp * 10;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            o[k] = ws * Fh[k];
-            o[5 + k] = ws * (vh[k] + (k == 4 ? pr.gT : 0.0));
-            if (!isfinite(Fh[k])) bad_fin = true;
+            o[k] = ws * SC::out(Fh[k]);
+            o[5 + k] = LIN ? ws * vhd[k] : ws * (vh0[k] + (k == 4 ? pr.gT : 0.0));
+            if (!isfinite(o[k])) bad_fin = true;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) ent += __shfl_down(ent, off, 64);
-    if ((tid & 63) == 0) L.red[tid >> 6] = ent;
+    if constexpr (!LIN) {
+        for (int off = 32; off > 0; off >>= 1) ent += __shfl_down(ent, off, 64);
+        if ((tid & 63) == 0) L.red[tid >> 6] = ent;
+    }
     __syncthreads();
-    if (tid == 0) entropy[m] = L.red[0] + L.red[1] + L.red[2] + L.red[3];
+    if constexpr (!LIN) {
+        if (tid == 0) entropy[m] = L.red[0] + L.red[1] + L.red[2] + L.red[3];
+    }
 
     // ---- 5. trace test functions
     constexpr int FS = 80 * nfs;   // (face, sub-triangle, component, node) entries
@@ -308,7 +422,7 @@ k_tet_residual(const double* __restrict__ v, const double* __restrict__ vhat, co
         for (int i = tid; i < 15 * n; i += TET_THREADS) R_q[m * 15 * n + i] = nan;
         for (int i = tid; i < 20 * nf; i += TET_THREADS) R_vh[m * 20 * nf + i] = nan;
         if (tid == 0) {
-            entropy[m] = nan;
+            if (!LIN) entropy[m] = nan;
             if (status) status[m] = any_phys ? 5 : 6;
         }
     } else if (tid == 0 && status) {

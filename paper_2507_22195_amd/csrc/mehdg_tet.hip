@@ -28,15 +28,18 @@ struct mehdg_tet_ctx {
 
 namespace {
 
-template <int P>
-size_t tet_lds() { return sizeof(TetLds<P>); }
+template <int P, bool LIN>
+size_t tet_lds() { return sizeof(TetLds<P, LIN>); }
 
-size_t tet_lds_bytes(int p) { return p == 1 ? tet_lds<1>() : p == 2 ? tet_lds<2>() : tet_lds<3>(); }
+template <bool LIN>
+size_t tet_lds_bytes(int p) { return p == 1 ? tet_lds<1, LIN>() : p == 2 ? tet_lds<2, LIN>() : tet_lds<3, LIN>(); }
 
 template <int P>
 bool tet_allow_lds() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tet_residual<P>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tet_lds<P>()) == hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tet<P, false>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tet_lds<P, false>()) == hipSuccess &&
+           hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tet<P, true>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tet_lds<P, true>()) == hipSuccess;
 }
 
 // J^-1, |det J|, outward normals and twice the areas of one macro; false if degenerate.
@@ -216,10 +219,30 @@ mehdg_err mehdg_tet_residual(mehdg_tet_ctx* c, const double* v, const double* vh
     if (!c || !v || !vhat || !v_old || !R_q || !R_v || !R_vhat || !entropy) return MEHDG_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const dim3 grid((unsigned)c->n_macro), block(TET_THREADS);
-    const size_t lds = tet_lds_bytes(c->p);
+    const size_t lds = tet_lds_bytes<false>(c->p);
 #define MEHDG_TET_LAUNCH(PP)                                                                                   \
-    hipLaunchKernelGGL(k_tet_residual<PP>, grid, block, lds, st, v, vhat, q, v_old, c->d_geo, c->dt, c->dp,    \
-                       c->d_bc, R_q, R_v, R_vhat, entropy, c->d_status)
+    hipLaunchKernelGGL((k_tet<PP, false>), grid, block, lds, st, v, vhat, q, v_old, nullptr, nullptr, nullptr, \
+                       c->d_geo, c->dt, c->dp, c->d_bc, R_q, R_v, R_vhat, entropy, c->d_status)
+    if (c->p == 1)
+        MEHDG_TET_LAUNCH(1);
+    else if (c->p == 2)
+        MEHDG_TET_LAUNCH(2);
+    else
+        MEHDG_TET_LAUNCH(3);
+#undef MEHDG_TET_LAUNCH
+    return hipGetLastError() == hipSuccess ? MEHDG_OK : MEHDG_EHIP;
+}
+
+mehdg_err mehdg_tet_jvp(mehdg_tet_ctx* c, const double* v, const double* vhat, const double* q, const double* dv,
+                        const double* dvhat, const double* dq, double* JR_q, double* JR_v, double* JR_vhat,
+                        mehdg_stream stream) {
+    if (!c || !v || !vhat || !dv || !dvhat || !JR_q || !JR_v || !JR_vhat) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)c->n_macro), block(TET_THREADS);
+    const size_t lds = tet_lds_bytes<true>(c->p);
+#define MEHDG_TET_LAUNCH(PP)                                                                                  \
+    hipLaunchKernelGGL((k_tet<PP, true>), grid, block, lds, st, v, vhat, q, nullptr, dv, dvhat, dq, c->d_geo, \
+                       c->dt, c->dp, c->d_bc, JR_q, JR_v, JR_vhat, nullptr, c->d_status)
     if (c->p == 1)
         MEHDG_TET_LAUNCH(1);
     else if (c->p == 2)

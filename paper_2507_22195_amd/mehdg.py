@@ -97,8 +97,9 @@ def load(path: str = LIB_PATH):
     lib.mehdg_tet_destroy.argtypes = [vp]
     lib.mehdg_tet_residual.argtypes = [vp] + [vp] * 8 + [vp]
     lib.mehdg_tet_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    lib.mehdg_tet_jvp.argtypes = [vp] + [vp] * 9 + [vp]
     for name in ("mehdg_tet_sizes", "mehdg_tet_create", "mehdg_tet_destroy", "mehdg_tet_residual",
-                 "mehdg_tet_status"):
+                 "mehdg_tet_status", "mehdg_tet_jvp"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
@@ -457,6 +458,17 @@ class TetContext:
             _ptr(entropy, S["entropy"], "entropy"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_tet_residual")
+
+    def jvp(self, v, vhat, q, dv, dvhat, dq, JR_q, JR_v, JR_vhat, stream=None):
+        """J [dq; dv; dvhat] at (q, v, vhat); q / dq None: the weak gradients."""
+        S = self.shapes()
+        rc = load().mehdg_tet_jvp(
+            self._handle, _ptr(v, S["v"], "v"), _ptr(vhat, S["vhat"], "vhat"), _ptr(q, S["q"], "q", optional=True),
+            _ptr(dv, S["v"], "dv"), _ptr(dvhat, S["vhat"], "dvhat"), _ptr(dq, S["q"], "dq", optional=True),
+            _ptr(JR_q, S["R_q"], "JR_q"), _ptr(JR_v, S["R_v"], "JR_v"), _ptr(JR_vhat, S["R_vhat"], "JR_vhat"),
+            _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_jvp")
 
     def status(self, stream=None):
         out = np.zeros(self.n_macro, dtype=np.int32)

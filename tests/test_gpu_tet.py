@@ -9,7 +9,12 @@ the oracle (oracle.forms on oracle.tet geometry).
 * wall faces (isothermal no-slip) on a seeded set of faces;
 * the entropy production to 1e-12 of the size of the face terms;
 * a macro with a non-physical state gets NaN outputs and ENONPHYSICAL while
-  the others are unaffected.
+  the others are unaffected;
+* mehdg_tet_jvp: the oracle's dense Jacobian (forms.jacobian, with the
+  pseudo-time term) times the direction, full (dq given) and reduced (dq the
+  weak gradient of (dv, dvhat)), per macro normwise relative <= 1e-12, with
+  walls; and at p = 3 against a central difference of the GPU residual
+  (EC flux, viscous, alpha_ps = 0, step 1e-6, relative 1e-7).
 """
 import numpy as np
 import pytest
@@ -101,3 +106,80 @@ def test_tet_nonphysical_macro_is_flagged():
     ok = [m for m in range(w.n_macro) if m != bad]
     ref = forms.residual(tet.TetGeometry(1, w.mesh.X[ok]), w.v[ok], w.vhat[ok], w.v_old[ok], w.params)
     assert rel_err(got["R_v"][ok], ref["R_v"]) <= TOL
+
+
+def _oracle_jvp(w, X, prm, dv, dh, dq=None, face_bc=None):
+    geo = tet.TetGeometry(w.p, X)
+    J = forms.jacobian(geo, w.v, w.vhat, w.v_old, prm, face_bc=face_bc)
+    if dq is None:
+        dq = forms.lift_q(geo, dv, dh)
+    M_ = w.n_macro
+    x = np.concatenate([dq.reshape(M_, -1), dv.reshape(M_, -1), dh.reshape(M_, -1)], axis=1)
+    out = []
+    for m in range(M_):
+        Jf = np.block([[J["A_qq"][m], J["A_qv"][m], J["A_qvh"][m]],
+                       [J["A_vq"][m], J["A_vv"][m], J["A_vvh"][m]],
+                       [J["A_hq"][m], J["A_hv"][m], J["A_hh"][m]]])
+        out.append(Jf @ x[m])
+    y = np.stack(out)
+    NQ, NV = dq[0].size, dv[0].size
+    return y[:, :NQ].reshape(dq.shape), y[:, NQ:NQ + NV].reshape(dv.shape), y[:, NQ + NV:].reshape(dh.shape)
+
+
+def _gpu_jvp(w, X, prm, dv, dh, dq=None, face_bc=None):
+    from paper_2507_22195_amd import mehdg
+    ctx = mehdg.TetContext(w.p, X, prm, face_bc=face_bc)
+    S = ctx.shapes()
+    Jq, Jv, Jh = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"])
+    ctx.jvp(dev(w.v), dev(w.vhat), None, dev(dv), dev(dh), None if dq is None else dev(dq), Jq, Jv, Jh)
+    rc, st = ctx.status()
+    ctx.close()
+    assert rc == 0, st
+    return host(Jq), host(Jv), host(Jh)
+
+
+@pytest.mark.parametrize("p,flux,walls", [(1, "KEPES", False), (2, "ES", True), (2, "EC", False)])
+def test_tet_jvp_matches_oracle(p, flux, walls):
+    w = _tgv(p, flux, flux != "EC", shape=(1, 1, 1), seed=101)
+    prm = dict(w.params, T_wall=1.05)
+    bc = None
+    if walls:
+        bc = (np.random.default_rng(3).random((w.n_macro, 4)) < 0.3).astype(np.uint8)
+    rng = np.random.default_rng(4)
+    dv, dh = rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape)
+    dq = rng.standard_normal((w.n_macro, 5, 3, w.v.shape[2]))
+    for label, dqq in (("full", dq), ("reduced", None)):
+        banner(f"tet jvp {label}: p={p} flux={flux} walls={walls}")
+        got = _gpu_jvp(w, w.mesh.X, prm, dv, dh, dq=dqq, face_bc=bc)
+        ref = _oracle_jvp(w, w.mesh.X, prm, dv, dh, dq=dqq, face_bc=bc)
+        errs = dict(JR_v=rel_err(got[1], ref[1]), JR_vhat=rel_err(got[2], ref[2]))
+        if dqq is not None:
+            errs["JR_q"] = rel_err(got[0], ref[0])
+        banner(f"  errors {errs}")
+        for k, e in errs.items():
+            assert e <= TOL, (k, e)
+
+
+def test_tet_jvp_p3_against_central_difference_of_the_gpu_residual():
+    # EC flux: no |.| anywhere in the trace flux, so the residual is smooth
+    # (the ES and KEPES dissipation has |Vhat.n|, which this state comes within
+    # 6e-6 of at some face point); the other fluxes are covered exactly above
+    w = _tgv(3, "EC", True, seed=111)
+    prm = dict(w.params, alpha_ps=0.0)
+    rng = np.random.default_rng(6)
+    dv, dh = rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape)
+    banner("tet jvp p3 vs central difference of the residual")
+    got = _gpu_jvp(w, w.mesh.X, prm, dv, dh)
+    eps = 1e-6
+    outs = []
+    for sgn in (1.0, -1.0):
+        ws = W.TetWorkload(w.name, w.p, w.mesh, prm, w.v + sgn * eps * dv, w.vhat + sgn * eps * dh, w.v_old,
+                           w.face_bc)
+        rc, st, r = _run(ws, w.mesh.X, prm=prm)
+        assert rc == 0, st
+        outs.append(r)
+    for key, g in (("R_v", got[1]), ("R_vhat", got[2])):
+        fd = (outs[0][key] - outs[1][key]) / (2 * eps)
+        e = rel_err(g, fd)
+        banner(f"  {key}: {e:.2e}")
+        assert e <= 1e-7, (key, e)
