@@ -354,8 +354,40 @@ mehdg_err mehdg_tet_jvp(mehdg_tet_ctx* ctx, const double* v, const double* vhat,
                         const double* dv, const double* dvhat, const double* dq, double* JR_q, double* JR_v,
                         double* JR_vhat, mehdg_stream stream);
 
-/* Per-macro status of the last mehdg_tet_residual or mehdg_tet_jvp (0, ENONPHYSICAL or
- * ENONFINITE) into host memory; returns the first non-zero code or OK.
+/* Local work of one Newton step on tetrahedral macros (Sec. 6.2 eq. R1-R6),
+ * with q the weak gradient of (v, vhat) (so R_Q = 0 up to rounding):
+ *
+ * mehdg_tet_assemble writes the residual (as mehdg_tet_residual with q NULL)
+ * and the bordered matrix [[S, -Y, r_V], [X, A', r_hat]] of every macro into
+ * the context.  With R_Q = 0 that matrix is [J_r | -R], J_r the reduced
+ * Jacobian of (R_V, R_Vhat) in (v, vhat) through the weak gradient
+ * (S = A_vv - A_vq A_qq^-1 A_qv, -Y = A_vvh - A_vq A_qq^-1 A_qvh,
+ * X = A_hv - A_hq A_qq^-1 A_qv, A' = A_hh - A_hq A_qq^-1 A_qvh; the
+ * pseudo-time term alpha_ps (A0 dv, w) is in S), built column by column with
+ * the JVP kernel.  The first call allocates the workspace, about
+ * (N_V + N_VH)^2 doubles per macro (7.7 MB at p = 3); ENOMEM if it does not fit.
+ *
+ * mehdg_tet_condense factors it (pivoted LU of S) and writes
+ * Ahat = A' + X S^-1 Y [n_macro][N_VH][N_VH] and bhat = r_hat - X S^-1 r_V
+ * [n_macro][N_VH] (eq. R5a-b); ESTATE before an assemble.
+ *
+ * mehdg_tet_recover, after a condense (else ESTATE): dV = S^-1 (r_V + Y dVhat)
+ * and dQ = A_qq^-1 (-R_Q - A_qv dV - A_qvh dVhat) (eq. R2, R6) for a trace
+ * update dvhat [n_macro][4][5][nf]; dv [n_macro][5][n], dq [n_macro][5][3][n];
+ * R_q as returned by the assemble.
+ *
+ * Device pointers, asynchronous on ``stream``; flagged macros (non-physical
+ * state, non-finite values, zero pivot: mehdg_tet_status) get NaN outputs. */
+mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* ctx, const double* v, const double* vhat, const double* v_old,
+                             double* R_q, double* R_v, double* R_vhat, double* entropy, mehdg_stream stream);
+mehdg_err mehdg_tet_condense(mehdg_tet_ctx* ctx, double* Ahat, double* bhat, mehdg_stream stream);
+mehdg_err mehdg_tet_recover(mehdg_tet_ctx* ctx, const double* R_q, const double* dvhat, double* dv,
+                            double* dq, mehdg_stream stream);
+
+/* Per-macro status of the calls since the last mehdg_tet_residual,
+ * mehdg_tet_jvp or mehdg_tet_assemble (0, ENONPHYSICAL, ENONFINITE, or
+ * ESINGULAR from a condense) into host memory; returns the first non-zero
+ * code or OK.
  * Synchronises the stream. */
 mehdg_err mehdg_tet_status(mehdg_tet_ctx* ctx, int32_t* status, mehdg_stream stream);
 

@@ -42,6 +42,26 @@ struct Dims {
     static constexpr int NH = 30 * nf;
 };
 
+// Sizes of a tetrahedral macro-element of degree p under the tag P = TET_TAG + p:
+// the degree-2p lattice of eight P_p sub-tetrahedra (n nodes, nf per face,
+// four faces).  Only the dense condensation kernels, which see NV and NH
+// alone, are instantiated with these tags.
+constexpr int TET_TAG = 100;
+template <int p>
+struct TetSizes {
+    static constexpr int n = (2 * p + 1) * (2 * p + 2) * (2 * p + 3) / 6;
+    static constexpr int nf = (2 * p + 1) * (2 * p + 2) / 2;
+    static constexpr int NV = 5 * n;
+    static constexpr int NQ = 15 * n;
+    static constexpr int NH = 20 * nf;
+};
+template <>
+struct Dims<TET_TAG + 1> : TetSizes<1> {};
+template <>
+struct Dims<TET_TAG + 2> : TetSizes<2> {};
+template <>
+struct Dims<TET_TAG + 3> : TetSizes<3> {};
+
 // face f: normal axis, side (0: xi = 0, outward normal -e_d; 1: xi = 2, +e_d)
 __host__ __device__ __forceinline__ int face_axis(int f) { return f >> 1; }
 __host__ __device__ __forceinline__ int face_side(int f) { return f & 1; }

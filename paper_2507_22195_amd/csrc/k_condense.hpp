@@ -93,7 +93,10 @@ struct Panel {
     static constexpr int NB = 64;
     static constexpr int OB = 2 * NB;
     static constexpr int NV = Dims<P>::NV;
-    static constexpr int THREADS = ((NV + 63) / 64) * 64 > 1024 ? 1024 : ((NV + 63) / 64) * 64;
+    // one thread per S row, at least two waves (wave 0 inverts L_kk, wave 1
+    // U_kk), at most 1024 threads
+    static constexpr int THREADS_R = ((NV + 63) / 64) * 64 > 1024 ? 1024 : ((NV + 63) / 64) * 64;
+    static constexpr int THREADS = THREADS_R < 128 ? 128 : THREADS_R;
     static constexpr int RPT = (NV + THREADS - 1) / THREADS;   // S rows per thread
     static constexpr int NPAN = (NV + NB - 1) / NB;             // panels of S
     // per macro: L^-1 of the first and of the second panel of the current

@@ -12,6 +12,84 @@
 
 namespace mehdg {
 
+// dV = U^-1 (y - U12 dVhat) for the macro whose factored bordered matrix
+// starts at Bm (dVhat in LDS dvh[NH]); the result is left in z[NV] (LDS).
+// Uses the whole workgroup; U is 64 x 64 LDS scratch.
+template <int P>
+__device__ void back_substitute(const double* __restrict__ Bm, const double* dvh, double* z, double (*U)[65]) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    // z = y - U12 dVhat: each wave takes RB rows at a time, lanes along the
+    // rows (coalesced), and reduces the RB dot products together
+    constexpr int RB = 8;
+    for (int r0 = wave * RB; r0 < NV; r0 += nw * RB) {
+        double s[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = 0.0;
+        for (int c = lane; c < NH; c += 64) {
+            const double x = dvh[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < NV) s[i] += Bm[(int64_t)(r0 + i) * ld + NV + c] * x;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+        if (lane < RB && r0 + lane < NV) {
+            double si = s[0];
+#pragma unroll
+            for (int i = 1; i < RB; ++i)
+                if (lane == i) si = s[i];
+            z[r0 + lane] = Bm[(int64_t)(r0 + lane) * ld + NV + NH] - si;
+        }
+    }
+    __syncthreads();
+    // U dV = z, left-looking over blocks of 64 rows from the bottom: the rows
+    // of a block first take their dot products with the solved part, then
+    // wave 0 solves the 64 x 64 triangle (lane j holds row j; the solved value
+    // is broadcast with a lane read)
+    for (int i1 = NV; i1 > 0; i1 -= 64) {
+        const int i0 = i1 - 64 > 0 ? i1 - 64 : 0;
+        const int nb = i1 - i0;
+        for (int e = tid; e < 64 * 64; e += blockDim.x) {
+            const int r = e >> 6, c = e & 63;
+            U[r][c] = (r < nb && c < nb) ? Bm[(int64_t)(i0 + r) * ld + i0 + c] : 0.0;
+        }
+        for (int r0 = i0 + wave * RB; r0 < i1; r0 += nw * RB) {
+            double s[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) s[i] = 0.0;
+            for (int c = i1 + lane; c < NV; c += 64) {
+                const double x = z[c];
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+                    if (r0 + i < i1) s[i] += Bm[(int64_t)(r0 + i) * ld + c] * x;
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+            if (lane < RB && r0 + lane < i1) {
+                double si = s[0];
+#pragma unroll
+                for (int i = 1; i < RB; ++i)
+                    if (lane == i) si = s[i];
+                z[r0 + lane] -= si;
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            double zi = (lane < nb) ? z[i0 + lane] : 0.0;
+            for (int j = nb - 1; j >= 0; --j) {
+                const double xj = read_lane_f64(zi, j) / U[j][j];
+                if (lane == j) zi = xj;
+                else if (lane < j) zi -= U[lane][j] * xj;
+            }
+            if (lane < nb) z[i0 + lane] = zi;   // now holds dV for this block
+        }
+        __syncthreads();
+    }
+}
+
 template <int P>
 struct RecLds {
     using D = Dims<P>;
@@ -29,12 +107,12 @@ __global__ void __launch_bounds__(1024) k_recover(const double* __restrict__ B, 
                                                  double* __restrict__ dq) {
     using D = Dims<P>;
     using BD = Bdims<P>;
-    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH, ld = BD::ld;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     RecLds<P>& L = *reinterpret_cast<RecLds<P>*>(smem_raw);
     const int64_t m = blockIdx.x;
     const double* Bm = B + m * BD::per_macro;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x;
     {
         const double* src = reinterpret_cast<const double*>(tab);
         double* dst = reinterpret_cast<double*>(&L.t);
@@ -42,73 +120,7 @@ __global__ void __launch_bounds__(1024) k_recover(const double* __restrict__ B, 
     }
     for (int i = tid; i < NH; i += blockDim.x) L.dvh[i] = dvhat[m * NH + i];
     __syncthreads();
-    // z = y - U12 dVhat: each wave takes RB rows at a time, lanes along the
-    // rows (coalesced), and reduces the RB dot products together
-    constexpr int RB = 8;
-    for (int r0 = wave * RB; r0 < NV; r0 += nw * RB) {
-        double s[RB];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) s[i] = 0.0;
-        for (int c = lane; c < NH; c += 64) {
-            const double x = L.dvh[c];
-#pragma unroll
-            for (int i = 0; i < RB; ++i)
-                if (r0 + i < NV) s[i] += Bm[(int64_t)(r0 + i) * ld + NV + c] * x;
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
-        if (lane < RB && r0 + lane < NV) {
-            double si = s[0];
-#pragma unroll
-            for (int i = 1; i < RB; ++i)
-                if (lane == i) si = s[i];
-            L.z[r0 + lane] = Bm[(int64_t)(r0 + lane) * ld + NV + NH] - si;
-        }
-    }
-    __syncthreads();
-    // U dV = z, left-looking over blocks of 64 rows from the bottom: the rows
-    // of a block first take their dot products with the solved part, then
-    // wave 0 solves the 64 x 64 triangle (lane j holds row j; the solved value
-    // is broadcast with a lane read)
-    for (int i1 = NV; i1 > 0; i1 -= 64) {
-        const int i0 = i1 - 64 > 0 ? i1 - 64 : 0;
-        const int nb = i1 - i0;
-        for (int e = tid; e < 64 * 64; e += blockDim.x) {
-            const int r = e >> 6, c = e & 63;
-            L.U[r][c] = (r < nb && c < nb) ? Bm[(int64_t)(i0 + r) * ld + i0 + c] : 0.0;
-        }
-        for (int r0 = i0 + wave * RB; r0 < i1; r0 += nw * RB) {
-            double s[RB];
-#pragma unroll
-            for (int i = 0; i < RB; ++i) s[i] = 0.0;
-            for (int c = i1 + lane; c < NV; c += 64) {
-                const double x = L.z[c];
-#pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    if (r0 + i < i1) s[i] += Bm[(int64_t)(r0 + i) * ld + c] * x;
-            }
-#pragma unroll
-            for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
-            if (lane < RB && r0 + lane < i1) {
-                double si = s[0];
-#pragma unroll
-                for (int i = 1; i < RB; ++i)
-                    if (lane == i) si = s[i];
-                L.z[r0 + lane] -= si;
-            }
-        }
-        __syncthreads();
-        if (wave == 0) {
-            double zi = (lane < nb) ? L.z[i0 + lane] : 0.0;
-            for (int j = nb - 1; j >= 0; --j) {
-                const double xj = read_lane_f64(zi, j) / L.U[j][j];
-                if (lane == j) zi = xj;
-                else if (lane < j) zi -= L.U[lane][j] * xj;
-            }
-            if (lane < nb) L.z[i0 + lane] = zi;   // now holds dV for this block
-        }
-        __syncthreads();
-    }
+    back_substitute<P>(Bm, L.dvh, L.z, L.U);
     for (int i = tid; i < NV; i += blockDim.x) dv[m * NV + i] = L.z[i];
     // M^-1 R_Q by three 1-D passes
     for (int i = tid; i < 15 * n; i += blockDim.x) L.a[i] = R_q[m * 15 * n + i];

@@ -23,12 +23,17 @@
 // tables are constant across macros (L2-resident), the per-macro geometry is
 // J^-1, |det J|, and per face the outward normal and twice the area.
 //
-// The same kernel with LIN = true is the Jacobian-vector product of that
-// residual (with the pseudo-time term alpha_ps (A0 dv, w), as in the
-// assembled Jacobian): phases 1, 3 and 5 are linear and run unchanged on the
-// tangents (dq, dv, dvhat); phases 2 and 4 evaluate the pointwise physics in
-// dual numbers seeded with the interpolated tangents and keep only the
-// tangent parts.
+// MODE 0 is the residual.  MODE 1 is its Jacobian-vector product (with the
+// pseudo-time term alpha_ps (A0 dv, w), as in the assembled Jacobian):
+// phases 1, 3 and 5 are linear and run unchanged on the tangents
+// (dq, dv, dvhat); phases 2 and 4 evaluate the pointwise physics in dual
+// numbers seeded with the interpolated tangents and keep only the tangent
+// parts.  MODE 2 is MODE 1 in the unit direction of column j = blockIdx.y of
+// (dv, dvhat), with dq the weak gradient: column j of the reduced Jacobian
+// J_r, written into column j of the macro's bordered matrix.  With q the weak
+// gradient (R_Q = 0), the bordered matrix of the condensation (eq. R3-R5),
+// [[S, -Y, r_V], [X, A', r_hat]], is exactly [J_r | -R]:
+//   S = A_vv - A_vq A_qq^-1 A_qv,  -Y = A_vvh - A_vq A_qq^-1 A_qvh, and so on.
 #pragma once
 #include <type_traits>
 
@@ -53,12 +58,12 @@ struct TetDims {
 constexpr int TET_GEO = 32;   // invJ[9], |det J|, normals[4][3], 2 area[4]
 
 struct TetDevTab {
-    const double *phi, *dphi, *wv, *BiT, *psi, *wf, *Mt, *CT, *ChT, *DT, *DhT;
+    const double *phi, *dphi, *wv, *BiT, *psi, *wf, *Mt, *CT, *ChT, *DT, *DhT, *Mi;
     const int *vnode, *fnode, *tnode, *vptr, *vinc, *fptr, *finc;
 };
 
 template <int P, bool LIN>
-struct TetLds {
+struct TetLds {   // LIN: MODE 1 or 2
     using D = TetDims<P>;
     static constexpr int PT = (20 * D::G > 10 * D::FP) ? 20 * D::G : 10 * D::FP;
     static constexpr int SC = (8 * 5 * D::ns > 2 * 80 * D::nfs) ? 8 * 5 * D::ns : 2 * 80 * D::nfs;
@@ -99,7 +104,7 @@ __device__ void tet_lift(const TetDevTab& T, const double* gm, const double* inv
                          const double (*V)[TetDims<P>::n], const double (*VH)[5][TetDims<P>::nf],
                          double (*Q)[TetDims<P>::n]) {
     constexpr int n = TetDims<P>::n, nf = TetDims<P>::nf;
-    for (int i = threadIdx.x; i < 5 * n; i += TET_THREADS) {
+    for (int i = threadIdx.x; i < 5 * n; i += blockDim.x) {
         const int k = i / n, a = i - k * n;
         double dv[3] = {0.0, 0.0, 0.0};
         for (int b = 0; b < n; ++b) {
@@ -128,7 +133,7 @@ __device__ void tet_rq(const TetDevTab& T, const double* gm, const double* invJ,
                        const double (*V)[TetDims<P>::n], const double (*VH)[5][TetDims<P>::nf],
                        const double (*Q)[TetDims<P>::n], double* __restrict__ out) {
     constexpr int n = TetDims<P>::n, nf = TetDims<P>::nf;
-    for (int i = threadIdx.x; i < 5 * n; i += TET_THREADS) {
+    for (int i = threadIdx.x; i < 5 * n; i += blockDim.x) {
         const int k = i / n, a = i - k * n;
         double mq[3] = {0.0, 0.0, 0.0}, cv[3] = {0.0, 0.0, 0.0};
         for (int b = 0; b < n; ++b) {
@@ -155,17 +160,21 @@ __device__ void tet_rq(const TetDevTab& T, const double* gm, const double* invJ,
     }
 }
 
-// LIN false: residual (R_q, R_v, R_vh, entropy) at (q, v, vhat) with q = qin or
-// the weak gradient.  LIN true: the tangents (JR_q, JR_v, JR_vh) in the
+// MODE 0: residual (R_q, R_v, R_vh, entropy) at (q, v, vhat) with q = qin or
+// the weak gradient.  MODE 1: the tangents (JR_q, JR_v, JR_vh) in the
 // direction (dq, dv, dvhat), dq = dqin or the weak gradient of (dv, dvhat);
-// entropy is not written and may be null.
-template <int P, bool LIN>
+// entropy is not written and may be null.  MODE 2: column blockIdx.y of J_r
+// into Bc (bordered matrices, ld and per_macro doubles apart), rows in the
+// order V then Vhat; R_q, R_v, R_vh, entropy unused.
+template <int P, int MODE>
 __global__ void __launch_bounds__(TET_THREADS)
 k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const double* __restrict__ qin,
       const double* __restrict__ v_old, const double* __restrict__ dvin, const double* __restrict__ dvhin,
       const double* __restrict__ dqin, const double* __restrict__ geo, TetDevTab T, DevParams pr,
       const uint8_t* __restrict__ face_bc, double* __restrict__ R_q, double* __restrict__ R_v,
-      double* __restrict__ R_vh, double* __restrict__ entropy, int32_t* __restrict__ status) {
+      double* __restrict__ R_vh, double* __restrict__ entropy, int32_t* __restrict__ status,
+      double* __restrict__ Bc, int ld, int64_t per_macro) {
+    constexpr bool LIN = MODE != 0;
     using D = TetDims<P>;
     using S = typename std::conditional<LIN, dual<1>, double>::type;
     using SC = TetScalar<S>;
@@ -182,29 +191,32 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
     bool bad_phys = false, bad_fin = false;
 
     // ---- 1. state, weak gradient, R_Q (tangents: the same linear maps)
+    const int col = (MODE == 2) ? (int)blockIdx.y : -1;
     for (int i = tid; i < 5 * n; i += TET_THREADS) {
         (&L.v[0][0])[i] = v[m * 5 * n + i];
-        if constexpr (LIN) (&L.dv[0][0])[i] = dvin[m * 5 * n + i];
+        if constexpr (MODE == 1) (&L.dv[0][0])[i] = dvin[m * 5 * n + i];
+        else if constexpr (MODE == 2) (&L.dv[0][0])[i] = (i == col) ? 1.0 : 0.0;
         else (&L.vo[0][0])[i] = v_old[m * 5 * n + i];
     }
     for (int i = tid; i < 20 * nf; i += TET_THREADS) {
         (&L.vh[0][0][0])[i] = vhat[m * 20 * nf + i];
-        if constexpr (LIN) (&L.dvh[0][0][0])[i] = dvhin[m * 20 * nf + i];
+        if constexpr (MODE == 1) (&L.dvh[0][0][0])[i] = dvhin[m * 20 * nf + i];
+        else if constexpr (MODE == 2) (&L.dvh[0][0][0])[i] = (i == col - 5 * n) ? 1.0 : 0.0;
     }
     if (qin)
         for (int i = tid; i < 15 * n; i += TET_THREADS) (&L.q[0][0])[i] = qin[m * 15 * n + i];
-    if constexpr (LIN) {
+    if constexpr (MODE == 1) {
         if (dqin)
             for (int i = tid; i < 15 * n; i += TET_THREADS) (&L.dq[0][0])[i] = dqin[m * 15 * n + i];
     }
     __syncthreads();
     if (!qin) tet_lift<P>(T, gm, invJ, adet, L.v, L.vh, L.q);
     if constexpr (LIN) {
-        if (!dqin) tet_lift<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq);
+        if (MODE == 2 || !dqin) tet_lift<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq);
     }
     __syncthreads();
-    if constexpr (LIN) tet_rq<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq, R_q + m * 15 * n);
-    else tet_rq<P>(T, gm, invJ, adet, L.v, L.vh, L.q, R_q + m * 15 * n);
+    if constexpr (MODE == 1) tet_rq<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq, R_q + m * 15 * n);
+    else if constexpr (MODE == 0) tet_rq<P>(T, gm, invJ, adet, L.v, L.vh, L.q, R_q + m * 15 * n);
 
     // ---- 2. volume points
     const double g = pr.gamma;
@@ -407,26 +419,86 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
                 accw += L.sc[FS + idx];
             }
             L.rv[k][T.fnode[f * nf + c]] += acc;
-            R_vh[((m * 4 + f) * 5 + k) * nf + c] = (wall && k > 0) ? accw : acc;
+            const double o = (wall && k > 0) ? accw : acc;
+            if constexpr (MODE == 2) Bc[m * per_macro + (int64_t)(5 * n + (f * 5 + k) * nf + c) * ld + col] = o;
+            else R_vh[((m * 4 + f) * 5 + k) * nf + c] = o;
         }
         __syncthreads();
     }
-    for (int i = tid; i < 5 * n; i += TET_THREADS) R_v[m * 5 * n + i] = (&L.rv[0][0])[i];
+    for (int i = tid; i < 5 * n; i += TET_THREADS) {
+        if constexpr (MODE == 2) Bc[m * per_macro + (int64_t)i * ld + col] = (&L.rv[0][0])[i];
+        else R_v[m * 5 * n + i] = (&L.rv[0][0])[i];
+    }
 
     // ---- status: a flagged macro's outputs are NaN
     const int flag = __syncthreads_or(bad_phys ? 1 : (bad_fin ? 2 : 0));
     if (flag) {
         const int any_phys = __syncthreads_or(bad_phys ? 1 : 0);
         const double nan = __builtin_nan("");
-        for (int i = tid; i < 5 * n; i += TET_THREADS) R_v[m * 5 * n + i] = nan;
-        for (int i = tid; i < 15 * n; i += TET_THREADS) R_q[m * 15 * n + i] = nan;
-        for (int i = tid; i < 20 * nf; i += TET_THREADS) R_vh[m * 20 * nf + i] = nan;
+        if constexpr (MODE == 2) {
+            for (int i = tid; i < 5 * n + 20 * nf; i += TET_THREADS) Bc[m * per_macro + (int64_t)i * ld + col] = nan;
+        } else {
+            for (int i = tid; i < 5 * n; i += TET_THREADS) R_v[m * 5 * n + i] = nan;
+            for (int i = tid; i < 15 * n; i += TET_THREADS) R_q[m * 15 * n + i] = nan;
+            for (int i = tid; i < 20 * nf; i += TET_THREADS) R_vh[m * 20 * nf + i] = nan;
+        }
         if (tid == 0) {
-            if (!LIN) entropy[m] = nan;
+            if (MODE == 0) entropy[m] = nan;
             if (status) status[m] = any_phys ? 5 : 6;
         }
-    } else if (tid == 0 && status) {
-        status[m] = 0;
+    } else if (MODE != 2 && tid == 0 && status) {
+        status[m] = 0;   // (column launches only ever raise a flag)
+    }
+}
+
+// Recovery of tetrahedral macros (eq. R2, R6): dV = U^-1 (y - U12 dVhat)
+// from the factored bordered matrix (the back-substitution of the hexahedral
+// path), then dQ = A_qq^-1 (-R_Q - A_qv dV - A_qvh dVhat) = lift(dV, dVhat)
+// - M^-1 R_Q with the weak-gradient tables.  One workgroup of 1024 threads
+// per macro.
+template <int P>
+struct TetRecLds {
+    double z[TetDims<P>::n * 5];
+    double dvh[TetDims<P>::nf * 20];
+    double U[64][65];
+};
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_tet_recover(const double* __restrict__ B, const double* __restrict__ R_q,
+                                                     const double* __restrict__ dvhat, const double* __restrict__ geo,
+                                                     TetDevTab T, double* __restrict__ dv, double* __restrict__ dq) {
+    using D = TetDims<P>;
+    constexpr int n = D::n, nf = D::nf, NV = 5 * n, NH = 20 * nf;
+    static_assert(Dims<TET_TAG + P>::NV == NV && Dims<TET_TAG + P>::NH == NH, "tetrahedral sizes");
+    extern __shared__ __align__(16) unsigned char smem[];
+    TetRecLds<P>& L = *reinterpret_cast<TetRecLds<P>*>(smem);
+    const int64_t m = blockIdx.x;
+    const int tid = threadIdx.x;
+    const double* gm = geo + m * TET_GEO;
+    double invJ[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) invJ[i] = gm[i];
+    const double adet = gm[9];
+    for (int i = tid; i < NH; i += blockDim.x) L.dvh[i] = dvhat[m * NH + i];
+    __syncthreads();
+    back_substitute<TET_TAG + P>(B + m * Bdims<TET_TAG + P>::per_macro, L.dvh, L.z, L.U);
+    __syncthreads();
+    for (int i = tid; i < NV; i += blockDim.x) dv[m * NV + i] = L.z[i];
+    double* out = dq + m * 15 * n;
+    tet_lift<P>(T, gm, invJ, adet, reinterpret_cast<const double(*)[n]>(L.z),
+                reinterpret_cast<const double(*)[5][nf]>(L.dvh), reinterpret_cast<double(*)[n]>(out));
+    // the same thread owns the same (k, a) entries as in the lift
+    const double* rq = R_q + m * 15 * n;
+    for (int i = tid; i < 5 * n; i += blockDim.x) {
+        const int k = i / n, a = i - k * n;
+        double s[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < n; ++b) {
+            const double mi = T.Mi[b * n + a];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) s[j] += mi * rq[(3 * k + j) * n + b];
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) out[(3 * k + j) * n + a] -= s[j] / adet;
     }
 }
 

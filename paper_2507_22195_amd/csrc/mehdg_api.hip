@@ -18,6 +18,7 @@
 #include "k_recover.hpp"
 #include "k_trace.hpp"
 #include "tables.hpp"
+#include "tet_cond.hpp"
 
 using namespace mehdg;
 
@@ -268,7 +269,7 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
     using D = Dims<P>;
     using BD = Bdims<P>;
     using PN = Panel<P>;
-    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld, ROWS = BD::rows, NB = PN::NB;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld, NB = PN::NB;
     const unsigned M = (unsigned)c->n_macro;
     double* B = c->d_B;
     mehdg_err e;
@@ -619,6 +620,49 @@ mehdg_err trace_gmres(mehdg_ctx* c, const double* Ahat, const double* F, double*
 }
 
 }  // namespace
+
+// --------------------------------------------------------------------------
+// condensation of tetrahedral bordered matrices (tet_cond.hpp)
+// --------------------------------------------------------------------------
+template <int P>
+void tet_cond_sizes_of(int64_t out[4]) {
+    out[0] = Bdims<P>::rows;
+    out[1] = Bdims<P>::ld;
+    out[2] = Panel<P>::TRI;
+    out[3] = Panel<P>::PERM;
+}
+
+bool tet_cond_sizes(int p, int64_t out[4]) {
+    switch (p) {
+        case 1: tet_cond_sizes_of<TET_TAG + 1>(out); return true;
+        case 2: tet_cond_sizes_of<TET_TAG + 2>(out); return true;
+        case 3: tet_cond_sizes_of<TET_TAG + 3>(out); return true;
+        default: return false;
+    }
+}
+
+mehdg_err tet_condense(int p, const TetCondWork& w, double* Ahat, double* bhat, hipStream_t st) {
+    // a context that only lends the workspace pointers to the launchers;
+    // nothing is allocated or freed through it
+    mehdg_ctx c;
+    c.p = TET_TAG + p;
+    c.n_macro = w.n_macro;
+    c.d_B = w.B;
+    c.d_ipiv = w.ipiv;
+    c.d_tri = w.tri;
+    c.d_perm = w.perm;
+    c.d_status = w.status;
+    mehdg_err e = MEHDG_EINVAL;
+    int64_t NH = 0;
+    switch (p) {
+        case 1: e = launch_condense<TET_TAG + 1>(&c, Ahat, bhat, st); NH = Dims<TET_TAG + 1>::NH; break;
+        case 2: e = launch_condense<TET_TAG + 2>(&c, Ahat, bhat, st); NH = Dims<TET_TAG + 2>::NH; break;
+        case 3: e = launch_condense<TET_TAG + 3>(&c, Ahat, bhat, st); NH = Dims<TET_TAG + 3>::NH; break;
+        default: break;
+    }
+    if (e == MEHDG_OK) e = launch_poison(&c, PoisonArgs{{Ahat, bhat, nullptr, nullptr}, {NH * NH, NH, 0, 0}}, st);
+    return e;
+}
 
 extern "C" {
 

@@ -1,5 +1,8 @@
-// Host runtime and C ABI of the tetrahedral macro-element residual
-// (mehdg_tet_*).  A separate translation unit of the same library.
+// Host runtime and C ABI of tetrahedral macro-elements (mehdg_tet_*): the
+// residual, its JVP, and the local work of a Newton step (assembly of the
+// bordered matrices from columns of the reduced Jacobian, the dense
+// condensation shared with the hexahedral path through tet_cond.hpp, and the
+// recovery).  A separate translation unit of the same library.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -8,7 +11,9 @@
 #include <vector>
 
 #include "../../include/mehdg.h"
+#include "k_recover.hpp"
 #include "k_tet.hpp"
+#include "tet_cond.hpp"
 #include "tet_tables.hpp"
 
 using namespace mehdg;
@@ -24,6 +29,13 @@ struct mehdg_tet_ctx {
     double* d_geo = nullptr;       // [n_macro][TET_GEO]
     uint8_t* d_bc = nullptr;       // [n_macro][4] or nullptr
     int32_t* d_status = nullptr;   // [n_macro]
+    // local work of a Newton step (allocated by the first mehdg_tet_assemble)
+    double* d_B = nullptr;         // [n_macro][rows][ld] bordered matrices
+    int32_t* d_ipiv = nullptr;     // [n_macro][N_V]
+    double* d_tri = nullptr;       // [n_macro][tri]
+    int32_t* d_perm = nullptr;     // [n_macro][perm]
+    int64_t rows = 0, ld = 0, per_tri = 0, per_perm = 0;
+    int stage = 0;                 // 0 nothing, 1 assembled, 2 condensed
 };
 
 namespace {
@@ -36,10 +48,23 @@ size_t tet_lds_bytes(int p) { return p == 1 ? tet_lds<1, LIN>() : p == 2 ? tet_l
 
 template <int P>
 bool tet_allow_lds() {
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tet<P, false>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tet_lds<P, false>()) == hipSuccess &&
-           hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tet<P, true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)tet_lds<P, true>()) == hipSuccess;
+    auto set = [](const void* k, size_t b) {
+        return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b) == hipSuccess;
+    };
+    return set(reinterpret_cast<const void*>(&k_tet<P, 0>), tet_lds<P, false>()) &&
+           set(reinterpret_cast<const void*>(&k_tet<P, 1>), tet_lds<P, true>()) &&
+           set(reinterpret_cast<const void*>(&k_tet<P, 2>), tet_lds<P, true>()) &&
+           set(reinterpret_cast<const void*>(&k_tet_recover<P>), sizeof(TetRecLds<P>));
+}
+
+// -B[:, NV + NH] = R: the right-hand-side column of the bordered matrices.
+__global__ void __launch_bounds__(256) k_tet_rhs(const double* __restrict__ R_v, const double* __restrict__ R_vh,
+                                                 int NV, int NH, int ld, int64_t per_macro, double* __restrict__ B) {
+    const int64_t m = blockIdx.x;
+    for (int i = threadIdx.x; i < NV + NH; i += blockDim.x) {
+        const double r = i < NV ? R_v[m * NV + i] : R_vh[m * NH + i - NV];
+        B[m * per_macro + (int64_t)i * ld + NV + NH] = -r;
+    }
 }
 
 // J^-1, |det J|, outward normals and twice the areas of one macro; false if degenerate.
@@ -136,6 +161,10 @@ mehdg_err mehdg_tet_destroy(mehdg_tet_ctx* c) {
     (void)hipFree(c->d_geo);
     (void)hipFree(c->d_bc);
     (void)hipFree(c->d_status);
+    (void)hipFree(c->d_B);
+    (void)hipFree(c->d_ipiv);
+    (void)hipFree(c->d_tri);
+    (void)hipFree(c->d_perm);
     delete c;
     return MEHDG_OK;
 }
@@ -181,13 +210,13 @@ mehdg_err mehdg_tet_create(const mehdg_tet_mesh* mesh, const mehdg_params* prm, 
     TetTab& t = c->tab;
     std::vector<const double*> dp;
     std::vector<const int*> ip;
-    if (!upload<double>({&t.phi, &t.dphi, &t.wv, &t.BiT, &t.psi, &t.wf, &t.Mt, &t.CT, &t.ChT, &t.DT, &t.DhT},
+    if (!upload<double>({&t.phi, &t.dphi, &t.wv, &t.BiT, &t.psi, &t.wf, &t.Mt, &t.CT, &t.ChT, &t.DT, &t.DhT, &t.Mi},
                         &c->d_tab, dp) ||
         !upload<int>({&t.vnode, &t.fnode, &t.tnode, &t.vptr, &t.vinc, &t.fptr, &t.finc}, &c->d_itab, ip)) {
         mehdg_tet_destroy(c);
         return MEHDG_ENOMEM;
     }
-    c->dt = TetDevTab{dp[0], dp[1], dp[2], dp[3], dp[4], dp[5], dp[6], dp[7], dp[8], dp[9], dp[10],
+    c->dt = TetDevTab{dp[0], dp[1], dp[2], dp[3], dp[4], dp[5], dp[6], dp[7], dp[8], dp[9], dp[10], dp[11],
                       ip[0], ip[1], ip[2], ip[3], ip[4], ip[5], ip[6]};
     const size_t gbytes = geo.size() * sizeof(double);
     if (hipMalloc(&c->d_geo, gbytes) != hipSuccess ||
@@ -221,8 +250,8 @@ mehdg_err mehdg_tet_residual(mehdg_tet_ctx* c, const double* v, const double* vh
     const dim3 grid((unsigned)c->n_macro), block(TET_THREADS);
     const size_t lds = tet_lds_bytes<false>(c->p);
 #define MEHDG_TET_LAUNCH(PP)                                                                                   \
-    hipLaunchKernelGGL((k_tet<PP, false>), grid, block, lds, st, v, vhat, q, v_old, nullptr, nullptr, nullptr, \
-                       c->d_geo, c->dt, c->dp, c->d_bc, R_q, R_v, R_vhat, entropy, c->d_status)
+    hipLaunchKernelGGL((k_tet<PP, 0>), grid, block, lds, st, v, vhat, q, v_old, nullptr, nullptr, nullptr, c->d_geo, \
+                       c->dt, c->dp, c->d_bc, R_q, R_v, R_vhat, entropy, c->d_status, nullptr, 0, (int64_t)0)
     if (c->p == 1)
         MEHDG_TET_LAUNCH(1);
     else if (c->p == 2)
@@ -241,8 +270,91 @@ mehdg_err mehdg_tet_jvp(mehdg_tet_ctx* c, const double* v, const double* vhat, c
     const dim3 grid((unsigned)c->n_macro), block(TET_THREADS);
     const size_t lds = tet_lds_bytes<true>(c->p);
 #define MEHDG_TET_LAUNCH(PP)                                                                                  \
-    hipLaunchKernelGGL((k_tet<PP, true>), grid, block, lds, st, v, vhat, q, nullptr, dv, dvhat, dq, c->d_geo, \
-                       c->dt, c->dp, c->d_bc, JR_q, JR_v, JR_vhat, nullptr, c->d_status)
+    hipLaunchKernelGGL((k_tet<PP, 1>), grid, block, lds, st, v, vhat, q, nullptr, dv, dvhat, dq, c->d_geo, c->dt, \
+                       c->dp, c->d_bc, JR_q, JR_v, JR_vhat, nullptr, c->d_status, nullptr, 0, (int64_t)0)
+    if (c->p == 1)
+        MEHDG_TET_LAUNCH(1);
+    else if (c->p == 2)
+        MEHDG_TET_LAUNCH(2);
+    else
+        MEHDG_TET_LAUNCH(3);
+#undef MEHDG_TET_LAUNCH
+    return hipGetLastError() == hipSuccess ? MEHDG_OK : MEHDG_EHIP;
+}
+
+mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* c, const double* v, const double* vhat, const double* v_old,
+                             double* R_q, double* R_v, double* R_vhat, double* entropy, mehdg_stream stream) {
+    if (!c || !v || !vhat || !v_old || !R_q || !R_v || !R_vhat || !entropy) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int64_t sz[5];
+    (void)mehdg_tet_sizes(c->p, sz);
+    const int NV = (int)sz[2], NH = (int)sz[4];
+    if (!c->d_B) {
+        int64_t cs[4];
+        if (!tet_cond_sizes(c->p, cs)) return MEHDG_EINVAL;
+        c->rows = cs[0];
+        c->ld = cs[1];
+        c->per_tri = cs[2];
+        c->per_perm = cs[3];
+        const int64_t M = c->n_macro;
+        if (hipMalloc(&c->d_B, (size_t)(M * c->rows * c->ld) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->d_ipiv, (size_t)(M * NV) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->d_tri, (size_t)(M * c->per_tri) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&c->d_perm, (size_t)(M * c->per_perm) * sizeof(int32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipFree(c->d_B);
+            (void)hipFree(c->d_ipiv);
+            (void)hipFree(c->d_tri);
+            (void)hipFree(c->d_perm);
+            c->d_B = nullptr;
+            c->d_ipiv = nullptr;
+            c->d_tri = nullptr;
+            c->d_perm = nullptr;
+            return MEHDG_ENOMEM;
+        }
+    }
+    c->stage = 0;
+    mehdg_err e = mehdg_tet_residual(c, v, vhat, nullptr, v_old, R_q, R_v, R_vhat, entropy, stream);
+    if (e != MEHDG_OK) return e;
+    const int64_t per = c->rows * c->ld;
+    hipLaunchKernelGGL(k_tet_rhs, dim3((unsigned)c->n_macro), dim3(256), 0, st, R_v, R_vhat, NV, NH, (int)c->ld, per,
+                       c->d_B);
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    const dim3 grid((unsigned)c->n_macro, (unsigned)(NV + NH)), block(TET_THREADS);
+    const size_t lds = tet_lds_bytes<true>(c->p);
+#define MEHDG_TET_LAUNCH(PP)                                                                                 \
+    hipLaunchKernelGGL((k_tet<PP, 2>), grid, block, lds, st, v, vhat, nullptr, nullptr, nullptr, nullptr,    \
+                       nullptr, c->d_geo, c->dt, c->dp, c->d_bc, nullptr, nullptr, nullptr, nullptr, c->d_status, \
+                       c->d_B, (int)c->ld, per)
+    if (c->p == 1)
+        MEHDG_TET_LAUNCH(1);
+    else if (c->p == 2)
+        MEHDG_TET_LAUNCH(2);
+    else
+        MEHDG_TET_LAUNCH(3);
+#undef MEHDG_TET_LAUNCH
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    c->stage = 1;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_tet_condense(mehdg_tet_ctx* c, double* Ahat, double* bhat, mehdg_stream stream) {
+    if (!c || !Ahat || !bhat) return MEHDG_EINVAL;
+    if (c->stage != 1) return MEHDG_ESTATE;
+    TetCondWork w{c->d_B, c->d_ipiv, c->d_tri, c->d_perm, c->d_status, c->n_macro};
+    mehdg_err e = tet_condense(c->p, w, Ahat, bhat, reinterpret_cast<hipStream_t>(stream));
+    if (e == MEHDG_OK) c->stage = 2;
+    return e;
+}
+
+mehdg_err mehdg_tet_recover(mehdg_tet_ctx* c, const double* R_q, const double* dvhat, double* dv, double* dq,
+                            mehdg_stream stream) {
+    if (!c || !R_q || !dvhat || !dv || !dq) return MEHDG_EINVAL;
+    if (c->stage != 2) return MEHDG_ESTATE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+#define MEHDG_TET_LAUNCH(PP)                                                                                     \
+    hipLaunchKernelGGL(k_tet_recover<PP>, dim3((unsigned)c->n_macro), dim3(1024), sizeof(TetRecLds<PP>), st,   \
+                       c->d_B, R_q, dvhat, c->d_geo, c->dt, dv, dq)
     if (c->p == 1)
         MEHDG_TET_LAUNCH(1);
     else if (c->p == 2)

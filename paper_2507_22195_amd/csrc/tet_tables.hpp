@@ -43,6 +43,7 @@ struct TetTab {
     std::vector<double> ChT;    // [4][nf][n]   ChT[f][c][a] = Ch_f[a][c]
     std::vector<double> DT;     // [3][n][n]    DT[i][b][a] = D_i[a][b]
     std::vector<double> DhT;    // [4][nf][n]   DhT[f][c][a] = Dh_f[a][c]
+    std::vector<double> Mi;     // [n][n]       M^-1 (symmetric)
     std::vector<int> vnode;     // [8][ns]      macro node of each sub-tet node
     std::vector<int> fnode;     // [4][nf]      macro node of each face node
     std::vector<int> tnode;     // [4][nfs]     face node of each sub-triangle node
@@ -409,6 +410,7 @@ inline bool build_tet_tables(int p, TetTab& t) {
     std::vector<double> Mi = M;
     if (!invert(n, Mi)) return false;
     t.Mt = M;
+    t.Mi = Mi;
     t.CT.assign((size_t)3 * n * n, 0.0);
     t.DT.assign((size_t)3 * n * n, 0.0);
     for (int i = 0; i < 3; ++i)

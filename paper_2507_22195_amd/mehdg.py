@@ -98,8 +98,12 @@ def load(path: str = LIB_PATH):
     lib.mehdg_tet_residual.argtypes = [vp] + [vp] * 8 + [vp]
     lib.mehdg_tet_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.mehdg_tet_jvp.argtypes = [vp] + [vp] * 9 + [vp]
+    lib.mehdg_tet_assemble.argtypes = [vp] + [vp] * 7 + [vp]
+    lib.mehdg_tet_condense.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_tet_recover.argtypes = [vp, vp, vp, vp, vp, vp]
     for name in ("mehdg_tet_sizes", "mehdg_tet_create", "mehdg_tet_destroy", "mehdg_tet_residual",
-                 "mehdg_tet_status", "mehdg_tet_jvp"):
+                 "mehdg_tet_status", "mehdg_tet_jvp", "mehdg_tet_assemble", "mehdg_tet_condense",
+                 "mehdg_tet_recover"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
@@ -444,9 +448,34 @@ class TetContext:
             pass
 
     def shapes(self):
-        M, n, nf = self.n_macro, self.sz["n"], self.sz["nf"]
+        M, n, nf, NH = self.n_macro, self.sz["n"], self.sz["nf"], self.sz["N_VH"]
         return dict(v=(M, 5, n), vhat=(M, 4, 5, nf), q=(M, 5, 3, n), R_q=(M, 5, 3, n), R_v=(M, 5, n),
-                    R_vhat=(M, 4, 5, nf), entropy=(M,))
+                    R_vhat=(M, 4, 5, nf), entropy=(M,), Ahat=(M, NH, NH), bhat=(M, NH), dv=(M, 5, n),
+                    dq=(M, 5, 3, n))
+
+    def assemble(self, v, vhat, v_old, R_q, R_v, R_vhat, entropy, stream=None):
+        """Residual (q the weak gradient) and the bordered matrices of the condensation."""
+        S = self.shapes()
+        rc = load().mehdg_tet_assemble(
+            self._handle, _ptr(v, S["v"], "v"), _ptr(vhat, S["vhat"], "vhat"), _ptr(v_old, S["v"], "v_old"),
+            _ptr(R_q, S["R_q"], "R_q"), _ptr(R_v, S["R_v"], "R_v"), _ptr(R_vhat, S["R_vhat"], "R_vhat"),
+            _ptr(entropy, S["entropy"], "entropy"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_assemble")
+
+    def condense(self, Ahat, bhat, stream=None):
+        S = self.shapes()
+        rc = load().mehdg_tet_condense(self._handle, _ptr(Ahat, S["Ahat"], "Ahat"), _ptr(bhat, S["bhat"], "bhat"),
+                                       _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_condense")
+
+    def recover(self, R_q, dvhat, dv, dq, stream=None):
+        S = self.shapes()
+        rc = load().mehdg_tet_recover(self._handle, _ptr(R_q, S["R_q"], "R_q"), _ptr(dvhat, S["vhat"], "dvhat"),
+                                      _ptr(dv, S["dv"], "dv"), _ptr(dq, S["dq"], "dq"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_recover")
 
     def residual(self, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, stream=None):
         """q None: the weak gradient of (v, vhat)."""

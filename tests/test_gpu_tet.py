@@ -14,7 +14,11 @@ the oracle (oracle.forms on oracle.tet geometry).
   pseudo-time term) times the direction, full (dq given) and reduced (dq the
   weak gradient of (dv, dvhat)), per macro normwise relative <= 1e-12, with
   walls; and at p = 3 against a central difference of the GPU residual
-  (EC flux, viscous, alpha_ps = 0, step 1e-6, relative 1e-7).
+  (EC flux, viscous, alpha_ps = 0, step 1e-6, relative 1e-7);
+* the local work of a Newton step (mehdg_tet_assemble, _condense, _recover)
+  against oracle.forms.condense and oracle.local.recover: Ahat, bhat, dv,
+  dq per macro normwise relative <= 1e-12, p = 1, 2, 3, walls; and the call
+  order (ESTATE).
 """
 import numpy as np
 import pytest
@@ -183,3 +187,54 @@ def test_tet_jvp_p3_against_central_difference_of_the_gpu_residual():
         e = rel_err(g, fd)
         banner(f"  {key}: {e:.2e}")
         assert e <= 1e-7, (key, e)
+
+
+def _step(w, prm, face_bc, dvh):
+    from paper_2507_22195_amd import mehdg
+    ctx = mehdg.TetContext(w.p, w.mesh.X, prm, face_bc=face_bc)
+    S = ctx.shapes()
+    e = {k: empty(S[k]) for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
+    ctx.assemble(dev(w.v), dev(w.vhat), dev(w.v_old), e["R_q"], e["R_v"], e["R_vhat"], e["entropy"])
+    ctx.condense(e["Ahat"], e["bhat"])
+    ctx.recover(e["R_q"], dev(dvh), e["dv"], e["dq"])
+    rc, st = ctx.status()
+    ctx.close()
+    assert rc == 0, st
+    return {k: host(x) for k, x in e.items()}
+
+
+@pytest.mark.parametrize("p,flux,walls", [(1, "KEPES", True), (2, "ES", False), (3, "ES", True)])
+def test_tet_step_matches_oracle(p, flux, walls):
+    from oracle import local
+    w = _tgv(p, flux, True, shape=(1, 1, 1), seed=121)
+    if p == 3:
+        w = W.TetWorkload(w.name, w.p, w.mesh, w.params, w.v[:3], w.vhat[:3], w.v_old[:3], w.face_bc[:3])
+        w.mesh = W.TetMesh(w.mesh.shape, w.mesh.lo, w.mesh.hi, w.mesh.X[:3], w.mesh.vid[:3])
+    prm = dict(w.params, T_wall=1.05)
+    bc = None
+    if walls:
+        bc = (np.random.default_rng(5).random((w.n_macro, 4)) < 0.3).astype(np.uint8)
+    dvh = 1e-2 * np.random.default_rng(6).standard_normal(w.vhat.shape)
+    banner(f"tet step: p={p} flux={flux} walls={walls} macros={w.n_macro}")
+    got = _step(w, prm, bc, dvh)
+    ref = forms.condense(tet.TetGeometry(w.p, w.mesh.X), w.v, w.vhat, w.v_old, prm, face_bc=bc)
+    rdv, rdq = local.recover(ref, dvh)
+    errs = dict(R_v=rel_err(got["R_v"], ref["R_v"]), Ahat=rel_err(got["Ahat"], ref["Ahat"]),
+                bhat=rel_err(got["bhat"], ref["bhat"]), dv=rel_err(got["dv"], rdv), dq=rel_err(got["dq"], rdq))
+    banner(f"  errors {errs}")
+    for k, e in errs.items():
+        assert e <= TOL, (k, e)
+
+
+def test_tet_step_call_order():
+    from paper_2507_22195_amd import mehdg
+    w = _tgv(1, shape=(1, 1, 1))
+    ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
+    S = ctx.shapes()
+    with pytest.raises(mehdg.MehdgError) as ex:
+        ctx.condense(empty(S["Ahat"]), empty(S["bhat"]))
+    assert ex.value.code == 4
+    with pytest.raises(mehdg.MehdgError) as ex:
+        ctx.recover(empty(S["R_q"]), empty(S["vhat"]), empty(S["dv"]), empty(S["dq"]))
+    assert ex.value.code == 4
+    ctx.close()
