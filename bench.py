@@ -345,6 +345,53 @@ def tet_residual(reps=5):
             "jvp_ms": round(ms_jvp, 4), "jvp_macro_per_s": round(M / (ms_jvp / 1e3), 1)}
 
 
+def tet_step(reps=2, shape=(6, 6, 6)):
+    """Local work of one Newton step on tetrahedral macro-elements (not part of
+    the metric): viscous Taylor-Green, cubes of six macro-tetrahedra of eight
+    P_3 sub-tetrahedra, KEPES flux, Re 1600, Mach 0.1; assemble (residual and
+    bordered matrices from reduced-Jacobian columns), condense, recover, each
+    timed with HIP events on the launch stream.  Dense work of the
+    condensation per macro: 2/3 N_V^3 + 2 N_V^2 N_VH + 2 N_VH^2 N_V."""
+    import torch
+    from paper_2507_22195_amd import mehdg
+    from paper_2507_22195_amd import workloads as W
+    w = W.tet_tgv_workload(shape=shape, p=3, M0=0.1, Re=1600.0, flux="KEPES", seed_v=61, seed_vh=62)
+    ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
+    S = ctx.shapes()
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    e = {k: torch.empty(S[k], dtype=torch.float64, device="cuda")
+         for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
+    v, vh, vo = dev(w.v), dev(w.vhat), dev(w.v_old)
+    dvh = dev(1e-2 * np.random.default_rng(1).standard_normal(w.vhat.shape))
+    calls = {"assemble": lambda: ctx.assemble(v, vh, vo, e["R_q"], e["R_v"], e["R_vhat"], e["entropy"]),
+             "condense": lambda: ctx.condense(e["Ahat"], e["bhat"]),
+             "recover": lambda: ctx.recover(e["R_q"], dvh, e["dv"], e["dq"])}
+    for f in calls.values():
+        f()
+    torch.cuda.synchronize()
+    ms = {k: 0.0 for k in calls}
+    for _ in range(reps):
+        for k, f in calls.items():
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            f()
+            b.record()
+            torch.cuda.synchronize()
+            ms[k] += a.elapsed_time(b) / reps
+    rc, _ = ctx.status()
+    M, NV, NH = w.n_macro, ctx.sz["N_V"], ctx.sz["N_VH"]
+    total = sum(ms.values())
+    flops = M * (2.0 / 3.0 * NV ** 3 + 2.0 * NV ** 2 * NH + 2.0 * NH ** 2 * NV)
+    ctx.close()
+    return {"workload": f"viscous TGV, {shape[0]}x{shape[1]}x{shape[2]} cubes of 6 tetrahedral macro-elements of 8 "
+                        "P_3 sub-tetrahedra (84 nodes, N_V 420, N_VH 560), KEPES flux, Re 1600, Mach 0.1, one "
+                        "Newton step (assemble + condense + recover)",
+            "n_macro": M, "status_ok": bool(rc == 0), "ms_per_step": round(total, 2),
+            "ms": {k: round(x, 2) for k, x in ms.items()},
+            "macro_per_s": round(M / (total / 1e3), 1),
+            "condense_TFLOP/s": round(flops / (ms["condense"] / 1e3) / 1e12, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -378,7 +425,7 @@ def main():
         print(json.dumps({"differentiation": differentiation(reps=args.steps)}), flush=True)
         return
     if args.tet_only:
-        print(json.dumps({"tet_residual": tet_residual(reps=args.steps)}), flush=True)
+        print(json.dumps({"tet_residual": tet_residual(reps=args.steps), "tet_step": tet_step()}), flush=True)
         return
     w = W.workload(args.config, shape=tuple(args.shape) if args.shape else None)
     ctx = mehdg.Context(w.p, w.mesh.h, w.params)
@@ -522,6 +569,7 @@ def main():
         out["mixed_degree"] = mixed_degree()
     if not args.no_tet:
         out["tet_residual"] = tet_residual()
+        out["tet_step"] = tet_step()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
