@@ -34,6 +34,11 @@
 // gradient (R_Q = 0), the bordered matrix of the condensation (eq. R3-R5),
 // [[S, -Y, r_V], [X, A', r_hat]], is exactly [J_r | -R]:
 //   S = A_vv - A_vq A_qq^-1 A_qv,  -Y = A_vvh - A_vq A_qq^-1 A_qvh, and so on.
+// MODE 2 takes the pointwise Jacobian coefficients that k_tet_coef stores once
+// per macro: the tangent at a point is the coefficient block times the unit
+// direction (its value at the point, and its weak gradient there, read from
+// the constant tables Phi M^-1 C_i and Phi M^-1 Ch_f), so neither the dual
+// arithmetic nor the lift is repeated per column.
 #pragma once
 #include <type_traits>
 
@@ -62,8 +67,32 @@ struct TetDevTab {
     const int *vnode, *fnode, *tnode, *vptr, *vinc, *fptr, *finc;
 };
 
+// Pointwise Jacobian coefficients (weighted; volume flux derivatives pulled
+// back to the sub-tet's reference axes e), stored coefficient-major with the
+// point index fastest ([n_macro][TET_CV][G], [n_macro][TET_CF][FP]) so that
+// the lanes of a wave, one point each, read contiguous memory:
+//   volume point, TET_CV coefficients:
+//     [5k + l]                     w (alpha_t + alpha_ps) du_k/dv_l
+//     [25 + 25e + 5k + l]          w sum_i BiT_s[i][e] sum_d invJ[i][d] d(F + G)_kd/dv_l
+//     [100 + 25(3e + j) + 5k + l]  w sum_i BiT_s[i][e] sum_d invJ[i][d] dG_kd/dq_lj
+//   face point, TET_CF coefficients:
+//     [5k + l]                     ws d(Fhat + Ghat)_k/dv_l
+//     [25 + 5k + l]                ws d(Fhat + Ghat)_k/dvhat_l
+//     [50 + 25j + 5k + l]          ws dGhat_k/dq_lj
+constexpr int TET_CV = 325, TET_CF = 125;
+
+// Tables of the coefficient-based columns (MODE 2).
+struct TetColTab {
+    const double *coefV, *coefF;      // [n_macro][TET_CV][G], [n_macro][TET_CF][FP]
+    const double *ED, *EDf;           // (Phi M^-1 C_i)[point][b] as [3][n][G], [3][n][FP]
+    const double *EH, *EHf;           // (Phi M^-1 Ch_f)[point][c] as [4][nf][G], [4][nf][FP]
+    int64_t m0;                       // first macro of the launch (blockIdx.y counts from it)
+    const int *vloc, *tloc, *fidx;    // [8][n] local index of a macro node in a sub-tet (-1: none),
+                                      // [4][nf] of a face node in a sub-triangle, [4][n] face node of a macro node
+};
+
 template <int P, bool LIN>
-struct TetLds {   // LIN: MODE 1 or 2
+struct TetLds {   // LIN: the tangent arrays of MODE 1
     using D = TetDims<P>;
     static constexpr int PT = (20 * D::G > 10 * D::FP) ? 20 * D::G : 10 * D::FP;
     static constexpr int SC = (8 * 5 * D::ns > 2 * 80 * D::nfs) ? 8 * 5 * D::ns : 2 * 80 * D::nfs;
@@ -165,7 +194,8 @@ __device__ void tet_rq(const TetDevTab& T, const double* gm, const double* invJ,
 // direction (dq, dv, dvhat), dq = dqin or the weak gradient of (dv, dvhat);
 // entropy is not written and may be null.  MODE 2: column blockIdx.y of J_r
 // into Bc (bordered matrices, ld and per_macro doubles apart), rows in the
-// order V then Vhat; R_q, R_v, R_vh, entropy unused.
+// order V then Vhat, from the coefficients and tables in ct; the state
+// arguments, R_q, R_v, R_vh and entropy are unused.
 template <int P, int MODE>
 __global__ void __launch_bounds__(TET_THREADS)
 k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const double* __restrict__ qin,
@@ -173,8 +203,9 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
       const double* __restrict__ dqin, const double* __restrict__ geo, TetDevTab T, DevParams pr,
       const uint8_t* __restrict__ face_bc, double* __restrict__ R_q, double* __restrict__ R_v,
       double* __restrict__ R_vh, double* __restrict__ entropy, int32_t* __restrict__ status,
-      double* __restrict__ Bc, int ld, int64_t per_macro) {
-    constexpr bool LIN = MODE != 0;
+      double* __restrict__ Bc, int ld, int64_t per_macro, TetColTab ct) {
+    constexpr bool LIN = MODE == 1;
+    constexpr bool COL = MODE == 2;    // one column of the bordered matrix
     using D = TetDims<P>;
     using S = typename std::conditional<LIN, dual<1>, double>::type;
     using SC = TetScalar<S>;
@@ -182,7 +213,8 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
     extern __shared__ __align__(16) unsigned char smem[];
     TetLds<P, LIN>& L = *reinterpret_cast<TetLds<P, LIN>*>(smem);
     const int tid = threadIdx.x;
-    const int64_t m = blockIdx.x;
+    // columns: blockIdx.x is the column, so the columns of one macro run back to back (L2 reuse)
+    const int64_t m = COL ? ct.m0 + blockIdx.y : (int64_t)blockIdx.x;
     const double* gm = geo + m * TET_GEO;
     double invJ[9];
 #pragma unroll
@@ -191,17 +223,17 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
     bool bad_phys = false, bad_fin = false;
 
     // ---- 1. state, weak gradient, R_Q (tangents: the same linear maps)
-    const int col = (MODE == 2) ? (int)blockIdx.y : -1;
+    // (MODE 2 needs none of it: the coefficients hold the state's part)
+    const int col = COL ? (int)blockIdx.x : -1;
+    if constexpr (MODE != 2) {
     for (int i = tid; i < 5 * n; i += TET_THREADS) {
         (&L.v[0][0])[i] = v[m * 5 * n + i];
         if constexpr (MODE == 1) (&L.dv[0][0])[i] = dvin[m * 5 * n + i];
-        else if constexpr (MODE == 2) (&L.dv[0][0])[i] = (i == col) ? 1.0 : 0.0;
         else (&L.vo[0][0])[i] = v_old[m * 5 * n + i];
     }
     for (int i = tid; i < 20 * nf; i += TET_THREADS) {
         (&L.vh[0][0][0])[i] = vhat[m * 20 * nf + i];
         if constexpr (MODE == 1) (&L.dvh[0][0][0])[i] = dvhin[m * 20 * nf + i];
-        else if constexpr (MODE == 2) (&L.dvh[0][0][0])[i] = (i == col - 5 * n) ? 1.0 : 0.0;
     }
     if (qin)
         for (int i = tid; i < 15 * n; i += TET_THREADS) (&L.q[0][0])[i] = qin[m * 15 * n + i];
@@ -212,14 +244,62 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
     __syncthreads();
     if (!qin) tet_lift<P>(T, gm, invJ, adet, L.v, L.vh, L.q);
     if constexpr (LIN) {
-        if (MODE == 2 || !dqin) tet_lift<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq);
+        if (!dqin) tet_lift<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq);
     }
     __syncthreads();
     if constexpr (MODE == 1) tet_rq<P>(T, gm, invJ, adet, L.dv, L.dvh, L.dq, R_q + m * 15 * n);
     else if constexpr (MODE == 0) tet_rq<P>(T, gm, invJ, adet, L.v, L.vh, L.q, R_q + m * 15 * n);
+    }   // MODE != 2
+
+    // unit direction of a MODE 2 column: V column (l, b) or trace column (f0, l, c0)
+    int cl = 0, cb = -1, cf0 = 0, cc0 = 0;
+    if constexpr (MODE == 2) {
+        if (col < 5 * n) {
+            cl = col / n;
+            cb = col - cl * n;
+        } else {
+            const int r = col - 5 * n;
+            cf0 = r / (5 * nf);
+            cl = (r / nf) % 5;
+            cc0 = r % nf;
+        }
+    }
 
     // ---- 2. volume points
     const double g = pr.gamma;
+    if constexpr (MODE == 2) {
+        for (int gp = tid; gp < D::G; gp += TET_THREADS) {
+            const int s = gp / Gs, gl = gp - s * Gs;
+            double dv = 0.0, dq[3];
+            if (cb >= 0) {
+                const int bl = ct.vloc[s * n + cb];
+                if (bl >= 0) dv = T.phi[gl * ns + bl];
+                double e[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) e[i] = ct.ED[((int64_t)i * n + cb) * D::G + gp];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dq[j] = -(invJ[0 * 3 + j] * e[0] + invJ[1 * 3 + j] * e[1] + invJ[2 * 3 + j] * e[2]);
+            } else {
+                const double eh = ct.EH[((int64_t)cf0 * nf + cc0) * D::G + gp] * (gm[22 + cf0] / adet);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dq[j] = eh * gm[10 + 3 * cf0 + j];
+            }
+            const double* C = ct.coefV + (int64_t)m * TET_CV * D::G + gp;   // coefficient i at C[i * G]
+            double* o = L.pt + gp * 20;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                o[k] = C[(5 * k + cl) * D::G] * dv;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    double x = C[(25 + 25 * e + 5 * k + cl) * D::G] * dv;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) x += C[(100 + 25 * (3 * e + j) + 5 * k + cl) * D::G] * dq[j];
+                    o[5 + 3 * k + e] = x;
+                }
+                if (!isfinite(o[k]) || !isfinite(o[5 + 3 * k])) bad_fin = true;
+            }
+        }
+    } else
     for (int gp = tid; gp < D::G; gp += TET_THREADS) {
         const int s = gp / Gs, gl = gp - s * Gs;
         double vv0[5] = {0, 0, 0, 0, 0}, vvd[5] = {0, 0, 0, 0, 0}, vvo[5] = {0, 0, 0, 0, 0};
@@ -319,6 +399,44 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
 
     // ---- 4. face points
     double ent = 0.0;
+    if constexpr (MODE == 2) {
+        for (int fp = tid; fp < D::FP; fp += TET_THREADS) {
+            const int f = fp / (4 * Ss), r = fp - f * 4 * Ss, tr = r / Ss, sl = r - tr * Ss;
+            double dv = 0.0, dvh = 0.0, dq[3];
+            if (cb >= 0) {
+                const int cf = ct.fidx[f * n + cb];
+                if (cf >= 0) {
+                    const int bl = ct.tloc[tr * nf + cf];
+                    if (bl >= 0) dv = T.psi[sl * nfs + bl];
+                }
+                double e[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) e[i] = ct.EDf[((int64_t)i * n + cb) * D::FP + fp];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dq[j] = -(invJ[0 * 3 + j] * e[0] + invJ[1 * 3 + j] * e[1] + invJ[2 * 3 + j] * e[2]);
+            } else {
+                if (f == cf0) {
+                    const int bl = ct.tloc[tr * nf + cc0];
+                    if (bl >= 0) dvh = T.psi[sl * nfs + bl];
+                }
+                const double eh = ct.EHf[((int64_t)cf0 * nf + cc0) * D::FP + fp] * (gm[22 + cf0] / adet);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) dq[j] = eh * gm[10 + 3 * cf0 + j];
+            }
+            const double* C = ct.coefF + (int64_t)m * TET_CF * D::FP + fp;   // coefficient i at C[i * FP]
+            const double ws = T.wf[sl] * gm[22 + f];
+            double* o = L.pt + fp * 10;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                double x = C[(5 * k + cl) * D::FP] * dv + C[(25 + 5 * k + cl) * D::FP] * dvh;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) x += C[(50 + 25 * j + 5 * k + cl) * D::FP] * dq[j];
+                o[k] = x;
+                o[5 + k] = (k == cl) ? ws * dvh : 0.0;
+                if (!isfinite(x)) bad_fin = true;
+            }
+        }
+    } else
     for (int fp = tid; fp < D::FP; fp += TET_THREADS) {
         const int f = fp / (4 * Ss), r = fp - f * 4 * Ss, tr = r / Ss, sl = r - tr * Ss;
         double vh0[5] = {0, 0, 0, 0, 0}, vs0[5] = {0, 0, 0, 0, 0}, qq0[5][3] = {};
@@ -383,12 +501,12 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
             if (!isfinite(o[k])) bad_fin = true;
         }
     }
-    if constexpr (!LIN) {
+    if constexpr (MODE == 0) {
         for (int off = 32; off > 0; off >>= 1) ent += __shfl_down(ent, off, 64);
         if ((tid & 63) == 0) L.red[tid >> 6] = ent;
     }
     __syncthreads();
-    if constexpr (!LIN) {
+    if constexpr (MODE == 0) {
         if (tid == 0) entropy[m] = L.red[0] + L.red[1] + L.red[2] + L.red[3];
     }
 
@@ -420,13 +538,13 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
             }
             L.rv[k][T.fnode[f * nf + c]] += acc;
             const double o = (wall && k > 0) ? accw : acc;
-            if constexpr (MODE == 2) Bc[m * per_macro + (int64_t)(5 * n + (f * 5 + k) * nf + c) * ld + col] = o;
+            if constexpr (COL) Bc[m * per_macro + (int64_t)(5 * n + (f * 5 + k) * nf + c) * ld + col] = o;
             else R_vh[((m * 4 + f) * 5 + k) * nf + c] = o;
         }
         __syncthreads();
     }
     for (int i = tid; i < 5 * n; i += TET_THREADS) {
-        if constexpr (MODE == 2) Bc[m * per_macro + (int64_t)i * ld + col] = (&L.rv[0][0])[i];
+        if constexpr (COL) Bc[m * per_macro + (int64_t)i * ld + col] = (&L.rv[0][0])[i];
         else R_v[m * 5 * n + i] = (&L.rv[0][0])[i];
     }
 
@@ -435,7 +553,7 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
     if (flag) {
         const int any_phys = __syncthreads_or(bad_phys ? 1 : 0);
         const double nan = __builtin_nan("");
-        if constexpr (MODE == 2) {
+        if constexpr (COL) {
             for (int i = tid; i < 5 * n + 20 * nf; i += TET_THREADS) Bc[m * per_macro + (int64_t)i * ld + col] = nan;
         } else {
             for (int i = tid; i < 5 * n; i += TET_THREADS) R_v[m * 5 * n + i] = nan;
@@ -446,9 +564,198 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
             if (MODE == 0) entropy[m] = nan;
             if (status) status[m] = any_phys ? 5 : 6;
         }
-    } else if (MODE != 2 && tid == 0 && status) {
+    } else if (!COL && tid == 0 && status) {
         status[m] = 0;   // (column launches only ever raise a flag)
     }
+}
+
+// Pointwise Jacobian coefficients of every volume and face point of a macro
+// (layout at TET_CV / TET_CF above), at the state (v, vhat) with q its weak
+// gradient: derivatives in v and vhat by dual numbers (dual<5>, one pass per
+// seeded argument), derivatives in q by evaluating the viscous fluxes at unit
+// q, since they are linear in q.  A non-physical state raises the macro's
+// status (the residual launched before it has reset it).
+template <int P>
+__global__ void __launch_bounds__(TET_THREADS)
+k_tet_coef(const double* __restrict__ v, const double* __restrict__ vhat, const double* __restrict__ geo,
+           TetDevTab T, DevParams pr, double* __restrict__ coefV, double* __restrict__ coefF,
+           int32_t* __restrict__ status) {
+    using D = TetDims<P>;
+    constexpr int n = D::n, nf = D::nf, ns = D::ns, nfs = D::nfs, Gs = D::Gs, Ss = D::Ss;
+    extern __shared__ __align__(16) unsigned char smem[];
+    TetLds<P, false>& L = *reinterpret_cast<TetLds<P, false>*>(smem);
+    const int tid = threadIdx.x;
+    const int64_t m = blockIdx.x;
+    const double* gm = geo + m * TET_GEO;
+    double invJ[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) invJ[i] = gm[i];
+    const double adet = gm[9];
+    const double g = pr.gamma;
+    bool bad = false;
+    for (int i = tid; i < 5 * n; i += TET_THREADS) (&L.v[0][0])[i] = v[m * 5 * n + i];
+    for (int i = tid; i < 20 * nf; i += TET_THREADS) (&L.vh[0][0][0])[i] = vhat[m * 20 * nf + i];
+    __syncthreads();
+    tet_lift<P>(T, gm, invJ, adet, L.v, L.vh, L.q);
+    __syncthreads();
+
+    for (int gp = tid; gp < D::G; gp += TET_THREADS) {
+        const int s = gp / Gs, gl = gp - s * Gs;
+        double vv[5] = {0, 0, 0, 0, 0}, qq[5][3] = {};
+        for (int b = 0; b < ns; ++b) {
+            const double ph = T.phi[gl * ns + b];
+            const int a = T.vnode[s * ns + b];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                vv[k] += ph * L.v[k][a];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) qq[k][j] += ph * L.q[3 * k + j][a];
+            }
+        }
+        const double w = T.wv[gl] * adet;
+        const double* Bi = T.BiT + s * 9;
+        double K[3][3];   // K[d][e] = w sum_i BiT_s[i][e] invJ[i][d]
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+                K[d][e] = w * (Bi[0 * 3 + e] * invJ[0 * 3 + d] + Bi[1 * 3 + e] * invJ[1 * 3 + d] + Bi[2 * 3 + e] * invJ[2 * 3 + d]);
+        double* out = coefV + (int64_t)m * TET_CV * D::G + gp;   // coefficient i at out[i * G]
+        auto put = [&](int i, double x) { out[(int64_t)i * D::G] = x; };
+        dual<5> vd[5];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) vd[l] = seed_dual<5>(vv[l], l);
+        Prim<dual<5>> st;
+        primitive(vd, g, st);
+        if (!(vv[4] < 0.0) || !(st.rho.v > 0.0)) bad = true;
+        {
+            dual<5> u[5];
+            conservative(st, g, u);
+            const double c = (pr.alpha_t + pr.alpha_ps) * w;
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int l = 0; l < 5; ++l) put(5 * k + l, c * u[k].d[l]);
+        }
+        dual<5> qd[5][3];
+#pragma unroll
+        for (int l = 0; l < 5; ++l)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) qd[l][j] = make_dual<5>(qq[l][j]);
+        double acc[3][25];
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int i = 0; i < 25; ++i) acc[e][i] = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            dual<5> F[5];
+            euler_flux(st, g, d, F);
+            if (pr.viscous) {
+                dual<5> Gv[5];
+                viscous_flux(vd, qd, pr, d, Gv);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) F[k] = F[k] + Gv[k];
+            }
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+#pragma unroll
+                for (int k = 0; k < 5; ++k)
+#pragma unroll
+                    for (int l = 0; l < 5; ++l) acc[e][5 * k + l] += K[d][e] * F[k].d[l];
+        }
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int i = 0; i < 25; ++i) put(25 + 25 * e + i, acc[e][i]);
+        // G is linear in q: its q-derivative columns are G at unit q
+        for (int l = 0; l < 5; ++l)
+            for (int j = 0; j < 3; ++j) {
+                double Gd[3][5] = {};
+                if (pr.viscous) {
+                    double qu[5][3];
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) qu[a][0] = qu[a][1] = qu[a][2] = 0.0;
+                    qu[l][j] = 1.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) viscous_flux(vv, qu, pr, d, Gd[d]);
+                }
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+#pragma unroll
+                    for (int k = 0; k < 5; ++k)
+                        put(100 + 25 * (3 * e + j) + 5 * k + l, K[0][e] * Gd[0][k] + K[1][e] * Gd[1][k] + K[2][e] * Gd[2][k]);
+            }
+    }
+
+    for (int fp = tid; fp < D::FP; fp += TET_THREADS) {
+        const int f = fp / (4 * Ss), r = fp - f * 4 * Ss, tr = r / Ss, sl = r - tr * Ss;
+        double vh[5] = {0, 0, 0, 0, 0}, vs[5] = {0, 0, 0, 0, 0}, qq[5][3] = {};
+        for (int b = 0; b < nfs; ++b) {
+            const double ps = T.psi[sl * nfs + b];
+            const int c = T.tnode[tr * nfs + b];
+            const int a = T.fnode[f * nf + c];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                vh[k] += ps * L.vh[f][k][c];
+                vs[k] += ps * L.v[k][a];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) qq[k][j] += ps * L.q[3 * k + j][a];
+            }
+        }
+        const double nrm[3] = {gm[10 + 3 * f], gm[11 + 3 * f], gm[12 + 3 * f]};
+        double t1[3], t2[3];
+        face_frame(nrm, t1, t2);
+        const double ws = T.wf[sl] * gm[22 + f];
+        if (!(vh[4] < 0.0)) bad = true;
+        double* out = coefF + (int64_t)m * TET_CF * D::FP + fp;   // coefficient i at out[i * FP]
+        auto put = [&](int i, double x) { out[(int64_t)i * D::FP] = x; };
+#pragma unroll 1
+        for (int pass = 0; pass < 2; ++pass) {   // 0: d/dv, 1: d/dvhat
+            dual<5> a[5], b[5], F[5];
+#pragma unroll
+            for (int l = 0; l < 5; ++l) {
+                a[l] = (pass == 1) ? seed_dual<5>(vh[l], l) : make_dual<5>(vh[l]);
+                b[l] = (pass == 0) ? seed_dual<5>(vs[l], l) : make_dual<5>(vs[l]);
+            }
+            trace_flux_n(a, b, pr, nrm, t1, t2, F);
+            if (pr.viscous) {
+                dual<5> qd[5][3], Gh[5];
+#pragma unroll
+                for (int l = 0; l < 5; ++l)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) qd[l][j] = make_dual<5>(qq[l][j]);
+                viscous_trace_flux_n(a, b, qd, pr, nrm, Gh);
+#pragma unroll
+                for (int k = 0; k < 5; ++k) F[k] = F[k] + Gh[k];
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int l = 0; l < 5; ++l) put(25 * pass + 5 * k + l, ws * F[k].d[l]);
+        }
+        // Ghat = G(vhat, q).n - ...: linear in q
+        for (int l = 0; l < 5; ++l)
+            for (int j = 0; j < 3; ++j) {
+                double Gn[5] = {0, 0, 0, 0, 0};
+                if (pr.viscous) {
+                    double qu[5][3];
+#pragma unroll
+                    for (int a = 0; a < 5; ++a) qu[a][0] = qu[a][1] = qu[a][2] = 0.0;
+                    qu[l][j] = 1.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        double Gd[5];
+                        viscous_flux(vh, qu, pr, d, Gd);
+#pragma unroll
+                        for (int k = 0; k < 5; ++k) Gn[k] += nrm[d] * Gd[k];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < 5; ++k) put(50 + 25 * j + 5 * k + l, ws * Gn[k]);
+            }
+    }
+    if (__syncthreads_or(bad ? 1 : 0) && tid == 0 && status) status[m] = 5;
 }
 
 // Recovery of tetrahedral macros (eq. R2, R6): dV = U^-1 (y - U12 dVhat)

@@ -34,6 +34,10 @@ struct mehdg_tet_ctx {
     int32_t* d_ipiv = nullptr;     // [n_macro][N_V]
     double* d_tri = nullptr;       // [n_macro][tri]
     int32_t* d_perm = nullptr;     // [n_macro][perm]
+    double* d_coef = nullptr;      // pointwise Jacobian coefficients [n_macro][G][TET_CV] then [n_macro][FP][TET_CF]
+    double* d_ctab = nullptr;      // weak-gradient tables of the columns
+    int* d_citab = nullptr;        // local-index maps of the columns
+    TetColTab ct{};
     int64_t rows = 0, ld = 0, per_tri = 0, per_perm = 0;
     int stage = 0;                 // 0 nothing, 1 assembled, 2 condensed
 };
@@ -53,9 +57,14 @@ bool tet_allow_lds() {
     };
     return set(reinterpret_cast<const void*>(&k_tet<P, 0>), tet_lds<P, false>()) &&
            set(reinterpret_cast<const void*>(&k_tet<P, 1>), tet_lds<P, true>()) &&
-           set(reinterpret_cast<const void*>(&k_tet<P, 2>), tet_lds<P, true>()) &&
+           set(reinterpret_cast<const void*>(&k_tet<P, 2>), tet_lds<P, false>()) &&
+           set(reinterpret_cast<const void*>(&k_tet_coef<P>), tet_lds<P, false>()) &&
            set(reinterpret_cast<const void*>(&k_tet_recover<P>), sizeof(TetRecLds<P>));
 }
+
+// doubles of the pointwise coefficients per macro (volume part, total)
+int64_t tet_coef_volume(int p) { return (int64_t)8 * (p + 1) * (p + 1) * (p + 1) * TET_CV; }
+int64_t tet_coef_doubles(int p) { return tet_coef_volume(p) + (int64_t)16 * (p + 1) * (p + 1) * TET_CF; }
 
 // -B[:, NV + NH] = R: the right-hand-side column of the bordered matrices.
 __global__ void __launch_bounds__(256) k_tet_rhs(const double* __restrict__ R_v, const double* __restrict__ R_vh,
@@ -165,6 +174,9 @@ mehdg_err mehdg_tet_destroy(mehdg_tet_ctx* c) {
     (void)hipFree(c->d_ipiv);
     (void)hipFree(c->d_tri);
     (void)hipFree(c->d_perm);
+    (void)hipFree(c->d_coef);
+    (void)hipFree(c->d_ctab);
+    (void)hipFree(c->d_citab);
     delete c;
     return MEHDG_OK;
 }
@@ -218,6 +230,20 @@ mehdg_err mehdg_tet_create(const mehdg_tet_mesh* mesh, const mehdg_params* prm, 
     }
     c->dt = TetDevTab{dp[0], dp[1], dp[2], dp[3], dp[4], dp[5], dp[6], dp[7], dp[8], dp[9], dp[10], dp[11],
                       ip[0], ip[1], ip[2], ip[3], ip[4], ip[5], ip[6]};
+    std::vector<const double*> cdp;
+    std::vector<const int*> cip;
+    if (!upload<double>({&t.ED, &t.EDf, &t.EH, &t.EHf}, &c->d_ctab, cdp) ||
+        !upload<int>({&t.vloc, &t.tloc, &t.fidx}, &c->d_citab, cip)) {
+        mehdg_tet_destroy(c);
+        return MEHDG_ENOMEM;
+    }
+    c->ct.ED = cdp[0];
+    c->ct.EDf = cdp[1];
+    c->ct.EH = cdp[2];
+    c->ct.EHf = cdp[3];
+    c->ct.vloc = cip[0];
+    c->ct.tloc = cip[1];
+    c->ct.fidx = cip[2];
     const size_t gbytes = geo.size() * sizeof(double);
     if (hipMalloc(&c->d_geo, gbytes) != hipSuccess ||
         hipMemcpy(c->d_geo, geo.data(), gbytes, hipMemcpyHostToDevice) != hipSuccess ||
@@ -251,7 +277,7 @@ mehdg_err mehdg_tet_residual(mehdg_tet_ctx* c, const double* v, const double* vh
     const size_t lds = tet_lds_bytes<false>(c->p);
 #define MEHDG_TET_LAUNCH(PP)                                                                                   \
     hipLaunchKernelGGL((k_tet<PP, 0>), grid, block, lds, st, v, vhat, q, v_old, nullptr, nullptr, nullptr, c->d_geo, \
-                       c->dt, c->dp, c->d_bc, R_q, R_v, R_vhat, entropy, c->d_status, nullptr, 0, (int64_t)0)
+                       c->dt, c->dp, c->d_bc, R_q, R_v, R_vhat, entropy, c->d_status, nullptr, 0, (int64_t)0, TetColTab{})
     if (c->p == 1)
         MEHDG_TET_LAUNCH(1);
     else if (c->p == 2)
@@ -271,7 +297,7 @@ mehdg_err mehdg_tet_jvp(mehdg_tet_ctx* c, const double* v, const double* vhat, c
     const size_t lds = tet_lds_bytes<true>(c->p);
 #define MEHDG_TET_LAUNCH(PP)                                                                                  \
     hipLaunchKernelGGL((k_tet<PP, 1>), grid, block, lds, st, v, vhat, q, nullptr, dv, dvhat, dq, c->d_geo, c->dt, \
-                       c->dp, c->d_bc, JR_q, JR_v, JR_vhat, nullptr, c->d_status, nullptr, 0, (int64_t)0)
+                       c->dp, c->d_bc, JR_q, JR_v, JR_vhat, nullptr, c->d_status, nullptr, 0, (int64_t)0, TetColTab{})
     if (c->p == 1)
         MEHDG_TET_LAUNCH(1);
     else if (c->p == 2)
@@ -300,12 +326,15 @@ mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* c, const double* v, const double* vh
         if (hipMalloc(&c->d_B, (size_t)(M * c->rows * c->ld) * sizeof(double)) != hipSuccess ||
             hipMalloc(&c->d_ipiv, (size_t)(M * NV) * sizeof(int32_t)) != hipSuccess ||
             hipMalloc(&c->d_tri, (size_t)(M * c->per_tri) * sizeof(double)) != hipSuccess ||
-            hipMalloc(&c->d_perm, (size_t)(M * c->per_perm) * sizeof(int32_t)) != hipSuccess) {
+            hipMalloc(&c->d_perm, (size_t)(M * c->per_perm) * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc(&c->d_coef, (size_t)(M * tet_coef_doubles(c->p)) * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             (void)hipFree(c->d_B);
             (void)hipFree(c->d_ipiv);
             (void)hipFree(c->d_tri);
             (void)hipFree(c->d_perm);
+            (void)hipFree(c->d_coef);
+            c->d_coef = nullptr;
             c->d_B = nullptr;
             c->d_ipiv = nullptr;
             c->d_tri = nullptr;
@@ -320,18 +349,31 @@ mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* c, const double* v, const double* vh
     hipLaunchKernelGGL(k_tet_rhs, dim3((unsigned)c->n_macro), dim3(256), 0, st, R_v, R_vhat, NV, NH, (int)c->ld, per,
                        c->d_B);
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
-    const dim3 grid((unsigned)c->n_macro, (unsigned)(NV + NH)), block(TET_THREADS);
-    const size_t lds = tet_lds_bytes<true>(c->p);
-#define MEHDG_TET_LAUNCH(PP)                                                                                 \
-    hipLaunchKernelGGL((k_tet<PP, 2>), grid, block, lds, st, v, vhat, nullptr, nullptr, nullptr, nullptr,    \
-                       nullptr, c->d_geo, c->dt, c->dp, c->d_bc, nullptr, nullptr, nullptr, nullptr, c->d_status, \
-                       c->d_B, (int)c->ld, per)
-    if (c->p == 1)
+    // pointwise coefficients once per macro, then one column per workgroup
+    TetColTab ct = c->ct;
+    ct.coefV = c->d_coef;
+    ct.coefF = c->d_coef + c->n_macro * tet_coef_volume(c->p);
+    const dim3 block(TET_THREADS);
+    const size_t lds0 = tet_lds_bytes<false>(c->p);
+    // column launches: blockIdx.x the column, blockIdx.y the macro (at most 65535 per launch)
+    constexpr int64_t kMaxY = 65535;
+#define MEHDG_TET_LAUNCH(PP)                                                                                    \
+    hipLaunchKernelGGL(k_tet_coef<PP>, dim3((unsigned)c->n_macro), block, lds0, st, v, vhat, c->d_geo, c->dt,   \
+                       c->dp, const_cast<double*>(ct.coefV), const_cast<double*>(ct.coefF), c->d_status);        \
+    for (int64_t m0 = 0; m0 < c->n_macro; m0 += kMaxY) {                                                        \
+        ct.m0 = m0;                                                                                             \
+        const int64_t cnt = (c->n_macro - m0) < kMaxY ? (c->n_macro - m0) : kMaxY;                               \
+        hipLaunchKernelGGL((k_tet<PP, 2>), dim3((unsigned)(NV + NH), (unsigned)cnt), block, lds0, st, v, vhat,  \
+                           nullptr, nullptr, nullptr, nullptr, nullptr, c->d_geo, c->dt, c->dp, c->d_bc, nullptr, \
+                           nullptr, nullptr, nullptr, c->d_status, c->d_B, (int)c->ld, per, ct);                 \
+    }
+    if (c->p == 1) {
         MEHDG_TET_LAUNCH(1);
-    else if (c->p == 2)
+    } else if (c->p == 2) {
         MEHDG_TET_LAUNCH(2);
-    else
+    } else {
         MEHDG_TET_LAUNCH(3);
+    }
 #undef MEHDG_TET_LAUNCH
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     c->stage = 1;

@@ -47,6 +47,15 @@ struct TetTab {
     std::vector<int> vnode;     // [8][ns]      macro node of each sub-tet node
     std::vector<int> fnode;     // [4][nf]      macro node of each face node
     std::vector<int> tnode;     // [4][nfs]     face node of each sub-triangle node
+    std::vector<int> vloc;      // [8][n]       local index of a macro node in a sub-tet, or -1
+    std::vector<int> tloc;      // [4][nf]      local index of a face node in a sub-triangle, or -1
+    std::vector<int> fidx;      // [4][n]       face node of a macro node on face f, or -1
+    // weak-gradient tables of the coefficient-based columns (point orders of the kernels:
+    // volume point s*Gs + gl, face point (f*4 + tr)*Ss + sl)
+    std::vector<double> ED;     // [3][n][8 Gs]   (Phi M^-1 C_i)[g][b], point index fastest
+    std::vector<double> EDf;    // [3][n][16 Ss]  the same at the face points
+    std::vector<double> EH;     // [4][nf][8 Gs]  (Phi M^-1 Ch_f)[g][c]
+    std::vector<double> EHf;    // [4][nf][16 Ss]
     std::vector<int> vptr, vinc;   // CSR over macro nodes: entries s*ns + b with vnode[s][b] = a
     std::vector<int> fptr, finc;   // CSR over face nodes: entries t*nfs + b with tnode[t][b] = c
 };
@@ -420,6 +429,65 @@ inline bool build_tet_tables(int p, TetTab& t) {
                 double d = 0.0;
                 for (int c = 0; c < n; ++c) d += Mi[(size_t)a * n + c] * C[((size_t)i * n + c) * n + b];
                 t.DT[((size_t)i * n + b) * n + a] = d;
+            }
+    // local-index maps and the weak-gradient tables at the points
+    t.vloc.assign(8 * n, -1);
+    for (int s = 0; s < 8; ++s)
+        for (int b = 0; b < ns; ++b) t.vloc[s * n + t.vnode[s * ns + b]] = b;
+    t.tloc.assign(4 * nf, -1);
+    for (int tr = 0; tr < 4; ++tr)
+        for (int b = 0; b < nfs; ++b) t.tloc[tr * nf + t.tnode[tr * nfs + b]] = b;
+    t.fidx.assign(4 * n, -1);
+    for (int f = 0; f < 4; ++f)
+        for (int c = 0; c < nf; ++c) t.fidx[f * n + t.fnode[f * nf + c]] = c;
+    const int G = 8 * Gs, FP = 16 * Ss;
+    auto Dm = [&](int i, int a, int b) {   // (M^-1 C_i)[a][b]
+        double d = 0.0;
+        for (int c = 0; c < n; ++c) d += Mi[(size_t)a * n + c] * C[((size_t)i * n + c) * n + b];
+        return d;
+    };
+    auto Dhm = [&](int f, int a, int c) {  // (M^-1 Ch_f)[a][c]
+        double d = 0.0;
+        for (int b = 0; b < n; ++b) d += Mi[(size_t)a * n + b] * Ch[((size_t)f * n + b) * nf + c];
+        return d;
+    };
+    std::vector<double> Dfull((size_t)3 * n * n), Dhfull((size_t)4 * n * nf);
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) Dfull[((size_t)i * n + a) * n + b] = Dm(i, a, b);
+    for (int f = 0; f < 4; ++f)
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < nf; ++c) Dhfull[((size_t)f * n + a) * nf + c] = Dhm(f, a, c);
+    t.ED.assign((size_t)3 * G * n, 0.0);
+    t.EH.assign((size_t)4 * G * nf, 0.0);
+    for (int s = 0; s < 8; ++s)
+        for (int gl = 0; gl < Gs; ++gl) {
+            const int gp = s * Gs + gl;
+            for (int bl = 0; bl < ns; ++bl) {
+                const double ph = t.phi[(size_t)gl * ns + bl];
+                const int a = t.vnode[s * ns + bl];
+                for (int i = 0; i < 3; ++i)
+                    for (int b = 0; b < n; ++b) t.ED[((size_t)i * n + b) * G + gp] += ph * Dfull[((size_t)i * n + a) * n + b];
+                for (int f = 0; f < 4; ++f)
+                    for (int c = 0; c < nf; ++c) t.EH[((size_t)f * nf + c) * G + gp] += ph * Dhfull[((size_t)f * n + a) * nf + c];
+            }
+        }
+    t.EDf.assign((size_t)3 * FP * n, 0.0);
+    t.EHf.assign((size_t)4 * FP * nf, 0.0);
+    for (int f = 0; f < 4; ++f)
+        for (int tr = 0; tr < 4; ++tr)
+            for (int sl = 0; sl < Ss; ++sl) {
+                const int fp = (f * 4 + tr) * Ss + sl;
+                for (int bl = 0; bl < nfs; ++bl) {
+                    const double ps = t.psi[(size_t)sl * nfs + bl];
+                    const int a = t.fnode[f * nf + t.tnode[tr * nfs + bl]];
+                    for (int i = 0; i < 3; ++i)
+                        for (int b = 0; b < n; ++b)
+                            t.EDf[((size_t)i * n + b) * FP + fp] += ps * Dfull[((size_t)i * n + a) * n + b];
+                    for (int f2 = 0; f2 < 4; ++f2)
+                        for (int c = 0; c < nf; ++c)
+                            t.EHf[((size_t)f2 * nf + c) * FP + fp] += ps * Dhfull[((size_t)f2 * n + a) * nf + c];
+                }
             }
     t.ChT.assign((size_t)4 * nf * n, 0.0);
     t.DhT.assign((size_t)4 * nf * n, 0.0);
