@@ -104,6 +104,19 @@ struct TetLds {   // LIN: the tangent arrays of MODE 1
     double red[4];
 };
 
+// LDS of a MODE 2 (column) workgroup: no nodal state, the sub-tet basis
+// tables staged once for the test sums instead.
+template <int P>
+struct TetColLds {
+    using D = TetDims<P>;
+    static constexpr int PT = TetLds<P, false>::PT, SC = TetLds<P, false>::SC;
+    double rv[5][D::n];
+    double pt[PT];
+    double sc[SC];
+    double ph[D::Gs * D::ns], dph[3 * D::Gs * D::ns];
+    double red[4];
+};
+
 constexpr int TET_THREADS = 256;
 
 // value / tangent access for the two scalar types of the point phases
@@ -211,7 +224,8 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
     using SC = TetScalar<S>;
     constexpr int n = D::n, nf = D::nf, ns = D::ns, nfs = D::nfs, Gs = D::Gs, Ss = D::Ss;
     extern __shared__ __align__(16) unsigned char smem[];
-    TetLds<P, LIN>& L = *reinterpret_cast<TetLds<P, LIN>*>(smem);
+    using Lds = typename std::conditional<MODE == 2, TetColLds<P>, TetLds<P, LIN>>::type;
+    Lds& L = *reinterpret_cast<Lds*>(smem);
     const int tid = threadIdx.x;
     // columns: blockIdx.x is the column, so the columns of one macro run back to back (L2 reuse)
     const int64_t m = COL ? ct.m0 + blockIdx.y : (int64_t)blockIdx.x;
@@ -253,7 +267,13 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
 
     // unit direction of a MODE 2 column: V column (l, b) or trace column (f0, l, c0)
     int cl = 0, cb = -1, cf0 = 0, cc0 = 0;
+    const double* PHI = T.phi;     // basis tables of the test sums (staged in LDS for MODE 2)
+    const double* DPHI = T.dphi;
     if constexpr (MODE == 2) {
+        for (int i = tid; i < Gs * ns; i += TET_THREADS) L.ph[i] = T.phi[i];
+        for (int i = tid; i < 3 * Gs * ns; i += TET_THREADS) L.dph[i] = T.dphi[i];
+        PHI = L.ph;
+        DPHI = L.dph;
         if (col < 5 * n) {
             cl = col / n;
             cb = col - cl * n;
@@ -380,8 +400,8 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
         double acc = 0.0;
         for (int gl = 0; gl < Gs; ++gl) {
             const double* o = L.pt + (s * Gs + gl) * 20;
-            acc += o[k] * T.phi[gl * ns + b] - o[5 + 3 * k + 0] * T.dphi[(0 * Gs + gl) * ns + b] -
-                   o[5 + 3 * k + 1] * T.dphi[(1 * Gs + gl) * ns + b] - o[5 + 3 * k + 2] * T.dphi[(2 * Gs + gl) * ns + b];
+            acc += o[k] * PHI[gl * ns + b] - o[5 + 3 * k + 0] * DPHI[(0 * Gs + gl) * ns + b] -
+                   o[5 + 3 * k + 1] * DPHI[(1 * Gs + gl) * ns + b] - o[5 + 3 * k + 2] * DPHI[(2 * Gs + gl) * ns + b];
         }
         L.sc[i] = acc;
     }

@@ -57,7 +57,7 @@ bool tet_allow_lds() {
     };
     return set(reinterpret_cast<const void*>(&k_tet<P, 0>), tet_lds<P, false>()) &&
            set(reinterpret_cast<const void*>(&k_tet<P, 1>), tet_lds<P, true>()) &&
-           set(reinterpret_cast<const void*>(&k_tet<P, 2>), tet_lds<P, false>()) &&
+           set(reinterpret_cast<const void*>(&k_tet<P, 2>), sizeof(TetColLds<P>)) &&
            set(reinterpret_cast<const void*>(&k_tet_coef<P>), tet_lds<P, false>()) &&
            set(reinterpret_cast<const void*>(&k_tet_recover<P>), sizeof(TetRecLds<P>));
 }
@@ -355,6 +355,7 @@ mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* c, const double* v, const double* vh
     ct.coefF = c->d_coef + c->n_macro * tet_coef_volume(c->p);
     const dim3 block(TET_THREADS);
     const size_t lds0 = tet_lds_bytes<false>(c->p);
+    const size_t ldsc = c->p == 1 ? sizeof(TetColLds<1>) : c->p == 2 ? sizeof(TetColLds<2>) : sizeof(TetColLds<3>);
     // column launches: blockIdx.x the column, blockIdx.y the macro (at most 65535 per launch)
     constexpr int64_t kMaxY = 65535;
 #define MEHDG_TET_LAUNCH(PP)                                                                                    \
@@ -363,7 +364,7 @@ mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* c, const double* v, const double* vh
     for (int64_t m0 = 0; m0 < c->n_macro; m0 += kMaxY) {                                                        \
         ct.m0 = m0;                                                                                             \
         const int64_t cnt = (c->n_macro - m0) < kMaxY ? (c->n_macro - m0) : kMaxY;                               \
-        hipLaunchKernelGGL((k_tet<PP, 2>), dim3((unsigned)(NV + NH), (unsigned)cnt), block, lds0, st, v, vhat,  \
+        hipLaunchKernelGGL((k_tet<PP, 2>), dim3((unsigned)(NV + NH), (unsigned)cnt), block, ldsc, st, v, vhat,  \
                            nullptr, nullptr, nullptr, nullptr, nullptr, c->d_geo, c->dt, c->dp, c->d_bc, nullptr, \
                            nullptr, nullptr, nullptr, c->d_status, c->d_B, (int)c->ld, per, ct);                 \
     }
