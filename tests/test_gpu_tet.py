@@ -18,7 +18,11 @@ the oracle (oracle.forms on oracle.tet geometry).
 * the local work of a Newton step (mehdg_tet_assemble, _condense, _recover)
   against oracle.forms.condense and oracle.local.recover: Ahat, bhat, dv,
   dq per macro normwise relative <= 1e-12, p = 1, 2, 3, walls; and the call
-  order (ESTATE).
+  order (ESTATE);
+* the benchmark's tetrahedral workloads at full size (1296-macro step, 10368-
+  macro residual), sampled macros against the oracle; the Mach 0.1 residual
+  R_V is bounded by max(1e-12, 10x the oracle's own change under one-ulp
+  input noise), measured in the test (about 6e-13).
 """
 import numpy as np
 import pytest
@@ -238,3 +242,52 @@ def test_tet_step_call_order():
         ctx.recover(empty(S["R_q"]), empty(S["vhat"]), empty(S["dv"]), empty(S["dq"]))
     assert ex.value.code == 4
     ctx.close()
+
+
+def test_tet_full_size_sampled_against_oracle():
+    """The benchmark's tetrahedral workloads at full size, in the launch shapes
+    bench.py times: the step on 6^3 cubes x 6 = 1296 p = 3 macros and the
+    residual on 12^3 cubes x 6 = 10368 macros, two sampled macros of each
+    against the oracle (plus finite, flag-free outputs everywhere)."""
+    from oracle import local
+    from paper_2507_22195_amd import mehdg
+    w = W.tet_tgv_workload(shape=(6, 6, 6), p=3, M0=0.1, Re=1600.0, flux="KEPES", seed_v=61, seed_vh=62)
+    dvh = 1e-2 * np.random.default_rng(9).standard_normal(w.vhat.shape)
+    banner(f"tet step full size: {w.n_macro} macros, p=3, KEPES")
+    got = _step(w, w.params, None, dvh)
+    for k in ("Ahat", "bhat", "dv", "dq"):
+        assert np.all(np.isfinite(got[k])), k
+    idx = [17, 1201]
+    ref = forms.condense(tet.TetGeometry(3, w.mesh.X[idx]), w.v[idx], w.vhat[idx], w.v_old[idx], w.params)
+    rdv, rdq = local.recover(ref, dvh[idx])
+    errs = dict(Ahat=rel_err(got["Ahat"][idx], ref["Ahat"]), bhat=rel_err(got["bhat"][idx], ref["bhat"]),
+                dv=rel_err(got["dv"][idx], rdv), dq=rel_err(got["dq"][idx], rdq))
+    banner(f"  sampled errors {errs}")
+    for k, e in errs.items():
+        assert e <= TOL, (k, e)
+    wr = W.tet_tgv_workload(shape=(12, 12, 12), p=3, M0=0.1, Re=1600.0, flux="KEPES", seed_v=61, seed_vh=62)
+    banner(f"tet residual full size: {wr.n_macro} macros")
+    rc, st, r = _run(wr, wr.mesh.X)
+    assert rc == 0, st
+    idx = [5, 9999]
+    geo = tet.TetGeometry(3, wr.mesh.X[idx])
+    v, vh, vo = wr.v[idx], wr.vhat[idx], wr.v_old[idx]
+    ref = forms.residual(geo, v, vh, vo, wr.params)
+    # At Mach 0.1 R_V is a small difference of large flux terms: the oracle's
+    # own R_V moves by ~6e-13 (relative) under one-ulp noise on (v, vhat).
+    # The bound is max(1e-12, 10x that measured change), per macro.
+    rng = np.random.default_rng(13)
+    floor = {k: np.zeros(2) for k in ("R_v", "R_vhat")}
+    for _ in range(2):
+        ulp = lambda x: x * (1.0 + 2.2e-16 * rng.choice([-1.0, 1.0], x.shape))
+        r2 = forms.residual(geo, ulp(v), ulp(vh), vo, wr.params)
+        for k in floor:
+            d = np.linalg.norm((r2[k] - ref[k]).reshape(2, -1), axis=1)
+            floor[k] = np.maximum(floor[k], 10.0 * d)
+    for k in ("R_v", "R_vhat"):
+        assert np.all(np.isfinite(r[k])), k
+        num = np.linalg.norm((r[k][idx] - ref[k]).reshape(2, -1), axis=1)
+        den = np.linalg.norm(ref[k].reshape(2, -1), axis=1)
+        bound = np.maximum(TOL * den, floor[k])
+        banner(f"  {k}: errors {num / den}, bounds {bound / den}")
+        assert np.all(num <= bound), (k, num / den, bound / den)
