@@ -28,11 +28,11 @@
 // phases 1, 3 and 5 are linear and run unchanged on the tangents
 // (dq, dv, dvhat); phases 2 and 4 evaluate the pointwise physics in dual
 // numbers seeded with the interpolated tangents and keep only the tangent
-// parts.  MODE 2 is MODE 1 in the unit direction of column j = blockIdx.y of
-// (dv, dvhat), with dq the weak gradient: column j of the reduced Jacobian
-// J_r, written into column j of the macro's bordered matrix.  With q the weak
-// gradient (R_Q = 0), the bordered matrix of the condensation (eq. R3-R5),
-// [[S, -Y, r_V], [X, A', r_hat]], is exactly [J_r | -R]:
+// parts.  MODE 2 writes column j = blockIdx.x of the reduced Jacobian J_r
+// (the JVP in the unit direction of column j of (dv, dvhat), dq the weak
+// gradient) into column j of the bordered matrix of macro m0 + blockIdx.y.
+// With q the weak gradient (R_Q = 0), the bordered matrix of the condensation
+// (eq. R3-R5), [[S, -Y, r_V], [X, A', r_hat]], is exactly [J_r | -R]:
 //   S = A_vv - A_vq A_qq^-1 A_qv,  -Y = A_vvh - A_vq A_qq^-1 A_qvh, and so on.
 // MODE 2 takes the pointwise Jacobian coefficients that k_tet_coef stores once
 // per macro: the tangent at a point is the coefficient block times the unit
@@ -205,10 +205,10 @@ __device__ void tet_rq(const TetDevTab& T, const double* gm, const double* invJ,
 // MODE 0: residual (R_q, R_v, R_vh, entropy) at (q, v, vhat) with q = qin or
 // the weak gradient.  MODE 1: the tangents (JR_q, JR_v, JR_vh) in the
 // direction (dq, dv, dvhat), dq = dqin or the weak gradient of (dv, dvhat);
-// entropy is not written and may be null.  MODE 2: column blockIdx.y of J_r
-// into Bc (bordered matrices, ld and per_macro doubles apart), rows in the
-// order V then Vhat, from the coefficients and tables in ct; the state
-// arguments, R_q, R_v, R_vh and entropy are unused.
+// entropy is not written and may be null.  MODE 2: column blockIdx.x of J_r
+// of macro ct.m0 + blockIdx.y into Bc (bordered matrices, ld and per_macro
+// doubles apart), rows in the order V then Vhat, from the coefficients and
+// tables in ct; the state arguments, R_q, R_v, R_vh and entropy are unused.
 template <int P, int MODE>
 __global__ void __launch_bounds__(TET_THREADS)
 k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const double* __restrict__ qin,
