@@ -105,11 +105,15 @@ struct TetLds {   // LIN: the tangent arrays of MODE 1
 };
 
 // LDS of a MODE 2 (column) workgroup: no nodal state, the sub-tet basis
-// tables staged once for the test sums instead.
+// tables staged once for the test sums instead, and the volume points held
+// for SB sub-tets at a time (at p = 3 two, which keeps the total under 80 KB:
+// two workgroups per CU).
 template <int P>
 struct TetColLds {
     using D = TetDims<P>;
-    static constexpr int PT = TetLds<P, false>::PT, SC = TetLds<P, false>::SC;
+    static constexpr int SB = (P == 3) ? 2 : 8;
+    static constexpr int PT = (20 * SB * D::Gs > 10 * D::FP) ? 20 * SB * D::Gs : 10 * D::FP;
+    static constexpr int SC = TetLds<P, false>::SC;
     double rv[5][D::n];
     double pt[PT];
     double sc[SC];
@@ -288,7 +292,11 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
     // ---- 2. volume points
     const double g = pr.gamma;
     if constexpr (MODE == 2) {
-        for (int gp = tid; gp < D::G; gp += TET_THREADS) {
+      // the points of SB sub-tets at a time, then their test sums (phase 3)
+      constexpr int SB = TetColLds<P>::SB;
+      for (int s0 = 0; s0 < 8; s0 += SB) {
+        for (int q = tid; q < SB * Gs; q += TET_THREADS) {
+            const int gp = s0 * Gs + q;
             const int s = gp / Gs, gl = gp - s * Gs;
             double dv = 0.0, dq[3];
             if (cb >= 0) {
@@ -305,7 +313,7 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
                 for (int j = 0; j < 3; ++j) dq[j] = eh * gm[10 + 3 * cf0 + j];
             }
             const double* C = ct.coefV + (int64_t)m * TET_CV * D::G + gp;   // coefficient i at C[i * G]
-            double* o = L.pt + gp * 20;
+            double* o = L.pt + q * 20;
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 o[k] = C[(5 * k + cl) * D::G] * dv;
@@ -319,7 +327,20 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
                 if (!isfinite(o[k]) || !isfinite(o[5 + 3 * k])) bad_fin = true;
             }
         }
-    } else
+        __syncthreads();
+        for (int i = tid; i < SB * 5 * ns; i += TET_THREADS) {
+            const int sl = i / (5 * ns), r = i - sl * 5 * ns, k = r / ns, b = r - k * ns;
+            double acc = 0.0;
+            for (int gl = 0; gl < Gs; ++gl) {
+                const double* o = L.pt + (sl * Gs + gl) * 20;
+                acc += o[k] * PHI[gl * ns + b] - o[5 + 3 * k + 0] * DPHI[(0 * Gs + gl) * ns + b] -
+                       o[5 + 3 * k + 1] * DPHI[(1 * Gs + gl) * ns + b] - o[5 + 3 * k + 2] * DPHI[(2 * Gs + gl) * ns + b];
+            }
+            L.sc[(s0 + sl) * 5 * ns + r] = acc;
+        }
+        __syncthreads();
+      }
+    } else {
     for (int gp = tid; gp < D::G; gp += TET_THREADS) {
         const int s = gp / Gs, gl = gp - s * Gs;
         double vv0[5] = {0, 0, 0, 0, 0}, vvd[5] = {0, 0, 0, 0, 0}, vvo[5] = {0, 0, 0, 0, 0};
@@ -406,6 +427,7 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
         L.sc[i] = acc;
     }
     __syncthreads();
+    }   // MODE != 2
     for (int i = tid; i < 5 * n; i += TET_THREADS) {
         const int k = i / n, a = i - k * n;
         double acc = 0.0;
