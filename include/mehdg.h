@@ -380,6 +380,15 @@ mehdg_err mehdg_tet_jvp(mehdg_tet_ctx* ctx, const double* v, const double* vhat,
  * state, non-finite values, zero pivot: mehdg_tet_status) get NaN outputs. */
 mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* ctx, const double* v, const double* vhat, const double* v_old,
                              double* R_q, double* R_v, double* R_vhat, double* entropy, mehdg_stream stream);
+/* Reduced vector-Jacobian product at the state of the last mehdg_tet_assemble,
+ * before mehdg_tet_condense (else ESTATE): [g_v; g_vhat] = J_r^T [w_v; w_vhat],
+ * the gradient of w_v.R_V + w_vhat.R_Vhat in (v, vhat) with q the weak
+ * gradient (the transpose of mehdg_tet_jvp with dq = NULL, pseudo-time term
+ * included), read from the assembled bordered matrices.  w_v, g_v
+ * [n_macro][5][n]; w_vhat, g_vhat [n_macro][4][5][nf]; device pointers;
+ * asynchronous on ``stream``. */
+mehdg_err mehdg_tet_vjp(mehdg_tet_ctx* ctx, const double* w_v, const double* w_vhat, double* g_v,
+                        double* g_vhat, mehdg_stream stream);
 mehdg_err mehdg_tet_condense(mehdg_tet_ctx* ctx, double* Ahat, double* bhat, mehdg_stream stream);
 mehdg_err mehdg_tet_recover(mehdg_tet_ctx* ctx, const double* R_q, const double* dvhat, double* dv,
                             double* dq, mehdg_stream stream);

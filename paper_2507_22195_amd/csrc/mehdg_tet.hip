@@ -62,6 +62,36 @@ bool tet_allow_lds() {
            set(reinterpret_cast<const void*>(&k_tet_recover<P>), sizeof(TetRecLds<P>));
 }
 
+// g = J_r^T w from the assembled bordered matrices (before the condensation
+// overwrites them): g[j] = sum_i B[i][j] w[i] over the rows i < NV + NH; one
+// workgroup per macro, lanes along the columns (coalesced row reads).
+__global__ void __launch_bounds__(256) k_tet_vjp_b(const double* __restrict__ B, const double* __restrict__ w_v,
+                                                   const double* __restrict__ w_h, int NV, int NH, int ld,
+                                                   int64_t per_macro, double* __restrict__ g_v,
+                                                   double* __restrict__ g_h) {
+    const int64_t m = blockIdx.x;
+    const int rows = NV + NH;
+    const double* Bm = B + m * per_macro;
+    for (int j0 = 0; j0 < rows; j0 += 4 * blockDim.x) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < rows; ++i) {
+            const double wi = i < NV ? w_v[m * NV + i] : w_h[m * NH + i - NV];
+            const double* row = Bm + (int64_t)i * ld;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u * blockDim.x + threadIdx.x;
+                if (j < rows) acc[u] += row[j] * wi;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u * blockDim.x + threadIdx.x;
+            if (j < NV) g_v[m * NV + j] = acc[u];
+            else if (j < rows) g_h[m * NH + j - NV] = acc[u];
+        }
+    }
+}
+
 // doubles of the pointwise coefficients per macro (volume part, total)
 int64_t tet_coef_volume(int p) { return (int64_t)8 * (p + 1) * (p + 1) * (p + 1) * TET_CV; }
 int64_t tet_coef_doubles(int p) { return tet_coef_volume(p) + (int64_t)16 * (p + 1) * (p + 1) * TET_CF; }
@@ -379,6 +409,17 @@ mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* c, const double* v, const double* vh
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     c->stage = 1;
     return MEHDG_OK;
+}
+
+mehdg_err mehdg_tet_vjp(mehdg_tet_ctx* c, const double* w_v, const double* w_vhat, double* g_v, double* g_vhat,
+                        mehdg_stream stream) {
+    if (!c || !w_v || !w_vhat || !g_v || !g_vhat) return MEHDG_EINVAL;
+    if (c->stage != 1) return MEHDG_ESTATE;
+    int64_t sz[5];
+    (void)mehdg_tet_sizes(c->p, sz);
+    hipLaunchKernelGGL(k_tet_vjp_b, dim3((unsigned)c->n_macro), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       c->d_B, w_v, w_vhat, (int)sz[2], (int)sz[4], (int)c->ld, c->rows * c->ld, g_v, g_vhat);
+    return hipGetLastError() == hipSuccess ? MEHDG_OK : MEHDG_EHIP;
 }
 
 mehdg_err mehdg_tet_condense(mehdg_tet_ctx* c, double* Ahat, double* bhat, mehdg_stream stream) {

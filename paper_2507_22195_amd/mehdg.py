@@ -101,9 +101,10 @@ def load(path: str = LIB_PATH):
     lib.mehdg_tet_assemble.argtypes = [vp] + [vp] * 7 + [vp]
     lib.mehdg_tet_condense.argtypes = [vp, vp, vp, vp]
     lib.mehdg_tet_recover.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mehdg_tet_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
     for name in ("mehdg_tet_sizes", "mehdg_tet_create", "mehdg_tet_destroy", "mehdg_tet_residual",
                  "mehdg_tet_status", "mehdg_tet_jvp", "mehdg_tet_assemble", "mehdg_tet_condense",
-                 "mehdg_tet_recover"):
+                 "mehdg_tet_recover", "mehdg_tet_vjp"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
@@ -462,6 +463,14 @@ class TetContext:
             _ptr(entropy, S["entropy"], "entropy"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_tet_assemble")
+
+    def vjp(self, w_v, w_vhat, g_v, g_vhat, stream=None):
+        """J_r^T [w_v; w_vhat] at the state of the last assemble (before condense)."""
+        S = self.shapes()
+        rc = load().mehdg_tet_vjp(self._handle, _ptr(w_v, S["R_v"], "w_v"), _ptr(w_vhat, S["R_vhat"], "w_vhat"),
+                                  _ptr(g_v, S["v"], "g_v"), _ptr(g_vhat, S["vhat"], "g_vhat"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_vjp")
 
     def condense(self, Ahat, bhat, stream=None):
         S = self.shapes()

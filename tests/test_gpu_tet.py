@@ -19,6 +19,9 @@ the oracle (oracle.forms on oracle.tet geometry).
   against oracle.forms.condense and oracle.local.recover: Ahat, bhat, dv,
   dq per macro normwise relative <= 1e-12, p = 1, 2, 3, walls; and the call
   order (ESTATE);
+* mehdg_tet_vjp (J_r^T w from the assembled bordered matrices) against the
+  oracle's reduced Jacobian transposed, and the adjoint identity
+  <w, J_r x> = <J_r^T w, x> against mehdg_tet_jvp, per macro at 1e-12;
 * the benchmark's tetrahedral workloads at full size (1296-macro step, 10368-
   macro residual), sampled macros against the oracle; the Mach 0.1 residual
   R_V is bounded by max(1e-12, 10x the oracle's own change under one-ulp
@@ -291,3 +294,44 @@ def test_tet_full_size_sampled_against_oracle():
         bound = np.maximum(TOL * den, floor[k])
         banner(f"  {k}: errors {num / den}, bounds {bound / den}")
         assert np.all(num <= bound), (k, num / den, bound / den)
+
+
+@pytest.mark.parametrize("p,flux", [(1, "KEPES"), (2, "ES")])
+def test_tet_vjp(p, flux):
+    from oracle import linearized
+    from paper_2507_22195_amd import mehdg
+    w = _tgv(p, flux, True, shape=(1, 1, 1), seed=131)
+    ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
+    S = ctx.shapes()
+    e = {k: empty(S[k]) for k in ("R_q", "R_v", "R_vhat", "entropy")}
+    rng = np.random.default_rng(8)
+    wv, wh = rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape)
+    xv, xh = rng.standard_normal(w.v.shape), rng.standard_normal(w.vhat.shape)
+    banner(f"tet vjp: p={p} flux={flux}")
+    ctx.assemble(dev(w.v), dev(w.vhat), dev(w.v_old), e["R_q"], e["R_v"], e["R_vhat"], e["entropy"])
+    gv, gh = empty(S["v"]), empty(S["vhat"])
+    ctx.vjp(dev(wv), dev(wh), gv, gh)
+    Jq, Jv, Jh = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"])
+    ctx.jvp(dev(w.v), dev(w.vhat), None, dev(xv), dev(xh), None, Jq, Jv, Jh)
+    rc, st = ctx.status()
+    ctx.close()
+    assert rc == 0, st
+    gv, gh, Jv, Jh = host(gv), host(gh), host(Jv), host(Jh)
+    J = forms.jacobian(tet.TetGeometry(w.p, w.mesh.X), w.v, w.vhat, w.v_old, w.params)
+    Jr = linearized.reduced_jacobian(J)
+    M_ = w.n_macro
+    wvec = np.concatenate([wv.reshape(M_, -1), wh.reshape(M_, -1)], axis=1)
+    ref = np.einsum("mji,mj->mi", Jr, wvec)
+    got = np.concatenate([gv.reshape(M_, -1), gh.reshape(M_, -1)], axis=1)
+    err = rel_err(got, ref)
+    lhs = np.einsum("mi,mi->m", wvec, np.concatenate([Jv.reshape(M_, -1), Jh.reshape(M_, -1)], axis=1))
+    rhs = np.einsum("mi,mi->m", got, np.concatenate([xv.reshape(M_, -1), xh.reshape(M_, -1)], axis=1))
+    adj = float(np.max(np.abs(lhs - rhs) / np.abs(lhs)))
+    banner(f"  vjp error {err:.2e}, adjoint identity {adj:.2e}")
+    assert err <= TOL and adj <= TOL, (err, adj)
+    # after the condensation the assembled matrices are gone
+    ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
+    with pytest.raises(mehdg.MehdgError) as ex:
+        ctx.vjp(dev(wv), dev(wh), empty(S["v"]), empty(S["vhat"]))
+    assert ex.value.code == 4
+    ctx.close()
