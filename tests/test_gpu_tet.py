@@ -22,6 +22,8 @@ the oracle (oracle.forms on oracle.tet geometry).
 * mehdg_tet_vjp (J_r^T w from the assembled bordered matrices) against the
   oracle's reduced Jacobian transposed, and the adjoint identity
   <w, J_r x> = <J_r^T w, x> against mehdg_tet_jvp, per macro at 1e-12;
+* more macros than one column launch holds (66654 at p = 1), macros on both
+  sides of the launch boundary;
 * the benchmark's tetrahedral workloads at full size (1296-macro step, 10368-
   macro residual), sampled macros against the oracle; the Mach 0.1 residual
   R_V is bounded by max(1e-12, 10x the oracle's own change under one-ulp
@@ -335,3 +337,34 @@ def test_tet_vjp(p, flux):
         ctx.vjp(dev(wv), dev(wh), empty(S["v"]), empty(S["vhat"]))
     assert ex.value.code == 4
     ctx.close()
+
+
+def test_tet_step_beyond_one_launch_of_macros():
+    """More macros than one column launch holds (65535 along the grid's y):
+    23 x 23 x 21 cubes x 6 = 66654 p = 1 macros; macros on both sides of the
+    launch boundary against the oracle."""
+    import torch
+    from oracle import local
+    from paper_2507_22195_amd import mehdg
+    w = W.tet_tgv_workload(shape=(23, 23, 21), p=1, M0=0.3, Re=500.0, flux="ES", seed_v=141, seed_vh=142)
+    assert w.n_macro > 65535
+    banner(f"tet step: {w.n_macro} p=1 macros (two column launches)")
+    ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
+    S = ctx.shapes()
+    e = {k: empty(S[k]) for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
+    dvh = 1e-2 * np.random.default_rng(10).standard_normal(w.vhat.shape)
+    ctx.assemble(dev(w.v), dev(w.vhat), dev(w.v_old), e["R_q"], e["R_v"], e["R_vhat"], e["entropy"])
+    ctx.condense(e["Ahat"], e["bhat"])
+    ctx.recover(e["R_q"], dev(dvh), e["dv"], e["dq"])
+    rc, st = ctx.status()
+    assert rc == 0, st
+    idx = [0, 65534, 65535, w.n_macro - 1]
+    got = {k: host(e[k][torch.tensor(idx, device="cuda")]) for k in ("Ahat", "bhat", "dv", "dq")}
+    ctx.close()
+    ref = forms.condense(tet.TetGeometry(1, w.mesh.X[idx]), w.v[idx], w.vhat[idx], w.v_old[idx], w.params)
+    rdv, rdq = local.recover(ref, dvh[idx])
+    errs = dict(Ahat=rel_err(got["Ahat"], ref["Ahat"]), bhat=rel_err(got["bhat"], ref["bhat"]),
+                dv=rel_err(got["dv"], rdv), dq=rel_err(got["dq"], rdq))
+    banner(f"  errors {errs}")
+    for k, x in errs.items():
+        assert x <= TOL, (k, x)
