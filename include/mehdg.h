@@ -390,6 +390,13 @@ mehdg_err mehdg_tet_assemble(mehdg_tet_ctx* ctx, const double* v, const double* 
 mehdg_err mehdg_tet_vjp(mehdg_tet_ctx* ctx, const double* w_v, const double* w_vhat, double* g_v,
                         double* g_vhat, mehdg_stream stream);
 mehdg_err mehdg_tet_condense(mehdg_tet_ctx* ctx, double* Ahat, double* bhat, mehdg_stream stream);
+/* The stored tetrahedral condensation applied to a new right-hand side, as
+ * mehdg_condense_rhs: r_V [n_macro][N_V] and r_hat [n_macro][N_VH] (NULL:
+ * zero) in place of -R_V and -R_Vhat; writes bhat = r_hat - X S^-1 r_V and
+ * makes the next mehdg_tet_recover return dV = S^-1 (r_V + Y dVhat).  After
+ * mehdg_tet_condense (else ESTATE); the factors are kept. */
+mehdg_err mehdg_tet_condense_rhs(mehdg_tet_ctx* ctx, const double* r_v, const double* r_hat, double* bhat,
+                                 mehdg_stream stream);
 mehdg_err mehdg_tet_recover(mehdg_tet_ctx* ctx, const double* R_q, const double* dvhat, double* dv,
                             double* dq, mehdg_stream stream);
 

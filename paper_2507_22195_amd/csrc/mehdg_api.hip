@@ -664,6 +664,26 @@ mehdg_err tet_condense(int p, const TetCondWork& w, double* Ahat, double* bhat, 
     return e;
 }
 
+mehdg_err tet_condense_rhs(int p, const TetCondWork& w, const double* r_v, const double* r_hat, double* bhat,
+                           hipStream_t st) {
+    mehdg_ctx c;   // lends the workspace pointers to the launcher, as in tet_condense
+    c.p = TET_TAG + p;
+    c.n_macro = w.n_macro;
+    c.d_B = w.B;
+    c.d_ipiv = w.ipiv;
+    c.d_status = w.status;
+    mehdg_err e = MEHDG_EINVAL;
+    int64_t NH = 0;
+    switch (p) {
+        case 1: e = launch_fsolve<TET_TAG + 1>(&c, r_v, r_hat, bhat, st); NH = Dims<TET_TAG + 1>::NH; break;
+        case 2: e = launch_fsolve<TET_TAG + 2>(&c, r_v, r_hat, bhat, st); NH = Dims<TET_TAG + 2>::NH; break;
+        case 3: e = launch_fsolve<TET_TAG + 3>(&c, r_v, r_hat, bhat, st); NH = Dims<TET_TAG + 3>::NH; break;
+        default: break;
+    }
+    if (e == MEHDG_OK) e = launch_poison(&c, PoisonArgs{{bhat, nullptr, nullptr, nullptr}, {NH, 0, 0, 0}}, st);
+    return e;
+}
+
 extern "C" {
 
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]) {

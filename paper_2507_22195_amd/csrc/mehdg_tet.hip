@@ -431,6 +431,14 @@ mehdg_err mehdg_tet_condense(mehdg_tet_ctx* c, double* Ahat, double* bhat, mehdg
     return e;
 }
 
+mehdg_err mehdg_tet_condense_rhs(mehdg_tet_ctx* c, const double* r_v, const double* r_hat, double* bhat,
+                                 mehdg_stream stream) {
+    if (!c || !r_v || !bhat) return MEHDG_EINVAL;
+    if (c->stage != 2) return MEHDG_ESTATE;
+    TetCondWork w{c->d_B, c->d_ipiv, c->d_tri, c->d_perm, c->d_status, c->n_macro};
+    return tet_condense_rhs(c->p, w, r_v, r_hat, bhat, reinterpret_cast<hipStream_t>(stream));
+}
+
 mehdg_err mehdg_tet_recover(mehdg_tet_ctx* c, const double* R_q, const double* dvhat, double* dv, double* dq,
                             mehdg_stream stream) {
     if (!c || !R_q || !dvhat || !dv || !dq) return MEHDG_EINVAL;

@@ -24,3 +24,10 @@ bool tet_cond_sizes(int p, int64_t out[4]);
 // Factors every macro's bordered matrix and writes Ahat = A' + X S^-1 Y,
 // bhat = r_hat - X S^-1 r_V (eq. R5a-b); flagged macros get NaN in Ahat, bhat.
 mehdg_err tet_condense(int p, const TetCondWork& w, double* Ahat, double* bhat, hipStream_t st);
+
+// The stored factors applied to a new right-hand side (eq. R4, R5b): bhat =
+// r_hat - X S^-1 r_V (r_hat NULL: zero), and the right-hand-side column of
+// the factored bordered matrices replaced so that the next recovery gives
+// dV = S^-1 (r_V + Y dVhat).
+mehdg_err tet_condense_rhs(int p, const TetCondWork& w, const double* r_v, const double* r_hat, double* bhat,
+                           hipStream_t st);

@@ -102,9 +102,10 @@ def load(path: str = LIB_PATH):
     lib.mehdg_tet_condense.argtypes = [vp, vp, vp, vp]
     lib.mehdg_tet_recover.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mehdg_tet_vjp.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.mehdg_tet_condense_rhs.argtypes = [vp, vp, vp, vp, vp]
     for name in ("mehdg_tet_sizes", "mehdg_tet_create", "mehdg_tet_destroy", "mehdg_tet_residual",
                  "mehdg_tet_status", "mehdg_tet_jvp", "mehdg_tet_assemble", "mehdg_tet_condense",
-                 "mehdg_tet_recover", "mehdg_tet_vjp"):
+                 "mehdg_tet_recover", "mehdg_tet_vjp", "mehdg_tet_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
@@ -478,6 +479,15 @@ class TetContext:
                                        _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_tet_condense")
+
+    def condense_rhs(self, r_v, r_hat, bhat, stream=None):
+        """bhat = r_hat - X S^-1 r_V with the stored factors (r_hat None: zero)."""
+        S = self.shapes()
+        rc = load().mehdg_tet_condense_rhs(self._handle, _ptr(r_v, S["R_v"], "r_v"),
+                                           _ptr(r_hat, S["bhat"], "r_hat", optional=True),
+                                           _ptr(bhat, S["bhat"], "bhat"), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_tet_condense_rhs")
 
     def recover(self, R_q, dvhat, dv, dq, stream=None):
         S = self.shapes()

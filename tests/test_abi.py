@@ -111,5 +111,6 @@ def test_tet_entry_points_check_arguments_on_the_host():
     assert lib.mehdg_tet_condense(None, None, None, None) == 1
     assert lib.mehdg_tet_recover(None, None, None, None, None, None) == 1
     assert lib.mehdg_tet_vjp(None, None, None, None, None, None) == 1
+    assert lib.mehdg_tet_condense_rhs(None, None, None, None, None) == 1
     assert lib.mehdg_tet_status(None, None, None) == 1
     assert lib.mehdg_tet_destroy(None) == 1

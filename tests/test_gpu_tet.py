@@ -22,6 +22,9 @@ the oracle (oracle.forms on oracle.tet geometry).
 * mehdg_tet_vjp (J_r^T w from the assembled bordered matrices) against the
   oracle's reduced Jacobian transposed, and the adjoint identity
   <w, J_r x> = <J_r^T w, x> against mehdg_tet_jvp, per macro at 1e-12;
+* mehdg_tet_condense_rhs: with (-R_V, -R_Vhat) it reproduces bhat of the
+  condensation; with a seeded right-hand side, bhat and the recovered dV
+  against the oracle's S, X, Y at 1e-12;
 * more macros than one column launch holds (66654 at p = 1), macros on both
   sides of the launch boundary;
 * the benchmark's tetrahedral workloads at full size (1296-macro step, 10368-
@@ -365,6 +368,41 @@ def test_tet_step_beyond_one_launch_of_macros():
     rdv, rdq = local.recover(ref, dvh[idx])
     errs = dict(Ahat=rel_err(got["Ahat"], ref["Ahat"]), bhat=rel_err(got["bhat"], ref["bhat"]),
                 dv=rel_err(got["dv"], rdv), dq=rel_err(got["dq"], rdq))
+    banner(f"  errors {errs}")
+    for k, x in errs.items():
+        assert x <= TOL, (k, x)
+
+
+def test_tet_condense_rhs():
+    from paper_2507_22195_amd import mehdg
+    w = _tgv(2, "ES", True, shape=(1, 1, 1), seed=151)
+    ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
+    S = ctx.shapes()
+    e = {k: empty(S[k]) for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
+    banner("tet condense_rhs: p=2")
+    ctx.assemble(dev(w.v), dev(w.vhat), dev(w.v_old), e["R_q"], e["R_v"], e["R_vhat"], e["entropy"])
+    ctx.condense(e["Ahat"], e["bhat"])
+    b1 = empty(S["bhat"])
+    ctx.condense_rhs(-e["R_v"], (-e["R_vhat"]).reshape(S["bhat"]).contiguous(), b1)
+    same = rel_err(host(b1), host(e["bhat"]))
+    rng = np.random.default_rng(17)
+    rv, rh = rng.standard_normal(w.v.shape), rng.standard_normal(S["bhat"])
+    b2 = empty(S["bhat"])
+    ctx.condense_rhs(dev(rv), dev(rh), b2)
+    dvh = rng.standard_normal(w.vhat.shape)
+    ctx.recover(e["R_q"], dev(dvh), e["dv"], e["dq"])
+    rc, st = ctx.status()
+    ctx.close()
+    assert rc == 0, st
+    ref = forms.condense(tet.TetGeometry(2, w.mesh.X), w.v, w.vhat, w.v_old, w.params)
+    M_ = w.n_macro
+    rb, rdv = [], []
+    for m in range(M_):
+        Ssol = np.linalg.solve(ref["S"][m], np.column_stack([rv[m].ravel(), ref["Y"][m] @ dvh[m].ravel()]))
+        rb.append(rh[m] - ref["X"][m] @ Ssol[:, 0])
+        rdv.append(Ssol[:, 0] + Ssol[:, 1])
+    errs = dict(same=same, bhat=rel_err(host(b2), np.stack(rb)),
+                dv=rel_err(host(e["dv"]).reshape(M_, -1), np.stack(rdv)))
     banner(f"  errors {errs}")
     for k, x in errs.items():
         assert x <= TOL, (k, x)
