@@ -227,3 +227,104 @@ def test_trace_flux_jacobians_match_fd():
                 col = (-cols[0] + 8 * cols[1] - 8 * cols[2] + cols[3]) / (12 * h)
                 err = np.abs(col - J[..., :, l]) / (np.abs(J[..., :, l]) + 1e-3)
                 assert np.max(err[keep]) < 1e-6, (fl, l, np.max(err[keep]))
+
+
+def _kepes_by_hand_x(rhoL, VL, PL, rhoR, VR, PR):
+    """KEPES flux for n = e_x written out from Sec. 5.1.3 on primitive states:
+    the EC flux (eq. EC), R-bar as printed, T-bar (eq. KEPES4), lambda^KEPES,
+    theta and lambda_max, assembled as Fbar - 1/2 R |Lambda| T R^T [[v]]
+    (eq. ES).  L is the element side (v), R the trace side (v-hat); the jump
+    is trace minus element.  Returns the flux and its pieces so that the
+    caller can plant a misreading into one of them."""
+    g = GAMMA
+
+    def entropy_vars(rho, V, P):
+        beta = rho / P
+        s = np.log(P / rho ** g)
+        return np.array([(g - s) / (g - 1) - beta * (V @ V) / 2, *(beta * V), -beta])
+
+    def lnmean(a, b):
+        return (b - a) / np.log1p((b - a) / a)
+
+    betaL, betaR = rhoL / PL, rhoR / PR
+    rho_ln, beta_ln = lnmean(rhoL, rhoR), lnmean(betaL, betaR)
+    Vb = (VL + VR) / 2
+    V2b = (VL @ VL + VR @ VR) / 2
+    Pb = ((rhoL + rhoR) / 2) / ((betaL + betaR) / 2)
+    f1 = rho_ln * Vb[0]
+    f2 = Vb * f1 + Pb * np.array([1.0, 0.0, 0.0])
+    f3 = (1 / (beta_ln * (g - 1)) - V2b / 2) * f1 + Vb @ f2
+    Fec = np.array([f1, *f2, f3])
+    c = np.sqrt(g * Pb / rho_ln)
+    h = g / (beta_ln * (g - 1)) + V2b / 2
+    Rm = np.array([[1, 1, 0, 0, 1],
+                   [Vb[0] - c, Vb[0], 0, 0, Vb[0] + c],
+                   [Vb[1], Vb[1], 1, 0, Vb[1]],
+                   [Vb[2], Vb[2], 0, 1, Vb[2]],
+                   [h - Vb[0] * c, V2b / 2, Vb[1], Vb[2], h + Vb[0] * c]])
+    parts = dict(Fec=Fec, R=Rm, rho_ln=rho_ln, rho_bar=(rhoL + rhoR) / 2, Pb=Pb, vn=Vb[0], c=c,
+                 ratio=abs((PL - PR) / (PL + PR)),
+                 jump=entropy_vars(rhoR, VR, PR) - entropy_vars(rhoL, VL, PL))
+    return parts
+
+
+def _kepes_assemble(parts, lam1_sign=1.0, theta_sqrt=True, T_rho="ln"):
+    g = GAMMA
+    r = parts["rho_ln"] if T_rho == "ln" else parts["rho_bar"]
+    T = np.array([r / (2 * g), r * (g - 1) / g, parts["Pb"], parts["Pb"], r / (2 * g)])
+    vn, c = parts["vn"], parts["c"]
+    lam = np.array([vn + lam1_sign * c, vn, vn, vn, vn + c])
+    lmax = abs(vn) + c
+    theta = np.sqrt(parts["ratio"]) if theta_sqrt else parts["ratio"]
+    L = (1 - theta) * np.abs(lam) + theta * lmax
+    R = parts["R"]
+    return parts["Fec"] - 0.5 * R @ (L * T * (R.T @ parts["jump"]))
+
+
+@pytest.mark.parametrize("rel", [1e-3, 0.05, 0.2, 0.4])
+def test_kepes_flux_against_hand_evaluation_at_distinct_states(rel):
+    """Sec. 5.1.3, eq. (KEPES3)-(KEPES5), (ES), n = e_x: the oracle's KEPES flux
+    equals a by-hand evaluation of the printed T-bar, lambda^KEPES (mass and
+    energy waves both v_n + c), lambda_max = |v_n| + c and
+    theta = sqrt|(P - P_hat)/(P + P_hat)| at distinct states.  The same
+    evaluation with lambda_1 = v_n - c, with theta lacking its square root, or
+    with the arithmetic mean of rho in T-bar must differ from the oracle by far
+    more than the tolerance, so that each of those misreadings fails here."""
+    rng = np.random.default_rng(101)
+    n = np.array([1.0, 0.0, 0.0])
+    worst = 0.0
+    gaps = dict(lam1=np.inf, theta=np.inf, Trho=np.inf)
+    for _ in range(60):
+        rhoL, PL = rng.uniform(0.5, 2.0), rng.uniform(0.4, 2.0)
+        cL = np.sqrt(GAMMA * PL / rhoL)
+        VL = rng.uniform(-0.6, 0.6, 3) * cL
+        VL[0] = np.sign(VL[0]) * max(abs(VL[0]), 0.2 * cL)   # keep v_n away from 0
+        rhoR = rhoL * (1 + rel * rng.choice([-1, 1]) * rng.uniform(0.5, 1))
+        PR = PL * (1 + rel * rng.choice([-1, 1]) * rng.uniform(0.5, 1))
+        VR = VL + rel * rng.uniform(-1, 1, 3) * cL
+        parts = _kepes_by_hand_x(rhoL, VL, PL, rhoR, VR, PR)
+        ref = _kepes_assemble(parts)
+        v = states_from_primitive(rhoL, VL, PL)
+        vh = states_from_primitive(rhoR, VR, PR)
+        got = np.array([float(x) for x in ph.kepes_flux(vh, v, n, GAMMA, EPS)])
+        scale_f = np.abs(ref).max()
+        worst = max(worst, np.abs(got - ref).max() / scale_f)
+        for key, alt in (("lam1", _kepes_assemble(parts, lam1_sign=-1.0)),
+                         ("theta", _kepes_assemble(parts, theta_sqrt=False)),
+                         ("Trho", _kepes_assemble(parts, T_rho="bar"))):
+            gaps[key] = min(gaps[key], np.abs(alt - got).max() / scale_f)
+    assert worst < 1e-12, worst
+    # Every misreading moves the flux of every sample by many times the
+    # tolerance: the dissipation is O(jump^2) (O(jump^1.5) through theta), and
+    # rho-bar differs from rho^ln at second order in the jump, so that
+    # misreading shows only at the larger jumps.
+    assert gaps["lam1"] > 1e3 * 1e-12 and gaps["theta"] > 1e3 * 1e-12, gaps
+    if rel >= 0.05:
+        assert gaps["Trho"] > 1e3 * 1e-12, gaps
+
+
+def states_from_primitive(rho, V, P):
+    beta = rho / P
+    s = np.log(P / rho ** GAMMA)
+    return [np.array((GAMMA - s) / (GAMMA - 1) - beta * (V @ V) / 2), np.array(beta * V[0]),
+            np.array(beta * V[1]), np.array(beta * V[2]), np.array(-beta)]

@@ -151,3 +151,58 @@ def test_viscous_flux_matches_primitive_gradients():
         assert np.allclose(G[j][4], -(tauV - phi), rtol=1e-6, atol=1e-9)
         assert np.all(G[j][0] == 0)
     assert np.all(np.isfinite(T))
+
+
+def test_viscous_constants_from_a_dimensional_flow():
+    """Readings of the viscous constants (eq. C5-C6 with the acoustic Reynolds
+    number, Sec. 7 scaling rho0 = 1, P0 = 1/gamma, c0 = T0 = 1), pinned
+    against dimensional Navier-Stokes physics rather than against their own
+    formulas: a linear velocity and temperature field of an ideal gas
+    (R = 287, mu from Re = rho0 U0 L / mu, k = mu c_p / Pr) gives a stress and
+    heat flux that, divided by rho0 c0^2 and rho0 c0^3, must equal the
+    oracle's viscous flux with the parameters built from (Re, M0, Pr) alone."""
+    from paper_2507_22195_amd import workloads as W
+    g, Rgas, Pr, Re, M0 = 1.4, 287.0, 0.71, 1600.0, 0.3
+    rho0, T0, L = 1.2, 300.0, 0.02
+    c0 = np.sqrt(g * Rgas * T0)
+    U0 = M0 * c0
+    mu_d = rho0 * U0 * L / Re
+    k_d = mu_d * (g * Rgas / (g - 1)) / Pr
+    rng = np.random.default_rng(5)
+    V0, GV = rng.uniform(-1, 1, 3) * U0, rng.uniform(-1, 1, (3, 3)) * U0 / L
+    rhoa, Ta = rng.uniform(-0.2, 0.2, 3) / L, rng.uniform(-0.2, 0.2, 3) / L
+    x0 = rng.uniform(-1, 1, 3) * L
+
+    def fields(x):   # dimensional density, velocity, temperature
+        return rho0 * (1 + rhoa @ x), V0 + GV @ x, T0 * (1 + Ta @ x)
+
+    def vstar(xs):   # entropy variables of the scaled state at scaled position xs
+        rho, V, T = fields(xs * L)
+        rs, Vs, Ps = rho / rho0, V / c0, rho * Rgas * T / (rho0 * c0 ** 2)
+        beta = rs / Ps
+        s = np.log(Ps) - g * np.log(rs)
+        return [(g - s) / (g - 1) - beta * (Vs @ Vs) / 2, beta * Vs[0], beta * Vs[1], beta * Vs[2], -beta]
+
+    xs0 = x0 / L
+    h = 1e-20
+    q = [[0.0] * 3 for _ in range(5)]
+    for j in range(3):
+        e = np.zeros(3, dtype=complex)
+        e[j] = 1j * h
+        vv = vstar(xs0 + e)
+        for l in range(5):
+            q[l][j] = float(np.imag(vv[l]) / h)          # complex-step derivative
+    v = [float(np.real(a)) for a in vstar(xs0.astype(complex))]
+    prm = W.make_params(gamma=g, viscous=True, Re=Re, M0=M0, Pr=Pr)
+    G = ph.viscous_flux([np.array(a) for a in v], [[np.array(b) for b in row] for row in q], prm)
+    rho, V, T = fields(x0)
+    div = np.trace(GV)
+    tau = mu_d * (GV + GV.T - 2.0 / 3.0 * div * np.eye(3))
+    qheat = -k_d * T0 * Ta
+    for j in range(3):
+        mom = -tau[:, j] / (rho0 * c0 ** 2)
+        ene = -(tau[j] @ V - qheat[j]) / (rho0 * c0 ** 3)
+        got = np.array([float(G[j][k]) for k in range(1, 5)])
+        want = np.array([*mom, ene])
+        assert float(G[j][0]) == 0.0
+        assert np.allclose(got, want, rtol=1e-11, atol=1e-13 * np.abs(want).max())
