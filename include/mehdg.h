@@ -190,6 +190,14 @@ mehdg_err mehdg_status(mehdg_ctx* ctx, int32_t* status, mehdg_stream stream);
  * *ld are set.  Synchronises the device. */
 mehdg_err mehdg_copy_bordered(mehdg_ctx* ctx, int64_t m, double* out, int64_t* rows, int64_t* ld);
 
+/* Tests.  Replaces the bordered matrix of macro m with host memory
+ * in[rows][ld] (layout of mehdg_copy_bordered), so that a test can hand the
+ * condensation a matrix the assembly would not produce (e.g. a singular S:
+ * MEHDG_ESINGULAR).  Requires the block workspace of an assemble with
+ * want_blocks = 1 (else MEHDG_ESTATE); the context returns to the assembled
+ * state (stored factors are invalid).  Synchronises the device. */
+mehdg_err mehdg_load_bordered(mehdg_ctx* ctx, int64_t m, const double* in);
+
 /* Kernel timing.  While enabled, every kernel launch of the context is
  * bracketed by HIP events recorded on the launch's own stream.
  * mehdg_profile_read synchronises the device, then returns and clears, per
@@ -275,7 +283,9 @@ mehdg_err mehdg_trace_solve(mehdg_ctx* ctx, const double* Ahat, const double* F,
  * else MEHDG_ESTATE. */
 mehdg_err mehdg_add_source(mehdg_ctx* ctx, const double* s, double* R_v, mehdg_stream stream);
 
-/* y = a x + b y for device vectors of n doubles (b = 0: y is not read). */
+/* y = a x + b y for device vectors of n doubles.  A zero coefficient drops its
+ * term without reading the vector (a = 0: x is not read; b = 0: y is not read),
+ * so NaN or Inf left in unread memory does not propagate. */
 mehdg_err mehdg_axpby(int64_t n, double a, const double* x, double b, double* y, mehdg_stream stream);
 
 /* *out = x . y for device vectors of n doubles (partial sums on the device,

@@ -604,7 +604,12 @@ k_tet(const double* __restrict__ v, const double* __restrict__ vhat, const doubl
         }
         if (tid == 0) {
             if (MODE == 0) entropy[m] = nan;
-            if (status) status[m] = any_phys ? 5 : 6;
+            // a column launch only raises a code and keeps the most basic one:
+            // the coefficient kernel before it has already flagged the state
+            if (status) {
+                if (COL) record_status(status, m, any_phys ? ST_NONPHYSICAL : ST_NONFINITE);
+                else status[m] = any_phys ? ST_NONPHYSICAL : ST_NONFINITE;
+            }
         }
     } else if (!COL && tid == 0 && status) {
         status[m] = 0;   // (column launches only ever raise a flag)

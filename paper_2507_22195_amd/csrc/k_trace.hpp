@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(256) k_axpby(int64_t n, double a, const double
                                                double* __restrict__ y) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride)
-        y[e] = a * x[e] + (b == 0.0 ? 0.0 : b * y[e]);
+        y[e] = (a == 0.0 ? 0.0 : a * x[e]) + (b == 0.0 ? 0.0 : b * y[e]);
 }
 
 // Constant source of a DIRK stage: R_v += s and r_V -= s in the bordered

@@ -684,6 +684,13 @@ mehdg_err tet_condense_rhs(int p, const TetCondWork& w, const double* r_v, const
     return e;
 }
 
+mehdg_err poison_flagged(const int32_t* status, int64_t n_macro, double* a, int64_t per_a, double* b,
+                         int64_t per_b, hipStream_t st) {
+    hipLaunchKernelGGL(k_poison, dim3((unsigned)n_macro), dim3(256), 0, st, status,
+                       PoisonArgs{{a, b, nullptr, nullptr}, {per_a, per_b, 0, 0}});
+    return hip_ok(hipGetLastError());
+}
+
 extern "C" {
 
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]) {
@@ -930,6 +937,17 @@ mehdg_err mehdg_copy_bordered(mehdg_ctx* c, int64_t m, double* out, int64_t* row
     if (hipDeviceSynchronize() != hipSuccess ||
         hipMemcpy(out, c->d_B + m * count, count * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         return MEHDG_EHIP;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_load_bordered(mehdg_ctx* c, int64_t m, const double* in) {
+    if (!c || m < 0 || m >= c->n_macro || !in) return MEHDG_EINVAL;
+    if (!c->d_B || c->stage < 1) return MEHDG_ESTATE;
+    const int64_t count = bordered_rows(c->p) * bordered_ld(c->p);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(c->d_B + m * count, in, count * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return MEHDG_EHIP;
+    c->stage = 1;
     return MEHDG_OK;
 }
 

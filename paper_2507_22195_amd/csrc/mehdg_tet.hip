@@ -419,7 +419,8 @@ mehdg_err mehdg_tet_vjp(mehdg_tet_ctx* c, const double* w_v, const double* w_vha
     (void)mehdg_tet_sizes(c->p, sz);
     hipLaunchKernelGGL(k_tet_vjp_b, dim3((unsigned)c->n_macro), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
                        c->d_B, w_v, w_vhat, (int)sz[2], (int)sz[4], (int)c->ld, c->rows * c->ld, g_v, g_vhat);
-    return hipGetLastError() == hipSuccess ? MEHDG_OK : MEHDG_EHIP;
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    return poison_flagged(c->d_status, c->n_macro, g_v, sz[2], g_vhat, sz[4], reinterpret_cast<hipStream_t>(stream));
 }
 
 mehdg_err mehdg_tet_condense(mehdg_tet_ctx* c, double* Ahat, double* bhat, mehdg_stream stream) {
@@ -454,7 +455,10 @@ mehdg_err mehdg_tet_recover(mehdg_tet_ctx* c, const double* R_q, const double* d
     else
         MEHDG_TET_LAUNCH(3);
 #undef MEHDG_TET_LAUNCH
-    return hipGetLastError() == hipSuccess ? MEHDG_OK : MEHDG_EHIP;
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    int64_t sz[5];
+    (void)mehdg_tet_sizes(c->p, sz);
+    return poison_flagged(c->d_status, c->n_macro, dv, sz[2], dq, sz[3], st);
 }
 
 mehdg_err mehdg_tet_status(mehdg_tet_ctx* c, int32_t* status, mehdg_stream stream) {

@@ -31,3 +31,9 @@ mehdg_err tet_condense(int p, const TetCondWork& w, double* Ahat, double* bhat, 
 // dV = S^-1 (r_V + Y dVhat).
 mehdg_err tet_condense_rhs(int p, const TetCondWork& w, const double* r_v, const double* r_hat, double* bhat,
                            hipStream_t st);
+
+// Overwrites with NaN the outputs a[per_a], b[per_b] (either may be NULL) of
+// every macro whose status code is set: the error contract of the compute
+// calls (a flagged macro's outputs are NaN).
+mehdg_err poison_flagged(const int32_t* status, int64_t n_macro, double* a, int64_t per_a, double* b,
+                         int64_t per_b, hipStream_t st);

@@ -99,7 +99,7 @@ class DirkStepper:
         for i in range(3):
             src = None
             if i > 0:
-                mehdg.axpby(0.0, self.src, 0.0, self.src)
+                self.src.zero_()
                 for j in range(i):
                     mehdg.axpby(self.alpha * self.dt * self.A[i, j], self.Rsp[j], 1.0, self.src)
                 src = self.src

@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH):
     lib.mehdg_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.mehdg_copy_bordered.argtypes = [vp, i64, vp, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64)]
+    lib.mehdg_load_bordered.argtypes = [vp, i64, vp]
     lib.mehdg_profile_enable.argtypes = [vp, i32]
     lib.mehdg_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32]
     lib.mehdg_workspace_bytes.argtypes = [vp]
@@ -110,7 +111,7 @@ def load(path: str = LIB_PATH):
     for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
-                 "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_profile_enable",
+                 "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_load_bordered", "mehdg_profile_enable",
                  "mehdg_profile_read", "mehdg_trace_setup", "mehdg_trace_rhs", "mehdg_trace_apply",
                  "mehdg_trace_gather", "mehdg_trace_precond_setup", "mehdg_trace_precond_apply",
                  "mehdg_trace_solve"):
@@ -380,6 +381,20 @@ class Context:
         if rc:
             raise MehdgError(rc, "mehdg_copy_bordered")
         return out
+
+    def load_bordered(self, m: int, Bm):
+        """Replaces macro m's bordered matrix with the host array Bm [rows][ld] (tests)."""
+        Bm = np.ascontiguousarray(Bm, dtype=np.float64)
+        rows, ld = ctypes.c_int64(), ctypes.c_int64()
+        lib = load()
+        rc = lib.mehdg_copy_bordered(self._handle, int(m), None, ctypes.byref(rows), ctypes.byref(ld))
+        if rc:
+            raise MehdgError(rc, "mehdg_copy_bordered")
+        if Bm.shape != (rows.value, ld.value):
+            raise ValueError(f"bordered matrix shape {Bm.shape}, expected {(rows.value, ld.value)}")
+        rc = lib.mehdg_load_bordered(self._handle, int(m), ctypes.c_void_p(Bm.ctypes.data))
+        if rc:
+            raise MehdgError(rc, "mehdg_load_bordered")
 
     def profile(self, enable: bool):
         rc = load().mehdg_profile_enable(self._handle, int(bool(enable)))

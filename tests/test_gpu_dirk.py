@@ -71,3 +71,36 @@ def test_gpu_convergence_matches_stored_table():
             errs.append((h, e))
         (h0, e0), (h1, e1) = errs[-2], errs[-1]
         assert np.log(e0 / e1) / np.log(h0 / h1) > p + 1 - 0.3
+
+
+def test_stage_source_ignores_stale_memory():
+    """The stage source and the work vectors may start from reused allocator
+    memory holding NaN: a step from NaN-filled buffers equals a step from a
+    fresh stepper bit for bit (mehdg_axpby drops a zero-coefficient term
+    without reading its vector)."""
+    import torch
+    from paper_2507_22195_amd import mehdg
+    from paper_2507_22195_amd.dirk import DirkStepper
+    banner("dirk: step from NaN-filled work buffers")
+    c = mc.setup("wave", 1, 2)
+    outs = []
+    for poison in (False, True):
+        st = DirkStepper(1, c["mesh"].h, c["prm"], c["dt"], c["ids"], c["nfaces"])
+        if poison:
+            for t in (st.src, st.dV, *st.Rsp):
+                t.fill_(float("nan"))
+        v, vh = dev(c["v"]), dev(c["vh_g"])
+        st.step(v, vh)
+        outs.append((host(v), host(vh)))
+        st.close()
+    assert np.all(np.isfinite(outs[1][0])) and np.all(np.isfinite(outs[1][1]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    # the kernel itself: a = 0 must not read x, b = 0 must not read y
+    x = torch.full((1000,), float("nan"), dtype=torch.float64, device="cuda")
+    y = torch.ones(1000, dtype=torch.float64, device="cuda")
+    mehdg.axpby(0.0, x, 2.0, y)
+    assert torch.equal(y, torch.full_like(y, 2.0))
+    y.fill_(float("inf"))
+    z = torch.ones(1000, dtype=torch.float64, device="cuda")
+    mehdg.axpby(3.0, z, 0.0, y)
+    assert torch.equal(y, torch.full_like(y, 3.0))

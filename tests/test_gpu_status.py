@@ -95,3 +95,106 @@ def test_call_order_and_argument_errors_of_the_newer_entry_points():
         ctx.trace_setup(np.zeros((w.n_macro, 6), dtype=np.int64), 1)
     assert ei.value.code == 1
     ctx.close()
+
+
+ENONFINITE, ESINGULAR = 6, 7
+
+
+def _step_outputs(ctx, S, w, v, q=None):
+    R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+    ctx.assemble(dev(v), dev(w.vhat), None if q is None else dev(q), dev(w.v_old), R_q, R_v, R_vh, ent,
+                 want_blocks=True)
+    return R_q, R_v, R_vh, ent
+
+
+def test_zero_pivot_is_singular_and_poisoned():
+    """A bordered matrix whose S has a zero column (loaded through the test
+    entry mehdg_load_bordered) meets a zero pivot in the LU of S: the macro is
+    flagged MEHDG_ESINGULAR, its Ahat, bhat, dV, dQ are NaN, and the other
+    macro-elements still equal the oracle."""
+    from paper_2507_22195_amd import mehdg
+    w = W.workload(1)
+    bad = 5
+    banner(f"status: zero column of S in macro {bad}")
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = _step_outputs(ctx, S, w, w.v)
+    Bm = ctx.bordered(bad)
+    NV = S["v"][1] * S["v"][2]
+    Bm[:NV, 7] = 0.0                                      # column 7 of S
+    ctx.load_bordered(bad, Bm)
+    Ahat, bhat, dv, dq = empty(S["Ahat"]), empty(S["bhat"]), empty(S["dv"]), empty(S["dq"])
+    ctx.condense(Ahat, bhat)
+    dvhat = 1e-2 * np.random.default_rng(5).standard_normal(w.vhat.shape)
+    ctx.recover(R_q, dev(dvhat), dv, dq)
+    rc, st = ctx.status()
+    ctx.close()
+    assert rc == ESINGULAR and st[bad] == ESINGULAR and np.count_nonzero(st) == 1, st
+    good = np.array([m for m in range(w.n_macro) if m != bad])
+    for name, t in (("Ahat", Ahat), ("bhat", bhat), ("dv", dv), ("dq", dq)):
+        a = host(t)
+        assert np.isnan(a[bad]).all(), name
+        assert np.isfinite(a[good]).all(), name
+    wg = W.subset(w, good)
+    ref = local.condense(wg.p, wg.mesh.h, wg.v, wg.vhat, wg.v_old, wg.params)
+    assert rel_err(host(Ahat)[good], ref["Ahat"]) < 1e-12
+
+
+def test_nonfinite_gradient_is_flagged_and_poisoned():
+    """A NaN in the given gradient q of one macro (viscous flux) keeps the
+    state physical but makes the flux non-finite: MEHDG_ENONFINITE for that
+    macro, NaN in all its outputs, the others equal to the oracle."""
+    from paper_2507_22195_amd import mehdg
+    w = W.workload(2, shape=(2, 2, 1))
+    bad = 2
+    geo = local.Geometry(w.p, w.mesh.h)
+    q = local.lift_q(geo, w.v, w.vhat)
+    q_bad = q.copy()
+    q_bad[bad, 1, 0, 10] = np.nan
+    banner(f"status: NaN in q of macro {bad}")
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = _step_outputs(ctx, S, w, w.v, q=q_bad)
+    Ahat, bhat, dv, dq = empty(S["Ahat"]), empty(S["bhat"]), empty(S["dv"]), empty(S["dq"])
+    ctx.condense(Ahat, bhat)
+    dvhat = 1e-2 * np.random.default_rng(6).standard_normal(w.vhat.shape)
+    ctx.recover(R_q, dev(dvhat), dv, dq)
+    rc, st = ctx.status()
+    ctx.close()
+    assert rc == ENONFINITE and st[bad] == ENONFINITE and np.count_nonzero(st) == 1, st
+    good = np.array([m for m in range(w.n_macro) if m != bad])
+    for name, t in (("R_q", R_q), ("R_v", R_v), ("R_vhat", R_vh), ("entropy", ent), ("Ahat", Ahat),
+                    ("bhat", bhat), ("dv", dv), ("dq", dq)):
+        a = host(t)
+        assert np.isnan(a[bad]).all(), name
+        assert np.isfinite(a[good]).all(), name
+    wg = W.subset(w, good)
+    ref = local.condense(wg.p, wg.mesh.h, wg.v, wg.vhat, wg.v_old, wg.params, q=q[good])
+    assert rel_err(host(Ahat)[good], ref["Ahat"]) < 1e-12
+
+
+def test_tet_flagged_macro_poisons_recover_and_vjp():
+    """Tetrahedral path: a non-physical macro's recovered dV, dQ and its VJP
+    outputs are NaN, the other macros' finite."""
+    from paper_2507_22195_amd import mehdg
+    wt = W.tet_tgv_workload(shape=(1, 1, 1), p=1, M0=0.3, Re=500.0, flux="ES", seed_v=7, seed_vh=8)
+    bad = 2
+    v = wt.v.copy()
+    v[bad, 4, :] = 0.5
+    banner(f"status: tetrahedral non-physical macro {bad}, recover and vjp")
+    ctx = mehdg.TetContext(1, wt.mesh.X, wt.params)
+    S = ctx.shapes()
+    t = {k: empty(S[k]) for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
+    ctx.assemble(dev(v), dev(wt.vhat), dev(wt.v_old), t["R_q"], t["R_v"], t["R_vhat"], t["entropy"])
+    gv, gh = empty(S["v"]), empty(S["vhat"])
+    rng = np.random.default_rng(3)
+    ctx.vjp(dev(rng.standard_normal(wt.v.shape)), dev(rng.standard_normal(wt.vhat.shape)), gv, gh)
+    ctx.condense(t["Ahat"], t["bhat"])
+    ctx.recover(t["R_q"], dev(1e-2 * rng.standard_normal(wt.vhat.shape)), t["dv"], t["dq"])
+    rc, st = ctx.status()
+    ctx.close()
+    assert rc == ENONPHYSICAL and st[bad] == ENONPHYSICAL and np.count_nonzero(st) == 1, st
+    good = [m for m in range(wt.n_macro) if m != bad]
+    for name, a in (("g_v", host(gv)), ("g_vhat", host(gh)), ("dv", host(t["dv"])), ("dq", host(t["dq"]))):
+        assert np.isnan(a[bad]).all(), name
+        assert np.isfinite(a[good]).all(), name
