@@ -392,6 +392,83 @@ def tet_step(reps=2, shape=(6, 6, 6)):
             "condense_TFLOP/s": round(flops / (ms["condense"] / 1e3) / 1e12, 2)}
 
 
+def precision(steps=2, shape=None, sample=64):
+    """Mixed precision against FP64 on the precision workload (16x16x8 macros of
+    2x2x2 p = 3 hexahedra, KEPES, viscous, Re 5000, Mach 0.3): the metric's
+    assemble + condense time per precision mode and the mixed-vs-FP64 speedup;
+    the recovery beside it; refinement steps; the largest per-macro normwise
+    relative difference to the FP64 result of bhat and dV (every macro) and of
+    Ahat (a seeded sample of macros; its FP64 copy for all would not fit)."""
+    import torch
+    from paper_2507_22195_amd import mehdg
+    from paper_2507_22195_amd import workloads as W
+    torch.cuda.empty_cache()
+    w = W.workload(5, shape=shape)
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params)
+    S = ctx.shapes()
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+    e = lambda k: torch.empty(S[k], dtype=torch.float64, device="cuda")
+    v, vh, vo = dev(w.v), dev(w.vhat), dev(w.v_old)
+    dvh = dev(1e-2 * np.random.default_rng(1).standard_normal(w.vhat.shape))
+    R_q, R_v, R_vh, ent = e("R_q"), e("R_v"), e("R_vhat"), e("entropy")
+    Ahat, bhat, dv, dq = e("Ahat"), e("bhat"), e("dv"), e("dq")
+    M = w.n_macro
+    idx = torch.tensor(np.sort(np.random.default_rng(77).choice(M, min(sample, M), replace=False)), device="cuda")
+    NV, NH = ctx.sz["N_V"], ctx.sz["N_VH"]
+    out = {"workload": f"viscous TGV, {w.mesh.shape[0]}x{w.mesh.shape[1]}x{w.mesh.shape[2]} macro-elements of "
+                       f"2x2x2 p={w.p} hexahedra (N_V {NV}, N_VH {NH}), KEPES flux, Re 5000, Mach 0.3",
+           "n_macro": M, "ir_tol": mehdg.IR_TOL, "ir_maxit": mehdg.IR_MAXIT}
+    ref = None
+
+    def relmax(a, b):
+        a, b = a.reshape(a.shape[0], -1), b.reshape(b.shape[0], -1)
+        return float(((a - b).norm(dim=1) / b.norm(dim=1)).max())
+
+    for prec in ("fp64", "fp32", "bf16"):
+        ctx.assemble(v, vh, None, vo, R_q, R_v, R_vh, ent, want_blocks=True)
+        ctx.condense(Ahat, bhat, prec=prec)
+        ctx.recover(R_q, dvh, dv, dq)
+        torch.cuda.synchronize()
+        ctx.status()
+        ctx.profile(True)
+        ctx.profile_read()
+        t_ac = t_rec = 0.0
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.assemble(v, vh, None, vo, R_q, R_v, R_vh, ent, want_blocks=True)
+            ctx.condense(Ahat, bhat, prec=prec)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.recover(R_q, dvh, dv, dq)
+            torch.cuda.synchronize()
+            t_ac += t1 - t0
+            t_rec += time.perf_counter() - t1
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        rc, st = ctx.status()
+        ms = t_ac * 1e3 / steps
+        entry = {"assemble_condense_ms": round(ms, 2), "macro_per_s": round(M / (ms / 1e3), 1),
+                 "recover_ms": round(t_rec * 1e3 / steps, 2), "status_ok": bool(rc == 0),
+                 "flagged": {mehdg.ERRORS.get(int(c), int(c)): int((st == c).sum()) for c in np.unique(st) if c},
+                 "kernels_ms": {k: round(m_ / steps, 2) for k, (m_, n_) in prof.items() if n_}}
+        if prec == "fp64":
+            ref = dict(Ahat=Ahat[idx].clone(), bhat=bhat.clone(), dv=dv.clone())
+        else:
+            entry["ir_steps"] = ctx.ir_iterations()
+            entry["speedup_vs_fp64"] = round(out["fp64"]["assemble_condense_ms"] / ms, 3)
+            ok = torch.isfinite(bhat).all(dim=1)
+            entry["max_rel_diff_vs_fp64"] = {
+                "Ahat": relmax(Ahat[idx], ref["Ahat"]) if bool(ok[idx].all()) else None,
+                "bhat": relmax(bhat[ok], ref["bhat"][ok]) if bool(ok.any()) else None,
+                "dv": relmax(dv[ok], ref["dv"][ok]) if bool(ok.any()) else None}
+        out[{"fp64": "fp64", "fp32": "fp32_ir", "bf16": "bf16_ir"}[prec]] = entry
+    ctx.close()
+    del Ahat, bhat, dv, dq, R_q, R_v, R_vh, ent, ref
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,6 +485,8 @@ def main():
     ap.add_argument("--config", type=int, default=2, choices=(2, 5),
                     help="2: viscous TGV 16^3, p=2, ES (default); 5: viscous TGV 16x16x8, p=3, KEPES, Re 5000, "
                          "Mach 0.3 (the FP64 path of the precision workload)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the mixed-precision measurement")
+    ap.add_argument("--precision-only", action="store_true", help="only the mixed-precision measurement")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="before warm-up, copy a MIB-sized buffer three times (untimed) so that a counter "
                          "run sees a plain copy kernel of known size")
@@ -423,6 +502,9 @@ def main():
 
     if args.diff_only:
         print(json.dumps({"differentiation": differentiation(reps=args.steps)}), flush=True)
+        return
+    if args.precision_only:
+        print(json.dumps({"mixed": precision(steps=args.steps)}), flush=True)
         return
     if args.tet_only:
         print(json.dumps({"tet_residual": tet_residual(reps=args.steps), "tet_step": tet_step()}), flush=True)
@@ -563,6 +645,10 @@ def main():
     if not args.no_trace:
         out["trace_solve"] = trace_solve(ctx, w, Ahat, bhat)
     ctx.close()
+    del Ahat, bhat, dv, dq, R_q, R_v, R_vh, ent
+    torch.cuda.empty_cache()
+    if not args.no_precision:
+        out["mixed"] = precision()
     if not args.no_diff:
         out["differentiation"] = differentiation()
     if not args.no_mixed:

@@ -60,8 +60,19 @@ typedef enum {
     MEHDG_ESTATE = 4,        /* call out of order (recover before condense) */
     MEHDG_ENONPHYSICAL = 5,  /* per macro: beta = -v5 <= 0 or rho, P not positive */
     MEHDG_ENONFINITE = 6,    /* per macro: NaN / Inf met in inputs or results */
-    MEHDG_ESINGULAR = 7      /* per macro: zero pivot in the LU of S */
+    MEHDG_ESINGULAR = 7,     /* per macro: zero pivot in the LU of S */
+    MEHDG_EIRNOCONV = 8      /* per macro: iterative refinement of a mixed-precision
+                                condensation did not reach ir_tol in ir_maxit steps */
 } mehdg_err;
+
+/* Arithmetic of the condensation (mehdg_condense). */
+typedef enum {
+    MEHDG_FP64 = 0,          /* blocked LU of S and Schur product in FP64 (MFMA) */
+    MEHDG_FP32_IR = 1,       /* LU of S and its solves in FP32 (MFMA, FP32 accumulation),
+                                refined with FP64 residuals; Schur product in FP64 */
+    MEHDG_BF16_IR = 2        /* as FP32_IR with the LU's trailing updates on BF16 MFMA
+                                (operands rounded to BF16, FP32 accumulation) */
+} mehdg_prec;
 
 typedef enum {
     MEHDG_FLUX_EC = 0,       /* entropy-conservative KEP flux, eq. (EC) */
@@ -82,6 +93,10 @@ typedef struct {
     double T_wall;         /* wall temperature T = gamma P / rho of isothermal wall faces (> 0 if any) */
     int32_t flux;          /* mehdg_flux */
     int32_t viscous;       /* 0: Euler (G = 0), 1: Navier-Stokes */
+    double ir_tol;         /* mixed precision: stop refining when the estimated relative
+                              forward error of S^-1 [-Y | r_V] is below ir_tol (> 0) */
+    int32_t ir_maxit;      /* mixed precision: at most this many refinement steps (>= 1) */
+    int32_t pad_;
 } mehdg_params;
 
 /* Macro-element mesh.  All pointers are host memory, copied at create. */
@@ -129,8 +144,28 @@ mehdg_err mehdg_assemble(mehdg_ctx* ctx, const double* v, const double* vhat, co
  * trace Schur complement Ahat = A' + X S^-1 Y and right-hand side
  * bhat = r_hat - X S^-1 r_V of every macro.  Requires a preceding assemble
  * with want_blocks = 1.  Ahat [n_macro][N_VH][N_VH] may be NULL (only bhat is
- * formed); bhat [n_macro][N_VH].  Device pointers. */
-mehdg_err mehdg_condense(mehdg_ctx* ctx, double* Ahat, double* bhat, mehdg_stream stream);
+ * formed); bhat [n_macro][N_VH].  Device pointers.
+ *   prec = MEHDG_FP64: the FP64 blocked LU over the bordered matrix.
+ *   prec = MEHDG_FP32_IR / MEHDG_BF16_IR: S is factored in low precision;
+ *   Z = S^-1 [-Y | r_V] is solved with those factors and refined with FP64
+ *   residuals [-Y | r_V] - S Z until the estimated relative forward error of
+ *   Z (the size of the last correction times the observed contraction
+ *   rho / (1 - rho)) is at most params.ir_tol, in at most params.ir_maxit
+ *   steps; a macro that does not get there is flagged MEHDG_EIRNOCONV (its
+ *   outputs are NaN like any flagged macro's).  Then Ahat = A' + X S^-1 Y and
+ *   bhat in FP64.  The residual, u(v), the log means and the entropy sums are
+ *   FP64 in every mode.  The low-precision workspace holds a wave of macros
+ *   (at most 32 GiB; the batch is processed wave by wave), allocated at the
+ *   first mixed call.  After a mixed condensation, mehdg_recover works as
+ *   after FP64, mehdg_condense_rhs returns MEHDG_ESTATE (the factors of S are
+ *   not kept), and mehdg_copy_bordered shows Z (its Y part transposed in the
+ *   X rows, its r_V part in the r_V column) in place of the factors.  Invalid
+ *   prec, or a mixed prec with ir_tol <= 0 or ir_maxit < 1: MEHDG_EINVAL. */
+mehdg_err mehdg_condense(mehdg_ctx* ctx, int32_t prec, double* Ahat, double* bhat, mehdg_stream stream);
+
+/* Refinement steps of the last mixed-precision mehdg_condense (the most any
+ * wave of macros needed; 0 after an FP64 condensation). */
+int32_t mehdg_ir_iterations(const mehdg_ctx* ctx);
 
 /* The stored condensation applied to a new right-hand side (Sec. 6.2 eq. R4,
  * R5b): with r_V [n_macro][N_V] (V ordering) and r_hat [n_macro][N_VH]
@@ -217,7 +252,12 @@ enum {
     MEHDG_PROF_JVP = 10,       /* Jacobian-vector product */
     MEHDG_PROF_VJP = 11,       /* vector-Jacobian product */
     MEHDG_PROF_FSOLVE = 12,    /* stored factors applied to a new right-hand side */
-    MEHDG_NPROF = 13
+    MEHDG_PROF_LP_PANEL = 13,  /* mixed precision: FP32 panel of the LU of S */
+    MEHDG_PROF_LP_UPDATE = 14, /* mixed precision: FP32 / BF16 MFMA trailing update */
+    MEHDG_PROF_LP_SOLVE = 15,  /* mixed precision: solves with the low-precision factors */
+    MEHDG_PROF_IR_RESID = 16,  /* mixed precision: FP64 refinement residual */
+    MEHDG_PROF_LP_MOVE = 17,   /* mixed precision: conversion in, Z out */
+    MEHDG_NPROF = 18
 };
 mehdg_err mehdg_profile_enable(mehdg_ctx* ctx, int32_t enable);
 mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t n);

@@ -28,6 +28,7 @@ struct Tab1D {
 #define ST_NONPHYSICAL 5
 #define ST_NONFINITE 6
 #define ST_SINGULAR 7
+#define ST_IRNOCONV 8
 
 template <int P>
 struct Dims {

@@ -100,27 +100,14 @@ struct RecLds {
     Tab1D t;
 };
 
+// dV (in L.z) to dv, then dQ = A_qq^-1 (-R_Q - A_qv dV - A_qvhat dVhat) by the
+// 1-D tensor structure of M and of the lifts (eq. R6).
 template <int P>
-__global__ void __launch_bounds__(1024) k_recover(const double* __restrict__ B, const double* __restrict__ R_q,
-                                                 const double* __restrict__ dvhat, const double* __restrict__ hs,
-                                                 const Tab1D* __restrict__ tab, double* __restrict__ dv,
-                                                 double* __restrict__ dq) {
+__device__ void recover_dq(RecLds<P>& L, const double* __restrict__ R_q, const double* __restrict__ hs, int64_t m,
+                           double* __restrict__ dv, double* __restrict__ dq) {
     using D = Dims<P>;
-    using BD = Bdims<P>;
-    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    RecLds<P>& L = *reinterpret_cast<RecLds<P>*>(smem_raw);
-    const int64_t m = blockIdx.x;
-    const double* Bm = B + m * BD::per_macro;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV;
     const int tid = threadIdx.x;
-    {
-        const double* src = reinterpret_cast<const double*>(tab);
-        double* dst = reinterpret_cast<double*>(&L.t);
-        for (int i = tid; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
-    }
-    for (int i = tid; i < NH; i += blockDim.x) L.dvh[i] = dvhat[m * NH + i];
-    __syncthreads();
-    back_substitute<P>(Bm, L.dvh, L.z, L.U);
     for (int i = tid; i < NV; i += blockDim.x) dv[m * NV + i] = L.z[i];
     // M^-1 R_Q by three 1-D passes
     for (int i = tid; i < 15 * n; i += blockDim.x) L.a[i] = R_q[m * 15 * n + i];
@@ -159,6 +146,69 @@ __global__ void __launch_bounds__(1024) k_recover(const double* __restrict__ B, 
         acc += L.t.Minv[ci[j]][n1d - 1] * L.dvh[((2 * j + 1) * 5 + l) * nf + fc];
         dq[m * 15 * n + i] = acc / h[j] - vinv * src[i];
     }
+}
+
+template <int P>
+__global__ void __launch_bounds__(1024) k_recover(const double* __restrict__ B, const double* __restrict__ R_q,
+                                                 const double* __restrict__ dvhat, const double* __restrict__ hs,
+                                                 const Tab1D* __restrict__ tab, double* __restrict__ dv,
+                                                 double* __restrict__ dq) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int NH = D::NH;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    RecLds<P>& L = *reinterpret_cast<RecLds<P>*>(smem_raw);
+    const int64_t m = blockIdx.x;
+    const double* Bm = B + m * BD::per_macro;
+    const int tid = threadIdx.x;
+    {
+        const double* src = reinterpret_cast<const double*>(tab);
+        double* dst = reinterpret_cast<double*>(&L.t);
+        for (int i = tid; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
+    }
+    for (int i = tid; i < NH; i += blockDim.x) L.dvh[i] = dvhat[m * NH + i];
+    __syncthreads();
+    back_substitute<P>(Bm, L.dvh, L.z, L.U);
+    recover_dq<P>(L, R_q, hs, m, dv, dq);
+}
+
+// Recovery after the mixed-precision condensation, which leaves
+// Z = S^-1 [-Y | r_V] in the bordered matrix (Z_Y transposed in the X rows,
+// z_r in the r_V column): dV = S^-1 (r_V + Y dVhat) = z_r - Z_Y dVhat, a
+// product read row by row of the X rows (coalesced over dV's index), then dQ
+// as in k_recover.
+template <int P>
+__global__ void __launch_bounds__(1024) k_recover_z(const double* __restrict__ B, const double* __restrict__ R_q,
+                                                   const double* __restrict__ dvhat, const double* __restrict__ hs,
+                                                   const Tab1D* __restrict__ tab, double* __restrict__ dv,
+                                                   double* __restrict__ dq) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    RecLds<P>& L = *reinterpret_cast<RecLds<P>*>(smem_raw);
+    const int64_t m = blockIdx.x;
+    const double* Bm = B + m * BD::per_macro;
+    const int tid = threadIdx.x;
+    {
+        const double* src = reinterpret_cast<const double*>(tab);
+        double* dst = reinterpret_cast<double*>(&L.t);
+        for (int i = tid; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
+    }
+    for (int i = tid; i < NH; i += blockDim.x) L.dvh[i] = dvhat[m * NH + i];
+    __syncthreads();
+    for (int c = tid; c < NV; c += blockDim.x) {
+        double s0 = 0.0, s1 = 0.0;
+        int i = 0;
+        for (; i + 2 <= NH; i += 2) {
+            s0 += Bm[(int64_t)(NV + i) * ld + c] * L.dvh[i];
+            s1 += Bm[(int64_t)(NV + i + 1) * ld + c] * L.dvh[i + 1];
+        }
+        for (; i < NH; ++i) s0 += Bm[(int64_t)(NV + i) * ld + c] * L.dvh[i];
+        L.z[c] = Bm[(int64_t)c * ld + NV + NH] - (s0 + s1);
+    }
+    __syncthreads();
+    recover_dq<P>(L, R_q, hs, m, dv, dq);
 }
 
 // New right-hand side (r_V, r_hat) for the stored factors: y = L^-1 P r_V and

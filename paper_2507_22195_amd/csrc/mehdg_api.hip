@@ -15,6 +15,7 @@
 #include "../../include/mehdg.h"
 #include "common.hpp"
 #include "k_linear.hpp"
+#include "k_mixed.hpp"
 #include "k_recover.hpp"
 #include "k_trace.hpp"
 #include "tables.hpp"
@@ -62,6 +63,20 @@ struct mehdg_ctx {
     double* d_coef = nullptr;       // [restart + 1]
     int gm_restart = 0;
     std::vector<double> h_part, h_coef;
+    // mixed-precision condensation: low-precision factors, solution, residual
+    // and stopping sums of one wave of macros (mehdg_condense with FP32_IR / BF16_IR)
+    int64_t lp_wave = 0;            // macros per wave the buffers hold
+    float* d_slo = nullptr;         // [wave][N_V][lds] factors of S
+    int32_t* d_lperm = nullptr;     // [wave][N_V] position -> row
+    float* d_ltri = nullptr;        // [wave][panels][2][32][32] inverses of the diagonal blocks of L, U
+    double* d_zb = nullptr;         // [wave][N_V][N_VH + 1] Z = S^-1 [-Y | r_V]
+    double* d_rb = nullptr;         // [wave][N_V][N_VH + 1] right-hand sides / residuals
+    float* d_yb = nullptr;          // [wave][N_V][ldy] solution of a solve with the FP32 factors
+    double* d_nrm = nullptr;        // [wave][2] |correction|^2, |Z|^2
+    int32_t* d_flags = nullptr;     // [wave] status codes raised by the refinement
+    std::vector<double> h_nrm;
+    std::vector<int32_t> h_flags;
+    int32_t ir_iters = 0;           // refinement steps of the last mixed condensation (most in a wave)
 };
 
 namespace {
@@ -361,6 +376,247 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         g.dsplit = 0;
     }
     return launch_gemm<1>(c, g, MEHDG_PROF_SCHUR, st);
+}
+
+// Same as launch_gemm over the first n macros of the batch that the
+// pointers start at (a wave of the mixed-precision condensation).
+template <int TAG>
+mehdg_err launch_gemm_n(mehdg_ctx* c, GemmArgs g, int64_t n, int slot, hipStream_t st) {
+    const int tr = (g.rows + GM - 1) / GM;
+    g.tiles_c = (g.cols + GT - 1) / GT;
+    if (tr <= 0 || g.tiles_c <= 0 || g.K <= 0 || n <= 0) return MEHDG_OK;
+    g.tiles = tr * g.tiles_c;
+    g.n_macro = n;
+    Timed t(c, slot, st);
+    hipLaunchKernelGGL(k_gemm<TAG>, dim3(xcd_grid(g.tiles, n)), dim3(GTHREADS), 0, st, g);
+    return hip_ok(hipGetLastError());
+}
+
+// Device memory the mixed-precision condensation may hold for one wave.
+constexpr int64_t kLpBudget = (int64_t)32 << 30;
+
+template <int P>
+int64_t lp_bytes_per_macro() {
+    using LD = LpDims<P>;
+    return LD::per_s * 4 + LD::per_t * 4 + 2 * LD::per_z * 8 + LpTrsmDims<P>::per_y * 4 + (int64_t)LD::NV * 4 +
+           2 * 8 + 4;
+}
+
+template <int P>
+mehdg_err ensure_lp_workspace(mehdg_ctx* c, int64_t wave) {
+    using LD = LpDims<P>;
+    if (c->lp_wave >= wave) return MEHDG_OK;
+    (void)hipFree(c->d_slo);
+    (void)hipFree(c->d_lperm);
+    (void)hipFree(c->d_ltri);
+    (void)hipFree(c->d_zb);
+    (void)hipFree(c->d_rb);
+    (void)hipFree(c->d_yb);
+    (void)hipFree(c->d_nrm);
+    (void)hipFree(c->d_flags);
+    c->d_yb = nullptr;
+    c->d_slo = nullptr;
+    c->d_lperm = nullptr;
+    c->d_ltri = nullptr;
+    c->d_zb = c->d_rb = c->d_nrm = nullptr;
+    c->d_flags = nullptr;
+    c->lp_wave = 0;
+    mehdg_err e;
+    if ((e = dev_alloc(c, &c->d_slo, wave * LD::per_s)) != MEHDG_OK ||
+        (e = dev_alloc(c, &c->d_lperm, wave * LD::NV)) != MEHDG_OK ||
+        (e = dev_alloc(c, &c->d_ltri, wave * LD::per_t)) != MEHDG_OK ||
+        (e = dev_alloc(c, &c->d_zb, wave * LD::per_z)) != MEHDG_OK ||
+        (e = dev_alloc(c, &c->d_rb, wave * LD::per_z)) != MEHDG_OK ||
+        (e = dev_alloc(c, &c->d_yb, wave * LpTrsmDims<P>::per_y)) != MEHDG_OK ||
+        (e = dev_alloc(c, &c->d_nrm, 2 * wave)) != MEHDG_OK || (e = dev_alloc(c, &c->d_flags, wave)) != MEHDG_OK)
+        return e;
+    c->h_nrm.assign((size_t)(2 * wave), 0.0);
+    c->h_flags.assign((size_t)wave, 0);
+    c->lp_wave = wave;
+    return MEHDG_OK;
+}
+
+// Mixed-precision condensation (precision modes FP32_IR, BF16_IR), macros in
+// waves that fit kLpBudget: FP32 LU of S (BF16 MFMA trailing updates for
+// BF16_IR), Z = S^-1 [-Y | r_V] refined with FP64 residuals until the
+// forward-error estimate |d_k| rho_k / (1 - rho_k) / |Z| <= ir_tol
+// (rho_k = |d_k| / |d_{k-1}|, the observed contraction; d_0 = Z_0), at most
+// ir_maxit refinement steps (else MEHDG_EIRNOCONV for the macro), then
+// [Ahat | bhat] = [A' | r_hat] - X Z in FP64 and Z stashed for the recovery.
+template <int P>
+mehdg_err launch_condense_mixed(mehdg_ctx* c, bool bf16, double* Ahat, double* bhat, hipStream_t st) {
+    using LD = LpDims<P>;
+    using BD = Bdims<P>;
+    constexpr int NV = LD::NV, NH = LD::NH, NR = LD::NR, ld = BD::ld;
+    const int64_t per = lp_bytes_per_macro<P>();
+    const int64_t nwave = (c->n_macro * per + kLpBudget - 1) / kLpBudget;
+    const int64_t Wmax = (c->n_macro + nwave - 1) / nwave;
+    mehdg_err e = ensure_lp_workspace<P>(c, Wmax);
+    if (e != MEHDG_OK) return e;
+    const double tol = c->prm.ir_tol;
+    const int maxit = c->prm.ir_maxit;
+    c->ir_iters = 0;
+    for (int64_t m0 = 0; m0 < c->n_macro; m0 += Wmax) {
+        const int64_t W = (c->n_macro - m0) < Wmax ? (c->n_macro - m0) : Wmax;
+        {
+            Timed t(c, MEHDG_PROF_LP_MOVE, st);
+            hipLaunchKernelGGL(k_lp_init<P>, dim3((unsigned)NV, (unsigned)W), dim3(256), 0, st, c->d_B, m0, W,
+                               c->d_slo, c->d_lperm, c->d_zb, c->d_rb);
+        }
+        if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+        for (int kb = 0; kb < NV; kb += LP_NB) {
+            {
+                Timed t(c, MEHDG_PROF_LP_PANEL, st);
+                hipLaunchKernelGGL(k_lp_panel<P>, dim3((unsigned)W), dim3(LD::PT), 0, st, c->d_slo, c->d_lperm,
+                                   c->d_ltri, kb, m0, c->d_status);
+            }
+            if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+            const int rows = NV - kb - LP_NB;
+            if (rows <= 0) continue;
+            const int tc = (rows + 63) / 64, tiles = ((rows + 127) / 128) * tc;
+            {
+                Timed t(c, MEHDG_PROF_LP_UPDATE, st);
+                if (bf16)
+                    hipLaunchKernelGGL((k_lp_update<P, true>), dim3(xcd_grid(tiles, W)), dim3(LP_UT), 0, st,
+                                       c->d_slo, c->d_lperm, kb, tc, tiles, W);
+                else
+                    hipLaunchKernelGGL((k_lp_update<P, false>), dim3(xcd_grid(tiles, W)), dim3(LP_UT), 0, st,
+                                       c->d_slo, c->d_lperm, kb, tc, tiles, W);
+            }
+            if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+        }
+        // x = S^-1 R with the low-precision factors (R in d_rb), Z += x
+        auto solve = [&]() -> mehdg_err {
+            hipLaunchKernelGGL(k_lp_fill, dim3((unsigned)((2 * W + 255) / 256)), dim3(256), 0, st, c->d_nrm, 2 * W, 0.0);
+            const dim3 grid(xcd_grid(LpTrsmDims<P>::TILES, W));
+            Timed t(c, MEHDG_PROF_LP_SOLVE, st);
+            for (int q = 0; q < LD::NPAN; ++q)
+                hipLaunchKernelGGL((k_lp_trsm<P, true>), grid, dim3(LPT_T), 0, st, c->d_slo, c->d_lperm, c->d_ltri,
+                                   c->d_rb, c->d_yb, q, W);
+            for (int q = LD::NPAN - 1; q >= 0; --q)
+                hipLaunchKernelGGL((k_lp_trsm<P, false>), grid, dim3(LPT_T), 0, st, c->d_slo, c->d_lperm, c->d_ltri,
+                                   c->d_rb, c->d_yb, q, W);
+            hipLaunchKernelGGL(k_lp_zadd<P>, dim3((unsigned)((NV + 31) / 32), (unsigned)W), dim3(256), 0, st, c->d_yb,
+                               c->d_zb, c->d_nrm, W);
+            return hip_ok(hipGetLastError());
+        };
+        if ((e = solve()) != MEHDG_OK) return e;
+        // refinement: R = [-Y | r_V] - S Z in FP64, Z += solve(R)
+        GemmArgs g{};
+        g.A = c->d_B + m0 * BD::per_macro;
+        g.lda = ld;
+        g.sA = BD::per_macro;
+        g.Bt = c->d_zb;
+        g.ldb = NR;
+        g.sB = LD::per_z;
+        g.C = c->d_B + m0 * BD::per_macro + NV;
+        g.ldc = ld;
+        g.sC = BD::per_macro;
+        g.D = c->d_rb;
+        g.ldd = NR;
+        g.sD = LD::per_z;
+        g.rows = NV;
+        g.cols = NR;
+        g.K = NV;
+        g.dsplit = NR;
+        g.skip_r = NV;
+        g.skip_c = NR;
+        std::vector<double> prev((size_t)W, 1.0);
+        std::vector<char> done((size_t)W, 0);
+        int it = 0;
+        bool all = false;
+        while (!all && it < maxit) {
+            if ((e = launch_gemm_n<2>(c, g, W, MEHDG_PROF_IR_RESID, st)) != MEHDG_OK) return e;
+            if ((e = solve()) != MEHDG_OK) return e;
+            ++it;
+            if (hipMemcpyAsync(c->h_nrm.data(), c->d_nrm, sizeof(double) * 2 * W, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return MEHDG_EHIP;
+            all = true;
+            for (int64_t i = 0; i < W; ++i) {
+                const double dx = std::sqrt(c->h_nrm[2 * i]), zz = std::sqrt(c->h_nrm[2 * i + 1]);
+                if (!std::isfinite(dx) || !std::isfinite(zz)) {
+                    done[i] = 2;
+                    continue;
+                }
+                const double rel = zz > 0.0 ? dx / zz : 0.0;
+                const double rho = prev[i] > 0.0 ? rel / prev[i] : 0.0;
+                prev[i] = rel;
+                if (!done[i] && (rel == 0.0 || (rho < 1.0 && rel * rho / (1.0 - rho) <= tol))) done[i] = 1;
+                if (!done[i]) all = false;
+            }
+        }
+        if (it > c->ir_iters) c->ir_iters = it;
+        bool any = false;
+        for (int64_t i = 0; i < W; ++i) {
+            c->h_flags[i] = done[i] == 1 ? 0 : (done[i] == 2 ? ST_NONFINITE : ST_IRNOCONV);
+            any = any || c->h_flags[i] != 0;
+        }
+        if (any) {
+            if (hipMemcpyAsync(c->d_flags, c->h_flags.data(), sizeof(int32_t) * W, hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                return MEHDG_EHIP;
+            hipLaunchKernelGGL(k_lp_flag, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, st, c->d_flags, m0, W,
+                               c->d_status);
+            if (hipStreamSynchronize(st) != hipSuccess) return MEHDG_EHIP;   // h_flags is reused by the next wave
+        }
+        // [Ahat | bhat] = [A' | r_hat] - X Z
+        GemmArgs s{};
+        s.A = c->d_B + m0 * BD::per_macro + (int64_t)NV * ld;
+        s.lda = ld;
+        s.sA = BD::per_macro;
+        s.Bt = c->d_zb;
+        s.ldb = NR;
+        s.sB = LD::per_z;
+        s.C = c->d_B + m0 * BD::per_macro + (int64_t)NV * ld + NV;
+        s.ldc = ld;
+        s.sC = BD::per_macro;
+        s.rows = NH;
+        s.K = NV;
+        s.skip_r = NH;
+        s.skip_c = NR;
+        if (Ahat) {
+            s.D = Ahat + m0 * (int64_t)NH * NH;
+            s.ldd = NH;
+            s.sD = (int64_t)NH * NH;
+            s.D2 = bhat + m0 * NH;
+            s.ldd2 = 1;
+            s.sD2 = NH;
+            s.cols = NR;
+            s.dsplit = NH;
+        } else {
+            s.Bt = c->d_zb + NH;
+            s.C = c->d_B + m0 * BD::per_macro + (int64_t)NV * ld + NV + NH;
+            s.D = bhat + m0 * NH;
+            s.ldd = 1;
+            s.sD = NH;
+            s.D2 = bhat + m0 * NH;
+            s.ldd2 = 1;
+            s.sD2 = NH;
+            s.cols = 1;
+            s.dsplit = 0;
+        }
+        if ((e = launch_gemm_n<1>(c, s, W, MEHDG_PROF_SCHUR, st)) != MEHDG_OK) return e;
+        {
+            Timed t(c, MEHDG_PROF_LP_MOVE, st);
+            hipLaunchKernelGGL(k_lp_stash<P>, dim3((unsigned)((NR + 31) / 32), (unsigned)((NV + 31) / 32), (unsigned)W),
+                               dim3(256), 0, st, c->d_zb, m0, W, c->d_B);
+        }
+        if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    }
+    return MEHDG_OK;
+}
+
+template <int P>
+mehdg_err launch_recover_z(mehdg_ctx* c, const double* R_q, const double* dvhat, double* dv, double* dq,
+                           hipStream_t st) {
+    const size_t lds = sizeof(RecLds<P>);
+    if (!allow_lds(&k_recover_z<P>, lds)) return MEHDG_EHIP;
+    Timed t(c, MEHDG_PROF_RECOVER, st);
+    hipLaunchKernelGGL(k_recover_z<P>, dim3((unsigned)c->n_macro), dim3(1024), lds, st, c->d_B, R_q, dvhat, c->d_h,
+                       c->d_tab, dv, dq);
+    return hip_ok(hipGetLastError());
 }
 
 template <int P>
@@ -736,6 +992,14 @@ mehdg_err mehdg_destroy(mehdg_ctx* c) {
     (void)hipFree(c->d_z);
     (void)hipFree(c->d_part);
     (void)hipFree(c->d_coef);
+    (void)hipFree(c->d_slo);
+    (void)hipFree(c->d_lperm);
+    (void)hipFree(c->d_ltri);
+    (void)hipFree(c->d_zb);
+    (void)hipFree(c->d_rb);
+    (void)hipFree(c->d_yb);
+    (void)hipFree(c->d_nrm);
+    (void)hipFree(c->d_flags);
     delete c;
     return MEHDG_OK;
 }
@@ -867,25 +1131,39 @@ mehdg_err mehdg_vjp(mehdg_ctx* c, const double* w_q, const double* w_v, const do
     return e;
 }
 
-mehdg_err mehdg_condense(mehdg_ctx* c, double* Ahat, double* bhat, mehdg_stream stream) {
-    if (!c || !bhat) return MEHDG_EINVAL;
+mehdg_err mehdg_condense(mehdg_ctx* c, int32_t prec, double* Ahat, double* bhat, mehdg_stream stream) {
+    if (!c || !bhat || prec < MEHDG_FP64 || prec > MEHDG_BF16_IR) return MEHDG_EINVAL;
+    if (prec != MEHDG_FP64 && (!(c->prm.ir_tol > 0.0) || c->prm.ir_maxit < 1)) return MEHDG_EINVAL;
     if (c->stage != 1) return MEHDG_ESTATE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     mehdg_err e = MEHDG_EINVAL;
-    switch (c->p) {
-        case 1: e = launch_condense<1>(c, Ahat, bhat, st); break;
-        case 2: e = launch_condense<2>(c, Ahat, bhat, st); break;
-        case 3: e = launch_condense<3>(c, Ahat, bhat, st); break;
-        default: break;
+    const bool bf = prec == MEHDG_BF16_IR;
+    if (prec == MEHDG_FP64) {
+        switch (c->p) {
+            case 1: e = launch_condense<1>(c, Ahat, bhat, st); break;
+            case 2: e = launch_condense<2>(c, Ahat, bhat, st); break;
+            case 3: e = launch_condense<3>(c, Ahat, bhat, st); break;
+            default: break;
+        }
+    } else {
+        switch (c->p) {
+            case 1: e = launch_condense_mixed<1>(c, bf, Ahat, bhat, st); break;
+            case 2: e = launch_condense_mixed<2>(c, bf, Ahat, bhat, st); break;
+            case 3: e = launch_condense_mixed<3>(c, bf, Ahat, bhat, st); break;
+            default: break;
+        }
     }
     if (e == MEHDG_OK) {
         int64_t sz[5];
         (void)mehdg_sizes(c->p, sz);
         e = launch_poison(c, PoisonArgs{{Ahat, bhat, nullptr, nullptr}, {sz[4] * sz[4], sz[4], 0, 0}}, st);
     }
-    if (e == MEHDG_OK) c->stage = 2;
+    if (e == MEHDG_OK) c->stage = prec == MEHDG_FP64 ? 2 : 3;
+    else c->stage = 0;   // the bordered matrices are partly factored: assemble again
     return e;
 }
+
+int32_t mehdg_ir_iterations(const mehdg_ctx* c) { return c ? c->ir_iters : 0; }
 
 mehdg_err mehdg_condense_rhs(mehdg_ctx* c, const double* r_v, const double* r_hat, double* bhat,
                              mehdg_stream stream) {
@@ -910,14 +1188,23 @@ mehdg_err mehdg_condense_rhs(mehdg_ctx* c, const double* r_v, const double* r_ha
 mehdg_err mehdg_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, double* dv, double* dq,
                         mehdg_stream stream) {
     if (!c || !R_q || !dvhat || !dv || !dq) return MEHDG_EINVAL;
-    if (c->stage != 2) return MEHDG_ESTATE;
+    if (c->stage != 2 && c->stage != 3) return MEHDG_ESTATE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     mehdg_err e = MEHDG_EINVAL;
-    switch (c->p) {
-        case 1: e = launch_recover<1>(c, R_q, dvhat, dv, dq, st); break;
-        case 2: e = launch_recover<2>(c, R_q, dvhat, dv, dq, st); break;
-        case 3: e = launch_recover<3>(c, R_q, dvhat, dv, dq, st); break;
-        default: break;
+    if (c->stage == 3) {
+        switch (c->p) {
+            case 1: e = launch_recover_z<1>(c, R_q, dvhat, dv, dq, st); break;
+            case 2: e = launch_recover_z<2>(c, R_q, dvhat, dv, dq, st); break;
+            case 3: e = launch_recover_z<3>(c, R_q, dvhat, dv, dq, st); break;
+            default: break;
+        }
+    } else {
+        switch (c->p) {
+            case 1: e = launch_recover<1>(c, R_q, dvhat, dv, dq, st); break;
+            case 2: e = launch_recover<2>(c, R_q, dvhat, dv, dq, st); break;
+            case 3: e = launch_recover<3>(c, R_q, dvhat, dv, dq, st); break;
+            default: break;
+        }
     }
     if (e == MEHDG_OK) {
         int64_t sz[5];

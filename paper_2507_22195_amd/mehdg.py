@@ -17,12 +17,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmehdg.so")
 
 ERRORS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ESTATE", 5: "ENONPHYSICAL",
-          6: "ENONFINITE", 7: "ESINGULAR"}
+          6: "ENONFINITE", 7: "ESINGULAR", 8: "EIRNOCONV"}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+# refinement defaults of the mixed-precision condensation: the estimated relative
+# forward error of S^-1 [-Y | r_V] at most 1e-10, at most 12 refinement steps
+IR_TOL, IR_MAXIT = 1e-10, 12
 EXPORTS = ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
            "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_workspace_bytes",
-           "mehdg_profile_enable", "mehdg_profile_read")
+           "mehdg_profile_enable", "mehdg_profile_read", "mehdg_ir_iterations", "mehdg_load_bordered")
 PROF_SLOTS = ("residual", "minv_rq", "rows_v", "rows_h", "panel", "rowblock", "update", "schur",
-              "recover", "trsm", "jvp", "vjp", "fsolve")
+              "recover", "trsm", "jvp", "vjp", "fsolve", "lp_panel", "lp_update", "lp_solve", "ir_resid",
+              "lp_move")
 
 
 class MehdgError(RuntimeError):
@@ -36,7 +41,8 @@ class Params(ctypes.Structure):
                 ("lam", ctypes.c_double), ("sigma_vis", ctypes.c_double * 5),
                 ("alpha_t", ctypes.c_double), ("alpha_ps", ctypes.c_double),
                 ("logmean_eps", ctypes.c_double), ("T_wall", ctypes.c_double), ("flux", ctypes.c_int32),
-                ("viscous", ctypes.c_int32)]
+                ("viscous", ctypes.c_int32), ("ir_tol", ctypes.c_double), ("ir_maxit", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class Mesh(ctypes.Structure):
@@ -69,7 +75,9 @@ def load(path: str = LIB_PATH):
     lib.mehdg_create.argtypes = [ctypes.POINTER(Mesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
     lib.mehdg_destroy.argtypes = [vp]
     lib.mehdg_assemble.argtypes = [vp] + [vp] * 8 + [i32, vp]
-    lib.mehdg_condense.argtypes = [vp, vp, vp, vp]
+    lib.mehdg_condense.argtypes = [vp, i32, vp, vp, vp]
+    lib.mehdg_ir_iterations.argtypes = [vp]
+    lib.mehdg_ir_iterations.restype = i32
     lib.mehdg_recover.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.mehdg_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     lib.mehdg_copy_bordered.argtypes = [vp, i64, vp, ctypes.POINTER(ctypes.c_int64),
@@ -152,6 +160,8 @@ def make_params(prm: dict) -> Params:
     P.T_wall = float(prm.get("T_wall", 1.0))
     P.flux = int(prm["flux"])
     P.viscous = int(prm["viscous"])
+    P.ir_tol = float(prm.get("ir_tol", IR_TOL))
+    P.ir_maxit = int(prm.get("ir_maxit", IR_MAXIT))
     return P
 
 
@@ -341,12 +351,20 @@ class Context:
         if rc:
             raise MehdgError(rc, "mehdg_vjp")
 
-    def condense(self, Ahat, bhat, stream=None):
+    def condense(self, Ahat, bhat, stream=None, prec="fp64"):
+        """Static condensation; prec "fp64", "fp32" (FP32 LU + FP64 refinement) or
+        "bf16" (BF16 MFMA trailing updates + FP64 refinement)."""
         S = self.shapes()
-        rc = load().mehdg_condense(self._handle, _ptr(Ahat, S["Ahat"], "Ahat", optional=True),
+        if prec not in PRECISIONS:
+            raise ValueError(f"prec must be one of {sorted(PRECISIONS)}")
+        rc = load().mehdg_condense(self._handle, PRECISIONS[prec], _ptr(Ahat, S["Ahat"], "Ahat", optional=True),
                                    _ptr(bhat, S["bhat"], "bhat"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_condense")
+
+    def ir_iterations(self) -> int:
+        """Refinement steps of the last mixed-precision condensation."""
+        return int(load().mehdg_ir_iterations(self._handle))
 
     def condense_rhs(self, r_v, r_hat, bhat, stream=None):
         """bhat = r_hat - X S^-1 r_v with the stored factors; r_hat None means zero.

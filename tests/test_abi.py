@@ -51,7 +51,8 @@ def test_argument_errors_are_synchronous():
     mesh = mehdg.Mesh(1, 7, 0, ctypes.cast(h, ctypes.POINTER(ctypes.c_double)))   # bad degree
     assert lib.mehdg_create(ctypes.byref(mesh), ctypes.byref(prm), ctypes.byref(handle)) == 1
     assert lib.mehdg_assemble(None, *([None] * 8), 0, None) == 1
-    assert lib.mehdg_condense(None, None, None, None) == 1
+    assert lib.mehdg_condense(None, 0, None, None, None) == 1
+    assert lib.mehdg_condense(None, 3, None, None, None) == 1
     assert lib.mehdg_recover(None, None, None, None, None, None) == 1
     assert lib.mehdg_status(None, None, None) == 1
     assert lib.mehdg_jvp(None, *([None] * 6), None) == 1
