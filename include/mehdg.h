@@ -333,6 +333,18 @@ mehdg_err mehdg_axpby(int64_t n, double a, const double* x, double b, double* y,
 mehdg_err mehdg_dot(mehdg_ctx* ctx, int64_t n, const double* x, const double* y, double* out,
                     mehdg_stream stream);
 
+/* mehdg_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * context, no allocation.  The partial sums (256 doubles, whatever n) live in
+ * a file-scope device array that each GPU holds for the life of the process;
+ * its address is looked up once per device (hipGetSymbolAddress) on the first
+ * call with that device current.  Same kernel and the same host summation
+ * order as mehdg_dot, so the result is identical.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race.  Synchronises the stream.  n < 0, a NULL output,
+ * or NULL vectors with n > 0: MEHDG_EINVAL; no usable device: MEHDG_EHIP. */
+mehdg_err mehdg_dot_noalloc(int64_t n, const double* x, const double* y, double* out, mehdg_stream stream);
+
 /* ------------------------------------------------------------------------
  * Tetrahedral macro-elements (Sec. 3.1: K a tetrahedron resolved by eight
  * P_p sub-tetrahedra, continuous inside K; the paper's own discretisation).

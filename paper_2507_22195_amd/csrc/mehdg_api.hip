@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -738,6 +739,37 @@ mehdg_err ensure_trace_work(mehdg_ctx* c, bool precond) {
     return MEHDG_OK;
 }
 
+}  // namespace
+
+// Partial sums of mehdg_dot_noalloc: a file-scope device array of kDotBlocks
+// doubles, one copy per GPU for the life of the process.  Host code reaches
+// it only through the address hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) double scratch[kDotBlocks];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kNoAllocDevices] = {};
+
+// The device address of this GPU's copy of the scratch array, looked up
+// once per device with that device current.
+mehdg_err scratch_on_device(double** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocDevices) return MEHDG_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return MEHDG_EHIP;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return MEHDG_OK;
+}
+
 // sums of the partial dot products of nv vectors, in block order
 mehdg_err host_dots(mehdg_ctx* c, const double* V, int64_t n, int nv, const double* w, double* out,
                     hipStream_t st) {
@@ -1423,6 +1455,29 @@ mehdg_err mehdg_axpby(int64_t n, double a, const double* x, double b, double* y,
     if (n < 0 || (n > 0 && (!x || !y))) return MEHDG_EINVAL;
     if (n == 0) return MEHDG_OK;
     return host_axpby(n, a, x, b, y, reinterpret_cast<hipStream_t>(stream));
+}
+
+mehdg_err mehdg_dot_noalloc(int64_t n, const double* x, const double* y, double* out, mehdg_stream stream) {
+    if (n < 0 || !out || (n > 0 && (!x || !y))) return MEHDG_EINVAL;
+    if (n == 0) {
+        *out = 0.0;
+        return MEHDG_OK;
+    }
+    double* part = nullptr;
+    mehdg_err e = scratch_on_device(&part);
+    if (e != MEHDG_OK) return e;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // every block writes its own partial, so nothing needs clearing first
+    hipLaunchKernelGGL(k_dots, dim3(kDotBlocks), dim3(256), 0, st, x, n, 1, y, part);
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    double h[kDotBlocks];
+    if (hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MEHDG_EHIP;
+    double sum = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) sum += h[b];
+    *out = sum;
+    return MEHDG_OK;
 }
 
 mehdg_err mehdg_dot(mehdg_ctx* c, int64_t n, const double* x, const double* y, double* out, mehdg_stream stream) {

@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.mehdg_vjp.argtypes = [vp] + [vp] * 6 + [vp]
     lib.mehdg_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
     lib.mehdg_dot.argtypes = [vp, i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.mehdg_dot_noalloc.argtypes = [i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.mehdg_tet_sizes.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
     lib.mehdg_tet_create.argtypes = [ctypes.POINTER(TetMesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
     lib.mehdg_tet_destroy.argtypes = [vp]
@@ -116,7 +117,8 @@ def load(path: str = LIB_PATH):
                  "mehdg_tet_status", "mehdg_tet_jvp", "mehdg_tet_assemble", "mehdg_tet_condense",
                  "mehdg_tet_recover", "mehdg_tet_vjp", "mehdg_tet_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
-    for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_jvp", "mehdg_vjp", "mehdg_condense_rhs"):
+    for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_dot_noalloc", "mehdg_jvp", "mehdg_vjp",
+                 "mehdg_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
                  "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_load_bordered", "mehdg_profile_enable",
@@ -136,6 +138,18 @@ def axpby(a, x, b, y, stream=None):
                             _ptr(y, tuple(y.shape), "y"), _stream(stream))
     if rc:
         raise MehdgError(rc, "mehdg_axpby")
+
+
+def dot_noalloc(x, y, stream=None) -> float:
+    """x . y through mehdg_dot_noalloc (no context, no device allocation)."""
+    if x.shape != y.shape:
+        raise ValueError("x and y differ in shape")
+    out = ctypes.c_double()
+    rc = load().mehdg_dot_noalloc(int(x.numel()), _ptr(x, tuple(x.shape), "x"), _ptr(y, tuple(y.shape), "y"),
+                                  ctypes.byref(out), _stream(stream))
+    if rc:
+        raise MehdgError(rc, "mehdg_dot_noalloc")
+    return out.value
 
 
 def sizes(p: int) -> dict:
