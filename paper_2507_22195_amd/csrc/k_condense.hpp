@@ -162,201 +162,44 @@ __device__ __forceinline__ void lds_mm64_store_global(const v4d (&acc)[TPW], dou
     }
 }
 
-// ---------------------------------------------------------------------------
-// Panel factorisation.  Each thread owns one (or RPT) rows of S in [kb, NV)
-// by identity: rows are never exchanged between threads, the pivot rows are
-// only broadcast.  A row's 64 values live in registers as z[0..64) and move
-// down by one register per column, so every column is the same code with
-// constant register indices.  For a row that is not a pivot yet, after j
-// columns z[0 .. 64-j) hold its current entries of columns j..63 and
-// z[64-j .. 64) the multipliers of columns 0..j-1:
-//   z[c] <- z[c+1] - l * prow[c+1]   (c < 63),   z[63] <- l,
-// where the broadcast pivot row reads as zero over its multiplier part.  A
-// pivot row takes l = 0 and z[63] <- z[0] instead, i.e. it just rotates, so
-// after the last column every row's z[c] belongs to column (c + nb) mod 64.
-// Column j: wave arg-max (DPP) and a reduction over the waves choose the
-// pivot row, which is broadcast through LDS; the next column is updated
-// first and its pivot search issued before the rest of the row (look-ahead),
-// with the LDS buffers alternating by column parity: two barriers per column
-// and no global memory traffic inside the column loop.  Afterwards the row
-// interchanges are replayed (LAPACK order: position kb+j with the pivot's
-// current position), rows go to their final positions through LDS
-// (coalesced), the inverses of the diagonal blocks L_kk (unit lower) and
-// U_kk are formed one column per lane, and the composed row interchange of
-// the block goes to perm.  A panel with kb > kb0 is the second panel of the
-// outer block that starts at kb0 (see the file comment).
+// LDS of a panel kernel that the common end of the panel (panel_finish) uses.
 template <int P>
-__global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb, int kb0,
-                                                             int32_t* __restrict__ ipiv,
-                                                             int32_t* __restrict__ perm,
-                                                             double* __restrict__ tri,
-                                                             int32_t* __restrict__ status) {
-    using BD = Bdims<P>;
+struct PanelShared {
+    static constexpr int NB = Panel<P>::NB, NV = Panel<P>::NV;
+    double raw[3 * NB * (NB + 1)];   // staging, then T and the two inverses
+    int pidj[NB];                    // pivot row (identity) of each column
+    int pivs[NB];                    // pivot position of each column (LAPACK order)
+    int mvd[2 * NB], mvs[2 * NB];    // rows whose first-panel segment moves, and their sources
+    int nmv;
+    int pv1[NB];                     // the first panel's pivots (second panel only)
+    int mp[NV];                      // position -> row identity
+    int ps[NV];                      // row identity -> position
+    int mark[NV];
+};
+
+// Common end of a panel once its rows sit at their final positions: the
+// pivots, this panel's interchange as lists (perm for the first panel of an
+// outer block; for the second, the rows whose first-panel multipliers move,
+// which it then moves), the composed interchange of the block, and the
+// inverses of the diagonal blocks (L_kk, U_kk; for the second panel the whole
+// block's unit-lower inverse on MFMA).
+template <int P>
+__device__ __forceinline__ void panel_finish(PanelShared<P>& sh, double* __restrict__ Bm, int kb, int kb0, int nb,
+                                             int64_t m, int32_t* __restrict__ ipiv, int32_t* __restrict__ perm,
+                                             double* __restrict__ tri, bool bad, int32_t* __restrict__ status) {
     using PN = Panel<P>;
-    constexpr int NB = PN::NB, OB = PN::OB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
+    constexpr int NB = PN::NB, OB = PN::OB, NV = PN::NV, ld = Bdims<P>::ld;
     constexpr int NT = PN::THREADS, NW = NT / 64;
-    constexpr int CH = 3 * NB;                  // rows per staging chunk of raw
-    __shared__ double raw[3 * NB * (NB + 1)];   // staging, then T and the two inverses
-    __shared__ double prow[2][NB];              // pivot row (by column parity)
-    __shared__ double redv[2][NW];
-    __shared__ int redi[2][NW];
-    __shared__ int pidj[NB];                    // pivot row (identity) of each column
-    __shared__ int pivs[NB];                    // pivot position of each column (LAPACK order)
-    __shared__ int mvd[2 * NB], mvs[2 * NB];    // rows whose first-panel segment moves, and their sources
-    __shared__ int nmv;
-    __shared__ int pv1[NB];                     // the first panel's pivots (second panel only)
-    __shared__ int mp[NV];                      // position -> row identity
-    __shared__ int ps[NV];                      // row identity -> position
-    __shared__ int mark[NV];
-    const int64_t m = blockIdx.x;
-    double* Bm = B + m * BD::per_macro;
-    const int nb = (NV - kb) < NB ? (NV - kb) : NB;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool second = kb > kb0;
-    const int nrows = NV - kb;
-    double (*stage)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
-
-    double z[RPT][NB];
-    int id[RPT];
-    bool done[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        id[r] = kb + tid + r * NT;
-        done[r] = id[r] >= NV;
-    }
-#pragma unroll
-    for (int r = 0; r < RPT; ++r)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) z[r][c] = (!done[r] && c < nb) ? Bm[(int64_t)id[r] * ld + kb + c] : 0.0;
-    for (int r = kb + tid; r < NV; r += NT) {
-        mp[r] = r;
-        ps[r] = r;
-        mark[r] = 0;
-    }
-    // wave candidate over the rows that are not pivots yet, from their current
-    // column values cv: arg-max to LDS (ties to the lower row)
-    auto candidate = [&](int bf, const double (&cv)[RPT]) {
-        double best = -1.0;
-        int bi = NV;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            double ax = fabs(cv[r]);
-            if (!(ax >= 0.0)) ax = 0.0;          // NaN
-            if (!done[r] && (ax > best || (ax == best && id[r] < bi))) {
-                best = ax;
-                bi = id[r];
-            }
-        }
-        const double wm = wave_max_f64(best);
-        const unsigned long long bal = __ballot(best == wm);
-        const int ol = bal ? (__ffsll((long long)bal) - 1) : 0;
-        const int wrow = __builtin_amdgcn_readlane(bi, ol);
-        if (lane == 0) {
-            redv[bf][wave] = wm;
-            redi[bf][wave] = wrow;
-        }
-    };
-    {
-        double cv[RPT];
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) cv[r] = z[r][0];
-        candidate(0, cv);
-    }
-    bool bad = false;
-    // one column; from column j0 on only z[0 .. 64-j0) can hold live entries
-    // (the pivot row reads as zero beyond), so the segment starting at j0 is
-    // compiled with AW = 64 - j0 live registers and moves the rest unchanged
-    auto column = [&](int j, auto aw) {
-        constexpr int AW = decltype(aw)::value;
-        const int bf = j & 1;
-        __syncthreads();
-        double b = redv[bf][0];
-        int p = redi[bf][0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w)
-            if (redv[bf][w] > b || (redv[bf][w] == b && redi[bf][w] < p)) {
-                b = redv[bf][w];
-                p = redi[bf][w];
-            }
-        if (!(b > 0.0) || !isfinite(b)) bad = true;
-        if (tid == 0) pidj[j] = p;
-        // the pivot row publishes its values; its wave then zeroes the multiplier part
-        bool own_wave = false;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const bool own = id[r] == p;
-            if (own) {
-#pragma unroll
-                for (int c = 0; c < AW; ++c) prow[bf][c] = z[r][c];
-                done[r] = true;
-            }
-            own_wave |= __ballot(own) != 0ull;
-        }
-        if (own_wave && lane >= NB - j && lane < AW) prow[bf][lane] = 0.0;   // same wave, after the row
-        __syncthreads();
-        const double pv = prow[bf][0];
-        const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
-        double l[RPT], nz0[RPT], z0[RPT];
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            z0[r] = z[r][0];
-            l[r] = done[r] ? 0.0 : z0[r] * inv;
-            nz0[r] = z[r][1] - l[r] * prow[bf][1];       // look-ahead column
-        }
-        if (j + 1 < nb) candidate(bf ^ 1, nz0);
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-#pragma unroll
-            for (int c = 1; c < AW - 1; ++c) z[r][c] = z[r][c + 1] - l[r] * prow[bf][c + 1];
-#pragma unroll
-            for (int c = (AW - 1 > 1 ? AW - 1 : 1); c < NB - 1; ++c) z[r][c] = z[r][c + 1];
-            z[r][0] = nz0[r];
-            z[r][NB - 1] = done[r] ? z0[r] : l[r];
-        }
-    };
-    const int j1 = nb < 16 ? nb : 16, j2 = nb < 32 ? nb : 32, j3 = nb < 48 ? nb : 48;
-#pragma clang loop unroll(disable)
-    for (int j = 0; j < j1; ++j) column(j, std::integral_constant<int, 64>{});
-#pragma clang loop unroll(disable)
-    for (int j = j1; j < j2; ++j) column(j, std::integral_constant<int, 48>{});
-#pragma clang loop unroll(disable)
-    for (int j = j2; j < j3; ++j) column(j, std::integral_constant<int, 32>{});
-#pragma clang loop unroll(disable)
-    for (int j = j3; j < nb; ++j) column(j, std::integral_constant<int, 16>{});
-    // replay of the interchanges: position kb+j with the pivot's current position
-    if (second && tid < NB) pv1[tid] = ipiv[m * NV + kb0 + tid];
-    __syncthreads();
-    if (tid == 0) {
-#pragma clang loop unroll(disable)
-        for (int j = 0; j < nb; ++j) {
-            const int pid = pidj[j], pp = ps[pid], other = mp[kb + j];
-            mp[kb + j] = pid;
-            ps[pid] = kb + j;
-            mp[pp] = other;
-            ps[other] = pp;
-            pivs[j] = pp;
-        }
-    }
-    __syncthreads();
-    // every row to its final position, through LDS in chunks (coalesced); its
-    // z[c] belongs to column (c + nb) mod 64
-    for (int base = 0; base < RPT * NT; base += CH) {
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int sl = tid + r * NT - base;
-            if (sl >= 0 && sl < CH) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) stage[sl][c] = z[r][c];
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < CH * NB; e += NT) {
-            const int rr = base + e / NB, c = e % NB;
-            if (rr < nrows && c < nb)
-                Bm[(int64_t)ps[kb + rr] * ld + kb + c] = stage[e / NB][(c - nb) & (NB - 1)];
-        }
-        __syncthreads();
-    }
+    double(&raw)[3 * NB * (NB + 1)] = sh.raw;
+    int(&pivs)[NB] = sh.pivs;
+    int(&mvd)[2 * NB] = sh.mvd;
+    int(&mvs)[2 * NB] = sh.mvs;
+    int& nmv = sh.nmv;
+    int(&pv1)[NB] = sh.pv1;
+    int(&mp)[NV] = sh.mp;
+    int(&mark)[NV] = sh.mark;
     if (tid < nb) ipiv[m * NV + kb + tid] = pivs[tid];
     // this panel's interchange as lists: perm (first panel) or the rows whose
     // first-panel multipliers move (second panel)
@@ -512,6 +355,419 @@ __global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict_
         }
     }
     if (bad && tid == 0) record_status(status, m, ST_SINGULAR);
+}
+
+// ---------------------------------------------------------------------------
+// Panel factorisation.  Each thread owns one (or RPT) rows of S in [kb, NV)
+// by identity: rows are never exchanged between threads, the pivot rows are
+// only broadcast.  A row's 64 values live in registers as z[0..64) and move
+// down by one register per column, so every column is the same code with
+// constant register indices.  For a row that is not a pivot yet, after j
+// columns z[0 .. 64-j) hold its current entries of columns j..63 and
+// z[64-j .. 64) the multipliers of columns 0..j-1:
+//   z[c] <- z[c+1] - l * prow[c+1]   (c < 63),   z[63] <- l,
+// where the broadcast pivot row reads as zero over its multiplier part.  A
+// pivot row takes l = 0 and z[63] <- z[0] instead, i.e. it just rotates, so
+// after the last column every row's z[c] belongs to column (c + nb) mod 64.
+// Column j: wave arg-max (DPP) and a reduction over the waves choose the
+// pivot row, which is broadcast through LDS; the next column is updated
+// first and its pivot search issued before the rest of the row (look-ahead),
+// with the LDS buffers alternating by column parity: two barriers per column
+// and no global memory traffic inside the column loop.  Afterwards the row
+// interchanges are replayed (LAPACK order: position kb+j with the pivot's
+// current position), rows go to their final positions through LDS
+// (coalesced), the inverses of the diagonal blocks L_kk (unit lower) and
+// U_kk are formed one column per lane, and the composed row interchange of
+// the block goes to perm.  A panel with kb > kb0 is the second panel of the
+// outer block that starts at kb0 (see the file comment).
+template <int P>
+__global__ void __launch_bounds__(Panel<P>::THREADS) k_panel(double* __restrict__ B, int kb, int kb0,
+                                                             int32_t* __restrict__ ipiv,
+                                                             int32_t* __restrict__ perm,
+                                                             double* __restrict__ tri,
+                                                             int32_t* __restrict__ status) {
+    using BD = Bdims<P>;
+    using PN = Panel<P>;
+    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
+    constexpr int NT = PN::THREADS, NW = NT / 64;
+    constexpr int CH = 3 * NB;                  // rows per staging chunk of raw
+    __shared__ PanelShared<P> sh;
+    __shared__ double prow[2][NB];              // pivot row (by column parity)
+    __shared__ double redv[2][NW];
+    __shared__ int redi[2][NW];
+    double(&raw)[3 * NB * (NB + 1)] = sh.raw;
+    int(&pidj)[NB] = sh.pidj;
+    int(&pv1)[NB] = sh.pv1;
+    int(&mp)[NV] = sh.mp;
+    int(&ps)[NV] = sh.ps;
+    int(&mark)[NV] = sh.mark;
+    int(&pivs)[NB] = sh.pivs;
+    const int64_t m = blockIdx.x;
+    double* Bm = B + m * BD::per_macro;
+    const int nb = (NV - kb) < NB ? (NV - kb) : NB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool second = kb > kb0;
+    const int nrows = NV - kb;
+    double (*stage)[NB + 1] = reinterpret_cast<double (*)[NB + 1]>(raw);
+
+    double z[RPT][NB];
+    int id[RPT];
+    bool done[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        id[r] = kb + tid + r * NT;
+        done[r] = id[r] >= NV;
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) z[r][c] = (!done[r] && c < nb) ? Bm[(int64_t)id[r] * ld + kb + c] : 0.0;
+    for (int r = kb + tid; r < NV; r += NT) {
+        mp[r] = r;
+        ps[r] = r;
+        mark[r] = 0;
+    }
+    // wave candidate over the rows that are not pivots yet, from their current
+    // column values cv: arg-max to LDS (ties to the lower row)
+    auto candidate = [&](int bf, const double (&cv)[RPT]) {
+        double best = -1.0;
+        int bi = NV;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            double ax = fabs(cv[r]);
+            if (!(ax >= 0.0)) ax = 0.0;          // NaN
+            if (!done[r] && (ax > best || (ax == best && id[r] < bi))) {
+                best = ax;
+                bi = id[r];
+            }
+        }
+        const double wm = wave_max_f64(best);
+        const unsigned long long bal = __ballot(best == wm);
+        const int ol = bal ? (__ffsll((long long)bal) - 1) : 0;
+        const int wrow = __builtin_amdgcn_readlane(bi, ol);
+        if (lane == 0) {
+            redv[bf][wave] = wm;
+            redi[bf][wave] = wrow;
+        }
+    };
+    {
+        double cv[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) cv[r] = z[r][0];
+        candidate(0, cv);
+    }
+    bool bad = false;
+    // one column; from column j0 on only z[0 .. 64-j0) can hold live entries
+    // (the pivot row reads as zero beyond), so the segment starting at j0 is
+    // compiled with AW = 64 - j0 live registers and moves the rest unchanged
+    auto column = [&](int j, auto aw) {
+        constexpr int AW = decltype(aw)::value;
+        const int bf = j & 1;
+        __syncthreads();
+        double b = redv[bf][0];
+        int p = redi[bf][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w)
+            if (redv[bf][w] > b || (redv[bf][w] == b && redi[bf][w] < p)) {
+                b = redv[bf][w];
+                p = redi[bf][w];
+            }
+        if (!(b > 0.0) || !isfinite(b)) bad = true;
+        if (tid == 0) pidj[j] = p;
+        // the pivot row publishes its values; its wave then zeroes the multiplier part
+        bool own_wave = false;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const bool own = id[r] == p;
+            if (own) {
+#pragma unroll
+                for (int c = 0; c < AW; ++c) prow[bf][c] = z[r][c];
+                done[r] = true;
+            }
+            own_wave |= __ballot(own) != 0ull;
+        }
+        if (own_wave && lane >= NB - j && lane < AW) prow[bf][lane] = 0.0;   // same wave, after the row
+        __syncthreads();
+        const double pv = prow[bf][0];
+        const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+        double l[RPT], nz0[RPT], z0[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            z0[r] = z[r][0];
+            l[r] = done[r] ? 0.0 : z0[r] * inv;
+            nz0[r] = z[r][1] - l[r] * prow[bf][1];       // look-ahead column
+        }
+        if (j + 1 < nb) candidate(bf ^ 1, nz0);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+#pragma unroll
+            for (int c = 1; c < AW - 1; ++c) z[r][c] = z[r][c + 1] - l[r] * prow[bf][c + 1];
+#pragma unroll
+            for (int c = (AW - 1 > 1 ? AW - 1 : 1); c < NB - 1; ++c) z[r][c] = z[r][c + 1];
+            z[r][0] = nz0[r];
+            z[r][NB - 1] = done[r] ? z0[r] : l[r];
+        }
+    };
+    const int j1 = nb < 16 ? nb : 16, j2 = nb < 32 ? nb : 32, j3 = nb < 48 ? nb : 48;
+#pragma clang loop unroll(disable)
+    for (int j = 0; j < j1; ++j) column(j, std::integral_constant<int, 64>{});
+#pragma clang loop unroll(disable)
+    for (int j = j1; j < j2; ++j) column(j, std::integral_constant<int, 48>{});
+#pragma clang loop unroll(disable)
+    for (int j = j2; j < j3; ++j) column(j, std::integral_constant<int, 32>{});
+#pragma clang loop unroll(disable)
+    for (int j = j3; j < nb; ++j) column(j, std::integral_constant<int, 16>{});
+    // replay of the interchanges: position kb+j with the pivot's current position
+    if (second && tid < NB) pv1[tid] = ipiv[m * NV + kb0 + tid];
+    __syncthreads();
+    if (tid == 0) {
+#pragma clang loop unroll(disable)
+        for (int j = 0; j < nb; ++j) {
+            const int pid = pidj[j], pp = ps[pid], other = mp[kb + j];
+            mp[kb + j] = pid;
+            ps[pid] = kb + j;
+            mp[pp] = other;
+            ps[other] = pp;
+            pivs[j] = pp;
+        }
+    }
+    __syncthreads();
+    // every row to its final position, through LDS in chunks (coalesced); its
+    // z[c] belongs to column (c + nb) mod 64
+    for (int base = 0; base < RPT * NT; base += CH) {
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int sl = tid + r * NT - base;
+            if (sl >= 0 && sl < CH) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) stage[sl][c] = z[r][c];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < CH * NB; e += NT) {
+            const int rr = base + e / NB, c = e % NB;
+            if (rr < nrows && c < nb)
+                Bm[(int64_t)ps[kb + rr] * ld + kb + c] = stage[e / NB][(c - nb) & (NB - 1)];
+        }
+        __syncthreads();
+    }
+    panel_finish<P>(sh, Bm, kb, kb0, nb, m, ipiv, perm, tri, bad, status);
+}
+
+// ---------------------------------------------------------------------------
+// The same panel for S with more rows than the workgroup has threads (degree
+// 3: 1715 rows, two per thread), whose 64-wide register segments would not
+// fit: the panel goes in sub-panels of SW columns (8 at degree 3), left-looking.
+// During the kernel a row keeps its panel values in its own storage row (its
+// identity); before sub-panel s the pivot rows chosen so far get their U
+// entries over its columns by a forward substitution among themselves
+// (one column per lane, in LDS), every other row subtracts its stored
+// multipliers times those entries, and then the sub-panel's columns are
+// eliminated in registers as in k_panel (arg-max over the rows that are not
+// pivots yet, the pivot row broadcast through LDS, rank-1 update).  The
+// multipliers and U entries go back to the rows' storage.  Afterwards only
+// the rows the interchanges move (at most 2 nb) are copied to their final
+// positions, and panel_finish completes the panel as in k_panel.
+template <int P, int SW>
+__global__ void __launch_bounds__(Panel<P>::THREADS) k_panel_sub(double* __restrict__ B, int kb, int kb0,
+                                                                 int32_t* __restrict__ ipiv,
+                                                                 int32_t* __restrict__ perm,
+                                                                 double* __restrict__ tri,
+                                                                 int32_t* __restrict__ status) {
+    using BD = Bdims<P>;
+    using PN = Panel<P>;
+    constexpr int NB = PN::NB, NV = PN::NV, RPT = PN::RPT, ld = BD::ld;
+    constexpr int NT = PN::THREADS, NW = NT / 64;
+    static_assert(NB % SW == 0, "whole sub-panels");
+    __shared__ PanelShared<P> sh;
+    __shared__ double prow[2][SW];
+    __shared__ double redv[2][NW];
+    __shared__ int redi[2][NW];
+    __shared__ int mvpos[2 * NB];
+    __shared__ int nmov;
+    int(&pidj)[NB] = sh.pidj;
+    int(&pivs)[NB] = sh.pivs;
+    int(&pv1)[NB] = sh.pv1;
+    int(&mp)[NV] = sh.mp;
+    int(&ps)[NV] = sh.ps;
+    int(&mark)[NV] = sh.mark;
+    double(&raw)[3 * NB * (NB + 1)] = sh.raw;
+    // during the sub-panels (raw is free until the rows move): the multipliers
+    // of the pivot rows among themselves, and their values over the current
+    // sub-panel (at most NB - SW pivots before the last sub-panel)
+    static_assert((NB - SW) * (NB + 1) + (NB - SW) * (SW + 1) <= 3 * NB * (NB + 1), "sub-panel tables fit in raw");
+    double(*Lp)[NB + 1] = reinterpret_cast<double(*)[NB + 1]>(raw);
+    double(*Us)[SW + 1] = reinterpret_cast<double(*)[SW + 1]>(raw + (NB - SW) * (NB + 1));
+    const int64_t m = blockIdx.x;
+    double* Bm = B + m * BD::per_macro;
+    const int nb = (NV - kb) < NB ? (NV - kb) : NB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool second = kb > kb0;
+    int id[RPT];
+    bool done[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        id[r] = kb + tid + r * NT;
+        done[r] = id[r] >= NV;
+    }
+    for (int r = kb + tid; r < NV; r += NT) {
+        mp[r] = r;
+        ps[r] = r;
+        mark[r] = 0;
+    }
+    bool bad = false;
+    double z[RPT][SW];
+    for (int c0 = 0; c0 < nb; c0 += SW) {
+        const int sw = (nb - c0) < SW ? (nb - c0) : SW;
+        __syncthreads();
+        if (c0 > 0) {
+            // U entries of the pivots so far over this sub-panel
+            for (int e = tid; e < c0 * c0; e += NT) {
+                const int k = e / c0, i = e % c0;
+                Lp[k][i] = i < k ? Bm[(int64_t)pidj[k] * ld + kb + i] : 0.0;
+            }
+            for (int e = tid; e < c0 * SW; e += NT) {
+                const int k = e / SW, c = e % SW;
+                Us[k][c] = c < sw ? Bm[(int64_t)pidj[k] * ld + kb + c0 + c] : 0.0;
+            }
+            __syncthreads();
+            if (wave == 0 && lane < SW) {
+                for (int k = 1; k < c0; ++k) {
+                    double u = Us[k][lane];
+                    for (int i = 0; i < k; ++i) u -= Lp[k][i] * Us[i][lane];
+                    Us[k][lane] = u;
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < c0 * SW; e += NT) {
+                const int k = e / SW, c = e % SW;
+                if (c < sw) Bm[(int64_t)pidj[k] * ld + kb + c0 + c] = Us[k][c];
+            }
+        }
+        // the rows that are not pivots yet: their sub-panel values, updated by
+        // the earlier sub-panels
+        bool act[RPT];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            act[r] = !done[r];
+#pragma unroll
+            for (int c = 0; c < SW; ++c) z[r][c] = (act[r] && c < sw) ? Bm[(int64_t)id[r] * ld + kb + c0 + c] : 0.0;
+            if (act[r]) {
+                for (int k = 0; k < c0; ++k) {
+                    const double l = Bm[(int64_t)id[r] * ld + kb + k];
+#pragma unroll
+                    for (int c = 0; c < SW; ++c) z[r][c] -= l * Us[k][c];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < SW; ++j) {
+            if (j < sw) {
+                const int bf = j & 1;
+                double best = -1.0;
+                int bi = NV;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    double ax = fabs(z[r][j]);
+                    if (!(ax >= 0.0)) ax = 0.0;          // NaN
+                    if (!done[r] && (ax > best || (ax == best && id[r] < bi))) {
+                        best = ax;
+                        bi = id[r];
+                    }
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ob = __shfl_xor(best, off, 64);
+                    const int oi = __shfl_xor(bi, off, 64);
+                    if (ob > best || (ob == best && oi < bi)) {
+                        best = ob;
+                        bi = oi;
+                    }
+                }
+                if (lane == 0) {
+                    redv[bf][wave] = best;
+                    redi[bf][wave] = bi;
+                }
+                __syncthreads();
+                double pbest = redv[bf][0];
+                int p = redi[bf][0];
+#pragma unroll
+                for (int w = 1; w < NW; ++w)
+                    if (redv[bf][w] > pbest || (redv[bf][w] == pbest && redi[bf][w] < p)) {
+                        pbest = redv[bf][w];
+                        p = redi[bf][w];
+                    }
+                if (!(pbest > 0.0) || !isfinite(pbest)) bad = true;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r)
+                    if (!done[r] && id[r] == p) {
+#pragma unroll
+                        for (int c = 0; c < SW; ++c) prow[bf][c] = z[r][c];
+                        done[r] = true;
+                    }
+                if (tid == 0) pidj[c0 + j] = p;
+                __syncthreads();
+                const double pv = prow[bf][j];
+                const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r)
+                    if (!done[r]) {
+                        const double l = z[r][j] * inv;
+                        z[r][j] = l;
+#pragma unroll
+                        for (int c = j + 1; c < SW; ++c) z[r][c] -= l * prow[bf][c];
+                    }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            if (act[r]) {
+#pragma unroll
+                for (int c = 0; c < SW; ++c)
+                    if (c < sw) Bm[(int64_t)id[r] * ld + kb + c0 + c] = z[r][c];
+            }
+    }
+    // replay of the interchanges: position kb+j with the pivot's current position
+    if (second && tid < NB) pv1[tid] = ipiv[m * NV + kb0 + tid];
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+#pragma clang loop unroll(disable)
+        for (int j = 0; j < nb; ++j) {
+            const int pid = pidj[j], pp = ps[pid], other = mp[kb + j];
+            mp[kb + j] = pid;
+            ps[pid] = kb + j;
+            mp[pp] = other;
+            ps[other] = pp;
+            pivs[j] = pp;
+        }
+        // the positions whose row changes (each listed once)
+#pragma clang loop unroll(disable)
+        for (int j = 0; j < nb; ++j) {
+            const int cand[2] = {kb + j, pivs[j]};
+            for (int t = 0; t < 2; ++t) {
+                const int q = cand[t];
+                bool seen = mp[q] == q;
+                for (int u = 0; u < n && !seen; ++u) seen = mvpos[u] == q;
+                if (!seen) mvpos[n++] = q;
+            }
+        }
+        nmov = n;
+    }
+    __syncthreads();
+    // moved rows to their final positions (read all, then write)
+    const int cnt = nmov * NB;
+    for (int e = tid; e < cnt; e += NT) {
+        const int c = e % NB;
+        raw[e] = c < nb ? Bm[(int64_t)mp[mvpos[e / NB]] * ld + kb + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < cnt; e += NT) {
+        const int c = e % NB;
+        if (c < nb) Bm[(int64_t)mvpos[e / NB] * ld + kb + c] = raw[e];
+    }
+    __syncthreads();
+    panel_finish<P>(sh, Bm, kb, kb0, nb, m, ipiv, perm, tri, bad, status);
 }
 
 // ---------------------------------------------------------------------------

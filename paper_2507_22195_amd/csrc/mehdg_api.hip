@@ -291,8 +291,14 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
     mehdg_err e;
     auto panel = [&](int kb, int kb0) {
         Timed t(c, MEHDG_PROF_PANEL, st);
-        hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, kb0, c->d_ipiv, c->d_perm,
-                           c->d_tri, c->d_status);
+        // more rows than threads: the 64-wide register segments would spill, so
+        // the panel goes in left-looking 8-column sub-panels
+        if constexpr (PN::RPT > 1)
+            hipLaunchKernelGGL((k_panel_sub<P, 8>), dim3(M), dim3(PN::THREADS), 0, st, B, kb, kb0, c->d_ipiv, c->d_perm,
+                               c->d_tri, c->d_status);
+        else
+            hipLaunchKernelGGL(k_panel<P>, dim3(M), dim3(PN::THREADS), 0, st, B, kb, kb0, c->d_ipiv, c->d_perm,
+                               c->d_tri, c->d_status);
         return hip_ok(hipGetLastError());
     };
     for (int kb0 = 0; kb0 < NV; kb0 += PN::OB) {
