@@ -118,14 +118,27 @@ def recorded_traffic(slot, workload):
     return None
 
 
-def cpu_baseline(w, target_s=15.0):
-    """Oracle (FP64, numpy) assemble + condense + recover on a sample of macros."""
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, target_s=12.0, one_core_s=6.0):
+    """Oracle (FP64, numpy) assemble + condense + recover on a seeded sample of
+    macros, with its BLAS on every thread it starts by default, and again on a
+    smaller sample with the BLAS held to one thread."""
     from oracle import local
     from paper_2507_22195_amd import workloads as W
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
     rng = np.random.default_rng(99)
 
@@ -137,14 +150,23 @@ def cpu_baseline(w, target_s=15.0):
         local.recover(c, dvh)
         return time.perf_counter() - t0
 
-    run(np.arange(1))                                  # warm caches / BLAS threads
-    per = run(np.arange(2)) / 2.0
-    count = int(max(2, min(256, target_s / max(per, 1e-3))))
-    idx = rng.choice(w.n_macro, size=count, replace=False)
-    t = run(np.sort(idx))
-    return dict(value=count / t, unit="macro-elements/s", cores=int(threads), kind="oracle",
-                sample=f"{count} of {w.n_macro} macro-elements (seeded random), assemble+condense+recover, "
-                       f"{t:.1f} s")
+    def measure(target):
+        run(np.arange(1))                              # warm caches / BLAS threads
+        per = run(np.arange(2)) / 2.0
+        count = int(max(2, min(256, target / max(per, 1e-3))))
+        idx = rng.choice(w.n_macro, size=count, replace=False)
+        return count, run(np.sort(idx))
+
+    count, t = measure(target_s)
+    out = dict(value=count / t, unit="macro-elements/s", cores=int(threads), kind="oracle",
+               cpu=cpu_model(), logical_cpus=os.cpu_count(),
+               sample=f"{count} of {w.n_macro} macro-elements (seeded random), assemble+condense+recover, "
+                      f"{t:.1f} s, BLAS on {threads} threads")
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            c1, t1 = measure(one_core_s)
+        out["one_core"] = dict(value=c1 / t1, sample=f"{c1} macro-elements, {t1:.1f} s, BLAS on 1 thread")
+    return out
 
 
 def trace_solve(ctx, w, Ahat, bhat, rtol=1e-8, restart=30, maxit=300):
