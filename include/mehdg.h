@@ -323,6 +323,13 @@ mehdg_err mehdg_trace_solve(mehdg_ctx* ctx, const double* Ahat, const double* F,
  * else MEHDG_ESTATE. */
 mehdg_err mehdg_add_source(mehdg_ctx* ctx, const double* s, double* R_v, mehdg_stream stream);
 
+/* Pseudo-transient continuation (Sec. 6.1): sets the pseudo-time coefficient
+ * alpha_ps = 1/tau of the Jacobian term alpha_ps (A0 dv, w) for the following
+ * mehdg_assemble calls (and the JVP / VJP of the state they store), so that a
+ * Newton loop can adapt tau between iterations; the residual does not depend
+ * on it.  alpha_ps < 0 or not finite: MEHDG_EINVAL. */
+mehdg_err mehdg_set_pseudo_time(mehdg_ctx* ctx, double alpha_ps);
+
 /* y = a x + b y for device vectors of n doubles.  A zero coefficient drops its
  * term without reading the vector (a = 0: x is not read; b = 0: y is not read),
  * so NaN or Inf left in unread memory does not propagate. */

@@ -1457,6 +1457,13 @@ mehdg_err mehdg_add_source(mehdg_ctx* c, const double* s, double* R_v, mehdg_str
     return hip_ok(hipGetLastError());
 }
 
+mehdg_err mehdg_set_pseudo_time(mehdg_ctx* c, double alpha_ps) {
+    if (!c || !(alpha_ps >= 0.0) || !std::isfinite(alpha_ps)) return MEHDG_EINVAL;
+    c->prm.alpha_ps = alpha_ps;
+    c->dp.alpha_ps = alpha_ps;
+    return MEHDG_OK;
+}
+
 mehdg_err mehdg_axpby(int64_t n, double a, const double* x, double b, double* y, mehdg_stream stream) {
     if (n < 0 || (n > 0 && (!x || !y))) return MEHDG_EINVAL;
     if (n == 0) return MEHDG_OK;

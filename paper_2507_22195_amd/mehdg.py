@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
     lib.mehdg_condense_rhs.argtypes = [vp, vp, vp, vp, vp]
     lib.mehdg_vjp.argtypes = [vp] + [vp] * 6 + [vp]
     lib.mehdg_axpby.argtypes = [i64, ctypes.c_double, vp, ctypes.c_double, vp, vp]
+    lib.mehdg_set_pseudo_time.argtypes = [vp, ctypes.c_double]
     lib.mehdg_dot.argtypes = [vp, i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.mehdg_dot_noalloc.argtypes = [i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.mehdg_tet_sizes.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
@@ -118,7 +119,7 @@ def load(path: str = LIB_PATH):
                  "mehdg_tet_recover", "mehdg_tet_vjp", "mehdg_tet_condense_rhs"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_add_source", "mehdg_axpby", "mehdg_dot", "mehdg_dot_noalloc", "mehdg_jvp", "mehdg_vjp",
-                 "mehdg_condense_rhs"):
+                 "mehdg_condense_rhs", "mehdg_set_pseudo_time"):
         getattr(lib, name).restype = ctypes.c_int
     for name in ("mehdg_sizes", "mehdg_create", "mehdg_destroy", "mehdg_assemble", "mehdg_condense",
                  "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_load_bordered", "mehdg_profile_enable",
@@ -301,6 +302,12 @@ class Context:
         rc = load().mehdg_trace_precond_apply(self._handle, _ptr(r, T, "r"), _ptr(z, T, "z"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_trace_precond_apply")
+
+    def set_pseudo_time(self, alpha_ps: float):
+        """alpha_ps = 1/tau of the pseudo-time Jacobian term for the following assembles."""
+        rc = load().mehdg_set_pseudo_time(self._handle, float(alpha_ps))
+        if rc:
+            raise MehdgError(rc, "mehdg_set_pseudo_time")
 
     def add_source(self, s, R_v, stream=None):
         S = self.shapes()

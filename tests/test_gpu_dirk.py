@@ -104,3 +104,46 @@ def test_stage_source_ignores_stale_memory():
     z = torch.ones(1000, dtype=torch.float64, device="cuda")
     mehdg.axpby(3.0, z, 0.0, y)
     assert torch.equal(y, torch.full_like(y, 3.0))
+
+
+@pytest.mark.parametrize("ptc", [True, False])
+def test_nonlinear_solvers_reach_the_oracles_step(ptc):
+    """Inexact Newton with pseudo-transient continuation (Sec. 6.1: tau_init =
+    1, tau_max = 1e8, residual-based tau) and exact Newton both converge to the
+    oracle's DIRK(3,3) step (a root does not depend on the path); with
+    continuation tau grows with the residual's decrease."""
+    from paper_2507_22195_amd.dirk import DirkStepper
+    c = mc.setup("wave", 1, 2)
+    st = DirkStepper(1, c["mesh"].h, c["prm"], c["dt"], c["ids"], c["nfaces"], ptc=ptc)
+    v, vh = dev(c["v"]), dev(c["vh_g"])
+    st.step(v, vh)
+    its, taus = st.iterations[0], st.tau_history
+    st.close()
+    v1, vh1, oits = global_solve.dirk33_step(1, c["mesh"].h, c["ids"], c["nfaces"], c["v"], c["vh_g"],
+                                             c["prm"], c["dt"])
+    banner(f"dirk: ptc={ptc} Newton iterations per stage {its} (oracle {oits}); tau {taus}")
+    assert rel_err(host(v).reshape(1, -1), v1.reshape(1, -1)) < 1e-9
+    assert rel_err(host(vh).reshape(1, -1), vh1.reshape(1, -1)) < 1e-9
+    if ptc:
+        assert all(t[0] == 1.0 for t in taus)
+        assert any(len(t) > 1 and t[-1] > t[0] for t in taus)
+
+
+def test_gpu_vortex_convergence_matches_stored_table():
+    """The advected isentropic vortex (Sec. 7.1.1: strength 2.5, Mach 0.5, 10 %
+    of a period) on the GPU reproduces the oracle's stored L2 errors
+    (tests/golden/convergence_vortex.txt) and the finest pair converges at
+    order p+1 (within 0.3)."""
+    table = _table("vortex")
+    for p in (1, 2):
+        Ns = sorted(N for (pp, N) in table if pp == p)
+        errs = []
+        for N in Ns:
+            c, (v, vh, its) = _gpu_run("vortex", p, N)
+            e = mc.l2_error("vortex", p, c["mesh"], v)
+            h, ref = table[(p, N)]
+            banner(f"dirk: vortex p={p} N={N} GPU error {e:.9e}, oracle {ref:.9e}")
+            assert abs(e - ref) <= 1e-6 * ref
+            errs.append((h, e))
+        (h0, e0), (h1, e1) = errs[-2], errs[-1]
+        assert np.log(e0 / e1) / np.log(h0 / h1) > p + 1 - 0.3
