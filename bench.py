@@ -195,11 +195,37 @@ def trace_solve(ctx, w, Ahat, bhat, rtol=1e-8, restart=30, maxit=300):
     its, rr = ctx.trace_solve(Ahat, F, x, rtol=rtol, maxit=maxit, restart=restart)
     torch.cuda.synchronize()
     solve_s = time.perf_counter() - t0
-    NH = ctx.sz["N_VH"]
-    return {"unknowns": int(np.prod(T)), "rtol": rtol, "restart": restart, "iterations": its,
-            "relres": rr, "solve_ms": round(solve_s * 1e3, 2),
-            "apply_ms": round(apply_s * 1e3, 3),
-            "apply_GBps": round(8.0 * NH * NH * w.n_macro / apply_s / 1e9, 1)}
+    NH, NV = ctx.sz["N_VH"], ctx.sz["N_V"]
+    out = {"unknowns": int(np.prod(T)), "rtol": rtol, "restart": restart, "iterations": its,
+           "relres": rr, "solve_ms": round(solve_s * 1e3, 2),
+           "apply_ms": round(apply_s * 1e3, 3),
+           "apply_GBps": round(8.0 * NH * NH * w.n_macro / apply_s / 1e9, 1)}
+    # Algorithm 1 without Ahat: K x from the stored factors (A' x - L21 (U12 x)),
+    # with GMRES and with Sec. 6.4's FGMRES + inner block-Jacobi GMRES
+    ctx.trace_apply(None, F, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.trace_apply(None, F, y)
+    torch.cuda.synchronize()
+    mf_apply_s = (time.perf_counter() - t0) / reps
+    mf = {"apply_ms": round(mf_apply_s * 1e3, 3),
+          "apply_GBps": round(8.0 * (NH * NH + 2 * NV * NH) * w.n_macro / mf_apply_s / 1e9, 1)}
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_m, rr_m = ctx.trace_solve(None, F, x, rtol=rtol, maxit=maxit, restart=restart)
+    torch.cuda.synchronize()
+    mf["gmres"] = {"iterations": its_m, "relres": rr_m, "solve_ms": round((time.perf_counter() - t0) * 1e3, 2)}
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its_f, inner_f, rr_f = ctx.trace_solve_fgmres(None, F, x, rtol=rtol, maxit=maxit, restart=restart, inner=5)
+    torch.cuda.synchronize()
+    mf["fgmres_inner5"] = {"outer_iterations": its_f, "inner_iterations": inner_f, "relres": rr_f,
+                           "solve_ms": round((time.perf_counter() - t0) * 1e3, 2)}
+    out["matrix_free"] = mf
+    return out
 
 
 def differentiation(reps=5):

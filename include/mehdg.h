@@ -284,7 +284,15 @@ mehdg_err mehdg_trace_setup(mehdg_ctx* ctx, const int64_t* face_ids, int64_t n_f
 /* F = sum_m P_m^T bhat_m. */
 mehdg_err mehdg_trace_rhs(mehdg_ctx* ctx, const double* bhat, double* F, mehdg_stream stream);
 
-/* y = K x, matrix-free from the per-macro Ahat (x, y global traces). */
+/* y = K x (x, y global traces) from the per-macro Ahat.  Ahat may be NULL
+ * after an FP64 mehdg_condense (else MEHDG_ESTATE): then K is applied without
+ * Ahat, from the factors the condensation left in the context (Algorithm 1,
+ * its four local stages): Ahat_m x_m = A' x_m + X S^-1 Y x_m
+ * = A' x_m - L21 (U12 x_m), with U12 = L^-1 P (-Y) and L21 = X U^-1, two
+ * products per macro and no triangular solve.  The same NULL convention holds
+ * for mehdg_trace_precond_setup, mehdg_trace_solve and
+ * mehdg_trace_solve_fgmres, so that a Newton step can call mehdg_condense
+ * with Ahat = NULL and never store Ahat. */
 mehdg_err mehdg_trace_apply(mehdg_ctx* ctx, const double* Ahat, const double* x, double* y,
                             mehdg_stream stream);
 
@@ -313,6 +321,19 @@ mehdg_err mehdg_trace_precond_apply(mehdg_ctx* ctx, const double* r, double* z, 
 mehdg_err mehdg_trace_solve(mehdg_ctx* ctx, const double* Ahat, const double* F, double* x, double rtol,
                             int32_t maxit, int32_t restart, int32_t* iters, double* relres,
                             mehdg_stream stream);
+
+/* Sec. 6.4's solver: flexible GMRES(restart) on K x = F whose preconditioner
+ * for every outer direction is `inner` iterations of GMRES (from zero, no
+ * restart, right-preconditioned by the block Jacobi of
+ * mehdg_trace_precond_setup, set up here); inner = 0 is plain block Jacobi.
+ * Stops at rtol ||F|| (residual estimate) or after maxit outer iterations;
+ * *iters outer iterations, *inner_iters inner iterations in total, *relres
+ * the final true residual / ||F||.  restart and inner in [1, 60] and [0, 60].
+ * Ahat NULL: matrix-free (see mehdg_trace_apply).  Synchronises the stream in
+ * every iteration. */
+mehdg_err mehdg_trace_solve_fgmres(mehdg_ctx* ctx, const double* Ahat, const double* F, double* x, double rtol,
+                                   int32_t maxit, int32_t restart, int32_t inner, int32_t* iters,
+                                   int32_t* inner_iters, double* relres, mehdg_stream stream);
 
 /* Constant source of a DIRK stage (Sec. 5.3): adds s [n_macro][5][n] to the
  * interior residual R_v and subtracts it from the right-hand side r_V of the

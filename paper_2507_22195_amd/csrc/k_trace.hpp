@@ -81,6 +81,154 @@ __global__ void __launch_bounds__(256) k_local_apply(const double* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-free product with the reduced operator (Algorithm 1, the four stages
+// of the local product), from the factors an FP64 condensation leaves in the
+// bordered matrix: U12 = L^-1 P (-Y) in the S rows' trace columns and
+// L21 = X U^-1 in place of X, with A' untouched.  Since
+// S^-1 Y x = -U^-1 U12 x and X = L21 U,
+//   Ahat_m x_m = A' x_m + X S^-1 Y x_m = A' x_m - L21 (U12 x_m),
+// two products per macro and no triangular solve; Ahat is never formed.
+// Phase 1: w_m = U12 x_m (N_V rows); phase 2: yl_m = A' x_m - L21 w_m (N_VH
+// rows); 64 rows of one macro per workgroup, lanes along the rows (coalesced).
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_w(const double* __restrict__ B, const double* __restrict__ xg,
+                                              const int64_t* __restrict__ fid, double* __restrict__ w,
+                                              int64_t n_macro) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int BS = 5 * D::nf, NV = D::NV, NH = D::NH, ld = BD::ld, RT = (NV + 63) / 64, RB = 8;
+    __shared__ double x[NH];
+    int64_t m;
+    int tile;
+    xcd_tile(RT, m, tile);
+    if (m >= n_macro) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < NH; i += blockDim.x) x[i] = xg[fid[6 * m + i / BS] * BS + i % BS];
+    __syncthreads();
+    const double* U12 = B + m * BD::per_macro + NV;
+    const int rlo = tile * 64, rhi = (rlo + 64) < NV ? (rlo + 64) : NV;
+    for (int r0 = rlo + wave * RB; r0 < rhi; r0 += nw * RB) {
+        double s[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = 0.0;
+        for (int c = lane; c < NH; c += 64) {
+            const double xc = x[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < rhi) s[i] += U12[(int64_t)(r0 + i) * ld + c] * xc;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+        if (lane < RB && r0 + lane < rhi) {
+            double si = s[0];
+#pragma unroll
+            for (int i = 1; i < RB; ++i)
+                if (lane == i) si = s[i];
+            w[m * NV + r0 + lane] = si;
+        }
+    }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_y(const double* __restrict__ B, const double* __restrict__ xg,
+                                              const int64_t* __restrict__ fid, const double* __restrict__ w,
+                                              double* __restrict__ yl, int64_t n_macro) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int BS = 5 * D::nf, NV = D::NV, NH = D::NH, ld = BD::ld, RT = (NH + 63) / 64, RB = 8;
+    __shared__ double x[NH];
+    __shared__ double ws[NV];
+    int64_t m;
+    int tile;
+    xcd_tile(RT, m, tile);
+    if (m >= n_macro) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int i = threadIdx.x; i < NH; i += blockDim.x) x[i] = xg[fid[6 * m + i / BS] * BS + i % BS];
+    for (int i = threadIdx.x; i < NV; i += blockDim.x) ws[i] = w[m * NV + i];
+    __syncthreads();
+    const double* Xr = B + m * BD::per_macro + (int64_t)NV * ld;   // rows of L21 | A'
+    const int rlo = tile * 64, rhi = (rlo + 64) < NH ? (rlo + 64) : NH;
+    for (int r0 = rlo + wave * RB; r0 < rhi; r0 += nw * RB) {
+        double s[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = 0.0;
+        for (int c = lane; c < NV; c += 64) {
+            const double wc = ws[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < rhi) s[i] -= Xr[(int64_t)(r0 + i) * ld + c] * wc;
+        }
+        for (int c = lane; c < NH; c += 64) {
+            const double xc = x[c];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                if (r0 + i < rhi) s[i] += Xr[(int64_t)(r0 + i) * ld + NV + c] * xc;
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+        if (lane < RB && r0 + lane < rhi) {
+            double si = s[0];
+#pragma unroll
+            for (int i = 1; i < RB; ++i)
+                if (lane == i) si = s[i];
+            yl[m * NH + r0 + lane] = si;
+        }
+    }
+}
+
+// Diagonal face blocks of K from the factors, without Ahat:
+//   D_g = Ahat_m1[f1,f1] + Ahat_m2[f2,f2] (+ Ahat_m[f1,f2] + Ahat_m[f2,f1] when
+//   both sides belong to one macro m),  Ahat_m[a,b] = A'[a,b] - L21[a,:] U12[:,b],
+// each 128 x 64 tile of the BS x BS block on FP64 MFMA (K = N_V), written to
+// the inverse workspace where k_face_block_inv<P, true> then inverts it.
+template <int P>
+__global__ void __launch_bounds__(GTHREADS, 4) k_mf_face_blocks(const double* __restrict__ B,
+                                                                const int64_t* __restrict__ side,
+                                                                double* __restrict__ Dblk, int64_t n_faces) {
+    using D = Dims<P>;
+    using BD = Bdims<P>;
+    constexpr int BS = 5 * D::nf, NV = D::NV, ld = BD::ld;
+    constexpr int TR = (BS + GM - 1) / GM, TC = (BS + GT - 1) / GT;
+    __shared__ TileSmem sm;
+    const int64_t g = blockIdx.x / (TR * TC);
+    if (g >= n_faces) return;
+    const int t = (int)(blockIdx.x % (TR * TC)), r0 = (t / TC) * GM, c0 = (t % TC) * GT;
+    const int64_t m1 = side[4 * g], f1 = side[4 * g + 1], m2 = side[4 * g + 2], f2 = side[4 * g + 3];
+    v4d acc[2][2];
+    zero_acc(acc);
+    // Ahat_m[a, b] tile: A' part added below, - L21[a rows] U12[b cols] accumulated here
+    auto product = [&](int64_t m, int64_t fa, int64_t fb) {
+        const double* Bm = B + m * BD::per_macro;
+        tile_mma<true>(Bm + (int64_t)(NV + fa * BS) * ld, ld, Bm + NV + fb * BS, ld, NV, r0, c0, BS, BS, acc, sm);
+        __syncthreads();
+    };
+    const bool same = m1 == m2;
+    product(m1, f1, f1);
+    product(m2, f2, f2);
+    if (same) {
+        product(m1, f1, f2);
+        product(m1, f2, f1);
+    }
+    double* out = Dblk + g * (int64_t)BS * BS;
+    auto aprime = [&](int64_t m, int64_t fa, int64_t fb, int r, int c) {
+        return B[m * BD::per_macro + (int64_t)(NV + fa * BS + r) * ld + NV + fb * BS + c];
+    };
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
+                if (r < BS && c < BS) {
+                    double d = acc[bi][bj][q] + aprime(m1, f1, f1, r, c) + aprime(m2, f2, f2, r, c);
+                    if (same) d += aprime(m1, f1, f2, r, c) + aprime(m1, f2, f1, r, c);
+                    out[(int64_t)r * BS + c] = d;
+                }
+            }
+}
+
 // Inverse of every diagonal face block of K:
 //   D_g = Ahat_m1[f1, f1] + Ahat_m2[f2, f2]   (BS x BS),
 // plus Ahat_m[f1, f2] + Ahat_m[f2, f1] when both sides belong to one macro m,
@@ -115,7 +263,8 @@ struct BlockInvCfg {
 };
 
 // Inverse of the diagonal face block of K by Gauss-Jordan with row pivoting.
-template <int P>
+// FROM_BLOCK: the block was already formed in Dinv (k_mf_face_blocks) and Ahat is unused.
+template <int P, bool FROM_BLOCK>
 __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict__ Ahat,
                                                         const int64_t* __restrict__ side, double* __restrict__ Dinv,
                                                         int64_t n_faces) {
@@ -143,11 +292,16 @@ __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict
     const bool same = m1 == m2;
     const double* A12 = Ahat + m1 * (int64_t)NH * NH + (f1 * BS) * (int64_t)NH + f2 * BS;
     const double* A21 = Ahat + m1 * (int64_t)NH * NH + (f2 * BS) * (int64_t)NH + f1 * BS;
-    for (int e = tid; e < BS * BS; e += blockDim.x) {
-        const int i = e / BS, j = e % BS;
-        double d = A1[(int64_t)i * NH + j] + A2[(int64_t)i * NH + j];
-        if (same) d += A12[(int64_t)i * NH + j] + A21[(int64_t)i * NH + j];
-        a[i * lda + j] = d;
+    if constexpr (FROM_BLOCK) {
+        if constexpr (CFG::in_lds)
+            for (int e = tid; e < BS * BS; e += blockDim.x) a[(e / BS) * lda + e % BS] = out[e];
+    } else {
+        for (int e = tid; e < BS * BS; e += blockDim.x) {
+            const int i = e / BS, j = e % BS;
+            double d = A1[(int64_t)i * NH + j] + A2[(int64_t)i * NH + j];
+            if (same) d += A12[(int64_t)i * NH + j] + A21[(int64_t)i * NH + j];
+            a[i * lda + j] = d;
+        }
     }
     __syncthreads();
     for (int k = 0; k < BS; ++k) {

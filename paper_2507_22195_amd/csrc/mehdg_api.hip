@@ -56,6 +56,10 @@ struct mehdg_ctx {
     int64_t* d_fid = nullptr;       // [n_macro][6] global face of each local face
     int64_t* d_side = nullptr;      // [n_faces][4] m1, f1, m2, f2
     double* d_yl = nullptr;         // [n_macro][N_VH] per-macro products
+    double* d_mfw = nullptr;        // [n_macro][N_V] U12 x of the matrix-free product
+    double* d_fZ = nullptr;         // FGMRES: preconditioned directions [restart][N]
+    double* d_iV = nullptr;         // FGMRES: inner GMRES basis [inner + 1][N]
+    int fg_restart = 0, fg_inner = 0;
     double* d_Dinv = nullptr;       // [n_faces][5nf][5nf] inverses of the diagonal face blocks
     double* d_V = nullptr;          // GMRES basis [restart + 1][N]
     double* d_w = nullptr;          // [N]
@@ -704,23 +708,44 @@ unsigned vec_grid(int64_t n) {
     return (unsigned)(b < 2048 ? (b > 0 ? b : 1) : 2048);
 }
 
+// K x; with Ahat NULL matrix-free from the factors of an FP64 condensation
+// (Algorithm 1: Ahat_m x_m = A' x_m - L21 (U12 x_m), k_mf_w then k_mf_y)
 template <int P>
 mehdg_err trace_launch_apply(mehdg_ctx* c, const double* Ahat, const double* x, double* y, hipStream_t st) {
     using D = Dims<P>;
-    constexpr int RT = (D::NH + 63) / 64;
-    hipLaunchKernelGGL(k_local_apply<P>, dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st, Ahat, x, c->d_fid, c->d_yl,
-                       (int64_t)c->n_macro);
+    constexpr int RT = (D::NH + 63) / 64, RTV = (D::NV + 63) / 64;
+    if (Ahat) {
+        hipLaunchKernelGGL(k_local_apply<P>, dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st, Ahat, x, c->d_fid,
+                           c->d_yl, (int64_t)c->n_macro);
+    } else {
+        hipLaunchKernelGGL(k_mf_w<P>, dim3(xcd_grid(RTV, c->n_macro)), dim3(256), 0, st, c->d_B, x, c->d_fid,
+                           c->d_mfw, (int64_t)c->n_macro);
+        hipLaunchKernelGGL(k_mf_y<P>, dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st, c->d_B, x, c->d_fid,
+                           c->d_mfw, c->d_yl, (int64_t)c->n_macro);
+    }
     hipLaunchKernelGGL(k_face_sum<P>, dim3((unsigned)c->n_faces), dim3(128), 0, st, c->d_yl, c->d_side, y,
                        c->n_faces);
     return hip_ok(hipGetLastError());
 }
 
+// inverses of K's diagonal face blocks; with Ahat NULL the blocks are formed
+// from the factors first (k_mf_face_blocks)
 template <int P>
 mehdg_err trace_launch_precond_setup(mehdg_ctx* c, const double* Ahat, hipStream_t st) {
     const size_t lds = BlockInvCfg<P>::lds_bytes;
-    if (!allow_lds(&k_face_block_inv<P>, lds)) return MEHDG_EHIP;
-    hipLaunchKernelGGL(k_face_block_inv<P>, dim3((unsigned)c->n_faces), dim3(256), lds, st, Ahat, c->d_side,
-                       c->d_Dinv, c->n_faces);
+    if (Ahat) {
+        if (!allow_lds(&k_face_block_inv<P, false>, lds)) return MEHDG_EHIP;
+        hipLaunchKernelGGL((k_face_block_inv<P, false>), dim3((unsigned)c->n_faces), dim3(256), lds, st, Ahat,
+                           c->d_side, c->d_Dinv, c->n_faces);
+    } else {
+        constexpr int BS = 5 * Dims<P>::nf;
+        constexpr int tiles = ((BS + GM - 1) / GM) * ((BS + GT - 1) / GT);
+        if (!allow_lds(&k_face_block_inv<P, true>, lds)) return MEHDG_EHIP;
+        hipLaunchKernelGGL(k_mf_face_blocks<P>, dim3((unsigned)(c->n_faces * tiles)), dim3(GTHREADS), 0, st, c->d_B,
+                           c->d_side, c->d_Dinv, c->n_faces);
+        hipLaunchKernelGGL((k_face_block_inv<P, true>), dim3((unsigned)c->n_faces), dim3(256), lds, st, c->d_B,
+                           c->d_side, c->d_Dinv, c->n_faces);
+    }
     return hip_ok(hipGetLastError());
 }
 
@@ -742,6 +767,15 @@ mehdg_err ensure_trace_work(mehdg_ctx* c, bool precond) {
     const int64_t BS = face_block(c->p), NH = 6 * BS;
     if (!c->d_yl && (e = dev_alloc(c, &c->d_yl, c->n_macro * NH)) != MEHDG_OK) return e;
     if (precond && !c->d_Dinv && (e = dev_alloc(c, &c->d_Dinv, c->n_faces * BS * BS)) != MEHDG_OK) return e;
+    return MEHDG_OK;
+}
+
+// The matrix-free operator reads the factors of an FP64 condensation.
+mehdg_err ensure_matrix_free(mehdg_ctx* c) {
+    if (c->stage != 2) return MEHDG_ESTATE;
+    int64_t sz[5];
+    (void)mehdg_sizes(c->p, sz);
+    if (!c->d_mfw) return dev_alloc(c, &c->d_mfw, c->n_macro * sz[2]);
     return MEHDG_OK;
 }
 
@@ -913,6 +947,190 @@ mehdg_err trace_gmres(mehdg_ctx* c, const double* Ahat, const double* F, double*
     return MEHDG_OK;
 }
 
+// z ~ K^-1 r by `inner` iterations of GMRES from z = 0, right-preconditioned
+// with the face-block Jacobi inverses (no restart, no stopping test: a fixed
+// polynomial-plus-Jacobi preconditioner, different for every r, which is
+// why the outer solver is flexible).  inner = 0: z = Jacobi(r).
+template <int P>
+mehdg_err inner_gmres(mehdg_ctx* c, const double* Ahat, const double* r, double* z, int inner, hipStream_t st) {
+    const int64_t N = c->n_faces * face_block(P);
+    mehdg_err e;
+    if (inner <= 0) return trace_launch_precond_apply<P>(c, r, z, st);
+    double* V = c->d_iV;
+    double* w = c->d_w;
+    double b2;
+    if ((e = host_dots(c, r, N, 1, r, &b2, st)) != MEHDG_OK) return e;
+    const double beta = std::sqrt(b2);
+    if (!(beta > 0.0) || !std::isfinite(beta)) return host_axpby(N, 0.0, r, 0.0, z, st);
+    if ((e = host_axpby(N, 1.0 / beta, r, 0.0, V, st)) != MEHDG_OK) return e;
+    std::vector<double> H((size_t)(inner + 1) * inner, 0.0), cs(inner), sn(inner), g(inner + 1, 0.0), y(inner),
+        h(inner + 1), h2(inner + 1);
+    auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * inner + j]; };
+    g[0] = beta;
+    int j = 0;
+    for (; j < inner; ++j) {
+        double* vj = V + (int64_t)j * N;
+        if ((e = trace_launch_precond_apply<P>(c, vj, z, st)) != MEHDG_OK) return e;
+        if ((e = trace_launch_apply<P>(c, Ahat, z, w, st)) != MEHDG_OK) return e;
+        for (int pass = 0; pass < 2; ++pass) {
+            double* hh = pass ? h2.data() : h.data();
+            if ((e = host_dots(c, V, N, j + 1, w, hh, st)) != MEHDG_OK) return e;
+            for (int i = 0; i <= j; ++i) hh[i] = -hh[i];
+            if ((e = host_combine(c, V, N, j + 1, hh, w, st)) != MEHDG_OK) return e;
+        }
+        for (int i = 0; i <= j; ++i) Hij(i, j) = -(h[i] + h2[i]);
+        double hn2;
+        if ((e = host_dots(c, w, N, 1, w, &hn2, st)) != MEHDG_OK) return e;
+        const double hn = std::sqrt(hn2);
+        Hij(j + 1, j) = hn;
+        for (int i = 0; i < j; ++i) {
+            const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+            Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+            Hij(i, j) = t;
+        }
+        const double rr = std::hypot(Hij(j, j), Hij(j + 1, j));
+        cs[j] = rr > 0.0 ? Hij(j, j) / rr : 1.0;
+        sn[j] = rr > 0.0 ? Hij(j + 1, j) / rr : 0.0;
+        Hij(j, j) = rr;
+        Hij(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        if (!(hn > 0.0) || j + 1 == inner) {
+            ++j;
+            break;
+        }
+        if ((e = host_axpby(N, 1.0 / hn, w, 0.0, V + (int64_t)(j + 1) * N, st)) != MEHDG_OK) return e;
+    }
+    for (int i = j - 1; i >= 0; --i) {
+        double sacc = g[i];
+        for (int k = i + 1; k < j; ++k) sacc -= Hij(i, k) * y[k];
+        y[i] = Hij(i, i) != 0.0 ? sacc / Hij(i, i) : 0.0;
+    }
+    // z = Jacobi (V y)
+    if ((e = host_axpby(N, 0.0, r, 0.0, w, st)) != MEHDG_OK) return e;
+    if ((e = host_combine(c, V, N, j, y.data(), w, st)) != MEHDG_OK) return e;
+    return trace_launch_precond_apply<P>(c, w, z, st);
+}
+
+// Flexible GMRES (Saad 1993) on K dVhat = F, Sec. 6.4: the preconditioner of
+// every outer direction is `inner` iterations of the inner GMRES above, so
+// the preconditioned directions Z_j are kept; classical Gram-Schmidt twice;
+// x += Z y at every restart.  Ahat NULL: K applied matrix-free from the
+// stored factors and the Jacobi blocks formed from them.
+template <int P>
+mehdg_err trace_fgmres(mehdg_ctx* c, const double* Ahat, const double* F, double* x, double rtol, int maxit,
+                       int restart, int inner, int32_t* iters, int32_t* inner_total, double* relres,
+                       hipStream_t st) {
+    const int64_t N = c->n_faces * face_block(P);
+    mehdg_err e;
+    const int nbasis = restart > inner ? restart : inner;
+    if (nbasis > c->gm_restart) {
+        (void)hipFree(c->d_V);
+        (void)hipFree(c->d_part);
+        (void)hipFree(c->d_coef);
+        c->d_V = c->d_part = c->d_coef = nullptr;
+        if ((e = dev_alloc(c, &c->d_V, (nbasis + 1) * N)) != MEHDG_OK ||
+            (e = dev_alloc(c, &c->d_part, (int64_t)(nbasis + 1) * kDotBlocks)) != MEHDG_OK ||
+            (e = dev_alloc(c, &c->d_coef, (int64_t)nbasis + 1)) != MEHDG_OK)
+            return e;
+        c->gm_restart = nbasis;
+    }
+    if (restart > c->fg_restart) {
+        (void)hipFree(c->d_fZ);
+        c->d_fZ = nullptr;
+        if ((e = dev_alloc(c, &c->d_fZ, (int64_t)restart * N)) != MEHDG_OK) return e;
+        c->fg_restart = restart;
+    }
+    if (inner > c->fg_inner) {
+        (void)hipFree(c->d_iV);
+        c->d_iV = nullptr;
+        if ((e = dev_alloc(c, &c->d_iV, (int64_t)(inner + 1) * N)) != MEHDG_OK) return e;
+        c->fg_inner = inner;
+    }
+    if (!c->d_w && (e = dev_alloc(c, &c->d_w, N)) != MEHDG_OK) return e;
+    if (!c->d_z && (e = dev_alloc(c, &c->d_z, N)) != MEHDG_OK) return e;
+    c->h_part.assign((size_t)(nbasis + 1) * kDotBlocks, 0.0);
+    c->h_coef.assign((size_t)nbasis + 1, 0.0);
+    if ((e = trace_launch_precond_setup<P>(c, Ahat, st)) != MEHDG_OK) return e;
+    double* V = c->d_V;
+    double* Z = c->d_fZ;
+    double* w = c->d_w;
+    double bn2;
+    if ((e = host_dots(c, F, N, 1, F, &bn2, st)) != MEHDG_OK) return e;
+    const double bnorm = std::sqrt(bn2);
+    int it = 0, itot = 0;
+    double res = 0.0;
+    *inner_total = 0;
+    if (!(bnorm > 0.0)) {
+        if ((e = host_axpby(N, 0.0, F, 0.0, x, st)) != MEHDG_OK) return e;
+        *iters = 0;
+        *relres = 0.0;
+        return MEHDG_OK;
+    }
+    std::vector<double> H((size_t)(restart + 1) * restart, 0.0), cs(restart), sn(restart), g(restart + 1),
+        y(restart), h(restart + 1), h2(restart + 1);
+    auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * restart + j]; };
+    while (true) {
+        if ((e = trace_launch_apply<P>(c, Ahat, x, w, st)) != MEHDG_OK) return e;
+        if ((e = host_axpby(N, 1.0, F, -1.0, w, st)) != MEHDG_OK) return e;
+        double b2;
+        if ((e = host_dots(c, w, N, 1, w, &b2, st)) != MEHDG_OK) return e;
+        const double beta = std::sqrt(b2);
+        res = beta;
+        if (beta <= rtol * bnorm || it >= maxit || !std::isfinite(beta)) break;
+        if ((e = host_axpby(N, 1.0 / beta, w, 0.0, V, st)) != MEHDG_OK) return e;
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        while (j < restart && it < maxit) {
+            double* zj = Z + (int64_t)j * N;
+            if ((e = inner_gmres<P>(c, Ahat, V + (int64_t)j * N, zj, inner, st)) != MEHDG_OK) return e;
+            itot += inner;
+            if ((e = trace_launch_apply<P>(c, Ahat, zj, w, st)) != MEHDG_OK) return e;
+            for (int pass = 0; pass < 2; ++pass) {
+                double* hh = pass ? h2.data() : h.data();
+                if ((e = host_dots(c, V, N, j + 1, w, hh, st)) != MEHDG_OK) return e;
+                for (int i = 0; i <= j; ++i) hh[i] = -hh[i];
+                if ((e = host_combine(c, V, N, j + 1, hh, w, st)) != MEHDG_OK) return e;
+            }
+            for (int i = 0; i <= j; ++i) Hij(i, j) = -(h[i] + h2[i]);
+            double hn2;
+            if ((e = host_dots(c, w, N, 1, w, &hn2, st)) != MEHDG_OK) return e;
+            const double hn = std::sqrt(hn2);
+            Hij(j + 1, j) = hn;
+            if (hn > 0.0 && (e = host_axpby(N, 1.0 / hn, w, 0.0, V + (int64_t)(j + 1) * N, st)) != MEHDG_OK)
+                return e;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+                Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+                Hij(i, j) = t;
+            }
+            const double rr = std::hypot(Hij(j, j), Hij(j + 1, j));
+            cs[j] = rr > 0.0 ? Hij(j, j) / rr : 1.0;
+            sn[j] = rr > 0.0 ? Hij(j + 1, j) / rr : 0.0;
+            Hij(j, j) = rr;
+            Hij(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            res = std::fabs(g[j + 1]);
+            ++it;
+            ++j;
+            if (res <= rtol * bnorm || hn == 0.0) break;
+        }
+        // x += Z y,  H y = g
+        for (int i = j - 1; i >= 0; --i) {
+            double sacc = g[i];
+            for (int k = i + 1; k < j; ++k) sacc -= Hij(i, k) * y[k];
+            y[i] = sacc / Hij(i, i);
+        }
+        if ((e = host_combine(c, Z, N, j, y.data(), x, st)) != MEHDG_OK) return e;
+    }
+    *iters = it;
+    *inner_total = itot;
+    *relres = res / bnorm;
+    return MEHDG_OK;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------------
@@ -1024,6 +1242,9 @@ mehdg_err mehdg_destroy(mehdg_ctx* c) {
     (void)hipFree(c->d_fid);
     (void)hipFree(c->d_side);
     (void)hipFree(c->d_yl);
+    (void)hipFree(c->d_mfw);
+    (void)hipFree(c->d_fZ);
+    (void)hipFree(c->d_iV);
     (void)hipFree(c->d_Dinv);
     (void)hipFree(c->d_V);
     (void)hipFree(c->d_w);
@@ -1360,7 +1581,8 @@ mehdg_err mehdg_trace_gather(mehdg_ctx* c, const double* xg, double* xl, mehdg_s
 mehdg_err mehdg_trace_apply(mehdg_ctx* c, const double* Ahat, const double* x, double* y, mehdg_stream stream) {
     mehdg_err e = trace_ready(c);
     if (e != MEHDG_OK) return e;
-    if (!Ahat || !x || !y) return MEHDG_EINVAL;
+    if (!x || !y) return MEHDG_EINVAL;
+    if (!Ahat && (e = ensure_matrix_free(c)) != MEHDG_OK) return e;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     switch (c->p) {
         case 1: return trace_launch_apply<1>(c, Ahat, x, y, st);
@@ -1373,7 +1595,7 @@ mehdg_err mehdg_trace_apply(mehdg_ctx* c, const double* Ahat, const double* x, d
 mehdg_err mehdg_trace_precond_setup(mehdg_ctx* c, const double* Ahat, mehdg_stream stream) {
     mehdg_err e = trace_ready(c);
     if (e != MEHDG_OK) return e;
-    if (!Ahat) return MEHDG_EINVAL;
+    if (!Ahat && (e = ensure_matrix_free(c)) != MEHDG_OK) return e;
     if ((e = ensure_trace_work(c, true)) != MEHDG_OK) return e;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     switch (c->p) {
@@ -1402,15 +1624,34 @@ mehdg_err mehdg_trace_solve(mehdg_ctx* c, const double* Ahat, const double* F, d
                             int32_t maxit, int32_t restart, int32_t* iters, double* relres, mehdg_stream stream) {
     mehdg_err e = trace_ready(c);
     if (e != MEHDG_OK) return e;
-    if (!Ahat || !F || !x || !iters || !relres || !(rtol > 0.0) || maxit < 0 || restart < 1 ||
-        restart > kMaxRestart)
+    if (!F || !x || !iters || !relres || !(rtol > 0.0) || maxit < 0 || restart < 1 || restart > kMaxRestart)
         return MEHDG_EINVAL;
+    if (!Ahat && (e = ensure_matrix_free(c)) != MEHDG_OK) return e;
     if ((e = ensure_trace_work(c, true)) != MEHDG_OK) return e;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     switch (c->p) {
         case 1: return trace_gmres<1>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
         case 2: return trace_gmres<2>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
         case 3: return trace_gmres<3>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
+        default: return MEHDG_EINVAL;
+    }
+}
+
+mehdg_err mehdg_trace_solve_fgmres(mehdg_ctx* c, const double* Ahat, const double* F, double* x, double rtol,
+                                   int32_t maxit, int32_t restart, int32_t inner, int32_t* iters,
+                                   int32_t* inner_iters, double* relres, mehdg_stream stream) {
+    mehdg_err e = trace_ready(c);
+    if (e != MEHDG_OK) return e;
+    if (!F || !x || !iters || !inner_iters || !relres || !(rtol > 0.0) || maxit < 0 || restart < 1 ||
+        restart > kMaxRestart || inner < 0 || inner > kMaxRestart)
+        return MEHDG_EINVAL;
+    if (!Ahat && (e = ensure_matrix_free(c)) != MEHDG_OK) return e;
+    if ((e = ensure_trace_work(c, true)) != MEHDG_OK) return e;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    switch (c->p) {
+        case 1: return trace_fgmres<1>(c, Ahat, F, x, rtol, maxit, restart, inner, iters, inner_iters, relres, st);
+        case 2: return trace_fgmres<2>(c, Ahat, F, x, rtol, maxit, restart, inner, iters, inner_iters, relres, st);
+        case 3: return trace_fgmres<3>(c, Ahat, F, x, rtol, maxit, restart, inner, iters, inner_iters, relres, st);
         default: return MEHDG_EINVAL;
     }
 }

@@ -95,6 +95,9 @@ def load(path: str = LIB_PATH):
     lib.mehdg_trace_precond_apply.argtypes = [vp, vp, vp, vp]
     lib.mehdg_trace_solve.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, i32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(ctypes.c_double), vp]
+    lib.mehdg_trace_solve_fgmres.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, i32, i32,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_double), vp]
     lib.mehdg_add_source.argtypes = [vp, vp, vp, vp]
     lib.mehdg_jvp.argtypes = [vp] + [vp] * 6 + [vp]
     lib.mehdg_condense_rhs.argtypes = [vp, vp, vp, vp, vp]
@@ -125,7 +128,7 @@ def load(path: str = LIB_PATH):
                  "mehdg_recover", "mehdg_status", "mehdg_copy_bordered", "mehdg_load_bordered", "mehdg_profile_enable",
                  "mehdg_profile_read", "mehdg_trace_setup", "mehdg_trace_rhs", "mehdg_trace_apply",
                  "mehdg_trace_gather", "mehdg_trace_precond_setup", "mehdg_trace_precond_apply",
-                 "mehdg_trace_solve"):
+                 "mehdg_trace_solve", "mehdg_trace_solve_fgmres"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -279,8 +282,9 @@ class Context:
             raise MehdgError(rc, "mehdg_trace_rhs")
 
     def trace_apply(self, Ahat, x, y, stream=None):
+        """y = K x; Ahat None: matrix-free from the factors of the last FP64 condensation."""
         S, T = self.shapes(), self.trace_shape()
-        rc = load().mehdg_trace_apply(self._handle, _ptr(Ahat, S["Ahat"], "Ahat"), _ptr(x, T, "x"),
+        rc = load().mehdg_trace_apply(self._handle, _ptr(Ahat, S["Ahat"], "Ahat", optional=True), _ptr(x, T, "x"),
                                       _ptr(y, T, "y"), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_trace_apply")
@@ -292,7 +296,8 @@ class Context:
             raise MehdgError(rc, "mehdg_trace_gather")
 
     def trace_precond_setup(self, Ahat, stream=None):
-        rc = load().mehdg_trace_precond_setup(self._handle, _ptr(Ahat, self.shapes()["Ahat"], "Ahat"),
+        rc = load().mehdg_trace_precond_setup(self._handle,
+                                              _ptr(Ahat, self.shapes()["Ahat"], "Ahat", optional=True),
                                               _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_trace_precond_setup")
@@ -331,12 +336,26 @@ class Context:
         S, T = self.shapes(), self.trace_shape()
         it = ctypes.c_int32()
         rr = ctypes.c_double()
-        rc = load().mehdg_trace_solve(self._handle, _ptr(Ahat, S["Ahat"], "Ahat"), _ptr(F, T, "F"),
+        rc = load().mehdg_trace_solve(self._handle, _ptr(Ahat, S["Ahat"], "Ahat", optional=True), _ptr(F, T, "F"),
                                       _ptr(x, T, "x"), float(rtol), int(maxit), int(restart),
                                       ctypes.byref(it), ctypes.byref(rr), _stream(stream))
         if rc:
             raise MehdgError(rc, "mehdg_trace_solve")
         return int(it.value), float(rr.value)
+
+    def trace_solve_fgmres(self, Ahat, F, x, rtol=1e-10, maxit=200, restart=30, inner=5, stream=None):
+        """FGMRES on K x = F with `inner` block-Jacobi GMRES iterations as its preconditioner
+        (Ahat None: matrix-free); returns (outer iterations, inner iterations, relative residual)."""
+        S, T = self.shapes(), self.trace_shape()
+        it, iin = ctypes.c_int32(), ctypes.c_int32()
+        rr = ctypes.c_double()
+        rc = load().mehdg_trace_solve_fgmres(self._handle, _ptr(Ahat, S["Ahat"], "Ahat", optional=True),
+                                             _ptr(F, T, "F"), _ptr(x, T, "x"), float(rtol), int(maxit),
+                                             int(restart), int(inner), ctypes.byref(it), ctypes.byref(iin),
+                                             ctypes.byref(rr), _stream(stream))
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_solve_fgmres")
+        return int(it.value), int(iin.value), float(rr.value)
 
     # calls --------------------------------------------------------------
     def assemble(self, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, want_blocks=False, stream=None):
