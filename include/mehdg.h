@@ -277,8 +277,10 @@ int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
  *
  * Builds the face map: face_ids [n_macro][6] (host) gives the global face of
  * every local face; every face in [0, n_faces) must occur exactly twice
- * (periodic or interior faces), else MEHDG_EINVAL; a context with wall faces
- * is MEHDG_EINVAL too (not part of this path).  Synchronises. */
+ * (periodic or interior faces) unless it is a wall face of the mesh's face_bc,
+ * which belongs to its macro alone (a domain boundary: exactly one side, the
+ * boundary operator's trace equations); anything else is MEHDG_EINVAL.
+ * Synchronises. */
 mehdg_err mehdg_trace_setup(mehdg_ctx* ctx, const int64_t* face_ids, int64_t n_faces);
 
 /* F = sum_m P_m^T bhat_m. */

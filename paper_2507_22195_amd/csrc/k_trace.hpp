@@ -17,7 +17,7 @@
 namespace mehdg {
 
 // dst[g][e] = src[m1][f1][e] + src[m2][f2][e]  (face blocks of BS = 5 nf values)
-// side[g] = {m1, f1, m2, f2}
+// side[g] = {m1, f1, m2, f2}; m2 = -1 on a wall face (one side)
 template <int P>
 __global__ void __launch_bounds__(128) k_face_sum(const double* __restrict__ src, const int64_t* __restrict__ side,
                                                   double* __restrict__ dst, int64_t n_faces) {
@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(128) k_face_sum(const double* __restrict__ src
     if (g >= n_faces) return;
     const int64_t m1 = side[4 * g], f1 = side[4 * g + 1], m2 = side[4 * g + 2], f2 = side[4 * g + 3];
     for (int e = threadIdx.x; e < BS; e += blockDim.x)
-        dst[g * BS + e] = src[m1 * NH + f1 * BS + e] + src[m2 * NH + f2 * BS + e];
+        dst[g * BS + e] = src[m1 * NH + f1 * BS + e] + (m2 >= 0 ? src[m2 * NH + f2 * BS + e] : 0.0);
 }
 
 // xl[m][f][e] = xg[fid[m][f]][e]
@@ -203,9 +203,9 @@ __global__ void __launch_bounds__(GTHREADS, 4) k_mf_face_blocks(const double* __
         tile_mma<true>(Bm + (int64_t)(NV + fa * BS) * ld, ld, Bm + NV + fb * BS, ld, NV, r0, c0, BS, BS, acc, sm);
         __syncthreads();
     };
-    const bool same = m1 == m2;
+    const bool same = m1 == m2, two = m2 >= 0;   // a wall face has one side
     product(m1, f1, f1);
-    product(m2, f2, f2);
+    if (two) product(m2, f2, f2);
     if (same) {
         product(m1, f1, f2);
         product(m1, f2, f1);
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(GTHREADS, 4) k_mf_face_blocks(const double* __
             for (int q = 0; q < 4; ++q) {
                 const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
                 if (r < BS && c < BS) {
-                    double d = acc[bi][bj][q] + aprime(m1, f1, f1, r, c) + aprime(m2, f2, f2, r, c);
+                    double d = acc[bi][bj][q] + aprime(m1, f1, f1, r, c) + (two ? aprime(m2, f2, f2, r, c) : 0.0);
                     if (same) d += aprime(m1, f1, f2, r, c) + aprime(m1, f2, f1, r, c);
                     out[(int64_t)r * BS + c] = d;
                 }
@@ -285,8 +285,9 @@ __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict
     double* a = CFG::in_lds ? &LL.a[0][0] : out;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t m1 = side[4 * g], f1 = side[4 * g + 1], m2 = side[4 * g + 2], f2 = side[4 * g + 3];
+    const bool two = m2 >= 0;   // a wall face has one side
     const double* A1 = Ahat + m1 * (int64_t)NH * NH + (f1 * BS) * (int64_t)NH + f1 * BS;
-    const double* A2 = Ahat + m2 * (int64_t)NH * NH + (f2 * BS) * (int64_t)NH + f2 * BS;
+    const double* A2 = two ? Ahat + m2 * (int64_t)NH * NH + (f2 * BS) * (int64_t)NH + f2 * BS : A1;
     // both sides on one macro (a periodic box one macro wide): K's block also
     // holds that macro's couplings between the two faces
     const bool same = m1 == m2;
@@ -298,7 +299,7 @@ __global__ void __launch_bounds__(256) k_face_block_inv(const double* __restrict
     } else {
         for (int e = tid; e < BS * BS; e += blockDim.x) {
             const int i = e / BS, j = e % BS;
-            double d = A1[(int64_t)i * NH + j] + A2[(int64_t)i * NH + j];
+            double d = A1[(int64_t)i * NH + j] + (two ? A2[(int64_t)i * NH + j] : 0.0);
             if (same) d += A12[(int64_t)i * NH + j] + A21[(int64_t)i * NH + j];
             a[i * lda + j] = d;
         }

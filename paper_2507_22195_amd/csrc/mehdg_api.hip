@@ -1516,10 +1516,16 @@ int64_t mehdg_workspace_bytes(const mehdg_ctx* c) { return c ? c->bytes : 0; }
 
 
 mehdg_err mehdg_trace_setup(mehdg_ctx* c, const int64_t* face_ids, int64_t n_faces) {
-    if (!c || !face_ids || n_faces <= 0 || c->d_bc) return MEHDG_EINVAL;
+    if (!c || !face_ids || n_faces <= 0) return MEHDG_EINVAL;
     const int64_t M = c->n_macro;
+    // wall flags of the macros' faces (host copy of the mesh's face_bc)
+    std::vector<uint8_t> bc;
+    if (c->d_bc) {
+        bc.resize((size_t)(6 * M));
+        if (hipMemcpy(bc.data(), c->d_bc, 6 * M, hipMemcpyDeviceToHost) != hipSuccess) return MEHDG_EHIP;
+    }
     std::vector<int64_t> side((size_t)n_faces * 4, -1);
-    std::vector<int> cnt((size_t)n_faces, 0);
+    std::vector<int> cnt((size_t)n_faces, 0), walls((size_t)n_faces, 0);
     for (int64_t m = 0; m < M; ++m)
         for (int f = 0; f < 6; ++f) {
             const int64_t g = face_ids[m * 6 + f];
@@ -1527,9 +1533,12 @@ mehdg_err mehdg_trace_setup(mehdg_ctx* c, const int64_t* face_ids, int64_t n_fac
             side[g * 4 + 2 * cnt[g]] = m;
             side[g * 4 + 2 * cnt[g] + 1] = f;
             ++cnt[g];
+            if (!bc.empty() && bc[m * 6 + f]) ++walls[g];
         }
+    // an interior face has two sides and no wall; a wall face is a face of
+    // one macro only (side 2 = -1)
     for (int64_t g = 0; g < n_faces; ++g)
-        if (cnt[g] != 2) return MEHDG_EINVAL;
+        if (!((cnt[g] == 2 && walls[g] == 0) || (cnt[g] == 1 && walls[g] == 1))) return MEHDG_EINVAL;
     (void)hipFree(c->d_fid);
     (void)hipFree(c->d_side);
     (void)hipFree(c->d_Dinv);

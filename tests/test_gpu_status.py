@@ -52,7 +52,7 @@ def test_nonphysical_macro_is_flagged_and_poisoned():
 def test_call_order_and_argument_errors_of_the_newer_entry_points():
     """mehdg_jvp / mehdg_vjp before an assemble that stored the coefficients,
     mehdg_condense_rhs before a condensation: MEHDG_ESTATE; w_q without g_q,
-    an unknown want_blocks, or the trace setup of a context with wall faces:
+    an unknown want_blocks, or a face map with a face of more than two sides:
     MEHDG_EINVAL.  A flagged macro's JVP outputs are NaN."""
     from paper_2507_22195_amd import mehdg
     w = W.subset(W.workload(1), [0, 1, 2])

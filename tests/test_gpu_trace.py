@@ -164,3 +164,57 @@ def test_matrix_free_operator_and_fgmres(case):
         ctx.trace_apply(None, x, y2)
     assert ei.value.code == 4
     ctx.close()
+
+
+def test_trace_system_with_wall_faces():
+    """Isothermal no-slip walls on the two z-ends of a 2x2x2 box (periodic in x
+    and y): each wall face is a face of one macro only.  K x, the block Jacobi
+    and the GMRES / FGMRES solutions (explicit and matrix-free) against the
+    oracle's sparse system of the same faces."""
+    from paper_2507_22195_amd import mehdg
+    w = W.tgv_workload(shape=(2, 2, 2), p=1, M0=0.1, Re=1600.0, flux="ES", seed_v=43, seed_vh=44)
+    ids, nfaces = global_solve.periodic_face_ids(w.mesh.shape, w.mesh.ijk)
+    bc = np.zeros((w.n_macro, 6), dtype=np.uint8)
+    k = w.mesh.ijk[:, 2]
+    top = np.flatnonzero(k == w.mesh.shape[2] - 1)
+    bot = np.flatnonzero(k == 0)
+    bc[bot, 4] = 1
+    bc[top, 5] = 1
+    ids = ids.copy()
+    ids[top, 5] = nfaces + np.arange(top.size)          # the top faces stop being the bottom ones
+    nfaces = nfaces + top.size
+    nf = (2 * w.p + 1) ** 2
+    banner(f"trace with walls: M={w.n_macro}, {2 * top.size} wall faces of {nfaces}")
+    ctx = mehdg.Context(w.p, w.mesh.h, w.params, face_bc=bc)
+    S = ctx.shapes()
+    R_q, R_v, R_vh, ent = empty(S["R_q"]), empty(S["R_v"]), empty(S["R_vhat"]), empty(S["entropy"])
+    ctx.assemble(dev(w.v), dev(w.vhat), None, dev(w.v_old), R_q, R_v, R_vh, ent, want_blocks=True)
+    Ahat, bhat = empty(S["Ahat"]), empty(S["bhat"])
+    ctx.condense(Ahat, bhat)
+    ctx.trace_setup(ids, nfaces)
+    T = ctx.trace_shape()
+    ref = local.condense(w.p, w.mesh.h, w.v, w.vhat, w.v_old, w.params, face_bc=bc)
+    K, F = global_solve.trace_system(ref, ids, nfaces, nf)
+    Fg = empty(T)
+    ctx.trace_rhs(bhat, Fg)
+    assert rel_err(host(Fg).reshape(1, -1), F.reshape(1, -1)) < 1e-11
+    x = dev(np.random.default_rng(5).standard_normal(T))
+    for A in (Ahat, None):
+        y = empty(T)
+        ctx.trace_apply(A, x, y)
+        assert rel_err(host(y).reshape(1, -1), (K @ host(x).reshape(-1)).reshape(1, -1)) < 1e-11
+    xd = spla.spsolve(K, F)
+    for A in (Ahat, None):
+        xs = empty(T)
+        xs.zero_()
+        its, rr = ctx.trace_solve(A, Fg, xs, rtol=1e-12, maxit=400, restart=40)
+        xf = empty(T)
+        xf.zero_()
+        itf, inner, rrf = ctx.trace_solve_fgmres(A, Fg, xf, rtol=1e-12, maxit=200, restart=30, inner=5)
+        banner(f"  {'explicit' if A is not None else 'matrix-free'}: GMRES {its}, FGMRES {itf} + {inner} inner")
+        assert rr < 1e-11 and rrf < 1e-11
+        assert rel_err(host(xs).reshape(1, -1), xd.reshape(1, -1)) < 1e-7
+        assert rel_err(host(xf).reshape(1, -1), xd.reshape(1, -1)) < 1e-7
+    rc, st = ctx.status()
+    assert rc == 0
+    ctx.close()
