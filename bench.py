@@ -328,12 +328,13 @@ def mixed_degree(steps=2):
     replay = (time.perf_counter() - t0) / steps
     rc, st = b.status()
     flops = 0.0
-    for (d, _, c, ctx) in b.groups:
-        NV, NH = ctx.sz["N_V"], ctx.sz["N_VH"]
+    for (d, _, c, sz) in b.groups:
+        NV, NH = sz["N_V"], sz["N_VH"]
         flops += c * (2.0 / 3.0 * NV ** 3 + 2.0 * NV ** 2 * NH + 2.0 * NH ** 2 * NV)
     res = {"workload": "viscous TGV 16x16x16 macro-elements of 2x2x2 hexahedra, degree drawn uniformly from "
                        "{1, 2, 3} (seed 41), isothermal wall on the -z face of 20% of them (seed 42), ES flux, "
-                       "Re 1600, Mach 0.1, one Newton step (assemble + condense + recover), one stream per degree",
+                       "Re 1600, Mach 0.1, one Newton step (assemble + condense + recover): one batch call "
+                       "per phase, each degree on a stream of its own",
            "n_macro": b.n_macro, "macros_per_degree": {str(d): c for (d, _, c, _) in b.groups},
            "wall_faces": int(bc.sum()),
            "status_ok": bool(rc == 0), "ms_per_step": round(eager * 1e3, 2),

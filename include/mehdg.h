@@ -108,7 +108,8 @@ typedef struct {
     const uint8_t* face_bc;/* [n_macro][6] or NULL: 1 = isothermal no-slip wall, 0 = interior/periodic */
 } mehdg_mesh;
 
-/* Sizes of one macro-element at degree p (n, nf, N_V, N_Q, N_VH). */
+/* Sizes of one macro-element at degree p = 1..3 (n, nf, N_V, N_Q, N_VH), the
+ * degrees mehdg_create accepts; other degrees are MEHDG_EINVAL. */
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]);
 
 /* Builds the reference tables, copies the mesh and allocates workspaces.
@@ -264,6 +265,69 @@ mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t
 
 /* Bytes of device workspace the context holds. */
 int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Batches of macro-elements of mixed degree (p = 1..3) and boundary type in
+ * one call per phase of the Newton step.
+ * The batch orders its macros by degree (stable) and keeps one context per
+ * degree present; every per-macro array of a batch call is one flat device
+ * array in that order, each macro's block of the size its degree gives:
+ *   MEHDG_KEY_V      5n doubles   (v, v_old, R_v, dv)
+ *   MEHDG_KEY_Q      15n          (R_q, dq)
+ *   MEHDG_KEY_VHAT   30nf         (vhat, R_vhat, dvhat)
+ *   MEHDG_KEY_ENTROPY 1, MEHDG_KEY_AHAT N_VH^2, MEHDG_KEY_BHAT N_VH
+ * (n, nf, N_VH of the macro's degree, as mehdg_sizes), each block laid out
+ * as in the single-degree calls.  Each degree's work runs on a stream of the
+ * batch (default priority) forked from the caller's stream and joined back to
+ * it, so the calls are asynchronous on that stream, and an FP64 step is
+ * capturable in a HIP graph once the contexts' workspaces exist (after the
+ * first step). */
+typedef struct mehdg_batch mehdg_batch;
+typedef struct {
+    int64_t n_macro;
+    const int32_t* p;        /* [n_macro] degree of every macro, 1..3 */
+    const double* h;         /* [n_macro][3] sub-element edge lengths */
+    const uint8_t* face_bc;  /* [n_macro][6] or NULL: 1 = isothermal no-slip wall */
+} mehdg_batch_mesh;
+typedef enum {
+    MEHDG_KEY_V = 0,
+    MEHDG_KEY_Q = 1,
+    MEHDG_KEY_VHAT = 2,
+    MEHDG_KEY_ENTROPY = 3,
+    MEHDG_KEY_AHAT = 4,
+    MEHDG_KEY_BHAT = 5,
+    MEHDG_NKEYS = 6
+} mehdg_batch_key;
+
+/* Creates the per-degree contexts (host mesh arrays, copied) and streams.
+ * A degree outside 1..3 or invalid mesh data: MEHDG_EINVAL (as mehdg_create). */
+mehdg_err mehdg_batch_create(const mehdg_batch_mesh* mesh, const mehdg_params* prm, mehdg_batch** out);
+mehdg_err mehdg_batch_destroy(mehdg_batch* batch);
+
+/* Flat layout of arrays of kind key: order[n_macro] (host) the macro at each
+ * batch position, offsets[n_macro + 1] (host) the first double of each
+ * position's block and the total; either may be NULL. */
+mehdg_err mehdg_batch_layout(const mehdg_batch* batch, int32_t key, int64_t* order, int64_t* offsets);
+
+/* Degree groups: *n_groups, and per group (arrays of at least 3 entries, or
+ * NULL) its degree, first batch position and number of macros. */
+mehdg_err mehdg_batch_groups(const mehdg_batch* batch, int32_t* n_groups, int32_t* degree, int64_t* first,
+                             int64_t* count);
+
+/* mehdg_assemble (want_blocks = 1) then mehdg_condense(prec) on every degree
+ * group, flat arrays as above (Ahat may be NULL).  Device pointers. */
+mehdg_err mehdg_batch_assemble_condense(mehdg_batch* batch, int32_t prec, const double* v, const double* vhat,
+                                        const double* v_old, double* R_q, double* R_v, double* R_vhat,
+                                        double* entropy, double* Ahat, double* bhat, mehdg_stream stream);
+
+/* mehdg_recover on every degree group.  Device pointers. */
+mehdg_err mehdg_batch_recover(mehdg_batch* batch, const double* R_q, const double* dvhat, double* dv, double* dq,
+                              mehdg_stream stream);
+
+/* Status codes of every macro (host status[n_macro], macro order, not batch
+ * order) since the last call, cleared; returns the first non-zero code in
+ * macro order.  Synchronises the batch's streams (stream is not used). */
+mehdg_err mehdg_batch_status(mehdg_batch* batch, int32_t* status, mehdg_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Global trace system of one Newton step (Sec. 6.2, Algorithm 1): with the

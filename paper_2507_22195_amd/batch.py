@@ -1,29 +1,32 @@
 """Macro-elements of mixed polynomial degree in one Newton step (argument
-marshalling only).
+marshalling over the library's ``mehdg_batch_*`` calls).
 
-The library's kernels are compiled per degree and a context holds one
-degree.  A MixedBatch orders the macro-elements by degree (stable), keeps
-one context per degree present, and lays every per-macro array out flat in
-that order, so the macros of one degree are one contiguous slice: the
-per-degree calls take views of the flat arrays, nothing is copied.  Each
-degree runs on its own stream (default priority), forked from and joined
-back to the caller's stream, so the small groups overlap the large ones; the
-whole step can be captured in one HIP graph (torch.cuda.graph), as its calls
-allocate nothing once the contexts' workspaces exist (the first step).
+The library's kernels are compiled per degree.  A batch orders the
+macro-elements by degree (stable), keeps one context per degree present,
+and lays every per-macro array out flat in that order, so the macros of one
+degree are one contiguous slice that its context reads and writes in place.
+One library call per phase runs every degree group, each on a stream of the
+batch (default priority) forked from and joined back to the caller's stream,
+so the small groups overlap the large ones; the whole FP64 step can be
+captured in one HIP graph (torch.cuda.graph), as its calls allocate nothing
+once the contexts' workspaces exist (the first step).
 """
 from __future__ import annotations
+
+import ctypes
 
 import numpy as np
 
 from . import mehdg
 
-# per-macro sizes of the flat arrays, from mehdg.sizes(p)
-_PER = {
-    "v": lambda s: 5 * s["n"], "q": lambda s: 15 * s["n"], "vhat": lambda s: 30 * s["nf"],
-    "R_q": lambda s: 15 * s["n"], "R_v": lambda s: 5 * s["n"], "R_vhat": lambda s: 30 * s["nf"],
-    "entropy": lambda s: 1, "Ahat": lambda s: s["N_VH"] ** 2, "bhat": lambda s: s["N_VH"],
-    "dv": lambda s: 5 * s["n"], "dq": lambda s: 15 * s["n"],
-}
+_KEY = {"v": "v", "q": "q", "vhat": "vhat", "R_q": "q", "R_v": "v", "R_vhat": "vhat", "entropy": "entropy",
+        "Ahat": "Ahat", "bhat": "bhat", "dv": "v", "dq": "q"}
+
+
+def _shape(key, cnt, s):
+    n, nf, NH = s["n"], s["nf"], s["N_VH"]
+    return {"v": (cnt, 5, n), "q": (cnt, 5, 3, n), "vhat": (cnt, 6, 5, nf), "entropy": (cnt,),
+            "Ahat": (cnt, NH, NH), "bhat": (cnt, NH)}[_KEY[key]]
 
 
 class MixedBatch:
@@ -31,79 +34,107 @@ class MixedBatch:
     [n_macro][6] wall flags or None."""
 
     def __init__(self, p, h, params, face_bc=None):
-        p = np.asarray(p, dtype=np.int64)
-        h = np.asarray(h, dtype=np.float64)
+        lib = mehdg.load()
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
+        h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
         if p.ndim != 1 or h.shape != (p.size, 3):
             raise ValueError("p must be [n_macro] and h [n_macro][3]")
+        bc_ptr = None
+        if face_bc is not None:
+            bc = np.ascontiguousarray(np.asarray(face_bc, dtype=np.uint8))
+            if bc.shape != (p.size, 6):
+                raise ValueError("face_bc must be [n_macro][6]")
+            bc_ptr = bc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        mesh = mehdg.BatchMesh(p.size, p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bc_ptr)
+        self._prm = mehdg.make_params(params)
+        handle = ctypes.c_void_p()
+        rc = lib.mehdg_batch_create(ctypes.byref(mesh), ctypes.byref(self._prm), ctypes.byref(handle))
+        if rc:
+            raise mehdg.MehdgError(rc, "mehdg_batch_create")
+        self._handle = handle
         self.n_macro = int(p.size)
-        self.order = np.argsort(p, kind="stable")       # batch position -> macro
-        self.p_sorted = p[self.order]
-        self.groups = []                                 # (degree, first, count, context)
-        first = 0
-        for d in sorted(set(p.tolist())):
-            cnt = int((p == d).sum())
-            idx = self.order[first:first + cnt]
-            bc = None if face_bc is None else np.asarray(face_bc, dtype=np.uint8)[idx]
-            self.groups.append((int(d), first, cnt, mehdg.Context(int(d), h[idx], params, face_bc=bc)))
-            first += cnt
-        self._streams = None
+        ng = ctypes.c_int32()
+        deg, first, count = (ctypes.c_int32 * 3)(), (ctypes.c_int64 * 3)(), (ctypes.c_int64 * 3)()
+        rc = lib.mehdg_batch_groups(handle, ctypes.byref(ng), deg, first, count)
+        if rc:
+            raise mehdg.MehdgError(rc, "mehdg_batch_groups")
+        # (degree, first batch position, count, sizes of the degree)
+        self.groups = [(int(deg[i]), int(first[i]), int(count[i]), mehdg.sizes(int(deg[i])))
+                       for i in range(ng.value)]
+        order = np.empty(self.n_macro, dtype=np.int64)
+        self._off = {}
+        for key, code in mehdg.BATCH_KEYS.items():
+            off = np.empty(self.n_macro + 1, dtype=np.int64)
+            rc = lib.mehdg_batch_layout(handle, code, order.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                        off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+            if rc:
+                raise mehdg.MehdgError(rc, "mehdg_batch_layout")
+            self._off[key] = off
+        self.order = order                                # batch position -> macro
 
     def close(self):
-        for g in self.groups:
-            g[3].close()
+        if getattr(self, "_handle", None) is not None and self._handle.value:
+            mehdg.load().mehdg_batch_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     # flat layout -------------------------------------------------------------
     def count(self, key):
         """Doubles of the flat array ``key`` over the whole batch."""
-        return sum(c * _PER[key](ctx.sz) for (_, _, c, ctx) in self.groups)
-
-    def offsets(self, key):
-        out, off = [], 0
-        for (_, _, c, ctx) in self.groups:
-            out.append(off)
-            off += c * _PER[key](ctx.sz)
-        return out
+        return int(self._off[_KEY[key]][-1])
 
     def alloc(self, key):
         import torch
         return torch.empty(self.count(key), dtype=torch.float64, device="cuda")
 
     def view(self, flat, key, gi):
-        """Group gi's slice of a flat array, shaped as its context expects."""
-        d, first, c, ctx = self.groups[gi]
-        off = self.offsets(key)[gi]
-        return flat[off:off + c * _PER[key](ctx.sz)].view(ctx.shapes()[key])
+        """Group gi's slice of a flat array, shaped as a context of its degree expects."""
+        d, first, c, s = self.groups[gi]
+        off = self._off[_KEY[key]]
+        return flat[int(off[first]):int(off[first + c])].view(_shape(key, c, s))
 
     def pack(self, key, parts):
         """Flat host array from per-degree arrays parts[d] ([count_d][...], macro order)."""
         return np.concatenate([np.ascontiguousarray(parts[d]).reshape(-1) for (d, _, _, _) in self.groups])
 
+    def _flat(self, t, key, name, optional=False):
+        return mehdg._ptr(t, (self.count(key),), name, optional)
+
     # the step ------------------------------------------------------------------
-    def step(self, v, vhat, v_old, R_q, R_v, R_vhat, entropy, Ahat, bhat, dvhat, dv, dq):
+    def assemble_condense(self, v, vhat, v_old, R_q, R_v, R_vhat, entropy, Ahat, bhat, prec="fp64",
+                          stream=None):
+        F = self._flat
+        rc = mehdg.load().mehdg_batch_assemble_condense(
+            self._handle, mehdg.PRECISIONS[prec], F(v, "v", "v"), F(vhat, "vhat", "vhat"), F(v_old, "v", "v_old"),
+            F(R_q, "R_q", "R_q"), F(R_v, "R_v", "R_v"), F(R_vhat, "R_vhat", "R_vhat"),
+            F(entropy, "entropy", "entropy"), F(Ahat, "Ahat", "Ahat", optional=True), F(bhat, "bhat", "bhat"),
+            mehdg._stream(stream))
+        if rc:
+            raise mehdg.MehdgError(rc, "mehdg_batch_assemble_condense")
+
+    def recover(self, R_q, dvhat, dv, dq, stream=None):
+        F = self._flat
+        rc = mehdg.load().mehdg_batch_recover(self._handle, F(R_q, "R_q", "R_q"), F(dvhat, "vhat", "dvhat"),
+                                              F(dv, "dv", "dv"), F(dq, "dq", "dq"), mehdg._stream(stream))
+        if rc:
+            raise mehdg.MehdgError(rc, "mehdg_batch_recover")
+
+    def step(self, v, vhat, v_old, R_q, R_v, R_vhat, entropy, Ahat, bhat, dvhat, dv, dq, prec="fp64"):
         """assemble + condense + recover of every degree group (flat arrays)."""
-        import torch
-        if self._streams is None:
-            self._streams = [torch.cuda.Stream() for _ in self.groups]
-        cur = torch.cuda.current_stream()
-        for gi, (d, first, c, ctx) in enumerate(self.groups):
-            s = self._streams[gi]
-            s.wait_stream(cur)
-            with torch.cuda.stream(s):
-                V = lambda t, k: self.view(t, k, gi)
-                ctx.assemble(V(v, "v"), V(vhat, "vhat"), None, V(v_old, "v"), V(R_q, "R_q"), V(R_v, "R_v"),
-                             V(R_vhat, "R_vhat"), V(entropy, "entropy"), want_blocks=True)
-                ctx.condense(V(Ahat, "Ahat"), V(bhat, "bhat"))
-                ctx.recover(V(R_q, "R_q"), V(dvhat, "vhat"), V(dv, "dv"), V(dq, "dq"))
-        for s in self._streams:
-            cur.wait_stream(s)
+        self.assemble_condense(v, vhat, v_old, R_q, R_v, R_vhat, entropy, Ahat, bhat, prec=prec)
+        self.recover(R_q, dvhat, dv, dq)
 
     def status(self):
         """(first non-zero code or 0, status per macro in macro order)."""
         st = np.zeros(self.n_macro, dtype=np.int32)
-        first_rc = 0
-        for (d, first, c, ctx) in self.groups:
-            rc, s = ctx.status()
-            st[self.order[first:first + c]] = s
-            if rc and not first_rc:
-                first_rc = rc
-        return first_rc, st
+        rc = mehdg.load().mehdg_batch_status(self._handle, st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             mehdg._stream(None))
+        if rc in (1, 3):
+            raise mehdg.MehdgError(rc, "mehdg_batch_status")
+        return int(rc), st

@@ -2,9 +2,10 @@
 
     python -m paper_2507_22195_amd.build
 
-The library is two translation units: ``csrc/mehdg_api.hip`` (hexahedral
-macro-elements, every kernel family of the step) and ``csrc/mehdg_tet.hip``
-(the tetrahedral residual).  Packed FP32 instructions are disabled for all device
+The library is three translation units: ``csrc/mehdg_api.hip`` (hexahedral
+macro-elements, every kernel family of the step), ``csrc/mehdg_tet.hip``
+(tetrahedral macro-elements) and ``csrc/mehdg_batch.hip`` (mixed-degree
+batches over per-degree contexts, host code).  Packed FP32 instructions are disabled for all device
 code.
 """
 from __future__ import annotations
@@ -28,7 +29,8 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, "mehdg_api.hip"), os.path.join(CSRC, "mehdg_tet.hip")]
+    srcs = [os.path.join(CSRC, "mehdg_api.hip"), os.path.join(CSRC, "mehdg_tet.hip"),
+            os.path.join(CSRC, "mehdg_batch.hip")]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

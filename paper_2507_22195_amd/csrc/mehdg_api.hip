@@ -1206,7 +1206,7 @@ mehdg_err poison_flagged(const int32_t* status, int64_t n_macro, double* a, int6
 extern "C" {
 
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]) {
-    if (!out || p < 1 || p > 4) return MEHDG_EINVAL;
+    if (!out || p < 1 || p > 3) return MEHDG_EINVAL;
     const int64_t n1d = 2 * p + 1;
     out[0] = n1d * n1d * n1d;
     out[1] = n1d * n1d;

@@ -50,6 +50,14 @@ class Mesh(ctypes.Structure):
                 ("h", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8))]
 
 
+class BatchMesh(ctypes.Structure):
+    _fields_ = [("n_macro", ctypes.c_int64), ("p", ctypes.POINTER(ctypes.c_int32)),
+                ("h", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8))]
+
+
+BATCH_KEYS = {"v": 0, "q": 1, "vhat": 2, "entropy": 3, "Ahat": 4, "bhat": 5}
+
+
 class TetMesh(ctypes.Structure):
     _fields_ = [("n_macro", ctypes.c_int64), ("p", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("X", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8))]
@@ -106,6 +114,17 @@ def load(path: str = LIB_PATH):
     lib.mehdg_set_pseudo_time.argtypes = [vp, ctypes.c_double]
     lib.mehdg_dot.argtypes = [vp, i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
     lib.mehdg_dot_noalloc.argtypes = [i64, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.mehdg_batch_create.argtypes = [ctypes.POINTER(BatchMesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
+    lib.mehdg_batch_destroy.argtypes = [vp]
+    lib.mehdg_batch_layout.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.mehdg_batch_groups.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.mehdg_batch_assemble_condense.argtypes = [vp, i32] + [vp] * 9 + [vp]
+    lib.mehdg_batch_recover.argtypes = [vp] + [vp] * 4 + [vp]
+    lib.mehdg_batch_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
+    for name in ("mehdg_batch_create", "mehdg_batch_destroy", "mehdg_batch_layout", "mehdg_batch_groups",
+                 "mehdg_batch_assemble_condense", "mehdg_batch_recover", "mehdg_batch_status"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.mehdg_tet_sizes.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
     lib.mehdg_tet_create.argtypes = [ctypes.POINTER(TetMesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
     lib.mehdg_tet_destroy.argtypes = [vp]

@@ -58,6 +58,22 @@ def test_argument_errors_are_synchronous():
     assert lib.mehdg_jvp(None, *([None] * 6), None) == 1
     assert lib.mehdg_vjp(None, *([None] * 6), None) == 1
     assert lib.mehdg_condense_rhs(None, None, None, None, None) == 1
+    # batches: bad degree or empty mesh before any device work, NULL handles
+    handle = ctypes.c_void_p()
+    deg = (ctypes.c_int32 * 2)(2, 4)
+    hh = (ctypes.c_double * 6)(0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
+    bm = mehdg.BatchMesh(2, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None)
+    assert lib.mehdg_batch_create(ctypes.byref(bm), ctypes.byref(prm), ctypes.byref(handle)) == 1
+    assert handle.value is None
+    bm = mehdg.BatchMesh(0, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None)
+    assert lib.mehdg_batch_create(ctypes.byref(bm), ctypes.byref(prm), ctypes.byref(handle)) == 1
+    assert lib.mehdg_batch_create(None, None, None) == 1
+    assert lib.mehdg_batch_destroy(None) == 1
+    assert lib.mehdg_batch_layout(None, 0, None, None) == 1
+    assert lib.mehdg_batch_groups(None, None, None, None, None) == 1
+    assert lib.mehdg_batch_assemble_condense(None, 0, *([None] * 9), None) == 1
+    assert lib.mehdg_batch_recover(None, *([None] * 4), None) == 1
+    assert lib.mehdg_batch_status(None, None, None) == 1
 
 
 def test_wall_flags_are_checked_before_any_device_work():

@@ -1,13 +1,14 @@
-"""Macro-elements of mixed degree in one step (paper_2507_22195_amd.batch).
+"""Macro-elements of mixed degree in one step (the library's mehdg_batch_*
+calls through paper_2507_22195_amd.batch).
 
 On a 3x2x2 viscous Taylor-Green box with degrees drawn from {1, 2, 3} and
 isothermal walls on the -z face of a third of the macros: every
 output of the batched step (residual, entropy production, Ahat, bhat, dV,
 dQ) equals, bit for bit, what a single-degree context computes for the same
-macros (the same kernels on the same data); one macro of each degree has its
-Ahat compared with the oracle (1e-12); the batched step captured in one HIP
-graph (three degree groups on three forked streams) replays to the same
-bits.
+macros (the same kernels on the same data), in FP64 and in the FP32 mode with
+FP64 refinement; one macro of each degree has its Ahat compared with the
+oracle (1e-12); the batched FP64 step captured in one HIP graph (three degree
+groups on three forked streams) replays to the same bits.
 """
 import numpy as np
 import pytest
@@ -39,11 +40,17 @@ def test_mixed_degree_batch():
     out = {k: b.alloc(k) for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
     args = (v, vh, vo, out["R_q"], out["R_v"], out["R_vhat"], out["entropy"], out["Ahat"], out["bhat"], dvh,
             out["dv"], out["dq"])
+    b.step(*args, prec="fp32")
+    torch.cuda.synchronize()
+    rc, st = b.status()
+    assert rc == 0 and not st.any()
+    ref32 = {k: t.clone() for k, t in out.items()}
     b.step(*args)
     torch.cuda.synchronize()
     rc, st = b.status()
     assert rc == 0 and not st.any()
     ref = {k: t.clone() for k, t in out.items()}
+    assert sorted(b.order.tolist()) == list(range(p.size)) and np.all(np.diff(p[b.order]) >= 0)
 
     for gi, (d, first, cnt, _) in enumerate(b.groups):
         w = parts[d]
@@ -57,6 +64,13 @@ def test_mixed_degree_batch():
         torch.cuda.synchronize()
         for k, t in o.items():
             assert torch.equal(b.view(ref[k], k, gi), t), f"degree {d}: {k} differs from a single-degree context"
+        ctx.assemble(dev(w.v), dev(w.vhat), None, dev(w.v_old), o["R_q"], o["R_v"], o["R_vhat"], o["entropy"],
+                     want_blocks=True)
+        ctx.condense(o["Ahat"], o["bhat"], prec="fp32")
+        ctx.recover(o["R_q"], dev(dvh_parts[d]), o["dv"], o["dq"])
+        torch.cuda.synchronize()
+        for k, t in o.items():
+            assert torch.equal(b.view(ref32[k], k, gi), t), f"degree {d}: fp32 {k} differs from a single context"
         ctx.close()
         ws = W.subset(w, [0])
         e = rel_err(host(b.view(ref["Ahat"], "Ahat", gi))[:1],
