@@ -266,6 +266,28 @@ mehdg_err mehdg_profile_read(mehdg_ctx* ctx, double* ms, int64_t* calls, int32_t
 /* Bytes of device workspace the context holds. */
 int64_t mehdg_workspace_bytes(const mehdg_ctx* ctx);
 
+/* Tile shapes of the batched FP64 MFMA products of the condensation (the
+ * trailing updates of the LU of S and the Schur product, Sec. 6.2).  The
+ * library carries a fixed list of variants; variant i is a workgroup of
+ * shapes[6i] x shapes[6i+1] waves, each owning shapes[6i+2] x shapes[6i+3]
+ * blocks of 16 x 16, K staged in chunks of shapes[6i+4], shapes[6i+5] waves
+ * per SIMD asked for.  Every variant adds the products of one output element
+ * in the same order, so the choice changes the time and never the bits.  A
+ * context starts with the variant of the table compiled into the library
+ * for its degree (written by the package's autotuner from a sweep that
+ * times every variant on the device); mehdg_set_tile overrides it for one
+ * call site (variant -1 restores the table's).  Host calls, no device work. */
+typedef enum {
+    MEHDG_TILE_UPDATE = 0,   /* trailing updates of the LU of S */
+    MEHDG_TILE_SCHUR = 1,    /* [Ahat | bhat] = [A' | r_hat] - L21 [U12 | y], and the
+                                products of the mixed-precision refinement */
+    MEHDG_NTILE_SITES = 2
+} mehdg_tile_site;
+/* *count variants; shapes (host, 6 * count entries, or NULL) as above. */
+mehdg_err mehdg_tile_variants(int32_t* count, int32_t* shapes);
+mehdg_err mehdg_set_tile(mehdg_ctx* ctx, int32_t site, int32_t variant);
+mehdg_err mehdg_get_tile(const mehdg_ctx* ctx, int32_t site, int32_t* variant);
+
 /* ---------------------------------------------------------------------------
  * Batches of macro-elements of mixed degree (p = 1..3) and boundary type in
  * one call per phase of the Newton step.

@@ -1058,44 +1058,145 @@ struct GemmArgs {
     int64_t n_macro;
 };
 
-// TAG only separates the trailing-update launches (0) from the final Schur
-// product (1) in profiles; the code is the same.
-template <int TAG>
-__global__ void __launch_bounds__(GTHREADS, 4) k_gemm(GemmArgs g) {
-    __shared__ TileSmem sm;
+// Tile shapes of the batched product (the sweep of the tile autotuner picks
+// one per degree and call site): WM x WN waves, each owning BI x BJ blocks of
+// 16 x 16, so a workgroup of 64 WM WN threads computes a TM x TN tile with
+// TM = 16 WM BI, TN = 16 WN BJ; K is staged through LDS in chunks of KC, and
+// OCC waves per SIMD are asked of the register allocator.
+// Every shape adds the products of one output element in the same order (K
+// ascending, four at a time per MFMA), so all shapes give the same bits.
+template <int WM_, int WN_, int BI_, int BJ_, int KC_, int OCC_>
+struct GTile {
+    static constexpr int WM = WM_, WN = WN_, BI = BI_, BJ = BJ_, KC = KC_, OCC = OCC_;
+    static constexpr int TM = 16 * WM * BI, TN = 16 * WN * BJ, NT = 64 * WM * WN;
+    static constexpr int LA = TM * KC / NT, LB = KC * TN / NT;   // staged elements per thread
+    static_assert(LA * NT == TM * KC && LB * NT == KC * TN, "tile does not divide among the threads");
+};
+
+template <class T>
+struct GTileSmem {
+    double As[2][T::TM][T::KC + 1];
+    double Bs[2][T::KC][T::TN + 1];
+};
+
+// The variants the library carries, in the order of their index.
+#define MEHDG_GEMM_VARIANTS(X) \
+    X(0, 4, 2, 2, 2, 16, 4)    \
+    X(1, 4, 2, 2, 4, 16, 2)    \
+    X(2, 2, 4, 4, 2, 16, 2)    \
+    X(3, 4, 2, 2, 2, 32, 2)    \
+    X(4, 2, 2, 2, 2, 16, 3)    \
+    X(5, 4, 4, 2, 2, 16, 2)    \
+    X(6, 2, 2, 2, 4, 16, 2)
+constexpr int kGemmVariants = 7;
+
+// acc (+)= -A[r0.., 0..K) * Bt[0..K, c0..) on a T tile (the negated form is
+// the only one the products need)
+template <class T>
+__device__ __forceinline__ void tile_mma_t(const double* A, int lda, const double* Bt, int ldb, int K, int r0,
+                                           int c0, int rows, int cols, v4d (&acc)[T::BI][T::BJ],
+                                           GTileSmem<T>& sm) {
+    constexpr int KC = T::KC, TN = T::TN, NT = T::NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / T::WN, wc = wave % T::WN;
+    double ra[T::LA], rb[T::LB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < T::LA; ++i) {
+            const int e = tid + NT * i;
+            const int r = r0 + e / KC, k = k0 + e % KC;
+            ra[i] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < T::LB; ++i) {
+            const int e = tid + NT * i;
+            const int kk = k0 + e / TN, c = c0 + e % TN;
+            rb[i] = (kk < K && c < cols) ? Bt[(int64_t)kk * ldb + c] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < T::LA; ++i) {
+            const int e = tid + NT * i;
+            sm.As[buf][e / KC][e % KC] = -ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < T::LB; ++i) {
+            const int e = tid + NT * i;
+            sm.Bs[buf][e / TN][e % TN] = rb[i];
+        }
+    };
+    const int nchunk = (K + KC - 1) / KC;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) load((ch + 1) * KC);
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 4) {
+            const int kq = ks + (lane >> 4);
+            double a[T::BI], b[T::BJ];
+#pragma unroll
+            for (int bi = 0; bi < T::BI; ++bi) a[bi] = sm.As[buf][(wr * T::BI + bi) * 16 + (lane & 15)][kq];
+#pragma unroll
+            for (int bj = 0; bj < T::BJ; ++bj) b[bj] = sm.Bs[buf][kq][(wc * T::BJ + bj) * 16 + (lane & 15)];
+#pragma unroll
+            for (int bi = 0; bi < T::BI; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < T::BJ; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        }
+        if (ch + 1 < nchunk) stash(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// TAG only separates the trailing-update launches (0), the Schur product (1)
+// and the refinement residual (2) in profiles; the code is the same.
+template <int TAG, class T>
+__global__ void __launch_bounds__(T::NT, T::OCC) k_gemm(GemmArgs g) {
+    __shared__ GTileSmem<T> sm;
     int64_t m;
     int tile;
     xcd_tile(g.tiles, m, tile);
     if (m >= g.n_macro) return;
     const int tr = tile / g.tiles_c, tc = tile % g.tiles_c;
-    const int r0 = tr * GM, c0 = tc * GT;
+    const int r0 = tr * T::TM, c0 = tc * T::TN;
     if (r0 >= g.skip_r && c0 >= g.skip_c) return;   // tile entirely in the masked corner
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / T::WN, wc = wave % T::WN;
+    auto row = [&](int bi, int q) { return r0 + (wr * T::BI + bi) * 16 + (lane >> 4) + 4 * q; };
+    auto col = [&](int bj) { return c0 + (wc * T::BJ + bj) * 16 + (lane & 15); };
     const double* C = g.C + m * g.sC;
     // C is fetched first and only added after the K loop, so its latency
     // overlaps the staging and the MFMA work.
-    double cr[2][2][4];
+    double cr[T::BI][T::BJ][4];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < T::BI; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < T::BJ; ++bj)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
+                const int r = row(bi, q), c = col(bj);
                 const bool in = r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c);
                 cr[bi][bj][q] = in ? C[(int64_t)r * g.ldc + c] : 0.0;
             }
-    v4d acc[2][2];
-    zero_acc(acc);
-    tile_mma<true>(g.A + m * g.sA, g.lda, g.Bt + m * g.sB, g.ldb, g.K, r0, c0, g.rows, g.cols, acc, sm);
+    v4d acc[T::BI][T::BJ];
+#pragma unroll
+    for (int bi = 0; bi < T::BI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < T::BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+    tile_mma_t<T>(g.A + m * g.sA, g.lda, g.Bt + m * g.sB, g.ldb, g.K, r0, c0, g.rows, g.cols, acc, sm);
     double* D = g.D ? g.D + m * g.sD : nullptr;
     double* D2 = g.D2 ? g.D2 + m * g.sD2 : nullptr;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < T::BI; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+        for (int bj = 0; bj < T::BJ; ++bj)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int r = tile_row(r0, bi, q), c = tile_col(c0, bj);
+                const int r = row(bi, q), c = col(bj);
                 if (r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c)) {
                     const double v = cr[bi][bj][q] + acc[bi][bj][q];
                     if (D2 && c >= g.dsplit) D2[(int64_t)r * g.ldd2 + (c - g.dsplit)] = v;

@@ -21,12 +21,14 @@
 #include "k_trace.hpp"
 #include "tables.hpp"
 #include "tet_cond.hpp"
+#include "tile_table.hpp"
 
 using namespace mehdg;
 
 struct mehdg_ctx {
     int p = 0;
     int64_t n_macro = 0;
+    int tile[MEHDG_NTILE_SITES] = {};   // product tile variant per call site
     mehdg_params prm{};
     DevParams dp{};
     Tab1D tab{};
@@ -232,16 +234,35 @@ mehdg_err launch_poison(mehdg_ctx* c, PoisonArgs a, hipStream_t st) {
     return hip_ok(hipGetLastError());
 }
 
+template <int TAG, class T>
+mehdg_err launch_gemm_t(GemmArgs g, int64_t n, hipStream_t st) {
+    const int tr = (g.rows + T::TM - 1) / T::TM;
+    g.tiles_c = (g.cols + T::TN - 1) / T::TN;
+    if (tr <= 0 || g.tiles_c <= 0 || g.K <= 0 || n <= 0) return MEHDG_OK;
+    g.tiles = tr * g.tiles_c;
+    g.n_macro = n;
+    hipLaunchKernelGGL((k_gemm<TAG, T>), dim3(xcd_grid(g.tiles, n)), dim3(T::NT), 0, st, g);
+    return hip_ok(hipGetLastError());
+}
+
+// The batched product over the first n macros that the pointers start at, in
+// the tile shape the context holds for the product's call site.
+template <int TAG>
+mehdg_err launch_gemm_n(mehdg_ctx* c, GemmArgs g, int64_t n, int slot, hipStream_t st) {
+    const int site = TAG == 0 ? MEHDG_TILE_UPDATE : MEHDG_TILE_SCHUR;
+    Timed t(c, slot, st);
+    switch (c->tile[site]) {
+#define MEHDG_LAUNCH_VARIANT(i, wm, wn, bi, bj, kc, occ) \
+    case i: return launch_gemm_t<TAG, GTile<wm, wn, bi, bj, kc, occ>>(g, n, st);
+        MEHDG_GEMM_VARIANTS(MEHDG_LAUNCH_VARIANT)
+#undef MEHDG_LAUNCH_VARIANT
+        default: return MEHDG_EINVAL;
+    }
+}
+
 template <int TAG>
 mehdg_err launch_gemm(mehdg_ctx* c, GemmArgs g, int slot, hipStream_t st) {
-    const int tr = (g.rows + GM - 1) / GM;
-    g.tiles_c = (g.cols + GT - 1) / GT;
-    if (tr <= 0 || g.tiles_c <= 0 || g.K <= 0) return MEHDG_OK;
-    g.tiles = tr * g.tiles_c;
-    g.n_macro = c->n_macro;
-    Timed t(c, slot, st);
-    hipLaunchKernelGGL(k_gemm<TAG>, dim3(xcd_grid(g.tiles, c->n_macro)), dim3(GTHREADS), 0, st, g);
-    return hip_ok(hipGetLastError());
+    return launch_gemm_n<TAG>(c, g, c->n_macro, slot, st);
 }
 
 // D(rows, cols) -= B[rows, kb0 : kb0+K] * B[kb0 : kb0+K, cols] inside one bordered matrix,
@@ -387,20 +408,6 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         g.dsplit = 0;
     }
     return launch_gemm<1>(c, g, MEHDG_PROF_SCHUR, st);
-}
-
-// Same as launch_gemm over the first n macros of the batch that the
-// pointers start at (a wave of the mixed-precision condensation).
-template <int TAG>
-mehdg_err launch_gemm_n(mehdg_ctx* c, GemmArgs g, int64_t n, int slot, hipStream_t st) {
-    const int tr = (g.rows + GM - 1) / GM;
-    g.tiles_c = (g.cols + GT - 1) / GT;
-    if (tr <= 0 || g.tiles_c <= 0 || g.K <= 0 || n <= 0) return MEHDG_OK;
-    g.tiles = tr * g.tiles_c;
-    g.n_macro = n;
-    Timed t(c, slot, st);
-    hipLaunchKernelGGL(k_gemm<TAG>, dim3(xcd_grid(g.tiles, n)), dim3(GTHREADS), 0, st, g);
-    return hip_ok(hipGetLastError());
 }
 
 // Device memory the mixed-precision condensation may hold for one wave.
@@ -1286,6 +1293,7 @@ mehdg_err mehdg_create(const mehdg_mesh* mesh, const mehdg_params* prm, mehdg_ct
     c->p = mesh->p;
     c->n_macro = mesh->n_macro;
     c->prm = *prm;
+    for (int site = 0; site < MEHDG_NTILE_SITES; ++site) c->tile[site] = kTileTable[c->p][site];
     DevParams& d = c->dp;
     d.gamma = prm->gamma;
     d.mu = prm->viscous ? prm->mu : 0.0;
@@ -1513,6 +1521,34 @@ mehdg_err mehdg_status(mehdg_ctx* c, int32_t* status, mehdg_stream stream) {
 }
 
 int64_t mehdg_workspace_bytes(const mehdg_ctx* c) { return c ? c->bytes : 0; }
+
+mehdg_err mehdg_tile_variants(int32_t* count, int32_t* shapes) {
+    if (!count) return MEHDG_EINVAL;
+    *count = kGemmVariants;
+    if (shapes) {
+#define MEHDG_SHAPE_VARIANT(i, wm, wn, bi, bj, kc, occ) \
+    {                                                   \
+        const int32_t v[6] = {wm, wn, bi, bj, kc, occ}; \
+        for (int k = 0; k < 6; ++k) shapes[6 * i + k] = v[k]; \
+    }
+        MEHDG_GEMM_VARIANTS(MEHDG_SHAPE_VARIANT)
+#undef MEHDG_SHAPE_VARIANT
+    }
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_set_tile(mehdg_ctx* c, int32_t site, int32_t variant) {
+    if (!c || site < 0 || site >= MEHDG_NTILE_SITES || variant < -1 || variant >= kGemmVariants)
+        return MEHDG_EINVAL;
+    c->tile[site] = variant < 0 ? kTileTable[c->p][site] : variant;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_get_tile(const mehdg_ctx* c, int32_t site, int32_t* variant) {
+    if (!c || !variant || site < 0 || site >= MEHDG_NTILE_SITES) return MEHDG_EINVAL;
+    *variant = c->tile[site];
+    return MEHDG_OK;
+}
 
 
 mehdg_err mehdg_trace_setup(mehdg_ctx* c, const int64_t* face_ids, int64_t n_faces) {

@@ -125,6 +125,11 @@ def load(path: str = LIB_PATH):
     for name in ("mehdg_batch_create", "mehdg_batch_destroy", "mehdg_batch_layout", "mehdg_batch_groups",
                  "mehdg_batch_assemble_condense", "mehdg_batch_recover", "mehdg_batch_status"):
         getattr(lib, name).restype = ctypes.c_int
+    lib.mehdg_tile_variants.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.mehdg_set_tile.argtypes = [vp, i32, i32]
+    lib.mehdg_get_tile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
+    for name in ("mehdg_tile_variants", "mehdg_set_tile", "mehdg_get_tile"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.mehdg_tet_sizes.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
     lib.mehdg_tet_create.argtypes = [ctypes.POINTER(TetMesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
     lib.mehdg_tet_destroy.argtypes = [vp]
@@ -173,6 +178,28 @@ def dot_noalloc(x, y, stream=None) -> float:
     if rc:
         raise MehdgError(rc, "mehdg_dot_noalloc")
     return out.value
+
+
+TILE_SITES = {"update": 0, "schur": 1}
+
+
+def tile_variants() -> list:
+    """The tile shapes of the batched FP64 products: per variant a dict of
+    waves (WM x WN), 16 x 16 blocks per wave (BI x BJ), K chunk, waves per SIMD,
+    and the workgroup tile TM x TN."""
+    lib = load()
+    n = ctypes.c_int32()
+    rc = lib.mehdg_tile_variants(ctypes.byref(n), None)
+    if rc:
+        raise MehdgError(rc, "mehdg_tile_variants")
+    buf = (ctypes.c_int32 * (6 * n.value))()
+    lib.mehdg_tile_variants(ctypes.byref(n), buf)
+    out = []
+    for i in range(n.value):
+        wm, wn, bi, bj, kc, occ = buf[6 * i:6 * i + 6]
+        out.append(dict(WM=wm, WN=wn, BI=bi, BJ=bj, KC=kc, OCC=occ, TM=16 * wm * bi, TN=16 * wn * bj,
+                        threads=64 * wm * wn))
+    return out
 
 
 def sizes(p: int) -> dict:
@@ -472,6 +499,19 @@ class Context:
         rc = lib.mehdg_load_bordered(self._handle, int(m), ctypes.c_void_p(Bm.ctypes.data))
         if rc:
             raise MehdgError(rc, "mehdg_load_bordered")
+
+    def set_tile(self, site: str, variant: int):
+        """Tile variant of a product call site ("update", "schur"); -1 = the tuned table's."""
+        rc = load().mehdg_set_tile(self._handle, TILE_SITES[site], int(variant))
+        if rc:
+            raise MehdgError(rc, "mehdg_set_tile")
+
+    def get_tile(self, site: str) -> int:
+        out = ctypes.c_int32()
+        rc = load().mehdg_get_tile(self._handle, TILE_SITES[site], ctypes.byref(out))
+        if rc:
+            raise MehdgError(rc, "mehdg_get_tile")
+        return int(out.value)
 
     def profile(self, enable: bool):
         rc = load().mehdg_profile_enable(self._handle, int(bool(enable)))

@@ -74,6 +74,15 @@ def test_argument_errors_are_synchronous():
     assert lib.mehdg_batch_assemble_condense(None, 0, *([None] * 9), None) == 1
     assert lib.mehdg_batch_recover(None, *([None] * 4), None) == 1
     assert lib.mehdg_batch_status(None, None, None) == 1
+    # tile variants: a list of shapes; NULL contexts and bad sites are EINVAL
+    n = ctypes.c_int32()
+    assert lib.mehdg_tile_variants(ctypes.byref(n), None) == 0 and n.value >= 1
+    shapes = (ctypes.c_int32 * (6 * n.value))()
+    assert lib.mehdg_tile_variants(ctypes.byref(n), shapes) == 0
+    assert list(shapes[:6]) == [4, 2, 2, 2, 16, 4]          # variant 0: 128 x 64 tiles of 512 threads
+    assert lib.mehdg_tile_variants(None, None) == 1
+    assert lib.mehdg_set_tile(None, 0, 0) == 1
+    assert lib.mehdg_get_tile(None, 0, ctypes.byref(n)) == 1
 
 
 def test_wall_flags_are_checked_before_any_device_work():
