@@ -102,14 +102,19 @@ typedef struct {
 /* Macro-element mesh.  All pointers are host memory, copied at create. */
 typedef struct {
     int64_t n_macro;
-    int32_t p;             /* polynomial degree of the sub-elements, 1..3 */
+    int32_t p;             /* polynomial degree of the sub-elements, 1..4 (4: see below) */
     int32_t pad_;
     const double* h;       /* [n_macro][3] sub-element edge lengths (macro = 2h) */
     const uint8_t* face_bc;/* [n_macro][6] or NULL: 1 = isothermal no-slip wall, 0 = interior/periodic */
 } mehdg_mesh;
 
-/* Sizes of one macro-element at degree p = 1..3 (n, nf, N_V, N_Q, N_VH), the
- * degrees mehdg_create accepts; other degrees are MEHDG_EINVAL. */
+/* Sizes of one macro-element at degree p = 1..4 (n, nf, N_V, N_Q, N_VH), the
+ * degrees mehdg_create accepts; other degrees are MEHDG_EINVAL.
+ * Degree 4 (N_V 3645, N_VH 2430, a 295 MB bordered matrix per macro) takes
+ * the FP64 Newton step: mehdg_assemble with want_blocks 0 or 1,
+ * mehdg_condense(MEHDG_FP64), mehdg_recover and the diagnostics.  The other
+ * entry points (products, stored-factor solves, the trace system, the
+ * mixed-precision modes, want_blocks 2) return MEHDG_EINVAL at degree 4. */
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]);
 
 /* Builds the reference tables, copies the mesh and allocates workspaces.
@@ -289,7 +294,7 @@ mehdg_err mehdg_set_tile(mehdg_ctx* ctx, int32_t site, int32_t variant);
 mehdg_err mehdg_get_tile(const mehdg_ctx* ctx, int32_t site, int32_t* variant);
 
 /* ---------------------------------------------------------------------------
- * Batches of macro-elements of mixed degree (p = 1..3) and boundary type in
+ * Batches of macro-elements of mixed degree (p = 1..4) and boundary type in
  * one call per phase of the Newton step.
  * The batch orders its macros by degree (stable) and keeps one context per
  * degree present; every per-macro array of a batch call is one flat device
@@ -303,13 +308,22 @@ mehdg_err mehdg_get_tile(const mehdg_ctx* ctx, int32_t site, int32_t* variant);
  * batch (default priority) forked from the caller's stream and joined back to
  * it, so the calls are asynchronous on that stream, and an FP64 step is
  * capturable in a HIP graph once the contexts' workspaces exist (after the
- * first step). */
+ * first step).
+ * Device memory: when the contexts of all groups would need more than
+ * max_workspace_bytes, the groups with the largest macros are streamed in
+ * waves (their context holds one wave and works through the group wave by
+ * wave); mehdg_batch_groups reports the wave of every group.  The factors of
+ * a streamed group are not kept, so mehdg_batch_recover assembles and
+ * condenses each of its waves again from v, vhat, v_old (the same values,
+ * bit for bit) before the back-substitution. */
 typedef struct mehdg_batch mehdg_batch;
 typedef struct {
     int64_t n_macro;
-    const int32_t* p;        /* [n_macro] degree of every macro, 1..3 */
+    const int32_t* p;        /* [n_macro] degree of every macro, 1..4 */
     const double* h;         /* [n_macro][3] sub-element edge lengths */
     const uint8_t* face_bc;  /* [n_macro][6] or NULL: 1 = isothermal no-slip wall */
+    int64_t max_workspace_bytes;   /* device workspace of the contexts; 0: 60% of the free
+                                      device memory at creation */
 } mehdg_batch_mesh;
 typedef enum {
     MEHDG_KEY_V = 0,
@@ -322,7 +336,7 @@ typedef enum {
 } mehdg_batch_key;
 
 /* Creates the per-degree contexts (host mesh arrays, copied) and streams.
- * A degree outside 1..3 or invalid mesh data: MEHDG_EINVAL (as mehdg_create). */
+ * A degree outside 1..4 or invalid mesh data: MEHDG_EINVAL (as mehdg_create). */
 mehdg_err mehdg_batch_create(const mehdg_batch_mesh* mesh, const mehdg_params* prm, mehdg_batch** out);
 mehdg_err mehdg_batch_destroy(mehdg_batch* batch);
 
@@ -331,20 +345,24 @@ mehdg_err mehdg_batch_destroy(mehdg_batch* batch);
  * position's block and the total; either may be NULL. */
 mehdg_err mehdg_batch_layout(const mehdg_batch* batch, int32_t key, int64_t* order, int64_t* offsets);
 
-/* Degree groups: *n_groups, and per group (arrays of at least 3 entries, or
- * NULL) its degree, first batch position and number of macros. */
+/* Degree groups: *n_groups, and per group (arrays of at least 4 entries, or
+ * NULL) its degree, first batch position, number of macros and wave (the
+ * macros its context holds; equal to the number unless streamed). */
 mehdg_err mehdg_batch_groups(const mehdg_batch* batch, int32_t* n_groups, int32_t* degree, int64_t* first,
-                             int64_t* count);
+                             int64_t* count, int64_t* wave);
 
 /* mehdg_assemble (want_blocks = 1) then mehdg_condense(prec) on every degree
- * group, flat arrays as above (Ahat may be NULL).  Device pointers. */
+ * group, flat arrays as above (Ahat may be NULL).  Device pointers.  The
+ * mixed-precision modes take degrees 1..3. */
 mehdg_err mehdg_batch_assemble_condense(mehdg_batch* batch, int32_t prec, const double* v, const double* vhat,
                                         const double* v_old, double* R_q, double* R_v, double* R_vhat,
                                         double* entropy, double* Ahat, double* bhat, mehdg_stream stream);
 
-/* mehdg_recover on every degree group.  Device pointers. */
-mehdg_err mehdg_batch_recover(mehdg_batch* batch, const double* R_q, const double* dvhat, double* dv, double* dq,
-                              mehdg_stream stream);
+/* mehdg_recover on every degree group, after mehdg_batch_assemble_condense.
+ * v, vhat, v_old: the inputs of that call, read by streamed groups only (NULL
+ * allowed when no group is streamed).  Device pointers. */
+mehdg_err mehdg_batch_recover(mehdg_batch* batch, const double* v, const double* vhat, const double* v_old,
+                              const double* R_q, const double* dvhat, double* dv, double* dq, mehdg_stream stream);
 
 /* Status codes of every macro (host status[n_macro], macro order, not batch
  * order) since the last call, cleared; returns the first non-zero code in

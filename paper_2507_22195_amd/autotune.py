@@ -8,7 +8,8 @@ the library from ``csrc/tile_table.hpp``; this module makes that table:
 
 * ``sweep`` times every variant at every site on the device, on the viscous
   Taylor-Green batch of each degree (16^3 macro-elements at p = 1 and 2,
-  16 x 16 x 8 at p = 3), with the library's own per-site event timers
+  16 x 16 x 8 at p = 3, 4^3 at p = 4, whose 295 MB bordered matrices allow
+  no more in one context beside the others), with the library's own per-site event timers
   (``mehdg_profile_read``), best of ``reps`` condensations each after a fresh
   assembly.  Every variant must give the same bits as variant 0 (the
   shapes add the products of one output element in the same order): the
@@ -35,7 +36,7 @@ from . import workloads as W
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "tile_table.hpp")
-SHAPES = {1: (16, 16, 16), 2: (16, 16, 16), 3: (16, 16, 8)}
+SHAPES = {1: (16, 16, 16), 2: (16, 16, 16), 3: (16, 16, 8), 4: (4, 4, 4)}
 
 
 def _bits_sum(t) -> int:
@@ -92,7 +93,7 @@ def sweep_degree(p: int, shape=None, reps: int = 2, log=print) -> dict:
     return res
 
 
-def sweep(degrees=(1, 2, 3), reps: int = 2, log=print) -> dict:
+def sweep(degrees=(1, 2, 3, 4), reps: int = 2, log=print) -> dict:
     import torch
     out = {"device": torch.cuda.get_device_name(0), "variants": mehdg.tile_variants(), "degrees": {}}
     for p in degrees:
@@ -134,11 +135,14 @@ def render(res: dict) -> str:
                 v = var[int(i)]
                 cells.append(f"{i}:{v['TM']}x{v['TN']}/{v['KC']} {t['ms']:.2f}" + ("" if t["same_bits"] else "!"))
             lines.append(f"//     {site:6s} " + ", ".join(cells))
-    lines += ["#pragma once", "", "namespace mehdg {", "constexpr int kTileTable[4][2] = {",
+    lines += ["#pragma once", "", "namespace mehdg {", "constexpr int kTileTable[5][2] = {",
               "    {0, 0},   // (unused)"]
-    for p in (1, 2, 3):
-        row = table.get(p, {"update": 0, "schur": 0})
-        lines.append(f"    {{{row['update']}, {row['schur']}}},   // p = {p}")
+    for p in (1, 2, 3, 4):
+        row = table.get(p)
+        if row is None:
+            lines.append(f"    {{0, 0}},   // p = {p} (not swept)")
+        else:
+            lines.append(f"    {{{row['update']}, {row['schur']}}},   // p = {p}")
     lines += ["};", "}  // namespace mehdg", ""]
     return "\n".join(lines)
 
@@ -146,7 +150,7 @@ def render(res: dict) -> str:
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--sweep", action="store_true", help="time every variant on the device")
-    ap.add_argument("--degrees", type=int, nargs="+", default=[1, 2, 3])
+    ap.add_argument("--degrees", type=int, nargs="+", default=[1, 2, 3, 4])
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--out", default=None, help="sweep result (JSON)")
     ap.add_argument("--render", default=None, metavar="JSON", help="write the table header from a sweep")

@@ -30,10 +30,12 @@ def _shape(key, cnt, s):
 
 
 class MixedBatch:
-    """p [n_macro] degrees, h [n_macro][3], one parameter set, face_bc
-    [n_macro][6] wall flags or None."""
+    """p [n_macro] degrees (1..4), h [n_macro][3], one parameter set, face_bc
+    [n_macro][6] wall flags or None; max_workspace_bytes bounds the contexts'
+    device workspace (0: the library's default), beyond which the groups with
+    the largest macros are streamed in waves (``waves``)."""
 
-    def __init__(self, p, h, params, face_bc=None):
+    def __init__(self, p, h, params, face_bc=None, max_workspace_bytes=0):
         lib = mehdg.load()
         p = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
         h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
@@ -46,7 +48,7 @@ class MixedBatch:
                 raise ValueError("face_bc must be [n_macro][6]")
             bc_ptr = bc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         mesh = mehdg.BatchMesh(p.size, p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                               h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bc_ptr)
+                               h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bc_ptr, int(max_workspace_bytes))
         self._prm = mehdg.make_params(params)
         handle = ctypes.c_void_p()
         rc = lib.mehdg_batch_create(ctypes.byref(mesh), ctypes.byref(self._prm), ctypes.byref(handle))
@@ -55,13 +57,15 @@ class MixedBatch:
         self._handle = handle
         self.n_macro = int(p.size)
         ng = ctypes.c_int32()
-        deg, first, count = (ctypes.c_int32 * 3)(), (ctypes.c_int64 * 3)(), (ctypes.c_int64 * 3)()
-        rc = lib.mehdg_batch_groups(handle, ctypes.byref(ng), deg, first, count)
+        deg, first, count, wave = (ctypes.c_int32 * 4)(), (ctypes.c_int64 * 4)(), (ctypes.c_int64 * 4)(), \
+            (ctypes.c_int64 * 4)()
+        rc = lib.mehdg_batch_groups(handle, ctypes.byref(ng), deg, first, count, wave)
         if rc:
             raise mehdg.MehdgError(rc, "mehdg_batch_groups")
         # (degree, first batch position, count, sizes of the degree)
         self.groups = [(int(deg[i]), int(first[i]), int(count[i]), mehdg.sizes(int(deg[i])))
                        for i in range(ng.value)]
+        self.waves = {int(deg[i]): int(wave[i]) for i in range(ng.value)}   # macros per wave, per degree
         order = np.empty(self.n_macro, dtype=np.int64)
         self._off = {}
         for key, code in mehdg.BATCH_KEYS.items():
@@ -118,17 +122,21 @@ class MixedBatch:
         if rc:
             raise mehdg.MehdgError(rc, "mehdg_batch_assemble_condense")
 
-    def recover(self, R_q, dvhat, dv, dq, stream=None):
+    def recover(self, R_q, dvhat, dv, dq, v=None, vhat=None, v_old=None, stream=None):
+        """Back-substitution; v, vhat, v_old (the inputs of assemble_condense) are
+        needed when a group is streamed."""
         F = self._flat
-        rc = mehdg.load().mehdg_batch_recover(self._handle, F(R_q, "R_q", "R_q"), F(dvhat, "vhat", "dvhat"),
-                                              F(dv, "dv", "dv"), F(dq, "dq", "dq"), mehdg._stream(stream))
+        rc = mehdg.load().mehdg_batch_recover(
+            self._handle, F(v, "v", "v", optional=True), F(vhat, "vhat", "vhat", optional=True),
+            F(v_old, "v", "v_old", optional=True), F(R_q, "R_q", "R_q"), F(dvhat, "vhat", "dvhat"),
+            F(dv, "dv", "dv"), F(dq, "dq", "dq"), mehdg._stream(stream))
         if rc:
             raise mehdg.MehdgError(rc, "mehdg_batch_recover")
 
     def step(self, v, vhat, v_old, R_q, R_v, R_vhat, entropy, Ahat, bhat, dvhat, dv, dq, prec="fp64"):
         """assemble + condense + recover of every degree group (flat arrays)."""
         self.assemble_condense(v, vhat, v_old, R_q, R_v, R_vhat, entropy, Ahat, bhat, prec=prec)
-        self.recover(R_q, dvhat, dv, dq)
+        self.recover(R_q, dvhat, dv, dq, v=v, vhat=vhat, v_old=v_old)
 
     def status(self):
         """(first non-zero code or 0, status per macro in macro order)."""

@@ -36,24 +36,33 @@ struct Bdims {
 
 // ---------------------------------------------------------------------------
 // M^-1 R_Q per macro (A_qq^-1 R_Q without the identity factor):
-// M^-1 = (Minv (x) Minv (x) Minv) / (hx hy hz).
+// M^-1 = (Minv (x) Minv (x) Minv) / (hx hy hz).  The 15 fields are independent;
+// a workgroup takes MinvRqCfg<P>::FG of them (blockIdx.y the group), so the two
+// LDS copies of its fields stay within the LDS at every degree.
+template <int P>
+struct MinvRqCfg {
+    static constexpr int FG = P >= 4 ? 5 : 15;
+    static constexpr int GROUPS = 15 / FG;
+};
+
 template <int P>
 __global__ void __launch_bounds__(256) k_minv_rq(const double* __restrict__ R_q, const double* __restrict__ hs,
                                                  const Tab1D* __restrict__ tab, double* __restrict__ out) {
     using D = Dims<P>;
-    constexpr int n1d = D::n1d, n = D::n;
-    __shared__ double a[15 * n], b[15 * n];
+    constexpr int n1d = D::n1d, n = D::n, FG = MinvRqCfg<P>::FG;
+    __shared__ double a[FG * n], b[FG * n];
     __shared__ double Mi[n1d][n1d];
     const int64_t m = blockIdx.x;
+    const int64_t f0 = (int64_t)blockIdx.y * FG * n;     // first element of the field group
     for (int i = threadIdx.x; i < n1d * n1d; i += blockDim.x) Mi[i / n1d][i % n1d] = tab->Minv[i / n1d][i % n1d];
-    for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) a[i] = R_q[m * 15 * n + i];
+    for (int i = threadIdx.x; i < FG * n; i += blockDim.x) a[i] = R_q[m * 15 * n + f0 + i];
     __syncthreads();
     const double s = 1.0 / (hs[3 * m] * hs[3 * m + 1] * hs[3 * m + 2]);
     double* src = a;
     double* dst = b;
     for (int axis = 0; axis < 3; ++axis) {
         const int stride = axis == 0 ? 1 : (axis == 1 ? n1d : n1d * n1d);
-        for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) {
+        for (int i = threadIdx.x; i < FG * n; i += blockDim.x) {
             const int node = i % n, field = i / n;
             const int ci = (node / stride) % n1d;
             const int base = node - ci * stride;
@@ -67,7 +76,7 @@ __global__ void __launch_bounds__(256) k_minv_rq(const double* __restrict__ R_q,
         src = dst;
         dst = t;
     }
-    for (int i = threadIdx.x; i < 15 * n; i += blockDim.x) out[m * 15 * n + i] = s * src[i];
+    for (int i = threadIdx.x; i < FG * n; i += blockDim.x) out[m * 15 * n + f0 + i] = s * src[i];
 }
 
 // ---------------------------------------------------------------------------

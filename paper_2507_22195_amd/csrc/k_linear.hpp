@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
     const int64_t m = blockIdx.x;
     const int tid = threadIdx.x;
 
+    static_assert(!ResLds<P>::QG, "the linearised products keep q in LDS (degrees 1..3)");
     stage_common<P>(L, tab);
     for (int i = tid; i < 5 * n; i += blockDim.x) (&L.v[0][0])[i] = dv[m * 5 * n + i];
     for (int i = tid; i < 30 * nf; i += blockDim.x) (&L.vh[0][0][0])[i] = dvh[m * 30 * nf + i];
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
     if (dq) {
         for (int i = tid; i < 15 * n; i += blockDim.x) (&L.q[0][0])[i] = dq[m * 15 * n + i];
     } else {
-        lift_gradient<P>(L, hinv);
+        lift_gradient<P>(L, hinv, &L.q[0][0]);
     }
     __syncthreads();
     double* scr = ResScratch<P>::get(smem_raw, scratch, m);
@@ -205,6 +206,7 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
     const int tid = threadIdx.x;
     const bool full = g_q != nullptr;
 
+    static_assert(!ResLds<P>::QG, "the linearised products keep q in LDS (degrees 1..3)");
     stage_common<P>(L, tab);
     for (int i = tid; i < 5 * n; i += blockDim.x) (&L.v[0][0])[i] = wv[m * 5 * n + i];
     for (int i = tid; i < 30 * nf; i += blockDim.x) (&L.vh[0][0][0])[i] = wvh[m * 30 * nf + i];

@@ -90,13 +90,16 @@ __device__ void back_substitute(const double* __restrict__ Bm, const double* dvh
     }
 }
 
+// The 15 fields of dQ go through the LDS in groups of FG (all at once up to
+// p = 3; five at a time from p = 4 on, where all 15 would need 175 KB).
 template <int P>
 struct RecLds {
     using D = Dims<P>;
+    static constexpr int FG = P >= 4 ? 5 : 15;
     double z[D::NV];
     double dvh[D::NH];
     double U[64][65];
-    double a[15 * D::n], b[15 * D::n];
+    double a[FG * D::n], b[FG * D::n];
     Tab1D t;
 };
 
@@ -106,45 +109,48 @@ template <int P>
 __device__ void recover_dq(RecLds<P>& L, const double* __restrict__ R_q, const double* __restrict__ hs, int64_t m,
                            double* __restrict__ dv, double* __restrict__ dq) {
     using D = Dims<P>;
-    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV;
+    constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, FG = RecLds<P>::FG;
     const int tid = threadIdx.x;
     for (int i = tid; i < NV; i += blockDim.x) dv[m * NV + i] = L.z[i];
-    // M^-1 R_Q by three 1-D passes
-    for (int i = tid; i < 15 * n; i += blockDim.x) L.a[i] = R_q[m * 15 * n + i];
-    __syncthreads();
-    double* src = L.a;
-    double* dst = L.b;
-    for (int axis = 0; axis < 3; ++axis) {
-        const int stride = axis == 0 ? 1 : (axis == 1 ? n1d : n1d * n1d);
-        for (int i = tid; i < 15 * n; i += blockDim.x) {
-            const int node = i % n, fld = i / n;
-            const int ci = (node / stride) % n1d;
-            const int base = node - ci * stride;
-            double acc = 0.0;
-#pragma unroll
-            for (int c = 0; c < n1d; ++c) acc += L.t.Minv[ci][c] * src[fld * n + base + c * stride];
-            dst[i] = acc;
-        }
-        __syncthreads();
-        double* t = src;
-        src = dst;
-        dst = t;
-    }
     const double h[3] = {hs[3 * m], hs[3 * m + 1], hs[3 * m + 2]};
     const double vinv = 1.0 / (h[0] * h[1] * h[2]);
-    for (int i = tid; i < 15 * n; i += blockDim.x) {
-        const int c = i % n, lj = i / n, l = lj / 3, j = lj % 3;
-        const int ci[3] = {c % n1d, (c / n1d) % n1d, c / (n1d * n1d)};
-        const int stride = j == 0 ? 1 : (j == 1 ? n1d : n1d * n1d);
-        const int base = c - ci[j] * stride;
-        double acc = 0.0;
+    for (int g0 = 0; g0 < 15; g0 += FG) {
+        // M^-1 R_Q of fields [g0, g0 + FG) by three 1-D passes
+        for (int i = tid; i < FG * n; i += blockDim.x) L.a[i] = R_q[m * 15 * n + g0 * n + i];
+        __syncthreads();
+        double* src = L.a;
+        double* dst = L.b;
+        for (int axis = 0; axis < 3; ++axis) {
+            const int stride = axis == 0 ? 1 : (axis == 1 ? n1d : n1d * n1d);
+            for (int i = tid; i < FG * n; i += blockDim.x) {
+                const int node = i % n, fld = i / n;
+                const int ci = (node / stride) % n1d;
+                const int base = node - ci * stride;
+                double acc = 0.0;
 #pragma unroll
-        for (int b = 0; b < n1d; ++b) acc -= L.t.Lam[ci[j]][b] * L.z[l * n + base + b * stride];
-        const int t1 = (j == 0) ? 1 : 0, t2 = (j == 2) ? 1 : 2;
-        const int fc = ci[t1] + n1d * ci[t2];
-        acc -= L.t.Minv[ci[j]][0] * L.dvh[(2 * j * 5 + l) * nf + fc];
-        acc += L.t.Minv[ci[j]][n1d - 1] * L.dvh[((2 * j + 1) * 5 + l) * nf + fc];
-        dq[m * 15 * n + i] = acc / h[j] - vinv * src[i];
+                for (int c = 0; c < n1d; ++c) acc += L.t.Minv[ci][c] * src[fld * n + base + c * stride];
+                dst[i] = acc;
+            }
+            __syncthreads();
+            double* t = src;
+            src = dst;
+            dst = t;
+        }
+        for (int i = tid; i < FG * n; i += blockDim.x) {
+            const int c = i % n, lj = g0 + i / n, l = lj / 3, j = lj % 3;
+            const int ci[3] = {c % n1d, (c / n1d) % n1d, c / (n1d * n1d)};
+            const int stride = j == 0 ? 1 : (j == 1 ? n1d : n1d * n1d);
+            const int base = c - ci[j] * stride;
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < n1d; ++b) acc -= L.t.Lam[ci[j]][b] * L.z[l * n + base + b * stride];
+            const int t1 = (j == 0) ? 1 : 0, t2 = (j == 2) ? 1 : 2;
+            const int fc = ci[t1] + n1d * ci[t2];
+            acc -= L.t.Minv[ci[j]][0] * L.dvh[(2 * j * 5 + l) * nf + fc];
+            acc += L.t.Minv[ci[j]][n1d - 1] * L.dvh[((2 * j + 1) * 5 + l) * nf + fc];
+            dq[m * 15 * n + g0 * n + i] = acc / h[j] - vinv * src[i];
+        }
+        __syncthreads();   // the next group overwrites a and b
     }
 }
 

@@ -25,12 +25,16 @@ namespace mehdg {
 //  [35,50)  (w/h_j) v_k                 index 35 + 5 j + k
 constexpr int RES_FIELDS = 50;
 
+// From degree 4 on, q (15 n doubles) and v_old stay out of the LDS (q in the
+// per-macro global scratch, v_old read where it is interpolated), so that
+// the rest fits: 101 KB at p = 4 against 217 KB with them.
 template <int P>
 struct ResLds {
     using D = Dims<P>;
+    static constexpr bool QG = P >= 4;
     double v[5][D::n];
-    double vo[5][D::n];
-    double q[15][D::n];
+    double vo[QG ? 1 : 5][D::n];
+    double q[QG ? 1 : 15][D::n];
     double vh[6][5][D::nf];
     double fh[6][5][D::S];      // w_s (Fhat + Ghat)_k
     double qh[6][5][D::S];      // w_s sg vhat_k (R_Q trace term)
@@ -47,9 +51,17 @@ struct ResScratch {
     static constexpr size_t bytes = (size_t)RES_FIELDS * Dims<P>::G * sizeof(double);
     static constexpr bool in_lds = offset + bytes <= 150 * 1024;
     static constexpr size_t lds_bytes = in_lds ? offset + bytes : sizeof(ResLds<P>);
+    // doubles of the global scratch per macro: the fields when they are not
+    // in LDS, then q when it is not in LDS
+    static constexpr int64_t per_macro =
+        (in_lds ? 0 : (int64_t)RES_FIELDS * Dims<P>::G) + (ResLds<P>::QG ? 15 * (int64_t)Dims<P>::n : 0);
     __device__ static double* get(unsigned char* smem, double* scratch, int64_t m) {
         if constexpr (in_lds) return reinterpret_cast<double*>(smem + offset);
-        else return scratch + m * (int64_t)RES_FIELDS * Dims<P>::G;
+        else return scratch + m * per_macro;
+    }
+    __device__ static double* q(ResLds<P>& L, double* scratch, int64_t m) {
+        if constexpr (ResLds<P>::QG) return scratch + m * per_macro + (in_lds ? 0 : (int64_t)RES_FIELDS * Dims<P>::G);
+        else return &L.q[0][0];
     }
 };
 
@@ -170,7 +182,7 @@ __device__ __forceinline__ void face_coefficients(const double vh[5], const doub
 // Weak gradient at every node (R_Q = 0): q_kj = (1/h_j)[ -sum_c Lam[b_j,c] v_k(b_j -> c)
 //   - Minv[b_j,0] vhat_k(face -j) + Minv[b_j,n1d-1] vhat_k(face +j) ].
 template <int P>
-__device__ void lift_gradient(ResLds<P>& L, const double hinv[3]) {
+__device__ void lift_gradient(ResLds<P>& L, const double hinv[3], double* __restrict__ Q) {
     using D = Dims<P>;
     constexpr int n1d = D::n1d;
     for (int idx = threadIdx.x; idx < 15 * D::n; idx += blockDim.x) {
@@ -189,7 +201,7 @@ __device__ void lift_gradient(ResLds<P>& L, const double hinv[3]) {
         const int fc = bi[t1] + n1d * bi[t2];
         acc -= L.t.Minv[bj][0] * L.vh[2 * j][k][fc];
         acc += L.t.Minv[bj][n1d - 1] * L.vh[2 * j + 1][k][fc];
-        L.q[kj][b] = acc * hinv[j];
+        Q[kj * D::n + b] = acc * hinv[j];
     }
 }
 
@@ -322,19 +334,22 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
         double* dst = reinterpret_cast<double*>(&L.t);
         for (int i = tid; i < (int)(sizeof(Tab1D) / 8); i += blockDim.x) dst[i] = src[i];
     }
+    constexpr bool QG = ResLds<P>::QG;
     for (int i = tid; i < 5 * n; i += blockDim.x) {
         (&L.v[0][0])[i] = v[m * 5 * n + i];
-        (&L.vo[0][0])[i] = v_old[m * 5 * n + i];
+        if constexpr (!QG) (&L.vo[0][0])[i] = v_old[m * 5 * n + i];
     }
     for (int i = tid; i < 30 * nf; i += blockDim.x) (&L.vh[0][0][0])[i] = vhat[m * 30 * nf + i];
+    double* __restrict__ Q = ResScratch<P>::q(L, scratch, m);
+    const double* __restrict__ vold_m = v_old + m * 5 * n;
     const double h[3] = {hs[3 * m], hs[3 * m + 1], hs[3 * m + 2]};
     const double hinv[3] = {1.0 / h[0], 1.0 / h[1], 1.0 / h[2]};
     const double vol = h[0] * h[1] * h[2];
     __syncthreads();
     if (q) {
-        for (int i = tid; i < 15 * n; i += blockDim.x) (&L.q[0][0])[i] = q[m * 15 * n + i];
+        for (int i = tid; i < 15 * n; i += blockDim.x) Q[i] = q[m * 15 * n + i];
     } else {
-        lift_gradient<P>(L, hinv);
+        lift_gradient<P>(L, hinv, Q);
     }
     __syncthreads();
 
@@ -361,9 +376,10 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
 #pragma unroll
                     for (int k = 0; k < 5; ++k) {
                         vv[k] += phi * L.v[k][a];
-                        vo[k] += phi * L.vo[k][a];
+                        if constexpr (QG) vo[k] += phi * vold_m[k * n + a];
+                        else vo[k] += phi * L.vo[k][a];
 #pragma unroll
-                        for (int j = 0; j < 3; ++j) qq[k][j] += phi * L.q[3 * k + j][a];
+                        for (int j = 0; j < 3; ++j) qq[k][j] += phi * Q[(3 * k + j) * n + a];
                     }
                 }
             }
@@ -434,7 +450,7 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
                     vv[k] += psi * L.v[k][a];
                     vh[k] += psi * L.vh[f][k][fc];
 #pragma unroll
-                    for (int j = 0; j < 3; ++j) qq[k][j] += psi * L.q[3 * k + j][a];
+                    for (int j = 0; j < 3; ++j) qq[k][j] += psi * Q[(3 * k + j) * n + a];
                 }
             }
         }

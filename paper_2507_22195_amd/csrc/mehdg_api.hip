@@ -29,6 +29,11 @@ struct mehdg_ctx {
     int p = 0;
     int64_t n_macro = 0;
     int tile[MEHDG_NTILE_SITES] = {};   // product tile variant per call site
+    int64_t cap = 0;                    // macros the per-macro workspaces hold
+    double* base_h = nullptr;           // the context's own mesh, status and wall arrays
+    int32_t* base_status = nullptr;     // (d_h, d_status, d_bc point here unless a
+    uint8_t* base_bc = nullptr;         // batch has set a view of its own arrays)
+    double base_gT = 0.0;
     mehdg_params prm{};
     DevParams dp{};
     Tab1D tab{};
@@ -88,7 +93,7 @@ struct mehdg_ctx {
 
 namespace {
 
-constexpr int kMaxP = 3;
+constexpr int kMaxP = 4;
 
 // Brackets one launch with events when profiling is on.
 struct Timed {
@@ -110,9 +115,15 @@ struct Timed {
     }
 };
 
+// per-macro doubles of the residual's global scratch (at least the fields,
+// which the products of k_linear.hpp keep there for p >= 3)
 int64_t res_scratch_doubles(int p) {
     const int nq1 = 2 * (p + 1);
-    return (int64_t)RES_FIELDS * nq1 * nq1 * nq1;
+    const int64_t fields = (int64_t)RES_FIELDS * nq1 * nq1 * nq1;
+    switch (p) {
+        case 4: return std::max<int64_t>(fields, ResScratch<4>::per_macro);
+        default: return fields;
+    }
 }
 
 template <int P>
@@ -143,8 +154,8 @@ mehdg_err ensure_coef_workspace(mehdg_ctx* c) {
     if (c->d_coefF) return MEHDG_OK;
     using D = Dims<P>;
     mehdg_err e;
-    if (!c->d_coefV && (e = dev_alloc(c, &c->d_coefV, c->n_macro * (int64_t)D::G * COEF_V)) != MEHDG_OK) return e;
-    return dev_alloc(c, &c->d_coefF, c->n_macro * (int64_t)6 * D::S * COEF_F);
+    if (!c->d_coefV && (e = dev_alloc(c, &c->d_coefV, c->cap * (int64_t)D::G * COEF_V)) != MEHDG_OK) return e;
+    return dev_alloc(c, &c->d_coefF, c->cap * (int64_t)6 * D::S * COEF_F);
 }
 
 template <int P>
@@ -153,12 +164,22 @@ mehdg_err ensure_block_workspace(mehdg_ctx* c) {
     if (e != MEHDG_OK) return e;
     if (c->d_B) return MEHDG_OK;
     using D = Dims<P>;
-    if ((e = dev_alloc(c, &c->d_minvrq, c->n_macro * (int64_t)15 * D::n)) != MEHDG_OK) return e;
-    if ((e = dev_alloc(c, &c->d_ipiv, c->n_macro * (int64_t)D::NV)) != MEHDG_OK) return e;
-    if ((e = dev_alloc(c, &c->d_tri, c->n_macro * Panel<P>::TRI)) != MEHDG_OK) return e;
-    if ((e = dev_alloc(c, &c->d_perm, c->n_macro * Panel<P>::PERM)) != MEHDG_OK) return e;
-    if ((e = dev_alloc(c, &c->d_B, c->n_macro * Bdims<P>::per_macro)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_minvrq, c->cap * (int64_t)15 * D::n)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_ipiv, c->cap * (int64_t)D::NV)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_tri, c->cap * Panel<P>::TRI)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_perm, c->cap * Panel<P>::PERM)) != MEHDG_OK) return e;
+    if ((e = dev_alloc(c, &c->d_B, c->cap * Bdims<P>::per_macro)) != MEHDG_OK) return e;
     return MEHDG_OK;
+}
+
+// Device bytes per macro of a context after assemble(want_blocks = 1) and an
+// FP64 condense: the workspaces above plus the residual scratch.
+template <int P>
+int64_t ctx_macro_bytes() {
+    using D = Dims<P>;
+    const int64_t doubles = (int64_t)D::G * COEF_V + (int64_t)6 * D::S * COEF_F + (int64_t)15 * D::n +
+                            Panel<P>::TRI + Bdims<P>::per_macro + res_scratch_doubles(P) + 3;
+    return doubles * 8 + (int64_t)D::NV * 4 + Panel<P>::PERM * 4 + 4 + 6;
 }
 
 template <int P>
@@ -189,7 +210,7 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     if (mode == 2) return MEHDG_OK;
     {
         Timed t(c, MEHDG_PROF_MINV_RQ, st);
-        hipLaunchKernelGGL(k_minv_rq<P>, dim3(M), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
+        hipLaunchKernelGGL(k_minv_rq<P>, dim3(M, MinvRqCfg<P>::GROUPS), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
     }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     const size_t rl = sizeof(RowLds<P>), rlh = sizeof(RowLdsH<P>);
@@ -687,6 +708,7 @@ int64_t bordered_rows(int p) {
         case 1: return Bdims<1>::rows;
         case 2: return Bdims<2>::rows;
         case 3: return Bdims<3>::rows;
+        case 4: return Bdims<4>::rows;
         default: return 0;
     }
 }
@@ -695,6 +717,7 @@ int64_t bordered_ld(int p) {
         case 1: return Bdims<1>::ld;
         case 2: return Bdims<2>::ld;
         case 3: return Bdims<3>::ld;
+        case 4: return Bdims<4>::ld;
         default: return 0;
     }
 }
@@ -1213,7 +1236,7 @@ mehdg_err poison_flagged(const int32_t* status, int64_t n_macro, double* a, int6
 extern "C" {
 
 mehdg_err mehdg_sizes(int32_t p, int64_t out[5]) {
-    if (!out || p < 1 || p > 3) return MEHDG_EINVAL;
+    if (!out || p < 1 || p > kMaxP) return MEHDG_EINVAL;
     const int64_t n1d = 2 * p + 1;
     out[0] = n1d * n1d * n1d;
     out[1] = n1d * n1d;
@@ -1234,10 +1257,10 @@ static void drop_marks(mehdg_ctx* c) {
 mehdg_err mehdg_destroy(mehdg_ctx* c) {
     if (!c) return MEHDG_EINVAL;
     drop_marks(c);
-    (void)hipFree(c->d_h);
+    (void)hipFree(c->base_h);
     (void)hipFree(c->d_tab);
-    (void)hipFree(c->d_status);
-    (void)hipFree(c->d_bc);
+    (void)hipFree(c->base_status);
+    (void)hipFree(c->base_bc);
     (void)hipFree(c->d_scratch);
     (void)hipFree(c->d_coefV);
     (void)hipFree(c->d_coefF);
@@ -1311,18 +1334,23 @@ mehdg_err mehdg_create(const mehdg_mesh* mesh, const mehdg_params* prm, mehdg_ct
         return MEHDG_EINVAL;
     }
     mehdg_err e;
-    if ((e = dev_alloc(c, &c->d_h, 3 * c->n_macro)) != MEHDG_OK ||
+    if ((e = dev_alloc(c, &c->base_h, 3 * c->n_macro)) != MEHDG_OK ||
         (e = dev_alloc(c, &c->d_tab, 1)) != MEHDG_OK ||
-        (e = dev_alloc(c, &c->d_status, c->n_macro)) != MEHDG_OK ||
+        (e = dev_alloc(c, &c->base_status, c->n_macro)) != MEHDG_OK ||
         (e = dev_alloc(c, &c->d_scratch, c->n_macro * res_scratch_doubles(c->p))) != MEHDG_OK) {
         mehdg_destroy(c);
         return e;
     }
-    if (walls && ((e = dev_alloc(c, &c->d_bc, 6 * c->n_macro)) != MEHDG_OK ||
-                  hipMemcpy(c->d_bc, mesh->face_bc, 6 * c->n_macro, hipMemcpyHostToDevice) != hipSuccess)) {
+    c->d_h = c->base_h;
+    c->d_status = c->base_status;
+    if (walls && ((e = dev_alloc(c, &c->base_bc, 6 * c->n_macro)) != MEHDG_OK ||
+                  hipMemcpy(c->base_bc, mesh->face_bc, 6 * c->n_macro, hipMemcpyHostToDevice) != hipSuccess)) {
         mehdg_destroy(c);
         return e != MEHDG_OK ? e : MEHDG_EHIP;
     }
+    c->d_bc = c->base_bc;
+    c->cap = c->n_macro;
+    c->base_gT = c->dp.gT;
     if (hipMemcpy(c->d_h, mesh->h, 3 * c->n_macro * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->d_tab, &c->tab, sizeof(Tab1D), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_status, 0, c->n_macro * sizeof(int32_t)) != hipSuccess ||
@@ -1346,6 +1374,9 @@ mehdg_err mehdg_assemble(mehdg_ctx* c, const double* v, const double* vhat, cons
         case 1: e = launch_assemble<1>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, mode, st); break;
         case 2: e = launch_assemble<2>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, mode, st); break;
         case 3: e = launch_assemble<3>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, mode, st); break;
+        case 4:
+            if (mode != 2) e = launch_assemble<4>(c, v, vhat, q, v_old, R_q, R_v, R_vhat, entropy, mode, st);
+            break;
         default: break;
     }
     if (e == MEHDG_OK) {
@@ -1400,7 +1431,7 @@ mehdg_err mehdg_vjp(mehdg_ctx* c, const double* w_q, const double* w_v, const do
 
 mehdg_err mehdg_condense(mehdg_ctx* c, int32_t prec, double* Ahat, double* bhat, mehdg_stream stream) {
     if (!c || !bhat || prec < MEHDG_FP64 || prec > MEHDG_BF16_IR) return MEHDG_EINVAL;
-    if (prec != MEHDG_FP64 && (!(c->prm.ir_tol > 0.0) || c->prm.ir_maxit < 1)) return MEHDG_EINVAL;
+    if (prec != MEHDG_FP64 && (!(c->prm.ir_tol > 0.0) || c->prm.ir_maxit < 1 || c->p > 3)) return MEHDG_EINVAL;
     if (c->stage != 1) return MEHDG_ESTATE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     mehdg_err e = MEHDG_EINVAL;
@@ -1410,6 +1441,7 @@ mehdg_err mehdg_condense(mehdg_ctx* c, int32_t prec, double* Ahat, double* bhat,
             case 1: e = launch_condense<1>(c, Ahat, bhat, st); break;
             case 2: e = launch_condense<2>(c, Ahat, bhat, st); break;
             case 3: e = launch_condense<3>(c, Ahat, bhat, st); break;
+            case 4: e = launch_condense<4>(c, Ahat, bhat, st); break;
             default: break;
         }
     } else {
@@ -1470,6 +1502,7 @@ mehdg_err mehdg_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, do
             case 1: e = launch_recover<1>(c, R_q, dvhat, dv, dq, st); break;
             case 2: e = launch_recover<2>(c, R_q, dvhat, dv, dq, st); break;
             case 3: e = launch_recover<3>(c, R_q, dvhat, dv, dq, st); break;
+            case 4: e = launch_recover<4>(c, R_q, dvhat, dv, dq, st); break;
             default: break;
         }
     }
@@ -1521,6 +1554,40 @@ mehdg_err mehdg_status(mehdg_ctx* c, int32_t* status, mehdg_stream stream) {
 }
 
 int64_t mehdg_workspace_bytes(const mehdg_ctx* c) { return c ? c->bytes : 0; }
+
+// Views for the batch calls (batch_view.hpp): the context works on the first n
+// of its cap macros with mesh sizes, wall flags and status codes read from
+// the caller's device arrays.
+mehdg_err mehdg_batch_ctx_view(mehdg_ctx* c, int64_t n, const double* d_h, const uint8_t* d_bc, int32_t* d_status) {
+    if (!c || n < 1 || n > c->cap || !d_h || !d_status) return MEHDG_EINVAL;
+    if (d_bc && !(c->prm.T_wall > 0.0)) return MEHDG_EINVAL;
+    c->n_macro = n;
+    c->d_h = const_cast<double*>(d_h);
+    c->d_bc = const_cast<uint8_t*>(d_bc);
+    c->d_status = d_status;
+    c->dp.gT = d_bc ? c->prm.gamma / c->prm.T_wall : 0.0;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_batch_ctx_unview(mehdg_ctx* c) {
+    if (!c) return MEHDG_EINVAL;
+    c->n_macro = c->cap;
+    c->d_h = c->base_h;
+    c->d_bc = c->base_bc;
+    c->d_status = c->base_status;
+    c->dp.gT = c->base_gT;
+    return MEHDG_OK;
+}
+
+int64_t mehdg_batch_ctx_bytes(int p) {
+    switch (p) {
+        case 1: return ctx_macro_bytes<1>();
+        case 2: return ctx_macro_bytes<2>();
+        case 3: return ctx_macro_bytes<3>();
+        case 4: return ctx_macro_bytes<4>();
+        default: return 0;
+    }
+}
 
 mehdg_err mehdg_tile_variants(int32_t* count, int32_t* shapes) {
     if (!count) return MEHDG_EINVAL;

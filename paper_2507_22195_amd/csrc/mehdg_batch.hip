@@ -9,6 +9,17 @@
 // (default priority), forked from the caller's stream with an event and
 // joined back with one event per degree, so the small groups overlap the
 // large ones and the whole FP64 step can be captured in one HIP graph.
+//
+// Device memory.  A context holds its bordered matrices and coefficients for
+// every macro it owns (about 300 MB per macro at p = 4).  When the groups
+// together would exceed the batch's workspace budget, the groups with the
+// largest macros are streamed: their context holds one wave of macros and
+// is pointed at successive slices of the group (mesh sizes, wall flags and
+// status codes in device arrays of the batch), assembling and condensing one
+// wave after the other on the group's stream.  Their factors cannot all be
+// kept, so recovering such a group assembles and factors each wave again
+// from the same inputs (the same kernels on the same data: the same bits)
+// before the back-substitution.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,21 +27,31 @@
 #include <vector>
 
 #include "../../include/mehdg.h"
+#include "batch_view.hpp"
 
 struct mehdg_batch {
     struct Group {
         int32_t p = 0;
-        int64_t first = 0, count = 0;   // slice of the batch order
+        int64_t first = 0, count = 0;    // slice of the batch order
+        int64_t wave = 0;                // macros the context holds (count unless streamed)
         mehdg_ctx* ctx = nullptr;
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr;
         int64_t sz[5] = {};              // mehdg_sizes(p)
+        // streamed groups only: mesh, wall flags and status of the whole group,
+        // and one wave of assemble outputs for the recovery
+        double* d_h = nullptr;
+        uint8_t* d_bc = nullptr;
+        int32_t* d_status = nullptr;
+        double* d_work = nullptr;
+        bool streamed() const { return wave < count; }
     };
     int64_t n_macro = 0;
     std::vector<int64_t> order;          // batch position -> macro
     std::vector<Group> groups;
     hipEvent_t fork = nullptr;
     std::vector<int32_t> h_status;
+    int32_t prec = MEHDG_FP64;           // of the last condensation
 };
 
 namespace {
@@ -55,9 +76,16 @@ int64_t group_offset(const mehdg_batch* b, int32_t key, size_t gi) {
     return off;
 }
 
+// group gi's slice of a flat array, from its macro w0 on
 template <typename T>
-T* slice(T* base, const mehdg_batch* b, int32_t key, size_t gi) {
-    return base ? base + group_offset(b, key, gi) : nullptr;
+T* slice(T* base, const mehdg_batch* b, int32_t key, size_t gi, int64_t w0 = 0) {
+    return base ? base + group_offset(b, key, gi) + w0 * per_macro(key, b->groups[gi].sz) : nullptr;
+}
+
+// doubles of one wave of assemble outputs (R_q, R_v, R_vhat, entropy, bhat)
+int64_t work_per_macro(const int64_t sz[5]) {
+    return per_macro(MEHDG_KEY_Q, sz) + per_macro(MEHDG_KEY_V, sz) + per_macro(MEHDG_KEY_VHAT, sz) + 1 +
+           per_macro(MEHDG_KEY_BHAT, sz);
 }
 
 // fork the group streams from st, run f(group index) on each, join back
@@ -76,6 +104,47 @@ mehdg_err fork_join(mehdg_batch* b, hipStream_t st, F&& f) {
     return first;
 }
 
+// run f(w0, n) over the waves of group g, the context viewing each in turn
+template <typename F>
+mehdg_err over_waves(mehdg_batch::Group& g, F&& f) {
+    if (!g.streamed()) return f(0, g.count);
+    for (int64_t w0 = 0; w0 < g.count; w0 += g.wave) {
+        const int64_t n = std::min(g.wave, g.count - w0);
+        mehdg_err e = mehdg_batch_ctx_view(g.ctx, n, g.d_h + 3 * w0, g.d_bc ? g.d_bc + 6 * w0 : nullptr,
+                                           g.d_status + w0);
+        if (e == MEHDG_OK) e = f(w0, n);
+        if (e != MEHDG_OK) {
+            (void)mehdg_batch_ctx_unview(g.ctx);
+            return e;
+        }
+    }
+    return MEHDG_OK;
+}
+
+// Wave sizes: whole groups while the budget allows, else the groups with the
+// largest macros shrink first, each to what the budget leaves it.
+void size_waves(std::vector<mehdg_batch::Group>& groups, int64_t budget) {
+    std::vector<int64_t> bytes(groups.size());
+    int64_t total = 0;
+    for (size_t i = 0; i < groups.size(); ++i) {
+        bytes[i] = mehdg_batch_ctx_bytes(groups[i].p);
+        groups[i].wave = groups[i].count;
+        total += groups[i].count * bytes[i];
+    }
+    std::vector<size_t> idx(groups.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t c) { return bytes[a] > bytes[c]; });
+    for (size_t i : idx) {
+        if (total <= budget) break;
+        auto& g = groups[i];
+        const int64_t rest = total - g.count * bytes[i];
+        int64_t w = (budget - rest) / bytes[i];
+        w = std::max<int64_t>(1, std::min(w, g.count));
+        total = rest + w * bytes[i];
+        g.wave = w;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -86,6 +155,10 @@ mehdg_err mehdg_batch_destroy(mehdg_batch* b) {
         if (g.ctx) mehdg_destroy(g.ctx);
         if (g.done) (void)hipEventDestroy(g.done);
         if (g.stream) (void)hipStreamDestroy(g.stream);
+        (void)hipFree(g.d_h);
+        (void)hipFree(g.d_bc);
+        (void)hipFree(g.d_status);
+        (void)hipFree(g.d_work);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
@@ -95,7 +168,8 @@ mehdg_err mehdg_batch_destroy(mehdg_batch* b) {
 mehdg_err mehdg_batch_create(const mehdg_batch_mesh* mesh, const mehdg_params* prm, mehdg_batch** out) {
     if (!out) return MEHDG_EINVAL;
     *out = nullptr;
-    if (!mesh || !prm || !mesh->p || !mesh->h || mesh->n_macro <= 0) return MEHDG_EINVAL;
+    if (!mesh || !prm || !mesh->p || !mesh->h || mesh->n_macro <= 0 || mesh->max_workspace_bytes < 0)
+        return MEHDG_EINVAL;
     const int64_t M = mesh->n_macro;
     for (int64_t i = 0; i < M; ++i) {
         int64_t sz[5];
@@ -109,42 +183,74 @@ mehdg_err mehdg_batch_create(const mehdg_batch_mesh* mesh, const mehdg_params* p
     std::stable_sort(b->order.begin(), b->order.end(),
                      [&](int64_t a, int64_t c) { return mesh->p[a] < mesh->p[c]; });
     b->h_status.assign((size_t)M, 0);
+    for (int64_t first = 0; first < M;) {
+        mehdg_batch::Group g;
+        g.p = mesh->p[b->order[(size_t)first]];
+        g.first = first;
+        while (first + g.count < M && mesh->p[b->order[(size_t)(first + g.count)]] == g.p) ++g.count;
+        (void)mehdg_sizes(g.p, g.sz);
+        b->groups.push_back(g);
+        first += g.count;
+    }
+    int64_t budget = mesh->max_workspace_bytes;
+    if (budget == 0) {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            mehdg_batch_destroy(b);
+            return MEHDG_EHIP;
+        }
+        budget = (int64_t)(0.6 * (double)free_b);
+    }
+    size_waves(b->groups, budget);
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
         mehdg_batch_destroy(b);
         return MEHDG_EHIP;
     }
-    for (int64_t first = 0; first < M;) {
-        const int32_t p = mesh->p[b->order[(size_t)first]];
-        int64_t cnt = 0;
-        while (first + cnt < M && mesh->p[b->order[(size_t)(first + cnt)]] == p) ++cnt;
-        std::vector<double> h((size_t)(3 * cnt));
-        std::vector<uint8_t> bc(mesh->face_bc ? (size_t)(6 * cnt) : 0);
-        for (int64_t i = 0; i < cnt; ++i) {
-            const int64_t m = b->order[(size_t)(first + i)];
+    for (auto& g : b->groups) {
+        // the context's own mesh: the group's first wave (a streamed group
+        // points it at each wave in turn)
+        std::vector<double> h((size_t)(3 * g.count));
+        std::vector<uint8_t> bc(mesh->face_bc ? (size_t)(6 * g.count) : 0);
+        bool walls = false;
+        for (int64_t i = 0; i < g.count; ++i) {
+            const int64_t m = b->order[(size_t)(g.first + i)];
             for (int k = 0; k < 3; ++k) h[(size_t)(3 * i + k)] = mesh->h[3 * m + k];
             if (mesh->face_bc)
-                for (int k = 0; k < 6; ++k) bc[(size_t)(6 * i + k)] = mesh->face_bc[6 * m + k];
+                for (int k = 0; k < 6; ++k) {
+                    bc[(size_t)(6 * i + k)] = mesh->face_bc[6 * m + k];
+                    walls = walls || mesh->face_bc[6 * m + k] != 0;
+                }
         }
+        mehdg_err e = MEHDG_OK;
+        for (size_t i = 0; i < bc.size(); ++i)
+            if (bc[i] > 1) e = MEHDG_EINVAL;
+        if (walls && !(prm->T_wall > 0.0)) e = MEHDG_EINVAL;
         mehdg_mesh sub{};
-        sub.n_macro = cnt;
-        sub.p = p;
+        sub.n_macro = g.wave;
+        sub.p = g.p;
         sub.h = h.data();
-        sub.face_bc = mesh->face_bc ? bc.data() : nullptr;
-        mehdg_batch::Group g;
-        g.p = p;
-        g.first = first;
-        g.count = cnt;
-        (void)mehdg_sizes(p, g.sz);
-        mehdg_err e = mehdg_create(&sub, prm, &g.ctx);
+        sub.face_bc = walls ? bc.data() : nullptr;
+        if (e == MEHDG_OK) e = mehdg_create(&sub, prm, &g.ctx);
         if (e == MEHDG_OK && (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
                               hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess))
             e = MEHDG_EHIP;
-        b->groups.push_back(g);
+        if (e == MEHDG_OK && g.streamed()) {
+            const int64_t wk = g.wave * work_per_macro(g.sz);
+            if (hipMalloc(&g.d_h, sizeof(double) * 3 * g.count) != hipSuccess ||
+                hipMalloc(&g.d_status, sizeof(int32_t) * g.count) != hipSuccess ||
+                hipMalloc(&g.d_work, sizeof(double) * wk) != hipSuccess ||
+                (walls && hipMalloc(&g.d_bc, 6 * g.count) != hipSuccess))
+                e = MEHDG_ENOMEM;
+            else if (hipMemcpy(g.d_h, h.data(), sizeof(double) * 3 * g.count, hipMemcpyHostToDevice) != hipSuccess ||
+                     hipMemset(g.d_status, 0, sizeof(int32_t) * g.count) != hipSuccess ||
+                     (walls && hipMemcpy(g.d_bc, bc.data(), 6 * g.count, hipMemcpyHostToDevice) != hipSuccess))
+                e = MEHDG_EHIP;
+        }
         if (e != MEHDG_OK) {
+            (void)hipGetLastError();
             mehdg_batch_destroy(b);
             return e;
         }
-        first += cnt;
     }
     *out = b;
     return MEHDG_OK;
@@ -169,13 +275,14 @@ mehdg_err mehdg_batch_layout(const mehdg_batch* b, int32_t key, int64_t* order, 
 }
 
 mehdg_err mehdg_batch_groups(const mehdg_batch* b, int32_t* n_groups, int32_t* degree, int64_t* first,
-                             int64_t* count) {
+                             int64_t* count, int64_t* wave) {
     if (!b || !n_groups) return MEHDG_EINVAL;
     *n_groups = (int32_t)b->groups.size();
     for (size_t i = 0; i < b->groups.size(); ++i) {
         if (degree) degree[i] = b->groups[i].p;
         if (first) first[i] = b->groups[i].first;
         if (count) count[i] = b->groups[i].count;
+        if (wave) wave[i] = b->groups[i].wave;
     }
     return MEHDG_OK;
 }
@@ -186,47 +293,72 @@ mehdg_err mehdg_batch_assemble_condense(mehdg_batch* b, int32_t prec, const doub
     if (!b || !v || !vhat || !v_old || !R_q || !R_v || !R_vhat || !entropy || !bhat) return MEHDG_EINVAL;
     if (prec < MEHDG_FP64 || prec > MEHDG_BF16_IR) return MEHDG_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    b->prec = prec;
     return fork_join(b, st, [&](size_t gi) -> mehdg_err {
         auto& g = b->groups[gi];
         mehdg_stream gs = reinterpret_cast<mehdg_stream>(g.stream);
-        mehdg_err e = mehdg_assemble(g.ctx, slice(v, b, MEHDG_KEY_V, gi), slice(vhat, b, MEHDG_KEY_VHAT, gi),
-                                     nullptr, slice(v_old, b, MEHDG_KEY_V, gi), slice(R_q, b, MEHDG_KEY_Q, gi),
-                                     slice(R_v, b, MEHDG_KEY_V, gi), slice(R_vhat, b, MEHDG_KEY_VHAT, gi),
-                                     slice(entropy, b, MEHDG_KEY_ENTROPY, gi), 1, gs);
-        if (e != MEHDG_OK) return e;
-        return mehdg_condense(g.ctx, prec, slice(Ahat, b, MEHDG_KEY_AHAT, gi), slice(bhat, b, MEHDG_KEY_BHAT, gi),
-                              gs);
+        return over_waves(g, [&](int64_t w0, int64_t) -> mehdg_err {
+            mehdg_err e = mehdg_assemble(g.ctx, slice(v, b, MEHDG_KEY_V, gi, w0), slice(vhat, b, MEHDG_KEY_VHAT, gi, w0),
+                                         nullptr, slice(v_old, b, MEHDG_KEY_V, gi, w0),
+                                         slice(R_q, b, MEHDG_KEY_Q, gi, w0), slice(R_v, b, MEHDG_KEY_V, gi, w0),
+                                         slice(R_vhat, b, MEHDG_KEY_VHAT, gi, w0),
+                                         slice(entropy, b, MEHDG_KEY_ENTROPY, gi, w0), 1, gs);
+            if (e != MEHDG_OK) return e;
+            return mehdg_condense(g.ctx, prec, slice(Ahat, b, MEHDG_KEY_AHAT, gi, w0),
+                                  slice(bhat, b, MEHDG_KEY_BHAT, gi, w0), gs);
+        });
     });
 }
 
-mehdg_err mehdg_batch_recover(mehdg_batch* b, const double* R_q, const double* dvhat, double* dv, double* dq,
-                              mehdg_stream stream) {
+mehdg_err mehdg_batch_recover(mehdg_batch* b, const double* v, const double* vhat, const double* v_old,
+                              const double* R_q, const double* dvhat, double* dv, double* dq, mehdg_stream stream) {
     if (!b || !R_q || !dvhat || !dv || !dq) return MEHDG_EINVAL;
+    for (const auto& g : b->groups)
+        if (g.streamed() && (!v || !vhat || !v_old)) return MEHDG_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     return fork_join(b, st, [&](size_t gi) -> mehdg_err {
         auto& g = b->groups[gi];
-        return mehdg_recover(g.ctx, slice(R_q, b, MEHDG_KEY_Q, gi), slice(dvhat, b, MEHDG_KEY_VHAT, gi),
-                             slice(dv, b, MEHDG_KEY_V, gi), slice(dq, b, MEHDG_KEY_Q, gi),
-                             reinterpret_cast<mehdg_stream>(g.stream));
+        mehdg_stream gs = reinterpret_cast<mehdg_stream>(g.stream);
+        if (!g.streamed())
+            return mehdg_recover(g.ctx, slice(R_q, b, MEHDG_KEY_Q, gi), slice(dvhat, b, MEHDG_KEY_VHAT, gi),
+                                 slice(dv, b, MEHDG_KEY_V, gi), slice(dq, b, MEHDG_KEY_Q, gi), gs);
+        // one wave of assemble outputs in the batch's work array
+        double* wq = g.d_work;
+        double* wv = wq + g.wave * per_macro(MEHDG_KEY_Q, g.sz);
+        double* wvh = wv + g.wave * per_macro(MEHDG_KEY_V, g.sz);
+        double* went = wvh + g.wave * per_macro(MEHDG_KEY_VHAT, g.sz);
+        double* wb = went + g.wave;
+        return over_waves(g, [&](int64_t w0, int64_t) -> mehdg_err {
+            mehdg_err e = mehdg_assemble(g.ctx, slice(v, b, MEHDG_KEY_V, gi, w0), slice(vhat, b, MEHDG_KEY_VHAT, gi, w0),
+                                         nullptr, slice(v_old, b, MEHDG_KEY_V, gi, w0), wq, wv, wvh, went, 1, gs);
+            if (e == MEHDG_OK) e = mehdg_condense(g.ctx, b->prec, nullptr, wb, gs);
+            if (e == MEHDG_OK)
+                e = mehdg_recover(g.ctx, wq, slice(dvhat, b, MEHDG_KEY_VHAT, gi, w0), slice(dv, b, MEHDG_KEY_V, gi, w0),
+                                  slice(dq, b, MEHDG_KEY_Q, gi, w0), gs);
+            return e;
+        });
     });
 }
 
 mehdg_err mehdg_batch_status(mehdg_batch* b, int32_t* status, mehdg_stream stream) {
     if (!b || !status) return MEHDG_EINVAL;
     (void)stream;
-    mehdg_err first = MEHDG_OK;
     for (const auto& g : b->groups) {
-        const mehdg_err e = mehdg_status(g.ctx, b->h_status.data() + g.first,
-                                         reinterpret_cast<mehdg_stream>(g.stream));
-        if (e == MEHDG_EINVAL || e == MEHDG_EHIP) return e;
-        for (int64_t i = 0; i < g.count; ++i) status[b->order[(size_t)(g.first + i)]] = b->h_status[(size_t)(g.first + i)];
+        int32_t* hs = b->h_status.data() + g.first;
+        if (g.streamed()) {
+            if (hipStreamSynchronize(g.stream) != hipSuccess ||
+                hipMemcpy(hs, g.d_status, sizeof(int32_t) * g.count, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemset(g.d_status, 0, sizeof(int32_t) * g.count) != hipSuccess)
+                return MEHDG_EHIP;
+        } else {
+            const mehdg_err e = mehdg_status(g.ctx, hs, reinterpret_cast<mehdg_stream>(g.stream));
+            if (e == MEHDG_EINVAL || e == MEHDG_EHIP) return e;
+        }
+        for (int64_t i = 0; i < g.count; ++i) status[b->order[(size_t)(g.first + i)]] = hs[i];
     }
     for (int64_t m = 0; m < b->n_macro; ++m)
-        if (status[m] != 0) {
-            first = static_cast<mehdg_err>(status[m]);
-            break;
-        }
-    return first;
+        if (status[m] != 0) return static_cast<mehdg_err>(status[m]);
+    return MEHDG_OK;
 }
 
 }  // extern "C"

@@ -17,10 +17,11 @@
 #pragma once
 
 namespace mehdg {
-constexpr int kTileTable[4][2] = {
+constexpr int kTileTable[5][2] = {
     {0, 0},   // (unused)
     {4, 4},   // p = 1
     {0, 0},   // p = 2
     {0, 0},   // p = 3
+    {0, 0},   // p = 4 (not swept yet)
 };
 }  // namespace mehdg

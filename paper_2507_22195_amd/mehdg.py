@@ -52,7 +52,8 @@ class Mesh(ctypes.Structure):
 
 class BatchMesh(ctypes.Structure):
     _fields_ = [("n_macro", ctypes.c_int64), ("p", ctypes.POINTER(ctypes.c_int32)),
-                ("h", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8))]
+                ("h", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8)),
+                ("max_workspace_bytes", ctypes.c_int64)]
 
 
 BATCH_KEYS = {"v": 0, "q": 1, "vhat": 2, "entropy": 3, "Ahat": 4, "bhat": 5}
@@ -118,9 +119,10 @@ def load(path: str = LIB_PATH):
     lib.mehdg_batch_destroy.argtypes = [vp]
     lib.mehdg_batch_layout.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.mehdg_batch_groups.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64)]
     lib.mehdg_batch_assemble_condense.argtypes = [vp, i32] + [vp] * 9 + [vp]
-    lib.mehdg_batch_recover.argtypes = [vp] + [vp] * 4 + [vp]
+    lib.mehdg_batch_recover.argtypes = [vp] + [vp] * 7 + [vp]
     lib.mehdg_batch_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp]
     for name in ("mehdg_batch_create", "mehdg_batch_destroy", "mehdg_batch_layout", "mehdg_batch_groups",
                  "mehdg_batch_assemble_condense", "mehdg_batch_recover", "mehdg_batch_status"):

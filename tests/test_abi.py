@@ -38,8 +38,9 @@ def test_argument_errors_are_synchronous():
         pytest.skip("libmehdg.so not built")
     lib = mehdg.load()
     out = (ctypes.c_int64 * 5)()
-    assert lib.mehdg_sizes(0, out) == 1
+    assert lib.mehdg_sizes(0, out) == 1 and lib.mehdg_sizes(5, out) == 1
     assert lib.mehdg_sizes(2, out) == 0 and list(out) == [125, 25, 625, 1875, 750]
+    assert lib.mehdg_sizes(4, out) == 0 and list(out) == [729, 81, 3645, 10935, 2430]
     assert lib.mehdg_create(None, None, None) == 1
     h = (ctypes.c_double * 3)(0.1, 0.1, -0.1)     # negative size
     mesh = mehdg.Mesh(1, 2, 0, ctypes.cast(h, ctypes.POINTER(ctypes.c_double)))
@@ -60,19 +61,19 @@ def test_argument_errors_are_synchronous():
     assert lib.mehdg_condense_rhs(None, None, None, None, None) == 1
     # batches: bad degree or empty mesh before any device work, NULL handles
     handle = ctypes.c_void_p()
-    deg = (ctypes.c_int32 * 2)(2, 4)
+    deg = (ctypes.c_int32 * 2)(2, 5)
     hh = (ctypes.c_double * 6)(0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
-    bm = mehdg.BatchMesh(2, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None)
+    bm = mehdg.BatchMesh(2, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None, 0)
     assert lib.mehdg_batch_create(ctypes.byref(bm), ctypes.byref(prm), ctypes.byref(handle)) == 1
     assert handle.value is None
-    bm = mehdg.BatchMesh(0, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None)
+    bm = mehdg.BatchMesh(0, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None, 0)
     assert lib.mehdg_batch_create(ctypes.byref(bm), ctypes.byref(prm), ctypes.byref(handle)) == 1
     assert lib.mehdg_batch_create(None, None, None) == 1
     assert lib.mehdg_batch_destroy(None) == 1
     assert lib.mehdg_batch_layout(None, 0, None, None) == 1
-    assert lib.mehdg_batch_groups(None, None, None, None, None) == 1
+    assert lib.mehdg_batch_groups(None, None, None, None, None, None) == 1
     assert lib.mehdg_batch_assemble_condense(None, 0, *([None] * 9), None) == 1
-    assert lib.mehdg_batch_recover(None, *([None] * 4), None) == 1
+    assert lib.mehdg_batch_recover(None, *([None] * 7), None) == 1
     assert lib.mehdg_batch_status(None, None, None) == 1
     # tile variants: a list of shapes; NULL contexts and bad sites are EINVAL
     n = ctypes.c_int32()

@@ -26,11 +26,12 @@ def test_pick_takes_the_fastest_bit_identical_variant():
 def test_rendered_header_holds_the_table():
     txt = autotune.render(_fake())
     rows = re.findall(r"\{(\d+), (\d+)\},\s+// p = (\d)", txt)
-    assert [(int(a), int(b), int(p)) for a, b, p in rows] == [(2, 0, 1), (1, 1, 2), (0, 2, 3)]
-    assert "kTileTable[4][2]" in txt and "#pragma once" in txt
+    assert [(int(a), int(b), int(p)) for a, b, p in rows] == [(2, 0, 1), (1, 1, 2), (0, 2, 3), (0, 0, 4)]
+    assert "p = 4 (not swept)" in txt
+    assert "kTileTable[5][2]" in txt and "#pragma once" in txt
 
 
 def test_committed_table_is_well_formed():
     txt = open(autotune.TABLE).read()
     rows = re.findall(r"\{(\d+), (\d+)\},\s+// p = (\d)", txt)
-    assert [int(p) for _, _, p in rows] == [1, 2, 3]
+    assert [int(p) for _, _, p in rows] == [1, 2, 3, 4]

@@ -6,6 +6,7 @@ launch configuration the benchmark times (Sec. 6.2 eq. R2-R6).
   Re 1600, Mach 0.1.
 * The degree-3 workload: 16x16x8 macros of 2x2x2 p = 3 hexahedra (2048 macros,
   N_V = 1715, N_VH = 1470), KEPES flux, Re 5000, Mach 0.3.
+* Degree 4 on two macros (the largest degree of the mixed-degree batches).
 
 The whole batch runs assemble + condense + recover on the GPU; the oracle
 computes a seeded sample of macros one by one.  The sample covers every
@@ -151,3 +152,10 @@ def test_full_size_tgv16x16x8_p3_kepes():
     w = W.workload(5)
     assert w.n_macro == 2048 and w.p == 3
     _run(w, _sample(w.n_macro, 2025, lanes=(3, 5)), kepes=True)
+
+
+def test_degree4_macros_against_the_oracle():
+    """Degree 4 (N_V 3645, N_VH 2430): two viscous Taylor-Green macros, ES
+    flux, every block and output at the 1e-12 bar (the r_V floor as above)."""
+    w = W.tgv_workload(shape=(2, 1, 1), p=4, M0=0.1, Re=1600.0, flux="ES", seed_v=21, seed_vh=22)
+    _run(w, [0, 1], kepes=False)
