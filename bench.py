@@ -551,6 +551,7 @@ def main():
     ap.add_argument("--no-diff", action="store_true", help="skip the JVP / VJP measurement")
     ap.add_argument("--diff-only", action="store_true", help="only the JVP / VJP measurement (profiling)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-degree measurement")
+    ap.add_argument("--mixed-only", action="store_true", help="only the mixed-degree measurement (profiling)")
     ap.add_argument("--no-tet", action="store_true", help="skip the tetrahedral residual measurement")
     ap.add_argument("--tet-only", action="store_true", help="only the tetrahedral residual measurement")
     ap.add_argument("--config", type=int, default=2, choices=(2, 5),
@@ -571,6 +572,9 @@ def main():
     from paper_2507_22195_amd import mehdg
     from paper_2507_22195_amd import workloads as W
 
+    if args.mixed_only:
+        print(json.dumps({"mixed_degree": mixed_degree()}), flush=True)
+        return
     if args.diff_only:
         print(json.dumps({"differentiation": differentiation(reps=args.steps)}), flush=True)
         return
