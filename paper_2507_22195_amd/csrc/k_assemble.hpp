@@ -83,10 +83,13 @@ __global__ void __launch_bounds__(256) k_minv_rq(const double* __restrict__ R_q,
 // Row workgroups build the KG rows (k = 0..KG-1 of one test node) together:
 // KG = 1: smaller LDS footprint, several workgroups per CU (measured faster
 // than building all five rows per pass, whose accumulators fill the LDS).
+// From p = 3 on the accumulators hold a CU's LDS nearly alone, so the
+// workgroup grows instead (measured on the row kernel: 512 threads at p = 3,
+// 1024 at p = 4 against 256).
 template <int P>
 struct RowCfg {
     static constexpr int KG = 1;
-    static constexpr int THREADS = 256;
+    static constexpr int THREADS = P >= 4 ? 1024 : (P == 3 ? 512 : 256);
 };
 
 template <int P>
@@ -95,7 +98,8 @@ struct RowLds {
     static constexpr int KG = RowCfg<P>::KG;
     static constexpr int E3 = (P + 1) * (P + 1) * (P + 1);
     static constexpr int E2 = (P + 1) * (P + 1);
-    static constexpr int WV = E3 * 20 * KG;     // per sub-element Gauss point: [0,5) value trial, [5,20) q trial
+    static constexpr int WS = E3 | 1;            // field stride of the volume weights (odd: no bank conflicts)
+    static constexpr int WV = 20 * WS * KG;     // per trial field ([0,5) value, [5,20) q) and sub-element point
     static constexpr int WF = E2 * 25 * KG;     // per sub-face Gauss point: [0,5) v, [5,10) vhat, [10,25) q
     double av[KG][5][D::n];         // coefficient of trial v_{l,b}
     double aq[KG][15][D::n];        // coefficient of trial q_{l,j,c}  (index 3 l + j)
@@ -115,58 +119,80 @@ __device__ void row_zero(RowLds<P>& L) {
     for (int i = threadIdx.x; i < KG * 30 * D::nf; i += blockDim.x) h[i] = 0.0;
 }
 
-// Volume part of the rows (k0 .. k0+KG-1) of node a for the sub-element (e1,e2,e3).
+// Volume part of row k of node a for the sub-element (e1,e2,e3):
+//   A[(a,k), (b,fld)] += sum_g W_fld(g) phi_b(g),
+// W_fld(g) the test function's value and gradient at sub-element point g
+// contracted with the pointwise coefficients of trial field fld (value trial l,
+// or q trial (l, j)).  phi_b(g) = B(g1,b1) B(g2,b2) B(g3,b3) on the sub-element's
+// Q^3 points and nodes, so the sum goes by sum factorisation: along axis 1 in
+// place in the weight buffer (a thread per line), then axes 2 and 3 in
+// registers (a thread per (b1, b2)): 3 Q^4 products per field instead of Q^6.
 template <int P>
 __device__ void row_volume(RowLds<P>& L, const double* __restrict__ coefV, int64_t m, int a1, int a2, int a3,
-                           int e1, int e2, int e3, int k0, bool viscous) {
+                           int e1, int e2, int e3, int k, bool viscous) {
     using D = Dims<P>;
     using R = RowLds<P>;
-    constexpr int n1d = D::n1d, nq1 = D::nq1, G = D::G, KG = R::KG;
+    constexpr int n1d = D::n1d, nq1 = D::nq1, G = D::G, E3 = R::E3, WS = R::WS;
     constexpr int Q = P + 1;
-    for (int idx = threadIdx.x; idx < R::E3 * KG; idx += blockDim.x) {
-        const int gl = idx % R::E3, kk = idx / R::E3, k = k0 + kk;
+    static_assert(R::KG == 1, "one row per pass");
+    const int nfld = viscous ? 20 : 5;
+    // weights, one (point, field) pair per thread (fields of one point adjacent:
+    // their coefficients share the point's record)
+    for (int idx = threadIdx.x; idx < nfld * E3; idx += blockDim.x) {
+        const int fld = idx % nfld, gl = idx / nfld;
         const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
         const int g = g1 + nq1 * (g2 + nq1 * g3);
         const double B1 = L.t.B[g1][a1], B2 = L.t.B[g2][a2], B3 = L.t.B[g3][a3];
-        const double t0 = B1 * B2 * B3;
-        const double ti[3] = {L.t.D[g1][a1] * B2 * B3, B1 * L.t.D[g2][a2] * B3, B1 * B2 * L.t.D[g3][a3]};
+        const double t1 = L.t.D[g1][a1] * B2 * B3, t2 = B1 * L.t.D[g2][a2] * B3, t3 = B1 * B2 * L.t.D[g3][a3];
         const double* c = coefV + ((int64_t)m * G + g) * COEF_V;
-        double* w = L.w + (kk * R::E3 + gl) * 20;
-#pragma unroll
-        for (int l = 0; l < 5; ++l) {
-            double w0 = t0 * c[5 * k + l];
-#pragma unroll
-            for (int i = 0; i < 3; ++i) w0 += ti[i] * c[25 + 25 * i + 5 * k + l];
-            w[l] = w0;
+        double wv;
+        if (fld < 5) {
+            const int o = 5 * k + fld;
+            wv = B1 * B2 * B3 * c[o] + t1 * c[25 + o] + t2 * c[50 + o] + t3 * c[75 + o];
+        } else {
+            const int j = (fld - 5) % 3, o = 5 * k + (fld - 5) / 3;
+            wv = t1 * c[100 + 25 * j + o] + t2 * c[100 + 25 * (3 + j) + o] + t3 * c[100 + 25 * (6 + j) + o];
         }
-        if (viscous) {
+        L.w[fld * WS + gl] = wv;
+    }
+    __syncthreads();
+    // axis 1, in place: W[fld][g1, g2, g3] -> T[fld][b1, g2, g3]
+    for (int idx = threadIdx.x; idx < nfld * Q * Q; idx += blockDim.x) {
+        const int fld = idx / (Q * Q), r = idx % (Q * Q);
+        double* line = L.w + fld * WS + Q * r;
+        double x[Q];
 #pragma unroll
-            for (int l = 0; l < 5; ++l)
+        for (int i = 0; i < Q; ++i) x[i] = line[i];
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    double wq = 0.0;
+        for (int b = 0; b < Q; ++b) {
+            double s = 0.0;
 #pragma unroll
-                    for (int i = 0; i < 3; ++i) wq += ti[i] * c[100 + 25 * (3 * i + j) + 5 * k + l];
-                    w[5 + 3 * l + j] = wq;
-                }
+            for (int i = 0; i < Q; ++i) s += x[i] * L.t.B[e1 * Q + i][e1 * P + b];
+            line[b] = s;
         }
     }
     __syncthreads();
-    const int nf_ = viscous ? 20 : 5;
-    const int nent = KG * nf_ * R::E3;
-    for (int idx = threadIdx.x; idx < nent; idx += blockDim.x) {
-        const int bl = idx % R::E3, rest = idx / R::E3;
-        const int fld = rest % nf_, kk = rest / nf_;     // fld < 5: v trial l; else q trial (l,j)
-        const int b1 = e1 * P + bl % Q, b2 = e2 * P + (bl / Q) % Q, b3 = e3 * P + bl / (Q * Q);
-        const double* w = L.w + kk * R::E3 * 20 + fld;
-        double acc = 0.0;
-        for (int gl = 0; gl < R::E3; ++gl) {
-            const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
-            acc += w[gl * 20] * (L.t.B[g1][b1] * L.t.B[g2][b2] * L.t.B[g3][b3]);
+    // axes 2 and 3 for one (b1, b2) per thread, added into the row's accumulators
+    for (int idx = threadIdx.x; idx < nfld * Q * Q; idx += blockDim.x) {
+        const int fld = idx / (Q * Q), r = idx % (Q * Q), b1l = r % Q, b2l = r / Q;
+        const double* T = L.w + fld * WS;
+        double t[Q];
+#pragma unroll
+        for (int g3l = 0; g3l < Q; ++g3l) {
+            double s = 0.0;
+#pragma unroll
+            for (int g2l = 0; g2l < Q; ++g2l) s += T[b1l + Q * (g2l + Q * g3l)] * L.t.B[e2 * Q + g2l][e2 * P + b2l];
+            t[g3l] = s;
         }
-        const int b = b1 + n1d * (b2 + n1d * b3);
-        if (fld < 5) L.av[kk][fld][b] += acc;
-        else L.aq[kk][fld - 5][b] += acc;
+        const int b12 = (e1 * P + b1l) + n1d * (e2 * P + b2l);
+        double* acc = fld < 5 ? &L.av[0][fld][0] : &L.aq[0][fld - 5][0];
+#pragma unroll
+        for (int b3l = 0; b3l < Q; ++b3l) {
+            double s = 0.0;
+#pragma unroll
+            for (int g3l = 0; g3l < Q; ++g3l) s += t[g3l] * L.t.B[e3 * Q + g3l][e3 * P + b3l];
+            acc[b12 + n1d * n1d * (e3 * P + b3l)] += s;
+        }
     }
     __syncthreads();
 }
@@ -362,6 +388,12 @@ __global__ void __launch_bounds__(RowCfg<P>::THREADS, 4) k_rows_v(const double* 
 // face's tangential axes), a quarter of the LDS of a volume row, so more
 // workgroups share a CU.  The elimination of Q is the same as in row_write,
 // with the off-face entries read as zero.
+// (trace rows: 256 threads at every degree, measured fastest)
+template <int P>
+struct RowCfgH {
+    static constexpr int THREADS = 256;
+};
+
 template <int P>
 struct RowLdsH {
     using D = Dims<P>;
@@ -370,7 +402,7 @@ struct RowLdsH {
     double aq[15][D::nf];
     double ah[5][D::nf];
     double w[E2 * 25];
-    double red[RowCfg<P>::THREADS / 64];
+    double red[RowCfgH<P>::THREADS / 64];
     Tab1D t;
 };
 
@@ -413,7 +445,7 @@ __device__ void row_face_h(RowLdsH<P>& L, const double* __restrict__ coefF, int6
 }
 
 template <int P>
-__global__ void __launch_bounds__(RowCfg<P>::THREADS, 6) k_rows_h(const double* __restrict__ coefF,
+__global__ void __launch_bounds__(RowCfgH<P>::THREADS, 6) k_rows_h(const double* __restrict__ coefF,
                                                                const double* __restrict__ R_vh,
                                                                const double* __restrict__ minvrq,
                                                                const double* __restrict__ hs,

@@ -223,7 +223,7 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     {
         Timed t(c, MEHDG_PROF_ROWS_H, st);
-        hipLaunchKernelGGL(k_rows_h<P>, dim3(xcd_grid(6 * D::nf, c->n_macro)), dim3(RowCfg<P>::THREADS), rlh, st,
+        hipLaunchKernelGGL(k_rows_h<P>, dim3(xcd_grid(6 * D::nf, c->n_macro)), dim3(RowCfgH<P>::THREADS), rlh, st,
                            c->d_coefF, R_vhat, c->d_minvrq, c->d_h, c->d_tab, c->dp.viscous, c->d_B,
                            (int64_t)c->n_macro);
         if (c->d_bc)
