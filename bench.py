@@ -224,6 +224,20 @@ def trace_solve(ctx, w, Ahat, bhat, rtol=1e-8, restart=30, maxit=300):
     torch.cuda.synchronize()
     mf["fgmres_inner5"] = {"outer_iterations": its_f, "inner_iterations": inner_f, "relres": rr_f,
                            "solve_ms": round((time.perf_counter() - t0) * 1e3, 2)}
+    # the same with the inner iterations on single-precision copies of the
+    # factors (the first solve after a condensation makes the copies)
+    ctx.trace_set_inner_precision("fp32")
+    f32 = {}
+    for key in ("first_solve", "solve"):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its_s, inner_s, rr_s = ctx.trace_solve_fgmres(None, F, x, rtol=rtol, maxit=maxit, restart=restart, inner=5)
+        torch.cuda.synchronize()
+        f32[key + "_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    f32.update({"outer_iterations": its_s, "inner_iterations": inner_s, "relres": rr_s})
+    mf["fgmres_inner5_fp32_factors"] = f32
+    ctx.trace_set_inner_precision("fp64")
     out["matrix_free"] = mf
     return out
 

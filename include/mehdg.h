@@ -441,6 +441,16 @@ mehdg_err mehdg_trace_solve_fgmres(mehdg_ctx* ctx, const double* Ahat, const dou
                                    int32_t maxit, int32_t restart, int32_t inner, int32_t* iters,
                                    int32_t* inner_iters, double* relres, mehdg_stream stream);
 
+/* Precision of the factors Algorithm 1's product reads inside the inner
+ * iterations of mehdg_trace_solve_fgmres with Ahat NULL: MEHDG_FP64 (default)
+ * or MEHDG_FP32_IR, single-precision copies of U12, L21 and A' (n_macro
+ * (2 N_V N_VH + N_VH^2) floats, made once per FP64 condensation, on the first
+ * such solve after it).  The product sums in FP64 either way; the outer
+ * iterations and every other product keep the FP64 factors, so the solution
+ * still meets rtol for the FP64 operator (the inner solve is only FGMRES's
+ * preconditioner).  Other values: MEHDG_EINVAL.  Host call. */
+mehdg_err mehdg_trace_set_inner_precision(mehdg_ctx* ctx, int32_t prec);
+
 /* Constant source of a DIRK stage (Sec. 5.3): adds s [n_macro][5][n] to the
  * interior residual R_v and subtracts it from the right-hand side r_V of the
  * bordered matrix.  With v_old = v^n, stage i of a DIRK method with a_ii = a

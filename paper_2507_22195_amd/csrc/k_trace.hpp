@@ -91,13 +91,15 @@ __global__ void __launch_bounds__(256) k_local_apply(const double* __restrict__ 
 // two products per macro and no triangular solve; Ahat is never formed.
 // Phase 1: w_m = U12 x_m (N_V rows); phase 2: yl_m = A' x_m - L21 w_m (N_VH
 // rows); 64 rows of one macro per workgroup, lanes along the rows (coalesced).
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_w(const double* __restrict__ B, const double* __restrict__ xg,
-                                              const int64_t* __restrict__ fid, double* __restrict__ w,
-                                              int64_t n_macro) {
+// The factors are read as T: double from the bordered matrix (stride sm per
+// macro, leading dimension ld), or float from their single-precision copies
+// (k_mf_to_f32) for the inner iterations of FGMRES; sums are FP64 in both.
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_mf_w(const T* __restrict__ U12, int64_t sm, int ldu,
+                                              const double* __restrict__ xg, const int64_t* __restrict__ fid,
+                                              double* __restrict__ w, int64_t n_macro) {
     using D = Dims<P>;
-    using BD = Bdims<P>;
-    constexpr int BS = 5 * D::nf, NV = D::NV, NH = D::NH, ld = BD::ld, RT = (NV + 63) / 64, RB = 8;
+    constexpr int BS = 5 * D::nf, NV = D::NV, NH = D::NH, RT = (NV + 63) / 64, RB = 8;
     __shared__ double x[NH];
     int64_t m;
     int tile;
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(256) k_mf_w(const double* __restrict__ B, cons
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int i = threadIdx.x; i < NH; i += blockDim.x) x[i] = xg[fid[6 * m + i / BS] * BS + i % BS];
     __syncthreads();
-    const double* U12 = B + m * BD::per_macro + NV;
+    const T* U = U12 + m * sm;
     const int rlo = tile * 64, rhi = (rlo + 64) < NV ? (rlo + 64) : NV;
     for (int r0 = rlo + wave * RB; r0 < rhi; r0 += nw * RB) {
         double s[RB];
@@ -116,7 +118,7 @@ __global__ void __launch_bounds__(256) k_mf_w(const double* __restrict__ B, cons
             const double xc = x[c];
 #pragma unroll
             for (int i = 0; i < RB; ++i)
-                if (r0 + i < rhi) s[i] += U12[(int64_t)(r0 + i) * ld + c] * xc;
+                if (r0 + i < rhi) s[i] += (double)U[(int64_t)(r0 + i) * ldu + c] * xc;
         }
 #pragma unroll
         for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
@@ -130,13 +132,15 @@ __global__ void __launch_bounds__(256) k_mf_w(const double* __restrict__ B, cons
     }
 }
 
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_y(const double* __restrict__ B, const double* __restrict__ xg,
+// L21 [NH][NV] (leading dimension ldl) and A' [NH][NH] (leading dimension
+// lda), both at stride sm per macro.
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_mf_y(const T* __restrict__ L21, const T* __restrict__ Ap, int64_t sm,
+                                              int ldl, int lda, const double* __restrict__ xg,
                                               const int64_t* __restrict__ fid, const double* __restrict__ w,
                                               double* __restrict__ yl, int64_t n_macro) {
     using D = Dims<P>;
-    using BD = Bdims<P>;
-    constexpr int BS = 5 * D::nf, NV = D::NV, NH = D::NH, ld = BD::ld, RT = (NH + 63) / 64, RB = 8;
+    constexpr int BS = 5 * D::nf, NV = D::NV, NH = D::NH, RT = (NH + 63) / 64, RB = 8;
     __shared__ double x[NH];
     __shared__ double ws[NV];
     int64_t m;
@@ -147,7 +151,8 @@ __global__ void __launch_bounds__(256) k_mf_y(const double* __restrict__ B, cons
     for (int i = threadIdx.x; i < NH; i += blockDim.x) x[i] = xg[fid[6 * m + i / BS] * BS + i % BS];
     for (int i = threadIdx.x; i < NV; i += blockDim.x) ws[i] = w[m * NV + i];
     __syncthreads();
-    const double* Xr = B + m * BD::per_macro + (int64_t)NV * ld;   // rows of L21 | A'
+    const T* Lm = L21 + m * sm;
+    const T* Am = Ap + m * sm;
     const int rlo = tile * 64, rhi = (rlo + 64) < NH ? (rlo + 64) : NH;
     for (int r0 = rlo + wave * RB; r0 < rhi; r0 += nw * RB) {
         double s[RB];
@@ -157,13 +162,13 @@ __global__ void __launch_bounds__(256) k_mf_y(const double* __restrict__ B, cons
             const double wc = ws[c];
 #pragma unroll
             for (int i = 0; i < RB; ++i)
-                if (r0 + i < rhi) s[i] -= Xr[(int64_t)(r0 + i) * ld + c] * wc;
+                if (r0 + i < rhi) s[i] -= (double)Lm[(int64_t)(r0 + i) * ldl + c] * wc;
         }
         for (int c = lane; c < NH; c += 64) {
             const double xc = x[c];
 #pragma unroll
             for (int i = 0; i < RB; ++i)
-                if (r0 + i < rhi) s[i] += Xr[(int64_t)(r0 + i) * ld + NV + c] * xc;
+                if (r0 + i < rhi) s[i] += (double)Am[(int64_t)(r0 + i) * lda + c] * xc;
         }
 #pragma unroll
         for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
@@ -173,6 +178,38 @@ __global__ void __launch_bounds__(256) k_mf_y(const double* __restrict__ B, cons
             for (int i = 1; i < RB; ++i)
                 if (lane == i) si = s[i];
             yl[m * NH + r0 + lane] = si;
+        }
+    }
+}
+
+// Single-precision copies of the factors the matrix-free product reads, per
+// macro [U12: NV x NH | L21: NH x NV | A': NH x NH] (rounded to nearest),
+// one row of the bordered matrix per workgroup row.
+template <int P>
+struct MfF32 {
+    static constexpr int NV = Dims<P>::NV, NH = Dims<P>::NH;
+    static constexpr int64_t per_macro = 2LL * NV * NH + (int64_t)NH * NH;
+    static constexpr int64_t off_l21 = (int64_t)NV * NH, off_ap = 2LL * NV * NH;
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_to_f32(const double* __restrict__ B, float* __restrict__ F32,
+                                                   int64_t n_macro) {
+    using BD = Bdims<P>;
+    using MF = MfF32<P>;
+    constexpr int NV = MF::NV, NH = MF::NH, ld = BD::ld;
+    const int r = blockIdx.x;                     // bordered row, 0 .. NV + NH - 1
+    for (int64_t m = blockIdx.y; m < n_macro; m += gridDim.y) {
+        const double* row = B + m * BD::per_macro + (int64_t)r * ld;
+        float* out = F32 + m * MF::per_macro;
+        if (r < NV) {
+            for (int c = threadIdx.x; c < NH; c += blockDim.x) out[(int64_t)r * NH + c] = (float)row[NV + c];
+        } else {
+            const int q = r - NV;
+            for (int c = threadIdx.x; c < NV; c += blockDim.x)
+                out[MF::off_l21 + (int64_t)q * NV + c] = (float)row[c];
+            for (int c = threadIdx.x; c < NH; c += blockDim.x)
+                out[MF::off_ap + (int64_t)q * NH + c] = (float)row[NV + c];
         }
     }
 }

@@ -29,6 +29,9 @@ struct mehdg_ctx {
     int p = 0;
     int64_t n_macro = 0;
     int tile[MEHDG_NTILE_SITES] = {};   // product tile variant per call site
+    int inner_prec = MEHDG_FP64;        // factors read by FGMRES's inner iterations
+    float* d_mf32 = nullptr;            // their single-precision copies
+    int64_t cond_count = 0, mf32_count = -1;   // FP64 condensations; the one the copies hold
     int64_t cap = 0;                    // macros the per-macro workspaces hold
     double* base_h = nullptr;           // the context's own mesh, status and wall arrays
     int32_t* base_status = nullptr;     // (d_h, d_status, d_bc point here unless a
@@ -741,21 +744,50 @@ unsigned vec_grid(int64_t n) {
 // K x; with Ahat NULL matrix-free from the factors of an FP64 condensation
 // (Algorithm 1: Ahat_m x_m = A' x_m - L21 (U12 x_m), k_mf_w then k_mf_y)
 template <int P>
-mehdg_err trace_launch_apply(mehdg_ctx* c, const double* Ahat, const double* x, double* y, hipStream_t st) {
+mehdg_err trace_launch_apply(mehdg_ctx* c, const double* Ahat, const double* x, double* y, hipStream_t st,
+                             bool inner = false) {
     using D = Dims<P>;
-    constexpr int RT = (D::NH + 63) / 64, RTV = (D::NV + 63) / 64;
+    using BD = Bdims<P>;
+    using MF = MfF32<P>;
+    constexpr int RT = (D::NH + 63) / 64, RTV = (D::NV + 63) / 64, NV = D::NV, NH = D::NH, ld = BD::ld;
     if (Ahat) {
         hipLaunchKernelGGL(k_local_apply<P>, dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st, Ahat, x, c->d_fid,
                            c->d_yl, (int64_t)c->n_macro);
+    } else if (inner && c->inner_prec == MEHDG_FP32_IR) {
+        const float* F = c->d_mf32;
+        hipLaunchKernelGGL((k_mf_w<P, float>), dim3(xcd_grid(RTV, c->n_macro)), dim3(256), 0, st, F, MF::per_macro,
+                           NH, x, c->d_fid, c->d_mfw, (int64_t)c->n_macro);
+        hipLaunchKernelGGL((k_mf_y<P, float>), dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st, F + MF::off_l21,
+                           F + MF::off_ap, MF::per_macro, NV, NH, x, c->d_fid, c->d_mfw, c->d_yl,
+                           (int64_t)c->n_macro);
     } else {
-        hipLaunchKernelGGL(k_mf_w<P>, dim3(xcd_grid(RTV, c->n_macro)), dim3(256), 0, st, c->d_B, x, c->d_fid,
-                           c->d_mfw, (int64_t)c->n_macro);
-        hipLaunchKernelGGL(k_mf_y<P>, dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st, c->d_B, x, c->d_fid,
+        const double* B = c->d_B;
+        hipLaunchKernelGGL((k_mf_w<P, double>), dim3(xcd_grid(RTV, c->n_macro)), dim3(256), 0, st, B + NV,
+                           BD::per_macro, ld, x, c->d_fid, c->d_mfw, (int64_t)c->n_macro);
+        hipLaunchKernelGGL((k_mf_y<P, double>), dim3(xcd_grid(RT, c->n_macro)), dim3(256), 0, st,
+                           B + (int64_t)NV * ld, B + (int64_t)NV * ld + NV, BD::per_macro, ld, ld, x, c->d_fid,
                            c->d_mfw, c->d_yl, (int64_t)c->n_macro);
     }
     hipLaunchKernelGGL(k_face_sum<P>, dim3((unsigned)c->n_faces), dim3(128), 0, st, c->d_yl, c->d_side, y,
                        c->n_faces);
     return hip_ok(hipGetLastError());
+}
+
+// Single-precision copies of the factors for the inner iterations, made once
+// per FP64 condensation.
+template <int P>
+mehdg_err ensure_mf32(mehdg_ctx* c, hipStream_t st) {
+    if (c->mf32_count == c->cond_count) return MEHDG_OK;
+    if (!c->d_mf32) {
+        mehdg_err e = dev_alloc(c, &c->d_mf32, c->n_macro * MfF32<P>::per_macro);
+        if (e != MEHDG_OK) return e;
+    }
+    const unsigned gy = (unsigned)std::min<int64_t>(c->n_macro, 65535);
+    hipLaunchKernelGGL(k_mf_to_f32<P>, dim3((unsigned)(Dims<P>::NV + Dims<P>::NH), gy), dim3(256), 0, st, c->d_B,
+                       c->d_mf32, (int64_t)c->n_macro);
+    if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
+    c->mf32_count = c->cond_count;
+    return MEHDG_OK;
 }
 
 // inverses of K's diagonal face blocks; with Ahat NULL the blocks are formed
@@ -1001,7 +1033,7 @@ mehdg_err inner_gmres(mehdg_ctx* c, const double* Ahat, const double* r, double*
     for (; j < inner; ++j) {
         double* vj = V + (int64_t)j * N;
         if ((e = trace_launch_precond_apply<P>(c, vj, z, st)) != MEHDG_OK) return e;
-        if ((e = trace_launch_apply<P>(c, Ahat, z, w, st)) != MEHDG_OK) return e;
+        if ((e = trace_launch_apply<P>(c, Ahat, z, w, st, true)) != MEHDG_OK) return e;
         for (int pass = 0; pass < 2; ++pass) {
             double* hh = pass ? h2.data() : h.data();
             if ((e = host_dots(c, V, N, j + 1, w, hh, st)) != MEHDG_OK) return e;
@@ -1082,6 +1114,7 @@ mehdg_err trace_fgmres(mehdg_ctx* c, const double* Ahat, const double* F, double
     c->h_part.assign((size_t)(nbasis + 1) * kDotBlocks, 0.0);
     c->h_coef.assign((size_t)nbasis + 1, 0.0);
     if ((e = trace_launch_precond_setup<P>(c, Ahat, st)) != MEHDG_OK) return e;
+    if (!Ahat && c->inner_prec == MEHDG_FP32_IR && inner > 0 && (e = ensure_mf32<P>(c, st)) != MEHDG_OK) return e;
     double* V = c->d_V;
     double* Z = c->d_fZ;
     double* w = c->d_w;
@@ -1275,6 +1308,7 @@ mehdg_err mehdg_destroy(mehdg_ctx* c) {
     (void)hipFree(c->d_mfw);
     (void)hipFree(c->d_fZ);
     (void)hipFree(c->d_iV);
+    (void)hipFree(c->d_mf32);
     (void)hipFree(c->d_Dinv);
     (void)hipFree(c->d_V);
     (void)hipFree(c->d_w);
@@ -1458,6 +1492,7 @@ mehdg_err mehdg_condense(mehdg_ctx* c, int32_t prec, double* Ahat, double* bhat,
         e = launch_poison(c, PoisonArgs{{Ahat, bhat, nullptr, nullptr}, {sz[4] * sz[4], sz[4], 0, 0}}, st);
     }
     if (e == MEHDG_OK) c->stage = prec == MEHDG_FP64 ? 2 : 3;
+    if (e == MEHDG_OK && prec == MEHDG_FP64) ++c->cond_count;
     else c->stage = 0;   // the bordered matrices are partly factored: assemble again
     return e;
 }
@@ -1747,6 +1782,12 @@ mehdg_err mehdg_trace_solve(mehdg_ctx* c, const double* Ahat, const double* F, d
         case 3: return trace_gmres<3>(c, Ahat, F, x, rtol, maxit, restart, iters, relres, st);
         default: return MEHDG_EINVAL;
     }
+}
+
+mehdg_err mehdg_trace_set_inner_precision(mehdg_ctx* c, int32_t prec) {
+    if (!c || (prec != MEHDG_FP64 && prec != MEHDG_FP32_IR)) return MEHDG_EINVAL;
+    c->inner_prec = prec;
+    return MEHDG_OK;
 }
 
 mehdg_err mehdg_trace_solve_fgmres(mehdg_ctx* c, const double* Ahat, const double* F, double* x, double rtol,

@@ -127,6 +127,8 @@ def load(path: str = LIB_PATH):
     for name in ("mehdg_batch_create", "mehdg_batch_destroy", "mehdg_batch_layout", "mehdg_batch_groups",
                  "mehdg_batch_assemble_condense", "mehdg_batch_recover", "mehdg_batch_status"):
         getattr(lib, name).restype = ctypes.c_int
+    lib.mehdg_trace_set_inner_precision.argtypes = [vp, i32]
+    lib.mehdg_trace_set_inner_precision.restype = ctypes.c_int
     lib.mehdg_tile_variants.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.mehdg_set_tile.argtypes = [vp, i32, i32]
     lib.mehdg_get_tile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
@@ -501,6 +503,12 @@ class Context:
         rc = lib.mehdg_load_bordered(self._handle, int(m), ctypes.c_void_p(Bm.ctypes.data))
         if rc:
             raise MehdgError(rc, "mehdg_load_bordered")
+
+    def trace_set_inner_precision(self, prec: str):
+        """Factors read by FGMRES's inner iterations (matrix-free): "fp64" or "fp32"."""
+        rc = load().mehdg_trace_set_inner_precision(self._handle, PRECISIONS[prec])
+        if rc:
+            raise MehdgError(rc, "mehdg_trace_set_inner_precision")
 
     def set_tile(self, site: str, variant: int):
         """Tile variant of a product call site ("update", "schur"); -1 = the tuned table's."""

@@ -83,6 +83,7 @@ def test_argument_errors_are_synchronous():
     assert list(shapes[:6]) == [4, 2, 2, 2, 16, 4]          # variant 0: 128 x 64 tiles of 512 threads
     assert lib.mehdg_tile_variants(None, None) == 1
     assert lib.mehdg_set_tile(None, 0, 0) == 1
+    assert lib.mehdg_trace_set_inner_precision(None, 0) == 1
     assert lib.mehdg_get_tile(None, 0, ctypes.byref(n)) == 1
 
 

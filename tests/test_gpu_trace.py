@@ -98,7 +98,8 @@ def test_matrix_free_operator_and_fgmres(case):
     from the stored factors) equals the explicit product; the face-block
     Jacobi formed from the factors equals the one formed from Ahat; Sec. 6.4's
     FGMRES with inner block-Jacobi GMRES, matrix-free after a condensation that
-    never formed Ahat, matches a sparse direct solve of the oracle's system."""
+    never formed Ahat, matches a sparse direct solve of the oracle's system, also
+    with the inner iterations on single-precision copies of the factors."""
     from paper_2507_22195_amd import mehdg
     name, w = _cases()[case]
     banner(f"trace matrix-free: {name} M={w.n_macro}")
@@ -149,6 +150,17 @@ def test_matrix_free_operator_and_fgmres(case):
     assert rr < 1e-11
     assert rel_err(host(xf).reshape(1, -1), xd.reshape(1, -1)) < 1e-7
     assert its < its_g
+    # the inner iterations on single-precision copies of the factors: the
+    # outer (FP64) iterations still reach the tolerance of the FP64 operator
+    ctx.trace_set_inner_precision("fp32")
+    x32 = empty(T)
+    x32.zero_()
+    its32, inner32, rr32 = ctx.trace_solve_fgmres(None, Fg, x32, rtol=1e-12, maxit=200, restart=30, inner=5)
+    ctx.trace_set_inner_precision("fp64")
+    banner(f"  FGMRES, FP32 inner factors: {its32} outer, {inner32} inner, relres {rr32:.2e}")
+    assert rr32 < 1e-11 and rel_err(host(x32).reshape(1, -1), xd.reshape(1, -1)) < 1e-7
+    with pytest.raises(mehdg.MehdgError):
+        ctx.trace_set_inner_precision("bf16")
     # the recovery after a condensation without Ahat
     xl = empty(S["vhat"])
     ctx.trace_gather(xf, xl)
