@@ -136,22 +136,23 @@ __device__ void row_volume(RowLds<P>& L, const double* __restrict__ coefV, int64
     constexpr int Q = P + 1;
     static_assert(R::KG == 1, "one row per pass");
     const int nfld = viscous ? 20 : 5;
-    // weights, one (point, field) pair per thread (fields of one point adjacent:
-    // their coefficients share the point's record)
+    // weights, one (point, field) pair per thread, points fastest (the
+    // coefficients are stored point index fastest)
     for (int idx = threadIdx.x; idx < nfld * E3; idx += blockDim.x) {
-        const int fld = idx % nfld, gl = idx / nfld;
+        const int gl = idx % E3, fld = idx / E3;
         const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
         const int g = g1 + nq1 * (g2 + nq1 * g3);
         const double B1 = L.t.B[g1][a1], B2 = L.t.B[g2][a2], B3 = L.t.B[g3][a3];
         const double t1 = L.t.D[g1][a1] * B2 * B3, t2 = B1 * L.t.D[g2][a2] * B3, t3 = B1 * B2 * L.t.D[g3][a3];
-        const double* c = coefV + ((int64_t)m * G + g) * COEF_V;
+        const double* c = coefV + (int64_t)m * G * COEF_V + g;
         double wv;
         if (fld < 5) {
             const int o = 5 * k + fld;
-            wv = B1 * B2 * B3 * c[o] + t1 * c[25 + o] + t2 * c[50 + o] + t3 * c[75 + o];
+            wv = B1 * B2 * B3 * c[o * G] + t1 * c[(25 + o) * G] + t2 * c[(50 + o) * G] + t3 * c[(75 + o) * G];
         } else {
             const int j = (fld - 5) % 3, o = 5 * k + (fld - 5) / 3;
-            wv = t1 * c[100 + 25 * j + o] + t2 * c[100 + 25 * (3 + j) + o] + t3 * c[100 + 25 * (6 + j) + o];
+            wv = t1 * c[(100 + 25 * j + o) * G] + t2 * c[(100 + 25 * (3 + j) + o) * G] +
+                 t3 * c[(100 + 25 * (6 + j) + o) * G];
         }
         L.w[fld * WS + gl] = wv;
     }
@@ -213,12 +214,12 @@ __device__ void row_face(RowLds<P>& L, const double* __restrict__ coefF, int64_t
         const int fld = rest % nff, kk = rest / nff, k = k0 + kk;
         const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
         const int s = s1 + nq1 * s2;
-        const double* c = coefF + ((int64_t)m * 6 * S + f * S + s) * COEF_F;
+        const double* c = coefF + (int64_t)m * 6 * S * COEF_F + f * S + s;
         int off;
         if (fld < 5) off = 5 * k + fld;
         else if (fld < 10) off = 25 + 5 * k + (fld - 5);
         else off = 50 + 25 * ((fld - 10) % 3) + 5 * k + (fld - 10) / 3;
-        L.w[(kk * R::E2 + sl) * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off];
+        L.w[(kk * R::E2 + sl) * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off * 6 * S];
     }
     __syncthreads();
     const int d = face_axis(f), t1 = face_t1(f), t2 = face_t2(f);
@@ -419,12 +420,12 @@ __device__ void row_face_h(RowLdsH<P>& L, const double* __restrict__ coefF, int6
         const int sl = idx % R::E2, fld = idx / R::E2;
         const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
         const int s = s1 + nq1 * s2;
-        const double* c = coefF + ((int64_t)m * 6 * S + f * S + s) * COEF_F;
+        const double* c = coefF + (int64_t)m * 6 * S * COEF_F + f * S + s;
         int off;
         if (fld < 5) off = 5 * k + fld;
         else if (fld < 10) off = 25 + 5 * k + (fld - 5);
         else off = 50 + 25 * ((fld - 10) % 3) + 5 * k + (fld - 10) / 3;
-        L.w[sl * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off];
+        L.w[sl * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off * 6 * S];
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < nf_ * R::E2; idx += blockDim.x) {

@@ -99,12 +99,12 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
             }
         }
         const double w = vol * L.t.w[g1] * L.t.w[g2] * L.t.w[g3];
-        const double* cv = coefV + ((int64_t)m * G + g) * COEF_V;
+        const double* cv = coefV + (int64_t)m * G * COEF_V + g;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < 5; ++l) acc += cv[5 * k + l] * vv[l];
+            for (int l = 0; l < 5; ++l) acc += cv[(5 * k + l) * G] * vv[l];
             scr[k * G + g] = acc;
         }
 #pragma unroll
@@ -113,12 +113,12 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
             for (int k = 0; k < 5; ++k) {
                 double acc = 0.0;
 #pragma unroll
-                for (int l = 0; l < 5; ++l) acc += cv[25 + 25 * i + 5 * k + l] * vv[l];
+                for (int l = 0; l < 5; ++l) acc += cv[(25 + 25 * i + 5 * k + l) * G] * vv[l];
                 if (viscous) {
 #pragma unroll
                     for (int j = 0; j < 3; ++j)
 #pragma unroll
-                        for (int l = 0; l < 5; ++l) acc += cv[100 + 25 * (3 * i + j) + 5 * k + l] * qq[l][j];
+                        for (int l = 0; l < 5; ++l) acc += cv[(100 + 25 * (3 * i + j) + 5 * k + l) * G] * qq[l][j];
                 }
                 scr[(5 + 5 * i + k) * G + g] = acc;
             }
@@ -164,17 +164,18 @@ __global__ void __launch_bounds__(256) k_jvp(const double* __restrict__ dv, cons
             }
         }
         const double ws = h[t1] * h[t2] * L.t.w[s1] * L.t.w[s2];
-        const double* cf = coefF + ((int64_t)m * 6 * S + idx) * COEF_F;
+        const double* cf = coefF + (int64_t)m * 6 * S * COEF_F + idx;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             double acc = 0.0;
 #pragma unroll
-            for (int l = 0; l < 5; ++l) acc += cf[5 * k + l] * vv[l] + cf[25 + 5 * k + l] * vh[l];
+            for (int l = 0; l < 5; ++l)
+                acc += cf[(5 * k + l) * (6 * S)] * vv[l] + cf[(25 + 5 * k + l) * (6 * S)] * vh[l];
             if (viscous) {
 #pragma unroll
                 for (int j = 0; j < 3; ++j)
 #pragma unroll
-                    for (int l = 0; l < 5; ++l) acc += cf[50 + 25 * j + 5 * k + l] * qq[l][j];
+                    for (int l = 0; l < 5; ++l) acc += cf[(50 + 25 * j + 5 * k + l) * (6 * S)] * qq[l][j];
             }
             L.fh[f][k][s] = acc;
             L.qh[f][k][s] = ws * sg * vh[k];
@@ -261,15 +262,15 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
             }
         }
         const double w = vol * L.t.w[g1] * L.t.w[g2] * L.t.w[g3];
-        const double* cv = coefV + ((int64_t)m * G + g) * COEF_V;
+        const double* cv = coefV + (int64_t)m * G * COEF_V + g;
 #pragma unroll
         for (int l = 0; l < 5; ++l) {
             double acc = 0.0;
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                acc += cv[5 * k + l] * mu0[k];
+                acc += cv[(5 * k + l) * G] * mu0[k];
 #pragma unroll
-                for (int i = 0; i < 3; ++i) acc += cv[25 + 25 * i + 5 * k + l] * mu[i][k];
+                for (int i = 0; i < 3; ++i) acc += cv[(25 + 25 * i + 5 * k + l) * G] * mu[i][k];
             }
             if (full) {
 #pragma unroll
@@ -286,7 +287,7 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
 #pragma unroll
                     for (int i = 0; i < 3; ++i)
 #pragma unroll
-                        for (int k = 0; k < 5; ++k) acc += cv[100 + 25 * (3 * i + j) + 5 * k + l] * mu[i][k];
+                        for (int k = 0; k < 5; ++k) acc += cv[(100 + 25 * (3 * i + j) + 5 * k + l) * G] * mu[i][k];
                 }
                 scr[(5 + 3 * l + j) * G + g] = acc;
             }
@@ -329,14 +330,14 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
             }
         }
         const double ws = h[t1] * h[t2] * L.t.w[s1] * L.t.w[s2];
-        const double* cf = coefF + ((int64_t)m * 6 * S + idx) * COEF_F;
+        const double* cf = coefF + (int64_t)m * 6 * S * COEF_F + idx;
 #pragma unroll
         for (int l = 0; l < 5; ++l) {
             double av = 0.0, ah = 0.0;
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                av += cf[5 * k + l] * rho[k];
-                ah += cf[25 + 5 * k + l] * rho[k];
+                av += cf[(5 * k + l) * (6 * S)] * rho[k];
+                ah += cf[(25 + 5 * k + l) * (6 * S)] * rho[k];
             }
             L.fh[f][l][s] = av;
             L.qh[f][l][s] = ah - ws * sg * tau[l] + ws * rw[l];
@@ -345,7 +346,7 @@ __global__ void __launch_bounds__(256) k_vjp(const double* __restrict__ wq, cons
                 double aq = 0.0;
                 if (viscous) {
 #pragma unroll
-                    for (int k = 0; k < 5; ++k) aq += cf[50 + 25 * j + 5 * k + l] * rho[k];
+                    for (int k = 0; k < 5; ++k) aq += cf[(50 + 25 * j + 5 * k + l) * (6 * S)] * rho[k];
                 }
                 scr[VS::FACE_Q + (3 * l + j) * 6 * S + idx] = aq;
             }

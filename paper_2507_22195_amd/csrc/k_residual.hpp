@@ -73,12 +73,15 @@ struct ResScratch {
 // Per face Gauss point, COEF_F doubles:
 //   [0,25) w dFtot/dv, [25,50) w dFtot/dvhat, [50,125) w dGhat/dq_{.j} (block j),
 // with Ftot = Fhat + Ghat the total trace flux.
+// Stored coefficient-major, point index fastest: coefV [m][COEF_V][G] and
+// coefF [m][COEF_F][6 S] (face points face by face), so that the lanes of a
+// wave, which own consecutive points, write and read consecutive addresses.
 constexpr int COEF_V = 325;
 constexpr int COEF_F = 125;
 
 __device__ __forceinline__ void volume_coefficients(const double vv[5], const double qq[5][3], double w,
                                                     const double hinv[3], const DevParams& pr,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, int stride) {
     dual<5> vd[5];
 #pragma unroll
     for (int l = 0; l < 5; ++l) vd[l] = seed_dual<5>(vv[l], l);
@@ -91,22 +94,16 @@ __device__ __forceinline__ void volume_coefficients(const double vv[5], const do
 #pragma unroll
         for (int k = 0; k < 5; ++k)
 #pragma unroll
-            for (int l = 0; l < 5; ++l) out[5 * k + l] = c * u[k].d[l];
+            for (int l = 0; l < 5; ++l) out[(5 * k + l) * stride] = c * u[k].d[l];
     }
-    dual<5> qd[5][3];
-    if (pr.viscous) {
-#pragma unroll
-        for (int l = 0; l < 5; ++l)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) qd[l][j] = make_dual<5>(qq[l][j]);
-    }
+    // q enters as plain values: G's v-derivative at fixed q
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         dual<5> F[5];
         euler_flux(s, pr.gamma, i, F);
         if (pr.viscous) {
             dual<5> Gv[5];
-            viscous_flux(vd, qd, pr, i, Gv);
+            viscous_flux(vd, qq, pr, i, Gv);
 #pragma unroll
             for (int k = 0; k < 5; ++k) F[k] = F[k] + Gv[k];
         }
@@ -114,7 +111,7 @@ __device__ __forceinline__ void volume_coefficients(const double vv[5], const do
 #pragma unroll
         for (int k = 0; k < 5; ++k)
 #pragma unroll
-            for (int l = 0; l < 5; ++l) out[25 + 25 * i + 5 * k + l] = c * F[k].d[l];
+            for (int l = 0; l < 5; ++l) out[(25 + 25 * i + 5 * k + l) * stride] = c * F[k].d[l];
     }
     // G is linear in q: its q-derivative columns are G evaluated at unit q.
     for (int i = 0; i < 3; ++i) {
@@ -130,14 +127,14 @@ __device__ __forceinline__ void volume_coefficients(const double vv[5], const do
                     viscous_flux(vv, qu, pr, i, Gv);
                 }
 #pragma unroll
-                for (int k = 0; k < 5; ++k) out[100 + 25 * (3 * i + j) + 5 * k + l] = c * Gv[k];
+                for (int k = 0; k < 5; ++k) out[(100 + 25 * (3 * i + j) + 5 * k + l) * stride] = c * Gv[k];
             }
     }
 }
 
 __device__ __forceinline__ void face_coefficients(const double vh[5], const double vv[5], const double qq[5][3],
                                                   double ws, const DevParams& pr, int d, double sg,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int stride) {
     // derivatives of the inviscid trace flux in v (pass 0) and vhat (pass 1)
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
@@ -149,19 +146,15 @@ __device__ __forceinline__ void face_coefficients(const double vh[5], const doub
         }
         trace_flux(a, b, pr, d, sg, F);
         if (pr.viscous) {
-            dual<5> qd[5][3], Gh[5];
-#pragma unroll
-            for (int l = 0; l < 5; ++l)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) qd[l][j] = make_dual<5>(qq[l][j]);
-            viscous_trace_flux(a, b, qd, pr, d, sg, Gh);
+            dual<5> Gh[5];
+            viscous_trace_flux(a, b, qq, pr, d, sg, Gh);
 #pragma unroll
             for (int k = 0; k < 5; ++k) F[k] = F[k] + Gh[k];
         }
 #pragma unroll
         for (int k = 0; k < 5; ++k)
 #pragma unroll
-            for (int l = 0; l < 5; ++l) out[25 * pass + 5 * k + l] = ws * F[k].d[l];
+            for (int l = 0; l < 5; ++l) out[(25 * pass + 5 * k + l) * stride] = ws * F[k].d[l];
     }
     // Ghat = sg G_d(vhat, q) - ...: linear in q
     for (int l = 0; l < 5; ++l)
@@ -175,7 +168,7 @@ __device__ __forceinline__ void face_coefficients(const double vh[5], const doub
                 viscous_flux(vh, qu, pr, d, Gv);
             }
 #pragma unroll
-            for (int k = 0; k < 5; ++k) out[50 + 25 * j + 5 * k + l] = ws * sg * Gv[k];
+            for (int k = 0; k < 5; ++k) out[(50 + 25 * j + 5 * k + l) * stride] = ws * sg * Gv[k];
         }
 }
 
@@ -418,7 +411,7 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
                 scr[(20 + 3 * k + j) * G + g] = w * qq[k][j];
                 scr[(35 + 5 * j + k) * G + g] = w * hinv[j] * vv[k];
             }
-        if constexpr (JAC) volume_coefficients(vv, qq, w, hinv, pr, coefV + ((int64_t)m * G + g) * COEF_V);
+        if constexpr (JAC) volume_coefficients(vv, qq, w, hinv, pr, coefV + (int64_t)m * G * COEF_V + g, G);
     }
 
     // ---- phase 3: face Gauss points
@@ -475,7 +468,8 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
 #pragma unroll
             for (int k = 0; k < 5; ++k) Fh[k] += Gh[k];
         }
-        if constexpr (JAC) face_coefficients(vh, vv, qq, ws, pr, d, sg, coefF + ((int64_t)m * 6 * S + idx) * COEF_F);
+        if constexpr (JAC)
+            face_coefficients(vh, vv, qq, ws, pr, d, sg, coefF + (int64_t)m * 6 * S * COEF_F + idx, 6 * S);
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
             L.fh[f][k][s] = ws * Fh[k];
