@@ -847,42 +847,62 @@ __device__ __forceinline__ void tile_mma(const double* A, int lda, const double*
     }
 }
 
-// tile_mma with the K rows of Bt taken from rows srcrow[k] of Bfull.
+// tile_mma (not negated) with the K rows of Bt taken from rows srcrow[k] of
+// Bfull, with the same one-chunk-ahead register prefetch.
 __device__ __forceinline__ void tile_mma_gather(const double* A, int lda, const double* Bfull, int ldb,
                                                 const int* srcrow, int K, int r0, int c0, int rows, int cols,
                                                 v4d acc[2][2], TileSmem& sm) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const int nchunk = (K + GK - 1) / GK;
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int k0 = ch * GK;
+    double ra[GLA], rb[GLB];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < GLA; ++i) {
             const int e = tid + GTHREADS * i;
             const int ar = e / GK, ak = e % GK;
             const int r = r0 + ar, k = k0 + ak;
-            sm.As[0][ar][ak] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
+            ra[i] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < GLB; ++i) {
             const int e = tid + GTHREADS * i;
             const int bk = e / GT, bc = e % GT;
             const int kk = k0 + bk, c = c0 + bc;
-            sm.Bs[0][bk][bc] = (kk < K && c < cols) ? Bfull[(int64_t)srcrow[kk] * ldb + c] : 0.0;
+            rb[i] = (kk < K && c < cols) ? Bfull[(int64_t)srcrow[kk] * ldb + c] : 0.0;
         }
-        __syncthreads();
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < GLA; ++i) {
+            const int e = tid + GTHREADS * i;
+            sm.As[buf][e / GK][e % GK] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < GLB; ++i) {
+            const int e = tid + GTHREADS * i;
+            sm.Bs[buf][e / GT][e % GT] = rb[i];
+        }
+    };
+    const int nchunk = (K + GK - 1) / GK;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) load((ch + 1) * GK);
 #pragma unroll
         for (int ks = 0; ks < GK; ks += 4) {
             const int kq = ks + (lane >> 4);
-            const double a0 = sm.As[0][wr * 32 + (lane & 15)][kq];
-            const double a1 = sm.As[0][wr * 32 + 16 + (lane & 15)][kq];
-            const double b0 = sm.Bs[0][kq][wc * 32 + (lane & 15)];
-            const double b1 = sm.Bs[0][kq][wc * 32 + 16 + (lane & 15)];
+            const double a0 = sm.As[buf][wr * 32 + (lane & 15)][kq];
+            const double a1 = sm.As[buf][wr * 32 + 16 + (lane & 15)][kq];
+            const double b0 = sm.Bs[buf][kq][wc * 32 + (lane & 15)];
+            const double b1 = sm.Bs[buf][kq][wc * 32 + 16 + (lane & 15)];
             acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
+        if (ch + 1 < nchunk) stash(buf ^ 1);
         __syncthreads();
     }
 }
