@@ -1491,9 +1491,12 @@ mehdg_err mehdg_condense(mehdg_ctx* c, int32_t prec, double* Ahat, double* bhat,
         (void)mehdg_sizes(c->p, sz);
         e = launch_poison(c, PoisonArgs{{Ahat, bhat, nullptr, nullptr}, {sz[4] * sz[4], sz[4], 0, 0}}, st);
     }
-    if (e == MEHDG_OK) c->stage = prec == MEHDG_FP64 ? 2 : 3;
-    if (e == MEHDG_OK && prec == MEHDG_FP64) ++c->cond_count;
-    else c->stage = 0;   // the bordered matrices are partly factored: assemble again
+    if (e == MEHDG_OK) {
+        c->stage = prec == MEHDG_FP64 ? 2 : 3;
+        if (prec == MEHDG_FP64) ++c->cond_count;
+    } else {
+        c->stage = 0;   // the bordered matrices are partly factored: assemble again
+    }
     return e;
 }
 
