@@ -373,13 +373,14 @@ def test_tet_step_beyond_one_launch_of_macros():
         assert x <= TOL, (k, x)
 
 
-def test_tet_condense_rhs():
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_tet_condense_rhs(p):
     from paper_2507_22195_amd import mehdg
-    w = _tgv(2, "ES", True, shape=(1, 1, 1), seed=151)
+    w = _tgv(p, "ES", True, shape=(1, 1, 1), seed=151)
     ctx = mehdg.TetContext(w.p, w.mesh.X, w.params)
     S = ctx.shapes()
     e = {k: empty(S[k]) for k in ("R_q", "R_v", "R_vhat", "entropy", "Ahat", "bhat", "dv", "dq")}
-    banner("tet condense_rhs: p=2")
+    banner(f"tet condense_rhs: p={p}")
     ctx.assemble(dev(w.v), dev(w.vhat), dev(w.v_old), e["R_q"], e["R_v"], e["R_vhat"], e["entropy"])
     ctx.condense(e["Ahat"], e["bhat"])
     b1 = empty(S["bhat"])
@@ -394,7 +395,7 @@ def test_tet_condense_rhs():
     rc, st = ctx.status()
     ctx.close()
     assert rc == 0, st
-    ref = forms.condense(tet.TetGeometry(2, w.mesh.X), w.v, w.vhat, w.v_old, w.params)
+    ref = forms.condense(tet.TetGeometry(p, w.mesh.X), w.v, w.vhat, w.v_old, w.params)
     M_ = w.n_macro
     rb, rdv = [], []
     for m in range(M_):
