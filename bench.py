@@ -299,7 +299,7 @@ def differentiation(reps=5):
     return out
 
 
-def _batch_run(degrees, steps):
+def _batch_run(degrees, steps, compare_per_degree=False):
     """A mixed-degree batch of 16^3 viscous Taylor-Green macro-elements, degrees
     drawn uniformly (seed 41) from ``degrees``, 20% with an isothermal wall on
     the -z face (seed 42): assemble + condense and recover timed apart (eager),
@@ -314,6 +314,7 @@ def _batch_run(degrees, steps):
     for d, w in parts.items():
         h[np.nonzero(p == d)[0]] = w.mesh.h
     b = MixedBatch(p, h, parts[1].params, face_bc=bc)
+    prm = parts[1].params
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
     rng = np.random.default_rng(1)
     v = dev(b.pack("v", {d: w.v for d, w in parts.items()}))
@@ -362,6 +363,17 @@ def _batch_run(degrees, steps):
            "dense_condense_TFLOP/s": round(flops / ac / 1e12, 2)}
     del g
     b.close()
+    if compare_per_degree:
+        # the same step with one residual launch per degree instead of the persistent one
+        b = MixedBatch(p, h, prm, face_bc=bc, residual_per_degree=True)
+        b.step(*args)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.assemble_condense(*args[:9])
+        torch.cuda.synchronize()
+        res["assemble_condense_ms_residual_per_degree"] = round((time.perf_counter() - t0) / steps * 1e3, 2)
+        b.close()
     del out, args, v, vh, vo, dvh
     torch.cuda.empty_cache()
     return res
@@ -378,7 +390,7 @@ def mixed_degree(steps=1):
                        "phase, each degree on a stream of its own, groups beyond the workspace budget streamed "
                        "in waves (their recovery re-forms each wave's factors)"}
     res.update(_batch_run((1, 2, 3, 4), steps))
-    res["degrees_1_to_3"] = _batch_run((1, 2, 3), steps)
+    res["degrees_1_to_3"] = _batch_run((1, 2, 3), steps, compare_per_degree=True)
     return res
 
 

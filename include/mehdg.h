@@ -308,7 +308,10 @@ mehdg_err mehdg_get_tile(const mehdg_ctx* ctx, int32_t site, int32_t* variant);
  * batch (default priority) forked from the caller's stream and joined back to
  * it, so the calls are asynchronous on that stream, and an FP64 step is
  * capturable in a HIP graph once the contexts' workspaces exist (after the
- * first step).
+ * first step).  The residual pass (residual, entropy production, pointwise
+ * Jacobian coefficients) of all groups that are not streamed is one
+ * persistent launch: its workgroups take the macros from a device queue in
+ * descending degree and run each with its degree's code.
  * Device memory: when the contexts of all groups would need more than
  * max_workspace_bytes, the groups with the largest macros are streamed in
  * waves (their context holds one wave and works through the group wave by
@@ -324,6 +327,10 @@ typedef struct {
     const uint8_t* face_bc;  /* [n_macro][6] or NULL: 1 = isothermal no-slip wall */
     int64_t max_workspace_bytes;   /* device workspace of the contexts; 0: 60% of the free
                                       device memory at creation */
+    int32_t residual_per_degree;   /* 0: the residual pass of all groups that are not streamed
+                                      in one persistent launch over a degree-sorted queue;
+                                      1: one residual launch per degree (same results) */
+    int32_t pad_;
 } mehdg_batch_mesh;
 typedef enum {
     MEHDG_KEY_V = 0,

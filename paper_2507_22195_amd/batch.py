@@ -33,9 +33,10 @@ class MixedBatch:
     """p [n_macro] degrees (1..4), h [n_macro][3], one parameter set, face_bc
     [n_macro][6] wall flags or None; max_workspace_bytes bounds the contexts'
     device workspace (0: the library's default), beyond which the groups with
-    the largest macros are streamed in waves (``waves``)."""
+    the largest macros are streamed in waves (``waves``); residual_per_degree
+    replaces the persistent residual launch by one launch per degree."""
 
-    def __init__(self, p, h, params, face_bc=None, max_workspace_bytes=0):
+    def __init__(self, p, h, params, face_bc=None, max_workspace_bytes=0, residual_per_degree=False):
         lib = mehdg.load()
         p = np.ascontiguousarray(np.asarray(p, dtype=np.int32))
         h = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
@@ -48,7 +49,8 @@ class MixedBatch:
                 raise ValueError("face_bc must be [n_macro][6]")
             bc_ptr = bc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         mesh = mehdg.BatchMesh(p.size, p.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                               h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bc_ptr, int(max_workspace_bytes))
+                               h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), bc_ptr, int(max_workspace_bytes),
+                               int(bool(residual_per_degree)), 0)
         self._prm = mehdg.make_params(params)
         handle = ctypes.c_void_p()
         rc = lib.mehdg_batch_create(ctypes.byref(mesh), ctypes.byref(self._prm), ctypes.byref(handle))

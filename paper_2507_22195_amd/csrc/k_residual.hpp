@@ -305,20 +305,22 @@ __device__ __forceinline__ void test_integrands(const ResLds<P>& L, const double
     }
 }
 
+// The residual (and with JAC the pointwise Jacobian coefficients) of macro m
+// by the whole workgroup, smem_raw the workgroup's dynamic LDS (ResScratch<P>::
+// lds_bytes).  Shared by the per-degree kernel and the batch's persistent one.
 template <int P, bool JAC>
-__global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, const double* __restrict__ vhat,
-                                                  const double* __restrict__ q, const double* __restrict__ v_old,
-                                                  const double* __restrict__ hs, DevParams pr,
-                                                  const Tab1D* __restrict__ tab, double* __restrict__ R_q,
-                                                  double* __restrict__ R_v, double* __restrict__ R_vh,
-                                                  double* __restrict__ entropy, double* __restrict__ scratch,
-                                                  double* __restrict__ coefV, double* __restrict__ coefF,
-                                                  const uint8_t* __restrict__ face_bc, int32_t* __restrict__ status) {
+__device__ __forceinline__ void residual_macro(int64_t m, unsigned char* smem_raw, const double* __restrict__ v,
+                                               const double* __restrict__ vhat, const double* __restrict__ q,
+                                               const double* __restrict__ v_old, const double* __restrict__ hs,
+                                               const DevParams& pr, const Tab1D* __restrict__ tab,
+                                               double* __restrict__ R_q, double* __restrict__ R_v,
+                                               double* __restrict__ R_vh, double* __restrict__ entropy,
+                                               double* __restrict__ scratch, double* __restrict__ coefV,
+                                               double* __restrict__ coefF, const uint8_t* __restrict__ face_bc,
+                                               int32_t* __restrict__ status) {
     using D = Dims<P>;
     constexpr int n1d = D::n1d, nq1 = D::nq1, n = D::n, nf = D::nf, G = D::G, S = D::S;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
     ResLds<P>& L = *reinterpret_cast<ResLds<P>*>(smem_raw);
-    const int64_t m = blockIdx.x;
     const int tid = threadIdx.x;
 
     // ---- phase 1: stage inputs
@@ -491,6 +493,20 @@ __global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, 
     test_integrands<P>(L, scr, m, face_bc ? face_bc + m * 6 : nullptr, h, pr.gT, R_q, R_v, R_vh);
     if (bad_phys) record_status(status, m, ST_NONPHYSICAL);
     else if (bad_fin) record_status(status, m, ST_NONFINITE);
+}
+
+template <int P, bool JAC>
+__global__ void __launch_bounds__(256) k_residual(const double* __restrict__ v, const double* __restrict__ vhat,
+                                                  const double* __restrict__ q, const double* __restrict__ v_old,
+                                                  const double* __restrict__ hs, DevParams pr,
+                                                  const Tab1D* __restrict__ tab, double* __restrict__ R_q,
+                                                  double* __restrict__ R_v, double* __restrict__ R_vh,
+                                                  double* __restrict__ entropy, double* __restrict__ scratch,
+                                                  double* __restrict__ coefV, double* __restrict__ coefF,
+                                                  const uint8_t* __restrict__ face_bc, int32_t* __restrict__ status) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    residual_macro<P, JAC>(blockIdx.x, smem_raw, v, vhat, q, v_old, hs, pr, tab, R_q, R_v, R_vh, entropy, scratch,
+                           coefV, coefF, face_bc, status);
 }
 
 }  // namespace mehdg

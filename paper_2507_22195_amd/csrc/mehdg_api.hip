@@ -15,6 +15,7 @@
 
 #include "../../include/mehdg.h"
 #include "common.hpp"
+#include "k_batch.hpp"
 #include "k_linear.hpp"
 #include "k_mixed.hpp"
 #include "k_recover.hpp"
@@ -22,6 +23,7 @@
 #include "tables.hpp"
 #include "tet_cond.hpp"
 #include "tile_table.hpp"
+#include "batch_view.hpp"
 
 using namespace mehdg;
 
@@ -186,10 +188,12 @@ int64_t ctx_macro_bytes() {
 }
 
 template <int P>
+mehdg_err launch_rows(mehdg_ctx* c, const double* R_q, const double* R_v, const double* R_vhat, hipStream_t st);
+
+template <int P>
 mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, const double* q,
                           const double* v_old, double* R_q, double* R_v, double* R_vhat, double* ent,
                           int mode, hipStream_t st) {
-    using D = Dims<P>;
     const size_t lds = res_lds<P>();
     const unsigned M = (unsigned)c->n_macro;
     if (mode == 0) {
@@ -211,6 +215,15 @@ mehdg_err launch_assemble(mehdg_ctx* c, const double* v, const double* vhat, con
     }
     if (hipGetLastError() != hipSuccess) return MEHDG_EHIP;
     if (mode == 2) return MEHDG_OK;
+    return launch_rows<P>(c, R_q, R_v, R_vhat, st);
+}
+
+// The rows of the bordered matrix from the residual pass's outputs and
+// coefficients: M^-1 R_Q, the interior rows, the trace rows, the wall rows.
+template <int P>
+mehdg_err launch_rows(mehdg_ctx* c, const double* R_q, const double* R_v, const double* R_vhat, hipStream_t st) {
+    using D = Dims<P>;
+    const unsigned M = (unsigned)c->n_macro;
     {
         Timed t(c, MEHDG_PROF_MINV_RQ, st);
         hipLaunchKernelGGL(k_minv_rq<P>, dim3(M, MinvRqCfg<P>::GROUPS), dim3(256), 0, st, R_q, c->d_h, c->d_tab, c->d_minvrq);
@@ -256,6 +269,19 @@ __global__ void __launch_bounds__(256) k_poison(const int32_t* __restrict__ stat
 mehdg_err launch_poison(mehdg_ctx* c, PoisonArgs a, hipStream_t st) {
     hipLaunchKernelGGL(k_poison, dim3((unsigned)c->n_macro), dim3(256), 0, st, c->d_status, a);
     return hip_ok(hipGetLastError());
+}
+
+// Compute units of the current device (cached per device).
+int device_cus() {
+    static int cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cached[dev] = v;
+    }
+    return cached[dev];
 }
 
 template <int TAG, class T>
@@ -1625,6 +1651,90 @@ int64_t mehdg_batch_ctx_bytes(int p) {
         case 4: return ctx_macro_bytes<4>();
         default: return 0;
     }
+}
+
+mehdg_err mehdg_batch_ctx_residual(mehdg_ctx* const* ctxs, const mehdg_batch_slices* sl, int ng,
+                                   unsigned long long* counter, mehdg_stream stream) {
+    if (!ctxs || !sl || ng < 1 || ng > 4 || !counter) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int order[4];
+    for (int i = 0; i < ng; ++i) {
+        if (!ctxs[i] || !sl[i].v || !sl[i].vhat || !sl[i].v_old || !sl[i].R_q || !sl[i].R_v || !sl[i].R_vhat ||
+            !sl[i].entropy)
+            return MEHDG_EINVAL;
+        order[i] = i;
+    }
+    std::sort(order, order + ng, [&](int a, int b2) { return ctxs[a]->p > ctxs[b2]->p; });
+    ResidualBatch b{};
+    b.ng = ng;
+    int64_t pos = 0;
+    size_t lds = 0;
+    for (int k = 0; k < ng; ++k) {
+        mehdg_ctx* c = ctxs[order[k]];
+        const mehdg_batch_slices& s = sl[order[k]];
+        mehdg_err e = MEHDG_EINVAL;
+        size_t l = 0;
+        switch (c->p) {
+            case 1: e = ensure_block_workspace<1>(c); l = res_lds<1>(); break;
+            case 2: e = ensure_block_workspace<2>(c); l = res_lds<2>(); break;
+            case 3: e = ensure_block_workspace<3>(c); l = res_lds<3>(); break;
+            case 4: e = ensure_block_workspace<4>(c); l = res_lds<4>(); break;
+            default: break;
+        }
+        if (e != MEHDG_OK) return e;
+        lds = std::max(lds, l);
+        ResidualGroup& g = b.g[k];
+        g.p = c->p;
+        g.pr = c->dp;
+        g.v = s.v;
+        g.vhat = s.vhat;
+        g.v_old = s.v_old;
+        g.hs = c->d_h;
+        g.tab = c->d_tab;
+        g.R_q = s.R_q;
+        g.R_v = s.R_v;
+        g.R_vh = s.R_vhat;
+        g.ent = s.entropy;
+        g.scratch = c->d_scratch;
+        g.coefV = c->d_coefV;
+        g.coefF = c->d_coefF;
+        g.bc = c->d_bc;
+        g.status = c->d_status;
+        b.first[k] = pos;
+        pos += c->n_macro;
+    }
+    b.first[ng] = pos;
+    if (pos == 0) return MEHDG_OK;
+    if (!allow_lds(&k_residual_batch, lds)) return MEHDG_EHIP;
+    // as many workgroups as the CUs hold at once with this LDS (at most 8 of 256 threads)
+    const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, 163840 / (lds + 1024)));
+    const int64_t grid = std::min<int64_t>(pos, (int64_t)device_cus() * per_cu);
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+    hipLaunchKernelGGL(k_residual_batch, dim3((unsigned)grid), dim3(256), lds, st, b, counter);
+    return hip_ok(hipGetLastError());
+}
+
+mehdg_err mehdg_batch_ctx_rows(mehdg_ctx* c, const mehdg_batch_slices* s, mehdg_stream stream) {
+    if (!c || !s || !s->R_q || !s->R_v || !s->R_vhat || !s->entropy) return MEHDG_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mehdg_err e = MEHDG_EINVAL;
+    switch (c->p) {
+        case 1: e = launch_rows<1>(c, s->R_q, s->R_v, s->R_vhat, st); break;
+        case 2: e = launch_rows<2>(c, s->R_q, s->R_v, s->R_vhat, st); break;
+        case 3: e = launch_rows<3>(c, s->R_q, s->R_v, s->R_vhat, st); break;
+        case 4: e = launch_rows<4>(c, s->R_q, s->R_v, s->R_vhat, st); break;
+        default: break;
+    }
+    if (e == MEHDG_OK) {
+        int64_t sz[5];
+        (void)mehdg_sizes(c->p, sz);
+        e = launch_poison(c, PoisonArgs{{s->R_q, s->R_v, s->R_vhat, s->entropy}, {sz[3], sz[2], sz[4], 1}}, st);
+    }
+    if (e == MEHDG_OK) {
+        c->stage = 1;
+        c->have_coef = true;
+    }
+    return e;
 }
 
 mehdg_err mehdg_tile_variants(int32_t* count, int32_t* shapes) {

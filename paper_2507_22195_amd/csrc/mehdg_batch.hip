@@ -5,10 +5,14 @@
 // degree present.  The macros are ordered by degree (stable), and every
 // per-macro array of the batch is flat in that order: the macros of one
 // degree are one contiguous slice, which that degree's context reads and
-// writes in place (no copies).  Each degree runs on a stream of its own
-// (default priority), forked from the caller's stream with an event and
-// joined back with one event per degree, so the small groups overlap the
-// large ones and the whole FP64 step can be captured in one HIP graph.
+// writes in place (no copies).  The residual pass of every group that is
+// not streamed (residual, entropy production, pointwise Jacobian
+// coefficients: the same workgroup shape at every degree) is one persistent
+// launch over a queue of all their macros in descending degree.  The rest of
+// each degree's work runs on a stream of its own (default priority), forked
+// from the caller's stream with an event and joined back with one event per
+// degree, so the small groups overlap the large ones and the whole FP64 step
+// can be captured in one HIP graph.
 //
 // Device memory.  A context holds its bordered matrices and coefficients for
 // every macro it owns (about 300 MB per macro at p = 4).  When the groups
@@ -52,6 +56,8 @@ struct mehdg_batch {
     hipEvent_t fork = nullptr;
     std::vector<int32_t> h_status;
     int32_t prec = MEHDG_FP64;           // of the last condensation
+    bool residual_per_degree = false;    // the residual pass per degree instead of one persistent launch
+    unsigned long long* d_counter = nullptr;   // work-queue position of the persistent launch
 };
 
 namespace {
@@ -161,6 +167,7 @@ mehdg_err mehdg_batch_destroy(mehdg_batch* b) {
         (void)hipFree(g.d_work);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
+    (void)hipFree(b->d_counter);
     delete b;
     return MEHDG_OK;
 }
@@ -168,7 +175,8 @@ mehdg_err mehdg_batch_destroy(mehdg_batch* b) {
 mehdg_err mehdg_batch_create(const mehdg_batch_mesh* mesh, const mehdg_params* prm, mehdg_batch** out) {
     if (!out) return MEHDG_EINVAL;
     *out = nullptr;
-    if (!mesh || !prm || !mesh->p || !mesh->h || mesh->n_macro <= 0 || mesh->max_workspace_bytes < 0)
+    if (!mesh || !prm || !mesh->p || !mesh->h || mesh->n_macro <= 0 || mesh->max_workspace_bytes < 0 ||
+        mesh->residual_per_degree < 0 || mesh->residual_per_degree > 1)
         return MEHDG_EINVAL;
     const int64_t M = mesh->n_macro;
     for (int64_t i = 0; i < M; ++i) {
@@ -183,6 +191,7 @@ mehdg_err mehdg_batch_create(const mehdg_batch_mesh* mesh, const mehdg_params* p
     std::stable_sort(b->order.begin(), b->order.end(),
                      [&](int64_t a, int64_t c) { return mesh->p[a] < mesh->p[c]; });
     b->h_status.assign((size_t)M, 0);
+    b->residual_per_degree = mesh->residual_per_degree != 0;
     for (int64_t first = 0; first < M;) {
         mehdg_batch::Group g;
         g.p = mesh->p[b->order[(size_t)first]];
@@ -202,7 +211,9 @@ mehdg_err mehdg_batch_create(const mehdg_batch_mesh* mesh, const mehdg_params* p
         budget = (int64_t)(0.6 * (double)free_b);
     }
     size_waves(b->groups, budget);
-    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&b->d_counter, sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
         mehdg_batch_destroy(b);
         return MEHDG_EHIP;
     }
@@ -294,9 +305,38 @@ mehdg_err mehdg_batch_assemble_condense(mehdg_batch* b, int32_t prec, const doub
     if (prec < MEHDG_FP64 || prec > MEHDG_BF16_IR) return MEHDG_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     b->prec = prec;
+    std::vector<mehdg_batch_slices> sl(b->groups.size());
+    for (size_t gi = 0; gi < b->groups.size(); ++gi)
+        sl[gi] = mehdg_batch_slices{slice(v, b, MEHDG_KEY_V, gi), slice(vhat, b, MEHDG_KEY_VHAT, gi),
+                                    slice(v_old, b, MEHDG_KEY_V, gi), slice(R_q, b, MEHDG_KEY_Q, gi),
+                                    slice(R_v, b, MEHDG_KEY_V, gi), slice(R_vhat, b, MEHDG_KEY_VHAT, gi),
+                                    slice(entropy, b, MEHDG_KEY_ENTROPY, gi)};
+    // the residual pass of the whole groups: one persistent launch on the caller's stream
+    std::vector<char> joint(b->groups.size(), 0);
+    if (!b->residual_per_degree) {
+        std::vector<mehdg_ctx*> ctxs;
+        std::vector<mehdg_batch_slices> jsl;
+        for (size_t gi = 0; gi < b->groups.size(); ++gi)
+            if (!b->groups[gi].streamed()) {
+                ctxs.push_back(b->groups[gi].ctx);
+                jsl.push_back(sl[gi]);
+                joint[gi] = 1;
+            }
+        if (!ctxs.empty()) {
+            const mehdg_err e =
+                mehdg_batch_ctx_residual(ctxs.data(), jsl.data(), (int)ctxs.size(), b->d_counter, stream);
+            if (e != MEHDG_OK) return e;
+        }
+    }
     return fork_join(b, st, [&](size_t gi) -> mehdg_err {
         auto& g = b->groups[gi];
         mehdg_stream gs = reinterpret_cast<mehdg_stream>(g.stream);
+        if (joint[gi]) {
+            const mehdg_err e = mehdg_batch_ctx_rows(g.ctx, &sl[gi], gs);
+            if (e != MEHDG_OK) return e;
+            return mehdg_condense(g.ctx, prec, slice(Ahat, b, MEHDG_KEY_AHAT, gi), slice(bhat, b, MEHDG_KEY_BHAT, gi),
+                                  gs);
+        }
         return over_waves(g, [&](int64_t w0, int64_t) -> mehdg_err {
             mehdg_err e = mehdg_assemble(g.ctx, slice(v, b, MEHDG_KEY_V, gi, w0), slice(vhat, b, MEHDG_KEY_VHAT, gi, w0),
                                          nullptr, slice(v_old, b, MEHDG_KEY_V, gi, w0),

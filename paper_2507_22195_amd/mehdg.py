@@ -53,7 +53,8 @@ class Mesh(ctypes.Structure):
 class BatchMesh(ctypes.Structure):
     _fields_ = [("n_macro", ctypes.c_int64), ("p", ctypes.POINTER(ctypes.c_int32)),
                 ("h", ctypes.POINTER(ctypes.c_double)), ("face_bc", ctypes.POINTER(ctypes.c_uint8)),
-                ("max_workspace_bytes", ctypes.c_int64)]
+                ("max_workspace_bytes", ctypes.c_int64), ("residual_per_degree", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 BATCH_KEYS = {"v": 0, "q": 1, "vhat": 2, "entropy": 3, "Ahat": 4, "bhat": 5}

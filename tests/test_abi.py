@@ -63,10 +63,10 @@ def test_argument_errors_are_synchronous():
     handle = ctypes.c_void_p()
     deg = (ctypes.c_int32 * 2)(2, 5)
     hh = (ctypes.c_double * 6)(0.1, 0.1, 0.1, 0.1, 0.1, 0.1)
-    bm = mehdg.BatchMesh(2, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None, 0)
+    bm = mehdg.BatchMesh(2, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None, 0, 0, 0)
     assert lib.mehdg_batch_create(ctypes.byref(bm), ctypes.byref(prm), ctypes.byref(handle)) == 1
     assert handle.value is None
-    bm = mehdg.BatchMesh(0, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None, 0)
+    bm = mehdg.BatchMesh(0, deg, ctypes.cast(hh, ctypes.POINTER(ctypes.c_double)), None, 0, 0, 0)
     assert lib.mehdg_batch_create(ctypes.byref(bm), ctypes.byref(prm), ctypes.byref(handle)) == 1
     assert lib.mehdg_batch_create(None, None, None) == 1
     assert lib.mehdg_batch_destroy(None) == 1

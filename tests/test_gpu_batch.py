@@ -13,7 +13,10 @@ isothermal walls on the -z face of a third of the macros:
   forked streams) replays to the same bits;
 * with a workspace budget too small for any group, every group is streamed
   one macro per wave (the recovery assembling and factoring each wave
-  again): the same bits again, eager and graph-replayed.
+  again): the same bits again, eager and graph-replayed;
+* the residual pass of the whole groups, one persistent launch over a
+  degree-sorted queue by default, gives the same bits as one launch per
+  degree (residual_per_degree).
 """
 import numpy as np
 import pytest
@@ -156,4 +159,17 @@ def test_streamed_groups_give_the_same_bits():
         assert torch.equal(out[k], ref[k]), f"streamed batch differs in {k}"
     _graph_replays(b, args, out, ref)
     banner("  one macro per wave: eager and graph replays equal the whole-group batch")
+    b.close()
+    del out, args
+
+    # one residual launch per degree instead of the persistent one: the same bits
+    b = MixedBatch(p, h, prm, face_bc=bc, residual_per_degree=True)
+    out, args = _inputs(b, parts, dvh_parts)
+    b.step(*args)
+    torch.cuda.synchronize()
+    rc, st = b.status()
+    assert rc == 0 and not st.any()
+    for k in out:
+        assert torch.equal(out[k], ref[k]), f"per-degree residual launches differ in {k}"
+    banner("  per-degree residual launches equal the persistent one")
     b.close()
