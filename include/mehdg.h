@@ -293,6 +293,23 @@ mehdg_err mehdg_tile_variants(int32_t* count, int32_t* shapes);
 mehdg_err mehdg_set_tile(mehdg_ctx* ctx, int32_t site, int32_t variant);
 mehdg_err mehdg_get_tile(const mehdg_ctx* ctx, int32_t site, int32_t* variant);
 
+/* Depth of the delayed trailing updates of the LU of S (Sec. 6.2).  The
+ * columns of S are eliminated in outer blocks of 128, taken in groups of
+ * `depth` blocks: inside a group the update of the S rows below waits until
+ * the group's last block (each block first takes the pending update of its
+ * own columns and rows), so the trailing part of the bordered matrix is read
+ * and written once per group.  Depth 1 updates after every block; a depth of
+ * at least the number of blocks makes the factorisation left-looking.  The
+ * depth changes the time and the rounding order, never the factors beyond
+ * rounding.  A context starts with the library's default for its degree;
+ * mehdg_set_lu_depth(ctx, 0) restores it.  A new depth takes effect at the
+ * next FP64 mehdg_condense; mehdg_condense_rhs always follows the depth of
+ * the condensation whose factors it applies.  mehdg_get_lu_depth gives the
+ * depth the next condensation will use.  Host calls, no device work;
+ * MEHDG_EINVAL for depth < 0 or > 1024. */
+mehdg_err mehdg_set_lu_depth(mehdg_ctx* ctx, int32_t depth);
+mehdg_err mehdg_get_lu_depth(const mehdg_ctx* ctx, int32_t* depth);
+
 /* ---------------------------------------------------------------------------
  * Batches of macro-elements of mixed degree (p = 1..4) and boundary type in
  * one call per phase of the Newton step.

@@ -1,10 +1,12 @@
-"""Tile autotuner of the batched FP64 MFMA products of the condensation.
+"""Autotuner of the FP64 condensation: tile shapes and LU update depth.
 
 The library carries a fixed list of tile shapes for its batched products
 (``mehdg.tile_variants()``) and two call sites that take one: the trailing
 updates of the LU of S and the Schur product [Ahat | bhat] = [A' | r_hat] -
-L21 [U12 | y] (Sec. 6.2).  The choice per degree and site is compiled into
-the library from ``csrc/tile_table.hpp``; this module makes that table:
+L21 [U12 | y] (Sec. 6.2).  It also groups the outer blocks of the LU for
+delayed trailing updates (``Context.set_lu_depth``).  The choices per degree
+are compiled into the library from ``csrc/tile_table.hpp``; this module makes
+that table:
 
 * ``sweep`` times every variant at every site on the device, on the viscous
   Taylor-Green batch of each degree (16^3 macro-elements at p = 1 and 2,
@@ -14,9 +16,14 @@ the library from ``csrc/tile_table.hpp``; this module makes that table:
   assembly.  Every variant must give the same bits as variant 0 (the
   shapes add the products of one output element in the same order): the
   sweep checks a 64-bit wrap-around sum of Ahat's bit patterns against
-  variant 0's and refuses a variant that differs.
-* ``render`` turns a sweep's result into the header, the fastest variant per
-  degree and site, with every measured time in its comments.
+  variant 0's and refuses a variant that differs.  Then, with the fastest
+  variants, it times the whole condensation (the sum of its kernels' event
+  times) at each depth of ``DEPTHS`` up to the degree's block count; a depth
+  changes the rounding, so its Ahat must agree with depth 1's to 1e-12
+  (relative, Frobenius) or the depth is refused.
+* ``render`` turns a sweep's result into the header: the fastest variant per
+  degree and site and the fastest depth per degree, with every measured time
+  in its comments.
 
     python -m paper_2507_22195_amd.autotune --sweep --out sweep.json     (device)
     python -m paper_2507_22195_amd.autotune --render sweep.json          (writes the header)
@@ -37,6 +44,8 @@ from . import workloads as W
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "tile_table.hpp")
 SHAPES = {1: (16, 16, 16), 2: (16, 16, 16), 3: (16, 16, 8), 4: (4, 4, 4)}
+DEPTHS = (1, 2, 3, 4, 7, 1024)
+OB = 128          # columns per outer block of the LU of S
 
 
 def _bits_sum(t) -> int:
@@ -89,6 +98,31 @@ def sweep_degree(p: int, shape=None, reps: int = 2, log=print) -> dict:
                 f"{best:9.3f} ms  {'ok' if same else 'DIFFERENT BITS'}")
         ctx.set_tile(site, 0)
         res["sites"][site] = times
+    # LU update depth, with the fastest bit-identical variants
+    for site, times in res["sites"].items():
+        ok = {int(i): t["ms"] for i, t in times.items() if t["same_bits"]}
+        ctx.set_tile(site, min(ok, key=ok.get) if ok else 0)
+    nblk = (ctx.sz["N_V"] + OB - 1) // OB
+    depths = sorted({min(d, nblk) for d in DEPTHS})
+    res["nblk"] = nblk
+    res["depths"] = {}
+    a1 = None
+    for d in depths:
+        ctx.set_lu_depth(d)
+        best = float("inf")
+        for _ in range(reps):
+            best = min(best, sum(ms for ms, calls in run().values() if calls))
+        rc, st = ctx.status()
+        if rc:
+            raise RuntimeError(f"p={p} depth {d}: status {mehdg.ERRORS.get(rc, rc)}")
+        if a1 is None:
+            a1 = out["Ahat"].clone()
+        dev_rel = float(((out["Ahat"] - a1).norm() / a1.norm()).item())
+        ok = dev_rel < 1e-12
+        res["depths"][str(d)] = {"ms": round(best, 3), "rel_to_depth1": dev_rel, "ok": ok}
+        log(f"  p={p} depth {d:2d}: {best:9.2f} ms per condensation  (Ahat vs depth 1: {dev_rel:.1e})"
+            + ("" if ok else "  REFUSED"))
+    ctx.set_lu_depth(0)
     ctx.close()
     return res
 
@@ -105,13 +139,15 @@ def sweep(degrees=(1, 2, 3, 4), reps: int = 2, log=print) -> dict:
 
 
 def pick(res: dict) -> dict:
-    """Fastest bit-identical variant per degree and site."""
+    """Fastest bit-identical variant per degree and site, and fastest accepted depth."""
     table = {}
     for p, r in res["degrees"].items():
         table[int(p)] = {}
         for site, times in r["sites"].items():
             ok = {int(i): t["ms"] for i, t in times.items() if t["same_bits"]}
             table[int(p)][site] = min(ok, key=ok.get) if ok else 0
+        dep = {int(d): t["ms"] for d, t in r.get("depths", {}).items() if t["ok"]}
+        table[int(p)]["depth"] = min(dep, key=dep.get) if dep else 1
     return table
 
 
@@ -121,11 +157,15 @@ def render(res: dict) -> str:
     lines = [
         "// Tile variant of the batched FP64 MFMA products per degree p (row) and call",
         "// site (column: trailing update, Schur product), indices into the variant",
-        "// list of k_condense.hpp.  Written by `python -m paper_2507_22195_amd.autotune",
-        "// --render`; edit by rerunning the sweep, not by hand.",
+        "// list of k_condense.hpp, and outer blocks per group of delayed trailing",
+        "// updates of the LU of S per degree.  Written by `python -m",
+        "// paper_2507_22195_amd.autotune --render`; edit by rerunning the sweep, not",
+        "// by hand.",
         "//",
         f"// sweep on {res['device']}: milliseconds per condensation spent at the site,",
-        "// best of the repetitions, viscous Taylor-Green batch of each degree",
+        "// best of the repetitions, viscous Taylor-Green batch of each degree; then,",
+        "// with the fastest variants, milliseconds per condensation (all its kernels)",
+        "// at each depth",
     ]
     for p, r in sorted(res["degrees"].items()):
         lines.append(f"//   p = {p}, {r['n_macro']} macro-elements ({'x'.join(map(str, r['shape']))}):")
@@ -135,6 +175,10 @@ def render(res: dict) -> str:
                 v = var[int(i)]
                 cells.append(f"{i}:{v['TM']}x{v['TN']}/{v['KC']} {t['ms']:.2f}" + ("" if t["same_bits"] else "!"))
             lines.append(f"//     {site:6s} " + ", ".join(cells))
+        if r.get("depths"):
+            cells = [f"{d}:{t['ms']:.1f}" + ("" if t["ok"] else "!")
+                     for d, t in sorted(r["depths"].items(), key=lambda kv: int(kv[0]))]
+            lines.append(f"//     depth  ({r['nblk']} blocks) " + ", ".join(cells))
     lines += ["#pragma once", "", "namespace mehdg {", "constexpr int kTileTable[5][2] = {",
               "    {0, 0},   // (unused)"]
     for p in (1, 2, 3, 4):
@@ -143,7 +187,12 @@ def render(res: dict) -> str:
             lines.append(f"    {{0, 0}},   // p = {p} (not swept)")
         else:
             lines.append(f"    {{{row['update']}, {row['schur']}}},   // p = {p}")
-    lines += ["};", "}  // namespace mehdg", ""]
+    lines += ["};", "constexpr int kLuDepth[5] = {1"]
+    for p in (1, 2, 3, 4):
+        row = table.get(p)
+        lines[-1] += f", {row['depth'] if row else 1}"
+    lines[-1] += "};   // (unused), p = 1, 2, 3, 4"
+    lines += ["}  // namespace mehdg", ""]
     return "\n".join(lines)
 
 

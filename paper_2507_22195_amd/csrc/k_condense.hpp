@@ -24,6 +24,16 @@
 //               block, the second panel's columns after the first panel;
 //               after the block, the S rows right of it (S and border
 //               columns) with K = 128.
+// Delayed trailing updates: the outer blocks go in groups of G (the depth;
+// G = 1 updates after every block, G >= the block count is left-looking).
+// A block whose group has earlier blocks first takes their pending update
+// on its own columns (k_gemm, K = the group's earlier columns), is factored
+// as above, moves the earlier blocks' multipliers by its interchange
+// (k_perm_rows, so that their rows stay in step with the rows they update),
+// and k_tri subtracts their pending product from its U rows before the
+// triangular solve.  After the last block of a group one k_gemm updates the
+// S rows below with K = the group's width, so the trailing matrix is read and
+// written once per group instead of once per block.
 // The X rows take no part in the factorisation of S.  Afterwards, panel by
 // panel, k_trsm_x forms L21 = X U^-1 left-looking,
 //   L21[:, q] = (X[:, q] - L21[:, <q] U[<q, q]) U_qq^-1,
@@ -927,7 +937,12 @@ __device__ __forceinline__ void zero_acc(v4d acc[2][2]) {
 // In-place triangular applications on MFMA after a panel or an outer block:
 //   tiles [0, ct):       U_top[:, c-tile] <- L^-1 (P B)_top[:, c-tile] for the
 //                        columns [c_lo, c_hi); L^-1 is w x w, the top rows are
-//                        [kb0, kb0+w) and P the composed interchange in perm
+//                        [kb0, kb0+w) and P the composed interchange in perm.
+//                        With DELAYED (kpre > 0) the earlier blocks of the group have not
+//                        updated these columns yet: the tile forms
+//                        T = (P B)_top - L[top, kb0-kpre : kb0] U[kb0-kpre : kb0, c-tile]
+//                        (their multipliers already in the top rows' order),
+//                        writes it to the top rows and solves U_top = L^-1 T
 //   tiles [ct, ct+rt):   L21[r-tile, :] <- X_panel[r-tile, :] U_kk^-1 for the
 //                        X rows and the panel columns [kp, kp+np)
 // Each workgroup reads everything it overwrites before writing it.
@@ -938,9 +953,10 @@ struct TriArgs {
     int kp, np;          // panel whose X columns become L21
     int uoff;            // that panel's U_kk^-1 (leading dimension NB) in the workspace
     int ct, rt;          // column tiles, X row tiles
+    int kpre;            // columns of the group's earlier blocks whose update is pending (0: none)
 };
 
-template <int P>
+template <int P, bool DELAYED>
 __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __restrict__ tri,
                                                   const int32_t* __restrict__ perm, TriArgs a, int64_t n_macro) {
     using BD = Bdims<P>;
@@ -964,16 +980,54 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
         const int nd = pm[3 * OB];
         // rows below the block that change read their new values before anything is written
         double mvr[MV];
+        if constexpr (DELAYED) {
+            const int kg = a.kb0 - a.kpre;
+            tile_mma<true>(Bm + kg, ld, Bm + (int64_t)kg * ld, ld, a.kpre, a.kb0, cc, a.kb0 + a.w, a.c_hi, acc,
+                           sm);
 #pragma unroll
-        for (int i = 0; i < MV; ++i) {
-            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
-            mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
-        }
-        tile_mma_gather(Ti + a.loff, a.ldl, Bm, ld, pm, a.w, 0, cc, a.w, a.c_hi, acc, sm);
+            for (int i = 0; i < MV; ++i) {
+                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+                mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
+            }
 #pragma unroll
-        for (int i = 0; i < MV; ++i) {
-            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
-            if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
+                        if (r < a.w && c < a.c_hi) acc[bi][bj][q] += Bm[(int64_t)pm[r] * ld + c];
+                    }
+            __syncthreads();                 // every read of the rows this tile rewrites is done
+#pragma unroll
+            for (int i = 0; i < MV; ++i) {
+                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+                if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
+                        if (r < a.w && c < a.c_hi) Bm[(int64_t)(a.kb0 + r) * ld + c] = acc[bi][bj][q];
+                    }
+            __syncthreads();
+            zero_acc(acc);
+            tile_mma<false>(Ti + a.loff, a.ldl, Bm + (int64_t)a.kb0 * ld, ld, a.w, 0, cc, a.w, a.c_hi, acc, sm);
+        } else {
+#pragma unroll
+            for (int i = 0; i < MV; ++i) {
+                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+                mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
+            }
+            tile_mma_gather(Ti + a.loff, a.ldl, Bm, ld, pm, a.w, 0, cc, a.w, a.c_hi, acc, sm);
+#pragma unroll
+            for (int i = 0; i < MV; ++i) {
+                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+                if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
+            }
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
@@ -996,6 +1050,44 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
                     const int r = tile_row(rr, bi, q), c = tile_col(0, bj);
                     if (r < ROWS && c < a.np) Bm[(int64_t)r * ld + a.kp + c] = acc[bi][bj][q];
                 }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The composed row interchange of the current outer block (perm) applied to
+// the columns [c_lo, c_hi) of the S rows [kb0, NV): position kb0+i takes row
+// perm[i] (i < w) and each displaced row below the block takes its source.
+// It moves the multipliers of the group's earlier blocks, whose update of
+// these rows is still pending.  Per 64-column tile: every read, then every write.
+template <int P>
+__global__ void __launch_bounds__(GTHREADS) k_perm_rows(double* B, const int32_t* __restrict__ perm, int kb0, int w,
+                                                        int c_lo, int c_hi, int ct, int64_t n_macro) {
+    using BD = Bdims<P>;
+    using PN = Panel<P>;
+    constexpr int OB = PN::OB, ld = BD::ld;
+    constexpr int MV = 2 * OB * GT / GTHREADS;   // moved elements per thread
+    __shared__ int pm[3 * OB + 1];
+    int64_t m;
+    int tile;
+    xcd_tile(ct, m, tile);
+    if (m >= n_macro) return;
+    double* Bm = B + m * BD::per_macro;
+    for (int i = threadIdx.x; i < 3 * OB + 1; i += GTHREADS) pm[i] = perm[m * PN::PERM + i];
+    __syncthreads();
+    const int nr = w + pm[3 * OB];
+    const int cc = c_lo + tile * GT;
+    double v[MV];
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+        const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+        v[i] = 0.0;
+        if (q < nr && c < c_hi) v[i] = Bm[(int64_t)(q < w ? pm[q] : pm[2 * OB + q - w]) * ld + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+        const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+        if (q < nr && c < c_hi) Bm[(int64_t)(q < w ? kb0 + q : pm[OB + q - w]) * ld + c] = v[i];
     }
 }
 

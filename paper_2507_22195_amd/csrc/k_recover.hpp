@@ -221,10 +221,11 @@ __global__ void __launch_bounds__(1024) k_recover_z(const double* __restrict__ B
 // bhat = r_hat - L21 y = r_hat - X S^-1 r_V (eq. R5b); y replaces the
 // right-hand-side column, so that the next k_recover gives
 // dV = S^-1 (r_V + Y dVhat).  The multipliers of an outer block are stored in
-// the row order of that block's elimination (later blocks never move the
-// columns left of them), so the forward substitution replays the block's
-// interchanges (LAPACK order) right before the block, exactly as the
-// condensation transformed its own right-hand-side column.  Per 64-column
+// the row order after the last block of its group of delayed updates (the
+// condensation moves them with the interchanges of the later blocks of the
+// group, never with those of later groups), so the forward substitution
+// replays the interchanges of a whole group (LAPACK order) right before the
+// group's columns: width = the group's columns.  Per 64-column
 // chunk: wave 0 solves the unit-lower triangle (lane j holds row j), then all
 // waves update the rows below with coalesced row reads.
 template <int P>
@@ -236,11 +237,10 @@ struct FsLds {
 template <int P>
 __global__ void __launch_bounds__(1024) k_fsolve(double* __restrict__ B, const int32_t* __restrict__ ipiv,
                                                 const double* __restrict__ r_v, const double* __restrict__ r_h,
-                                                double* __restrict__ bhat) {
+                                                double* __restrict__ bhat, int width) {
     using D = Dims<P>;
     using BD = Bdims<P>;
-    using PN = Panel<P>;
-    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld, OB = PN::OB;
+    constexpr int NV = D::NV, NH = D::NH, ld = BD::ld;
     constexpr int RB = 8;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     FsLds<P>& L = *reinterpret_cast<FsLds<P>*>(smem_raw);
@@ -250,8 +250,8 @@ __global__ void __launch_bounds__(1024) k_fsolve(double* __restrict__ B, const i
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     for (int i = tid; i < NV; i += blockDim.x) L.z[i] = r_v[m * NV + i];
     __syncthreads();
-    for (int kb0 = 0; kb0 < NV; kb0 += OB) {
-        const int w = (NV - kb0) < OB ? (NV - kb0) : OB;
+    for (int kb0 = 0; kb0 < NV; kb0 += width) {
+        const int w = (NV - kb0) < width ? (NV - kb0) : width;
         if (tid == 0) {
             for (int j = kb0; j < kb0 + w; ++j) {
                 const int p = pv[j];

@@ -31,6 +31,8 @@ struct mehdg_ctx {
     int p = 0;
     int64_t n_macro = 0;
     int tile[MEHDG_NTILE_SITES] = {};   // product tile variant per call site
+    int lu_depth = 0;                   // outer blocks per group of delayed updates (0: the degree's default)
+    int lu_width = 0;                   // columns per group of the last condensation (0: the default's)
     int inner_prec = MEHDG_FP64;        // factors read by FGMRES's inner iterations
     float* d_mf32 = nullptr;            // their single-precision copies
     int64_t cond_count = 0, mf32_count = -1;   // FP64 condensations; the one the copies hold
@@ -343,6 +345,30 @@ mehdg_err launch_update(mehdg_ctx* c, int kb0, int K, int o_r, int o_c, int rows
     return launch_gemm<0>(c, g, MEHDG_PROF_UPDATE, st);
 }
 
+// Outer blocks per group of delayed trailing updates of the LU of S, by
+// degree from the tuned table (other element families: 1).
+constexpr int lu_depth_default(int p) { return p >= 1 && p <= 4 ? kLuDepth[p] : 1; }
+
+// Columns per group of delayed trailing updates: depth outer blocks (the
+// context's, else the degree's default).
+template <int P>
+int lu_group_width(const mehdg_ctx* c) {
+    int depth = c->lu_depth > 0 ? c->lu_depth : lu_depth_default(P);
+    const int nblk = (Dims<P>::NV + Panel<P>::OB - 1) / Panel<P>::OB;
+    if (depth > nblk) depth = nblk;
+    return depth * Panel<P>::OB;
+}
+
+template <int P>
+mehdg_err launch_perm_rows(mehdg_ctx* c, int kb0, int w, int c_lo, int c_hi, hipStream_t st) {
+    const int ct = (c_hi - c_lo + GT - 1) / GT;
+    if (ct <= 0) return MEHDG_OK;
+    Timed t(c, MEHDG_PROF_ROWBLOCK, st);
+    hipLaunchKernelGGL(k_perm_rows<P>, dim3(xcd_grid(ct, c->n_macro)), dim3(GTHREADS), 0, st, c->d_B, c->d_perm,
+                       kb0, w, c_lo, c_hi, ct, (int64_t)c->n_macro);
+    return hip_ok(hipGetLastError());
+}
+
 template <int P>
 mehdg_err launch_tri(mehdg_ctx* c, TriArgs a, hipStream_t st) {
     using D = Dims<P>;
@@ -350,8 +376,12 @@ mehdg_err launch_tri(mehdg_ctx* c, TriArgs a, hipStream_t st) {
     a.rt = a.np > 0 ? (D::NH + GM - 1) / GM : 0;
     if (a.ct + a.rt == 0) return MEHDG_OK;
     Timed t(c, MEHDG_PROF_ROWBLOCK, st);
-    hipLaunchKernelGGL(k_tri<P>, dim3(xcd_grid(a.ct + a.rt, c->n_macro)), dim3(GTHREADS), 0, st, c->d_B, c->d_tri,
-                       c->d_perm, a, (int64_t)c->n_macro);
+    if (a.kpre > 0)
+        hipLaunchKernelGGL((k_tri<P, true>), dim3(xcd_grid(a.ct + a.rt, c->n_macro)), dim3(GTHREADS), 0, st, c->d_B,
+                           c->d_tri, c->d_perm, a, (int64_t)c->n_macro);
+    else
+        hipLaunchKernelGGL((k_tri<P, false>), dim3(xcd_grid(a.ct + a.rt, c->n_macro)), dim3(GTHREADS), 0, st,
+                           c->d_B, c->d_tri, c->d_perm, a, (int64_t)c->n_macro);
     return hip_ok(hipGetLastError());
 }
 
@@ -376,8 +406,18 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
                                c->d_tri, c->d_status);
         return hip_ok(hipGetLastError());
     };
+    // outer blocks in groups of delayed trailing updates, gw columns each
+    const int gw = lu_group_width<P>(c);
+    c->lu_width = gw;
+    constexpr int ncol = NV + NH + 1;
     for (int kb0 = 0; kb0 < NV; kb0 += PN::OB) {
         const int w = (NV - kb0) < PN::OB ? (NV - kb0) : PN::OB;
+        const int kg = kb0 - kb0 % gw;               // first column of the group
+        const int kpre = kb0 - kg;                   // columns of its earlier blocks
+        const bool group_end = kb0 + w - kg >= gw || kb0 + w >= NV;
+        // the earlier blocks' pending update of this block's columns
+        if (kpre > 0 && (e = launch_update<P>(c, kg, kpre, kb0, kb0, NV - kb0, w, NV - kb0, w, st)) != MEHDG_OK)
+            return e;
         if ((e = panel(kb0, kb0)) != MEHDG_OK) return e;
         TriArgs a{};
         a.kb0 = kb0;
@@ -394,26 +434,26 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
             if ((e = launch_update<P>(c, kb0, NB, o, o, NV - o, w - NB, NV - o, w - NB, st)) != MEHDG_OK)
                 return e;
             if ((e = panel(kb0 + NB, kb0)) != MEHDG_OK) return e;
-            // the whole block: U rows right of it
-            a.w = w;
             a.loff = PN::LINVW;
             a.ldl = PN::OB;
-            a.c_lo = kb0 + w;
-            a.c_hi = ld;
-            if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
         } else {
-            a.w = w;
             a.loff = PN::LINV1;
             a.ldl = NB;
-            a.c_lo = kb0 + w;
-            a.c_hi = ld;
-            if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
         }
-        // trailing update of the S rows (S and border columns)
-        const int o = kb0 + w;
-        if ((e = launch_update<P>(c, kb0, w, o, o, NV - o, NV + NH + 1 - o, NV - o, NV + NH + 1 - o, st)) !=
-            MEHDG_OK)
-            return e;
+        // the earlier blocks' multipliers follow this block's interchange
+        if (kpre > 0 && (e = launch_perm_rows<P>(c, kb0, w, kg, kb0, st)) != MEHDG_OK) return e;
+        // the whole block: U rows right of it (after the group's pending update of them)
+        a.w = w;
+        a.c_lo = kb0 + w;
+        a.c_hi = ld;
+        a.kpre = kpre;
+        if ((e = launch_tri<P>(c, a, st)) != MEHDG_OK) return e;
+        // after the group: trailing update of the S rows (S and border columns)
+        if (group_end) {
+            const int o = kb0 + w;
+            if ((e = launch_update<P>(c, kg, o - kg, o, o, NV - o, ncol - o, NV - o, ncol - o, st)) != MEHDG_OK)
+                return e;
+        }
     }
     // L21 of the X rows, panel by panel
     {
@@ -727,8 +767,9 @@ mehdg_err launch_fsolve(mehdg_ctx* c, const double* r_v, const double* r_h, doub
     const size_t lds = sizeof(FsLds<P>);
     if (!allow_lds(&k_fsolve<P>, lds)) return MEHDG_EHIP;
     Timed t(c, MEHDG_PROF_FSOLVE, st);
+    const int width = c->lu_width > 0 ? c->lu_width : lu_group_width<P>(c);
     hipLaunchKernelGGL(k_fsolve<P>, dim3((unsigned)c->n_macro), dim3(1024), lds, st, c->d_B, c->d_ipiv, r_v, r_h,
-                       bhat);
+                       bhat, width);
     return hip_ok(hipGetLastError());
 }
 
@@ -1762,6 +1803,26 @@ mehdg_err mehdg_set_tile(mehdg_ctx* c, int32_t site, int32_t variant) {
 mehdg_err mehdg_get_tile(const mehdg_ctx* c, int32_t site, int32_t* variant) {
     if (!c || !variant || site < 0 || site >= MEHDG_NTILE_SITES) return MEHDG_EINVAL;
     *variant = c->tile[site];
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_set_lu_depth(mehdg_ctx* c, int32_t depth) {
+    if (!c || depth < 0 || depth > 1024) return MEHDG_EINVAL;
+    c->lu_depth = depth;
+    return MEHDG_OK;
+}
+
+mehdg_err mehdg_get_lu_depth(const mehdg_ctx* c, int32_t* depth) {
+    if (!c || !depth) return MEHDG_EINVAL;
+    int w = 0;
+    switch (c->p) {
+        case 1: w = lu_group_width<1>(c); break;
+        case 2: w = lu_group_width<2>(c); break;
+        case 3: w = lu_group_width<3>(c); break;
+        case 4: w = lu_group_width<4>(c); break;
+        default: return MEHDG_EINVAL;
+    }
+    *depth = w / Panel<1>::OB;
     return MEHDG_OK;
 }
 

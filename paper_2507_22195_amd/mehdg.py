@@ -133,7 +133,10 @@ def load(path: str = LIB_PATH):
     lib.mehdg_tile_variants.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     lib.mehdg_set_tile.argtypes = [vp, i32, i32]
     lib.mehdg_get_tile.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
-    for name in ("mehdg_tile_variants", "mehdg_set_tile", "mehdg_get_tile"):
+    lib.mehdg_set_lu_depth.argtypes = [vp, i32]
+    lib.mehdg_get_lu_depth.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    for name in ("mehdg_tile_variants", "mehdg_set_tile", "mehdg_get_tile", "mehdg_set_lu_depth",
+                 "mehdg_get_lu_depth"):
         getattr(lib, name).restype = ctypes.c_int
     lib.mehdg_tet_sizes.argtypes = [i32, ctypes.POINTER(ctypes.c_int64)]
     lib.mehdg_tet_create.argtypes = [ctypes.POINTER(TetMesh), ctypes.POINTER(Params), ctypes.POINTER(vp)]
@@ -522,6 +525,19 @@ class Context:
         rc = load().mehdg_get_tile(self._handle, TILE_SITES[site], ctypes.byref(out))
         if rc:
             raise MehdgError(rc, "mehdg_get_tile")
+        return int(out.value)
+
+    def set_lu_depth(self, depth: int):
+        """Outer blocks per group of delayed trailing updates of the LU of S (0 = the degree's default)."""
+        rc = load().mehdg_set_lu_depth(self._handle, int(depth))
+        if rc:
+            raise MehdgError(rc, "mehdg_set_lu_depth")
+
+    def get_lu_depth(self) -> int:
+        out = ctypes.c_int32()
+        rc = load().mehdg_get_lu_depth(self._handle, ctypes.byref(out))
+        if rc:
+            raise MehdgError(rc, "mehdg_get_lu_depth")
         return int(out.value)
 
     def profile(self, enable: bool):

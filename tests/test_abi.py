@@ -85,6 +85,8 @@ def test_argument_errors_are_synchronous():
     assert lib.mehdg_set_tile(None, 0, 0) == 1
     assert lib.mehdg_trace_set_inner_precision(None, 0) == 1
     assert lib.mehdg_get_tile(None, 0, ctypes.byref(n)) == 1
+    assert lib.mehdg_set_lu_depth(None, 1) == 1
+    assert lib.mehdg_get_lu_depth(None, ctypes.byref(n)) == 1
 
 
 def test_wall_flags_are_checked_before_any_device_work():
