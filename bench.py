@@ -28,16 +28,20 @@ FP64_MFMA_PEAK_TFS = 78.6
 FP64_VALU_PEAK_TFS = 78.6
 
 
-def kernel_models(p, n_macro, NV, NH, viscous):
+def kernel_models(p, n_macro, NV, NH, viscous, depth=1):
     """Algorithmic work per step of each kernel slot: (kind, flops or bytes).
 
     Follows the blocking of the condensation: outer blocks of OB = 128
-    columns made of two 64-column panels; inside a block the second panel's
-    columns are updated after the first panel (K = 64), after the block the
-    S rows right of it (K = block width); the X rows are solved afterwards,
-    panel by panel (L21[:, q] = (X[:, q] - L21[:, <q] U[<q, q]) U_qq^-1), and
-    at the end Ahat = A' - L21 U12 with K = N_V.  Flops count useful
-    products only (no padding of tiles or of the triangular inverses).
+    columns made of two 64-column panels, in groups of `depth` blocks whose
+    trailing update is delayed to the group's last block; inside a block the
+    second panel's columns are updated after the first panel (K = 64); a
+    later block of a group first takes the group's pending update of its own
+    columns (update slot) and of its U rows (with the triangular solve, in
+    the row-block slot); after the group the S rows right of it (K = the
+    group's width); the X rows are solved afterwards, panel by panel
+    (L21[:, q] = (X[:, q] - L21[:, <q] U[<q, q]) U_qq^-1), and at the end
+    Ahat = A' - L21 U12 with K = N_V.  Flops count useful products only (no
+    padding of tiles or of the triangular inverses).
     """
     from paper_2507_22195_amd.workloads import sizes
     s = sizes(p)
@@ -46,8 +50,13 @@ def kernel_models(p, n_macro, NV, NH, viscous):
     ld = (COLS + 7) // 8 * 8
     NB, OB = 64, 128
     upd = tri = panel = trsm = 0.0
+    gw = max(1, depth) * OB
     for kb0 in range(0, NV, OB):
         w = min(OB, NV - kb0)
+        kg = kb0 - kb0 % gw
+        kpre = kb0 - kg
+        group_end = kb0 + w - kg >= gw or kb0 + w >= NV
+        upd += 2.0 * kpre * (NV - kb0) * w                   # the group's pending update of this block's columns
         panels = [(kb0, min(NB, w))] + ([(kb0 + NB, w - NB)] if w > NB else [])
         for kb, nb in panels:
             # panel: rank-1 updates inside the panel columns, then the two inverses
@@ -57,8 +66,9 @@ def kernel_models(p, n_macro, NV, NH, viscous):
             upd += 2.0 * NB * (NV - o) * (w - NB)            # second panel's columns, S rows
             tri += NB * NB * (w - NB)                        # its U rows (unit-lower solve)
         o = kb0 + w
-        tri += w * w * (COLS - o)                            # U rows right of the block
-        upd += 2.0 * w * (NV - o) * (COLS - o)               # S rows right of the block
+        tri += w * w * (COLS - o) + 2.0 * w * kpre * (COLS - o)   # U rows right of the block
+        if group_end:
+            upd += 2.0 * (o - kg) * (NV - o) * (COLS - o)    # S rows right of the group
     for kq in range(0, NV, NB):
         nbq = min(NB, NV - kq)
         trsm += 2.0 * NH * nbq * kq + NH * nbq * nbq          # X rows: long-K product + U_qq^-1
@@ -676,7 +686,7 @@ def main():
     sz = ctx.sz
     NV, NH = sz["N_V"], sz["N_VH"]
 
-    models = kernel_models(w.p, M, NV, NH, w.params["viscous"])
+    models = kernel_models(w.p, M, NV, NH, w.params["viscous"], depth=ctx.get_lu_depth())
     kernels = {}
     for name, (ms, calls) in prof.items():
         if calls == 0:
