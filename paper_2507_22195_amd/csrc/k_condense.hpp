@@ -933,6 +933,133 @@ __device__ __forceinline__ void zero_acc(v4d acc[2][2]) {
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
 }
 
+// Tile shapes of the batched product (the sweep of the tile autotuner picks
+// one per degree and call site): WM x WN waves, each owning BI x BJ blocks of
+// 16 x 16, so a workgroup of 64 WM WN threads computes a TM x TN tile with
+// TM = 16 WM BI, TN = 16 WN BJ; K is staged through LDS in chunks of KC, and
+// OCC waves per SIMD are asked of the register allocator.
+// Every shape adds the products of one output element in the same order (K
+// ascending, four at a time per MFMA), so all shapes give the same bits.
+template <int WM_, int WN_, int BI_, int BJ_, int KC_, int OCC_>
+struct GTile {
+    static constexpr int WM = WM_, WN = WN_, BI = BI_, BJ = BJ_, KC = KC_, OCC = OCC_;
+    static constexpr int TM = 16 * WM * BI, TN = 16 * WN * BJ, NT = 64 * WM * WN;
+    static constexpr int LA = TM * KC / NT, LB = KC * TN / NT;   // staged elements per thread
+    static_assert(LA * NT == TM * KC && LB * NT == KC * TN, "tile does not divide among the threads");
+};
+
+template <class T>
+struct GTileSmem {
+    double As[2][T::TM][T::KC + 1];
+    double Bs[2][T::KC][T::TN + 1];
+};
+
+// The variants the library carries, in the order of their index.
+#define MEHDG_GEMM_VARIANTS(X) \
+    X(0, 4, 2, 2, 2, 16, 4)    \
+    X(1, 4, 2, 2, 4, 16, 2)    \
+    X(2, 2, 4, 4, 2, 16, 2)    \
+    X(3, 4, 2, 2, 2, 32, 2)    \
+    X(4, 2, 2, 2, 2, 16, 3)    \
+    X(5, 4, 4, 2, 2, 16, 2)    \
+    X(6, 2, 2, 2, 4, 16, 2)
+constexpr int kGemmVariants = 7;
+
+// acc += A[r0.., 0..K) * Bt[0..K, c0..) on a T tile.  The operands are read
+// with buffer loads: each element a thread stages keeps one byte offset for
+// the whole K loop, and each chunk moves the buffer's base (scalar work), so
+// the loop spends no vector instructions on addresses or bounds.  Rows of A
+// beyond the product's rows and columns of Bt beyond its columns are read
+// as they stand (they only feed outputs that are never stored) and reads past
+// a_bytes / b_bytes give 0; only the last chunk, when K is not a multiple of
+// KC, zeroes the terms k >= K on both sides.
+template <class T>
+__device__ __forceinline__ void tile_mma_t(const double* A, int lda, int64_t a_bytes, const double* Bt, int ldb,
+                                           int64_t b_bytes, int K, int r0, int c0, v4d (&acc)[T::BI][T::BJ],
+                                           GTileSmem<T>& sm) {
+    constexpr int KC = T::KC, TN = T::TN, NT = T::NT;
+    constexpr int RA = NT / KC, RB = NT / TN;     // rows of A / of Bt between a thread's staged elements
+    static_assert(RA * KC == NT && RB * TN == NT, "staging does not tile the chunk");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave / T::WN, wc = wave % T::WN;
+    const int ak = tid % KC, bk = tid / TN;
+    int va[T::LA], vb[T::LB];
+#pragma unroll
+    for (int i = 0; i < T::LA; ++i) va[i] = ((r0 + tid / KC + i * RA) * lda + ak) * 8;
+#pragma unroll
+    for (int i = 0; i < T::LB; ++i) vb[i] = ((bk + i * RB) * ldb + c0 + tid % TN) * 8;
+    double ra[T::LA], rb[T::LB];
+    auto clamp32 = [](int64_t b) { return (uint32_t)(b < 0 ? 0 : (b > 0xffffffffll ? 0xffffffffll : b)); };
+    const uint32_t na = clamp32(a_bytes), nb = clamp32(b_bytes);
+    const uint32_t sta = 8u * KC, stb = 8u * KC * (uint32_t)ldb;   // bytes per chunk
+    // descriptors are wave-uniform: readfirstlane keeps them in scalar registers
+    auto rsrc = [](const double* p, uint32_t n) {
+        const uint64_t a = (uint64_t)p;
+        const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+        const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(lo | (hi << 32)), (short)0,
+                                                 __builtin_amdgcn_readfirstlane((int)n), 0x00020000);
+    };
+    auto load = [&](int k0) {
+        const uint32_t ch = (uint32_t)k0 / KC;
+        const auto sa = rsrc(A + k0, na > ch * sta ? na - ch * sta : 0u);
+        const auto sb = rsrc(Bt + (int64_t)k0 * ldb, nb > ch * stb ? nb - ch * stb : 0u);
+#pragma unroll
+        for (int i = 0; i < T::LA; ++i)
+            ra[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, va[i], 0, 0));
+#pragma unroll
+        for (int i = 0; i < T::LB; ++i)
+            rb[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, vb[i], 0, 0));
+        if (k0 + KC > K) {                          // the last, partial chunk
+#pragma unroll
+            for (int i = 0; i < T::LA; ++i)
+                if (k0 + ak >= K) ra[i] = 0.0;
+#pragma unroll
+            for (int i = 0; i < T::LB; ++i)
+                if (k0 + bk + i * RB >= K) rb[i] = 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < T::LA; ++i) {
+            const int e = tid + NT * i;
+            sm.As[buf][e / KC][e % KC] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < T::LB; ++i) {
+            const int e = tid + NT * i;
+            sm.Bs[buf][e / TN][e % TN] = rb[i];
+        }
+    };
+    const int nchunk = (K + KC - 1) / KC;
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nchunk) load((ch + 1) * KC);
+#pragma unroll
+        for (int ks = 0; ks < KC; ks += 4) {
+            const int kq = ks + (lane >> 4);
+            double a[T::BI], b[T::BJ];
+#pragma unroll
+            for (int bi = 0; bi < T::BI; ++bi) a[bi] = sm.As[buf][(wr * T::BI + bi) * 16 + (lane & 15)][kq];
+#pragma unroll
+            for (int bj = 0; bj < T::BJ; ++bj) b[bj] = sm.Bs[buf][kq][(wc * T::BJ + bj) * 16 + (lane & 15)];
+#pragma unroll
+            for (int bi = 0; bi < T::BI; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < T::BJ; ++bj)
+                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        }
+        if (ch + 1 < nchunk) stash(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// The fixed 128 x 64 tile of the triangular kernels is variant 0's shape.
+using GTri = GTile<4, 2, 2, 2, 16, 4>;
+
 // ---------------------------------------------------------------------------
 // In-place triangular applications on MFMA after a panel or an outer block:
 //   tiles [0, ct):       U_top[:, c-tile] <- L^-1 (P B)_top[:, c-tile] for the
@@ -965,6 +1092,8 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
     constexpr int MV = OB * GT / GTHREADS;       // displaced-row elements per thread
     __shared__ TileSmem sm;
     __shared__ int pm[3 * OB + 1];
+    static_assert(sizeof(TileSmem) == sizeof(GTileSmem<GTri>), "the two staging layouts coincide");
+    GTileSmem<GTri>& gsm = *reinterpret_cast<GTileSmem<GTri>*>(&sm);
     int64_t m;
     int tile;
     xcd_tile(a.ct + a.rt, m, tile);
@@ -982,8 +1111,8 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
         double mvr[MV];
         if constexpr (DELAYED) {
             const int kg = a.kb0 - a.kpre;
-            tile_mma<true>(Bm + kg, ld, Bm + (int64_t)kg * ld, ld, a.kpre, a.kb0, cc, a.kb0 + a.w, a.c_hi, acc,
-                           sm);
+            tile_mma_t<GTri>(Bm + kg, ld, ((int64_t)BD::per_macro - kg) * 8, Bm + (int64_t)kg * ld, ld,
+                             ((int64_t)BD::per_macro - (int64_t)kg * ld) * 8, a.kpre, a.kb0, cc, acc, gsm);
 #pragma unroll
             for (int i = 0; i < MV; ++i) {
                 const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
@@ -996,7 +1125,7 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
-                        if (r < a.w && c < a.c_hi) acc[bi][bj][q] += Bm[(int64_t)pm[r] * ld + c];
+                        if (r < a.w && c < a.c_hi) acc[bi][bj][q] = Bm[(int64_t)pm[r] * ld + c] - acc[bi][bj][q];
                     }
             __syncthreads();                 // every read of the rows this tile rewrites is done
 #pragma unroll
@@ -1015,7 +1144,8 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
                     }
             __syncthreads();
             zero_acc(acc);
-            tile_mma<false>(Ti + a.loff, a.ldl, Bm + (int64_t)a.kb0 * ld, ld, a.w, 0, cc, a.w, a.c_hi, acc, sm);
+            tile_mma_t<GTri>(Ti + a.loff, a.ldl, ((int64_t)PN::TRI - a.loff) * 8, Bm + (int64_t)a.kb0 * ld, ld,
+                             ((int64_t)BD::per_macro - (int64_t)a.kb0 * ld) * 8, a.w, 0, cc, acc, gsm);
         } else {
 #pragma unroll
             for (int i = 0; i < MV; ++i) {
@@ -1103,7 +1233,7 @@ __global__ void __launch_bounds__(GTHREADS, 4) k_trsm_x(double* B, const double*
     using BD = Bdims<P>;
     using PN = Panel<P>;
     constexpr int NB = PN::NB, NV = PN::NV, ld = BD::ld, ROWS = BD::rows;
-    __shared__ TileSmem sm;
+    __shared__ GTileSmem<GTri> sm;
     int64_t m;
     int tile;
     xcd_tile((ROWS - NV + GM - 1) / GM, m, tile);
@@ -1123,7 +1253,9 @@ __global__ void __launch_bounds__(GTHREADS, 4) k_trsm_x(double* B, const double*
             }
     v4d acc[2][2];
     zero_acc(acc);
-    if (kq > 0) tile_mma<true>(Bm, ld, Bm + kq, ld, kq, rr, 0, ROWS, nbq, acc, sm);
+    if (kq > 0)
+        tile_mma_t<GTri>(Bm, ld, (int64_t)BD::per_macro * 8, Bm + kq, ld, ((int64_t)BD::per_macro - kq) * 8, kq, rr,
+                         0, acc, sm);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1131,12 +1263,13 @@ __global__ void __launch_bounds__(GTHREADS, 4) k_trsm_x(double* B, const double*
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
                 const int r = tile_row(rr, bi, qq), c = tile_col(0, bj);
-                if (r < ROWS && c < nbq) Bm[(int64_t)r * ld + kq + c] = cr[bi][bj][qq] + acc[bi][bj][qq];
+                if (r < ROWS && c < nbq) Bm[(int64_t)r * ld + kq + c] = cr[bi][bj][qq] - acc[bi][bj][qq];
             }
     __syncthreads();
     zero_acc(acc);
     const double* Ui = tri + m * PN::TRI + PN::UINV + (int64_t)q * NB * NB;
-    tile_mma<false>(Bm + kq, ld, Ui, NB, nbq, rr, 0, ROWS, nbq, acc, sm);
+    tile_mma_t<GTri>(Bm + kq, ld, ((int64_t)BD::per_macro - kq) * 8, Ui, NB, (int64_t)NB * NB * 8, nbq, rr, 0, acc,
+                     sm);
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1162,6 +1295,7 @@ struct GemmArgs {
     double* D;
     double* D2;
     int64_t sA, sB, sC, sD, sD2;
+    int64_t limA, limB;      // doubles of a macro's block readable from its A / Bt (reads beyond give 0)
     int lda, ldb, ldc, ldd, ldd2;
     int rows, cols, K;       // extent of the region (relative to its origin)
     int dsplit;              // first column that goes to D2 (cols if none)
@@ -1169,100 +1303,6 @@ struct GemmArgs {
     int tiles_c, tiles;      // column tiles, tiles per macro
     int64_t n_macro;
 };
-
-// Tile shapes of the batched product (the sweep of the tile autotuner picks
-// one per degree and call site): WM x WN waves, each owning BI x BJ blocks of
-// 16 x 16, so a workgroup of 64 WM WN threads computes a TM x TN tile with
-// TM = 16 WM BI, TN = 16 WN BJ; K is staged through LDS in chunks of KC, and
-// OCC waves per SIMD are asked of the register allocator.
-// Every shape adds the products of one output element in the same order (K
-// ascending, four at a time per MFMA), so all shapes give the same bits.
-template <int WM_, int WN_, int BI_, int BJ_, int KC_, int OCC_>
-struct GTile {
-    static constexpr int WM = WM_, WN = WN_, BI = BI_, BJ = BJ_, KC = KC_, OCC = OCC_;
-    static constexpr int TM = 16 * WM * BI, TN = 16 * WN * BJ, NT = 64 * WM * WN;
-    static constexpr int LA = TM * KC / NT, LB = KC * TN / NT;   // staged elements per thread
-    static_assert(LA * NT == TM * KC && LB * NT == KC * TN, "tile does not divide among the threads");
-};
-
-template <class T>
-struct GTileSmem {
-    double As[2][T::TM][T::KC + 1];
-    double Bs[2][T::KC][T::TN + 1];
-};
-
-// The variants the library carries, in the order of their index.
-#define MEHDG_GEMM_VARIANTS(X) \
-    X(0, 4, 2, 2, 2, 16, 4)    \
-    X(1, 4, 2, 2, 4, 16, 2)    \
-    X(2, 2, 4, 4, 2, 16, 2)    \
-    X(3, 4, 2, 2, 2, 32, 2)    \
-    X(4, 2, 2, 2, 2, 16, 3)    \
-    X(5, 4, 4, 2, 2, 16, 2)    \
-    X(6, 2, 2, 2, 4, 16, 2)
-constexpr int kGemmVariants = 7;
-
-// acc (+)= -A[r0.., 0..K) * Bt[0..K, c0..) on a T tile (the negated form is
-// the only one the products need)
-template <class T>
-__device__ __forceinline__ void tile_mma_t(const double* A, int lda, const double* Bt, int ldb, int K, int r0,
-                                           int c0, int rows, int cols, v4d (&acc)[T::BI][T::BJ],
-                                           GTileSmem<T>& sm) {
-    constexpr int KC = T::KC, TN = T::TN, NT = T::NT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave / T::WN, wc = wave % T::WN;
-    double ra[T::LA], rb[T::LB];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < T::LA; ++i) {
-            const int e = tid + NT * i;
-            const int r = r0 + e / KC, k = k0 + e % KC;
-            ra[i] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < T::LB; ++i) {
-            const int e = tid + NT * i;
-            const int kk = k0 + e / TN, c = c0 + e % TN;
-            rb[i] = (kk < K && c < cols) ? Bt[(int64_t)kk * ldb + c] : 0.0;
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < T::LA; ++i) {
-            const int e = tid + NT * i;
-            sm.As[buf][e / KC][e % KC] = -ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < T::LB; ++i) {
-            const int e = tid + NT * i;
-            sm.Bs[buf][e / TN][e % TN] = rb[i];
-        }
-    };
-    const int nchunk = (K + KC - 1) / KC;
-    load(0);
-    stash(0);
-    __syncthreads();
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nchunk) load((ch + 1) * KC);
-#pragma unroll
-        for (int ks = 0; ks < KC; ks += 4) {
-            const int kq = ks + (lane >> 4);
-            double a[T::BI], b[T::BJ];
-#pragma unroll
-            for (int bi = 0; bi < T::BI; ++bi) a[bi] = sm.As[buf][(wr * T::BI + bi) * 16 + (lane & 15)][kq];
-#pragma unroll
-            for (int bj = 0; bj < T::BJ; ++bj) b[bj] = sm.Bs[buf][kq][(wc * T::BJ + bj) * 16 + (lane & 15)];
-#pragma unroll
-            for (int bi = 0; bi < T::BI; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < T::BJ; ++bj)
-                    acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
-        }
-        if (ch + 1 < nchunk) stash(buf ^ 1);
-        __syncthreads();
-    }
-}
 
 // TAG only separates the trailing-update launches (0), the Schur product (1)
 // and the refinement residual (2) in profiles; the code is the same.
@@ -1299,7 +1339,7 @@ __global__ void __launch_bounds__(T::NT, T::OCC) k_gemm(GemmArgs g) {
     for (int bi = 0; bi < T::BI; ++bi)
 #pragma unroll
         for (int bj = 0; bj < T::BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-    tile_mma_t<T>(g.A + m * g.sA, g.lda, g.Bt + m * g.sB, g.ldb, g.K, r0, c0, g.rows, g.cols, acc, sm);
+    tile_mma_t<T>(g.A + m * g.sA, g.lda, g.limA * 8, g.Bt + m * g.sB, g.ldb, g.limB * 8, g.K, r0, c0, acc, sm);
     double* D = g.D ? g.D + m * g.sD : nullptr;
     double* D2 = g.D2 ? g.D2 + m * g.sD2 : nullptr;
 #pragma unroll
@@ -1310,7 +1350,7 @@ __global__ void __launch_bounds__(T::NT, T::OCC) k_gemm(GemmArgs g) {
             for (int q = 0; q < 4; ++q) {
                 const int r = row(bi, q), c = col(bj);
                 if (r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c)) {
-                    const double v = cr[bi][bj][q] + acc[bi][bj][q];
+                    const double v = cr[bi][bj][q] - acc[bi][bj][q];
                     if (D2 && c >= g.dsplit) D2[(int64_t)r * g.ldd2 + (c - g.dsplit)] = v;
                     else if (D) D[(int64_t)r * g.ldd + c] = v;
                 }

@@ -329,6 +329,8 @@ mehdg_err launch_update(mehdg_ctx* c, int kb0, int K, int o_r, int o_c, int rows
     GemmArgs g{};
     g.A = B + (int64_t)o_r * ld + kb0;
     g.Bt = B + (int64_t)kb0 * ld + o_c;
+    g.limA = BD::per_macro - ((int64_t)o_r * ld + kb0);
+    g.limB = BD::per_macro - ((int64_t)kb0 * ld + o_c);
     g.C = B + (int64_t)o_r * ld + o_c;
     g.D = B + (int64_t)o_r * ld + o_c;
     g.D2 = nullptr;
@@ -468,6 +470,7 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
     // Ahat = A' - L21 U12, bhat = r_hat - L21 y
     GemmArgs g{};
     g.A = B + (int64_t)NV * ld;
+    g.limA = BD::per_macro - (int64_t)NV * ld;
     g.sA = g.sB = g.sC = BD::per_macro;
     g.lda = g.ldb = g.ldc = ld;
     g.rows = NH;
@@ -476,6 +479,7 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
     g.skip_c = NH + 1;
     if (Ahat) {
         g.Bt = B + NV;
+        g.limB = BD::per_macro - NV;
         g.C = B + (int64_t)NV * ld + NV;
         g.D = Ahat;
         g.sD = (int64_t)NH * NH;
@@ -487,6 +491,7 @@ mehdg_err launch_condense(mehdg_ctx* c, double* Ahat, double* bhat, hipStream_t 
         g.dsplit = NH;
     } else {
         g.Bt = B + NV + NH;
+        g.limB = BD::per_macro - (NV + NH);
         g.C = B + (int64_t)NV * ld + NV + NH;
         g.D = bhat;
         g.sD = NH;
@@ -614,9 +619,11 @@ mehdg_err launch_condense_mixed(mehdg_ctx* c, bool bf16, double* Ahat, double* b
         g.A = c->d_B + m0 * BD::per_macro;
         g.lda = ld;
         g.sA = BD::per_macro;
+        g.limA = BD::per_macro;
         g.Bt = c->d_zb;
         g.ldb = NR;
         g.sB = LD::per_z;
+        g.limB = LD::per_z;
         g.C = c->d_B + m0 * BD::per_macro + NV;
         g.ldc = ld;
         g.sC = BD::per_macro;
@@ -674,9 +681,11 @@ mehdg_err launch_condense_mixed(mehdg_ctx* c, bool bf16, double* Ahat, double* b
         s.A = c->d_B + m0 * BD::per_macro + (int64_t)NV * ld;
         s.lda = ld;
         s.sA = BD::per_macro;
+        s.limA = BD::per_macro - (int64_t)NV * ld;
         s.Bt = c->d_zb;
         s.ldb = NR;
         s.sB = LD::per_z;
+        s.limB = LD::per_z;
         s.C = c->d_B + m0 * BD::per_macro + (int64_t)NV * ld + NV;
         s.ldc = ld;
         s.sC = BD::per_macro;
@@ -695,6 +704,7 @@ mehdg_err launch_condense_mixed(mehdg_ctx* c, bool bf16, double* Ahat, double* b
             s.dsplit = NH;
         } else {
             s.Bt = c->d_zb + NH;
+            s.limB = LD::per_z - NH;
             s.C = c->d_B + m0 * BD::per_macro + (int64_t)NV * ld + NV + NH;
             s.D = bhat + m0 * NH;
             s.ldd = 1;
