@@ -989,21 +989,22 @@ __device__ __forceinline__ void tile_mma_t(const double* A, int lda, int64_t a_b
 #pragma unroll
     for (int i = 0; i < T::LB; ++i) vb[i] = ((bk + i * RB) * ldb + c0 + tid % TN) * 8;
     double ra[T::LA], rb[T::LB];
-    auto clamp32 = [](int64_t b) { return (uint32_t)(b < 0 ? 0 : (b > 0xffffffffll ? 0xffffffffll : b)); };
-    const uint32_t na = clamp32(a_bytes), nb = clamp32(b_bytes);
-    const uint32_t sta = 8u * KC, stb = 8u * KC * (uint32_t)ldb;   // bytes per chunk
+    // record counts as non-negative int32 (buffers here stay far below 2 GiB)
+    auto clamp31 = [](int64_t b) { return (int)(b < 0 ? 0 : (b > 0x7fffffffll ? 0x7fffffffll : b)); };
+    const int na = clamp31(a_bytes), nb = clamp31(b_bytes);
+    const int sta = 8 * KC, stb = 8 * KC * ldb;   // bytes per chunk
     // descriptors are wave-uniform: readfirstlane keeps them in scalar registers
-    auto rsrc = [](const double* p, uint32_t n) {
+    auto rsrc = [](const double* p, int n) {
         const uint64_t a = (uint64_t)p;
         const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
         const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
         return __builtin_amdgcn_make_buffer_rsrc((void*)(lo | (hi << 32)), (short)0,
-                                                 __builtin_amdgcn_readfirstlane((int)n), 0x00020000);
+                                                 __builtin_amdgcn_readfirstlane(n), 0x00020000);
     };
     auto load = [&](int k0) {
-        const uint32_t ch = (uint32_t)k0 / KC;
-        const auto sa = rsrc(A + k0, na > ch * sta ? na - ch * sta : 0u);
-        const auto sb = rsrc(Bt + (int64_t)k0 * ldb, nb > ch * stb ? nb - ch * stb : 0u);
+        const int ch = k0 / KC;
+        const auto sa = rsrc(A + k0, max(na - ch * sta, 0));
+        const auto sb = rsrc(Bt + (int64_t)k0 * ldb, max(nb - ch * stb, 0));
 #pragma unroll
         for (int i = 0; i < T::LA; ++i)
             ra[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, va[i], 0, 0));
@@ -1032,28 +1033,35 @@ __device__ __forceinline__ void tile_mma_t(const double* A, int lda, int64_t a_b
         }
     };
     const int nchunk = (K + KC - 1) / KC;
-    load(0);
-    stash(0);
-    __syncthreads();
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int buf = ch & 1;
+    // one chunk: prefetch the next into registers, multiply this one from LDS
+    // buffer BUF, stash the next into the other buffer; BUF is a constant of
+    // the unrolled pair, so the LDS addresses are fixed offsets
+    auto step = [&](int ch, auto bufc) {
+        constexpr int BUF = decltype(bufc)::value;
         if (ch + 1 < nchunk) load((ch + 1) * KC);
 #pragma unroll
         for (int ks = 0; ks < KC; ks += 4) {
             const int kq = ks + (lane >> 4);
             double a[T::BI], b[T::BJ];
 #pragma unroll
-            for (int bi = 0; bi < T::BI; ++bi) a[bi] = sm.As[buf][(wr * T::BI + bi) * 16 + (lane & 15)][kq];
+            for (int bi = 0; bi < T::BI; ++bi) a[bi] = sm.As[BUF][(wr * T::BI + bi) * 16 + (lane & 15)][kq];
 #pragma unroll
-            for (int bj = 0; bj < T::BJ; ++bj) b[bj] = sm.Bs[buf][kq][(wc * T::BJ + bj) * 16 + (lane & 15)];
+            for (int bj = 0; bj < T::BJ; ++bj) b[bj] = sm.Bs[BUF][kq][(wc * T::BJ + bj) * 16 + (lane & 15)];
 #pragma unroll
             for (int bi = 0; bi < T::BI; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < T::BJ; ++bj)
                     acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
         }
-        if (ch + 1 < nchunk) stash(buf ^ 1);
+        if (ch + 1 < nchunk) stash(BUF ^ 1);
         __syncthreads();
+    };
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ch += 2) {
+        step(ch, std::integral_constant<int, 0>{});
+        if (ch + 1 < nchunk) step(ch + 1, std::integral_constant<int, 1>{});
     }
 }
 

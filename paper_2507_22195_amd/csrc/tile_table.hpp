@@ -14,13 +14,13 @@
 //     schur  0:128x64/16 3.25, 1:128x128/16 4.08, 2:128x128/16 4.13, 3:128x64/32 4.22, 4:64x64/16 3.05, 5:128x128/16 3.98, 6:64x128/16 3.55
 //     depth  (2 blocks) 1:13.5, 2:14.0
 //   p = 2, 4096 macro-elements (16x16x16):
-//     update 0:128x64/16 28.70, 1:128x128/16 31.40, 2:128x128/16 31.55, 3:128x64/32 33.03, 4:64x64/16 30.10, 5:128x128/16 30.66, 6:64x128/16 30.55
-//     schur  0:128x64/16 53.31, 1:128x128/16 57.38, 2:128x128/16 58.47, 3:128x64/32 62.52, 4:64x64/16 55.63, 5:128x128/16 55.39, 6:64x128/16 57.32
-//     depth  (5 blocks) 1:179.9, 2:177.3, 3:177.1, 4:177.9, 5:179.1
+//     update 0:128x64/16 22.26, 1:128x128/16 24.44, 2:128x128/16 24.13, 3:128x64/32 25.65, 4:64x64/16 22.27, 5:128x128/16 23.34, 6:64x128/16 22.86
+//     schur  0:128x64/16 50.29, 1:128x128/16 55.40, 2:128x128/16 54.63, 3:128x64/32 59.18, 4:64x64/16 51.02, 5:128x128/16 52.16, 6:64x128/16 52.74
+//     depth  (5 blocks) 1:177.7, 2:174.0, 3:173.8, 4:174.4, 5:174.9
 //   p = 3, 2048 macro-elements (16x16x8):
-//     update 0:128x64/16 178.17, 1:128x128/16 191.02, 2:128x128/16 194.44, 3:128x64/32 204.86, 4:64x64/16 176.58, 5:128x128/16 185.17, 6:64x128/16 181.38
-//     schur  0:128x64/16 264.37, 1:128x128/16 292.13, 2:128x128/16 298.28, 3:128x64/32 305.43, 4:64x64/16 272.05, 5:128x128/16 282.00, 6:64x128/16 285.58
-//     depth  (14 blocks) 1:1059.3, 2:1007.2, 3:991.3, 4:983.9, 7:981.9, 14:987.1
+//     update 0:128x64/16 170.06, 1:128x128/16 185.09, 2:128x128/16 182.90, 3:128x64/32 195.96, 4:64x64/16 166.80, 5:128x128/16 176.15, 6:64x128/16 170.98
+//     schur  0:128x64/16 249.87, 1:128x128/16 281.30, 2:128x128/16 276.99, 3:128x64/32 289.92, 4:64x64/16 259.34, 5:128x128/16 263.89, 6:64x128/16 269.32
+//     depth  (14 blocks) 1:1036.2, 2:976.8, 3:965.4, 4:958.4, 7:957.7, 14:964.1
 //   p = 4, 64 macro-elements (4x4x4):
 //     update 0:128x64/16 64.06, 1:128x128/16 67.77, 2:128x128/16 68.73, 3:128x64/32 71.47, 4:64x64/16 68.11, 5:128x128/16 66.39, 6:64x128/16 67.78
 //     schur  0:128x64/16 46.67, 1:128x128/16 48.30, 2:128x128/16 49.03, 3:128x64/32 52.29, 4:64x64/16 52.99, 5:128x128/16 46.33, 6:64x128/16 49.20
