@@ -943,6 +943,9 @@ __device__ __forceinline__ void zero_acc(v4d acc[2][2]) {
 template <int WM_, int WN_, int BI_, int BJ_, int KC_, int OCC_>
 struct GTile {
     static constexpr int WM = WM_, WN = WN_, BI = BI_, BJ = BJ_, KC = KC_, OCC = OCC_;
+    // from 6 waves per SIMD on (three 8-wave workgroups per CU) C is read
+    // after the K loop instead of being held across it
+    static constexpr bool C_LATE = OCC >= 6;
     static constexpr int TM = 16 * WM * BI, TN = 16 * WN * BJ, NT = 64 * WM * WN;
     static constexpr int LA = TM * KC / NT, LB = KC * TN / NT;   // staged elements per thread
     static_assert(LA * NT == TM * KC && LB * NT == KC * TN, "tile does not divide among the threads");
@@ -962,8 +965,9 @@ struct GTileSmem {
     X(3, 4, 2, 2, 2, 32, 2)    \
     X(4, 2, 2, 2, 2, 16, 3)    \
     X(5, 4, 4, 2, 2, 16, 2)    \
-    X(6, 2, 2, 2, 4, 16, 2)
-constexpr int kGemmVariants = 7;
+    X(6, 2, 2, 2, 4, 16, 2)    \
+    X(7, 4, 2, 2, 2, 16, 6)
+constexpr int kGemmVariants = 8;
 
 // acc += A[r0.., 0..K) * Bt[0..K, c0..) on a T tile.  The operands are read
 // with buffer loads: each element a thread stages keeps one byte offset for
@@ -1332,22 +1336,26 @@ __global__ void __launch_bounds__(T::NT, T::OCC) k_gemm(GemmArgs g) {
     // C is fetched first and only added after the K loop, so its latency
     // overlaps the staging and the MFMA work.
     double cr[T::BI][T::BJ][4];
+    auto load_c = [&]() {
 #pragma unroll
-    for (int bi = 0; bi < T::BI; ++bi)
+        for (int bi = 0; bi < T::BI; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < T::BJ; ++bj)
+            for (int bj = 0; bj < T::BJ; ++bj)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int r = row(bi, q), c = col(bj);
-                const bool in = r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c);
-                cr[bi][bj][q] = in ? C[(int64_t)r * g.ldc + c] : 0.0;
-            }
+                for (int q = 0; q < 4; ++q) {
+                    const int r = row(bi, q), c = col(bj);
+                    const bool in = r < g.rows && c < g.cols && !(r >= g.skip_r && c >= g.skip_c);
+                    cr[bi][bj][q] = in ? C[(int64_t)r * g.ldc + c] : 0.0;
+                }
+    };
+    if constexpr (!T::C_LATE) load_c();
     v4d acc[T::BI][T::BJ];
 #pragma unroll
     for (int bi = 0; bi < T::BI; ++bi)
 #pragma unroll
         for (int bj = 0; bj < T::BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
     tile_mma_t<T>(g.A + m * g.sA, g.lda, g.limA * 8, g.Bt + m * g.sB, g.ldb, g.limB * 8, g.K, r0, c0, acc, sm);
+    if constexpr (T::C_LATE) load_c();
     double* D = g.D ? g.D + m * g.sD : nullptr;
     double* D2 = g.D2 ? g.D2 + m * g.sD2 : nullptr;
 #pragma unroll

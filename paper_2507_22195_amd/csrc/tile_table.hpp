@@ -14,13 +14,13 @@
 //     schur  0:128x64/16 3.25, 1:128x128/16 4.08, 2:128x128/16 4.13, 3:128x64/32 4.22, 4:64x64/16 3.05, 5:128x128/16 3.98, 6:64x128/16 3.55
 //     depth  (2 blocks) 1:13.5, 2:14.0
 //   p = 2, 4096 macro-elements (16x16x16):
-//     update 0:128x64/16 22.26, 1:128x128/16 24.44, 2:128x128/16 24.13, 3:128x64/32 25.65, 4:64x64/16 22.27, 5:128x128/16 23.34, 6:64x128/16 22.86
-//     schur  0:128x64/16 50.29, 1:128x128/16 55.40, 2:128x128/16 54.63, 3:128x64/32 59.18, 4:64x64/16 51.02, 5:128x128/16 52.16, 6:64x128/16 52.74
-//     depth  (5 blocks) 1:177.7, 2:174.0, 3:173.8, 4:174.4, 5:174.9
+//     update 0:128x64/16 21.82, 1:128x128/16 24.16, 2:128x128/16 24.27, 3:128x64/32 25.79, 4:64x64/16 22.02, 5:128x128/16 23.48, 6:64x128/16 23.35, 7:128x64/16 21.40
+//     schur  0:128x64/16 49.10, 1:128x128/16 54.80, 2:128x128/16 55.20, 3:128x64/32 60.08, 4:64x64/16 50.02, 5:128x128/16 52.17, 6:64x128/16 52.27, 7:128x64/16 48.02
+//     depth  (5 blocks) 1:172.9, 2:169.6, 3:169.8, 4:170.4, 5:171.2
 //   p = 3, 2048 macro-elements (16x16x8):
-//     update 0:128x64/16 170.06, 1:128x128/16 185.09, 2:128x128/16 182.90, 3:128x64/32 195.96, 4:64x64/16 166.80, 5:128x128/16 176.15, 6:64x128/16 170.98
-//     schur  0:128x64/16 249.87, 1:128x128/16 281.30, 2:128x128/16 276.99, 3:128x64/32 289.92, 4:64x64/16 259.34, 5:128x128/16 263.89, 6:64x128/16 269.32
-//     depth  (14 blocks) 1:1036.2, 2:976.8, 3:965.4, 4:958.4, 7:957.7, 14:964.1
+//     update 0:128x64/16 165.61, 1:128x128/16 183.15, 2:128x128/16 184.06, 3:128x64/32 196.65, 4:64x64/16 161.44, 5:128x128/16 174.64, 6:64x128/16 167.12, 7:128x64/16 162.76
+//     schur  0:128x64/16 240.13, 1:128x128/16 278.40, 2:128x128/16 279.73, 3:128x64/32 291.58, 4:64x64/16 243.07, 5:128x128/16 261.48, 6:64x128/16 254.19, 7:128x64/16 237.12
+//     depth  (14 blocks) 1:1016.4, 2:954.8, 3:936.9, 4:930.2, 7:926.5, 14:933.2
 //   p = 4, 64 macro-elements (4x4x4):
 //     update 0:128x64/16 64.06, 1:128x128/16 67.77, 2:128x128/16 68.73, 3:128x64/32 71.47, 4:64x64/16 68.11, 5:128x128/16 66.39, 6:64x128/16 67.78
 //     schur  0:128x64/16 46.67, 1:128x128/16 48.30, 2:128x128/16 49.03, 3:128x64/32 52.29, 4:64x64/16 52.99, 5:128x128/16 46.33, 6:64x128/16 49.20
@@ -31,9 +31,9 @@ namespace mehdg {
 constexpr int kTileTable[5][2] = {
     {0, 0},   // (unused)
     {4, 4},   // p = 1
-    {0, 0},   // p = 2
-    {4, 0},   // p = 3
+    {7, 7},   // p = 2
+    {4, 7},   // p = 3
     {0, 5},   // p = 4
 };
-constexpr int kLuDepth[5] = {1, 1, 3, 7, 7};   // (unused), p = 1, 2, 3, 4
+constexpr int kLuDepth[5] = {1, 1, 2, 7, 7};   // (unused), p = 1, 2, 3, 4
 }  // namespace mehdg
