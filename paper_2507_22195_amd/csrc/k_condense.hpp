@@ -1240,7 +1240,7 @@ __global__ void __launch_bounds__(GTHREADS) k_perm_rows(double* B, const int32_t
 // L21[:, q] = acc U_qq^-1 (K = nbq) in place.  Each workgroup reads its own
 // tile back only after writing it.
 template <int P>
-__global__ void __launch_bounds__(GTHREADS, 4) k_trsm_x(double* B, const double* __restrict__ tri, int q,
+__global__ void __launch_bounds__(GTHREADS, 6) k_trsm_x(double* B, const double* __restrict__ tri, int q,
                                                      int64_t n_macro) {
     using BD = Bdims<P>;
     using PN = Panel<P>;
@@ -1253,21 +1253,12 @@ __global__ void __launch_bounds__(GTHREADS, 4) k_trsm_x(double* B, const double*
     double* Bm = B + m * BD::per_macro;
     const int kq = q * NB, nbq = (NV - kq) < NB ? (NV - kq) : NB;
     const int rr = NV + tile * GM;                 // rows [rr, rr+128) of X
-    double cr[2][2][4];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int r = tile_row(rr, bi, qq), c = tile_col(0, bj);
-                cr[bi][bj][qq] = (r < ROWS && c < nbq) ? Bm[(int64_t)r * ld + kq + c] : 0.0;
-            }
     v4d acc[2][2];
     zero_acc(acc);
     if (kq > 0)
         tile_mma_t<GTri>(Bm, ld, (int64_t)BD::per_macro * 8, Bm + kq, ld, ((int64_t)BD::per_macro - kq) * 8, kq, rr,
                          0, acc, sm);
+    // X[:, q] is read after the long product (not held across it: 6 waves per SIMD)
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1275,7 +1266,8 @@ __global__ void __launch_bounds__(GTHREADS, 4) k_trsm_x(double* B, const double*
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
                 const int r = tile_row(rr, bi, qq), c = tile_col(0, bj);
-                if (r < ROWS && c < nbq) Bm[(int64_t)r * ld + kq + c] = cr[bi][bj][qq] - acc[bi][bj][qq];
+                if (r < ROWS && c < nbq)
+                    Bm[(int64_t)r * ld + kq + c] = Bm[(int64_t)r * ld + kq + c] - acc[bi][bj][qq];
             }
     __syncthreads();
     zero_acc(acc);
