@@ -857,66 +857,6 @@ __device__ __forceinline__ void tile_mma(const double* A, int lda, const double*
     }
 }
 
-// tile_mma (not negated) with the K rows of Bt taken from rows srcrow[k] of
-// Bfull, with the same one-chunk-ahead register prefetch.
-__device__ __forceinline__ void tile_mma_gather(const double* A, int lda, const double* Bfull, int ldb,
-                                                const int* srcrow, int K, int r0, int c0, int rows, int cols,
-                                                v4d acc[2][2], TileSmem& sm) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    double ra[GLA], rb[GLB];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < GLA; ++i) {
-            const int e = tid + GTHREADS * i;
-            const int ar = e / GK, ak = e % GK;
-            const int r = r0 + ar, k = k0 + ak;
-            ra[i] = (r < rows && k < K) ? A[(int64_t)r * lda + k] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < GLB; ++i) {
-            const int e = tid + GTHREADS * i;
-            const int bk = e / GT, bc = e % GT;
-            const int kk = k0 + bk, c = c0 + bc;
-            rb[i] = (kk < K && c < cols) ? Bfull[(int64_t)srcrow[kk] * ldb + c] : 0.0;
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < GLA; ++i) {
-            const int e = tid + GTHREADS * i;
-            sm.As[buf][e / GK][e % GK] = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < GLB; ++i) {
-            const int e = tid + GTHREADS * i;
-            sm.Bs[buf][e / GT][e % GT] = rb[i];
-        }
-    };
-    const int nchunk = (K + GK - 1) / GK;
-    load(0);
-    stash(0);
-    __syncthreads();
-    for (int ch = 0; ch < nchunk; ++ch) {
-        const int buf = ch & 1;
-        if (ch + 1 < nchunk) load((ch + 1) * GK);
-#pragma unroll
-        for (int ks = 0; ks < GK; ks += 4) {
-            const int kq = ks + (lane >> 4);
-            const double a0 = sm.As[buf][wr * 32 + (lane & 15)][kq];
-            const double a1 = sm.As[buf][wr * 32 + 16 + (lane & 15)][kq];
-            const double b0 = sm.Bs[buf][kq][wc * 32 + (lane & 15)];
-            const double b1 = sm.Bs[buf][kq][wc * 32 + 16 + (lane & 15)];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        if (ch + 1 < nchunk) stash(buf ^ 1);
-        __syncthreads();
-    }
-}
-
 __device__ __forceinline__ int tile_row(int r0, int bi, int q) {
     const int lane = threadIdx.x & 63, wr = (threadIdx.x >> 6) >> 1;
     return r0 + wr * 32 + bi * 16 + (lane >> 4) + 4 * q;
@@ -977,10 +917,12 @@ constexpr int kGemmVariants = 8;
 // as they stand (they only feed outputs that are never stored) and reads past
 // a_bytes / b_bytes give 0; only the last chunk, when K is not a multiple of
 // KC, zeroes the terms k >= K on both sides.
-template <class T>
+// GATHER: row k of Bt is row srcrow[k] of the matrix at Bt (b_bytes from its
+// start); its offsets are formed per chunk from the list.
+template <class T, bool GATHER = false>
 __device__ __forceinline__ void tile_mma_t(const double* A, int lda, int64_t a_bytes, const double* Bt, int ldb,
                                            int64_t b_bytes, int K, int r0, int c0, v4d (&acc)[T::BI][T::BJ],
-                                           GTileSmem<T>& sm) {
+                                           GTileSmem<T>& sm, const int* srcrow = nullptr) {
     constexpr int KC = T::KC, TN = T::TN, NT = T::NT;
     constexpr int RA = NT / KC, RB = NT / TN;     // rows of A / of Bt between a thread's staged elements
     static_assert(RA * KC == NT && RB * TN == NT, "staging does not tile the chunk");
@@ -1008,13 +950,23 @@ __device__ __forceinline__ void tile_mma_t(const double* A, int lda, int64_t a_b
     auto load = [&](int k0) {
         const int ch = k0 / KC;
         const auto sa = rsrc(A + k0, max(na - ch * sta, 0));
-        const auto sb = rsrc(Bt + (int64_t)k0 * ldb, max(nb - ch * stb, 0));
 #pragma unroll
         for (int i = 0; i < T::LA; ++i)
             ra[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sa, va[i], 0, 0));
+        if constexpr (GATHER) {
+            const auto sb = rsrc(Bt, nb);
 #pragma unroll
-        for (int i = 0; i < T::LB; ++i)
-            rb[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, vb[i], 0, 0));
+            for (int i = 0; i < T::LB; ++i) {
+                const int kk = k0 + bk + i * RB;
+                const int off = kk < K ? (srcrow[kk] * ldb + c0 + tid % TN) * 8 : -1;
+                rb[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, off, 0, 0));
+            }
+        } else {
+            const auto sb = rsrc(Bt + (int64_t)k0 * ldb, max(nb - ch * stb, 0));
+#pragma unroll
+            for (int i = 0; i < T::LB; ++i)
+                rb[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(sb, vb[i], 0, 0));
+        }
         if (k0 + KC > K) {                          // the last, partial chunk
 #pragma unroll
             for (int i = 0; i < T::LA; ++i)
@@ -1164,7 +1116,8 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
                 const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
                 mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
             }
-            tile_mma_gather(Ti + a.loff, a.ldl, Bm, ld, pm, a.w, 0, cc, a.w, a.c_hi, acc, sm);
+            tile_mma_t<GTri, true>(Ti + a.loff, a.ldl, ((int64_t)PN::TRI - a.loff) * 8, Bm, ld,
+                                   (int64_t)BD::per_macro * 8, a.w, 0, cc, acc, gsm, pm);
 #pragma unroll
             for (int i = 0; i < MV; ++i) {
                 const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
