@@ -1025,25 +1025,20 @@ __device__ __forceinline__ void tile_mma_t(const double* A, int lda, int64_t a_b
 using GTri = GTile<4, 2, 2, 2, 16, 4>;
 
 // ---------------------------------------------------------------------------
-// In-place triangular applications on MFMA after a panel or an outer block:
-//   tiles [0, ct):       U_top[:, c-tile] <- L^-1 (P B)_top[:, c-tile] for the
-//                        columns [c_lo, c_hi); L^-1 is w x w, the top rows are
-//                        [kb0, kb0+w) and P the composed interchange in perm.
-//                        With DELAYED (kpre > 0) the earlier blocks of the group have not
-//                        updated these columns yet: the tile forms
-//                        T = (P B)_top - L[top, kb0-kpre : kb0] U[kb0-kpre : kb0, c-tile]
-//                        (their multipliers already in the top rows' order),
-//                        writes it to the top rows and solves U_top = L^-1 T
-//   tiles [ct, ct+rt):   L21[r-tile, :] <- X_panel[r-tile, :] U_kk^-1 for the
-//                        X rows and the panel columns [kp, kp+np)
-// Each workgroup reads everything it overwrites before writing it.
+// In-place triangular application on MFMA after a panel or an outer block:
+// per 64-column tile of [c_lo, c_hi), U_top[:, c-tile] <- L^-1 (P B)_top[:, c-tile];
+// L^-1 is w x w, the top rows are [kb0, kb0+w) and P the composed interchange
+// in perm.  With DELAYED (kpre > 0) the earlier blocks of the group have not
+// updated these columns yet: the tile forms
+//   T = (P B)_top - L[top, kb0-kpre : kb0] U[kb0-kpre : kb0, c-tile]
+// (their multipliers already in the top rows' order), writes it to the top
+// rows and solves U_top = L^-1 T.  Each workgroup reads everything it
+// overwrites before writing it.
 struct TriArgs {
     int kb0, w;          // top rows [kb0, kb0+w), also the K of the column tiles
     int loff, ldl;       // L^-1 of the top rows: offset in the per-macro workspace, leading dimension
     int c_lo, c_hi;      // columns that get U_top
-    int kp, np;          // panel whose X columns become L21
-    int uoff;            // that panel's U_kk^-1 (leading dimension NB) in the workspace
-    int ct, rt;          // column tiles, X row tiles
+    int ct;              // column tiles
     int kpre;            // columns of the group's earlier blocks whose update is pending (0: none)
 };
 
@@ -1060,69 +1055,41 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
     GTileSmem<GTri>& gsm = *reinterpret_cast<GTileSmem<GTri>*>(&sm);
     int64_t m;
     int tile;
-    xcd_tile(a.ct + a.rt, m, tile);
+    xcd_tile(a.ct, m, tile);
     if (m >= n_macro) return;
     double* Bm = B + m * BD::per_macro;
     const double* Ti = tri + m * PN::TRI;
     v4d acc[2][2];
     zero_acc(acc);
-    if (tile < a.ct) {
-        const int cc = a.c_lo + tile * GT;     // columns [cc, cc+64)
-        for (int i = threadIdx.x; i < 3 * OB + 1; i += GTHREADS) pm[i] = perm[m * PN::PERM + i];
-        __syncthreads();
-        const int nd = pm[3 * OB];
-        // rows below the block that change read their new values before anything is written
-        double mvr[MV];
-        if constexpr (DELAYED) {
-            const int kg = a.kb0 - a.kpre;
-            tile_mma_t<GTri>(Bm + kg, ld, ((int64_t)BD::per_macro - kg) * 8, Bm + (int64_t)kg * ld, ld,
-                             ((int64_t)BD::per_macro - (int64_t)kg * ld) * 8, a.kpre, a.kb0, cc, acc, gsm);
+    const int cc = a.c_lo + tile * GT;     // columns [cc, cc+64)
+    for (int i = threadIdx.x; i < 3 * OB + 1; i += GTHREADS) pm[i] = perm[m * PN::PERM + i];
+    __syncthreads();
+    const int nd = pm[3 * OB];
+    // rows below the block that change read their new values before anything is written
+    double mvr[MV];
+    if constexpr (DELAYED) {
+        const int kg = a.kb0 - a.kpre;
+        tile_mma_t<GTri>(Bm + kg, ld, ((int64_t)BD::per_macro - kg) * 8, Bm + (int64_t)kg * ld, ld,
+                         ((int64_t)BD::per_macro - (int64_t)kg * ld) * 8, a.kpre, a.kb0, cc, acc, gsm);
 #pragma unroll
-            for (int i = 0; i < MV; ++i) {
-                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
-                mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
-            }
+        for (int i = 0; i < MV; ++i) {
+            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+            mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
+        }
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
+            for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
-                        if (r < a.w && c < a.c_hi) acc[bi][bj][q] = Bm[(int64_t)pm[r] * ld + c] - acc[bi][bj][q];
-                    }
-            __syncthreads();                 // every read of the rows this tile rewrites is done
+                for (int q = 0; q < 4; ++q) {
+                    const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
+                    if (r < a.w && c < a.c_hi) acc[bi][bj][q] = Bm[(int64_t)pm[r] * ld + c] - acc[bi][bj][q];
+                }
+        __syncthreads();                 // every read of the rows this tile rewrites is done
 #pragma unroll
-            for (int i = 0; i < MV; ++i) {
-                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
-                if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
-            }
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
-                        if (r < a.w && c < a.c_hi) Bm[(int64_t)(a.kb0 + r) * ld + c] = acc[bi][bj][q];
-                    }
-            __syncthreads();
-            zero_acc(acc);
-            tile_mma_t<GTri>(Ti + a.loff, a.ldl, ((int64_t)PN::TRI - a.loff) * 8, Bm + (int64_t)a.kb0 * ld, ld,
-                             ((int64_t)BD::per_macro - (int64_t)a.kb0 * ld) * 8, a.w, 0, cc, acc, gsm);
-        } else {
-#pragma unroll
-            for (int i = 0; i < MV; ++i) {
-                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
-                mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
-            }
-            tile_mma_t<GTri, true>(Ti + a.loff, a.ldl, ((int64_t)PN::TRI - a.loff) * 8, Bm, ld,
-                                   (int64_t)BD::per_macro * 8, a.w, 0, cc, acc, gsm, pm);
-#pragma unroll
-            for (int i = 0; i < MV; ++i) {
-                const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
-                if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
-            }
+        for (int i = 0; i < MV; ++i) {
+            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+            if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
         }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
@@ -1133,20 +1100,35 @@ __global__ void __launch_bounds__(GTHREADS) k_tri(double* B, const double* __res
                     const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
                     if (r < a.w && c < a.c_hi) Bm[(int64_t)(a.kb0 + r) * ld + c] = acc[bi][bj][q];
                 }
+        __syncthreads();
+        zero_acc(acc);
+        tile_mma_t<GTri>(Ti + a.loff, a.ldl, ((int64_t)PN::TRI - a.loff) * 8, Bm + (int64_t)a.kb0 * ld, ld,
+                         ((int64_t)BD::per_macro - (int64_t)a.kb0 * ld) * 8, a.w, 0, cc, acc, gsm);
     } else {
-        const int rr = NV + (tile - a.ct) * GM;   // rows [rr, rr+128) of the X block
-        tile_mma<false>(Bm + a.kp, ld, Ti + a.uoff, NB, a.np, rr, 0, ROWS, a.np, acc, sm);
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+        for (int i = 0; i < MV; ++i) {
+            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+            mvr[i] = (q < nd && c < a.c_hi) ? Bm[(int64_t)pm[2 * OB + q] * ld + c] : 0.0;
+        }
+        tile_mma_t<GTri, true>(Ti + a.loff, a.ldl, ((int64_t)PN::TRI - a.loff) * 8, Bm, ld,
+                               (int64_t)BD::per_macro * 8, a.w, 0, cc, acc, gsm, pm);
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int r = tile_row(rr, bi, q), c = tile_col(0, bj);
-                    if (r < ROWS && c < a.np) Bm[(int64_t)r * ld + a.kp + c] = acc[bi][bj][q];
-                }
+        for (int i = 0; i < MV; ++i) {
+            const int e = threadIdx.x + GTHREADS * i, q = e / GT, c = cc + e % GT;
+            if (q < nd && c < a.c_hi) Bm[(int64_t)pm[OB + q] * ld + c] = mvr[i];
+        }
     }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = tile_row(0, bi, q), c = tile_col(cc, bj);
+                if (r < a.w && c < a.c_hi) Bm[(int64_t)(a.kb0 + r) * ld + c] = acc[bi][bj][q];
+            }
 }
+
 
 // ---------------------------------------------------------------------------
 // The composed row interchange of the current outer block (perm) applied to

@@ -375,14 +375,13 @@ template <int P>
 mehdg_err launch_tri(mehdg_ctx* c, TriArgs a, hipStream_t st) {
     using D = Dims<P>;
     a.ct = a.c_hi > a.c_lo ? (a.c_hi - a.c_lo + GT - 1) / GT : 0;
-    a.rt = a.np > 0 ? (D::NH + GM - 1) / GM : 0;
-    if (a.ct + a.rt == 0) return MEHDG_OK;
+    if (a.ct == 0) return MEHDG_OK;
     Timed t(c, MEHDG_PROF_ROWBLOCK, st);
     if (a.kpre > 0)
-        hipLaunchKernelGGL((k_tri<P, true>), dim3(xcd_grid(a.ct + a.rt, c->n_macro)), dim3(GTHREADS), 0, st, c->d_B,
+        hipLaunchKernelGGL((k_tri<P, true>), dim3(xcd_grid(a.ct, c->n_macro)), dim3(GTHREADS), 0, st, c->d_B,
                            c->d_tri, c->d_perm, a, (int64_t)c->n_macro);
     else
-        hipLaunchKernelGGL((k_tri<P, false>), dim3(xcd_grid(a.ct + a.rt, c->n_macro)), dim3(GTHREADS), 0, st,
+        hipLaunchKernelGGL((k_tri<P, false>), dim3(xcd_grid(a.ct, c->n_macro)), dim3(GTHREADS), 0, st,
                            c->d_B, c->d_tri, c->d_perm, a, (int64_t)c->n_macro);
     return hip_ok(hipGetLastError());
 }
