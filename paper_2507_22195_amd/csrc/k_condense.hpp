@@ -172,6 +172,34 @@ __device__ __forceinline__ void lds_mm64_store_global(const v4d (&acc)[TPW], dou
     }
 }
 
+// D = sgn * A B for 32 x 32 LDS matrices (leading dimension LD) by one wave
+// on FP64 MFMA: four 16 x 16 output tiles, K in steps of 4 (register r of lane
+// l holds row (l >> 4) + 4 r, column l & 15 of a tile).
+template <int LD>
+__device__ __forceinline__ void wave_mm32(const double* A, const double* B, double* D, double sgn) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = lane >> 4;
+    v4d acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+        const double a0 = A[r16 * LD + k0 + kq], a1 = A[(16 + r16) * LD + k0 + kq];
+        const double b0 = B[(k0 + kq) * LD + r16], b1 = B[(k0 + kq) * LD + 16 + r16];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) D[(16 * i + kq + 4 * r) * LD + 16 * j + r16] = sgn * acc[i][j][r];
+}
+
 // LDS of a panel kernel that the common end of the panel (panel_finish) uses.
 template <int P>
 struct PanelShared {
@@ -298,36 +326,73 @@ __device__ __forceinline__ void panel_finish(PanelShared<P>& sh, double* __restr
         T[i][c] = (i < nb && c < nb) ? Bm[(int64_t)(kb + i) * ld + kb + c] : (i == c ? 1.0 : 0.0);
     }
     __syncthreads();
-    // L_kk^-1 by wave 0 and U_kk^-1 by wave 1, one column per lane:
-    //   L x = e_c forward (unit diagonal),  U x = e_c backward
-    // (four partial sums keep the LDS reads of a row in flight together)
-    if (wave == 0) {
-        const int c = lane;
-        for (int i = 0; i < NB; ++i) {
-            double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int k = 0;
-            for (; k + 4 <= i; k += 4) {
-                s0 -= T[i][k] * XL[k][c];
-                s1 -= T[i][k + 1] * XL[k + 1][c];
-                s2 -= T[i][k + 2] * XL[k + 2][c];
-                s3 -= T[i][k + 3] * XL[k + 3][c];
+    // L_kk^-1 by wave 0 and U_kk^-1 by wave 1 in 32 x 32 blocks:
+    //   L^-1 = [[A^-1, 0], [-D^-1 (C A^-1), D^-1]],  U^-1 = [[A^-1, -A^-1 (B D^-1)], [0, D^-1]].
+    // Each lane inverts one column of a diagonal block in registers (lanes
+    // 0..31 the first block, 32..63 the second; four partial sums per row),
+    // then the wave forms the off-diagonal block with two 32 x 32 products on
+    // MFMA, using the block of the result that stays zero as scratch.
+    constexpr int H = NB / 2;
+    static_assert(NB == 64, "the blocked inverse is written for 64-column panels");
+    if (wave < 2) {
+        const int hb = lane / H, cc = lane % H, o = hb * H;
+        double x[H];
+        if (wave == 0) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                double s0 = (i == cc) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+                for (int k = 0; k + 4 <= i; k += 4) {
+                    s0 -= T[o + i][o + k] * x[k];
+                    s1 -= T[o + i][o + k + 1] * x[k + 1];
+                    s2 -= T[o + i][o + k + 2] * x[k + 2];
+                    s3 -= T[o + i][o + k + 3] * x[k + 3];
+                }
+#pragma unroll
+                for (int k = i & ~3; k < i; ++k) s0 -= T[o + i][o + k] * x[k];
+                x[i] = (s0 + s1) + (s2 + s3);
             }
-            for (; k < i; ++k) s0 -= T[i][k] * XL[k][c];
-            XL[i][c] = (s0 + s1) + (s2 + s3);
+#pragma unroll
+            for (int i = 0; i < H; ++i) XL[o + i][o + cc] = x[i];
+        } else {
+#pragma unroll
+            for (int i = H - 1; i >= 0; --i) {
+                double s0 = (i == cc) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                int k = i + 1;
+#pragma unroll
+                for (; k + 4 <= H; k += 4) {
+                    s0 -= T[o + i][o + k] * x[k];
+                    s1 -= T[o + i][o + k + 1] * x[k + 1];
+                    s2 -= T[o + i][o + k + 2] * x[k + 2];
+                    s3 -= T[o + i][o + k + 3] * x[k + 3];
+                }
+#pragma unroll
+                for (; k < H; ++k) s0 -= T[o + i][o + k] * x[k];
+                x[i] = ((s0 + s1) + (s2 + s3)) / T[o + i][o + i];
+            }
+#pragma unroll
+            for (int i = 0; i < H; ++i) XU[o + i][o + cc] = x[i];
         }
-    } else if (wave == 1) {
-        const int c = lane;
-        for (int i = NB - 1; i >= 0; --i) {
-            double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int k = i + 1;
-            for (; k + 4 <= NB; k += 4) {
-                s0 -= T[i][k] * XU[k][c];
-                s1 -= T[i][k + 1] * XU[k + 1][c];
-                s2 -= T[i][k + 2] * XU[k + 2][c];
-                s3 -= T[i][k + 3] * XU[k + 3][c];
-            }
-            for (; k < NB; ++k) s0 -= T[i][k] * XU[k][c];
-            XU[i][c] = ((s0 + s1) + (s2 + s3)) / T[i][i];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (wave == 0) {
+            wave_mm32<NB + 1>(&T[H][0], &XL[0][0], &XL[0][H], 1.0);     // C A^-1 into the zero block
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_mm32<NB + 1>(&XL[H][H], &XL[0][H], &XL[H][0], -1.0);   // -D^-1 (C A^-1)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int i = 0; i < H; i += 2) XL[i + hb][H + cc] = 0.0;
+        } else {
+            wave_mm32<NB + 1>(&T[0][H], &XU[H][H], &XU[H][0], 1.0);     // B D^-1 into the zero block
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_mm32<NB + 1>(&XU[0][0], &XU[H][0], &XU[0][H], -1.0);   // -A^-1 (B D^-1)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int i = 0; i < H; i += 2) XU[H + i + hb][cc] = 0.0;
         }
     }
     __syncthreads();
