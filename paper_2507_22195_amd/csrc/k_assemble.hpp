@@ -219,7 +219,7 @@ __device__ void row_face(RowLds<P>& L, const double* __restrict__ coefF, int64_t
         if (fld < 5) off = 5 * k + fld;
         else if (fld < 10) off = 25 + 5 * k + (fld - 5);
         else off = 50 + 25 * ((fld - 10) % 3) + 5 * k + (fld - 10) / 3;
-        L.w[(kk * R::E2 + sl) * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off * 6 * S];
+        L.w[(kk * 25 + fld) * R::E2 + sl] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off * 6 * S];
     }
     __syncthreads();
     const int d = face_axis(f), t1 = face_t1(f), t2 = face_t2(f);
@@ -230,12 +230,16 @@ __device__ void row_face(RowLds<P>& L, const double* __restrict__ coefF, int64_t
         const int bl = idx % R::E2, rest = idx / R::E2;
         const int fld = rest % nf_, kk = rest / nf_;
         const int b1 = e1 * P + bl % Q, b2 = e2 * P + bl / Q;
-        const double* w = L.w + kk * R::E2 * 25 + fld;
-        double acc = 0.0;
-        for (int sl = 0; sl < R::E2; ++sl) {
-            const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
-            acc += w[sl * 25] * (L.t.B[s1][b1] * L.t.B[s2][b2]);
+        const double* w = L.w + (kk * 25 + fld) * R::E2;
+        double bb1[Q], bb2[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            bb1[i] = L.t.B[e1 * Q + i][b1];
+            bb2[i] = L.t.B[e2 * Q + i][b2];
         }
+        double acc = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < R::E2; ++sl) acc += w[sl] * (bb1[sl % Q] * bb2[sl / Q]);
         int bi[3];
         bi[d] = ad;
         bi[t1] = b1;
@@ -257,45 +261,68 @@ __device__ void row_write(RowLds<P>& L, double* __restrict__ Bm, int row0, int r
     using D = Dims<P>;
     using BD = Bdims<P>;
     constexpr int n1d = D::n1d, n = D::n, nf = D::nf, NV = D::NV, NH = D::NH, KG = RowLds<P>::KG;
-    for (int idx = threadIdx.x; idx < KG * BD::ld; idx += blockDim.x) {
-        const int kk = idx / BD::ld, col = idx % BD::ld;
-        double val = 0.0;
-        if (col < NV) {
-            const int l = col / n, b = col % n;
-            val = L.av[kk][l][b];
-            if (viscous) {
-                const int bi[3] = {b % n1d, (b / n1d) % n1d, b / (n1d * n1d)};
+    static_assert(KG == 1, "one row per pass");
+    double* row = Bm + (int64_t)row0 * BD::ld;
+    // V columns (l, b): an item per trial node b, whose index arithmetic and
+    // lift coefficients Lam[c][b_j] serve the five fields l; Vhat columns
+    // (f, l, e): an item per face node (f, e), the same for the five fields
+    for (int t = threadIdx.x; t < n + 6 * nf; t += blockDim.x) {
+        if (t < n) {
+            const int b = t;
+            const int bi[3] = {b % n1d, (b / n1d) % n1d, b / (n1d * n1d)};
+            double lam[3][n1d];
+            int base[3];
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const int stride = j == 0 ? 1 : (j == 1 ? n1d : n1d * n1d);
-                    const int base = b - bi[j] * stride;
+            for (int j = 0; j < 3; ++j) {
+                const int stride = j == 0 ? 1 : (j == 1 ? n1d : n1d * n1d);
+                base[j] = b - bi[j] * stride;
+#pragma unroll
+                for (int c = 0; c < n1d; ++c) lam[j][c] = L.t.Lam[c][bi[j]];
+            }
+#pragma unroll
+            for (int l = 0; l < 5; ++l) {
+                double val = L.av[0][l][b];
+                if (viscous) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int stride = j == 0 ? 1 : (j == 1 ? n1d : n1d * n1d);
+                        const double* aq = &L.aq[0][3 * l + j][base[j]];
+                        double acc = 0.0;
+#pragma unroll
+                        for (int c = 0; c < n1d; ++c) acc += aq[c * stride] * lam[j][c];
+                        val -= hinv[j] * acc;
+                    }
+                }
+                row[l * n + b] = val;
+            }
+        } else {
+            const int f = (t - n) / nf, e = (t - n) % nf;
+            const int d = face_axis(f);
+            auto stride_of = [](int ax) { return ax == 0 ? 1 : (ax == 1 ? n1d : n1d * n1d); };
+            const int iF = face_side(f) ? (n1d - 1) : 0;
+            const int dstride = stride_of(d);
+            // volume index of face node e with coordinate 0 along the normal
+            const int cbase = (e % n1d) * stride_of(face_t1(f)) + (e / n1d) * stride_of(face_t2(f));
+            double mv[n1d];
+#pragma unroll
+            for (int cd = 0; cd < n1d; ++cd) mv[cd] = L.t.Minv[cd][iF];
+            const double sh = face_sign(f) * hinv[d];
+#pragma unroll
+            for (int l = 0; l < 5; ++l) {
+                double val = L.ah[0][f][l][e];
+                if (viscous) {
+                    const double* aq = &L.aq[0][3 * l + d][cbase];
                     double acc = 0.0;
 #pragma unroll
-                    for (int c = 0; c < n1d; ++c) acc += L.aq[kk][3 * l + j][base + c * stride] * L.t.Lam[c][bi[j]];
-                    val -= hinv[j] * acc;
+                    for (int cd = 0; cd < n1d; ++cd) acc += aq[cd * dstride] * mv[cd];
+                    val += sh * acc;
                 }
-            }
-        } else if (col < NV + NH) {
-            const int r = col - NV;
-            const int f = r / (5 * nf), l = (r / nf) % 5, e = r % nf;
-            val = L.ah[kk][f][l][e];
-            if (viscous) {
-                const int d = face_axis(f);
-                int ci[3];
-                ci[face_t1(f)] = e % n1d;
-                ci[face_t2(f)] = e / n1d;
-                const int iF = face_side(f) ? (n1d - 1) : 0;
-                double acc = 0.0;
-#pragma unroll
-                for (int cd = 0; cd < n1d; ++cd) {
-                    ci[d] = cd;
-                    acc += L.aq[kk][3 * l + d][ci[0] + n1d * (ci[1] + n1d * ci[2])] * L.t.Minv[cd][iF];
-                }
-                val += face_sign(f) * hinv[d] * acc;
+                row[NV + (f * 5 + l) * nf + e] = val;
             }
         }
-        if (col != NV + NH) Bm[(int64_t)(row0 + kk * rstride) * BD::ld + col] = val;
     }
+    // padding columns after the right-hand side
+    for (int col = NV + NH + 1 + threadIdx.x; col < BD::ld; col += blockDim.x) row[col] = 0.0;
     // right-hand sides
     double part[KG];
 #pragma unroll
@@ -425,18 +452,22 @@ __device__ void row_face_h(RowLdsH<P>& L, const double* __restrict__ coefF, int6
         if (fld < 5) off = 5 * k + fld;
         else if (fld < 10) off = 25 + 5 * k + (fld - 5);
         else off = 50 + 25 * ((fld - 10) % 3) + 5 * k + (fld - 10) / 3;
-        L.w[sl * 25 + fld] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off * 6 * S];
+        L.w[fld * R::E2 + sl] = L.t.B[s1][c1] * L.t.B[s2][c2] * c[off * 6 * S];
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < nf_ * R::E2; idx += blockDim.x) {
         const int bl = idx % R::E2, fld = idx / R::E2;
         const int b1 = e1 * P + bl % Q, b2 = e2 * P + bl / Q;
-        const double* w = L.w + fld;
-        double acc = 0.0;
-        for (int sl = 0; sl < R::E2; ++sl) {
-            const int s1 = e1 * Q + sl % Q, s2 = e2 * Q + sl / Q;
-            acc += w[sl * 25] * (L.t.B[s1][b1] * L.t.B[s2][b2]);
+        const double* w = L.w + fld * R::E2;
+        double bb1[Q], bb2[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            bb1[i] = L.t.B[e1 * Q + i][b1];
+            bb2[i] = L.t.B[e2 * Q + i][b2];
         }
+        double acc = 0.0;
+#pragma unroll
+        for (int sl = 0; sl < R::E2; ++sl) acc += w[sl] * (bb1[sl % Q] * bb2[sl / Q]);
         const int e = b1 + n1d * b2;
         if (fld < 5) L.av[fld][e] += acc;
         else if (fld < 10) L.ah[fld - 5][e] += acc;
@@ -483,55 +514,84 @@ __global__ void __launch_bounds__(RowCfgH<P>::THREADS, 6) k_rows_h(const double*
         for (int e2 = l2; e2 <= u2; ++e2)
             for (int e1 = l1; e1 <= u1; ++e1) row_face_h<P>(L, coefF, m, f, c1, c2, e1, e2, k, viscous);
         const int64_t row = NV + (f * 5 + k) * nf + c;
-        for (int col = threadIdx.x; col < BD::ld; col += blockDim.x) {
-            double val = 0.0;
-            if (col < NV) {
-                const int l = col / n, b = col % n;
+        double* rowp = Bm + row * BD::ld;
+        // an item per trial node b (the five V columns (l, b)) or per face node
+        // (fp, e) (the five Vhat columns (fp, l, e)): index arithmetic and lift
+        // coefficients once per item
+        for (int t = threadIdx.x; t < n + 6 * nf; t += blockDim.x) {
+            if (t < n) {
+                const int b = t;
                 const int bi[3] = {b % n1d, (b / n1d) % n1d, b / (n1d * n1d)};
                 const int t1 = bi[ft1], t2 = bi[ft2];
+                const int e = t1 + n1d * t2;
                 const bool on = bi[d] == iF;
-                if (on) val = L.av[l][t1 + n1d * t2];
-                if (viscous) {
-                    // lift along the normal axis: the line meets the face in one node
-                    val -= hinv[d] * (L.aq[3 * l + d][t1 + n1d * t2] * L.t.Lam[iF][bi[d]]);
-                    // lifts along the face: only for nodes of the face
-                    if (on) {
-                        double a1 = 0.0, a2 = 0.0;
-                        for (int cc = 0; cc < n1d; ++cc) {
-                            a1 += L.aq[3 * l + ft1][cc + n1d * t2] * L.t.Lam[cc][t1];
-                            a2 += L.aq[3 * l + ft2][t1 + n1d * cc] * L.t.Lam[cc][t2];
+                const double lamd = L.t.Lam[iF][bi[d]];
+#pragma unroll
+                for (int l = 0; l < 5; ++l) {
+                    double val = 0.0;
+                    if (on) val = L.av[l][e];
+                    if (viscous) {
+                        // lift along the normal axis: the line meets the face in one node
+                        val -= hinv[d] * (L.aq[3 * l + d][e] * lamd);
+                        // lifts along the face: only for nodes of the face
+                        if (on) {
+                            double a1 = 0.0, a2 = 0.0;
+#pragma unroll
+                            for (int cc = 0; cc < n1d; ++cc) {
+                                a1 += L.aq[3 * l + ft1][cc + n1d * t2] * L.t.Lam[cc][t1];
+                                a2 += L.aq[3 * l + ft2][t1 + n1d * cc] * L.t.Lam[cc][t2];
+                            }
+                            val -= hinv[ft1] * a1;
+                            val -= hinv[ft2] * a2;
                         }
-                        val -= hinv[ft1] * a1;
-                        val -= hinv[ft2] * a2;
+                    }
+                    rowp[l * n + b] = val;
+                }
+            } else {
+                const int fp = (t - n) / nf, e = (t - n) % nf;
+                const int dp = face_axis(fp);
+                const int iFp = face_side(fp) ? (n1d - 1) : 0;
+                const double sh = face_sign(fp) * hinv[dp];
+                // faces of the same axis: the line along d meets face f at node e;
+                // another face: the line along dp through its node e runs in face f
+                // where that node lies on f, at the face-compact indices q0 + cd qs
+                const int u = e % n1d, v = e / n1d;
+                bool meets = false;
+                int q0 = 0, qs = 1;
+                if (dp != d) {
+                    const bool d_is_t1 = d == face_t1(fp);
+                    const int cx = d_is_t1 ? v : u;       // coordinate along the third axis
+                    meets = (d_is_t1 ? u : v) == iF;
+                    if (ft1 == dp) q0 = n1d * cx;
+                    else {
+                        q0 = cx;
+                        qs = n1d;
                     }
                 }
-            } else if (col < NV + NH) {
-                const int r = col - NV;
-                const int fp = r / (5 * nf), l = (r / nf) % 5, e = r % nf;
-                if (fp == f) val = L.ah[l][e];
-                if (viscous) {
-                    const int dp = face_axis(fp);
-                    const int iFp = face_side(fp) ? (n1d - 1) : 0;
-                    double acc = 0.0;
-                    if (dp == d) {
-                        // faces of the same axis: the line along d meets face f at node e
-                        acc = L.aq[3 * l + d][e] * L.t.Minv[iF][iFp];
-                    } else {
-                        int ci[3];
-                        ci[face_t1(fp)] = e % n1d;
-                        ci[face_t2(fp)] = e / n1d;
-                        if (ci[d] == iF) {
-                            for (int cd = 0; cd < n1d; ++cd) {
-                                ci[dp] = cd;
-                                acc += L.aq[3 * l + dp][ci[ft1] + n1d * ci[ft2]] * L.t.Minv[cd][iFp];
-                            }
+                double mv[n1d];
+#pragma unroll
+                for (int cd = 0; cd < n1d; ++cd) mv[cd] = L.t.Minv[cd][iFp];
+                const double mff = L.t.Minv[iF][iFp];
+#pragma unroll
+                for (int l = 0; l < 5; ++l) {
+                    double val = 0.0;
+                    if (fp == f) val = L.ah[l][e];
+                    if (viscous) {
+                        double acc = 0.0;
+                        if (dp == d) {
+                            acc = L.aq[3 * l + d][e] * mff;
+                        } else if (meets) {
+#pragma unroll
+                            for (int cd = 0; cd < n1d; ++cd) acc += L.aq[3 * l + dp][q0 + cd * qs] * mv[cd];
                         }
+                        val += sh * acc;
                     }
-                    val += face_sign(fp) * hinv[dp] * acc;
+                    rowp[NV + (fp * 5 + l) * nf + e] = val;
                 }
             }
-            if (col != NV + NH) Bm[row * BD::ld + col] = val;
         }
+        // padding columns after the right-hand side
+        for (int col = NV + NH + 1 + threadIdx.x; col < BD::ld; col += blockDim.x) rowp[col] = 0.0;
         // right-hand side -R_Vhat + A_hq A_qq^-1 R_Q (only face nodes of q contribute)
         double part = 0.0;
         if (viscous)
