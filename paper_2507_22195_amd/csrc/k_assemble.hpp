@@ -136,25 +136,30 @@ __device__ void row_volume(RowLds<P>& L, const double* __restrict__ coefV, int64
     constexpr int Q = P + 1;
     static_assert(R::KG == 1, "one row per pass");
     const int nfld = viscous ? 20 : 5;
-    // weights, one (point, field) pair per thread, points fastest (the
-    // coefficients are stored point index fastest)
-    for (int idx = threadIdx.x; idx < nfld * E3; idx += blockDim.x) {
-        const int gl = idx % E3, fld = idx / E3;
+    // weights: a thread per sub-element point (consecutive threads on
+    // consecutive points: the coefficients are stored point index fastest),
+    // its basis factors formed once for the fields it takes in turn
+    const int fpp = (int)blockDim.x / E3;        // fields per pass
+    if ((int)threadIdx.x < fpp * E3) {
+        const int gl = threadIdx.x % E3, f0 = threadIdx.x / E3;
         const int g1 = e1 * Q + gl % Q, g2 = e2 * Q + (gl / Q) % Q, g3 = e3 * Q + gl / (Q * Q);
         const int g = g1 + nq1 * (g2 + nq1 * g3);
         const double B1 = L.t.B[g1][a1], B2 = L.t.B[g2][a2], B3 = L.t.B[g3][a3];
         const double t1 = L.t.D[g1][a1] * B2 * B3, t2 = B1 * L.t.D[g2][a2] * B3, t3 = B1 * B2 * L.t.D[g3][a3];
+        const double b123 = B1 * B2 * B3;
         const double* c = coefV + (int64_t)m * G * COEF_V + g;
-        double wv;
-        if (fld < 5) {
-            const int o = 5 * k + fld;
-            wv = B1 * B2 * B3 * c[o * G] + t1 * c[(25 + o) * G] + t2 * c[(50 + o) * G] + t3 * c[(75 + o) * G];
-        } else {
-            const int j = (fld - 5) % 3, o = 5 * k + (fld - 5) / 3;
-            wv = t1 * c[(100 + 25 * j + o) * G] + t2 * c[(100 + 25 * (3 + j) + o) * G] +
-                 t3 * c[(100 + 25 * (6 + j) + o) * G];
+        for (int fld = f0; fld < nfld; fld += fpp) {
+            double wv;
+            if (fld < 5) {
+                const int o = 5 * k + fld;
+                wv = b123 * c[o * G] + t1 * c[(25 + o) * G] + t2 * c[(50 + o) * G] + t3 * c[(75 + o) * G];
+            } else {
+                const int j = (fld - 5) % 3, o = 5 * k + (fld - 5) / 3;
+                wv = t1 * c[(100 + 25 * j + o) * G] + t2 * c[(100 + 25 * (3 + j) + o) * G] +
+                     t3 * c[(100 + 25 * (6 + j) + o) * G];
+            }
+            L.w[fld * WS + gl] = wv;
         }
-        L.w[fld * WS + gl] = wv;
     }
     __syncthreads();
     // axis 1, in place: W[fld][g1, g2, g3] -> T[fld][b1, g2, g3]
