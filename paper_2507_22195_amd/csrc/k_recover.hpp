@@ -45,36 +45,17 @@ __device__ void back_substitute(const double* __restrict__ Bm, const double* dvh
         }
     }
     __syncthreads();
-    // U dV = z, left-looking over blocks of 64 rows from the bottom: the rows
-    // of a block first take their dot products with the solved part, then
-    // wave 0 solves the 64 x 64 triangle (lane j holds row j; the solved value
-    // is broadcast with a lane read)
-    for (int i1 = NV; i1 > 0; i1 -= 64) {
-        const int i0 = i1 - 64 > 0 ? i1 - 64 : 0;
+    // U dV = z, right-looking over blocks of 64 rows from the last: wave 0
+    // solves the block's 64 x 64 triangle (lane j holds row j; the solved
+    // value is broadcast with a lane read), then every row above the block
+    // subtracts its product with the block's solution (all waves, RB rows at
+    // a time, one 64-column chunk per row)
+    for (int i0 = ((NV - 1) / 64) * 64; i0 >= 0; i0 -= 64) {
+        const int i1 = i0 + 64 < NV ? i0 + 64 : NV;
         const int nb = i1 - i0;
         for (int e = tid; e < 64 * 64; e += blockDim.x) {
             const int r = e >> 6, c = e & 63;
             U[r][c] = (r < nb && c < nb) ? Bm[(int64_t)(i0 + r) * ld + i0 + c] : 0.0;
-        }
-        for (int r0 = i0 + wave * RB; r0 < i1; r0 += nw * RB) {
-            double s[RB];
-#pragma unroll
-            for (int i = 0; i < RB; ++i) s[i] = 0.0;
-            for (int c = i1 + lane; c < NV; c += 64) {
-                const double x = z[c];
-#pragma unroll
-                for (int i = 0; i < RB; ++i)
-                    if (r0 + i < i1) s[i] += Bm[(int64_t)(r0 + i) * ld + c] * x;
-            }
-#pragma unroll
-            for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
-            if (lane < RB && r0 + lane < i1) {
-                double si = s[0];
-#pragma unroll
-                for (int i = 1; i < RB; ++i)
-                    if (lane == i) si = s[i];
-                z[r0 + lane] -= si;
-            }
         }
         __syncthreads();
         if (wave == 0) {
@@ -85,6 +66,23 @@ __device__ void back_substitute(const double* __restrict__ Bm, const double* dvh
                 else if (lane < j) zi -= U[lane][j] * xj;
             }
             if (lane < nb) z[i0 + lane] = zi;   // now holds dV for this block
+        }
+        __syncthreads();
+        const double x = lane < nb ? z[i0 + lane] : 0.0;
+        for (int r0 = wave * RB; r0 < i0; r0 += nw * RB) {
+            double s[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+                s[i] = (r0 + i < i0 && lane < nb) ? Bm[(int64_t)(r0 + i) * ld + i0 + lane] * x : 0.0;
+#pragma unroll
+            for (int i = 0; i < RB; ++i) s[i] = wave_sum_f64(s[i]);
+            if (lane < RB && r0 + lane < i0) {
+                double si = s[0];
+#pragma unroll
+                for (int i = 1; i < RB; ++i)
+                    if (lane == i) si = s[i];
+                z[r0 + lane] -= si;
+            }
         }
         __syncthreads();
     }
