@@ -60,8 +60,10 @@ __device__ void back_substitute(const double* __restrict__ Bm, const double* dvh
         __syncthreads();
         if (wave == 0) {
             double zi = (lane < nb) ? z[i0 + lane] : 0.0;
+            // reciprocals of the diagonal formed up front, off the dependent chain
+            const double rd = (lane < nb) ? 1.0 / U[lane][lane] : 0.0;
             for (int j = nb - 1; j >= 0; --j) {
-                const double xj = read_lane_f64(zi, j) / U[j][j];
+                const double xj = read_lane_f64(zi, j) * read_lane_f64(rd, j);
                 if (lane == j) zi = xj;
                 else if (lane < j) zi -= U[lane][j] * xj;
             }
@@ -88,12 +90,13 @@ __device__ void back_substitute(const double* __restrict__ Bm, const double* dvh
     }
 }
 
-// The 15 fields of dQ go through the LDS in groups of FG (all at once up to
-// p = 3; five at a time from p = 4 on, where all 15 would need 175 KB).
+// The 15 fields of dQ go through the LDS in groups of FG: all at once up to
+// p = 2; three at a time at p = 3, so that two macros' LDS (79 KB each) share
+// a CU; five at a time from p = 4 on, where all 15 would need 175 KB.
 template <int P>
 struct RecLds {
     using D = Dims<P>;
-    static constexpr int FG = P >= 4 ? 5 : 15;
+    static constexpr int FG = P >= 4 ? 5 : (P == 3 ? 3 : 15);
     double z[D::NV];
     double dvh[D::NH];
     double U[64][65];

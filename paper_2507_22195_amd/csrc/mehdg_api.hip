@@ -742,7 +742,10 @@ mehdg_err launch_recover(mehdg_ctx* c, const double* R_q, const double* dvhat, d
     const size_t lds = sizeof(RecLds<P>);
     if (!allow_lds(&k_recover<P>, lds)) return MEHDG_EHIP;
     Timed t(c, MEHDG_PROF_RECOVER, st);
-    hipLaunchKernelGGL(k_recover<P>, dim3((unsigned)c->n_macro), dim3(1024), lds, st, c->d_B, R_q, dvhat, c->d_h,
+    // up to p = 3 the LDS holds two macros per CU: two 512-thread workgroups
+    // overlap one macro's serial block solves with the other's loads
+    const unsigned threads = P <= 3 ? 512 : 1024;
+    hipLaunchKernelGGL(k_recover<P>, dim3((unsigned)c->n_macro), dim3(threads), lds, st, c->d_B, R_q, dvhat, c->d_h,
                        c->d_tab, dv, dq);
     return hip_ok(hipGetLastError());
 }
